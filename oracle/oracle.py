@@ -1,0 +1,201 @@
+"""ctypes binding of the FP64 CPU oracle (oracle/qlra_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg.  It never imports the GPU package and the GPU
+package never imports it.
+
+Quaternion matrices are numpy arrays of shape (4, rows, cols): planes
+(real, i, j, k) of X = X0 + X1 i + X2 j + X3 k (Sec. 2).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "qlra_oracle.c")
+_LIB = os.path.join(_HERE, "libqlra_oracle.so")
+
+SUBSPACE, BLOCK_KRYLOV, ALG1, ALG3 = 0, 1, 2, 3
+
+
+def build(force=True):
+    """Compile the oracle with gcc (FP contraction off: the Gaussian
+    generator's operation sequence is part of its definition)."""
+    if not force and os.path.exists(_LIB):
+        return _LIB
+    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-std=c11", "-Wall",
+           "-shared", "-fPIC", _SRC, "-o", _LIB + ".tmp", "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        L.qo_philox4x32_10.argtypes = [P, P, P]
+        L.qo_log_unit.argtypes = [ctypes.c_double]
+        L.qo_log_unit.restype = ctypes.c_double
+        L.qo_sqrt_pos.argtypes = [ctypes.c_double]
+        L.qo_sqrt_pos.restype = ctypes.c_double
+        L.qo_sincos_2pi.argtypes = [ctypes.c_double, P, P]
+        L.qo_omega.argtypes = [ctypes.c_uint64, i64, i64, P]
+        L.qo_qgemm.argtypes = [P, i64, i64, P, i64, P]
+        L.qo_qgemm_adj.argtypes = [P, i64, i64, P, i64, P]
+        L.qo_qr.argtypes = [P, i64, i64, P, P]
+        L.qo_qsvd.argtypes = [P, i64, P, P, P]
+        L.qo_qlra.argtypes = [P, i64, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                              ctypes.c_int, ctypes.c_uint64, P, P, P, P]
+        L.qo_qlra_sketch.argtypes = [P, i64, i64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, P, P, P, P, P, P, P, P, P]
+        for name in ("qo_qgemm", "qo_qgemm_adj", "qo_qr", "qo_qsvd", "qo_qlra", "qo_qlra_sketch"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _planes(x, dtype=np.float64):
+    x = np.ascontiguousarray(x, dtype=dtype)
+    assert x.ndim == 3 and x.shape[0] == 4, x.shape
+    return x
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with status {rc}")
+
+
+def philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().qo_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def log_unit(u):
+    return lib().qo_log_unit(float(u))
+
+
+def sqrt_pos(x):
+    return lib().qo_sqrt_pos(float(x))
+
+
+def sincos_2pi(u):
+    s = ctypes.c_double()
+    c = ctypes.c_double()
+    lib().qo_sincos_2pi(float(u), ctypes.byref(s), ctypes.byref(c))
+    return s.value, c.value
+
+
+def omega(seed, n, l):
+    """Gaussian quaternion sketch, FP32 planes (4, n, l)."""
+    out = np.empty((4, n, l), dtype=np.float32)
+    lib().qo_omega(ctypes.c_uint64(seed), n, l, _p(out))
+    return out
+
+
+def qgemm(A, B):
+    A = _planes(A)
+    B = _planes(B)
+    m, n = A.shape[1:]
+    assert B.shape[1] == n
+    C = np.empty((4, m, B.shape[2]))
+    _check(lib().qo_qgemm(_p(A), m, n, _p(B), B.shape[2], _p(C)), "qgemm")
+    return C
+
+
+def qgemm_adj(A, B):
+    A = _planes(A)
+    B = _planes(B)
+    m, n = A.shape[1:]
+    assert B.shape[1] == m
+    C = np.empty((4, n, B.shape[2]))
+    _check(lib().qo_qgemm_adj(_p(A), m, n, _p(B), B.shape[2], _p(C)), "qgemm_adj")
+    return C
+
+
+def qr(Y):
+    Y = _planes(Y)
+    m, w = Y.shape[1:]
+    Q = np.empty((4, m, w))
+    R = np.empty((4, w, w))
+    _check(lib().qo_qr(_p(Y), m, w, _p(Q), _p(R)), "qr")
+    return Q, R
+
+
+def qsvd(R):
+    R = _planes(R)
+    w = R.shape[1]
+    assert R.shape[2] == w
+    U = np.empty((4, w, w))
+    V = np.empty((4, w, w))
+    S = np.empty(w)
+    _check(lib().qo_qsvd(_p(R), w, _p(U), _p(S), _p(V)), "qsvd")
+    return U, S, V
+
+
+def qlra(A, k, p, v, scheme, seed):
+    """Full method on FP64 planes A (4, m, n) with the seeded sketch.
+    Returns U (4, m, k), S (k,), V (4, n, k), pass_err (v,)."""
+    A = _planes(A)
+    m, n = A.shape[1:]
+    U = np.empty((4, m, k))
+    V = np.empty((4, n, k))
+    S = np.empty(k)
+    e = np.empty(v)
+    _check(lib().qo_qlra(_p(A), m, n, k, p, v, scheme, ctypes.c_uint64(seed),
+                         _p(U), _p(S), _p(V), _p(e)), "qlra")
+    return U, S, V, e
+
+
+def qlra_sketch(A, k, p, v, scheme, Om, bases=False):
+    """Full method with an explicit sketch Om (4, n, k+p).  With bases=True
+    also returns the final range/co-range bases Q1, Q2."""
+    A = _planes(A)
+    Om = _planes(Om)
+    m, n = A.shape[1:]
+    l = k + p
+    assert Om.shape == (4, n, l), Om.shape
+    U = np.empty((4, m, k))
+    V = np.empty((4, n, k))
+    S = np.empty(k)
+    e = np.empty(v)
+    wmax = min(min(m, n), (v // 2 + 1) * l)
+    if bases:
+        Q1 = np.empty(4 * m * wmax)
+        Q2 = np.empty(4 * n * wmax)
+        w1 = ctypes.c_int64()
+        w2 = ctypes.c_int64()
+        rc = lib().qo_qlra_sketch(_p(A), m, n, k, p, v, scheme, _p(Om), _p(U), _p(S), _p(V), _p(e),
+                                  _p(Q1), ctypes.byref(w1), _p(Q2), ctypes.byref(w2))
+        _check(rc, "qlra_sketch")
+        Q1 = Q1[: 4 * m * w1.value].reshape(4, m, w1.value)
+        Q2 = Q2[: 4 * n * w2.value].reshape(4, n, w2.value)
+        return U, S, V, e, Q1, Q2
+    rc = lib().qo_qlra_sketch(_p(A), m, n, k, p, v, scheme, _p(Om), _p(U), _p(S), _p(V), _p(e),
+                              None, None, None, None)
+    _check(rc, "qlra_sketch")
+    return U, S, V, e
+
+
+def reconstruct(U, S, V):
+    """U diag(S) V^H with the oracle's own product (FP64 planes)."""
+    US = np.asarray(U, dtype=np.float64) * np.asarray(S)[None, None, :]
+    Vh = np.asarray(V, dtype=np.float64).transpose(0, 2, 1).copy()
+    Vh[1:] *= -1.0                     # (V^H) planes: V0^T, -V1^T, -V2^T, -V3^T
+    return qgemm(US, Vh)
