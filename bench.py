@@ -1,0 +1,202 @@
+"""Benchmark: pass-efficient randomized truncated QSVD on one MI355X.
+
+Workload (the 2048 x 2048 configuration): dense quaternion FP32 matrix
+A = U diag(sigma) V^H + E, sigma_i = exp(-i/20), Haar quaternion unitaries, E i.i.d. N(0, 1e-4)
+per real component (synthetic, seeded).  k = 50, p = 10, subspace scheme (Alg. 2).  One step
+= one solve for each pass budget v in {2, 3, 4, 6}: 15 passes over A, each a quaternion view
+product A X or A^H X followed by CholeskyQR2, then the small QSVD and the back-multiplication,
+with per-pass error estimates.
+
+Printed: one JSON line with passes/s (value), the dominant kernel's roofline position (FP32
+MFMA view product, timed with HIP events on its own stream), the FP64 CPU oracle timed on the
+host as a baseline, and accuracy against the oracle.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+M = N = 2048
+K_RANK, P_OVER = 50, 10
+BUDGETS = (2, 3, 4, 6)
+SEED_DATA, SEED_SKETCH = 1, 1
+PEAK_FP32_MFMA = 157.3e12
+PEAK_HBM = 8.0e12
+PMC_FILE = os.path.join(ROOT, "profiles", "qgemm_f32_view_2048x2048x60_pmc.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    return ap.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("qgemm.hip", "common.h"):
+        h.update(open(os.path.join(ROOT, "paper_2507_13731_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def time_view_kernels(Q, torch, A, reps):
+    """Average duration of the FP32 view product kernel (both orientations) with HIP events
+    on the stream the kernel runs on."""
+    w = K_RANK + P_OVER
+    g = torch.Generator(device="cuda").manual_seed(0)
+    X = torch.randn((4, N, w), device="cuda", generator=g)
+    out = {}
+    for op in (0, 1):
+        ws = Q.qlra_qgemm_workspace(op, M, N, w)
+        C = torch.empty((4, M if op == 0 else N, w), device="cuda")
+        st = torch.cuda.current_stream()
+        for _ in range(3):
+            Q.qlra_qgemm(op, A, X, C, stream=st, workspace=ws)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            Q.qlra_qgemm(op, A, X, C, stream=st, workspace=ws)
+        e1.record(st)
+        e1.synchronize()
+        out[op] = e0.elapsed_time(e1) * 1e-3 / reps
+    return out
+
+
+def cpu_baseline(A_np):
+    """The FP64 oracle on the host: one full step (v = 2, 3, 4, 6) on the same matrix."""
+    from oracle import oracle as O
+    import numpy as np
+    cores = len(os.sched_getaffinity(0))
+    os.environ["OMP_NUM_THREADS"] = str(cores)
+    A64 = A_np.astype(np.float64)
+    t0 = time.perf_counter()
+    for v in BUDGETS:
+        O.qlra(A64, K_RANK, P_OVER, v, O.SUBSPACE, SEED_SKETCH)
+    dt = time.perf_counter() - t0
+    return {"value": round(sum(BUDGETS) / dt, 4), "unit": "A-passes/s", "cores": cores, "kind": "oracle",
+            "sample": "one full step (subspace solves at v = 2, 3, 4, 6; 15 passes) on the same 2048x2048 matrix, "
+                      f"{dt:.1f} s wall"}
+
+
+def accuracy(Q, torch, A, A_np):
+    """Error of the GPU result and of the oracle against A for each budget (outside the timed region)."""
+    import numpy as np
+    from oracle import oracle as O
+    A64 = A_np.astype(np.float64)
+    nA = np.sqrt(np.sum(A64 ** 2))
+    rows = []
+    for v in BUDGETS:
+        U, S, V, e, ws = Q.qlra(A, K_RANK, P_OVER, v, "subspace", SEED_SKETCH)
+        torch.cuda.synchronize()
+        Ug, Sg, Vg = (x.cpu().numpy().astype(np.float64) for x in (U, S, V))
+        Uo, So, Vo, eo = O.qlra(A64, K_RANK, P_OVER, v, O.SUBSPACE, SEED_SKETCH)
+        Ag, Ao = O.reconstruct(Ug, Sg, Vg), O.reconstruct(Uo, So, Vo)
+        eg_ = np.sqrt(np.sum((A64 - Ag) ** 2)) / nA
+        eo_ = np.sqrt(np.sum((A64 - Ao) ** 2)) / nA
+        rows.append({"v": v, "rel_err_gpu": float(eg_), "rel_err_oracle": float(eo_), "ratio": float(eg_ / eo_),
+                     "ahat_diff": float(np.sqrt(np.sum((Ag - Ao) ** 2)) / nA),
+                     "pass_err_gpu_last": float(e.cpu().numpy()[-1])})
+    return rows
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1",
+                          "n_gpus_requested": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2507_13731_amd import qlra as Q
+    import workloads as W
+
+    print("generating the 2048x2048 workload", file=sys.stderr, flush=True)
+    A_np, _ = W.config1(seed=SEED_DATA, n=M, noise_std=0.01)
+    A = torch.from_numpy(A_np).cuda()
+    outs = {}
+    for v in BUDGETS:
+        need = Q.qlra_workspace_size(M, N, K_RANK, P_OVER, v, "subspace")
+        outs[v] = dict(U=torch.empty((4, M, K_RANK), device="cuda"), V=torch.empty((4, N, K_RANK), device="cuda"),
+                       S=torch.empty(K_RANK, dtype=torch.float64, device="cuda"),
+                       e=torch.empty(v, dtype=torch.float64, device="cuda"),
+                       ws=torch.empty(need, dtype=torch.uint8, device="cuda"))
+
+    def step():
+        for v in BUDGETS:
+            o = outs[v]
+            Q.qlra(A, K_RANK, P_OVER, v, "subspace", SEED_SKETCH, U=o["U"], S=o["S"], V=o["V"],
+                   pass_err=o["e"], workspace=o["ws"])
+
+    print(f"warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    for v in BUDGETS:
+        assert Q.qlra_status(outs[v]["ws"]) == Q.QLRA_OK
+    print(f"timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt * 1e3 / args.steps
+    passes = sum(BUDGETS) * args.steps
+    value = passes / dt
+
+    # per-budget solve times (not part of the value)
+    per_v = {}
+    for v in BUDGETS:
+        o = outs[v]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(5):
+            Q.qlra(A, K_RANK, P_OVER, v, "subspace", SEED_SKETCH, U=o["U"], S=o["S"], V=o["V"], pass_err=o["e"],
+                   workspace=o["ws"])
+        torch.cuda.synchronize()
+        per_v[f"v{v}_ms"] = round((time.perf_counter() - t1) * 1e3 / 5, 4)
+
+    print("timing the view kernels", file=sys.stderr, flush=True)
+    kt = time_view_kernels(Q, torch, A, args.kernel_reps)
+    w = K_RANK + P_OVER
+    flops = 32.0 * M * N * w                      # algorithmic flops of one view (16 real FMAs per qMAC)
+    t_view = 0.5 * (kt[0] + kt[1])
+    achieved = flops / t_view
+    traffic = None
+    if os.path.exists(PMC_FILE):
+        pmc = json.load(open(PMC_FILE))
+        if pmc.get("kernel_source_hash") == kernel_source_hash():
+            traffic = pmc.get("hbm_bytes_per_launch")
+    roofline = {"bound": "mfma", "achieved": round(achieved / 1e12, 3), "peak": PEAK_FP32_MFMA / 1e12,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": traffic,
+                "kernel": "k_qgemm FP32 view product, 2048x2048 by 60 quaternion columns",
+                "t_forward_us": round(kt[0] * 1e6, 2), "t_adjoint_us": round(kt[1] * 1e6, 2),
+                "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": 16.0 * M * N + 2 * 16.0 * N * w}
+
+    print("accuracy against the oracle", file=sys.stderr, flush=True)
+    acc = accuracy(Q, torch, A, A_np)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(A_np)
+    line = {"metric": "A-passes/s", "value": round(value, 3), "unit": "A-passes/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic (seeded; Haar quaternion unitaries, exp(-i/20) spectrum + Gaussian noise)",
+            "config": {"workload": "dense quaternion 2048x2048 FP32, sigma_i=exp(-i/20)+N(0,1e-4) noise, "
+                                   "k=50, p=10, subspace scheme (Alg. 2), budgets v=2,3,4,6 per step",
+                       "m": M, "n": N, "k": K_RANK, "p": P_OVER, "budgets": list(BUDGETS),
+                       "passes_per_step": sum(BUDGETS)},
+            "qgemm_tflops": round(achieved / 1e12, 3), "solve_ms": per_v, "accuracy": acc,
+            "roofline": roofline, "cpu_baseline": cpu}
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,112 @@
+// Internal declarations shared by the library's HIP sources (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "qlra.h"
+
+namespace qlra_impl {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// Plane-major quaternion matrix view: plane p at ptr + p * ps, row-major, leading dim ld.
+template <class T>
+struct QView {
+    T* ptr;
+    int64_t ld;
+    int64_t ps;
+};
+
+// Which product a qgemm launch computes.
+enum QOp { OP_NN = 0, OP_HN = 1 };   // C = A B  |  C = A^H B
+
+// How the result is stored.
+enum QStore { ST_SET = 0, ST_SUB = 1 };   // C = R  |  C = C - R
+
+// Arithmetic of a qgemm launch.
+enum QMath { MATH_F32 = 0, MATH_F64 = 1 };
+
+struct QgemmDesc {
+    QOp op;
+    QMath math;
+    QStore store;
+    int a_f64, b_f64, c_f64;   // element types of A, B, C (0 = float, 1 = double)
+    const void* A; int64_t lda, aps;
+    const void* B; int64_t ldb, bps;
+    void* C; int64_t ldc, cps;
+    int64_t M, N, K;           // C is M x N, reduction length K
+    const int* skip_flag;      // if non-null and *skip_flag == 0 the launch does nothing
+};
+
+// Device workspace carved into aligned regions.
+struct Arena {
+    char* base;
+    size_t size;
+    size_t used;
+    bool dry;   // sizing pass: count only
+    void* take(size_t bytes) {
+        size_t off = (used + 255) & ~size_t(255);
+        used = off + ((bytes + 255) & ~size_t(255));
+        if (dry) return nullptr;
+        return base + off;
+    }
+};
+
+// Scratch a qgemm launch needs: split-K partials and per-tile counters.
+struct QgemmScratch {
+    void* partial;          // bytes given by qgemm_scratch_bytes
+    unsigned* counters;     // qgemm_counter_count entries, zero at rest
+};
+
+size_t qgemm_partial_bytes(const QgemmDesc& d);
+size_t qgemm_counter_count(const QgemmDesc& d);
+hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t st);
+
+hipError_t omega_launch(uint64_t seed, int64_t n, int64_t l, float* Om, int64_t ld, int64_t ps,
+                        hipStream_t st);
+
+// Cholesky of a Hermitian quaternion Gram G (w x w FP64 planes, ld = w): G (+ shift I) = R^H R
+// and Rinv = R^{-1} (if non-null).  If the unshifted factorization breaks down and allow_shift
+// is set, it is redone with shift = shift_scale * trace(G) and *shift_out (if non-null) is set to
+// 1 (else 0).  A failure that remains ORs 2 into *status.  If gate is non-null and *gate == 0
+// nothing is done.  work: 4*w*w doubles.
+hipError_t chol_launch(const double* G, int64_t w, double* R, double* Rinv, double* work, int* status,
+                       int* shift_out, const int* gate, int allow_shift, double shift_scale,
+                       hipStream_t st);
+// Rout = R2 * R1 (upper triangular w x w); nothing if gate && !*gate.
+hipError_t rmul_launch(const double* R2, const double* R1, double* Rout, int64_t w,
+                       const int* gate, hipStream_t st);
+// dst = src (FP64 planes w x w) when gate is null or *gate != 0.
+hipError_t rcopy_launch(const double* src, double* dst, int64_t w, const int* gate, hipStream_t st);
+
+// dst (rows x cols FP32 planes) = src, when gate is null or *gate != 0.
+hipError_t copy_planes_launch(const float* src, int64_t lds, int64_t sps, float* dst, int64_t ldd,
+                              int64_t dps, int64_t rows, int64_t cols, const int* gate, hipStream_t st);
+// p[0..count) = value.
+hipError_t fill_int_launch(int* p, int64_t count, int value, hipStream_t st);
+hipError_t fill_u32_launch(unsigned* p, int64_t count, hipStream_t st);
+
+// One-sided Jacobi QSVD of X (w x w FP64 planes): S descending, U = left vectors, V right
+// vectors (if want_vectors).  work: 8*w*w + 2*w doubles.
+hipError_t qsvd_launch(const double* X, int64_t w, double* U, double* S, double* V, double* work,
+                       int want_vectors, hipStream_t st);
+size_t qsvd_work_doubles(int64_t w);
+
+// e = sqrt(max(0, nA2 - sum_{j<k} S_j^2) / nA2)
+hipError_t estimate_launch(const double* S, int k, const double* nA2, double* e, hipStream_t st);
+hipError_t nan_launch(double* e, hipStream_t st);
+
+// ||A||_F^2 (FP64) into *out; partial: 1024 doubles.
+hipError_t fro2_launch(const float* A, int64_t m, int64_t n, int64_t lda, int64_t aps,
+                       double* partial, double* out, hipStream_t st);
+
+// Canonical phase: for each column j < k of V (n x k), the entry of largest modulus (lowest row
+// on ties) is made real positive by right-multiplying columns j of U and V by its conjugate phase.
+hipError_t phase_launch(float* U, int64_t m, int64_t ldu, int64_t ups, float* V, int64_t n,
+                        int64_t ldv, int64_t vps, int k, hipStream_t st);
+
+}  // namespace qlra_impl

@@ -1,0 +1,584 @@
+// Host side of the library: argument checks, workspace layout and the per-view launch sequence
+// of Alg. 2 (Sec. 3) and Alg. 4 (Sec. 5), plus the C ABI declared in include/qlra.h.
+//
+// Everything between views stays on the device: a solve is a fixed sequence of kernel
+// launches on the caller's stream with no host synchronisation.  The per-pass error
+// estimates need a small QSVD of each view's R; they run on a side stream (fork/join with
+// events) so that they overlap the next views instead of lengthening the chain.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+
+#include "common.h"
+
+namespace qlra_impl {
+namespace {
+
+// ---------------------------------------------------------------------------------------
+// launch context: a dry run only sizes the qgemm scratch
+
+struct Ctx {
+    bool dry = false;
+    hipStream_t st = nullptr;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    QgemmScratch scr{};
+    size_t part_need = 0, cnt_need = 0;
+    hipError_t err = hipSuccess;
+    int* status = nullptr;          // status[0]: sticky solve status bits, status[1..]: gates
+    double* chol_work = nullptr;
+    double* G = nullptr;            // Gram, wmax x wmax
+    double* R1 = nullptr;
+    double* R2 = nullptr;
+    double* Rt = nullptr;
+    double* Rinv = nullptr;
+    float* T2 = nullptr;            // CholQR intermediate, rows x wmax
+    int64_t T2_rows = 0;
+    double* Rjunk = nullptr;        // R of QRs whose factor is not needed
+};
+
+void note(Ctx& c, hipError_t e) {
+    if (c.err == hipSuccess && e != hipSuccess) c.err = e;
+}
+
+void qg(Ctx& c, const QgemmDesc& d) {
+    if (c.dry) {
+        c.part_need = std::max(c.part_need, qgemm_partial_bytes(d));
+        c.cnt_need = std::max(c.cnt_need, qgemm_counter_count(d));
+        return;
+    }
+    note(c, qgemm_launch(d, c.scr, c.st));
+}
+
+QgemmDesc desc(QOp op, QMath math, const void* A, int64_t lda, int64_t aps, int a64, const void* B, int64_t ldb,
+               int64_t bps, int b64, void* C, int64_t ldc, int64_t cps, int c64, int64_t M, int64_t N, int64_t K,
+               QStore store = ST_SET, const int* skip = nullptr) {
+    QgemmDesc d{};
+    d.op = op; d.math = math; d.store = store;
+    d.a_f64 = a64; d.b_f64 = b64; d.c_f64 = c64;
+    d.A = A; d.lda = lda; d.aps = aps;
+    d.B = B; d.ldb = ldb; d.bps = bps;
+    d.C = C; d.ldc = ldc; d.cps = cps;
+    d.M = M; d.N = N; d.K = K;
+    d.skip_flag = skip;
+    return d;
+}
+
+double shift_scale(int64_t rows, int64_t w) {
+    // Shifted CholeskyQR (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa 2020):
+    // s = 11 (m w + w (w + 1)) u ||Y||_2^2, with ||Y||_F^2 = trace(Y^H Y) as the bound.
+    return 11.0 * ((double)rows * w + (double)w * (w + 1)) * 1.1102230246251565e-16;
+}
+
+// Thin QR of Y (rows x w) by CholeskyQR2 with a gated shifted third round: Q (ld ldq, plane
+// stride qps) and R (w x w FP64, ld w).  Q may alias Y.
+void cholqr(Ctx& c, const float* Y, int64_t rows, int64_t w, int64_t ldy, int64_t yps, float* Q, int64_t ldq,
+            int64_t qps, double* R) {
+    const int64_t tps = rows * w;
+    int* gate = c.status ? c.status + 1 : nullptr;
+    // round 1: G = Y^H Y; G = R1^H R1; Z = Y R1^{-1}
+    qg(c, desc(OP_HN, MATH_F64, Y, ldy, yps, 0, Y, ldy, yps, 0, c.G, w, w * w, 1, w, w, rows));
+    if (!c.dry) note(c, chol_launch(c.G, w, c.R1, c.Rinv, c.chol_work, c.status, gate, nullptr, 1,
+                                    shift_scale(rows, w), c.st));
+    qg(c, desc(OP_NN, MATH_F64, Y, ldy, yps, 0, c.Rinv, w, w * w, 1, c.T2, w, tps, 0, rows, w, w));
+    // round 2: Z = Q R2
+    qg(c, desc(OP_HN, MATH_F64, c.T2, w, tps, 0, c.T2, w, tps, 0, c.G, w, w * w, 1, w, w, rows));
+    if (!c.dry) note(c, chol_launch(c.G, w, c.R2, c.Rinv, c.chol_work, c.status, nullptr, nullptr, 0, 0.0, c.st));
+    qg(c, desc(OP_NN, MATH_F64, c.T2, w, tps, 0, c.Rinv, w, w * w, 1, Q, ldq, qps, 0, rows, w, w));
+    if (!c.dry) note(c, rmul_launch(c.R2, c.R1, R, w, nullptr, c.st));
+    // round 3, only when round 1 had to be shifted: Q <- Q R3^{-1}, R <- R3 R
+    qg(c, desc(OP_HN, MATH_F64, Q, ldq, qps, 0, Q, ldq, qps, 0, c.G, w, w * w, 1, w, w, rows, ST_SET, gate));
+    if (!c.dry) {
+        note(c, chol_launch(c.G, w, c.R2, c.Rinv, c.chol_work, c.status, nullptr, gate, 0, 0.0, c.st));
+    }
+    qg(c, desc(OP_NN, MATH_F64, Q, ldq, qps, 0, c.Rinv, w, w * w, 1, c.T2, w, tps, 0, rows, w, w, ST_SET, gate));
+    if (!c.dry) {
+        note(c, copy_planes_launch(c.T2, w, tps, Q, ldq, qps, rows, w, gate, c.st));
+        note(c, rmul_launch(c.R2, R, c.Rt, w, gate, c.st));
+        note(c, rcopy_launch(c.Rt, R, w, gate, c.st));
+    }
+}
+
+// Orthonormalise the columns of a stack of blocks (rows x W, ld W) whose blocks of width l are
+// each already orthonormal: block Gram-Schmidt with reorthogonalisation (two projections
+// against all earlier blocks), then CholeskyQR2 of the block in place.
+void orth_stack(Ctx& c, float* K, int64_t rows, int64_t W, int64_t l, double* Cbuf) {
+    const int64_t kps = rows * W;
+    for (int64_t b0 = l; b0 < W; b0 += l) {
+        const int64_t lb = std::min(l, W - b0);
+        float* Z = K + b0;
+        for (int pass = 0; pass < 2; pass++) {
+            // C = K_prev^H Z (b0 x lb, FP64), then Z -= K_prev C
+            qg(c, desc(OP_HN, MATH_F64, K, W, kps, 0, Z, W, kps, 0, Cbuf, lb, b0 * lb, 1, b0, lb, rows));
+            qg(c, desc(OP_NN, MATH_F64, K, W, kps, 0, Cbuf, lb, b0 * lb, 1, Z, W, kps, 0, rows, lb, b0, ST_SUB));
+        }
+        cholqr(c, Z, rows, lb, W, kps, Z, W, kps, c.Rjunk);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// solve layout
+
+struct Problem {
+    const float* A; int64_t m, n, lda, aps;
+    int k, p, v, scheme;
+    uint64_t seed;
+    float* U; int64_t ldu, ups;
+    double* S;
+    float* V; int64_t ldv, vps;
+    double* pass_err;
+    int estimate;
+};
+
+struct Dims {
+    int64_t l, Wk, wmax, rows_max, stack_rows;
+    bool krylov, even;
+    int s;
+};
+
+Dims dims_of(int64_t m, int64_t n, int k, int p, int v, int scheme) {
+    Dims d{};
+    d.l = (int64_t)k + p;
+    d.krylov = scheme == QLRA_BLOCK_KRYLOV;
+    d.even = (v % 2) == 0;
+    d.s = (v - 1) / 2;
+    const int64_t cap = std::min(m, n);
+    if (d.krylov) {
+        const int64_t nb = d.even ? v / 2 : d.s;
+        d.Wk = std::min(nb * d.l, cap);
+        d.stack_rows = d.even ? m : n;
+    } else {
+        d.Wk = d.l;
+        d.stack_rows = 0;
+    }
+    d.wmax = std::max(d.l, d.Wk);
+    d.rows_max = std::max(m, n);
+    return d;
+}
+
+struct Bufs {
+    int* status;            // 16 ints
+    unsigned* counters;
+    double* nA2;
+    double* fro_part;       // 1024
+    float* Om;              // n x l
+    float* Q1;              // m x wmax
+    float* Q2;              // n x wmax
+    float* T;               // rows_max x wmax
+    float* T2;              // rows_max x wmax
+    float* stack;           // stack_rows x Wk
+    double* G; double* R1; double* R2; double* Rt; double* Rinv; double* chol_work;
+    double* Rv;             // v x (l x l)
+    double* Rfin;           // wmax x wmax
+    double* Cbuf;           // Wk x l
+    double* Lh; double* Rh; double* Sw; double* qsvd_work;
+    double* side_S; double* side_work;
+    void* partial;
+};
+
+void carve(const Problem& pr, const Dims& d, Arena& ar, Bufs& b, size_t part_bytes, size_t cnt) {
+    const int64_t w2 = d.wmax * d.wmax, l2 = d.l * d.l;
+    b.status = (int*)ar.take(16 * sizeof(int));
+    b.counters = (unsigned*)ar.take(std::max<size_t>(cnt, 1) * sizeof(unsigned));
+    b.nA2 = (double*)ar.take(sizeof(double));
+    b.fro_part = (double*)ar.take(1024 * sizeof(double));
+    b.Om = (float*)ar.take(4 * pr.n * d.l * sizeof(float));
+    b.Q1 = (float*)ar.take(4 * pr.m * d.wmax * sizeof(float));
+    b.Q2 = (float*)ar.take(4 * pr.n * d.wmax * sizeof(float));
+    b.T = (float*)ar.take(4 * d.rows_max * d.wmax * sizeof(float));
+    b.T2 = (float*)ar.take(4 * d.rows_max * d.wmax * sizeof(float));
+    b.stack = d.krylov ? (float*)ar.take(4 * d.stack_rows * d.Wk * sizeof(float)) : nullptr;
+    b.G = (double*)ar.take(4 * w2 * sizeof(double));
+    b.R1 = (double*)ar.take(4 * w2 * sizeof(double));
+    b.R2 = (double*)ar.take(4 * w2 * sizeof(double));
+    b.Rt = (double*)ar.take(4 * w2 * sizeof(double));
+    b.Rinv = (double*)ar.take(4 * w2 * sizeof(double));
+    b.chol_work = (double*)ar.take(4 * w2 * sizeof(double));
+    b.Rv = (double*)ar.take((size_t)pr.v * 4 * l2 * sizeof(double));
+    b.Rfin = (double*)ar.take(4 * w2 * sizeof(double));
+    b.Cbuf = (double*)ar.take(4 * d.Wk * d.l * sizeof(double));
+    b.Lh = (double*)ar.take(4 * w2 * sizeof(double));
+    b.Rh = (double*)ar.take(4 * w2 * sizeof(double));
+    b.Sw = (double*)ar.take(d.wmax * sizeof(double));
+    b.qsvd_work = (double*)ar.take(qsvd_work_doubles(d.wmax) * sizeof(double));
+    b.side_S = (double*)ar.take(d.l * sizeof(double));
+    b.side_work = (double*)ar.take(qsvd_work_doubles(d.l) * sizeof(double));
+    b.partial = part_bytes ? ar.take(part_bytes) : nullptr;
+}
+
+// Per-device side stream and events (default priority).
+struct Side {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+std::mutex g_side_mu;
+Side g_side[64];
+
+hipError_t get_side(Side* out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    Side& sd = g_side[dev];
+    if (!sd.s) {
+        if ((e = hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming)) != hipSuccess) return e;
+        if ((e = hipEventCreateWithFlags(&sd.join, hipEventDisableTiming)) != hipSuccess) return e;
+    }
+    *out = sd;
+    return hipSuccess;
+}
+
+// Side-stream estimate of view `i` (1-based) from its R (l x l).
+void fork_estimate(Ctx& c, const Bufs& b, const Problem& pr, const double* R, int64_t l, int i) {
+    if (c.dry || !pr.estimate) return;
+    note(c, hipEventRecord(c.ev_fork, c.st));
+    note(c, hipStreamWaitEvent(c.side, c.ev_fork, 0));
+    note(c, qsvd_launch(R, l, nullptr, b.side_S, nullptr, b.side_work, 0, c.side));
+    note(c, estimate_launch(b.side_S, pr.k, b.nA2, pr.pass_err + (i - 1), c.side));
+}
+
+// The final TSVD of the last view's R (w x w) and the back-multiplication U = Q1 Uh,
+// V = Q2 Vh (Alg. 2 and Alg. 4, last lines).  r_is_r2: even budget (A^H Q1 = Q2 R2, so
+// R2 = Vh S Uh^H); otherwise A Q2 = Q1 R1 and R1 = Uh S Vh^H.
+void finish(Ctx& c, const Bufs& b, const Problem& pr, const double* R, int64_t w, const float* Q1, int64_t ldq1,
+            const float* Q2, int64_t ldq2, bool r_is_r2) {
+    const int k = pr.k;
+    if (!c.dry) {
+        note(c, qsvd_launch(R, w, b.Lh, b.Sw, b.Rh, b.qsvd_work, 1, c.st));
+        if (pr.estimate) note(c, estimate_launch(b.Sw, k, b.nA2, pr.pass_err + (pr.v - 1), c.st));
+    }
+    const double* Uh = r_is_r2 ? b.Rh : b.Lh;
+    const double* Vh = r_is_r2 ? b.Lh : b.Rh;
+    qg(c, desc(OP_NN, MATH_F64, Q1, ldq1, pr.m * ldq1, 0, Uh, w, w * w, 1, pr.U, pr.ldu, pr.ups, 0, pr.m, k, w));
+    qg(c, desc(OP_NN, MATH_F64, Q2, ldq2, pr.n * ldq2, 0, Vh, w, w * w, 1, pr.V, pr.ldv, pr.vps, 0, pr.n, k, w));
+    if (!c.dry) {
+        note(c, phase_launch(pr.U, pr.m, pr.ldu, pr.ups, pr.V, pr.n, pr.ldv, pr.vps, k, c.st));
+        note(c, hipMemcpyAsync(pr.S, b.Sw, sizeof(double) * k, hipMemcpyDeviceToDevice, c.st));
+    }
+}
+
+// One view: C = A X (forward) or C = A^H X (adjoint), then its QR.
+void view(Ctx& c, const Problem& pr, bool adjoint, const float* X, int64_t ldx, int64_t w, float* T, float* Q,
+          int64_t ldq, double* R) {
+    const int64_t rows_out = adjoint ? pr.n : pr.m;
+    const int64_t kdim = adjoint ? pr.m : pr.n;
+    const int64_t xps = kdim * ldx;
+    qg(c, desc(adjoint ? OP_HN : OP_NN, MATH_F32, pr.A, pr.lda, pr.aps, 0, X, ldx, xps, 0, T, w, rows_out * w, 0,
+               rows_out, w, kdim));
+    cholqr(c, T, rows_out, w, w, rows_out * w, Q, ldq, rows_out * ldq, R);
+}
+
+void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
+    const int64_t l = d.l, l2 = l * l;
+    if (!c.dry) {
+        note(c, fill_int_launch(b.status, 16, 0, c.st));
+        note(c, fill_u32_launch(b.counters, (int64_t)std::max<size_t>(c.cnt_need, 1), c.st));
+        note(c, fro2_launch(pr.A, pr.m, pr.n, pr.lda, pr.aps, b.fro_part, b.nA2, c.st));
+        note(c, omega_launch(pr.seed, pr.n, l, b.Om, l, pr.n * l, c.st));
+        if (pr.estimate) note(c, nan_launch(pr.pass_err, c.st));
+    }
+    const float* Q2cur = b.Om;
+    if (!d.krylov) {
+        // Alg. 2: odd views [Q1, R1] = QR(A Q2), even views [Q2, R2] = QR(A^H Q1)
+        for (int i = 1; i <= pr.v; i++) {
+            double* R = b.Rv + (size_t)(i - 1) * 4 * l2;
+            if (i % 2 == 1) view(c, pr, false, Q2cur, l, l, b.T, b.Q1, l, R);
+            else { view(c, pr, true, b.Q1, l, l, b.T, b.Q2, l, R); Q2cur = b.Q2; }
+            if (i >= 2 && i < pr.v) fork_estimate(c, b, pr, R, l, i);
+        }
+        finish(c, b, pr, b.Rv + (size_t)(pr.v - 1) * 4 * l2, l, b.Q1, l, Q2cur, l, d.even);
+        return;
+    }
+    // Alg. 4: ping-pong views, Krylov blocks stacked (range blocks for even v, co-range for odd)
+    const int64_t Wk = d.Wk, rs = d.stack_rows, sps = rs * Wk;
+    int i = 0;
+    auto stack_in = [&](const float* Qb, int slot) {
+        const int64_t c0 = (int64_t)slot * l;
+        if (c.dry || c0 >= Wk) return;
+        note(c, copy_planes_launch(Qb, l, rs * l, b.stack + c0, Wk, sps, rs, std::min(l, Wk - c0), nullptr, c.st));
+    };
+    for (int j = 1; j <= d.s; j++) {
+        double* R = b.Rv + (size_t)i * 4 * l2;
+        view(c, pr, false, Q2cur, l, l, b.T, b.Q1, l, R);
+        i++;
+        if (i >= 2) fork_estimate(c, b, pr, R, l, i);
+        if (d.even) stack_in(b.Q1, j - 1);
+        R = b.Rv + (size_t)i * 4 * l2;
+        view(c, pr, true, b.Q1, l, l, b.T, b.Q2, l, R);
+        i++;
+        fork_estimate(c, b, pr, R, l, i);
+        Q2cur = b.Q2;
+        if (!d.even) stack_in(b.Q2, j - 1);
+    }
+    if (d.even) {
+        double* R = b.Rv + (size_t)i * 4 * l2;
+        view(c, pr, false, Q2cur, l, l, b.T, b.Q1, l, R);
+        i++;
+        if (i >= 2) fork_estimate(c, b, pr, R, l, i);
+        stack_in(b.Q1, d.s);
+        orth_stack(c, b.stack, pr.m, Wk, l, b.Cbuf);
+        view(c, pr, true, b.stack, Wk, Wk, b.T, b.Q2, Wk, b.Rfin);
+        finish(c, b, pr, b.Rfin, Wk, b.stack, Wk, b.Q2, Wk, true);
+    } else {
+        orth_stack(c, b.stack, pr.n, Wk, l, b.Cbuf);
+        view(c, pr, false, b.stack, Wk, Wk, b.T, b.Q1, Wk, b.Rfin);
+        finish(c, b, pr, b.Rfin, Wk, b.Q1, Wk, b.stack, Wk, false);
+    }
+}
+
+void bind_ctx(Ctx& c, const Bufs& b, const Dims& d) {
+    c.status = b.status;
+    c.chol_work = b.chol_work;
+    c.G = b.G; c.R1 = b.R1; c.R2 = b.R2; c.Rt = b.Rt; c.Rinv = b.Rinv;
+    c.T2 = b.T2; c.T2_rows = d.rows_max;
+    c.Rjunk = b.Rfin;
+    c.scr.partial = b.partial;
+    c.scr.counters = b.counters;
+}
+
+// Sizes of the workspace pieces: run the solve dry to find the largest split-K scratch.
+void size_solve(const Problem& pr, const Dims& d, size_t* part, size_t* cnt, size_t* total) {
+    Ctx c;
+    c.dry = true;
+    Arena ar{nullptr, 0, 0, true};
+    Bufs b{};
+    carve(pr, d, ar, b, 0, 0);
+    bind_ctx(c, b, d);
+    run_solve(c, pr, d, b);
+    *part = c.part_need;
+    *cnt = c.cnt_need;
+    Arena ar2{nullptr, 0, 0, true};
+    Bufs b2{};
+    carve(pr, d, ar2, b2, c.part_need, c.cnt_need);
+    *total = ar2.used;
+}
+
+int check_problem(const Problem& pr) {
+    if (pr.m < 1 || pr.n < 1 || pr.k < 1 || pr.p < 0 || pr.v < 2) return QLRA_E_ARG;
+    if (pr.scheme != QLRA_SUBSPACE && pr.scheme != QLRA_BLOCK_KRYLOV) return QLRA_E_ARG;
+    const int64_t l = (int64_t)pr.k + pr.p;
+    if (l > pr.m || l > pr.n) return QLRA_E_ARG;
+    if (pr.v > 64) return QLRA_E_TOO_LARGE;
+    return QLRA_OK;
+}
+
+int check_layout(const void* P, int64_t rows, int64_t cols, int64_t ld, int64_t ps) {
+    if (!P) return QLRA_E_ARG;
+    if (ld < cols || ps < rows * ld) return QLRA_E_ARG;
+    return QLRA_OK;
+}
+
+}  // namespace
+}  // namespace qlra_impl
+
+using namespace qlra_impl;
+
+extern "C" {
+
+const char* qlra_strerror(int status) {
+    switch (status) {
+        case QLRA_OK: return "success";
+        case QLRA_E_ARG: return "invalid argument";
+        case QLRA_E_WORKSPACE: return "workspace missing, too small or misaligned";
+        case QLRA_E_HIP: return "HIP runtime error";
+        case QLRA_E_NUMERIC: return "numerical breakdown (non-finite data or failed Cholesky)";
+        case QLRA_E_TOO_LARGE: return "request larger than supported";
+        case QLRA_E_UNSUPPORTED: return "unsupported option";
+        default: return "unknown status";
+    }
+}
+
+int qlra_workspace_size(int64_t m, int64_t n, int k, int p, int pass_budget, int scheme, const qlra_opts_t* opts,
+                        size_t* bytes) {
+    if (!bytes) return QLRA_E_ARG;
+    Problem pr{};
+    pr.m = m; pr.n = n; pr.k = k; pr.p = p; pr.v = pass_budget; pr.scheme = scheme;
+    pr.lda = n; pr.aps = m * n; pr.ldu = k; pr.ups = m * k; pr.ldv = k; pr.vps = n * k;
+    pr.estimate = opts ? opts->estimate_passes : 1;
+    int rc = check_problem(pr);
+    if (rc) return rc;
+    if (opts && opts->pass_precision != QLRA_FP32) return QLRA_E_UNSUPPORTED;
+    const Dims d = dims_of(m, n, k, p, pass_budget, scheme);
+    size_t part, cnt, total;
+    size_solve(pr, d, &part, &cnt, &total);
+    *bytes = total;
+    return QLRA_OK;
+}
+
+int qlra(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stride, int k, int p,
+         int pass_budget, int scheme, uint64_t seed, const qlra_opts_t* opts, float* U, int64_t ldu,
+         int64_t u_plane_stride, double* S, float* V, int64_t ldv, int64_t v_plane_stride, double* pass_err) {
+    if (!opts) return QLRA_E_ARG;
+    Problem pr{};
+    pr.A = A; pr.m = m; pr.n = n; pr.lda = lda; pr.aps = a_plane_stride;
+    pr.k = k; pr.p = p; pr.v = pass_budget; pr.scheme = scheme; pr.seed = seed;
+    pr.U = U; pr.ldu = ldu; pr.ups = u_plane_stride; pr.S = S;
+    pr.V = V; pr.ldv = ldv; pr.vps = v_plane_stride;
+    pr.pass_err = pass_err;
+    pr.estimate = (opts->estimate_passes && pass_err) ? 1 : 0;
+    int rc = check_problem(pr);
+    if (rc) return rc;
+    if (opts->pass_precision != QLRA_FP32) return QLRA_E_UNSUPPORTED;
+    if ((rc = check_layout(A, m, n, lda, a_plane_stride))) return rc;
+    if ((rc = check_layout(U, m, k, ldu, u_plane_stride))) return rc;
+    if ((rc = check_layout(V, n, k, ldv, v_plane_stride))) return rc;
+    if (!S) return QLRA_E_ARG;
+    const Dims d = dims_of(m, n, k, p, pass_budget, scheme);
+    size_t part, cnt, total;
+    size_solve(pr, d, &part, &cnt, &total);
+    if (!opts->workspace || opts->workspace_bytes < total || ((uintptr_t)opts->workspace & 255))
+        return QLRA_E_WORKSPACE;
+    Arena ar{(char*)opts->workspace, opts->workspace_bytes, 0, false};
+    Bufs b{};
+    carve(pr, d, ar, b, part, cnt);
+    Ctx c;
+    c.st = (hipStream_t)opts->stream;
+    c.cnt_need = cnt;
+    bind_ctx(c, b, d);
+    Side sd;
+    if (pr.estimate) {
+        if (get_side(&sd) != hipSuccess) return QLRA_E_HIP;
+        c.side = sd.s; c.ev_fork = sd.fork; c.ev_join = sd.join;
+    }
+    run_solve(c, pr, d, b);
+    if (pr.estimate) {
+        note(c, hipEventRecord(c.ev_join, c.side));
+        note(c, hipStreamWaitEvent(c.st, c.ev_join, 0));
+    }
+    return c.err == hipSuccess ? QLRA_OK : QLRA_E_HIP;
+}
+
+int qlra_status(const void* workspace, void* stream, int* status) {
+    if (!workspace || !status) return QLRA_E_ARG;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return QLRA_E_HIP;
+    int word = 0;
+    if (hipMemcpy(&word, workspace, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return QLRA_E_HIP;
+    *status = (word & 2) ? QLRA_E_NUMERIC : QLRA_OK;
+    return QLRA_OK;
+}
+
+int qlra_omega(uint64_t seed, int64_t n, int64_t l, float* Om, int64_t ld, int64_t plane_stride, void* stream) {
+    if (n < 0 || l < 0) return QLRA_E_ARG;
+    if (n * l == 0) return QLRA_OK;
+    int rc = check_layout(Om, n, l, ld, plane_stride);
+    if (rc) return rc;
+    return omega_launch(seed, n, l, Om, ld, plane_stride, (hipStream_t)stream) == hipSuccess ? QLRA_OK : QLRA_E_HIP;
+}
+
+static QgemmDesc view_desc(int op, const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_ps, const float* B,
+                           int64_t w, int64_t ldb, int64_t b_ps, float* C, int64_t ldc, int64_t c_ps) {
+    return op == 0 ? desc(OP_NN, MATH_F32, A, lda, a_ps, 0, B, ldb, b_ps, 0, C, ldc, c_ps, 0, m, w, n)
+                   : desc(OP_HN, MATH_F32, A, lda, a_ps, 0, B, ldb, b_ps, 0, C, ldc, c_ps, 0, n, w, m);
+}
+
+int qlra_qgemm_workspace_size(int op, int64_t m, int64_t n, int64_t w, size_t* bytes) {
+    if (!bytes || (op != 0 && op != 1) || m < 0 || n < 0 || w < 0) return QLRA_E_ARG;
+    const QgemmDesc d = view_desc(op, nullptr, m, n, n, m * n, nullptr, w, w, 0, nullptr, w, 0);
+    Arena ar{nullptr, 0, 0, true};
+    ar.take(std::max<size_t>(qgemm_counter_count(d), 1) * sizeof(unsigned));
+    ar.take(qgemm_partial_bytes(d));
+    *bytes = ar.used;
+    return QLRA_OK;
+}
+
+int qlra_qgemm(int op, const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_ps, const float* B, int64_t w,
+               int64_t ldb, int64_t b_ps, float* C, int64_t ldc, int64_t c_ps, void* workspace,
+               size_t workspace_bytes, void* stream) {
+    if (op != 0 && op != 1) return QLRA_E_ARG;
+    if (m < 0 || n < 0 || w < 0) return QLRA_E_ARG;
+    const int64_t kdim = op == 0 ? n : m, rows = op == 0 ? m : n;
+    if (rows == 0 || w == 0) return QLRA_OK;
+    int rc;
+    if ((rc = check_layout(A, m, n, lda, a_ps))) return rc;
+    if ((rc = check_layout(B, kdim, w, ldb, b_ps))) return rc;
+    if ((rc = check_layout(C, rows, w, ldc, c_ps))) return rc;
+    size_t need = 0;
+    qlra_qgemm_workspace_size(op, m, n, w, &need);
+    if (workspace_bytes < need || (need > 0 && !workspace) || ((uintptr_t)workspace & 255)) return QLRA_E_WORKSPACE;
+    const QgemmDesc d = view_desc(op, A, m, n, lda, a_ps, B, w, ldb, b_ps, C, ldc, c_ps);
+    Arena ar{(char*)workspace, workspace_bytes, 0, false};
+    const size_t cnt = qgemm_counter_count(d);
+    QgemmScratch s{};
+    s.counters = (unsigned*)ar.take(std::max<size_t>(cnt, 1) * sizeof(unsigned));
+    s.partial = ar.take(qgemm_partial_bytes(d));
+    return qgemm_launch(d, s, (hipStream_t)stream) == hipSuccess ? QLRA_OK : QLRA_E_HIP;
+}
+
+// CholeskyQR workspace: status words, counters, Gram and factors, intermediate, qgemm scratch.
+static void cholqr_carve(int64_t m, int64_t w, Arena& ar, Ctx& c, size_t part, size_t cnt) {
+    const int64_t w2 = w * w;
+    c.status = (int*)ar.take(16 * sizeof(int));
+    c.scr.counters = (unsigned*)ar.take(std::max<size_t>(cnt, 1) * sizeof(unsigned));
+    c.G = (double*)ar.take(4 * w2 * sizeof(double));
+    c.R1 = (double*)ar.take(4 * w2 * sizeof(double));
+    c.R2 = (double*)ar.take(4 * w2 * sizeof(double));
+    c.Rt = (double*)ar.take(4 * w2 * sizeof(double));
+    c.Rinv = (double*)ar.take(4 * w2 * sizeof(double));
+    c.chol_work = (double*)ar.take(4 * w2 * sizeof(double));
+    c.T2 = (float*)ar.take(4 * m * w * sizeof(float));
+    c.T2_rows = m;
+    c.scr.partial = part ? ar.take(part) : nullptr;
+}
+
+static void cholqr_sizes(int64_t m, int64_t w, size_t* part, size_t* cnt, size_t* total) {
+    Ctx c;
+    c.dry = true;
+    Arena ar{nullptr, 0, 0, true};
+    cholqr_carve(m, w, ar, c, 0, 0);
+    cholqr(c, nullptr, m, w, w, m * w, nullptr, w, m * w, nullptr);
+    *part = c.part_need;
+    *cnt = c.cnt_need;
+    Arena ar2{nullptr, 0, 0, true};
+    Ctx c2;
+    c2.dry = true;
+    cholqr_carve(m, w, ar2, c2, *part, *cnt);
+    *total = ar2.used;
+}
+
+int qlra_cholqr_workspace_size(int64_t m, int64_t w, size_t* bytes) {
+    if (!bytes || w < 1 || m < w) return QLRA_E_ARG;
+    size_t part, cnt;
+    cholqr_sizes(m, w, &part, &cnt, bytes);
+    return QLRA_OK;
+}
+
+int qlra_cholqr(const float* Y, int64_t m, int64_t w, int64_t ldy, int64_t y_ps, float* Q, int64_t ldq,
+                int64_t q_ps, double* R, void* workspace, size_t workspace_bytes, void* stream) {
+    if (w < 1 || m < w || !R) return QLRA_E_ARG;
+    int rc;
+    if ((rc = check_layout(Y, m, w, ldy, y_ps))) return rc;
+    if ((rc = check_layout(Q, m, w, ldq, q_ps))) return rc;
+    size_t part, cnt, total;
+    cholqr_sizes(m, w, &part, &cnt, &total);
+    if (!workspace || workspace_bytes < total || ((uintptr_t)workspace & 255)) return QLRA_E_WORKSPACE;
+    Arena ar{(char*)workspace, workspace_bytes, 0, false};
+    Ctx c;
+    c.st = (hipStream_t)stream;
+    cholqr_carve(m, w, ar, c, part, cnt);
+    note(c, fill_int_launch(c.status, 16, 0, c.st));
+    note(c, fill_u32_launch(c.scr.counters, (int64_t)std::max<size_t>(cnt, 1), c.st));
+    cholqr(c, Y, m, w, ldy, y_ps, Q, ldq, q_ps, R);
+    return c.err == hipSuccess ? QLRA_OK : QLRA_E_HIP;
+}
+
+int qlra_qsvd_workspace_size(int64_t w, size_t* bytes) {
+    if (!bytes || w < 1) return QLRA_E_ARG;
+    *bytes = qsvd_work_doubles(w) * sizeof(double);
+    return QLRA_OK;
+}
+
+int qlra_qsvd(const double* R, int64_t w, double* Uh, double* S, double* Vh, void* workspace,
+              size_t workspace_bytes, void* stream) {
+    if (!R || !S || w < 1) return QLRA_E_ARG;
+    if (!workspace || workspace_bytes < qsvd_work_doubles(w) * sizeof(double) || ((uintptr_t)workspace & 7))
+        return QLRA_E_WORKSPACE;
+    return qsvd_launch(R, w, Uh, S, Vh, (double*)workspace, (Uh || Vh) ? 1 : 0, (hipStream_t)stream) == hipSuccess
+               ? QLRA_OK
+               : QLRA_E_HIP;
+}
+
+}  // extern "C"

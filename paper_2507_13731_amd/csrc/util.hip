@@ -1,0 +1,56 @@
+// Element-wise helpers: gated plane copies and fills used instead of memsets (they stay valid
+// inside captured HIP graphs).
+#include "common.h"
+
+namespace qlra_impl {
+namespace {
+
+__global__ __launch_bounds__(256) void k_copy_planes(const float* __restrict__ src, int64_t lds, int64_t sps,
+                                                     float* __restrict__ dst, int64_t ldd, int64_t dps,
+                                                     int64_t rows, int64_t cols, const int* gate) {
+    if (gate && *gate == 0) return;
+    const int64_t total = rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / cols, c = e - r * cols;
+#pragma unroll
+        for (int p = 0; p < 4; p++) dst[p * dps + r * ldd + c] = src[p * sps + r * lds + c];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill_int(int* p, int64_t count, int value) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) p[e] = value;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(unsigned* p, int64_t count) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) p[e] = 0u;
+}
+
+}  // namespace
+
+hipError_t copy_planes_launch(const float* src, int64_t lds, int64_t sps, float* dst, int64_t ldd, int64_t dps,
+                              int64_t rows, int64_t cols, const int* gate, hipStream_t st) {
+    const int64_t total = rows * cols;
+    if (total <= 0) return hipSuccess;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_copy_planes, dim3((unsigned)blocks), dim3(256), 0, st, src, lds, sps, dst, ldd, dps,
+                       rows, cols, gate);
+    return hipGetLastError();
+}
+
+hipError_t fill_int_launch(int* p, int64_t count, int value, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count, value);
+    return hipGetLastError();
+}
+
+hipError_t fill_u32_launch(unsigned* p, int64_t count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count);
+    return hipGetLastError();
+}
+
+}  // namespace qlra_impl

@@ -1,0 +1,209 @@
+"""Thin Python binding of libqlra.so (include/qlra.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP kernels.
+PyTorch provides device memory (tensors) and streams.  Quaternion matrices are tensors
+of shape (4, rows, cols) whose last dimension is contiguous: plane stride = stride(0),
+leading dimension = stride(1).
+
+The library must have been built (``python -m paper_2507_13731_amd.build`` or
+``__graft_entry__.build()``); importing this module without it raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqlra.so")
+
+QLRA_OK, QLRA_E_ARG, QLRA_E_WORKSPACE, QLRA_E_HIP, QLRA_E_NUMERIC, QLRA_E_TOO_LARGE, QLRA_E_UNSUPPORTED = range(7)
+QLRA_SUBSPACE, QLRA_BLOCK_KRYLOV = 0, 1
+QLRA_FP32, QLRA_BF16, QLRA_FP16 = 0, 1, 2
+SCHEMES = {"subspace": QLRA_SUBSPACE, "block_krylov": QLRA_BLOCK_KRYLOV, "krylov": QLRA_BLOCK_KRYLOV}
+
+
+class QlraError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {strerror(code)} (status {code})")
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("pass_precision", ctypes.c_int),
+                ("estimate_passes", ctypes.c_int),
+                ("stream", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build the HIP library first (paper_2507_13731_amd/build.py)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I = ctypes.c_int
+_SZ = ctypes.POINTER(ctypes.c_size_t)
+
+_lib.qlra_strerror.argtypes = [_I]
+_lib.qlra_strerror.restype = ctypes.c_char_p
+_lib.qlra_workspace_size.argtypes = [_I64, _I64, _I, _I, _I, _I, ctypes.POINTER(Opts), _SZ]
+_lib.qlra.argtypes = [_P, _I64, _I64, _I64, _I64, _I, _I, _I, _I, ctypes.c_uint64, ctypes.POINTER(Opts),
+                      _P, _I64, _I64, _P, _P, _I64, _I64, _P]
+_lib.qlra_status.argtypes = [_P, _P, ctypes.POINTER(_I)]
+_lib.qlra_omega.argtypes = [ctypes.c_uint64, _I64, _I64, _P, _I64, _I64, _P]
+_lib.qlra_qgemm_workspace_size.argtypes = [_I, _I64, _I64, _I64, _SZ]
+_lib.qlra_qgemm.argtypes = [_I, _P, _I64, _I64, _I64, _I64, _P, _I64, _I64, _I64, _P, _I64, _I64, _P,
+                            ctypes.c_size_t, _P]
+_lib.qlra_cholqr_workspace_size.argtypes = [_I64, _I64, _SZ]
+_lib.qlra_cholqr.argtypes = [_P, _I64, _I64, _I64, _I64, _P, _I64, _I64, _P, _P, ctypes.c_size_t, _P]
+_lib.qlra_qsvd_workspace_size.argtypes = [_I64, _SZ]
+_lib.qlra_qsvd.argtypes = [_P, _I64, _P, _P, _P, _P, ctypes.c_size_t, _P]
+for _name in ("qlra_workspace_size", "qlra", "qlra_status", "qlra_omega", "qlra_qgemm_workspace_size",
+              "qlra_qgemm", "qlra_cholqr_workspace_size", "qlra_cholqr", "qlra_qsvd_workspace_size", "qlra_qsvd"):
+    getattr(_lib, _name).restype = _I
+
+EXPORTS = ("qlra", "qlra_workspace_size", "qlra_status", "qlra_strerror", "qlra_omega", "qlra_qgemm",
+           "qlra_qgemm_workspace_size", "qlra_cholqr", "qlra_cholqr_workspace_size", "qlra_qsvd",
+           "qlra_qsvd_workspace_size")
+
+
+def strerror(code):
+    return _lib.qlra_strerror(int(code)).decode()
+
+
+def _check(rc, what):
+    if rc != QLRA_OK:
+        raise QlraError(rc, what)
+
+
+def _stream_ptr(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _planes(t, rows, cols, what, dtype=torch.float32):
+    if t.dtype != dtype or t.dim() != 3 or t.shape[0] != 4 or t.shape[1] != rows or t.shape[2] != cols:
+        raise ValueError(f"{what}: expected a (4, {rows}, {cols}) {dtype} tensor, got {tuple(t.shape)} {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{what}: expected a device tensor")
+    if cols > 1 and t.stride(2) != 1:
+        raise ValueError(f"{what}: the last dimension must be contiguous")
+    return ctypes.c_void_p(t.data_ptr()), t.stride(1) if rows > 1 else max(cols, 1), t.stride(0)
+
+
+def _workspace(nbytes, device):
+    # 256-byte alignment: the caching allocator returns 512-byte aligned blocks
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def qlra_workspace_size(m, n, k, p, pass_budget, scheme, estimate=True):
+    o = Opts(QLRA_FP32, 1 if estimate else 0, None, None, 0)
+    out = ctypes.c_size_t()
+    _check(_lib.qlra_workspace_size(m, n, k, p, pass_budget, SCHEMES.get(scheme, scheme), ctypes.byref(o),
+                                    ctypes.byref(out)), "qlra_workspace_size")
+    return out.value
+
+
+def qlra(A, k, p, pass_budget, scheme, seed, U=None, S=None, V=None, pass_err=None, workspace=None,
+         estimate=True, stream=None, precision=QLRA_FP32):
+    """Truncated QSVD of A (4, m, n) FP32 on the GPU: returns (U, S, V, pass_err, workspace).
+    Enqueued on `stream` (default: torch's current stream); no synchronisation."""
+    scheme = SCHEMES.get(scheme, scheme)
+    m, n = A.shape[1], A.shape[2]
+    dev = A.device
+    pa, lda, aps = _planes(A, m, n, "A")
+    if U is None:
+        U = torch.empty((4, m, k), dtype=torch.float32, device=dev)
+    if V is None:
+        V = torch.empty((4, n, k), dtype=torch.float32, device=dev)
+    if S is None:
+        S = torch.empty(k, dtype=torch.float64, device=dev)
+    if estimate and pass_err is None:
+        pass_err = torch.empty(pass_budget, dtype=torch.float64, device=dev)
+    pu, ldu, ups = _planes(U, m, k, "U")
+    pv, ldv, vps = _planes(V, n, k, "V")
+    need = qlra_workspace_size(m, n, k, p, pass_budget, scheme, estimate)
+    if workspace is None or workspace.numel() < need:
+        workspace = _workspace(need, dev)
+    o = Opts(precision, 1 if estimate else 0, _stream_ptr(stream), ctypes.c_void_p(workspace.data_ptr()),
+             workspace.numel())
+    rc = _lib.qlra(pa, m, n, lda, aps, k, p, pass_budget, scheme, ctypes.c_uint64(seed), ctypes.byref(o),
+                   pu, ldu, ups, ctypes.c_void_p(S.data_ptr()), pv, ldv, vps,
+                   ctypes.c_void_p(pass_err.data_ptr()) if pass_err is not None else None)
+    _check(rc, "qlra")
+    return U, S, V, pass_err, workspace
+
+
+def qlra_status(workspace, stream=None):
+    st = ctypes.c_int()
+    _check(_lib.qlra_status(ctypes.c_void_p(workspace.data_ptr()), _stream_ptr(stream), ctypes.byref(st)),
+           "qlra_status")
+    return st.value
+
+
+def qlra_omega(seed, n, l, out=None, stream=None, device="cuda"):
+    if out is None:
+        out = torch.empty((4, n, l), dtype=torch.float32, device=device)
+    po, ld, ps = _planes(out, n, l, "Om")
+    _check(_lib.qlra_omega(ctypes.c_uint64(seed), n, l, po, ld, ps, _stream_ptr(stream)), "qlra_omega")
+    return out
+
+
+def qlra_qgemm_workspace(op, m, n, w, device="cuda"):
+    """A zero-filled workspace for qlra_qgemm with these sizes (reusable across calls)."""
+    need = ctypes.c_size_t()
+    _check(_lib.qlra_qgemm_workspace_size(op, m, n, w, ctypes.byref(need)), "qlra_qgemm_workspace_size")
+    return torch.zeros(max(need.value, 1), dtype=torch.uint8, device=device)
+
+
+def qlra_qgemm(op, A, B, C=None, stream=None, workspace=None):
+    """op 0: C = A B (A m x n, B n x w); op 1: C = A^H B (B m x w)."""
+    m, n = A.shape[1], A.shape[2]
+    w = B.shape[2]
+    rows = m if op == 0 else n
+    kdim = n if op == 0 else m
+    if C is None:
+        C = torch.empty((4, rows, w), dtype=torch.float32, device=A.device)
+    pa, lda, aps = _planes(A, m, n, "A")
+    pb, ldb, bps = _planes(B, kdim, w, "B")
+    pc, ldc, cps = _planes(C, rows, w, "C")
+    ws = workspace if workspace is not None else qlra_qgemm_workspace(op, m, n, w, A.device)
+    _check(_lib.qlra_qgemm(op, pa, m, n, lda, aps, pb, w, ldb, bps, pc, ldc, cps, ctypes.c_void_p(ws.data_ptr()),
+                           ws.numel(), _stream_ptr(stream)), "qlra_qgemm")
+    return C
+
+
+def qlra_cholqr(Y, Q=None, stream=None, return_workspace=False):
+    m, w = Y.shape[1], Y.shape[2]
+    if Q is None:
+        Q = torch.empty((4, m, w), dtype=torch.float32, device=Y.device)
+    R = torch.empty((4, w, w), dtype=torch.float64, device=Y.device)
+    py, ldy, yps = _planes(Y, m, w, "Y")
+    pq, ldq, qps = _planes(Q, m, w, "Q")
+    need = ctypes.c_size_t()
+    _check(_lib.qlra_cholqr_workspace_size(m, w, ctypes.byref(need)), "qlra_cholqr_workspace_size")
+    ws = _workspace(need.value, Y.device)
+    _check(_lib.qlra_cholqr(py, m, w, ldy, yps, pq, ldq, qps, ctypes.c_void_p(R.data_ptr()),
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)), "qlra_cholqr")
+    if return_workspace:
+        return Q, R, ws
+    return Q, R
+
+
+def qlra_qsvd(R, vectors=True, stream=None):
+    w = R.shape[1]
+    R = R.contiguous()
+    if R.dtype != torch.float64 or tuple(R.shape) != (4, w, w):
+        raise ValueError("R must be a (4, w, w) float64 tensor")
+    S = torch.empty(w, dtype=torch.float64, device=R.device)
+    Uh = torch.empty((4, w, w), dtype=torch.float64, device=R.device) if vectors else None
+    Vh = torch.empty((4, w, w), dtype=torch.float64, device=R.device) if vectors else None
+    need = ctypes.c_size_t()
+    _check(_lib.qlra_qsvd_workspace_size(w, ctypes.byref(need)), "qlra_qsvd_workspace_size")
+    ws = _workspace(need.value, R.device)
+    _check(_lib.qlra_qsvd(ctypes.c_void_p(R.data_ptr()), w,
+                          ctypes.c_void_p(Uh.data_ptr()) if vectors else None, ctypes.c_void_p(S.data_ptr()),
+                          ctypes.c_void_p(Vh.data_ptr()) if vectors else None,
+                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)), "qlra_qsvd")
+    return Uh, S, Vh

@@ -1,0 +1,43 @@
+"""The C-ABI library loads without a GPU and exports every function include/qlra.h declares;
+argument checks that need no device run on the CPU."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "qlra.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(qlra\w*)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for required in ("qlra", "qlra_workspace_size", "qlra_status", "qlra_strerror", "qlra_omega", "qlra_qgemm",
+                     "qlra_cholqr", "qlra_qsvd"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2507_13731_amd import qlra as Q
+    lib = ctypes.CDLL(Q.LIB_PATH)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared()) == set(Q.EXPORTS)
+
+
+def test_workspace_size_and_argument_errors_without_gpu():
+    from paper_2507_13731_amd import qlra as Q
+    assert Q.qlra_workspace_size(2048, 2048, 50, 10, 6, "subspace") > 0
+    assert Q.qlra_workspace_size(16384, 16384, 128, 32, 8, "block_krylov") > 0
+    for args in [(10, 8, 0, 2, 2, 0), (10, 8, 3, -1, 2, 0), (10, 8, 3, 2, 1, 0), (10, 8, 7, 2, 2, 0),
+                 (10, 8, 3, 2, 2, 5)]:
+        try:
+            Q.qlra_workspace_size(*args)
+        except Q.QlraError as e:
+            assert e.code == Q.QLRA_E_ARG
+        else:
+            raise AssertionError(args)
+    assert Q.strerror(Q.QLRA_E_NUMERIC).startswith("numerical")
