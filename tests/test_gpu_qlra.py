@@ -126,7 +126,22 @@ def test_config2_krylov(gq, oracle):
     Ug, Sg, Vg, eg, st = run_gpu(gq, A, 64, 16, 6, 1, 2)
     assert st == gq.QLRA_OK
     Uo, So, Vo, eo = oracle.qlra(A.astype(np.float64), 64, 16, 6, 1, 2)
-    np.testing.assert_allclose(Sg, So, rtol=1e-4)
+    # FP32 view products carry an absolute error ~ u32 sqrt(K) sigma_1; with entries in [0, 1]
+    # sigma_1 ~ 1100 is a mean-field component far above the rest, so small singular values are
+    # compared absolutely against sigma_1.
+    np.testing.assert_allclose(Sg, So, rtol=1e-4, atol=4e-6 * So[0])
+    # That absolute error (~1e-3) exceeds the gaps between neighbouring sigma_j near j = 64, so
+    # the rank-64 truncation itself is not FP32-stable here; singular vectors are compared where
+    # the spectrum separates them (relative gap > 5 %).
+    # Perturbation bound: angle(u_j, u_j') <~ delta / gap_j with delta the absolute error above.
+    gap = np.minimum(np.r_[np.inf, So[:-1] - So[1:]], np.r_[So[:-1] - So[1:], np.inf])
+    sep = np.where(gap[:-1] / So[:-1] > 0.05)[0]
+    assert len(sep) >= 10
+    delta = 4e-6 * So[0]
+    for j in sep:
+        for X, Y in ((Ug, Uo), (Vg, Vo)):
+            ip = qref.mul(qref.adj(X[:, :, j:j + 1]), Y[:, :, j:j + 1])[:, 0, 0]
+            assert 1 - np.sqrt(np.sum(ip ** 2)) <= 0.5 * (3 * delta / gap[j]) ** 2 + 1e-6, j
     err_g = qref.fro(oracle_reconstruct(Ug, Sg, Vg) - A) / qref.fro(A)
     err_o = qref.fro(oracle_reconstruct(Uo, So, Vo) - A) / qref.fro(A)
     assert abs(err_g / err_o - 1) < 1e-3
