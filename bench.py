@@ -134,7 +134,7 @@ def main():
         for v in BUDGETS:
             o = outs[v]
             Q.qlra(A, K_RANK, P_OVER, v, "subspace", SEED_SKETCH, U=o["U"], S=o["S"], V=o["V"],
-                   pass_err=o["e"], workspace=o["ws"])
+                   pass_err=o["e"], workspace=o["ws"], graph=True)
 
     print(f"warmup {args.warmup} steps", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -161,7 +161,7 @@ def main():
         t1 = time.perf_counter()
         for _ in range(5):
             Q.qlra(A, K_RANK, P_OVER, v, "subspace", SEED_SKETCH, U=o["U"], S=o["S"], V=o["V"], pass_err=o["e"],
-                   workspace=o["ws"])
+                   workspace=o["ws"], graph=True)
         torch.cuda.synchronize()
         per_v[f"v{v}_ms"] = round((time.perf_counter() - t1) * 1e3 / 5, 4)
 

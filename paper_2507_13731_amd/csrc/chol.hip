@@ -1,8 +1,9 @@
 // Small FP64 kernels of the quaternion CholeskyQR (eq. (QQR) computed as Y = Q R with
 // R^H R = Y^H Y): the Hermitian quaternion Cholesky with a shifted retry, the triangular
-// inverse, and products of triangular factors.  One workgroup per factorization: the
-// matrices are l x l with l = k + p, tiny next to a pass over A; the latency chain, not the
-// arithmetic, is what costs here.
+// inverse, and products of triangular factors.  One workgroup per factorization: the matrices
+// are l x l with l = k + p, tiny next to a pass over A; the chain of dependent steps is what
+// costs, so for l <= kLdsMax the whole factor lives in LDS (packed upper triangle, four FP64
+// planes) and each step is one barrier-separated parallel update.
 #include "common.h"
 
 namespace qlra_impl {
@@ -18,6 +19,8 @@ __device__ __forceinline__ Q4 qmul(Q4 a, Q4 b) {   // eq. (1)
               a.w * b.z + a.x * b.y - a.y * b.x + a.z * b.w};
 }
 __device__ __forceinline__ Q4 qconj(Q4 a) { return Q4{a.w, -a.x, -a.y, -a.z}; }
+__device__ __forceinline__ Q4 qsub(Q4 a, Q4 b) { return Q4{a.w - b.w, a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ Q4 qscale(Q4 a, double s) { return Q4{a.w * s, a.x * s, a.y * s, a.z * s}; }
 __device__ __forceinline__ Q4 ld4(const double* P, int64_t ps, int64_t i) {
     return Q4{P[i], P[ps + i], P[2 * ps + i], P[3 * ps + i]};
 }
@@ -26,17 +29,179 @@ __device__ __forceinline__ void st4(double* P, int64_t ps, int64_t i, Q4 v) {
 }
 
 constexpr int kThreads = 1024;
+constexpr int kLdsMax = 96;                        // packed upper triangle of 96 x 96 in LDS
+constexpr int kPacked = kLdsMax * (kLdsMax + 1) / 2;
 
-// G (w x w Hermitian, full storage, FP64 planes) -> R upper triangular with real positive
-// diagonal, G + shift I = R^H R; Rinv = R^{-1}.  Right-looking: row j of R is row j of the
-// updated G divided by sqrt(pivot); the trailing block loses conj(R_ja) R_jb.
-__global__ __launch_bounds__(kThreads) void k_chol(const double* __restrict__ G, int w,
-                                                    double* __restrict__ R, double* __restrict__ Rinv,
-                                                    double* __restrict__ W, int* status,
-                                                    int* shift_out, const int* gate, int allow_shift,
-                                                    double shift_scale) {
+// LDS copy of an upper triangular quaternion matrix, packed by rows, four planes.
+struct Tri {
+    double* p;   // 4 * np doubles
+    int w, np;
+    __device__ __forceinline__ int idx(int a, int b) const { return a * w - (a * (a - 1)) / 2 + (b - a); }
+    __device__ __forceinline__ Q4 get(int a, int b) const {
+        const int i = idx(a, b);
+        return Q4{p[i], p[np + i], p[2 * np + i], p[3 * np + i]};
+    }
+    __device__ __forceinline__ void set(int a, int b, Q4 v) {
+        const int i = idx(a, b);
+        p[i] = v.w; p[np + i] = v.x; p[2 * np + i] = v.y; p[3 * np + i] = v.z;
+    }
+};
+
+// Cholesky, triangular inverse and optional product with an earlier factor, all in LDS.
+//   G (w x w Hermitian, full storage, FP64 planes):  G + shift I = R^H R
+//   R_out = R * Rprev (Rprev null: R_out = R);  Rinv = R^{-1}
+//   cond_gate (if non-null) := 1 when ||R||_F ||R^{-1}||_F > cond_limit, else 0.
+// Thread layout: 32 x 32 for element-wise updates (row ty, column tx), and 128 groups of 8
+// lanes for the dot products of the inverse and of the product with Rprev.
+__global__ __launch_bounds__(kThreads) void k_chol_lds(const double* __restrict__ G, int w,
+                                                        double* __restrict__ Rout, double* __restrict__ Rinv,
+                                                        const double* __restrict__ Rprev, int* status,
+                                                        int* shift_out, const int* gate, int allow_shift,
+                                                        double shift_scale, int* cond_gate, double cond_limit) {
+    __shared__ double lds[4 * kPacked];
     __shared__ int s_fail;
-    __shared__ double s_trace;
+    __shared__ double s_red[kThreads / 64][2];
+    if (gate && *gate == 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ty = tid >> 5, tx = tid & 31;        // 32 x 32
+    const int grp = tid >> 3, sub = tid & 7;       // 128 groups of 8
+    const int64_t ps = (int64_t)w * w;
+    const int np = w * (w + 1) / 2;
+    Tri T{lds, w, np};
+    double shift = 0.0;
+    int shifted = 0, failed = 0;
+    for (int attempt = 0; attempt < 2; attempt++) {
+        for (int a = ty; a < w; a += 32)
+            for (int b = a + tx; b < w; b += 32) {
+                Q4 v = ld4(G, ps, (int64_t)a * w + b);
+                if (a == b) { v.w += shift; v.x = v.y = v.z = 0.0; }
+                T.set(a, b, v);
+            }
+        if (tid == 0) s_fail = 0;
+        __syncthreads();
+        for (int j = 0; j < w; j++) {
+            const double d = T.get(j, j).w;
+            if (!(d > 0.0) || !(d < 1e300)) {   // breakdown or non-finite pivot (uniform branch)
+                if (tid == 0) s_fail = 1;
+                break;
+            }
+            const double rjj = sqrt(d), inv = 1.0 / rjj;
+            for (int b = j + 1 + tid; b < w; b += kThreads) T.set(j, b, qscale(T.get(j, b), inv));
+            __syncthreads();
+            // trailing update; the pivot entry itself is written here (nobody reads it now)
+            if (tid == 0) T.set(j, j, Q4{rjj, 0, 0, 0});
+            for (int a = j + 1 + ty; a < w; a += 32) {
+                const Q4 rja = qconj(T.get(j, a));
+                for (int b = a + tx; b < w; b += 32) {
+                    Q4 v = qsub(T.get(a, b), qmul(rja, T.get(j, b)));
+                    if (a == b) v.x = v.y = v.z = 0.0;
+                    T.set(a, b, v);
+                }
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+        if (!s_fail) break;
+        if (!allow_shift || attempt == 1) { failed = 1; break; }
+        // shifted CholeskyQR (Fukaya et al.): add shift_scale * trace(G) to the diagonal
+        double tr = 0.0;
+        for (int i = 0; i < w; i++) tr += G[(int64_t)i * w + i];
+        shift = shift_scale * tr;
+        if (!(shift > 0.0)) shift = 1e-300;
+        shifted = 1;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (shift_out) *shift_out = shifted;
+        if (failed) atomicOr(status, 2);
+    }
+    // R_out = R * Rprev (both upper triangular) or R.  Entry (a, b), a <= b, of the product is
+    // one 8-lane group's dot product; all entries are independent.
+    if (Rprev) {
+        for (int e = grp; e < w * w; e += kThreads / 8) {
+            const int a = e / w, b = e % w;
+            Q4 s{0, 0, 0, 0};
+            if (b >= a) {
+                for (int t = a + sub; t <= b; t += 8) {
+                    const Q4 pr = qmul(T.get(a, t), ld4(Rprev, ps, (int64_t)t * w + b));
+                    s.w += pr.w; s.x += pr.x; s.y += pr.y; s.z += pr.z;
+                }
+            }
+#pragma unroll
+            for (int o = 4; o > 0; o >>= 1) {
+                s.w += __shfl_xor(s.w, o, 64); s.x += __shfl_xor(s.x, o, 64);
+                s.y += __shfl_xor(s.y, o, 64); s.z += __shfl_xor(s.z, o, 64);
+            }
+            if (sub == 0) {
+                if (a == b) s.x = s.y = s.z = 0.0;
+                st4(Rout, ps, (int64_t)a * w + b, s);
+            }
+        }
+    } else {
+        for (int a = ty; a < w; a += 32)
+            for (int b = tx; b < w; b += 32) st4(Rout, ps, (int64_t)a * w + b, b >= a ? T.get(a, b) : Q4{0, 0, 0, 0});
+    }
+    // ||R||_F^2 for the conditioning estimate
+    double nr = 0.0;
+    for (int e = tid; e < np; e += kThreads) {
+        nr += lds[e] * lds[e] + lds[np + e] * lds[np + e] + lds[2 * np + e] * lds[2 * np + e] +
+              lds[3 * np + e] * lds[3 * np + e];
+    }
+    __syncthreads();
+    // In-place inverse, rows from the bottom: X_ii = 1/r_ii, X_ic = -(1/r_ii) sum_{t=i+1}^{c} R_it X_tc.
+    // Row i of R is read before it is overwritten (compute, barrier, write); each X_ic is one
+    // 8-lane group's dot product.
+    for (int i = w - 1; i >= 0; i--) {
+        const double rii = T.get(i, i).w;
+        const double inv = rii > 0.0 ? 1.0 / rii : 0.0;
+        const int c = i + 1 + grp;
+        Q4 s{0, 0, 0, 0};
+        if (c < w) {
+            for (int t = i + 1 + sub; t <= c; t += 8) {
+                const Q4 pr = qmul(T.get(i, t), T.get(t, c));
+                s.w += pr.w; s.x += pr.x; s.y += pr.y; s.z += pr.z;
+            }
+        }
+#pragma unroll
+        for (int o = 4; o > 0; o >>= 1) {
+            s.w += __shfl_xor(s.w, o, 64); s.x += __shfl_xor(s.x, o, 64);
+            s.y += __shfl_xor(s.y, o, 64); s.z += __shfl_xor(s.z, o, 64);
+        }
+        __syncthreads();
+        if (c < w && sub == 0) T.set(i, c, qscale(s, -inv));
+        if (tid == 0) T.set(i, i, Q4{inv, 0, 0, 0});
+        __syncthreads();
+    }
+    double ni = 0.0;
+    for (int a = ty; a < w; a += 32)
+        for (int b = tx; b < w; b += 32) {
+            const Q4 v = b >= a ? T.get(a, b) : Q4{0, 0, 0, 0};
+            if (Rinv) st4(Rinv, ps, (int64_t)a * w + b, v);
+            ni += v.w * v.w + v.x * v.x + v.y * v.y + v.z * v.z;
+        }
+    if (cond_gate) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            nr += __shfl_xor(nr, o, 64);
+            ni += __shfl_xor(ni, o, 64);
+        }
+        if (lane == 0) { s_red[wave][0] = nr; s_red[wave][1] = ni; }
+        __syncthreads();
+        if (tid == 0) {
+            double a = 0, b = 0;
+            for (int i = 0; i < kThreads / 64; i++) { a += s_red[i][0]; b += s_red[i][1]; }
+            *cond_gate = (failed || shifted || !(a * b <= cond_limit * cond_limit)) ? 1 : 0;
+        }
+    }
+}
+
+// Larger factors: the same algorithm on a scratch copy in global memory (L2 resident).
+__global__ __launch_bounds__(kThreads) void k_chol_global(const double* __restrict__ G, int w,
+                                                           double* __restrict__ Rout, double* __restrict__ Rinv,
+                                                           const double* __restrict__ Rprev, double* __restrict__ W,
+                                                           int* status, int* shift_out, const int* gate,
+                                                           int allow_shift, double shift_scale, int* cond_gate) {
+    __shared__ int s_fail;
     if (gate && *gate == 0) return;
     const int tid = threadIdx.x;
     const int64_t ps = (int64_t)w * w;
@@ -53,18 +218,15 @@ __global__ __launch_bounds__(kThreads) void k_chol(const double* __restrict__ G,
         __syncthreads();
         for (int j = 0; j < w; j++) {
             const double d = W[(int64_t)j * w + j];
-            if (!(d > 0.0) || !(d < 1e300)) {   // breakdown or non-finite pivot
+            if (!(d > 0.0) || !(d < 1e300)) {
                 if (tid == 0) s_fail = 1;
-                __syncthreads();
                 break;
             }
             const double rjj = sqrt(d), inv = 1.0 / rjj;
             __syncthreads();
             for (int c = j + 1 + tid; c < w; c += kThreads) {
                 const int64_t e = (int64_t)j * w + c;
-                Q4 v = ld4(W, ps, e);
-                v.w *= inv; v.x *= inv; v.y *= inv; v.z *= inv;
-                st4(W, ps, e, v);
+                st4(W, ps, e, qscale(ld4(W, ps, e), inv));
             }
             if (tid == 0) st4(W, ps, (int64_t)j * w + j, Q4{rjj, 0, 0, 0});
             __syncthreads();
@@ -72,27 +234,19 @@ __global__ __launch_bounds__(kThreads) void k_chol(const double* __restrict__ G,
             for (int64_t e = tid; e < (int64_t)t * t; e += kThreads) {
                 const int a = j + 1 + (int)(e / t), b = j + 1 + (int)(e % t);
                 if (b < a) continue;
-                const Q4 ra = qconj(ld4(W, ps, (int64_t)j * w + a));
-                const Q4 rb = ld4(W, ps, (int64_t)j * w + b);
-                const Q4 pr = qmul(ra, rb);
-                Q4 v = ld4(W, ps, (int64_t)a * w + b);
-                v.w -= pr.w; v.x -= pr.x; v.y -= pr.y; v.z -= pr.z;
+                const int64_t ab = (int64_t)a * w + b;
+                Q4 v = qsub(ld4(W, ps, ab), qmul(qconj(ld4(W, ps, (int64_t)j * w + a)), ld4(W, ps, (int64_t)j * w + b)));
                 if (a == b) v.x = v.y = v.z = 0.0;
-                st4(W, ps, (int64_t)a * w + b, v);
+                st4(W, ps, ab, v);
             }
             __syncthreads();
         }
         __syncthreads();
         if (!s_fail) break;
         if (!allow_shift || attempt == 1) { failed = 1; break; }
-        // Shifted CholeskyQR (Fukaya et al.): add s = shift_scale * trace(G) to the diagonal.
-        if (tid == 0) {
-            double tr = 0.0;
-            for (int i = 0; i < w; i++) tr += G[(int64_t)i * w + i];
-            s_trace = tr;
-        }
-        __syncthreads();
-        shift = shift_scale * s_trace;
+        double tr = 0.0;
+        for (int i = 0; i < w; i++) tr += G[(int64_t)i * w + i];
+        shift = shift_scale * tr;
         if (!(shift > 0.0)) shift = 1e-300;
         shifted = 1;
         __syncthreads();
@@ -100,31 +254,39 @@ __global__ __launch_bounds__(kThreads) void k_chol(const double* __restrict__ G,
     if (tid == 0) {
         if (shift_out) *shift_out = shifted;
         if (failed) atomicOr(status, 2);
+        if (cond_gate) *cond_gate = 1;    // large factors: always run the second round
     }
-    // R = upper(W)
     for (int64_t e = tid; e < ps; e += kThreads) {
         const int a = (int)(e / w), b = (int)(e % w);
-        st4(R, ps, e, b >= a ? ld4(W, ps, e) : Q4{0, 0, 0, 0});
+        Q4 v{0, 0, 0, 0};
+        if (b >= a) {
+            if (Rprev) {
+                for (int t = a; t <= b; t++) {
+                    const Q4 pr = qmul(ld4(W, ps, (int64_t)a * w + t), ld4(Rprev, ps, (int64_t)t * w + b));
+                    v.w += pr.w; v.x += pr.x; v.y += pr.y; v.z += pr.z;
+                }
+                if (a == b) v.x = v.y = v.z = 0.0;
+            } else {
+                v = ld4(W, ps, e);
+            }
+        }
+        st4(Rout, ps, e, v);
     }
-    __syncthreads();
     if (!Rinv) return;
-    // Rinv: rows from the bottom; Rinv_ii = 1 / r_ii, Rinv_ic = -(1/r_ii) sum_{t=i+1}^{c} R_it Rinv_tc.
+    __syncthreads();
     for (int64_t e = tid; e < ps; e += kThreads) st4(Rinv, ps, e, Q4{0, 0, 0, 0});
     __syncthreads();
     for (int i = w - 1; i >= 0; i--) {
-        const double rii = R[(int64_t)i * w + i];
+        const double rii = W[(int64_t)i * w + i];
         const double inv = rii > 0.0 ? 1.0 / rii : 0.0;
         for (int c = i + tid; c < w; c += kThreads) {
-            if (c == i) {
-                Rinv[(int64_t)i * w + i] = inv;
-                continue;
-            }
+            if (c == i) { Rinv[(int64_t)i * w + i] = inv; continue; }
             Q4 s{0, 0, 0, 0};
             for (int t = i + 1; t <= c; t++) {
-                const Q4 pr = qmul(ld4(R, ps, (int64_t)i * w + t), ld4(Rinv, ps, (int64_t)t * w + c));
+                const Q4 pr = qmul(ld4(W, ps, (int64_t)i * w + t), ld4(Rinv, ps, (int64_t)t * w + c));
                 s.w += pr.w; s.x += pr.x; s.y += pr.y; s.z += pr.z;
             }
-            st4(Rinv, ps, (int64_t)i * w + c, Q4{-inv * s.w, -inv * s.x, -inv * s.y, -inv * s.z});
+            st4(Rinv, ps, (int64_t)i * w + c, qscale(s, -inv));
         }
         __syncthreads();
     }
@@ -156,10 +318,18 @@ __global__ __launch_bounds__(256) void k_rcopy(const double* __restrict__ src, d
 
 }  // namespace
 
-hipError_t chol_launch(const double* G, int64_t w, double* R, double* Rinv, double* work, int* status,
-                       int* shift_out, const int* gate, int allow_shift, double shift_scale, hipStream_t st) {
-    hipLaunchKernelGGL(k_chol, dim3(1), dim3(kThreads), 0, st, G, (int)w, R, Rinv, work, status, shift_out,
-                       gate, allow_shift, shift_scale);
+int chol_lds_max() { return kLdsMax; }
+
+hipError_t chol_launch(const double* G, int64_t w, double* R, double* Rinv, const double* Rprev, double* work,
+                       int* status, int* shift_out, const int* gate, int allow_shift, double shift_scale,
+                       int* cond_gate, double cond_limit, hipStream_t st) {
+    if (w <= kLdsMax) {
+        hipLaunchKernelGGL(k_chol_lds, dim3(1), dim3(kThreads), 0, st, G, (int)w, R, Rinv, Rprev, status, shift_out,
+                           gate, allow_shift, shift_scale, cond_gate, cond_limit);
+    } else {
+        hipLaunchKernelGGL(k_chol_global, dim3(1), dim3(kThreads), 0, st, G, (int)w, R, Rinv, Rprev, work, status,
+                           shift_out, gate, allow_shift, shift_scale, cond_gate);
+    }
     return hipGetLastError();
 }
 

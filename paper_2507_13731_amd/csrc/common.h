@@ -69,14 +69,17 @@ hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t s
 hipError_t omega_launch(uint64_t seed, int64_t n, int64_t l, float* Om, int64_t ld, int64_t ps,
                         hipStream_t st);
 
-// Cholesky of a Hermitian quaternion Gram G (w x w FP64 planes, ld = w): G (+ shift I) = R^H R
-// and Rinv = R^{-1} (if non-null).  If the unshifted factorization breaks down and allow_shift
-// is set, it is redone with shift = shift_scale * trace(G) and *shift_out (if non-null) is set to
-// 1 (else 0).  A failure that remains ORs 2 into *status.  If gate is non-null and *gate == 0
-// nothing is done.  work: 4*w*w doubles.
-hipError_t chol_launch(const double* G, int64_t w, double* R, double* Rinv, double* work, int* status,
-                       int* shift_out, const int* gate, int allow_shift, double shift_scale,
-                       hipStream_t st);
+// Cholesky of a Hermitian quaternion Gram G (w x w FP64 planes, ld = w): G (+ shift I) = R^H R,
+// Rout = R * Rprev (Rprev null: Rout = R) and Rinv = R^{-1} (if non-null).  If the unshifted
+// factorization breaks down and allow_shift is set, it is redone with
+// shift = shift_scale * trace(G) and *shift_out (if non-null) is set to 1 (else 0).  A failure
+// that remains ORs 2 into *status.  cond_gate (if non-null) is set to 1 when
+// ||R||_F ||R^{-1}||_F > cond_limit or the shift was needed, else 0.  If gate is non-null and
+// *gate == 0 nothing is done.  work: 4*w*w doubles (used only for w > chol_lds_max()).
+hipError_t chol_launch(const double* G, int64_t w, double* Rout, double* Rinv, const double* Rprev,
+                       double* work, int* status, int* shift_out, const int* gate, int allow_shift,
+                       double shift_scale, int* cond_gate, double cond_limit, hipStream_t st);
+int chol_lds_max();
 // Rout = R2 * R1 (upper triangular w x w); nothing if gate && !*gate.
 hipError_t rmul_launch(const double* R2, const double* R1, double* Rout, int64_t w,
                        const int* gate, hipStream_t st);
@@ -86,6 +89,8 @@ hipError_t rcopy_launch(const double* src, double* dst, int64_t w, const int* ga
 // dst (rows x cols FP32 planes) = src, when gate is null or *gate != 0.
 hipError_t copy_planes_launch(const float* src, int64_t lds, int64_t sps, float* dst, int64_t ldd,
                               int64_t dps, int64_t rows, int64_t cols, const int* gate, hipStream_t st);
+// dst[0..count) = src[0..count) (FP64).
+hipError_t copy_f64_launch(const double* src, double* dst, int64_t count, hipStream_t st);
 // p[0..count) = value.
 hipError_t fill_int_launch(int* p, int64_t count, int value, hipStream_t st);
 hipError_t fill_u32_launch(unsigned* p, int64_t count, hipStream_t st);
@@ -95,6 +100,15 @@ hipError_t fill_u32_launch(unsigned* p, int64_t count, hipStream_t st);
 hipError_t qsvd_launch(const double* X, int64_t w, double* U, double* S, double* V, double* work,
                        int want_vectors, hipStream_t st);
 size_t qsvd_work_doubles(int64_t w);
+
+// Hermitian quaternion eigendecomposition of G (w x w FP64 planes, full storage): lam
+// descending, E eigenvectors as columns (may be null).  work: heig_work_doubles(w).
+hipError_t heig_launch(const double* G, int64_t w, double* lam, double* E, double* work, hipStream_t st);
+size_t heig_work_doubles(int64_t w);
+// QSVD of a small square X through the eigendecomposition of X^H X.
+hipError_t qsvd_gram_launch(const double* X, int64_t w, double* U, double* S, double* V, double* work,
+                            hipStream_t st);
+size_t qsvd_gram_work_doubles(int64_t w);
 
 // e = sqrt(max(0, nA2 - sum_{j<k} S_j^2) / nA2)
 hipError_t estimate_launch(const double* S, int k, const double* nA2, double* e, hipStream_t st);

@@ -10,17 +10,18 @@
 // never to A.
 //
 // Tiling (gfx950, wave64): a workgroup of 4 waves owns a BM x BN tile of all four output
-// planes; wave (wm, wn) owns RM x CN MFMA sub-tiles of 16 x 16 in every plane.  Per K step
-// the four planes of an A tile and of a B tile are staged through LDS with coalesced loads;
-// the MFMA A operand always comes from the A tile, so the same kernel serves A B (A tile stored
-// row-major) and A^H B (A tile stored k-major, i.e. transposed through LDS).  When there are
-// too few output tiles to fill 256 CUs, K is split across workgroups; partial tiles go to
-// scratch and the last workgroup of a tile (counter in scratch, reset after use) adds them in
-// split order, so results are deterministic.
+// planes; wave (wm, wn) owns RM x CN MFMA sub-tiles of 16 x 16 in every plane.  Per K step of
+// BK the four planes of an A tile and of a B tile are staged through LDS; the global loads of
+// step t+1 are issued into registers before the MFMAs of step t so that their latency hides
+// behind the matrix cores.  The MFMA A operand always comes from the A tile, stored row-major
+// for A B and k-major for A^H B (the transpose happens in the LDS staging), so one kernel
+// serves both orientations.  When the output tiles cannot fill 256 CUs, K is split across
+// workgroups; partial tiles go to scratch and a separate element-parallel kernel adds them in
+// split order (deterministic, no floating-point atomics).
 //
 // math = MATH_F32: FP32 operands, v_mfma_f32_16x16x4f32, FP32 accumulation.
 // math = MATH_F64: operands converted to FP64 in LDS (exact for FP32 data),
-//                  v_mfma_f64_16x16x4f64; used for Gram matrices and small triangular products.
+//                  v_mfma_f64_16x16x4f64; used for Gram matrices and small products.
 #include "common.h"
 
 #include <algorithm>
@@ -72,21 +73,43 @@ struct KParams {
     int splits;
     void* part;
     int64_t Mp, Np;
-    unsigned* counters;
     int store;
+    int avec, bvec;      // 4-element vector loads allowed for A / B
     const int* skip;
 };
+
+// Four consecutive elements (along the contiguous dimension) of a plane, zero outside
+// [0, valid).  Vector load when all four are valid and the layout allows it.
+template <class TG, class T>
+__device__ __forceinline__ void load4(const TG* __restrict__ p, int valid, bool vec, T out[4]) {
+    if (valid >= 4 && vec) {
+        if constexpr (sizeof(TG) == 4) {
+            const f32x4 v = *reinterpret_cast<const f32x4*>(p);
+            out[0] = (T)v[0]; out[1] = (T)v[1]; out[2] = (T)v[2]; out[3] = (T)v[3];
+        } else {
+            typedef double d2 __attribute__((ext_vector_type(2)));
+            const d2 v0 = reinterpret_cast<const d2*>(p)[0], v1 = reinterpret_cast<const d2*>(p)[1];
+            out[0] = (T)v0[0]; out[1] = (T)v0[1]; out[2] = (T)v1[0]; out[3] = (T)v1[1];
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; t++) out[t] = t < valid ? (T)p[t] : (T)0;
+    }
+}
 
 template <class T, int WM, int WN, int RM, int CN, int BK, bool ADJ, class TA, class TB, class TC>
 __global__ __launch_bounds__(256) void k_qgemm(KParams P) {
     static_assert(WM * WN == 4, "four waves");
+    static_assert(BK % 4 == 0, "BK");
     constexpr int BM = WM * RM * 16, BN = WN * CN * 16;
-    constexpr int AROWS = ADJ ? BK : BM;      // A tile rows in LDS
+    constexpr int AROWS = ADJ ? BK : BM;       // A tile rows in LDS
     constexpr int AST = ADJ ? BM + 4 : BK + 4; // A tile row stride (elements)
     constexpr int BST = BN + 4;
-    __shared__ T sA[4 * AROWS * AST];
-    __shared__ T sB[4 * BK * BST];
-    __shared__ int s_last;
+    // chunks of 4 contiguous elements per plane and their share per thread
+    constexpr int ACH = BM * BK / 4, BCH = BK * BN / 4;
+    constexpr int APT = (4 * ACH + 255) / 256, BPT = (4 * BCH + 255) / 256;
+    __shared__ __attribute__((aligned(16))) T sA[4 * AROWS * AST];
+    __shared__ __attribute__((aligned(16))) T sB[4 * BK * BST];
 
     if (P.skip && *P.skip == 0) return;
     using M_ = Mma<T>;
@@ -99,6 +122,7 @@ __global__ __launch_bounds__(256) void k_qgemm(KParams P) {
     const int64_t ke = P.K < kb + P.kchunk ? P.K : kb + P.kchunk;
     const TA* __restrict__ A = (const TA*)P.A;
     const TB* __restrict__ B = (const TB*)P.B;
+    const bool avec = P.avec != 0, bvec = P.bvec != 0;
 
     acc_t acc[RM][CN][4];
 #pragma unroll
@@ -108,40 +132,72 @@ __global__ __launch_bounds__(256) void k_qgemm(KParams P) {
 #pragma unroll
             for (int p = 0; p < 4; p++) acc[rm][cn][p] = acc_t{0, 0, 0, 0};
 
+    T ra[APT][4], rb[BPT][4];   // register stage of the next tiles
+
+    auto fetch = [&](int64_t k0) {
+#pragma unroll
+        for (int it = 0; it < APT; it++) {
+            const int ch = it * 256 + tid;
+            if (ch >= 4 * ACH) break;
+            const int q = ch / ACH, rem = ch % ACH;
+            if (!ADJ) {
+                const int r = rem / (BK / 4), kq = rem % (BK / 4);
+                const int64_t gr = row0 + r, gk = k0 + 4 * kq;
+                const int valid = gr < P.M ? (int)std::min<int64_t>(4, std::max<int64_t>(0, ke - gk)) : 0;
+                load4<TA, T>(A + q * P.aps + gr * P.lda + gk, valid, avec, ra[it]);
+            } else {
+                const int kk = rem / (BM / 4), cq = rem % (BM / 4);
+                const int64_t gk = k0 + kk, gr = row0 + 4 * cq;
+                const int valid = gk < ke ? (int)std::min<int64_t>(4, std::max<int64_t>(0, P.M - gr)) : 0;
+                load4<TA, T>(A + q * P.aps + gk * P.lda + gr, valid, avec, ra[it]);
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < BPT; it++) {
+            const int ch = it * 256 + tid;
+            if (ch >= 4 * BCH) break;
+            const int q = ch / BCH, rem = ch % BCH;
+            const int kk = rem / (BN / 4), cq = rem % (BN / 4);
+            const int64_t gk = k0 + kk, gc = col0 + 4 * cq;
+            const int valid = gk < ke ? (int)std::min<int64_t>(4, std::max<int64_t>(0, P.N - gc)) : 0;
+            load4<TB, T>(B + q * P.bps + gk * P.ldb + gc, valid, bvec, rb[it]);
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int it = 0; it < APT; it++) {
+            const int ch = it * 256 + tid;
+            if (ch >= 4 * ACH) break;
+            const int q = ch / ACH, rem = ch % ACH;
+            T* dst;
+            if (!ADJ) {
+                const int r = rem / (BK / 4), kq = rem % (BK / 4);
+                dst = &sA[(q * AROWS + r) * AST + 4 * kq];
+            } else {
+                const int kk = rem / (BM / 4), cq = rem % (BM / 4);
+                dst = &sA[(q * AROWS + kk) * AST + 4 * cq];
+            }
+            dst[0] = ra[it][0]; dst[1] = ra[it][1]; dst[2] = ra[it][2]; dst[3] = ra[it][3];
+        }
+#pragma unroll
+        for (int it = 0; it < BPT; it++) {
+            const int ch = it * 256 + tid;
+            if (ch >= 4 * BCH) break;
+            const int q = ch / BCH, rem = ch % BCH;
+            const int kk = rem / (BN / 4), cq = rem % (BN / 4);
+            T* dst = &sB[(q * BK + kk) * BST + 4 * cq];
+            dst[0] = rb[it][0]; dst[1] = rb[it][1]; dst[2] = rb[it][2]; dst[3] = rb[it][3];
+        }
+    };
+
     const int g = lane >> 4, r16 = lane & 15;
+    if (kb < ke) fetch(kb);
     for (int64_t k0 = kb; k0 < ke; k0 += BK) {
+        __syncthreads();          // previous tile fully consumed
+        stash();
         __syncthreads();
-        // ---- stage the four planes of the A tile
-        if (!ADJ) {
-            // A (M x K, k contiguous): LDS [q][r][kk]
-            for (int e = tid; e < 4 * BM * BK; e += 256) {
-                const int q = e / (BM * BK), rem = e % (BM * BK), r = rem / BK, kk = rem % BK;
-                const int64_t gr = row0 + r, gk = k0 + kk;
-                T v = 0;
-                if (gr < P.M && gk < ke) v = (T)A[q * P.aps + gr * P.lda + gk];
-                sA[(q * AROWS + r) * AST + kk] = v;
-            }
-        } else {
-            // A stored K x M (row of C = column of A, contiguous): LDS [q][kk][r]
-            for (int e = tid; e < 4 * BM * BK; e += 256) {
-                const int q = e / (BM * BK), rem = e % (BM * BK), kk = rem / BM, r = rem % BM;
-                const int64_t gr = row0 + r, gk = k0 + kk;
-                T v = 0;
-                if (gr < P.M && gk < ke) v = (T)A[q * P.aps + gk * P.lda + gr];
-                sA[(q * AROWS + kk) * AST + r] = v;
-            }
-        }
-        // ---- stage the four planes of the B tile (K x N, n contiguous): LDS [q][kk][c]
-        for (int e = tid; e < 4 * BK * BN; e += 256) {
-            const int q = e / (BK * BN), rem = e % (BK * BN), kk = rem / BN, c = rem % BN;
-            const int64_t gk = k0 + kk, gc = col0 + c;
-            T v = 0;
-            if (gk < ke && gc < P.N) v = (T)B[q * P.bps + gk * P.ldb + gc];
-            sB[(q * BK + kk) * BST + c] = v;
-        }
-        __syncthreads();
-        // ---- 16 plane products per (row sub-tile, column sub-tile), 4 k per MFMA
-#pragma unroll 2
+        if (k0 + BK < ke) fetch(k0 + BK);   // in flight during the MFMAs below
+#pragma unroll
         for (int ks = 0; ks < BK; ks += 4) {
             T a[4][RM];
 #pragma unroll
@@ -151,29 +207,33 @@ __global__ __launch_bounds__(256) void k_qgemm(KParams P) {
                     const int r = (wm * RM + rm) * 16 + r16, kk = ks + g;
                     a[q][rm] = ADJ ? sA[(q * AROWS + kk) * AST + r] : sA[(q * AROWS + r) * AST + kk];
                 }
+            T b[CN][4], nb[CN][4];
 #pragma unroll
             for (int cn = 0; cn < CN; cn++) {
                 const int c = (wn * CN + cn) * 16 + r16;
-                T b[4], nb[4];
 #pragma unroll
                 for (int q = 0; q < 4; q++) {
-                    b[q] = sB[(q * BK + ks + g) * BST + c];
-                    nb[q] = -b[q];
+                    b[cn][q] = sB[(q * BK + ks + g) * BST + c];
+                    nb[cn][q] = -b[cn][q];
                 }
+            }
+            // q outermost: consecutive MFMAs update different accumulators
+#pragma unroll
+            for (int q = 0; q < 4; q++)
 #pragma unroll
                 for (int rm = 0; rm < RM; rm++)
 #pragma unroll
-                    for (int p = 0; p < 4; p++)
+                    for (int cn = 0; cn < CN; cn++)
 #pragma unroll
-                        for (int q = 0; q < 4; q++)
-                            acc[rm][cn][p] = M_::mma(a[q][rm], term_sign<ADJ>(p, q) > 0 ? b[p ^ q] : nb[p ^ q],
+                        for (int p = 0; p < 4; p++)
+                            acc[rm][cn][p] = M_::mma(a[q][rm],
+                                                     term_sign<ADJ>(p, q) > 0 ? b[cn][p ^ q] : nb[cn][p ^ q],
                                                      acc[rm][cn][p]);
-            }
         }
     }
 
-    TC* __restrict__ C = (TC*)P.C;
     if (P.splits == 1) {
+        TC* __restrict__ C = (TC*)P.C;
 #pragma unroll
         for (int rm = 0; rm < RM; rm++)
 #pragma unroll
@@ -193,8 +253,7 @@ __global__ __launch_bounds__(256) void k_qgemm(KParams P) {
                 }
         return;
     }
-
-    // ---- split K: publish the partial tile, the last workgroup of the tile reduces
+    // split K: publish this split's partial tile
     T* __restrict__ part = (T*)P.part;
 #pragma unroll
     for (int rm = 0; rm < RM; rm++)
@@ -208,26 +267,37 @@ __global__ __launch_bounds__(256) void k_qgemm(KParams P) {
                 for (int p = 0; p < 4; p++)
                     part[(((int64_t)split * 4 + p) * P.Mp + r) * P.Np + c] = acc[rm][cn][p][i];
             }
-    __threadfence();
-    __syncthreads();
-    const int tile = blockIdx.y * gridDim.x + blockIdx.x;
-    if (tid == 0) {
-        const unsigned prev = atomicAdd(&P.counters[tile], 1u);
-        s_last = (prev == (unsigned)(P.splits - 1));
+}
+
+// C (M x N, 4 planes) = sum over splits of the partial tiles.  Eight lanes per output entry
+// each add every eighth split in order, then the eight sums are combined in a fixed tree:
+// deterministic, and enough independent loads in flight to stream the partials.
+template <class T, class TC>
+__global__ __launch_bounds__(256) void k_splitk_reduce(const T* __restrict__ part, int splits, int64_t Mp, int64_t Np,
+                                                       TC* __restrict__ C, int64_t ldc, int64_t cps, int64_t M,
+                                                       int64_t N, int store, const int* skip) {
+    if (skip && *skip == 0) return;
+    const int64_t total = 4 * M * N;
+    const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+    const int sub = threadIdx.x & 7;
+    const bool act = e < total;
+    T s = 0;
+    int64_t p = 0, r = 0, c = 0;
+    if (act) {
+        p = e / (M * N);
+        const int64_t rem = e - p * M * N;
+        r = rem / N;
+        c = rem - r * N;
+        const int64_t stride = 4 * Mp * Np;
+        const T* src = part + (p * Mp + r) * Np + c;
+        for (int sp = sub; sp < splits; sp += 8) s += src[sp * stride];
     }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    for (int e = tid; e < 4 * BM * BN; e += 256) {
-        const int p = e / (BM * BN), rem = e % (BM * BN), rr = rem / BN, cc = rem % BN;
-        const int64_t r = row0 + rr, c = col0 + cc;
-        if (r >= P.M || c >= P.N) continue;
-        T s = 0;
-        for (int sp = 0; sp < P.splits; sp++) s += part[(((int64_t)sp * 4 + p) * P.Mp + r) * P.Np + c];
-        TC* dst = C + p * P.cps + r * P.ldc + c;
-        *dst = P.store == ST_SUB ? (TC)((T)*dst - s) : (TC)s;
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) s += __shfl_xor(s, o, 64);
+    if (act && sub == 0) {
+        TC* dst = C + p * cps + r * ldc + c;
+        *dst = store == ST_SUB ? (TC)((T)*dst - s) : (TC)s;
     }
-    if (tid == 0) P.counters[tile] = 0u;
 }
 
 // ------------------------------------------------------------------------------------------
@@ -248,10 +318,13 @@ Plan make_plan(const QgemmDesc& d) {
         p.CN = (int)std::max<int64_t>(1, cn_needed);
         const int64_t gy = (d.N + 16 * p.CN - 1) / (16 * p.CN);
         p.RM = ((d.M + 127) / 128) * gy >= kCUs ? 2 : 1;
+    } else if (d.op == OP_HN) {
+        // Gram-like products: small M x N output, long K; 32 x 32 tiles so that K splits
+        // spread the FP64 MFMA work over many CUs
+        p.BK = 16; p.WM = 2; p.WN = 2; p.RM = 1; p.CN = 1;
     } else {
-        p.BK = 16;
-        if (d.op == OP_HN) { p.WM = 2; p.WN = 2; p.RM = 1; p.CN = 2; }   // Gram-like: small M, N
-        else { p.WM = 1; p.WN = 4; p.RM = 1; p.CN = 1; }                 // tall times small
+        // tall times small (applies, projections, back-multiplication)
+        p.BK = 16; p.WM = 1; p.WN = 4; p.RM = 1; p.CN = 1;
     }
     const int64_t BM = p.WM * p.RM * 16, BN = p.WN * p.CN * 16;
     p.gx = (d.M + BM - 1) / BM;
@@ -259,9 +332,11 @@ Plan make_plan(const QgemmDesc& d) {
     p.Mp = p.gx * BM;
     p.Np = p.gy * BN;
     const int64_t tiles = p.gx * p.gy;
+    // split K so that about 256 workgroups run, each over at least 4 (F32) or 2 (F64) K steps
+    const int64_t min_steps = d.math == MATH_F32 ? 4 : 2;
     int64_t splits = 1;
-    if (tiles < kCUs && d.K > 4 * p.BK) {
-        splits = std::min<int64_t>((2 * kCUs + tiles - 1) / tiles, (d.K + 4 * p.BK - 1) / (4 * p.BK));
+    if (tiles < kCUs) {
+        splits = std::min<int64_t>((kCUs + tiles - 1) / tiles, (d.K + min_steps * p.BK - 1) / (min_steps * p.BK));
         splits = std::max<int64_t>(splits, 1);
     }
     int64_t kchunk = (d.K + splits - 1) / splits;
@@ -278,6 +353,12 @@ template <class T, int WM, int WN, int RM, int CN, int BK, bool ADJ, class TA, c
 hipError_t launch_t(const Plan& pl, const KParams& kp, hipStream_t st) {
     dim3 grid((unsigned)pl.gx, (unsigned)pl.gy, (unsigned)pl.splits);
     hipLaunchKernelGGL((k_qgemm<T, WM, WN, RM, CN, BK, ADJ, TA, TB, TC>), grid, dim3(256), 0, st, kp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || pl.splits == 1) return e;
+    const int64_t total = 8 * 4 * kp.M * kp.N;
+    hipLaunchKernelGGL((k_splitk_reduce<T, TC>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       (const T*)kp.part, (int)pl.splits, pl.Mp, pl.Np, (TC*)kp.C, kp.ldc, kp.cps, kp.M, kp.N,
+                       kp.store, kp.skip);
     return hipGetLastError();
 }
 
@@ -291,6 +372,10 @@ hipError_t launch_f32(const Plan& pl, const KParams& kp, hipStream_t st) {
     return hipErrorInvalidValue;
 }
 
+bool vec_ok(const void* p, int64_t ld, int64_t ps, size_t el) {
+    return ((uintptr_t)p % 16) == 0 && ld % 4 == 0 && ps % 4 == 0 && (el == 4 || el == 8);
+}
+
 }  // namespace
 
 size_t qgemm_partial_bytes(const QgemmDesc& d) {
@@ -300,10 +385,7 @@ size_t qgemm_partial_bytes(const QgemmDesc& d) {
     return (size_t)p.splits * 4 * (size_t)p.Mp * (size_t)p.Np * el;
 }
 
-size_t qgemm_counter_count(const QgemmDesc& d) {
-    const Plan p = make_plan(d);
-    return p.splits <= 1 ? 0 : (size_t)(p.gx * p.gy);
-}
+size_t qgemm_counter_count(const QgemmDesc&) { return 0; }
 
 hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t st) {
     if (d.M <= 0 || d.N <= 0) return hipSuccess;
@@ -315,10 +397,11 @@ hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t s
     kp.M = d.M; kp.N = d.N; kp.K = d.K;
     kp.kchunk = pl.kchunk; kp.splits = (int)pl.splits;
     kp.part = s.partial; kp.Mp = pl.Mp; kp.Np = pl.Np;
-    kp.counters = s.counters;
     kp.store = d.store;
     kp.skip = d.skip_flag;
-    if (pl.splits > 1 && (!s.partial || !s.counters)) return hipErrorInvalidValue;
+    kp.avec = vec_ok(d.A, d.lda, d.aps, d.a_f64 ? 8 : 4);
+    kp.bvec = vec_ok(d.B, d.ldb, d.bps, d.b_f64 ? 8 : 4);
+    if (pl.splits > 1 && !s.partial) return hipErrorInvalidValue;
     if (d.math == MATH_F32) {
         if (d.a_f64 || d.b_f64 || d.c_f64) return hipErrorInvalidValue;
         return d.op == OP_HN ? launch_f32<true>(pl, kp, st) : launch_f32<false>(pl, kp, st);
@@ -326,9 +409,9 @@ hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t s
     // FP64 arithmetic
     if (d.op == OP_HN) {
         if (!d.a_f64 && !d.b_f64 && d.c_f64)
-            return launch_t<double, 2, 2, 1, 2, 16, true, float, float, double>(pl, kp, st);
+            return launch_t<double, 2, 2, 1, 1, 16, true, float, float, double>(pl, kp, st);
         if (d.a_f64 && d.b_f64 && d.c_f64)
-            return launch_t<double, 2, 2, 1, 2, 16, true, double, double, double>(pl, kp, st);
+            return launch_t<double, 2, 2, 1, 1, 16, true, double, double, double>(pl, kp, st);
         return hipErrorInvalidValue;
     }
     if (!d.a_f64 && d.b_f64 && !d.c_f64)

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "common.h"
 
@@ -72,40 +73,40 @@ double shift_scale(int64_t rows, int64_t w) {
     return 11.0 * ((double)rows * w + (double)w * (w + 1)) * 1.1102230246251565e-16;
 }
 
-// Thin QR of Y (rows x w) by CholeskyQR2 with a gated shifted third round: Q (ld ldq, plane
-// stride qps) and R (w x w FP64, ld w).  Q may alias Y.
+// Thin QR of Y (rows x w): Q (ld ldq, plane stride qps) and R (w x w FP64, ld w), Q may alias Y.
+// Each round is CholeskyQR with an FP64 Gram (exact products of FP32 data), FP64 Cholesky and
+// an FP64 application of R^{-1}.  With an FP64 Cholesky the orthogonality error of one round is
+// about u64 cond(Y)^2 + u32, so for the views (cond(Y) <= 1e4, the FP32 storage of Q dominating)
+// one round suffices; rounds = 2 is CholeskyQR2, used where the basis is returned or stacked.
+// A breakdown in the first round is retried with a shift (shifted CholeskyQR).
 void cholqr(Ctx& c, const float* Y, int64_t rows, int64_t w, int64_t ldy, int64_t yps, float* Q, int64_t ldq,
-            int64_t qps, double* R) {
+            int64_t qps, double* R, int rounds) {
     const int64_t tps = rows * w;
-    int* gate = c.status ? c.status + 1 : nullptr;
-    // round 1: G = Y^H Y; G = R1^H R1; Z = Y R1^{-1}
-    qg(c, desc(OP_HN, MATH_F64, Y, ldy, yps, 0, Y, ldy, yps, 0, c.G, w, w * w, 1, w, w, rows));
-    if (!c.dry) note(c, chol_launch(c.G, w, c.R1, c.Rinv, c.chol_work, c.status, gate, nullptr, 1,
-                                    shift_scale(rows, w), c.st));
-    qg(c, desc(OP_NN, MATH_F64, Y, ldy, yps, 0, c.Rinv, w, w * w, 1, c.T2, w, tps, 0, rows, w, w));
-    // round 2: Z = Q R2
-    qg(c, desc(OP_HN, MATH_F64, c.T2, w, tps, 0, c.T2, w, tps, 0, c.G, w, w * w, 1, w, w, rows));
-    if (!c.dry) note(c, chol_launch(c.G, w, c.R2, c.Rinv, c.chol_work, c.status, nullptr, nullptr, 0, 0.0, c.st));
-    qg(c, desc(OP_NN, MATH_F64, c.T2, w, tps, 0, c.Rinv, w, w * w, 1, Q, ldq, qps, 0, rows, w, w));
-    if (!c.dry) note(c, rmul_launch(c.R2, c.R1, R, w, nullptr, c.st));
-    // round 3, only when round 1 had to be shifted: Q <- Q R3^{-1}, R <- R3 R
-    qg(c, desc(OP_HN, MATH_F64, Q, ldq, qps, 0, Q, ldq, qps, 0, c.G, w, w * w, 1, w, w, rows, ST_SET, gate));
-    if (!c.dry) {
-        note(c, chol_launch(c.G, w, c.R2, c.Rinv, c.chol_work, c.status, nullptr, gate, 0, 0.0, c.st));
-    }
-    qg(c, desc(OP_NN, MATH_F64, Q, ldq, qps, 0, c.Rinv, w, w * w, 1, c.T2, w, tps, 0, rows, w, w, ST_SET, gate));
-    if (!c.dry) {
-        note(c, copy_planes_launch(c.T2, w, tps, Q, ldq, qps, rows, w, gate, c.st));
-        note(c, rmul_launch(c.R2, R, c.Rt, w, gate, c.st));
-        note(c, rcopy_launch(c.Rt, R, w, gate, c.st));
+    int* shifted = c.status ? c.status + 1 : nullptr;
+    const double* Rprev = nullptr;
+    const float* src = Y;
+    int64_t lds = ldy, sps = yps;
+    for (int round = 0; round < rounds; round++) {
+        const bool last = round == rounds - 1;
+        float* dst = last ? Q : c.T2;
+        const int64_t ldd = last ? ldq : w, dps = last ? qps : tps;
+        double* Rout = last ? R : (round == 0 ? c.R1 : c.R2);
+        qg(c, desc(OP_HN, MATH_F64, src, lds, sps, 0, src, lds, sps, 0, c.G, w, w * w, 1, w, w, rows));
+        if (!c.dry)
+            note(c, chol_launch(c.G, w, Rout, c.Rinv, Rprev, c.chol_work, c.status, round == 0 ? shifted : nullptr,
+                                nullptr, round == 0 ? 1 : 0, shift_scale(rows, w), nullptr, 0.0, c.st));
+        qg(c, desc(OP_NN, MATH_F64, src, lds, sps, 0, c.Rinv, w, w * w, 1, dst, ldd, dps, 0, rows, w, w));
+        Rprev = Rout;
+        src = dst; lds = ldd; sps = dps;
     }
 }
 
-// Orthonormalise the columns of a stack of blocks (rows x W, ld W) whose blocks of width l are
-// each already orthonormal: block Gram-Schmidt with reorthogonalisation (two projections
-// against all earlier blocks), then CholeskyQR2 of the block in place.
+// Orthonormalise the columns of a stack of blocks (rows x W, ld W) of width l: CholeskyQR2 of
+// the first block, then for each further block block Gram-Schmidt with reorthogonalisation (two
+// projections against all earlier blocks) and CholeskyQR2 of the block in place.
 void orth_stack(Ctx& c, float* K, int64_t rows, int64_t W, int64_t l, double* Cbuf) {
     const int64_t kps = rows * W;
+    cholqr(c, K, rows, std::min(l, W), W, kps, K, W, kps, c.Rjunk, 2);
     for (int64_t b0 = l; b0 < W; b0 += l) {
         const int64_t lb = std::min(l, W - b0);
         float* Z = K + b0;
@@ -114,7 +115,7 @@ void orth_stack(Ctx& c, float* K, int64_t rows, int64_t W, int64_t l, double* Cb
             qg(c, desc(OP_HN, MATH_F64, K, W, kps, 0, Z, W, kps, 0, Cbuf, lb, b0 * lb, 1, b0, lb, rows));
             qg(c, desc(OP_NN, MATH_F64, K, W, kps, 0, Cbuf, lb, b0 * lb, 1, Z, W, kps, 0, rows, lb, b0, ST_SUB));
         }
-        cholqr(c, Z, rows, lb, W, kps, Z, W, kps, c.Rjunk);
+        cholqr(c, Z, rows, lb, W, kps, Z, W, kps, c.Rjunk, 2);
     }
 }
 
@@ -232,6 +233,39 @@ hipError_t get_side(Side* out) {
     return hipSuccess;
 }
 
+// Captured solves, replayed when a call repeats with identical arguments (same buffers).
+struct GraphKey {
+    int dev;
+    const void* A; int64_t m, n, lda, aps;
+    int k, p, v, scheme, estimate;
+    uint64_t seed;
+    const void* U; int64_t ldu, ups;
+    const void* S;
+    const void* V; int64_t ldv, vps;
+    const void* pass_err;
+    const void* ws;
+    bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
+};
+struct GraphEntry {
+    GraphKey key;
+    hipGraphExec_t exec;
+    uint64_t last;
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;
+uint64_t g_graph_clock = 0;
+hipStream_t g_capture[64] = {};
+constexpr size_t kMaxGraphs = 32;
+
+hipError_t get_capture_stream(int dev, hipStream_t* out) {
+    if (!g_capture[dev]) {
+        hipError_t e = hipStreamCreateWithFlags(&g_capture[dev], hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+    }
+    *out = g_capture[dev];
+    return hipSuccess;
+}
+
 // Side-stream estimate of view `i` (1-based) from its R (l x l).
 void fork_estimate(Ctx& c, const Bufs& b, const Problem& pr, const double* R, int64_t l, int i) {
     if (c.dry || !pr.estimate) return;
@@ -257,19 +291,19 @@ void finish(Ctx& c, const Bufs& b, const Problem& pr, const double* R, int64_t w
     qg(c, desc(OP_NN, MATH_F64, Q2, ldq2, pr.n * ldq2, 0, Vh, w, w * w, 1, pr.V, pr.ldv, pr.vps, 0, pr.n, k, w));
     if (!c.dry) {
         note(c, phase_launch(pr.U, pr.m, pr.ldu, pr.ups, pr.V, pr.n, pr.ldv, pr.vps, k, c.st));
-        note(c, hipMemcpyAsync(pr.S, b.Sw, sizeof(double) * k, hipMemcpyDeviceToDevice, c.st));
+        note(c, copy_f64_launch(b.Sw, pr.S, k, c.st));
     }
 }
 
 // One view: C = A X (forward) or C = A^H X (adjoint), then its QR.
 void view(Ctx& c, const Problem& pr, bool adjoint, const float* X, int64_t ldx, int64_t w, float* T, float* Q,
-          int64_t ldq, double* R) {
+          int64_t ldq, double* R, int rounds = 1) {
     const int64_t rows_out = adjoint ? pr.n : pr.m;
     const int64_t kdim = adjoint ? pr.m : pr.n;
     const int64_t xps = kdim * ldx;
     qg(c, desc(adjoint ? OP_HN : OP_NN, MATH_F32, pr.A, pr.lda, pr.aps, 0, X, ldx, xps, 0, T, w, rows_out * w, 0,
                rows_out, w, kdim));
-    cholqr(c, T, rows_out, w, w, rows_out * w, Q, ldq, rows_out * ldq, R);
+    cholqr(c, T, rows_out, w, w, rows_out * w, Q, ldq, rows_out * ldq, R, rounds);
 }
 
 void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
@@ -286,8 +320,10 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
         // Alg. 2: odd views [Q1, R1] = QR(A Q2), even views [Q2, R2] = QR(A^H Q1)
         for (int i = 1; i <= pr.v; i++) {
             double* R = b.Rv + (size_t)(i - 1) * 4 * l2;
-            if (i % 2 == 1) view(c, pr, false, Q2cur, l, l, b.T, b.Q1, l, R);
-            else { view(c, pr, true, b.Q1, l, l, b.T, b.Q2, l, R); Q2cur = b.Q2; }
+            // the last two views produce the returned bases: CholeskyQR2 there
+            const int rounds = i >= pr.v - 1 ? 2 : 1;
+            if (i % 2 == 1) view(c, pr, false, Q2cur, l, l, b.T, b.Q1, l, R, rounds);
+            else { view(c, pr, true, b.Q1, l, l, b.T, b.Q2, l, R, rounds); Q2cur = b.Q2; }
             if (i >= 2 && i < pr.v) fork_estimate(c, b, pr, R, l, i);
         }
         finish(c, b, pr, b.Rv + (size_t)(pr.v - 1) * 4 * l2, l, b.Q1, l, Q2cur, l, d.even);
@@ -321,11 +357,11 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
         if (i >= 2) fork_estimate(c, b, pr, R, l, i);
         stack_in(b.Q1, d.s);
         orth_stack(c, b.stack, pr.m, Wk, l, b.Cbuf);
-        view(c, pr, true, b.stack, Wk, Wk, b.T, b.Q2, Wk, b.Rfin);
+        view(c, pr, true, b.stack, Wk, Wk, b.T, b.Q2, Wk, b.Rfin, 2);
         finish(c, b, pr, b.Rfin, Wk, b.stack, Wk, b.Q2, Wk, true);
     } else {
         orth_stack(c, b.stack, pr.n, Wk, l, b.Cbuf);
-        view(c, pr, false, b.stack, Wk, Wk, b.T, b.Q1, Wk, b.Rfin);
+        view(c, pr, false, b.stack, Wk, Wk, b.T, b.Q1, Wk, b.Rfin, 2);
         finish(c, b, pr, b.Rfin, Wk, b.Q1, Wk, b.stack, Wk, false);
     }
 }
@@ -444,12 +480,58 @@ int qlra(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stri
         if (get_side(&sd) != hipSuccess) return QLRA_E_HIP;
         c.side = sd.s; c.ev_fork = sd.fork; c.ev_join = sd.join;
     }
-    run_solve(c, pr, d, b);
-    if (pr.estimate) {
-        note(c, hipEventRecord(c.ev_join, c.side));
-        note(c, hipStreamWaitEvent(c.st, c.ev_join, 0));
+    auto enqueue = [&]() {
+        run_solve(c, pr, d, b);
+        if (pr.estimate) {
+            note(c, hipEventRecord(c.ev_join, c.side));
+            note(c, hipStreamWaitEvent(c.st, c.ev_join, 0));
+        }
+    };
+    if (!opts->graph) {
+        enqueue();
+        return c.err == hipSuccess ? QLRA_OK : QLRA_E_HIP;
     }
-    return c.err == hipSuccess ? QLRA_OK : QLRA_E_HIP;
+    // graph path: replay a captured solve with the same arguments, or capture one
+    GraphKey key;
+    std::memset(&key, 0, sizeof(key));
+    if (hipGetDevice(&key.dev) != hipSuccess || key.dev < 0 || key.dev >= 64) return QLRA_E_HIP;
+    key.A = A; key.m = m; key.n = n; key.lda = lda; key.aps = a_plane_stride;
+    key.k = k; key.p = p; key.v = pass_budget; key.scheme = scheme; key.estimate = pr.estimate; key.seed = seed;
+    key.U = U; key.ldu = ldu; key.ups = u_plane_stride; key.S = S; key.V = V; key.ldv = ldv;
+    key.vps = v_plane_stride; key.pass_err = pass_err; key.ws = opts->workspace;
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto& ge : g_graphs) {
+        if (ge.key == key) {
+            ge.last = ++g_graph_clock;
+            return hipGraphLaunch(ge.exec, (hipStream_t)opts->stream) == hipSuccess ? QLRA_OK : QLRA_E_HIP;
+        }
+    }
+    hipStream_t cap;
+    if (get_capture_stream(key.dev, &cap) != hipSuccess) return QLRA_E_HIP;
+    c.st = cap;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return QLRA_E_HIP;
+    enqueue();
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(cap, &graph);
+    if (c.err != hipSuccess || ee != hipSuccess || !graph) {
+        if (graph) hipGraphDestroy(graph);
+        return QLRA_E_HIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (ie != hipSuccess) return QLRA_E_HIP;
+    if (g_graphs.size() >= kMaxGraphs) {
+        size_t lru = 0;
+        for (size_t i = 1; i < g_graphs.size(); i++)
+            if (g_graphs[i].last < g_graphs[lru].last) lru = i;
+        // the evicted graph may still be in flight on some stream
+        if (hipDeviceSynchronize() != hipSuccess) return QLRA_E_HIP;
+        hipGraphExecDestroy(g_graphs[lru].exec);
+        g_graphs.erase(g_graphs.begin() + (long)lru);
+    }
+    g_graphs.push_back(GraphEntry{key, exec, ++g_graph_clock});
+    return hipGraphLaunch(exec, (hipStream_t)opts->stream) == hipSuccess ? QLRA_OK : QLRA_E_HIP;
 }
 
 int qlra_status(const void* workspace, void* stream, int* status) {
@@ -529,7 +611,7 @@ static void cholqr_sizes(int64_t m, int64_t w, size_t* part, size_t* cnt, size_t
     c.dry = true;
     Arena ar{nullptr, 0, 0, true};
     cholqr_carve(m, w, ar, c, 0, 0);
-    cholqr(c, nullptr, m, w, w, m * w, nullptr, w, m * w, nullptr);
+    cholqr(c, nullptr, m, w, w, m * w, nullptr, w, m * w, nullptr, 2);
     *part = c.part_need;
     *cnt = c.cnt_need;
     Arena ar2{nullptr, 0, 0, true};
@@ -561,7 +643,7 @@ int qlra_cholqr(const float* Y, int64_t m, int64_t w, int64_t ldy, int64_t y_ps,
     cholqr_carve(m, w, ar, c, part, cnt);
     note(c, fill_int_launch(c.status, 16, 0, c.st));
     note(c, fill_u32_launch(c.scr.counters, (int64_t)std::max<size_t>(cnt, 1), c.st));
-    cholqr(c, Y, m, w, ldy, y_ps, Q, ldq, q_ps, R);
+    cholqr(c, Y, m, w, ldy, y_ps, Q, ldq, q_ps, R, 2);
     return c.err == hipSuccess ? QLRA_OK : QLRA_E_HIP;
 }
 

@@ -18,6 +18,12 @@ __global__ __launch_bounds__(256) void k_copy_planes(const float* __restrict__ s
     }
 }
 
+__global__ __launch_bounds__(256) void k_copy_f64(const double* __restrict__ src, double* __restrict__ dst,
+                                                  int64_t count) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < count) dst[e] = src[e];
+}
+
 __global__ __launch_bounds__(256) void k_fill_int(int* p, int64_t count, int value) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < count) p[e] = value;
@@ -38,6 +44,12 @@ hipError_t copy_planes_launch(const float* src, int64_t lds, int64_t sps, float*
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_copy_planes, dim3((unsigned)blocks), dim3(256), 0, st, src, lds, sps, dst, ldd, dps,
                        rows, cols, gate);
+    return hipGetLastError();
+}
+
+hipError_t copy_f64_launch(const double* src, double* dst, int64_t count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_f64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, src, dst, count);
     return hipGetLastError();
 }
 

@@ -33,7 +33,8 @@ class Opts(ctypes.Structure):
                 ("estimate_passes", ctypes.c_int),
                 ("stream", ctypes.c_void_p),
                 ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t),
+                ("graph", ctypes.c_int)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -98,7 +99,7 @@ def _workspace(nbytes, device):
 
 
 def qlra_workspace_size(m, n, k, p, pass_budget, scheme, estimate=True):
-    o = Opts(QLRA_FP32, 1 if estimate else 0, None, None, 0)
+    o = Opts(QLRA_FP32, 1 if estimate else 0, None, None, 0, 0)
     out = ctypes.c_size_t()
     _check(_lib.qlra_workspace_size(m, n, k, p, pass_budget, SCHEMES.get(scheme, scheme), ctypes.byref(o),
                                     ctypes.byref(out)), "qlra_workspace_size")
@@ -106,7 +107,7 @@ def qlra_workspace_size(m, n, k, p, pass_budget, scheme, estimate=True):
 
 
 def qlra(A, k, p, pass_budget, scheme, seed, U=None, S=None, V=None, pass_err=None, workspace=None,
-         estimate=True, stream=None, precision=QLRA_FP32):
+         estimate=True, stream=None, precision=QLRA_FP32, graph=False):
     """Truncated QSVD of A (4, m, n) FP32 on the GPU: returns (U, S, V, pass_err, workspace).
     Enqueued on `stream` (default: torch's current stream); no synchronisation."""
     scheme = SCHEMES.get(scheme, scheme)
@@ -127,7 +128,7 @@ def qlra(A, k, p, pass_budget, scheme, seed, U=None, S=None, V=None, pass_err=No
     if workspace is None or workspace.numel() < need:
         workspace = _workspace(need, dev)
     o = Opts(precision, 1 if estimate else 0, _stream_ptr(stream), ctypes.c_void_p(workspace.data_ptr()),
-             workspace.numel())
+             workspace.numel(), 1 if graph else 0)
     rc = _lib.qlra(pa, m, n, lda, aps, k, p, pass_budget, scheme, ctypes.c_uint64(seed), ctypes.byref(o),
                    pu, ldu, ups, ctypes.c_void_p(S.data_ptr()), pv, ldv, vps,
                    ctypes.c_void_p(pass_err.data_ptr()) if pass_err is not None else None)
