@@ -47,15 +47,15 @@ struct Tri {
     }
 };
 
-// Cholesky, triangular inverse and optional product with an earlier factor, all in LDS.
+// Cholesky and triangular inverse, all in LDS.
 //   G (w x w Hermitian, full storage, FP64 planes):  G + shift I = R^H R
-//   R_out = R * Rprev (Rprev null: R_out = R);  Rinv = R^{-1}
+//   R_out = R;  Rinv = R^{-1}
 //   cond_gate (if non-null) := 1 when ||R||_F ||R^{-1}||_F > cond_limit, else 0.
 // Thread layout: 32 x 32 for element-wise updates (row ty, column tx), and 128 groups of 8
-// lanes for the dot products of the inverse and of the product with Rprev.
+// lanes for the dot products of the inverse.
 __global__ __launch_bounds__(kThreads) void k_chol_lds(const double* __restrict__ G, int w,
                                                         double* __restrict__ Rout, double* __restrict__ Rinv,
-                                                        const double* __restrict__ Rprev, int* status,
+                                                        int* status,
                                                         int* shift_out, const int* gate, int allow_shift,
                                                         double shift_scale, int* cond_gate, double cond_limit) {
     __shared__ double lds[4 * kPacked];
@@ -115,32 +115,9 @@ __global__ __launch_bounds__(kThreads) void k_chol_lds(const double* __restrict_
         if (shift_out) *shift_out = shifted;
         if (failed) atomicOr(status, 2);
     }
-    // R_out = R * Rprev (both upper triangular) or R.  Entry (a, b), a <= b, of the product is
-    // one 8-lane group's dot product; all entries are independent.
-    if (Rprev) {
-        for (int e = grp; e < w * w; e += kThreads / 8) {
-            const int a = e / w, b = e % w;
-            Q4 s{0, 0, 0, 0};
-            if (b >= a) {
-                for (int t = a + sub; t <= b; t += 8) {
-                    const Q4 pr = qmul(T.get(a, t), ld4(Rprev, ps, (int64_t)t * w + b));
-                    s.w += pr.w; s.x += pr.x; s.y += pr.y; s.z += pr.z;
-                }
-            }
-#pragma unroll
-            for (int o = 4; o > 0; o >>= 1) {
-                s.w += __shfl_xor(s.w, o, 64); s.x += __shfl_xor(s.x, o, 64);
-                s.y += __shfl_xor(s.y, o, 64); s.z += __shfl_xor(s.z, o, 64);
-            }
-            if (sub == 0) {
-                if (a == b) s.x = s.y = s.z = 0.0;
-                st4(Rout, ps, (int64_t)a * w + b, s);
-            }
-        }
-    } else {
-        for (int a = ty; a < w; a += 32)
-            for (int b = tx; b < w; b += 32) st4(Rout, ps, (int64_t)a * w + b, b >= a ? T.get(a, b) : Q4{0, 0, 0, 0});
-    }
+    // R_out = R (the product with an earlier factor, if any, is formed by k_rmul afterwards)
+    for (int a = ty; a < w; a += 32)
+        for (int b = tx; b < w; b += 32) st4(Rout, ps, (int64_t)a * w + b, b >= a ? T.get(a, b) : Q4{0, 0, 0, 0});
     // ||R||_F^2 for the conditioning estimate
     double nr = 0.0;
     for (int e = tid; e < np; e += kThreads) {
@@ -324,8 +301,15 @@ hipError_t chol_launch(const double* G, int64_t w, double* R, double* Rinv, cons
                        int* status, int* shift_out, const int* gate, int allow_shift, double shift_scale,
                        int* cond_gate, double cond_limit, hipStream_t st) {
     if (w <= kLdsMax) {
-        hipLaunchKernelGGL(k_chol_lds, dim3(1), dim3(kThreads), 0, st, G, (int)w, R, Rinv, Rprev, status, shift_out,
-                           gate, allow_shift, shift_scale, cond_gate, cond_limit);
+        // with an earlier factor: the new factor goes to `work`, then R = work * Rprev
+        double* Rnew = Rprev ? work : R;
+        hipLaunchKernelGGL(k_chol_lds, dim3(1), dim3(kThreads), 0, st, G, (int)w, Rnew, Rinv, status,
+                           shift_out, gate, allow_shift, shift_scale, cond_gate, cond_limit);
+        if (Rprev) {
+            const int64_t n = w * w;
+            hipLaunchKernelGGL(k_rmul, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const double*)Rnew, Rprev,
+                               R, (int)w, gate);
+        }
     } else {
         hipLaunchKernelGGL(k_chol_global, dim3(1), dim3(kThreads), 0, st, G, (int)w, R, Rinv, Rprev, work, status,
                            shift_out, gate, allow_shift, shift_scale, cond_gate);

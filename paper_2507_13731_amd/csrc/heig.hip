@@ -12,8 +12,9 @@
 //     tridiagonal (the structure-preserving counterpart of reducing the complex adjoint).
 //  2. Eigenvalues of T by multisection with Sturm counts from the division-free three-term
 //     recurrence of the characteristic polynomials (rescaled to stay in range).
-//  3. Eigenvectors of T by inverse iteration (tridiagonal LU with partial pivoting),
-//     re-orthogonalised inside clusters of close eigenvalues.
+//  3. Eigenvectors of T from twisted factorisations (forward and backward pivots of T - mu,
+//     twist index of least |gamma|; inverse iteration with a tridiagonal LU for widths above
+//     the LDS limit), re-orthogonalised inside clusters of close eigenvalues.
 //  4. Back-transformation y = Q D x with the stored reflectors.
 // Storage: the lower triangle of G, packed by rows, four planes; in LDS for w <= kHeigLds,
 // otherwise in the caller's scratch (L2 resident).  Reflector v_j overwrites column j below
@@ -98,6 +99,277 @@ __device__ int sturm_count(const double* d, const double* b2, int w, double x) {
     return cnt;
 }
 
+// Scratch of the eigensolver (w <= kHeigLds): everything the dependent steps touch is in LDS.
+struct HeigLds {
+    double G[4 * kLdsPacked];          // lower triangle, reflectors below the subdiagonal
+    double P[4 * kHeigLds];            // p, then q
+    double tau[kHeigLds], sq[4 * kHeigLds], ph[4 * kHeigLds];
+    double dg[kHeigLds], b[kHeigLds], b2[kHeigLds], lasc[kHeigLds];
+    double X[kHeigLds * kHeigLds];     // eigenvectors of T, column k at X + k * kHeigLds
+    double piv[kHeigLds * kHeigLds];   // forward pivots of the twisted factorisations
+    double red[HT / 64];
+    double bnd[2];
+};
+
+// Eigendecomposition for w <= kHeigLds, all scratch in LDS.
+__global__ __launch_bounds__(HT) void k_heig_lds(const double* __restrict__ Gin, int w, double* __restrict__ lam,
+                                                 double* __restrict__ E) {
+    __shared__ HeigLds L;
+    const int tid = threadIdx.x;
+    const int ty = tid >> 5, tx = tid & 31;
+    const int grp8 = tid >> 3, sub8 = tid & 7;
+    const int np = w * (w + 1) / 2;
+    Low G{L.G, np};
+    double* P = L.P;
+    const int64_t gps = (int64_t)w * w;
+    for (int i = ty; i < w; i += 32)
+        for (int t = tx; t <= i; t += 32) {
+            const int64_t e = (int64_t)i * w + t;
+            Q4 v{Gin[e], Gin[gps + e], Gin[2 * gps + e], Gin[3 * gps + e]};
+            if (i == t) v.x = v.y = v.z = 0.0;
+            G.set(i, t, v);
+        }
+    __syncthreads();
+
+    // ---- 1. tridiagonalisation
+    for (int j = 0; j + 2 < w; j++) {
+        double part = 0.0;
+        for (int i = j + 1 + tid; i < w; i += HT) part += qn2(G.get(i, j));
+        const double alpha2 = block_sum(part, L.red);
+        const Q4 x1 = G.get(j + 1, j);
+        const double ax1 = sqrt(qn2(x1));
+        const double alpha = sqrt(alpha2);
+        const Q4 phi = ax1 > 0.0 ? qscale(x1, 1.0 / ax1) : Q4{1, 0, 0, 0};
+        const bool live = alpha > 0.0;
+        const double tj = live ? 2.0 / (2.0 * alpha * (alpha + ax1)) : 0.0;
+        __syncthreads();                           // everyone has read x1 before v_0 replaces it
+        if (tid == 0) {
+            L.tau[j] = tj;
+            const Q4 s = qscale(phi, -alpha);      // H x = -alpha phi e_1
+            L.sq[j] = s.w; L.sq[kHeigLds + j] = s.x; L.sq[2 * kHeigLds + j] = s.y; L.sq[3 * kHeigLds + j] = s.z;
+            if (live) G.set(j + 1, j, qadd(x1, qscale(phi, alpha)));
+        }
+        __syncthreads();
+        if (!live) continue;                       // uniform: alpha is a block-wide value
+        // p_i = tau sum_t G22(i, t) v_t over i, t in [j+1, w); 8 lanes per row
+        for (int i = j + 1 + grp8; i < w; i += HT / 8) {
+            Q4 s{0, 0, 0, 0};
+            for (int t = j + 1 + sub8; t < w; t += 8) s = qadd(s, qmul(G.herm(i, t), G.get(t, j)));
+#pragma unroll
+            for (int o = 4; o > 0; o >>= 1) {
+                s.w += __shfl_xor(s.w, o, 64); s.x += __shfl_xor(s.x, o, 64);
+                s.y += __shfl_xor(s.y, o, 64); s.z += __shfl_xor(s.z, o, 64);
+            }
+            if (sub8 == 0) {
+                P[i] = tj * s.w; P[kHeigLds + i] = tj * s.x; P[2 * kHeigLds + i] = tj * s.y; P[3 * kHeigLds + i] = tj * s.z;
+            }
+        }
+        __syncthreads();
+        double kp = 0.0;
+        for (int i = j + 1 + tid; i < w; i += HT)
+            kp += qdot(G.get(i, j), Q4{P[i], P[kHeigLds + i], P[2 * kHeigLds + i], P[3 * kHeigLds + i]});
+        const double K = 0.5 * tj * block_sum(kp, L.red);
+        for (int i = j + 1 + tid; i < w; i += HT) {
+            const Q4 v = G.get(i, j);
+            P[i] -= K * v.w; P[kHeigLds + i] -= K * v.x; P[2 * kHeigLds + i] -= K * v.y; P[3 * kHeigLds + i] -= K * v.z;
+        }
+        __syncthreads();
+        // G22 -= v q^H + q v^H on the lower triangle
+        for (int i = j + 1 + ty; i < w; i += 32) {
+            const Q4 vi = G.get(i, j), qi{P[i], P[kHeigLds + i], P[2 * kHeigLds + i], P[3 * kHeigLds + i]};
+            for (int t = j + 1 + tx; t <= i; t += 32) {
+                const Q4 vt = G.get(t, j), qt{P[t], P[kHeigLds + t], P[2 * kHeigLds + t], P[3 * kHeigLds + t]};
+                Q4 g = qsub(qsub(G.get(i, t), qmul(vi, qconj(qt))), qmul(qi, qconj(vt)));
+                if (i == t) g.x = g.y = g.z = 0.0;
+                G.set(i, t, g);
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (w >= 2) {
+            const Q4 s = G.get(w - 1, w - 2);
+            L.sq[w - 2] = s.w; L.sq[kHeigLds + w - 2] = s.x; L.sq[2 * kHeigLds + w - 2] = s.y;
+            L.sq[3 * kHeigLds + w - 2] = s.z;
+            L.tau[w - 2] = 0.0;
+        }
+        L.tau[w - 1] = 0.0;
+        Q4 pj{1, 0, 0, 0};
+        double lo = 1e300, hi = -1e300;
+        for (int i = 0; i < w; i++) {
+            L.dg[i] = G.get(i, i).w;
+            L.ph[i] = pj.w; L.ph[kHeigLds + i] = pj.x; L.ph[2 * kHeigLds + i] = pj.y; L.ph[3 * kHeigLds + i] = pj.z;
+            double bl = 0.0, br = 0.0;
+            L.b[i] = 0.0; L.b2[i] = 0.0;
+            if (i + 1 < w) {
+                const Q4 s{L.sq[i], L.sq[kHeigLds + i], L.sq[2 * kHeigLds + i], L.sq[3 * kHeigLds + i]};
+                const double bs = sqrt(qn2(s));
+                L.b[i] = bs;
+                L.b2[i] = bs * bs;
+                br = bs;
+                pj = bs > 0.0 ? qscale(qmul(s, pj), 1.0 / bs) : Q4{1, 0, 0, 0};
+            }
+            if (i > 0) bl = L.b[i - 1];
+            lo = fmin(lo, L.dg[i] - bl - br);
+            hi = fmax(hi, L.dg[i] + bl + br);
+        }
+        const double pad = 1e-14 * fmax(fabs(lo), fabs(hi)) + 1e-300;
+        L.bnd[0] = lo - pad;
+        L.bnd[1] = hi + pad;
+    }
+    __syncthreads();
+
+    // ---- 2. eigenvalues: 16 lanes per eigenvalue, 17-section per round
+    {
+        const int g16 = tid >> 4, s16 = tid & 15;
+        const int k = g16;                         // ascending index, w <= 64 = HT / 16
+        double a = L.bnd[0], bb = L.bnd[1];
+        for (int round = 0; round < 20; round++) {
+            const double x = a + (bb - a) * (double)(s16 + 1) / 17.0;
+            const int c = k < w ? sturm_count(L.dg, L.b2, w, x) : 0;
+            const unsigned long long m = __ballot(c > k);
+            const unsigned grpmask = (unsigned)((m >> ((tid & 63) & ~15)) & 0xFFFFull);
+            const int first = grpmask ? __builtin_ctz(grpmask) : 16;
+            const double xa = first == 0 ? a : a + (bb - a) * (double)first / 17.0;
+            const double xb = first == 16 ? bb : a + (bb - a) * (double)(first + 1) / 17.0;
+            a = xa;
+            bb = xb;
+        }
+        if (k < w && s16 == 0) L.lasc[k] = 0.5 * (a + bb);
+    }
+    __syncthreads();
+    for (int k = tid; k < w; k += HT) lam[k] = L.lasc[w - 1 - k];    // descending
+    if (!E) return;
+
+    // ---- 3. eigenvectors of T by twisted factorisations, one thread per eigenvalue:
+    // forward pivots D+ from the top, backward pivots D- from the bottom, twist index r with
+    // minimal |gamma_r| = |D+_r + D-_r - (d_r - mu)|, then x_r = 1 propagated both ways.
+    const double tnorm = fmax(fabs(L.bnd[0]), fabs(L.bnd[1])) + 1e-300;
+    const double tiny = 1e-300 + 2.220446049250313e-16 * tnorm * 1e-3;
+    if (tid < w) {
+        const int k = tid;
+        const double mu = L.lasc[k];
+        double* dp = L.piv + k * kHeigLds;
+        double* x = L.X + k * kHeigLds;
+        // forward: dp_0 = d_0 - mu, dp_i = d_i - mu - b_{i-1}^2 / dp_{i-1}
+        double prev = L.dg[0] - mu;
+        if (fabs(prev) < tiny) prev = -tiny;
+        dp[0] = prev;
+        for (int i = 1; i < w; i++) {
+            double v = (L.dg[i] - mu) - L.b2[i - 1] / prev;
+            if (fabs(v) < tiny) v = -tiny;
+            dp[i] = v;
+            prev = v;
+        }
+        // backward pivots (kept in x temporarily) and the twist index
+        double dm = L.dg[w - 1] - mu;
+        if (fabs(dm) < tiny) dm = -tiny;
+        x[w - 1] = dm;
+        int r = w - 1;
+        double best = fabs(dp[w - 1]);            // gamma_{w-1} = dp_{w-1}
+        for (int i = w - 2; i >= 0; i--) {
+            double v = (L.dg[i] - mu) - L.b2[i] / dm;
+            if (fabs(v) < tiny) v = -tiny;
+            x[i] = v;
+            dm = v;
+            const double gam = fabs(dp[i] + v - (L.dg[i] - mu));
+            if (gam < best) { best = gam; r = i; }
+        }
+        // downward from r: x_{i+1} = -b_i x_i / dm_{i+1}; upward: x_{i-1} = -b_{i-1} x_i / dp_{i-1}
+        double xv = 1.0;
+        double nrm = 1.0;
+        for (int i = r; i + 1 < w; i++) {
+            const double nx = -L.b[i] * xv / x[i + 1];
+            x[i + 1] = nx;
+            xv = nx;
+            nrm += nx * nx;
+        }
+        xv = 1.0;
+        for (int i = r; i > 0; i--) {
+            const double nx = -L.b[i - 1] * xv / dp[i - 1];
+            x[i - 1] = nx;
+            xv = nx;
+            nrm += nx * nx;
+        }
+        x[r] = 1.0;
+        nrm = 1.0 / sqrt(nrm);
+        for (int i = 0; i < w; i++) x[i] *= nrm;
+    }
+    __syncthreads();
+    // clusters of close eigenvalues: modified Gram-Schmidt, ascending order (one wave)
+    if (tid < 64) {
+        int c0 = 0;
+        for (int k = 1; k <= w; k++) {
+            if (k < w && L.lasc[k] - L.lasc[k - 1] <= 1e-10 * tnorm) continue;
+            for (int a = c0 + 1; a < k; a++) {
+                double* xa = L.X + a * kHeigLds;
+                for (int bq = c0; bq < a; bq++) {
+                    const double* xb = L.X + bq * kHeigLds;
+                    double dot = 0.0;
+                    for (int i = tid; i < w; i += 64) dot += xa[i] * xb[i];
+                    dot = wave_sum(dot);
+                    for (int i = tid; i < w; i += 64) xa[i] -= dot * xb[i];
+                }
+                double nr2 = 0.0;
+                for (int i = tid; i < w; i += 64) nr2 += xa[i] * xa[i];
+                nr2 = wave_sum(nr2);
+                const double inv = nr2 > 0.0 ? 1.0 / sqrt(nr2) : 0.0;
+                for (int i = tid; i < w; i += 64) xa[i] *= inv;
+            }
+            c0 = k;
+        }
+    }
+    __syncthreads();
+    // ---- 4. back-transformation y = H_0 ... H_{w-3} D x, one 16-lane group per eigenvector,
+    // y in registers (lane s16 holds rows s16, s16 + 16, s16 + 32, s16 + 48)
+    {
+        const int g16 = tid >> 4, s16 = tid & 15;
+        const int kk = g16;                        // output column, descending order
+        const bool act = kk < w;
+        const double* xk = L.X + (act ? (w - 1 - kk) : 0) * kHeigLds;
+        Q4 y[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int i = s16 + 16 * u;
+            const double xv = (act && i < w) ? xk[i] : 0.0;
+            y[u] = i < w ? Q4{L.ph[i] * xv, L.ph[kHeigLds + i] * xv, L.ph[2 * kHeigLds + i] * xv,
+                              L.ph[3 * kHeigLds + i] * xv}
+                         : Q4{0, 0, 0, 0};
+        }
+        for (int j = w - 3; j >= 0; j--) {
+            const double tj = L.tau[j];
+            if (tj == 0.0) continue;               // uniform
+            Q4 s{0, 0, 0, 0};
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int i = s16 + 16 * u;
+                if (i > j && i < w) s = qadd(s, qmul(qconj(G.get(i, j)), y[u]));
+            }
+#pragma unroll
+            for (int o = 8; o > 0; o >>= 1) {
+                s.w += __shfl_xor(s.w, o, 64); s.x += __shfl_xor(s.x, o, 64);
+                s.y += __shfl_xor(s.y, o, 64); s.z += __shfl_xor(s.z, o, 64);
+            }
+            s = qscale(s, tj);
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int i = s16 + 16 * u;
+                if (i > j && i < w) y[u] = qsub(y[u], qmul(G.get(i, j), s));
+            }
+        }
+        if (act) {
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int i = s16 + 16 * u;
+                if (i < w) {
+                    const int64_t o = (int64_t)i * w + kk;
+                    E[o] = y[u].w; E[gps + o] = y[u].x; E[2 * gps + o] = y[u].y; E[3 * gps + o] = y[u].z;
+                }
+            }
+        }
+    }
+}
+
 template <bool SH>
 __global__ __launch_bounds__(HT) void k_heig(const double* __restrict__ Gin, int w, double* __restrict__ lam,
                                              double* __restrict__ E, double* __restrict__ work) {
@@ -143,6 +415,7 @@ __global__ __launch_bounds__(HT) void k_heig(const double* __restrict__ Gin, int
         const Q4 phi = ax1 > 0.0 ? qscale(x1, 1.0 / ax1) : Q4{1, 0, 0, 0};
         const bool live = alpha > 0.0;
         const double tj = live ? 2.0 / (2.0 * alpha * (alpha + ax1)) : 0.0;
+        __syncthreads();                           // everyone has read x1 before v_0 replaces it
         if (tid == 0) {
             tau[j] = tj;
             const Q4 s = qscale(phi, -alpha);     // H x = -alpha phi e_1
@@ -412,7 +685,7 @@ size_t heig_work_doubles(int64_t w) {
 
 hipError_t heig_launch(const double* G, int64_t w, double* lam, double* E, double* work, hipStream_t st) {
     if (w <= kHeigLds)
-        hipLaunchKernelGGL(k_heig<true>, dim3(1), dim3(HT), 0, st, G, (int)w, lam, E, work);
+        hipLaunchKernelGGL(k_heig_lds, dim3(1), dim3(HT), 0, st, G, (int)w, lam, E);
     else
         hipLaunchKernelGGL(k_heig<false>, dim3(1), dim3(HT), 0, st, G, (int)w, lam, E, work);
     return hipGetLastError();
