@@ -172,6 +172,217 @@ __global__ __launch_bounds__(kThreads) void k_chol_lds(const double* __restrict_
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// Factors of order w <= kRegMax: the matrix in registers (1024 threads, 2 x 2 entries each:
+// rows ty, ty + 32, columns tx, tx + 32), one barrier per elimination step.
+constexpr int kRegMax = 64;
+
+__device__ __forceinline__ Q4 qadd(Q4 a, Q4 b) { return Q4{a.w + b.w, a.x + b.x, a.y + b.y, a.z + b.z}; }
+template <int S>
+__device__ __forceinline__ Q4 ldp(const double* p, int i) { return Q4{p[i], p[S + i], p[2 * S + i], p[3 * S + i]}; }
+template <int S>
+__device__ __forceinline__ void stp(double* p, int i, Q4 v) {
+    p[i] = v.w; p[S + i] = v.x; p[2 * S + i] = v.y; p[3 * S + i] = v.z;
+}
+
+// lane i's value of v (i uniform)
+__device__ __forceinline__ double bcast(double v, int i) {
+    const long long u = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(u & 0xffffffffll), i);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), i);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Right-looking Cholesky G + shift I = R^H R (R upper triangular with real positive diagonal):
+// step j scales row j by 1 / r_jj (the half wave that owns row j, double-buffered row in LDS),
+// then every owner of an entry (a, b), j < a <= b, subtracts conj(r_ja) r_jb.
+template <int H>
+__device__ __forceinline__ void chol_row(Q4 (&g)[2][2], int j, int w, int tx, double* rb, double rjj, double inv) {
+#pragma unroll
+    for (int ci = 0; ci < 2; ci++) {
+        const int c = tx + 32 * ci;
+        if (c == j) g[H][ci] = Q4{rjj, 0, 0, 0};
+        else if (c > j && c < w) {
+            const Q4 r = qscale(g[H][ci], inv);
+            g[H][ci] = r;
+            stp<kRegMax>(rb, c, r);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict__ G, int w, double* __restrict__ Rout,
+                                                        int* status, int* shift_out, const int* gate, int allow_shift,
+                                                        double shift_scale) {
+    __shared__ double rowb[2][4 * kRegMax];
+    __shared__ int s_fail;
+    if (gate && *gate == 0) return;
+    const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
+    const int64_t ps = (int64_t)w * w;
+    Q4 g[2][2];
+    double shift = 0.0;
+    int shifted = 0, failed = 0;
+    for (int attempt = 0; attempt < 2; attempt++) {
+#pragma unroll
+        for (int ri = 0; ri < 2; ri++)
+#pragma unroll
+            for (int ci = 0; ci < 2; ci++) {
+                const int a = ty + 32 * ri, b = tx + 32 * ci;
+                Q4 v{0, 0, 0, 0};
+                if (a < w && b < w && b >= a) {
+                    v = ld4(G, ps, (int64_t)a * w + b);
+                    if (a == b) { v.w += shift; v.x = v.y = v.z = 0.0; }
+                }
+                g[ri][ci] = v;
+            }
+        if (tid == 0) s_fail = 0;
+        __syncthreads();
+        for (int j = 0; j < w; j++) {
+            const int jr = j & 31, jh = j >> 5;
+            double* rb = rowb[j & 1];
+            if (ty == jr) {
+                // the pivot (j, j) is register g[jh][jh] of lane (ty & 1) * 32 + jr of this wave
+                const double d = bcast(jh ? g[1][1].w : g[0][0].w, ((ty & 1) << 5) | jr);
+                if (!(d > 0.0) || !(d < 1e300)) {     // breakdown or non-finite pivot
+                    if (tx == 0) s_fail = 1;
+                } else {
+                    const double rjj = sqrt(d), inv = 1.0 / rjj;
+                    if (jh) chol_row<1>(g, j, w, tx, rb, rjj, inv);
+                    else chol_row<0>(g, j, w, tx, rb, rjj, inv);
+                }
+            }
+            __syncthreads();
+            if (s_fail) break;                         // uniform: read after the barrier
+#pragma unroll
+            for (int ri = 0; ri < 2; ri++) {
+                const int a = ty + 32 * ri;
+                if (a <= j || a >= w) continue;
+                const Q4 rja = qconj(ldp<kRegMax>(rb, a));
+#pragma unroll
+                for (int ci = 0; ci < 2; ci++) {
+                    const int b = tx + 32 * ci;
+                    if (b < a || b >= w) continue;
+                    Q4 v = qsub(g[ri][ci], qmul(rja, ldp<kRegMax>(rb, b)));
+                    if (a == b) v.x = v.y = v.z = 0.0;
+                    g[ri][ci] = v;
+                }
+            }
+        }
+        __syncthreads();
+        if (!s_fail) break;
+        if (!allow_shift || attempt == 1) { failed = 1; break; }
+        // shifted CholeskyQR (Fukaya et al.): add shift_scale * trace(G) to the diagonal
+        double tr = 0.0;
+        for (int i = 0; i < w; i++) tr += G[(int64_t)i * w + i];
+        shift = shift_scale * tr;
+        if (!(shift > 0.0)) shift = 1e-300;
+        shifted = 1;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (shift_out) *shift_out = shifted;
+        if (failed) atomicOr(status, 2);
+    }
+#pragma unroll
+    for (int ri = 0; ri < 2; ri++)
+#pragma unroll
+        for (int ci = 0; ci < 2; ci++) {
+            const int a = ty + 32 * ri, b = tx + 32 * ci;
+            if (a < w && b < w) st4(Rout, ps, (int64_t)a * w + b, b >= a ? g[ri][ci] : Q4{0, 0, 0, 0});
+        }
+}
+
+// Q = Y R^{-1} by forward substitution along each row (q R = y): R upper triangular FP64
+// (w x w planes, ld w, w <= kRegMax), Y and Q FP32 planes (Q may alias Y).  One 16-lane group
+// per row, lane s owning columns s, s + 16, s + 32, s + 48; the finished q_t is broadcast to
+// the group and subtracted, times row t of R, from the later columns.
+constexpr int kTrsmRows = 16;   // rows per 256-thread workgroup
+__global__ __launch_bounds__(256) void k_trsm(const float* Y, int64_t ldy, int64_t yps, float* Q, int64_t ldq,
+                                              int64_t qps, const double* __restrict__ R, int w, int64_t rows,
+                                              const int* gate) {
+    __shared__ double sR[4 * kRegMax * kRegMax];   // sR[p][t][c], upper triangle
+    __shared__ double sinv[kRegMax];
+    if (gate && *gate == 0) return;
+    const int tid = threadIdx.x, s = tid & 15, lane = tid & 63;
+    const int64_t ps = (int64_t)w * w;
+    for (int e = tid; e < w * w; e += 256) {
+        const int t = e / w, c = e - t * w;
+        if (c >= t) stp<kRegMax * kRegMax>(sR, t * kRegMax + c, ld4(R, ps, e));
+    }
+    for (int t = tid; t < w; t += 256) sinv[t] = 1.0 / R[(int64_t)t * w + t];
+    __syncthreads();
+    const int64_t row = (int64_t)blockIdx.x * kTrsmRows + (tid >> 4);
+    const bool act = row < rows;
+    Q4 acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const int c = s + 16 * u;
+        acc[u] = Q4{0, 0, 0, 0};
+        if (act && c < w) {
+            const int64_t o = row * ldy + c;
+            acc[u] = Q4{(double)Y[o], (double)Y[yps + o], (double)Y[2 * yps + o], (double)Y[3 * yps + o]};
+        }
+    }
+    const int base = lane & ~15;
+#pragma unroll
+    for (int tb = 0; tb < 4; tb++) {
+        for (int tt = 0; tt < 16; tt++) {
+            const int t = 16 * tb + tt;
+            if (t >= w) break;
+            Q4 q = qscale(acc[tb], sinv[t]);
+            const int src = base | tt;
+            q.w = __shfl(q.w, src, 64); q.x = __shfl(q.x, src, 64);
+            q.y = __shfl(q.y, src, 64); q.z = __shfl(q.z, src, 64);
+            if (s == tt) acc[tb] = q;
+#pragma unroll
+            for (int u = tb; u < 4; u++) {
+                const int c = s + 16 * u;
+                if (c > t && c < w) acc[u] = qsub(acc[u], qmul(q, ldp<kRegMax * kRegMax>(sR, t * kRegMax + c)));
+            }
+        }
+    }
+    if (act) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int c = s + 16 * u;
+            if (c < w) {
+                const int64_t o = row * ldq + c;
+                Q[o] = (float)acc[u].w; Q[qps + o] = (float)acc[u].x;
+                Q[2 * qps + o] = (float)acc[u].y; Q[3 * qps + o] = (float)acc[u].z;
+            }
+        }
+    }
+}
+
+// Rout = R2 R1 for upper triangular factors of order w <= kRegMax: one 16 x 16 tile per
+// workgroup, the row strip of R2 and the column strip of R1 staged in LDS.
+__global__ __launch_bounds__(256) void k_rmul_tile(const double* __restrict__ R2, const double* __restrict__ R1,
+                                                   double* __restrict__ Rout, int w, const int* gate) {
+    __shared__ double sa[4 * 16 * kRegMax];   // sa[p][r][t] rows a0.. of R2
+    __shared__ double sb[4 * kRegMax * 16];   // sb[p][t][c] columns b0.. of R1
+    if (gate && *gate == 0) return;
+    const int64_t ps = (int64_t)w * w;
+    const int a0 = blockIdx.y * 16, b0 = blockIdx.x * 16;
+    const int tid = threadIdx.x, aa = tid >> 4, bq = tid & 15;
+    const int a = a0 + aa, b = b0 + bq;
+    if (a0 > b0 + 15) {                       // tile below the diagonal
+        if (a < w && b < w) st4(Rout, ps, (int64_t)a * w + b, Q4{0, 0, 0, 0});
+        return;
+    }
+    for (int e = tid; e < 16 * w; e += 256) {
+        const int r = e / w, t = e - r * w;       // sa: row a0 + r, column t
+        stp<16 * kRegMax>(sa, r * kRegMax + t, a0 + r < w ? ld4(R2, ps, (int64_t)(a0 + r) * w + t) : Q4{0, 0, 0, 0});
+        const int t2 = e >> 4, c = e & 15;        // sb: row t2, column b0 + c
+        stp<16 * kRegMax>(sb, t2 * 16 + c, b0 + c < w ? ld4(R1, ps, (int64_t)t2 * w + b0 + c) : Q4{0, 0, 0, 0});
+    }
+    __syncthreads();
+    if (a >= w || b >= w) return;
+    Q4 acc{0, 0, 0, 0};
+    for (int t = a; t <= b; t++)
+        acc = qadd(acc, qmul(ldp<16 * kRegMax>(sa, aa * kRegMax + t), ldp<16 * kRegMax>(sb, t * 16 + bq)));
+    if (a == b) acc.x = acc.y = acc.z = 0.0;   // the product of real diagonals is real
+    st4(Rout, ps, (int64_t)a * w + b, acc);
+}
+
 // Larger factors: the same algorithm on a scratch copy in global memory (L2 resident).
 __global__ __launch_bounds__(kThreads) void k_chol_global(const double* __restrict__ G, int w,
                                                            double* __restrict__ Rout, double* __restrict__ Rinv,
@@ -296,6 +507,25 @@ __global__ __launch_bounds__(256) void k_rcopy(const double* __restrict__ src, d
 }  // namespace
 
 int chol_lds_max() { return kLdsMax; }
+int chol_reg_max() { return kRegMax; }
+
+hipError_t chol_reg_launch(const double* G, int64_t w, double* R, int* status, int* shift_out, const int* gate,
+                           int allow_shift, double shift_scale, hipStream_t st) {
+    if (w < 1 || w > kRegMax) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_chol_reg, dim3(1), dim3(kThreads), 0, st, G, (int)w, R, status, shift_out, gate,
+                       allow_shift, shift_scale);
+    return hipGetLastError();
+}
+
+hipError_t trsm_launch(const float* Y, int64_t ldy, int64_t yps, float* Q, int64_t ldq, int64_t qps, const double* R,
+                       int64_t w, int64_t rows, const int* gate, hipStream_t st) {
+    if (w < 1 || w > kRegMax || rows < 0) return hipErrorInvalidValue;
+    if (rows == 0) return hipSuccess;
+    const int64_t blocks = (rows + kTrsmRows - 1) / kTrsmRows;
+    hipLaunchKernelGGL(k_trsm, dim3((unsigned)blocks), dim3(256), 0, st, Y, ldy, yps, Q, ldq, qps, R, (int)w, rows,
+                       gate);
+    return hipGetLastError();
+}
 
 hipError_t chol_launch(const double* G, int64_t w, double* R, double* Rinv, const double* Rprev, double* work,
                        int* status, int* shift_out, const int* gate, int allow_shift, double shift_scale,
@@ -319,6 +549,11 @@ hipError_t chol_launch(const double* G, int64_t w, double* R, double* Rinv, cons
 
 hipError_t rmul_launch(const double* R2, const double* R1, double* Rout, int64_t w, const int* gate,
                        hipStream_t st) {
+    if (w <= kRegMax) {
+        const unsigned t = (unsigned)((w + 15) / 16);
+        hipLaunchKernelGGL(k_rmul_tile, dim3(t, t), dim3(256), 0, st, R2, R1, Rout, (int)w, gate);
+        return hipGetLastError();
+    }
     const int64_t n = w * w;
     hipLaunchKernelGGL(k_rmul, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, R2, R1, Rout, (int)w, gate);
     return hipGetLastError();

@@ -80,6 +80,15 @@ hipError_t chol_launch(const double* G, int64_t w, double* Rout, double* Rinv, c
                        double* work, int* status, int* shift_out, const int* gate, int allow_shift,
                        double shift_scale, int* cond_gate, double cond_limit, hipStream_t st);
 int chol_lds_max();
+// Cholesky alone for w <= chol_reg_max(), factor to R (no inverse); same status, shift and gate
+// behaviour as chol_launch.
+int chol_reg_max();
+hipError_t chol_reg_launch(const double* G, int64_t w, double* R, int* status, int* shift_out, const int* gate,
+                           int allow_shift, double shift_scale, hipStream_t st);
+// Q = Y R^{-1} (rows x w FP32 planes, Q may alias Y), R upper triangular FP64 (ld w),
+// w <= chol_reg_max().
+hipError_t trsm_launch(const float* Y, int64_t ldy, int64_t yps, float* Q, int64_t ldq, int64_t qps, const double* R,
+                       int64_t w, int64_t rows, const int* gate, hipStream_t st);
 // Rout = R2 * R1 (upper triangular w x w); nothing if gate && !*gate.
 hipError_t rmul_launch(const double* R2, const double* R1, double* Rout, int64_t w,
                        const int* gate, hipStream_t st);
@@ -101,14 +110,20 @@ hipError_t qsvd_launch(const double* X, int64_t w, double* U, double* S, double*
                        int want_vectors, hipStream_t st);
 size_t qsvd_work_doubles(int64_t w);
 
-// Hermitian quaternion eigendecomposition of G (w x w FP64 planes, full storage): lam
-// descending, E eigenvectors as columns (may be null).  work: heig_work_doubles(w).
+// Hermitian quaternion eigendecomposition of G (w x w FP64 planes, full storage, w <= heig_max()):
+// lam descending, E eigenvectors as columns (may be null).  work: heig_work_doubles(1).
+int heig_max();
+size_t heig_work_doubles(int64_t nprob);
 hipError_t heig_launch(const double* G, int64_t w, double* lam, double* E, double* work, hipStream_t st);
-size_t heig_work_doubles(int64_t w);
-// QSVD of a small square X through the eigendecomposition of X^H X.
+// QSVD of a small square X (w <= heig_max()) through the eigendecomposition of X^H X.
 hipError_t qsvd_gram_launch(const double* X, int64_t w, double* U, double* S, double* V, double* work,
                             hipStream_t st);
 size_t qsvd_gram_work_doubles(int64_t w);
+// Estimates of nprob problems from their Grams (problem b at G + b * gstride, w <= heig_max()):
+// e[b] = sqrt(max(0, nA2 - sum of the k largest eigenvalues of G_b) / nA2).
+// work: heig_work_doubles(nprob).
+hipError_t estimate_batch_launch(const double* G, int64_t gstride, int64_t w, int nprob, int k, const double* nA2,
+                                 double* e, double* work, hipStream_t st);
 
 // e = sqrt(max(0, nA2 - sum_{j<k} S_j^2) / nA2)
 hipError_t estimate_launch(const double* S, int k, const double* nA2, double* e, hipStream_t st);

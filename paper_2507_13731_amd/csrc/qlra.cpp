@@ -3,8 +3,10 @@
 //
 // Everything between views stays on the device: a solve is a fixed sequence of kernel
 // launches on the caller's stream with no host synchronisation.  The per-pass error
-// estimates need a small QSVD of each view's R; they run on a side stream (fork/join with
-// events) so that they overlap the next views instead of lengthening the chain.
+// estimates need the singular values of each view's R, i.e. the eigenvalues of the view's
+// Gram, which the CholeskyQR forms anyway: each intermediate view leaves its Gram in a slot,
+// and one batched eigenvalue launch on a side stream (fork/join with events) turns all of
+// them into estimates while the final QSVD runs on the main stream.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -73,32 +75,49 @@ double shift_scale(int64_t rows, int64_t w) {
     return 11.0 * ((double)rows * w + (double)w * (w + 1)) * 1.1102230246251565e-16;
 }
 
-// Thin QR of Y (rows x w): Q (ld ldq, plane stride qps) and R (w x w FP64, ld w), Q may alias Y.
-// Each round is CholeskyQR with an FP64 Gram (exact products of FP32 data), FP64 Cholesky and
-// an FP64 application of R^{-1}.  With an FP64 Cholesky the orthogonality error of one round is
-// about u64 cond(Y)^2 + u32, so for the views (cond(Y) <= 1e4, the FP32 storage of Q dominating)
-// one round suffices; rounds = 2 is CholeskyQR2, used where the basis is returned or stacked.
-// A breakdown in the first round is retried with a shift (shifted CholeskyQR).
+// Thin QR of Y (rows x w): Q (ld ldq, plane stride qps) and R (w x w FP64, ld w; may be null
+// when only Q is wanted), Q may alias Y.  Each round is CholeskyQR with an FP64 Gram (exact
+// products of FP32 data), FP64 Cholesky and an FP64 application of R^{-1}.  With an FP64
+// Cholesky the orthogonality error of one round is about u64 cond(Y)^2 + u32, so for the views
+// (cond(Y) <= 1e4, the FP32 storage of Q dominating) one round suffices; rounds = 2 is
+// CholeskyQR2 (R = R2 R1), used where the basis is returned or stacked.  A breakdown in the
+// first round is retried with a shift (shifted CholeskyQR).  G0 (optional) receives the first
+// round's Gram Y^H Y (w x w, FP64 planes) and keeps it.
+// For w <= chol_reg_max() R^{-1} is applied by forward substitution along the rows of Y;
+// larger factors are inverted explicitly and applied as a product.
 void cholqr(Ctx& c, const float* Y, int64_t rows, int64_t w, int64_t ldy, int64_t yps, float* Q, int64_t ldq,
-            int64_t qps, double* R, int rounds) {
+            int64_t qps, double* R, int rounds, double* G0 = nullptr) {
     const int64_t tps = rows * w;
     int* shifted = c.status ? c.status + 1 : nullptr;
-    const double* Rprev = nullptr;
     const float* src = Y;
     int64_t lds = ldy, sps = yps;
+    const bool small = w <= chol_reg_max();
+    const double* Rprev = nullptr;
     for (int round = 0; round < rounds; round++) {
         const bool last = round == rounds - 1;
         float* dst = last ? Q : c.T2;
         const int64_t ldd = last ? ldq : w, dps = last ? qps : tps;
-        double* Rout = last ? R : (round == 0 ? c.R1 : c.R2);
-        qg(c, desc(OP_HN, MATH_F64, src, lds, sps, 0, src, lds, sps, 0, c.G, w, w * w, 1, w, w, rows));
-        if (!c.dry)
-            note(c, chol_launch(c.G, w, Rout, c.Rinv, Rprev, c.chol_work, c.status, round == 0 ? shifted : nullptr,
-                                nullptr, round == 0 ? 1 : 0, shift_scale(rows, w), nullptr, 0.0, c.st));
-        qg(c, desc(OP_NN, MATH_F64, src, lds, sps, 0, c.Rinv, w, w * w, 1, dst, ldd, dps, 0, rows, w, w));
-        Rprev = Rout;
+        double* G = (round == 0 && G0) ? G0 : c.G;
+        qg(c, desc(OP_HN, MATH_F64, src, lds, sps, 0, src, lds, sps, 0, G, w, w * w, 1, w, w, rows));
+        if (small) {
+            // this round's own factor; the product R2 R1 is formed at the end when R is wanted
+            double* Rr = (rounds == 1 && R) ? R : (round == 0 ? c.R1 : c.R2);
+            if (!c.dry) {
+                note(c, chol_reg_launch(G, w, Rr, c.status, round == 0 ? shifted : nullptr, nullptr, round == 0 ? 1 : 0,
+                                        shift_scale(rows, w), c.st));
+                note(c, trsm_launch(src, lds, sps, dst, ldd, dps, Rr, w, rows, nullptr, c.st));
+            }
+        } else {
+            double* Rout = last ? (R ? R : c.Rjunk) : (round == 0 ? c.R1 : c.R2);
+            if (!c.dry)
+                note(c, chol_launch(G, w, Rout, c.Rinv, Rprev, c.chol_work, c.status, round == 0 ? shifted : nullptr,
+                                    nullptr, round == 0 ? 1 : 0, shift_scale(rows, w), nullptr, 0.0, c.st));
+            qg(c, desc(OP_NN, MATH_F64, src, lds, sps, 0, c.Rinv, w, w * w, 1, dst, ldd, dps, 0, rows, w, w));
+            Rprev = Rout;
+        }
         src = dst; lds = ldd; sps = dps;
     }
+    if (small && rounds == 2 && R && !c.dry) note(c, rmul_launch(c.R2, c.R1, R, w, nullptr, c.st));
 }
 
 // Orthonormalise the columns of a stack of blocks (rows x W, ld W) of width l: CholeskyQR2 of
@@ -106,7 +125,7 @@ void cholqr(Ctx& c, const float* Y, int64_t rows, int64_t w, int64_t ldy, int64_
 // projections against all earlier blocks) and CholeskyQR2 of the block in place.
 void orth_stack(Ctx& c, float* K, int64_t rows, int64_t W, int64_t l, double* Cbuf) {
     const int64_t kps = rows * W;
-    cholqr(c, K, rows, std::min(l, W), W, kps, K, W, kps, c.Rjunk, 2);
+    cholqr(c, K, rows, std::min(l, W), W, kps, K, W, kps, nullptr, 2);
     for (int64_t b0 = l; b0 < W; b0 += l) {
         const int64_t lb = std::min(l, W - b0);
         float* Z = K + b0;
@@ -115,7 +134,7 @@ void orth_stack(Ctx& c, float* K, int64_t rows, int64_t W, int64_t l, double* Cb
             qg(c, desc(OP_HN, MATH_F64, K, W, kps, 0, Z, W, kps, 0, Cbuf, lb, b0 * lb, 1, b0, lb, rows));
             qg(c, desc(OP_NN, MATH_F64, K, W, kps, 0, Cbuf, lb, b0 * lb, 1, Z, W, kps, 0, rows, lb, b0, ST_SUB));
         }
-        cholqr(c, Z, rows, lb, W, kps, Z, W, kps, c.Rjunk, 2);
+        cholqr(c, Z, rows, lb, W, kps, Z, W, kps, nullptr, 2);
     }
 }
 
@@ -176,6 +195,8 @@ struct Bufs {
     double* Cbuf;           // Wk x l
     double* Lh; double* Rh; double* Sw; double* qsvd_work;
     double* side_S; double* side_work;
+    double* Gs;             // Grams of views 2 .. v-1, (v - 2) x (l x l)
+    double* est_work;
     void* partial;
 };
 
@@ -204,8 +225,12 @@ void carve(const Problem& pr, const Dims& d, Arena& ar, Bufs& b, size_t part_byt
     b.Rh = (double*)ar.take(4 * w2 * sizeof(double));
     b.Sw = (double*)ar.take(d.wmax * sizeof(double));
     b.qsvd_work = (double*)ar.take(qsvd_work_doubles(d.wmax) * sizeof(double));
-    b.side_S = (double*)ar.take(d.l * sizeof(double));
-    b.side_work = (double*)ar.take(qsvd_work_doubles(d.l) * sizeof(double));
+    const bool batched = d.l <= heig_max();
+    const int64_t nest = pr.v > 2 ? pr.v - 2 : 0;
+    b.side_S = batched ? nullptr : (double*)ar.take(d.l * sizeof(double));
+    b.side_work = batched ? nullptr : (double*)ar.take(qsvd_work_doubles(d.l) * sizeof(double));
+    b.Gs = batched && nest ? (double*)ar.take((size_t)nest * 4 * l2 * sizeof(double)) : nullptr;
+    b.est_work = batched && nest ? (double*)ar.take(heig_work_doubles(nest) * sizeof(double)) : nullptr;
     b.partial = part_bytes ? ar.take(part_bytes) : nullptr;
 }
 
@@ -266,9 +291,24 @@ hipError_t get_capture_stream(int dev, hipStream_t* out) {
     return hipSuccess;
 }
 
-// Side-stream estimate of view `i` (1-based) from its R (l x l).
+// Gram slot of view `i` (1-based) for the batched estimates (views 2 .. v-1), or null.
+double* gram_slot(const Bufs& b, const Problem& pr, int64_t l, int i) {
+    if (!pr.estimate || !b.Gs || i < 2 || i >= pr.v) return nullptr;
+    return b.Gs + (size_t)(i - 2) * 4 * l * l;
+}
+
+// Estimates of views 2 .. v-1 from their Grams, one batched launch on the side stream.
+void fork_estimates(Ctx& c, const Bufs& b, const Problem& pr, int64_t l) {
+    if (c.dry || !pr.estimate || !b.Gs) return;
+    note(c, hipEventRecord(c.ev_fork, c.st));
+    note(c, hipStreamWaitEvent(c.side, c.ev_fork, 0));
+    note(c, estimate_batch_launch(b.Gs, 4 * l * l, l, pr.v - 2, pr.k, b.nA2, pr.pass_err + 1, b.est_work, c.side));
+}
+
+// Side-stream estimate of view `i` (1-based) from its R (l x l), for widths above the batched
+// eigensolver's limit.
 void fork_estimate(Ctx& c, const Bufs& b, const Problem& pr, const double* R, int64_t l, int i) {
-    if (c.dry || !pr.estimate) return;
+    if (c.dry || !pr.estimate || b.Gs || i >= pr.v) return;
     note(c, hipEventRecord(c.ev_fork, c.st));
     note(c, hipStreamWaitEvent(c.side, c.ev_fork, 0));
     note(c, qsvd_launch(R, l, nullptr, b.side_S, nullptr, b.side_work, 0, c.side));
@@ -297,13 +337,13 @@ void finish(Ctx& c, const Bufs& b, const Problem& pr, const double* R, int64_t w
 
 // One view: C = A X (forward) or C = A^H X (adjoint), then its QR.
 void view(Ctx& c, const Problem& pr, bool adjoint, const float* X, int64_t ldx, int64_t w, float* T, float* Q,
-          int64_t ldq, double* R, int rounds = 1) {
+          int64_t ldq, double* R, int rounds = 1, double* G0 = nullptr) {
     const int64_t rows_out = adjoint ? pr.n : pr.m;
     const int64_t kdim = adjoint ? pr.m : pr.n;
     const int64_t xps = kdim * ldx;
     qg(c, desc(adjoint ? OP_HN : OP_NN, MATH_F32, pr.A, pr.lda, pr.aps, 0, X, ldx, xps, 0, T, w, rows_out * w, 0,
                rows_out, w, kdim));
-    cholqr(c, T, rows_out, w, w, rows_out * w, Q, ldq, rows_out * ldq, R, rounds);
+    cholqr(c, T, rows_out, w, w, rows_out * w, Q, ldq, rows_out * ldq, R, rounds, G0);
 }
 
 void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
@@ -319,13 +359,16 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
     if (!d.krylov) {
         // Alg. 2: odd views [Q1, R1] = QR(A Q2), even views [Q2, R2] = QR(A^H Q1)
         for (int i = 1; i <= pr.v; i++) {
-            double* R = b.Rv + (size_t)(i - 1) * 4 * l2;
+            // R is kept for the last view (the final QSVD) and for side-stream estimates from R
+            double* R = (i == pr.v || (pr.estimate && !b.Gs)) ? b.Rv + (size_t)(i - 1) * 4 * l2 : nullptr;
             // the last two views produce the returned bases: CholeskyQR2 there
             const int rounds = i >= pr.v - 1 ? 2 : 1;
-            if (i % 2 == 1) view(c, pr, false, Q2cur, l, l, b.T, b.Q1, l, R, rounds);
-            else { view(c, pr, true, b.Q1, l, l, b.T, b.Q2, l, R, rounds); Q2cur = b.Q2; }
-            if (i >= 2 && i < pr.v) fork_estimate(c, b, pr, R, l, i);
+            double* G0 = gram_slot(b, pr, l, i);
+            if (i % 2 == 1) view(c, pr, false, Q2cur, l, l, b.T, b.Q1, l, R, rounds, G0);
+            else { view(c, pr, true, b.Q1, l, l, b.T, b.Q2, l, R, rounds, G0); Q2cur = b.Q2; }
+            if (i >= 2) fork_estimate(c, b, pr, R, l, i);
         }
+        fork_estimates(c, b, pr, l);
         finish(c, b, pr, b.Rv + (size_t)(pr.v - 1) * 4 * l2, l, b.Q1, l, Q2cur, l, d.even);
         return;
     }
@@ -337,29 +380,32 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
         if (c.dry || c0 >= Wk) return;
         note(c, copy_planes_launch(Qb, l, rs * l, b.stack + c0, Wk, sps, rs, std::min(l, Wk - c0), nullptr, c.st));
     };
+    const bool keepR = pr.estimate && !b.Gs;
     for (int j = 1; j <= d.s; j++) {
-        double* R = b.Rv + (size_t)i * 4 * l2;
-        view(c, pr, false, Q2cur, l, l, b.T, b.Q1, l, R);
+        double* R = keepR ? b.Rv + (size_t)i * 4 * l2 : nullptr;
+        view(c, pr, false, Q2cur, l, l, b.T, b.Q1, l, R, 1, gram_slot(b, pr, l, i + 1));
         i++;
         if (i >= 2) fork_estimate(c, b, pr, R, l, i);
         if (d.even) stack_in(b.Q1, j - 1);
-        R = b.Rv + (size_t)i * 4 * l2;
-        view(c, pr, true, b.Q1, l, l, b.T, b.Q2, l, R);
+        R = keepR ? b.Rv + (size_t)i * 4 * l2 : nullptr;
+        view(c, pr, true, b.Q1, l, l, b.T, b.Q2, l, R, 1, gram_slot(b, pr, l, i + 1));
         i++;
         fork_estimate(c, b, pr, R, l, i);
         Q2cur = b.Q2;
         if (!d.even) stack_in(b.Q2, j - 1);
     }
     if (d.even) {
-        double* R = b.Rv + (size_t)i * 4 * l2;
-        view(c, pr, false, Q2cur, l, l, b.T, b.Q1, l, R);
+        double* R = keepR ? b.Rv + (size_t)i * 4 * l2 : nullptr;
+        view(c, pr, false, Q2cur, l, l, b.T, b.Q1, l, R, 1, gram_slot(b, pr, l, i + 1));
         i++;
         if (i >= 2) fork_estimate(c, b, pr, R, l, i);
         stack_in(b.Q1, d.s);
+        fork_estimates(c, b, pr, l);
         orth_stack(c, b.stack, pr.m, Wk, l, b.Cbuf);
         view(c, pr, true, b.stack, Wk, Wk, b.T, b.Q2, Wk, b.Rfin, 2);
         finish(c, b, pr, b.Rfin, Wk, b.stack, Wk, b.Q2, Wk, true);
     } else {
+        fork_estimates(c, b, pr, l);
         orth_stack(c, b.stack, pr.n, Wk, l, b.Cbuf);
         view(c, pr, false, b.stack, Wk, Wk, b.T, b.Q1, Wk, b.Rfin, 2);
         finish(c, b, pr, b.Rfin, Wk, b.Q1, Wk, b.stack, Wk, false);

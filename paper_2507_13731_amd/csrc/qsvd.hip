@@ -151,170 +151,6 @@ __global__ __launch_bounds__(kThreads) void k_qsvd(const double* __restrict__ X,
     }
 }
 
-// The same Jacobi for w <= kLdsW with the columns resident in LDS (column-major, four
-// planes) and 32 lanes per column pair; right vectors, if wanted, are formed afterwards as
-// V = X^H U diag(1/sigma) instead of accumulating rotations.
-constexpr int kLdsW = 64;
-
-__device__ __forceinline__ double half_sum(double v) {
-#pragma unroll
-    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-__global__ __launch_bounds__(kThreads) void k_qsvd_lds(const double* __restrict__ X, int w,
-                                                        double* __restrict__ U, double* __restrict__ S,
-                                                        double* __restrict__ V, double* __restrict__ info) {
-    __shared__ double Mt[4 * kLdsW * kLdsW];   // Mt[p][col][row]
-    __shared__ double sig[kLdsW];              // squared column norms during the sweeps
-    __shared__ int rnk[kLdsW];
-    __shared__ int s_rot;
-    __shared__ double s_fro;
-    const int tid = threadIdx.x;
-    const int grp = tid >> 5, t = tid & 31;      // one 32-lane group per column pair
-    constexpr int PS = kLdsW * kLdsW;
-    const int64_t xps = (int64_t)w * w;
-    for (int e = tid; e < w * w; e += kThreads) {
-        const int r = e / w, c = e % w;
-#pragma unroll
-        for (int p = 0; p < 4; p++) Mt[p * PS + c * kLdsW + r] = X[p * xps + e];
-    }
-    __syncthreads();
-    const int np = w + (w & 1);
-    const double eps = 2.220446049250313e-16;
-    const double tol = (double)w * eps;
-    int sweep = 0;
-    for (; sweep < 30; sweep++) {
-        // exact squared column norms at the start of every sweep
-        for (int c = grp; c < w; c += kThreads / 32) {
-            double sq = 0;
-            for (int i = t; i < w; i += 32)
-#pragma unroll
-                for (int p = 0; p < 4; p++) {
-                    const double v = Mt[p * PS + c * kLdsW + i];
-                    sq += v * v;
-                }
-            sq = half_sum(sq);
-            if (t == 0) sig[c] = sq;
-        }
-        if (tid == 0) s_rot = 0;
-        __syncthreads();
-        if (tid == 0) {
-            double f = 0;
-            for (int c = 0; c < w; c++) f += sig[c];
-            s_fro = f;
-        }
-        __syncthreads();
-        const double tiny = eps * eps * s_fro;   // columns below this carry no information
-        for (int r = 0; r < np - 1; r++) {
-            int a = w, b = w;
-            if (grp < np / 2) rr_pair(r, grp, np, &a, &b);
-            const bool live = a < w && b < w;
-            double g0 = 0, g1 = 0, g2 = 0, g3 = 0;
-            if (live) {
-                for (int i = t; i < w; i += 32) {
-                    const double a0 = Mt[a * kLdsW + i], a1 = Mt[PS + a * kLdsW + i];
-                    const double a2 = Mt[2 * PS + a * kLdsW + i], a3 = Mt[3 * PS + a * kLdsW + i];
-                    const double b0 = Mt[b * kLdsW + i], b1 = Mt[PS + b * kLdsW + i];
-                    const double b2 = Mt[2 * PS + b * kLdsW + i], b3 = Mt[3 * PS + b * kLdsW + i];
-                    g0 += a0 * b0 + a1 * b1 + a2 * b2 + a3 * b3;
-                    g1 += a0 * b1 - a1 * b0 - a2 * b3 + a3 * b2;
-                    g2 += a0 * b2 + a1 * b3 - a2 * b0 - a3 * b1;
-                    g3 += a0 * b3 - a1 * b2 + a2 * b1 - a3 * b0;
-                }
-            }
-            g0 = half_sum(g0); g1 = half_sum(g1); g2 = half_sum(g2); g3 = half_sum(g3);
-            if (live) {
-                const double al = sig[a], be = sig[b];
-                const double ag = sqrt(g0 * g0 + g1 * g1 + g2 * g2 + g3 * g3);
-                if (al > tiny && be > tiny && ag > tol * sqrt(al * be)) {
-                    if (t == 0) s_rot = 1;
-                    const double p0 = g0 / ag, p1 = -g1 / ag, p2 = -g2 / ag, p3 = -g3 / ag;  // conj(phi)
-                    const double zeta = (be - al) / (2.0 * ag);
-                    const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                    const double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-                    for (int i = t; i < w; i += 32) {
-                        const int ia = a * kLdsW + i, ib = b * kLdsW + i;
-                        const double a0 = Mt[ia], a1 = Mt[PS + ia], a2 = Mt[2 * PS + ia], a3 = Mt[3 * PS + ia];
-                        const double x0 = Mt[ib], x1 = Mt[PS + ib], x2 = Mt[2 * PS + ib], x3 = Mt[3 * PS + ib];
-                        const double b0 = x0 * p0 - x1 * p1 - x2 * p2 - x3 * p3;
-                        const double b1 = x0 * p1 + x1 * p0 + x2 * p3 - x3 * p2;
-                        const double b2 = x0 * p2 - x1 * p3 + x2 * p0 + x3 * p1;
-                        const double b3 = x0 * p3 + x1 * p2 - x2 * p1 + x3 * p0;
-                        Mt[ia] = cs * a0 - sn * b0; Mt[PS + ia] = cs * a1 - sn * b1;
-                        Mt[2 * PS + ia] = cs * a2 - sn * b2; Mt[3 * PS + ia] = cs * a3 - sn * b3;
-                        Mt[ib] = sn * a0 + cs * b0; Mt[PS + ib] = sn * a1 + cs * b1;
-                        Mt[2 * PS + ib] = sn * a2 + cs * b2; Mt[3 * PS + ib] = sn * a3 + cs * b3;
-                    }
-                    // the rotation moves t |g| of squared norm from column a to column b
-                    if (t == 0) { sig[a] = al - tt * ag; sig[b] = be + tt * ag; }
-                }
-            }
-            __syncthreads();
-        }
-        if (s_rot == 0) break;
-        __syncthreads();
-    }
-    if (info && tid == 0) info[0] = (double)(sweep + 1);
-    // sigma_c = ||column c||, rank by descending value (ties: lower index first)
-    __syncthreads();
-    for (int c = grp; c < w; c += kThreads / 32) {
-        double sq = 0;
-        for (int i = t; i < w; i += 32)
-#pragma unroll
-            for (int p = 0; p < 4; p++) {
-                const double v = Mt[p * PS + c * kLdsW + i];
-                sq += v * v;
-            }
-        sq = half_sum(sq);
-        if (t == 0) sig[c] = sqrt(sq);
-    }
-    __syncthreads();
-    for (int c = tid; c < w; c += kThreads) {
-        const double sc = sig[c];
-        int rank = 0;
-        for (int o = 0; o < w; o++) rank += (sig[o] > sc) || (sig[o] == sc && o < c);
-        rnk[c] = rank;
-        S[rank] = sc;
-    }
-    __syncthreads();
-    // left vectors: normalised columns (in place), written in rank order
-    for (int e = tid; e < w * w; e += kThreads) {
-        const int c = e / w, i = e % w;
-        const double inv = sig[c] > 0.0 ? 1.0 / sig[c] : 0.0;
-#pragma unroll
-        for (int p = 0; p < 4; p++) Mt[p * PS + c * kLdsW + i] *= inv;
-    }
-    __syncthreads();
-    if (U) {
-        for (int e = tid; e < w * w; e += kThreads) {
-            const int c = e / w, i = e % w;
-#pragma unroll
-            for (int p = 0; p < 4; p++) U[p * xps + (int64_t)i * w + rnk[c]] = Mt[p * PS + c * kLdsW + i];
-        }
-    }
-    if (V) {
-        // V(:, rank c) = X^H u_c / sigma_c: entry j = sum_i conj(X_ij) u_ic / sigma_c
-        for (int e = tid; e < w * w; e += kThreads) {
-            const int c = e / w, j = e % w;
-            double v0 = 0, v1 = 0, v2 = 0, v3 = 0;
-            for (int i = 0; i < w; i++) {
-                const int64_t xi = (int64_t)i * w + j;
-                const double x0 = X[xi], x1 = -X[xps + xi], x2 = -X[2 * xps + xi], x3 = -X[3 * xps + xi];
-                const double u0 = Mt[c * kLdsW + i], u1 = Mt[PS + c * kLdsW + i];
-                const double u2 = Mt[2 * PS + c * kLdsW + i], u3 = Mt[3 * PS + c * kLdsW + i];
-                v0 += x0 * u0 - x1 * u1 - x2 * u2 - x3 * u3;
-                v1 += x0 * u1 + x1 * u0 + x2 * u3 - x3 * u2;
-                v2 += x0 * u2 - x1 * u3 + x2 * u0 + x3 * u1;
-                v3 += x0 * u3 + x1 * u2 - x2 * u1 + x3 * u0;
-            }
-            const double inv = sig[c] > 0.0 ? 1.0 / sig[c] : 0.0;
-            const int64_t o = (int64_t)j * w + rnk[c];
-            V[o] = v0 * inv; V[xps + o] = v1 * inv; V[2 * xps + o] = v2 * inv; V[3 * xps + o] = v3 * inv;
-        }
-    }
-}
-
 __global__ void k_estimate(const double* S, int k, const double* nA2, double* e) {
     if (threadIdx.x != 0) return;
     double top = 0.0;
@@ -425,9 +261,9 @@ size_t qsvd_work_doubles(int64_t w) {
 
 hipError_t qsvd_launch(const double* X, int64_t w, double* U, double* S, double* V, double* work,
                        int want_vectors, hipStream_t st) {
-    if (w <= kLdsW) {
-        // eigendecomposition of X^H X (Householder tridiagonalisation, multisection, inverse
-        // iteration): O(w) dependent steps instead of O(sweeps * w) Jacobi rounds
+    if (w <= heig_max()) {
+        // eigendecomposition of X^H X (Householder tridiagonalisation, multisection, twisted
+        // factorisations): O(w) dependent steps instead of O(sweeps * w) Jacobi rounds
         return qsvd_gram_launch(X, w, want_vectors ? U : nullptr, S, want_vectors ? V : nullptr, work, st);
     } else {
         hipLaunchKernelGGL(k_qsvd, dim3(1), dim3(kThreads), 0, st, X, (int)w, U, S, V, work, want_vectors);

@@ -99,7 +99,8 @@ def test_qgemm_config1_view_sampled(gq, oracle):
         assert np.all(np.abs(got[:, rows, :] - ref) <= tol[None])
 
 
-@pytest.mark.parametrize("m,w", [(500, 15), (2048, 60), (1024, 80), (80, 80), (3000, 160)])
+@pytest.mark.parametrize("m,w", [(37, 1), (500, 15), (333, 33), (2048, 60), (1001, 64), (64, 64), (1024, 80), (80, 80),
+                                 (3000, 160)])
 def test_cholqr_matches_householder(gq, oracle, m, w):
     print(f"cholqr m={m} w={w}", flush=True)
     rng = np.random.default_rng(m + w)
