@@ -291,22 +291,69 @@ __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict_
         }
 }
 
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// lane n of each 16-lane row, to the whole row (DPP row_newbcast)
+template <int N>
+__device__ __forceinline__ Q4 row_bcast(Q4 q) {
+    return Q4{dpp<0x150 + N>(q.w), dpp<0x150 + N>(q.x), dpp<0x150 + N>(q.y), dpp<0x150 + N>(q.z)};
+}
+
 // Q = Y R^{-1} by forward substitution along each row (q R = y): R upper triangular FP64
 // (w x w planes, ld w, w <= kRegMax), Y and Q FP32 planes (Q may alias Y).  One 16-lane group
 // per row, lane s owning columns s, s + 16, s + 32, s + 48; the finished q_t is broadcast to
 // the group and subtracted, times row t of R, from the later columns.
 constexpr int kTrsmRows = 16;   // rows per 256-thread workgroup
+constexpr int kRegPacked = kRegMax * (kRegMax + 1) / 2;
+// upper triangle packed by rows: (t, c), c >= t
+__device__ __forceinline__ int upk(int t, int c) { return t * (2 * kRegMax - t + 1) / 2 + (c - t); }
+
+// columns t = 16 TB + TT of the substitution: q_t = acc_t / r_tt on lane TT, broadcast over the
+// row's 16 lanes, then acc_c -= q_t r_tc for the later columns c > t.
+template <int TB, int TT>
+__device__ __forceinline__ void trsm_step(Q4 (&acc)[4], const double* sR, const double* sinv, int s, int w) {
+    constexpr int t = 16 * TB + TT;
+    const Q4 q = row_bcast<TT>(qscale(acc[TB], sinv[t]));
+    if (s == TT) acc[TB] = q;
+#pragma unroll
+    for (int u = TB; u < 4; u++) {
+        const int c = s + 16 * u;
+        if (c > t && c < w) acc[u] = qsub(acc[u], qmul(q, ldp<kRegPacked>(sR, upk(t, c))));
+    }
+}
+template <int TB, int TT = 0>
+__device__ __forceinline__ void trsm_block(Q4 (&acc)[4], const double* sR, const double* sinv, int s, int w) {
+    if constexpr (TT < 16) {
+        if (16 * TB + TT >= w) return;
+        trsm_step<TB, TT>(acc, sR, sinv, s, w);
+        trsm_block<TB, TT + 1>(acc, sR, sinv, s, w);
+    }
+}
 __global__ __launch_bounds__(256) void k_trsm(const float* Y, int64_t ldy, int64_t yps, float* Q, int64_t ldq,
                                               int64_t qps, const double* __restrict__ R, int w, int64_t rows,
                                               const int* gate) {
-    __shared__ double sR[4 * kRegMax * kRegMax];   // sR[p][t][c], upper triangle
+    __shared__ double sR[4 * kRegPacked];   // upper triangle, packed by rows
     __shared__ double sinv[kRegMax];
     if (gate && *gate == 0) return;
-    const int tid = threadIdx.x, s = tid & 15, lane = tid & 63;
+    const int tid = threadIdx.x, s = tid & 15;
     const int64_t ps = (int64_t)w * w;
-    for (int e = tid; e < w * w; e += 256) {
-        const int t = e / w, c = e - t * w;
-        if (c >= t) stp<kRegMax * kRegMax>(sR, t * kRegMax + c, ld4(R, ps, e));
+    // staging: eight loads in flight per thread (clamped addresses, guarded stores)
+    const int n = w * w;
+    for (int base = 0; base < n; base += 8 * 256) {
+        Q4 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) v[u] = ld4(R, ps, min(base + u * 256 + tid, n - 1));
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const int e = base + u * 256 + tid;
+            const int t = e / w, c = e - t * w;
+            if (e < n && c >= t) stp<kRegPacked>(sR, upk(t, c), v[u]);
+        }
     }
     for (int t = tid; t < w; t += 256) sinv[t] = 1.0 / R[(int64_t)t * w + t];
     __syncthreads();
@@ -322,24 +369,10 @@ __global__ __launch_bounds__(256) void k_trsm(const float* Y, int64_t ldy, int64
             acc[u] = Q4{(double)Y[o], (double)Y[yps + o], (double)Y[2 * yps + o], (double)Y[3 * yps + o]};
         }
     }
-    const int base = lane & ~15;
-#pragma unroll
-    for (int tb = 0; tb < 4; tb++) {
-        for (int tt = 0; tt < 16; tt++) {
-            const int t = 16 * tb + tt;
-            if (t >= w) break;
-            Q4 q = qscale(acc[tb], sinv[t]);
-            const int src = base | tt;
-            q.w = __shfl(q.w, src, 64); q.x = __shfl(q.x, src, 64);
-            q.y = __shfl(q.y, src, 64); q.z = __shfl(q.z, src, 64);
-            if (s == tt) acc[tb] = q;
-#pragma unroll
-            for (int u = tb; u < 4; u++) {
-                const int c = s + 16 * u;
-                if (c > t && c < w) acc[u] = qsub(acc[u], qmul(q, ldp<kRegMax * kRegMax>(sR, t * kRegMax + c)));
-            }
-        }
-    }
+    trsm_block<0>(acc, sR, sinv, s, w);
+    trsm_block<1>(acc, sR, sinv, s, w);
+    trsm_block<2>(acc, sR, sinv, s, w);
+    trsm_block<3>(acc, sR, sinv, s, w);
     if (act) {
 #pragma unroll
         for (int u = 0; u < 4; u++) {
@@ -368,11 +401,26 @@ __global__ __launch_bounds__(256) void k_rmul_tile(const double* __restrict__ R2
         if (a < w && b < w) st4(Rout, ps, (int64_t)a * w + b, Q4{0, 0, 0, 0});
         return;
     }
-    for (int e = tid; e < 16 * w; e += 256) {
-        const int r = e / w, t = e - r * w;       // sa: row a0 + r, column t
-        stp<16 * kRegMax>(sa, r * kRegMax + t, a0 + r < w ? ld4(R2, ps, (int64_t)(a0 + r) * w + t) : Q4{0, 0, 0, 0});
-        const int t2 = e >> 4, c = e & 15;        // sb: row t2, column b0 + c
-        stp<16 * kRegMax>(sb, t2 * 16 + c, b0 + c < w ? ld4(R1, ps, (int64_t)t2 * w + b0 + c) : Q4{0, 0, 0, 0});
+    const int n = 16 * w;
+    for (int base = 0; base < n; base += 4 * 256) {
+        Q4 va[4], vb[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int e = min(base + u * 256 + tid, n - 1);
+            const int r = e / w, t = e - r * w;       // sa: row a0 + r, column t
+            va[u] = ld4(R2, ps, (int64_t)min(a0 + r, w - 1) * w + t);
+            const int t2 = e >> 4, c = e & 15;        // sb: row t2, column b0 + c
+            vb[u] = ld4(R1, ps, (int64_t)t2 * w + min(b0 + c, w - 1));
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int e = base + u * 256 + tid;
+            if (e >= n) continue;
+            const int r = e / w, t = e - r * w;
+            stp<16 * kRegMax>(sa, r * kRegMax + t, a0 + r < w ? va[u] : Q4{0, 0, 0, 0});
+            const int t2 = e >> 4, c = e & 15;
+            stp<16 * kRegMax>(sb, t2 * 16 + c, b0 + c < w ? vb[u] : Q4{0, 0, 0, 0});
+        }
     }
     __syncthreads();
     if (a >= w || b >= w) return;

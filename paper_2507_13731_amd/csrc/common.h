@@ -119,6 +119,9 @@ hipError_t heig_launch(const double* G, int64_t w, double* lam, double* E, doubl
 hipError_t qsvd_gram_launch(const double* X, int64_t w, double* U, double* S, double* V, double* work,
                             hipStream_t st);
 size_t qsvd_gram_work_doubles(int64_t w);
+// S_j = sqrt(max(lam_j, 0)) (j < k) and Wk = E[:, :k] diag(1 / S) (w x k FP64 planes, ld k),
+// from lam (descending) and E (w x w, ld w) of a Gram's eigendecomposition.
+hipError_t svals_launch(const double* lam, const double* E, int64_t w, int k, double* S, double* Wk, hipStream_t st);
 // Estimates of nprob problems from their Grams (problem b at G + b * gstride, w <= heig_max()):
 // e[b] = sqrt(max(0, nA2 - sum of the k largest eigenvalues of G_b) / nA2).
 // work: heig_work_doubles(nprob).

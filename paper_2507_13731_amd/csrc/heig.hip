@@ -18,6 +18,8 @@
 //              T - mu, twist index of least |gamma|), modified Gram-Schmidt inside clusters of
 //              close eigenvalues, and the back-transformation y = Q D x with the stored
 //              reflectors; 16 eigenvectors per workgroup.
+#include <algorithm>
+
 #include "common.h"
 
 namespace qlra_impl {
@@ -25,7 +27,6 @@ namespace {
 
 constexpr int kW = 64;                          // largest order
 constexpr int kPacked = kW * (kW + 1) / 2;      // packed lower triangle, (i, t) at i (i + 1) / 2 + t
-constexpr int TT = 1024;                        // tridiagonalisation threads: 32 x 32, 2 x 2 entries each
 constexpr int ET = 256;                         // eigenvalue / eigenvector workgroups
 constexpr int kPer = ET / 16;                   // eigenvalues (vectors) per workgroup, 16 lanes each
 constexpr int kRounds = 14;                     // 17-section rounds: width shrinks by 17^14 > 1e17
@@ -64,13 +65,6 @@ __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
-// sum over the 32 lanes of a half wave (all of them receive it)
-__device__ __forceinline__ double half_sum(double v) {
-#pragma unroll
-    for (int o = 16; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
 // lane i's value of v, broadcast (i uniform)
 __device__ __forceinline__ double bcast(double v, int i) {
     const long long u = __double_as_longlong(v);
@@ -80,110 +74,159 @@ __device__ __forceinline__ double bcast(double v, int i) {
 }
 
 // ------------------------------------------------------------------------------------------
+// cross-lane sums on the VALU (DPP), all lanes active
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(u & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+// sum over the 4 lanes of a quad
+__device__ __forceinline__ double quad_sum(double v) {
+    v += dpp<0xB1>(v);       // quad_perm [1, 0, 3, 2]
+    v += dpp<0x4E>(v);       // quad_perm [2, 3, 0, 1]
+    return v;
+}
+// sum over the 16 lanes of a row
+__device__ __forceinline__ double row_sum(double v) {
+    v = quad_sum(v);
+    v += dpp<0x141>(v);      // row_half_mirror
+    v += dpp<0x140>(v);      // row_mirror
+    return v;
+}
+// sum over the wave (uniform result)
+__device__ __forceinline__ double wave_total(double v) {
+    v = row_sum(v);
+    return bcast(v, 0) + bcast(v, 16) + bcast(v, 32) + bcast(v, 48);
+}
+
+// ------------------------------------------------------------------------------------------
 // 1. tridiagonalisation
+//
+// 1024 threads: row r = tid / 16 of G is held by one 16-lane DPP row, lane s owning the
+// columns c = s + 16 kk (kk = 0 .. 3), so matrix-vector products reduce on the VALU and every
+// step skips the column blocks and waves that lie left of / above the active part.
+// Step j: the wave holding row j forms the reflector from that row (the column below the
+// diagonal by Hermitian symmetry); barrier; p = tau G v per row with the wave's share of
+// K = tau/2 v^H p; barrier; the rank-2 update.  v, p and the K shares are double-buffered, so
+// the next reflector needs no third barrier.
+
+constexpr int TT = 1024;
+constexpr int TW = TT / 64;                 // waves
 
 __global__ __launch_bounds__(TT) void k_tridiag(const double* __restrict__ Gall, int64_t gstride, int w,
                                                 double* __restrict__ triall, int store_refl) {
-    __shared__ double col[4 * kW];     // column j below the diagonal, for the next reflector
-    __shared__ double vb[4 * kW];      // reflector v (zero outside rows j+1 .. w-1)
-    __shared__ double pb[4 * kW];      // p = tau G v
-    __shared__ double sq[4 * kW];      // quaternion subdiagonal s_j
+    __shared__ double xb[4 * kW];           // column j below the diagonal
+    __shared__ double vb[2][4 * kW];        // reflector v (zero outside rows j+1 .. w-1)
+    __shared__ double pb[2][4 * kW];        // p = tau G v
+    __shared__ double kr[2][TW];            // per-wave shares of v^H p
+    __shared__ double tb[2];
+    __shared__ double sq[4 * kW];           // quaternion subdiagonal s_j
     __shared__ double dg[kW];
-    __shared__ double kred[32];
-    __shared__ double s_tau;
-    const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = tid >> 4, s = tid & 15;
     const double* G = Gall + (int64_t)blockIdx.x * gstride;
     double* tri = triall + (int64_t)blockIdx.x * kTriStride;
     const int64_t gps = (int64_t)w * w;
 
-    // entries (ty + 32 ri, tx + 32 ci)
-    Q4 g[2][2];
+    Q4 g[4];
 #pragma unroll
-    for (int ri = 0; ri < 2; ri++)
-#pragma unroll
-        for (int ci = 0; ci < 2; ci++) {
-            const int r = ty + 32 * ri, c = tx + 32 * ci;
-            Q4 v{0, 0, 0, 0};
-            if (r < w && c < w) {
-                const int64_t e = (int64_t)r * w + c;
-                v = Q4{G[e], G[gps + e], G[2 * gps + e], G[3 * gps + e]};
-                if (r == c) v.x = v.y = v.z = 0.0;
-            }
-            g[ri][ci] = v;
+    for (int kk = 0; kk < 4; kk++) {
+        const int c = s + 16 * kk;
+        Q4 v{0, 0, 0, 0};
+        if (r < w && c < w) {
+            const int64_t e = (int64_t)r * w + c;
+            v = Q4{G[e], G[gps + e], G[2 * gps + e], G[3 * gps + e]};
+            if (r == c) v.x = v.y = v.z = 0.0;
         }
-    if (tx == 0)
-#pragma unroll
-        for (int ri = 0; ri < 2; ri++) {
-            const int r = ty + 32 * ri;
-            if (r >= 1 && r < w) stq<kW>(col, r, g[ri][0]);
-        }
+        g[kk] = v;
+    }
 
     for (int j = 0; j + 2 < w; j++) {
-        __syncthreads();                                  // col holds column j
-        if (tid < 64) {
-            const Q4 x = (lane > j && lane < w) ? ldq<kW>(col, lane) : Q4{0, 0, 0, 0};
-            const double alpha = sqrt(wave_sum(qn2(x)));
-            const Q4 x1 = ldq<kW>(col, j + 1);
+        const int bsel = j & 1;
+        double* vbj = vb[bsel];
+        double* pbj = pb[bsel];
+        const int kk0 = (j + 1) >> 4;                          // first column block with c > j
+        if (wave == (j >> 2)) {
+            // the row-j lanes publish x_c = G(c, j) = conj(G(j, c)), c > j
+            if (r == j) {
+#pragma unroll
+                for (int kk = 0; kk < 4; kk++) {
+                    const int c = s + 16 * kk;
+                    if (kk >= kk0 && c > j && c < w) stq<kW>(xb, c, qconj(g[kk]));
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const Q4 x = (lane > j && lane < w) ? ldq<kW>(xb, lane) : Q4{0, 0, 0, 0};
+            const double alpha = sqrt(wave_total(qn2(x)));
+            const Q4 x1 = ldq<kW>(xb, j + 1);
             const double ax1 = sqrt(qn2(x1));
             const Q4 phi = ax1 > 0.0 ? qscale(x1, 1.0 / ax1) : Q4{1, 0, 0, 0};
             const double tau = alpha > 0.0 ? 1.0 / (alpha * (alpha + ax1)) : 0.0;
             Q4 v = x;
             if (lane == j + 1) v = qadd(x, qscale(phi, alpha));   // H x = -alpha phi e_1
-            stq<kW>(vb, lane, v);
+            stq<kW>(vbj, lane, v);
             if (store_refl && lane > j && lane < w) stq<kPacked>(tri + OFF_REFL, lane * (lane + 1) / 2 + j, v);
             if (lane == 0) {
-                s_tau = tau;
+                tb[bsel] = tau;
                 stq<kW>(sq, j, qscale(phi, -alpha));
                 tri[OFF_TAU + j] = tau;
             }
         }
         __syncthreads();
-        const double tau = s_tau;
-        {
-            const Q4 vc0 = ldq<kW>(vb, tx), vc1 = ldq<kW>(vb, tx + 32);
-            double kp = 0.0;
+        const double tau = tb[bsel];
+        const bool wave_live = 4 * wave + 3 > j;                // some row of this wave is active
+        if (wave_live) {
+            Q4 vc[4];
 #pragma unroll
-            for (int ri = 0; ri < 2; ri++) {
-                Q4 s = qadd(qmul(g[ri][0], vc0), qmul(g[ri][1], vc1));
-                s.w = half_sum(s.w); s.x = half_sum(s.x); s.y = half_sum(s.y); s.z = half_sum(s.z);
-                s = qscale(s, tau);
-                if (tx == 0) {
-                    stq<kW>(pb, ty + 32 * ri, s);
-                    kp += qdot(ldq<kW>(vb, ty + 32 * ri), s);
-                }
+            for (int kk = 0; kk < 4; kk++) vc[kk] = kk >= kk0 ? ldq<kW>(vbj, s + 16 * kk) : Q4{0, 0, 0, 0};
+            Q4 acc{0, 0, 0, 0};
+#pragma unroll
+            for (int kk = 0; kk < 4; kk++)
+                if (kk >= kk0) acc = qadd(acc, qmul(g[kk], vc[kk]));
+            acc.w = row_sum(acc.w); acc.x = row_sum(acc.x); acc.y = row_sum(acc.y); acc.z = row_sum(acc.z);
+            const Q4 p = qscale(acc, tau);
+            double kp = 0.0;
+            if (s == 0 && r < w) {
+                stq<kW>(pbj, r, p);
+                if (r > j) kp = qdot(ldq<kW>(vbj, r), p);
             }
-            if (tx == 0) kred[ty] = kp;
+            kp = bcast(kp, 0) + bcast(kp, 16) + bcast(kp, 32) + bcast(kp, 48);
+            if (lane == 0) kr[bsel][wave] = kp;
+        } else if (lane == 0) {
+            kr[bsel][wave] = 0.0;
         }
         __syncthreads();
-        const double K = 0.5 * tau * half_sum(kred[tx]);
+        if (wave_live) {
+            const double K = 0.5 * tau * row_sum(kr[bsel][s]);
+            const bool row_live = r > j && r < w;
+            const Q4 vr = ldq<kW>(vbj, r);
+            const Q4 qr = qsub(ldq<kW>(pbj, r), qscale(vr, K));
 #pragma unroll
-        for (int ri = 0; ri < 2; ri++) {
-            const int r = ty + 32 * ri;
-            if (r <= j || r >= w) continue;
-            const Q4 vr = ldq<kW>(vb, r);
-            const Q4 qr = qsub(ldq<kW>(pb, r), qscale(vr, K));
-#pragma unroll
-            for (int ci = 0; ci < 2; ci++) {
-                const int c = tx + 32 * ci;
-                if (c <= j || c >= w) continue;
-                const Q4 vc = ldq<kW>(vb, c);
-                const Q4 qc = qsub(ldq<kW>(pb, c), qscale(vc, K));
-                Q4 t = qsub(qsub(g[ri][ci], qmul(vr, qconj(qc))), qmul(qr, qconj(vc)));
-                if (r == c) t.x = t.y = t.z = 0.0;
-                g[ri][ci] = t;
-                if (c == j + 1 && r > j + 1) stq<kW>(col, r, t);
+            for (int kk = 0; kk < 4; kk++) {
+                const int c = s + 16 * kk;
+                if (kk < kk0) continue;                         // uniform
+                const Q4 vc = ldq<kW>(vbj, c);
+                const Q4 qc = qsub(ldq<kW>(pbj, c), qscale(vc, K));
+                if (row_live && c > j && c < w) {
+                    Q4 t = qsub(qsub(g[kk], qmul(vr, qconj(qc))), qmul(qr, qconj(vc)));
+                    if (r == c) t.x = t.y = t.z = 0.0;
+                    g[kk] = t;
+                }
             }
         }
     }
-    __syncthreads();
+    // diagonal and the last subdiagonal entry s_{w-2} = G(w-1, w-2)
 #pragma unroll
-    for (int ri = 0; ri < 2; ri++)
-#pragma unroll
-        for (int ci = 0; ci < 2; ci++) {
-            const int r = ty + 32 * ri, c = tx + 32 * ci;
-            if (r == c && r < w) dg[r] = g[ri][ci].w;
-        }
-    if (tid == 0 && w >= 2) stq<kW>(sq, w - 2, ldq<kW>(col, w - 1));
+    for (int kk = 0; kk < 4; kk++) {
+        const int c = s + 16 * kk;
+        if (r < w && c == r) dg[r] = g[kk].w;
+        if (w >= 2 && r == w - 1 && c == w - 2) stq<kW>(sq, w - 2, g[kk]);
+    }
     __syncthreads();
     if (tid == 0) {
         // D: ph_0 = 1, ph_{j+1} = s_j ph_j / |s_j| turns s_j into the real b_j = |s_j|
@@ -195,9 +238,9 @@ __global__ __launch_bounds__(TT) void k_tridiag(const double* __restrict__ Gall,
             stq<kW>(tri + OFF_PH, i, pj);
             double br = 0.0;
             if (i + 1 < w) {
-                const Q4 s = ldq<kW>(sq, i);
-                br = sqrt(qn2(s));
-                pj = br > 0.0 ? qscale(qmul(s, pj), 1.0 / br) : Q4{1, 0, 0, 0};
+                const Q4 sj = ldq<kW>(sq, i);
+                br = sqrt(qn2(sj));
+                pj = br > 0.0 ? qscale(qmul(sj, pj), 1.0 / br) : Q4{1, 0, 0, 0};
             }
             tri[OFF_B + i] = br;
             tri[OFF_B2 + i] = br * br;
@@ -217,25 +260,35 @@ __global__ __launch_bounds__(TT) void k_tridiag(const double* __restrict__ Gall,
 // 2. eigenvalues
 
 // Number of eigenvalues of T below x: sign changes of the Sturm sequence p_0 = 1,
-// p_1 = d_0 - x, p_i = (d_{i-1} - x) p_{i-1} - b_{i-2}^2 p_{i-2} (rescaled to stay in range).
-// Lane i of the wave holds d_i and b_i^2.
+// p_1 = d_0 - x, p_i = (d_{i-1} - x) p_{i-1} - b_{i-2}^2 p_{i-2}.  Lane i of the wave holds d_i
+// and b_i^2, scaled so that |d_i - x| <= 2 and b_i^2 <= 4: |p| grows at most 6-fold per step,
+// so a rescale every fourth step keeps it in range, and only one FMA per step is on the chain.
+__device__ __forceinline__ void sturm_step(double di, double bi, double x, double& pm, double& pc, int& prev,
+                                           int& cnt) {
+    const double pn = fma(di - x, pc, -bi * pm);
+    pm = pc;
+    pc = pn;
+    // the sign of p_i (an exact zero keeps the previous sign), without branches
+    int neg = pn < 0.0;
+    neg = pn == 0.0 ? prev : neg;
+    cnt += neg ^ prev;
+    prev = neg;
+}
+
 __device__ int sturm_count(double dv, double b2v, int w, double x) {
     double pm = 1.0, pc = bcast(dv, 0) - x;
-    int prev_neg = pc < 0.0;
-    int cnt = prev_neg;
-    for (int i = 1; i < w; i++) {
-        const double di = bcast(dv, i), bi = bcast(b2v, i - 1);
-        const double pn = (di - x) * pc - bi * pm;
-        pm = pc;
-        pc = pn;
-        const double a = fabs(pc);
-        const double sc = a > 1e150 ? 1e-150 : ((a < 1e-150 && fabs(pm) < 1e-150) ? 1e150 : 1.0);
+    int prev = pc < 0.0 ? 1 : 0;
+    int cnt = prev;
+    int i = 1;
+    for (; i + 3 < w; i += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) sturm_step(bcast(dv, i + u), bcast(b2v, i + u - 1), x, pm, pc, prev, cnt);
+        const double a = fmax(fabs(pc), fabs(pm));
+        const double sc = a > 1e150 ? 1e-150 : (a < 1e-150 ? 1e150 : 1.0);
         pc *= sc;
         pm *= sc;
-        const int neg = pc < 0.0 ? 1 : (pc > 0.0 ? 0 : prev_neg);
-        cnt += neg ^ prev_neg;
-        prev_neg = neg;
     }
+    for (; i < w; i++) sturm_step(bcast(dv, i), bcast(b2v, i - 1), x, pm, pc, prev, cnt);
     return cnt;
 }
 
@@ -245,10 +298,13 @@ __global__ __launch_bounds__(ET) void k_eigvals(double* __restrict__ triall, int
                                                 int64_t lam_stride) {
     double* tri = triall + (int64_t)blockIdx.y * kTriStride;
     const int tid = threadIdx.x, lane = tid & 63, s16 = tid & 15;
-    const double dv = lane < w ? tri[OFF_D + lane] : 0.0;
-    const double b2v = lane < w ? tri[OFF_B2 + lane] : 0.0;
+    // exact power-of-two scaling: |bounds| <= 1 afterwards
+    int ex;
+    frexp(fmax(fabs(tri[OFF_BND]), fabs(tri[OFF_BND + 1])), &ex);
+    const double dv = lane < w ? ldexp(tri[OFF_D + lane], -ex) : 0.0;
+    const double b2v = lane < w ? ldexp(tri[OFF_B2 + lane], -2 * ex) : 0.0;
     const int k = blockIdx.x * kPer + (tid >> 4);          // ascending index
-    double a = tri[OFF_BND], bb = tri[OFF_BND + 1];
+    double a = ldexp(tri[OFF_BND], -ex), bb = ldexp(tri[OFF_BND + 1], -ex);
     for (int round = 0; round < kRounds; round++) {
         const double x = a + (bb - a) * (double)(s16 + 1) / 17.0;
         const int c = sturm_count(dv, b2v, w, x);
@@ -260,6 +316,8 @@ __global__ __launch_bounds__(ET) void k_eigvals(double* __restrict__ triall, int
         a = xa;
         bb = xb;
     }
+    a = ldexp(a, ex);
+    bb = ldexp(bb, ex);
     if (k < w && s16 == 0) {
         const double lam = 0.5 * (a + bb);
         tri[OFF_LAM + k] = lam;
@@ -275,20 +333,44 @@ struct VecLds {
     double ph[4 * kW];
     double dg[kW], b[kW], b2[kW], lam[kW], tau[kW];
     double X[kW * kW];        // eigenvectors of T, ascending index k at X + k * kW
-    double piv[kW * kW];      // forward pivots of the twisted factorisations
+    double dm[kW * kW];       // backward pivots of the twisted factorisations
     double bnd[2];
 };
 
-// grid ceil(w / kPer): workgroup g returns the eigenvectors of ascending indices
-// [g kPer, g kPer + kPer) as columns w - 1 - k of E (descending order).  Clusters reaching
-// across the slice are recomputed whole (the same arithmetic in every workgroup).
+constexpr int kVecPer = ET / 64;   // eigenvectors per workgroup, one wave each
+
+// x / y from the hardware reciprocal refined by two Newton steps (a few ulp; the twisted
+// factorisation only needs pivots to working accuracy)
+__device__ __forceinline__ double fdiv(double x, double y) {
+    double r = __builtin_amdgcn_rcp(y);
+    r = fma(r, fma(-y, r, 1.0), r);
+    r = fma(r, fma(-y, r, 1.0), r);
+    return x * r;
+}
+
+// grid ceil(w / kVecPer): workgroup g returns the eigenvectors of ascending indices
+// [g kVecPer, g kVecPer + kVecPer) as columns w - 1 - k of E (descending order).  Clusters
+// reaching across the slice are recomputed whole (the same arithmetic in every workgroup).
 __global__ __launch_bounds__(ET) void k_eigvecs(const double* __restrict__ tri, int w, double* __restrict__ E) {
     __shared__ VecLds L;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int np = w * (w + 1) / 2;
-    for (int e = tid; e < np; e += ET)
+    for (int base = 0; base < np; base += 4 * ET) {
+        double v[4][4];
 #pragma unroll
-        for (int p = 0; p < 4; p++) L.refl[p * kPacked + e] = tri[OFF_REFL + p * kPacked + e];
+        for (int u = 0; u < 4; u++) {
+            const int e = min(base + u * ET + tid, np - 1);
+#pragma unroll
+            for (int p = 0; p < 4; p++) v[u][p] = tri[OFF_REFL + p * kPacked + e];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int e = base + u * ET + tid;
+            if (e < np)
+#pragma unroll
+                for (int p = 0; p < 4; p++) L.refl[p * kPacked + e] = v[u][p];
+        }
+    }
     for (int i = tid; i < w; i += ET) {
         L.dg[i] = tri[OFF_D + i];
         L.b[i] = tri[OFF_B + i];
@@ -303,54 +385,59 @@ __global__ __launch_bounds__(ET) void k_eigvecs(const double* __restrict__ tri, 
 
     const double tnorm = fmax(fabs(L.bnd[0]), fabs(L.bnd[1])) + 1e-300;
     const double ctol = 1e-10 * tnorm;
-    const int k0 = blockIdx.x * kPer, k1 = min(k0 + kPer, w);
+    const int k0 = blockIdx.x * kVecPer, k1 = min(k0 + kVecPer, w);
     int c0 = k0, c1 = k1;
     while (c0 > 0 && L.lam[c0] - L.lam[c0 - 1] <= ctol) c0--;
     while (c1 < w && L.lam[c1] - L.lam[c1 - 1] <= ctol) c1++;
 
     // twisted factorisation of T - mu for each eigenvalue mu in [c0, c1): forward pivots
-    // dp_0 = d_0 - mu, dp_i = d_i - mu - b_{i-1}^2 / dp_{i-1}; backward pivots from the bottom;
-    // twist r with the least |gamma_r| = |dp_r + dm_r - (d_r - mu)|; x_r = 1 propagated both ways.
+    // dp_0 = d_0 - mu, dp_i = d_i - mu - b_{i-1}^2 / dp_{i-1} and backward pivots
+    // dm_{w-1} = d_{w-1} - mu, dm_i = d_i - mu - b_i^2 / dm_{i+1} (the two recurrences
+    // interleaved); twist r with the least |gamma_r| = |dp_r + dm_r - (d_r - mu)|; x_r = 1,
+    // x_{i+1} = -b_i x_i / dm_{i+1} below r and x_{i-1} = -b_{i-1} x_i / dp_{i-1} above.
     const double tiny = 1e-300 + 2.220446049250313e-16 * tnorm * 1e-3;
     for (int k = c0 + tid; k < c1; k += ET) {
         const double mu = L.lam[k];
-        double* dp = L.piv + k * kW;
-        double* x = L.X + k * kW;
-        double prev = L.dg[0] - mu;
-        if (fabs(prev) < tiny) prev = -tiny;
-        dp[0] = prev;
+        double* x = L.X + k * kW;          // forward pivots first, the vector at the end
+        double* dm = L.dm + k * kW;
+        double fp = L.dg[0] - mu, bp = L.dg[w - 1] - mu;
+        if (fabs(fp) < tiny) fp = -tiny;
+        if (fabs(bp) < tiny) bp = -tiny;
+        x[0] = fp;
+        dm[w - 1] = bp;
         for (int i = 1; i < w; i++) {
-            double v = (L.dg[i] - mu) - L.b2[i - 1] / prev;
-            if (fabs(v) < tiny) v = -tiny;
-            dp[i] = v;
-            prev = v;
+            const int ib = w - 1 - i;
+            double f = (L.dg[i] - mu) - fdiv(L.b2[i - 1], fp);
+            double g = (L.dg[ib] - mu) - fdiv(L.b2[ib], bp);
+            if (fabs(f) < tiny) f = -tiny;
+            if (fabs(g) < tiny) g = -tiny;
+            x[i] = f;
+            dm[ib] = g;
+            fp = f;
+            bp = g;
         }
-        double dm = L.dg[w - 1] - mu;
-        if (fabs(dm) < tiny) dm = -tiny;
-        x[w - 1] = dm;                               // backward pivots kept in x for now
         int r = w - 1;
-        double best = fabs(dp[w - 1]);
+        double best = fabs(x[w - 1]);
         for (int i = w - 2; i >= 0; i--) {
-            double v = (L.dg[i] - mu) - L.b2[i] / dm;
-            if (fabs(v) < tiny) v = -tiny;
-            x[i] = v;
-            dm = v;
-            const double gam = fabs(dp[i] + v - (L.dg[i] - mu));
+            const double gam = fabs(x[i] + dm[i] - (L.dg[i] - mu));
             if (gam < best) { best = gam; r = i; }
         }
-        double xv = 1.0, nrm = 1.0;
-        for (int i = r; i + 1 < w; i++) {            // x_{i+1} = -b_i x_i / dm_{i+1}
-            const double nx = -L.b[i] * xv / x[i + 1];
-            x[i + 1] = nx;
-            xv = nx;
-            nrm += nx * nx;
-        }
-        xv = 1.0;
-        for (int i = r; i > 0; i--) {                // x_{i-1} = -b_{i-1} x_i / dp_{i-1}
-            const double nx = -L.b[i - 1] * xv / dp[i - 1];
-            x[i - 1] = nx;
-            xv = nx;
-            nrm += nx * nx;
+        // both propagations from r at once: downward writes x[i > r], upward reads the
+        // forward pivots x[i < r] before overwriting them
+        double xd = 1.0, xu = 1.0, nrm = 1.0;
+        const int steps = max(w - 1 - r, r);
+        for (int t = 1; t <= steps; t++) {
+            const int id = r + t, iu = r - t;
+            if (id < w) {
+                xd = -fdiv(L.b[id - 1] * xd, dm[id]);
+                x[id] = xd;
+                nrm += xd * xd;
+            }
+            if (iu >= 0) {
+                xu = -fdiv(L.b[iu] * xu, x[iu]);
+                x[iu] = xu;
+                nrm += xu * xu;
+            }
         }
         x[r] = 1.0;
         nrm = 1.0 / sqrt(nrm);
@@ -381,51 +468,27 @@ __global__ __launch_bounds__(ET) void k_eigvecs(const double* __restrict__ tri, 
         }
     }
     __syncthreads();
-    // back-transformation y = H_0 ... H_{w-3} D x: one 16-lane group per eigenvector, lane s16
-    // holds rows s16, s16 + 16, s16 + 32, s16 + 48
-    const int s16 = tid & 15;
-    const int k = k0 + (tid >> 4);
-    const bool act = k < k1;
-    const double* xk = L.X + (act ? k : c0) * kW;
-    Q4 y[4];
-#pragma unroll
-    for (int u = 0; u < 4; u++) {
-        const int i = s16 + 16 * u;
-        y[u] = Q4{0, 0, 0, 0};
-        if (i < w) y[u] = qscale(ldq<kW>(L.ph, i), xk[i]);
-    }
+    // back-transformation y = H_0 ... H_{w-3} D x: one wave per eigenvector, lane i = row i,
+    // the reflector of the next step loaded while the current one is applied
+    const int k = k0 + wave;
+    if (k >= k1) return;                                   // uniform per wave
+    const int i = lane;
+    Q4 y{0, 0, 0, 0};
+    if (i < w) y = qscale(ldq<kW>(L.ph, i), L.X[k * kW + i]);
+    auto refl = [&](int j) { return (i > j && i < w) ? ldq<kPacked>(L.refl, i * (i + 1) / 2 + j) : Q4{0, 0, 0, 0}; };
+    Q4 vn = w >= 3 ? refl(w - 3) : Q4{0, 0, 0, 0};
     for (int j = w - 3; j >= 0; j--) {
+        const Q4 v = vn;
+        if (j > 0) vn = refl(j - 1);
         const double tj = L.tau[j];
-        if (tj == 0.0) continue;                      // uniform
-        Q4 s{0, 0, 0, 0};
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const int i = s16 + 16 * u;
-            if (i > j && i < w) s = qadd(s, qmul(qconj(ldq<kPacked>(L.refl, i * (i + 1) / 2 + j)), y[u]));
-        }
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) {
-            s.w += __shfl_xor(s.w, o, 64); s.x += __shfl_xor(s.x, o, 64);
-            s.y += __shfl_xor(s.y, o, 64); s.z += __shfl_xor(s.z, o, 64);
-        }
-        s = qscale(s, tj);
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const int i = s16 + 16 * u;
-            if (i > j && i < w) y[u] = qsub(y[u], qmul(ldq<kPacked>(L.refl, i * (i + 1) / 2 + j), s));
-        }
+        Q4 s = qmul(qconj(v), y);
+        s.w = wave_total(s.w); s.x = wave_total(s.x); s.y = wave_total(s.y); s.z = wave_total(s.z);
+        y = qsub(y, qmul(v, qscale(s, tj)));
     }
-    if (act) {
+    if (i < w) {
         const int64_t gps = (int64_t)w * w;
-        const int kk = w - 1 - k;
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const int i = s16 + 16 * u;
-            if (i < w) {
-                const int64_t o = (int64_t)i * w + kk;
-                E[o] = y[u].w; E[gps + o] = y[u].x; E[2 * gps + o] = y[u].y; E[3 * gps + o] = y[u].z;
-            }
-        }
+        const int64_t o = (int64_t)i * w + (w - 1 - k);
+        E[o] = y.w; E[gps + o] = y.x; E[2 * gps + o] = y.y; E[3 * gps + o] = y.z;
     }
 }
 
@@ -439,12 +502,29 @@ __global__ __launch_bounds__(256) void k_gram_small(const double* __restrict__ X
     const int64_t ps = (int64_t)w * w;
     const int a0 = blockIdx.x * 16, b0 = blockIdx.y * 16;
     const int tid = threadIdx.x;
-    for (int e = tid; e < w * 16; e += 256) {
-        const int i = e >> 4, cc = e & 15;
+    const int n = w * 16;
+    for (int base = 0; base < n; base += 4 * 256) {
+        double va[4][4], vb[4][4];
 #pragma unroll
-        for (int p = 0; p < 4; p++) {
-            sa[p * kW * 16 + e] = a0 + cc < w ? X[p * ps + (int64_t)i * w + a0 + cc] : 0.0;
-            sb[p * kW * 16 + e] = b0 + cc < w ? X[p * ps + (int64_t)i * w + b0 + cc] : 0.0;
+        for (int u = 0; u < 4; u++) {
+            const int e = min(base + u * 256 + tid, n - 1);
+            const int i = e >> 4, cc = e & 15;
+#pragma unroll
+            for (int p = 0; p < 4; p++) {
+                va[u][p] = X[p * ps + (int64_t)i * w + min(a0 + cc, w - 1)];
+                vb[u][p] = X[p * ps + (int64_t)i * w + min(b0 + cc, w - 1)];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int e = base + u * 256 + tid;
+            if (e >= n) continue;
+            const int cc = e & 15;
+#pragma unroll
+            for (int p = 0; p < 4; p++) {
+                sa[p * kW * 16 + e] = a0 + cc < w ? va[u][p] : 0.0;
+                sb[p * kW * 16 + e] = b0 + cc < w ? vb[u][p] : 0.0;
+            }
         }
     }
     __syncthreads();
@@ -480,6 +560,21 @@ __global__ __launch_bounds__(256) void k_left_vectors(const double* __restrict__
     U[e] = s.w * inv; U[ps + e] = s.x * inv; U[2 * ps + e] = s.y * inv; U[3 * ps + e] = s.z * inv;
 }
 
+// From the eigendecomposition G = E diag(lam) E^H of a view's Gram Y^H Y (lam descending):
+// S_j = sqrt(max(lam_j, 0)) and W = E_k diag(1 / S) (w x k, ld k; zero columns where S_j = 0).
+__global__ __launch_bounds__(256) void k_svals(const double* __restrict__ lam, const double* __restrict__ E, int w,
+                                               int k, double* __restrict__ S, double* __restrict__ Wk) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < k) S[e] = sqrt(fmax(lam[e], 0.0));
+    if (e >= (int64_t)w * k) return;
+    const int i = (int)(e / k), j = (int)(e % k);
+    const double sj = sqrt(fmax(lam[j], 0.0));
+    const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
+    const int64_t eps = (int64_t)w * w, wps = (int64_t)w * k, src = (int64_t)i * w + j;
+#pragma unroll
+    for (int p = 0; p < 4; p++) Wk[p * wps + e] = E[p * eps + src] * inv;
+}
+
 // e_b = sqrt(max(0, ||A||^2 - sum of the k largest max(lambda, 0)) / ||A||^2) per problem b.
 __global__ void k_estimate_batch(const double* __restrict__ triall, int nprob, int w, int k,
                                  const double* __restrict__ nA2, double* __restrict__ e) {
@@ -504,7 +599,9 @@ hipError_t heig_launch(const double* G, int64_t w, double* lam, double* E, doubl
     hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(TT), 0, st, G, (int64_t)0, (int)w, work, E ? 1 : 0);
     const unsigned slices = (unsigned)((w + kPer - 1) / kPer);
     hipLaunchKernelGGL(k_eigvals, dim3(slices, 1), dim3(ET), 0, st, work, (int)w, lam, (int64_t)0);
-    if (E) hipLaunchKernelGGL(k_eigvecs, dim3(slices), dim3(ET), 0, st, (const double*)work, (int)w, E);
+    if (E)
+        hipLaunchKernelGGL(k_eigvecs, dim3((unsigned)((w + kVecPer - 1) / kVecPer)), dim3(ET), 0, st,
+                           (const double*)work, (int)w, E);
     return hipGetLastError();
 }
 
@@ -538,6 +635,12 @@ hipError_t qsvd_gram_launch(const double* X, int64_t w, double* U, double* S, do
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_left_vectors, dim3((unsigned)((ps + 255) / 256)), dim3(256), 0, st, X, (int)w, lam,
                        Vout, S, U);
+    return hipGetLastError();
+}
+
+hipError_t svals_launch(const double* lam, const double* E, int64_t w, int k, double* S, double* Wk, hipStream_t st) {
+    const int64_t n = std::max<int64_t>(w * k, k);
+    hipLaunchKernelGGL(k_svals, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, lam, E, (int)w, k, S, Wk);
     return hipGetLastError();
 }
 

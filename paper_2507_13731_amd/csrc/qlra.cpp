@@ -335,14 +335,42 @@ void finish(Ctx& c, const Bufs& b, const Problem& pr, const double* R, int64_t w
     }
 }
 
+// The last view without its QR.  With Y = A X (or A^H X) = Q R, R^H R = Y^H Y, so the truncated
+// QSVD of R (Alg. 2 and Alg. 4, last lines) follows from the eigendecomposition
+// Y^H Y = E diag(lam) E^H: S = sqrt(lam_k), the Y-side factor Q Uh = Y E_k S^{-1} and the
+// X-side factor X E_k.  y_is_u: odd budget (Y = A Q2 gives U, X = Q2 gives V); otherwise Y gives
+// V and X = Q1 gives U.  For w <= heig_max().
+void finish_gram(Ctx& c, const Bufs& b, const Problem& pr, const float* Y, int64_t rows_y, const float* X,
+                 int64_t ldx, int64_t rows_x, int64_t w, bool y_is_u) {
+    const int k = pr.k;
+    qg(c, desc(OP_HN, MATH_F64, Y, w, rows_y * w, 0, Y, w, rows_y * w, 0, c.G, w, w * w, 1, w, w, rows_y));
+    if (!c.dry) {
+        note(c, heig_launch(c.G, w, b.Sw, b.Rh, b.qsvd_work, c.st));
+        note(c, svals_launch(b.Sw, b.Rh, w, k, pr.S, b.Lh, c.st));
+        if (pr.estimate) note(c, estimate_launch(pr.S, k, b.nA2, pr.pass_err + (pr.v - 1), c.st));
+    }
+    float* Oy = y_is_u ? pr.U : pr.V;
+    float* Ox = y_is_u ? pr.V : pr.U;
+    const int64_t ldoy = y_is_u ? pr.ldu : pr.ldv, psoy = y_is_u ? pr.ups : pr.vps;
+    const int64_t ldox = y_is_u ? pr.ldv : pr.ldu, psox = y_is_u ? pr.vps : pr.ups;
+    qg(c, desc(OP_NN, MATH_F64, Y, w, rows_y * w, 0, b.Lh, k, w * k, 1, Oy, ldoy, psoy, 0, rows_y, k, w));
+    qg(c, desc(OP_NN, MATH_F64, X, ldx, rows_x * ldx, 0, b.Rh, w, w * w, 1, Ox, ldox, psox, 0, rows_x, k, w));
+    if (!c.dry) note(c, phase_launch(pr.U, pr.m, pr.ldu, pr.ups, pr.V, pr.n, pr.ldv, pr.vps, k, c.st));
+}
+
+// The product of a view alone: T = A X (forward, m x w) or T = A^H X (adjoint, n x w), ld w.
+void view_product(Ctx& c, const Problem& pr, bool adjoint, const float* X, int64_t ldx, int64_t w, float* T) {
+    const int64_t rows_out = adjoint ? pr.n : pr.m;
+    const int64_t kdim = adjoint ? pr.m : pr.n;
+    qg(c, desc(adjoint ? OP_HN : OP_NN, MATH_F32, pr.A, pr.lda, pr.aps, 0, X, ldx, kdim * ldx, 0, T, w, rows_out * w, 0,
+               rows_out, w, kdim));
+}
+
 // One view: C = A X (forward) or C = A^H X (adjoint), then its QR.
 void view(Ctx& c, const Problem& pr, bool adjoint, const float* X, int64_t ldx, int64_t w, float* T, float* Q,
           int64_t ldq, double* R, int rounds = 1, double* G0 = nullptr) {
     const int64_t rows_out = adjoint ? pr.n : pr.m;
-    const int64_t kdim = adjoint ? pr.m : pr.n;
-    const int64_t xps = kdim * ldx;
-    qg(c, desc(adjoint ? OP_HN : OP_NN, MATH_F32, pr.A, pr.lda, pr.aps, 0, X, ldx, xps, 0, T, w, rows_out * w, 0,
-               rows_out, w, kdim));
+    view_product(c, pr, adjoint, X, ldx, w, T);
     cholqr(c, T, rows_out, w, w, rows_out * w, Q, ldq, rows_out * ldq, R, rounds, G0);
 }
 
@@ -358,7 +386,15 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
     const float* Q2cur = b.Om;
     if (!d.krylov) {
         // Alg. 2: odd views [Q1, R1] = QR(A Q2), even views [Q2, R2] = QR(A^H Q1)
+        const bool gram_final = l <= heig_max();
         for (int i = 1; i <= pr.v; i++) {
+            if (i == pr.v && gram_final) {
+                fork_estimates(c, b, pr, l);
+                const bool odd = i % 2 == 1;
+                view_product(c, pr, !odd, odd ? Q2cur : b.Q1, l, l, b.T);
+                finish_gram(c, b, pr, b.T, odd ? pr.m : pr.n, odd ? Q2cur : b.Q1, l, odd ? pr.n : pr.m, l, odd);
+                return;
+            }
             // R is kept for the last view (the final QSVD) and for side-stream estimates from R
             double* R = (i == pr.v || (pr.estimate && !b.Gs)) ? b.Rv + (size_t)(i - 1) * 4 * l2 : nullptr;
             // the last two views produce the returned bases: CholeskyQR2 there
@@ -402,13 +438,23 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
         stack_in(b.Q1, d.s);
         fork_estimates(c, b, pr, l);
         orth_stack(c, b.stack, pr.m, Wk, l, b.Cbuf);
-        view(c, pr, true, b.stack, Wk, Wk, b.T, b.Q2, Wk, b.Rfin, 2);
-        finish(c, b, pr, b.Rfin, Wk, b.stack, Wk, b.Q2, Wk, true);
+        if (Wk <= heig_max()) {
+            view_product(c, pr, true, b.stack, Wk, Wk, b.T);
+            finish_gram(c, b, pr, b.T, pr.n, b.stack, Wk, pr.m, Wk, false);
+        } else {
+            view(c, pr, true, b.stack, Wk, Wk, b.T, b.Q2, Wk, b.Rfin, 2);
+            finish(c, b, pr, b.Rfin, Wk, b.stack, Wk, b.Q2, Wk, true);
+        }
     } else {
         fork_estimates(c, b, pr, l);
         orth_stack(c, b.stack, pr.n, Wk, l, b.Cbuf);
-        view(c, pr, false, b.stack, Wk, Wk, b.T, b.Q1, Wk, b.Rfin, 2);
-        finish(c, b, pr, b.Rfin, Wk, b.Q1, Wk, b.stack, Wk, false);
+        if (Wk <= heig_max()) {
+            view_product(c, pr, false, b.stack, Wk, Wk, b.T);
+            finish_gram(c, b, pr, b.T, pr.m, b.stack, Wk, pr.n, Wk, true);
+        } else {
+            view(c, pr, false, b.stack, Wk, Wk, b.T, b.Q1, Wk, b.Rfin, 2);
+            finish(c, b, pr, b.Rfin, Wk, b.Q1, Wk, b.stack, Wk, false);
+        }
     }
 }
 
@@ -560,12 +606,12 @@ int qlra(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stri
     hipGraph_t graph = nullptr;
     const hipError_t ee = hipStreamEndCapture(cap, &graph);
     if (c.err != hipSuccess || ee != hipSuccess || !graph) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         return QLRA_E_HIP;
     }
     hipGraphExec_t exec = nullptr;
     const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     if (ie != hipSuccess) return QLRA_E_HIP;
     if (g_graphs.size() >= kMaxGraphs) {
         size_t lru = 0;
@@ -573,7 +619,7 @@ int qlra(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stri
             if (g_graphs[i].last < g_graphs[lru].last) lru = i;
         // the evicted graph may still be in flight on some stream
         if (hipDeviceSynchronize() != hipSuccess) return QLRA_E_HIP;
-        hipGraphExecDestroy(g_graphs[lru].exec);
+        (void)hipGraphExecDestroy(g_graphs[lru].exec);
         g_graphs.erase(g_graphs.begin() + (long)lru);
     }
     g_graphs.push_back(GraphEntry{key, exec, ++g_graph_clock});
