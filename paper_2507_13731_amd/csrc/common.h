@@ -27,8 +27,10 @@ enum QOp { OP_NN = 0, OP_HN = 1 };   // C = A B  |  C = A^H B
 // How the result is stored.
 enum QStore { ST_SET = 0, ST_SUB = 1 };   // C = R  |  C = C - R
 
-// Arithmetic of a qgemm launch.
-enum QMath { MATH_F32 = 0, MATH_F64 = 1 };
+// Arithmetic of a qgemm launch.  MATH_BF16 / MATH_F16: A is a low-precision copy laid out as
+// the rows of the output (for OP_HN the transposed copy A^T; op then only selects the
+// conjugation signs), B is FP32 and converted per launch, C is FP32 and multiplied by *cscale.
+enum QMath { MATH_F32 = 0, MATH_F64 = 1, MATH_BF16 = 2, MATH_F16 = 3 };
 
 struct QgemmDesc {
     QOp op;
@@ -40,6 +42,7 @@ struct QgemmDesc {
     void* C; int64_t ldc, cps;
     int64_t M, N, K;           // C is M x N, reduction length K
     const int* skip_flag;      // if non-null and *skip_flag == 0 the launch does nothing
+    const float* cscale;       // low-precision math: device scalar the result is multiplied by
 };
 
 // Device workspace carved into aligned regions.
@@ -62,9 +65,18 @@ struct QgemmScratch {
     unsigned* counters;     // qgemm_counter_count entries, zero at rest
 };
 
-size_t qgemm_partial_bytes(const QgemmDesc& d);
+size_t qgemm_partial_bytes(const QgemmDesc& d);   // split-K partials (+ the converted B, low precision)
 size_t qgemm_counter_count(const QgemmDesc& d);
 hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t st);
+
+// Low-precision copies of A (m x n, four FP32 planes): Alo (m x n, ld n) and Alo_t = A^T (n x m,
+// ld m), both scaled by *scale (read on the device; null: 1); elements are TL = bf16 or fp16
+// by prec (QLRA_BF16 / QLRA_FP16).
+hipError_t lowp_copy_launch(const float* A, int64_t m, int64_t n, int64_t lda, int64_t aps, int prec, void* Alo,
+                            void* Alo_t, const float* scale, hipStream_t st);
+// FP16 scale from ||A||_F^2 (nA2): scale = 2^e with e = 14 - ceil(log2 ||A||_F) (so that every
+// |a| * scale <= 2^14), inv = 1 / scale; BF16: scale = inv = 1.
+hipError_t lowp_scale_launch(const double* nA2, int prec, float* scale, float* inv, hipStream_t st);
 
 hipError_t omega_launch(uint64_t seed, int64_t n, int64_t l, float* Om, int64_t ld, int64_t ps,
                         hipStream_t st);

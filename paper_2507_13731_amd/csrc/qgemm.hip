@@ -372,6 +372,222 @@ hipError_t launch_f32(const Plan& pl, const KParams& kp, hipStream_t st) {
     return hipErrorInvalidValue;
 }
 
+// ------------------------------------------------------------------------------------------
+// Low-precision views: BF16 / FP16 operands, v_mfma_f32_16x16x32_{bf16,f16}, FP32 accumulation.
+//
+// A is a low-precision copy laid out as the rows of the output (A itself for A B, the
+// transposed copy A^T for A^H B), so the MFMA A operand (row l % 16, eight consecutive k at
+// 8 (l / 16)) is one 16-byte load per lane straight from global memory: every A element is used
+// by exactly one wave, so it bypasses LDS.  The thin operand is converted once per launch into
+// Bt[plane][column][k] (low precision, columns padded to 16, k padded to LBK) and each K step's
+// tile is staged through LDS for the four waves.  Each wave owns 16 rows of the output and all
+// its column tiles in the four planes.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+template <class TL>
+struct LpMma;
+template <>
+struct LpMma<__bf16> {
+    using v8 = bf16x8;
+    static __device__ __forceinline__ f32x4 mma(v8 a, v8 b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct LpMma<_Float16> {
+    using v8 = f16x8;
+    static __device__ __forceinline__ f32x4 mma(v8 a, v8 b, f32x4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+// flip the sign bit of eight 16-bit values
+template <class V>
+__device__ __forceinline__ V neg8(V v) {
+    u32x4 u = __builtin_bit_cast(u32x4, v);
+    u ^= 0x80008000u;
+    return __builtin_bit_cast(V, u);
+}
+
+constexpr int LBK = 64;    // K per step: two MFMA k-blocks of 32
+constexpr int LBM = 64;    // output rows per workgroup (16 per wave)
+
+struct LpParams {
+    const void* A; int64_t lda, aps;
+    const void* Bt; int64_t bkp;          // converted thin operand: [4][Np][bkp]
+    float* C; int64_t ldc, cps;
+    int64_t M, N, K;
+    int64_t kchunk;
+    int splits;
+    float* part;
+    int64_t Mp, Np;
+    const int* skip;
+    const float* cscale;
+};
+
+// Bt[p][c][k] = (TL) B[p][k][c] (zero padded to Np x Kp)
+template <class TL>
+__global__ __launch_bounds__(256) void k_lp_thin(const float* __restrict__ B, int64_t ldb, int64_t bps, int64_t K,
+                                                 int64_t N, TL* __restrict__ Bt, int64_t Np, int64_t Kp) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 4 * Np * Kp) return;
+    const int64_t p = e / (Np * Kp), rem = e - p * Np * Kp, c = rem / Kp, k = rem - c * Kp;
+    const float x = (k < K && c < N) ? B[p * bps + k * ldb + c] : 0.0f;
+    Bt[e] = (TL)x;
+}
+
+template <class TL, bool ADJ, int CN>
+__global__ __launch_bounds__(256) void k_qgemm_lp(LpParams P) {
+    using L = LpMma<TL>;
+    using v8 = typename L::v8;
+    constexpr int NP = 16 * CN;
+    constexpr int SK = LBK + 8;   // LDS row stride of the staged tile (elements)
+    __shared__ __attribute__((aligned(16))) TL sB[4 * NP * SK];
+    if (P.skip && *P.skip == 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int split = blockIdx.z;
+    const int64_t kb = (int64_t)split * P.kchunk;
+    const int64_t ke = kb + P.kchunk < P.K ? kb + P.kchunk : P.K;
+    const int ar = lane & 15, ak = 8 * (lane >> 4);
+    const int64_t rbase = (int64_t)blockIdx.x * LBM + 16 * wave;
+    const int64_t arow = rbase + ar;
+    const bool arow_ok = arow < P.M;
+    const TL* __restrict__ Ab = (const TL*)P.A + (arow_ok ? arow : 0) * P.lda;
+    const TL* __restrict__ Bt = (const TL*)P.Bt;
+    const bool avec = (P.lda % 8) == 0 && (P.aps % 8) == 0 && ((uintptr_t)P.A % 16) == 0;
+
+    f32x4 acc[4][CN];
+#pragma unroll
+    for (int p = 0; p < 4; p++)
+#pragma unroll
+        for (int cn = 0; cn < CN; cn++) acc[p][cn] = f32x4{0, 0, 0, 0};
+
+    for (int64_t k0 = kb; k0 < ke; k0 += LBK) {
+        // A fragments for both k-blocks of this step
+        v8 a[4][2];
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int64_t kk = k0 + 32 * h + ak;
+                const TL* src = Ab + q * P.aps + kk;
+                if (arow_ok && avec && kk + 8 <= ke) {
+                    a[q][h] = *reinterpret_cast<const v8*>(src);
+                } else {
+                    v8 t;
+#pragma unroll
+                    for (int u = 0; u < 8; u++) t[u] = (arow_ok && kk + u < ke) ? src[u] : (TL)0.0f;
+                    a[q][h] = t;
+                }
+            }
+        __syncthreads();   // the previous tile is consumed
+        // stage Bt[:, :, k0 .. k0 + LBK): 16-byte chunks, 8 per (plane, column) row
+        for (int e = tid; e < 4 * NP * (LBK / 8); e += 256) {
+            const int row = e / (LBK / 8), ch = e - row * (LBK / 8);   // row = p * NP + c
+            const int p = row / NP, c = row - p * NP;
+            const v8 v = *reinterpret_cast<const v8*>(Bt + ((int64_t)p * P.Np + c) * P.bkp + k0 + 8 * ch);
+            *reinterpret_cast<v8*>(&sB[row * SK + 8 * ch]) = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; h++)
+#pragma unroll
+            for (int cn = 0; cn < CN; cn++) {
+                v8 b[4], nb[4];
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    b[r] = *reinterpret_cast<const v8*>(&sB[(r * NP + cn * 16 + ar) * SK + 32 * h + ak]);
+                    nb[r] = neg8(b[r]);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+#pragma unroll
+                    for (int p = 0; p < 4; p++) {
+                        const int r = p ^ q;
+                        acc[p][cn] = L::mma(a[q][h], term_sign<ADJ>(p, q) > 0 ? b[r] : nb[r], acc[p][cn]);
+                    }
+            }
+    }
+    const float sc = P.cscale ? *P.cscale : 1.0f;
+#pragma unroll
+    for (int cn = 0; cn < CN; cn++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int64_t r = rbase + 4 * (lane >> 4) + i;
+            const int64_t c = cn * 16 + ar;
+            if (P.splits == 1) {
+                if (r < P.M && c < P.N)
+#pragma unroll
+                    for (int p = 0; p < 4; p++) P.C[p * P.cps + r * P.ldc + c] = acc[p][cn][i] * sc;
+            } else {
+#pragma unroll
+                for (int p = 0; p < 4; p++)
+                    P.part[(((int64_t)split * 4 + p) * P.Mp + r) * P.Np + c] = acc[p][cn][i] * sc;
+            }
+        }
+}
+
+struct LpPlan {
+    int CN;
+    int64_t gx, splits, kchunk, Mp, Np, Kp;
+};
+
+LpPlan make_lp_plan(const QgemmDesc& d) {
+    LpPlan p{};
+    p.CN = (int)std::max<int64_t>(1, (d.N + 15) / 16);
+    p.Np = 16 * (int64_t)p.CN;
+    p.gx = (d.M + LBM - 1) / LBM;
+    p.Mp = p.gx * LBM;
+    p.Kp = ((d.K + LBK - 1) / LBK) * LBK;
+    // split K for about 2 workgroups per CU, each over at least 2 K steps
+    int64_t splits = 1;
+    if (p.gx < 2 * kCUs) splits = std::min<int64_t>((2 * kCUs + p.gx - 1) / p.gx, (d.K + 2 * LBK - 1) / (2 * LBK));
+    splits = std::max<int64_t>(splits, 1);
+    int64_t kchunk = (d.K + splits - 1) / splits;
+    kchunk = ((kchunk + LBK - 1) / LBK) * LBK;
+    p.splits = (d.K + kchunk - 1) / kchunk;
+    if (p.splits < 1) p.splits = 1;
+    p.kchunk = kchunk;
+    return p;
+}
+
+size_t lp_thin_bytes(const LpPlan& p) { return (size_t)4 * p.Np * p.Kp * 2; }
+size_t lp_part_bytes(const LpPlan& p) { return p.splits > 1 ? (size_t)p.splits * 4 * p.Mp * p.Np * sizeof(float) : 0; }
+
+template <class TL, bool ADJ>
+hipError_t launch_lp(const QgemmDesc& d, const LpPlan& pl, void* scratch, hipStream_t st) {
+    char* base = (char*)scratch;
+    TL* Bt = (TL*)base;
+    float* part = (float*)(base + ((lp_thin_bytes(pl) + 255) & ~size_t(255)));
+    const int64_t nt = 4 * pl.Np * pl.Kp;
+    hipLaunchKernelGGL(k_lp_thin<TL>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, (const float*)d.B, d.ldb,
+                       d.bps, d.K, d.N, Bt, pl.Np, pl.Kp);
+    LpParams P{};
+    P.A = d.A; P.lda = d.lda; P.aps = d.aps;
+    P.Bt = Bt; P.bkp = pl.Kp;
+    P.C = (float*)d.C; P.ldc = d.ldc; P.cps = d.cps;
+    P.M = d.M; P.N = d.N; P.K = d.K;
+    P.kchunk = pl.kchunk; P.splits = (int)pl.splits;
+    P.part = part; P.Mp = pl.Mp; P.Np = pl.Np;
+    P.skip = d.skip_flag;
+    P.cscale = d.cscale;
+    dim3 grid((unsigned)pl.gx, 1, (unsigned)pl.splits);
+#define QL_LP(CN_) \
+    if (pl.CN == CN_) hipLaunchKernelGGL((k_qgemm_lp<TL, ADJ, CN_>), grid, dim3(256), 0, st, P); else
+    QL_LP(1) QL_LP(2) QL_LP(3) QL_LP(4) QL_LP(5) return hipErrorInvalidValue;
+#undef QL_LP
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || pl.splits == 1) return e;
+    const int64_t total = 8 * 4 * d.M * d.N;
+    hipLaunchKernelGGL((k_splitk_reduce<float, float>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       (const float*)part, (int)pl.splits, pl.Mp, pl.Np, (float*)d.C, d.ldc, d.cps, d.M, d.N,
+                       (int)ST_SET, d.skip_flag);
+    return hipGetLastError();
+}
+
 bool vec_ok(const void* p, int64_t ld, int64_t ps, size_t el) {
     return ((uintptr_t)p % 16) == 0 && ld % 4 == 0 && ps % 4 == 0 && (el == 4 || el == 8);
 }
@@ -379,6 +595,10 @@ bool vec_ok(const void* p, int64_t ld, int64_t ps, size_t el) {
 }  // namespace
 
 size_t qgemm_partial_bytes(const QgemmDesc& d) {
+    if (d.math == MATH_BF16 || d.math == MATH_F16) {
+        const LpPlan lp = make_lp_plan(d);
+        return ((lp_thin_bytes(lp) + 255) & ~size_t(255)) + lp_part_bytes(lp);
+    }
     const Plan p = make_plan(d);
     if (p.splits <= 1) return 0;
     const size_t el = d.math == MATH_F32 ? sizeof(float) : sizeof(double);
@@ -389,6 +609,13 @@ size_t qgemm_counter_count(const QgemmDesc&) { return 0; }
 
 hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t st) {
     if (d.M <= 0 || d.N <= 0) return hipSuccess;
+    if (d.math == MATH_BF16 || d.math == MATH_F16) {
+        if (d.b_f64 || d.c_f64 || d.store != ST_SET || d.N > 80 || !s.partial) return hipErrorInvalidValue;
+        const LpPlan lp = make_lp_plan(d);
+        if (d.math == MATH_BF16)
+            return d.op == OP_HN ? launch_lp<__bf16, true>(d, lp, s.partial, st) : launch_lp<__bf16, false>(d, lp, s.partial, st);
+        return d.op == OP_HN ? launch_lp<_Float16, true>(d, lp, s.partial, st) : launch_lp<_Float16, false>(d, lp, s.partial, st);
+    }
     const Plan pl = make_plan(d);
     KParams kp{};
     kp.A = d.A; kp.lda = d.lda; kp.aps = d.aps;

@@ -150,6 +150,7 @@ struct Problem {
     float* V; int64_t ldv, vps;
     double* pass_err;
     int estimate;
+    int prec;               // QLRA_FP32, QLRA_BF16 or QLRA_FP16 for views 1 .. v-2
 };
 
 struct Dims {
@@ -197,6 +198,8 @@ struct Bufs {
     double* side_S; double* side_work;
     double* Gs;             // Grams of views 2 .. v-1, (v - 2) x (l x l)
     double* est_work;
+    void* Alo; void* Alo_t;  // low-precision copies of A and A^T (views 1 .. v-2)
+    float* lp_scale;        // [scale, 1 / scale]
     void* partial;
 };
 
@@ -231,6 +234,10 @@ void carve(const Problem& pr, const Dims& d, Arena& ar, Bufs& b, size_t part_byt
     b.side_work = batched ? nullptr : (double*)ar.take(qsvd_work_doubles(d.l) * sizeof(double));
     b.Gs = batched && nest ? (double*)ar.take((size_t)nest * 4 * l2 * sizeof(double)) : nullptr;
     b.est_work = batched && nest ? (double*)ar.take(heig_work_doubles(nest) * sizeof(double)) : nullptr;
+    const bool lowp = pr.prec != QLRA_FP32 && pr.v > 2;
+    b.Alo = lowp ? ar.take((size_t)4 * pr.m * pr.n * 2) : nullptr;
+    b.Alo_t = lowp ? ar.take((size_t)4 * pr.m * pr.n * 2) : nullptr;
+    b.lp_scale = (float*)ar.take(2 * sizeof(float));
     b.partial = part_bytes ? ar.take(part_bytes) : nullptr;
 }
 
@@ -262,7 +269,7 @@ hipError_t get_side(Side* out) {
 struct GraphKey {
     int dev;
     const void* A; int64_t m, n, lda, aps;
-    int k, p, v, scheme, estimate;
+    int k, p, v, scheme, estimate, prec;
     uint64_t seed;
     const void* U; int64_t ldu, ups;
     const void* S;
@@ -359,18 +366,28 @@ void finish_gram(Ctx& c, const Bufs& b, const Problem& pr, const float* Y, int64
 }
 
 // The product of a view alone: T = A X (forward, m x w) or T = A^H X (adjoint, n x w), ld w.
-void view_product(Ctx& c, const Problem& pr, bool adjoint, const float* X, int64_t ldx, int64_t w, float* T) {
+// lowp: from the BF16 / FP16 copies (A for the forward product, A^T for the adjoint one).
+void view_product(Ctx& c, const Problem& pr, const Bufs& b, bool adjoint, const float* X, int64_t ldx, int64_t w,
+                  float* T, bool lowp = false) {
     const int64_t rows_out = adjoint ? pr.n : pr.m;
     const int64_t kdim = adjoint ? pr.m : pr.n;
+    if (lowp) {
+        QgemmDesc d = desc(adjoint ? OP_HN : OP_NN, pr.prec == QLRA_BF16 ? MATH_BF16 : MATH_F16,
+                           adjoint ? b.Alo_t : b.Alo, kdim, pr.m * pr.n, 0, X, ldx, kdim * ldx, 0, T, w, rows_out * w, 0,
+                           rows_out, w, kdim);
+        d.cscale = b.lp_scale ? b.lp_scale + 1 : nullptr;
+        qg(c, d);
+        return;
+    }
     qg(c, desc(adjoint ? OP_HN : OP_NN, MATH_F32, pr.A, pr.lda, pr.aps, 0, X, ldx, kdim * ldx, 0, T, w, rows_out * w, 0,
                rows_out, w, kdim));
 }
 
 // One view: C = A X (forward) or C = A^H X (adjoint), then its QR.
-void view(Ctx& c, const Problem& pr, bool adjoint, const float* X, int64_t ldx, int64_t w, float* T, float* Q,
-          int64_t ldq, double* R, int rounds = 1, double* G0 = nullptr) {
+void view(Ctx& c, const Problem& pr, const Bufs& b, bool adjoint, const float* X, int64_t ldx, int64_t w, float* T,
+          float* Q, int64_t ldq, double* R, int rounds = 1, double* G0 = nullptr, bool lowp = false) {
     const int64_t rows_out = adjoint ? pr.n : pr.m;
-    view_product(c, pr, adjoint, X, ldx, w, T);
+    view_product(c, pr, b, adjoint, X, ldx, w, T, lowp);
     cholqr(c, T, rows_out, w, w, rows_out * w, Q, ldq, rows_out * ldq, R, rounds, G0);
 }
 
@@ -382,7 +399,13 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
         note(c, fro2_launch(pr.A, pr.m, pr.n, pr.lda, pr.aps, b.fro_part, b.nA2, c.st));
         note(c, omega_launch(pr.seed, pr.n, l, b.Om, l, pr.n * l, c.st));
         if (pr.estimate) note(c, nan_launch(pr.pass_err, c.st));
+        if (b.Alo) {
+            note(c, lowp_scale_launch(b.nA2, pr.prec, b.lp_scale, b.lp_scale + 1, c.st));
+            note(c, lowp_copy_launch(pr.A, pr.m, pr.n, pr.lda, pr.aps, pr.prec, b.Alo, b.Alo_t, b.lp_scale, c.st));
+        }
     }
+    // views 1 .. v-2 in reduced precision when asked; the last two keep FP32
+    auto lowp_view = [&](int i) { return pr.prec != QLRA_FP32 && pr.v > 2 && i <= pr.v - 2; };
     const float* Q2cur = b.Om;
     if (!d.krylov) {
         // Alg. 2: odd views [Q1, R1] = QR(A Q2), even views [Q2, R2] = QR(A^H Q1)
@@ -391,7 +414,7 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
             if (i == pr.v && gram_final) {
                 fork_estimates(c, b, pr, l);
                 const bool odd = i % 2 == 1;
-                view_product(c, pr, !odd, odd ? Q2cur : b.Q1, l, l, b.T);
+                view_product(c, pr, b, !odd, odd ? Q2cur : b.Q1, l, l, b.T);
                 finish_gram(c, b, pr, b.T, odd ? pr.m : pr.n, odd ? Q2cur : b.Q1, l, odd ? pr.n : pr.m, l, odd);
                 return;
             }
@@ -400,8 +423,8 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
             // the last two views produce the returned bases: CholeskyQR2 there
             const int rounds = i >= pr.v - 1 ? 2 : 1;
             double* G0 = gram_slot(b, pr, l, i);
-            if (i % 2 == 1) view(c, pr, false, Q2cur, l, l, b.T, b.Q1, l, R, rounds, G0);
-            else { view(c, pr, true, b.Q1, l, l, b.T, b.Q2, l, R, rounds, G0); Q2cur = b.Q2; }
+            if (i % 2 == 1) view(c, pr, b, false, Q2cur, l, l, b.T, b.Q1, l, R, rounds, G0, lowp_view(i));
+            else { view(c, pr, b, true, b.Q1, l, l, b.T, b.Q2, l, R, rounds, G0, lowp_view(i)); Q2cur = b.Q2; }
             if (i >= 2) fork_estimate(c, b, pr, R, l, i);
         }
         fork_estimates(c, b, pr, l);
@@ -419,12 +442,12 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
     const bool keepR = pr.estimate && !b.Gs;
     for (int j = 1; j <= d.s; j++) {
         double* R = keepR ? b.Rv + (size_t)i * 4 * l2 : nullptr;
-        view(c, pr, false, Q2cur, l, l, b.T, b.Q1, l, R, 1, gram_slot(b, pr, l, i + 1));
+        view(c, pr, b, false, Q2cur, l, l, b.T, b.Q1, l, R, 1, gram_slot(b, pr, l, i + 1), lowp_view(i + 1));
         i++;
         if (i >= 2) fork_estimate(c, b, pr, R, l, i);
         if (d.even) stack_in(b.Q1, j - 1);
         R = keepR ? b.Rv + (size_t)i * 4 * l2 : nullptr;
-        view(c, pr, true, b.Q1, l, l, b.T, b.Q2, l, R, 1, gram_slot(b, pr, l, i + 1));
+        view(c, pr, b, true, b.Q1, l, l, b.T, b.Q2, l, R, 1, gram_slot(b, pr, l, i + 1), lowp_view(i + 1));
         i++;
         fork_estimate(c, b, pr, R, l, i);
         Q2cur = b.Q2;
@@ -432,27 +455,27 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
     }
     if (d.even) {
         double* R = keepR ? b.Rv + (size_t)i * 4 * l2 : nullptr;
-        view(c, pr, false, Q2cur, l, l, b.T, b.Q1, l, R, 1, gram_slot(b, pr, l, i + 1));
+        view(c, pr, b, false, Q2cur, l, l, b.T, b.Q1, l, R, 1, gram_slot(b, pr, l, i + 1), lowp_view(i + 1));
         i++;
         if (i >= 2) fork_estimate(c, b, pr, R, l, i);
         stack_in(b.Q1, d.s);
         fork_estimates(c, b, pr, l);
         orth_stack(c, b.stack, pr.m, Wk, l, b.Cbuf);
         if (Wk <= heig_max()) {
-            view_product(c, pr, true, b.stack, Wk, Wk, b.T);
+            view_product(c, pr, b, true, b.stack, Wk, Wk, b.T);
             finish_gram(c, b, pr, b.T, pr.n, b.stack, Wk, pr.m, Wk, false);
         } else {
-            view(c, pr, true, b.stack, Wk, Wk, b.T, b.Q2, Wk, b.Rfin, 2);
+            view(c, pr, b, true, b.stack, Wk, Wk, b.T, b.Q2, Wk, b.Rfin, 2);
             finish(c, b, pr, b.Rfin, Wk, b.stack, Wk, b.Q2, Wk, true);
         }
     } else {
         fork_estimates(c, b, pr, l);
         orth_stack(c, b.stack, pr.n, Wk, l, b.Cbuf);
         if (Wk <= heig_max()) {
-            view_product(c, pr, false, b.stack, Wk, Wk, b.T);
+            view_product(c, pr, b, false, b.stack, Wk, Wk, b.T);
             finish_gram(c, b, pr, b.T, pr.m, b.stack, Wk, pr.n, Wk, true);
         } else {
-            view(c, pr, false, b.stack, Wk, Wk, b.T, b.Q1, Wk, b.Rfin, 2);
+            view(c, pr, b, false, b.stack, Wk, Wk, b.T, b.Q1, Wk, b.Rfin, 2);
             finish(c, b, pr, b.Rfin, Wk, b.Q1, Wk, b.stack, Wk, false);
         }
     }
@@ -491,6 +514,9 @@ int check_problem(const Problem& pr) {
     const int64_t l = (int64_t)pr.k + pr.p;
     if (l > pr.m || l > pr.n) return QLRA_E_ARG;
     if (pr.v > 64) return QLRA_E_TOO_LARGE;
+    if (pr.prec != QLRA_FP32 && pr.prec != QLRA_BF16 && pr.prec != QLRA_FP16) return QLRA_E_UNSUPPORTED;
+    // the low-precision view kernel keeps all output columns of a view in one workgroup
+    if (pr.prec != QLRA_FP32 && pr.v > 2 && (int64_t)pr.k + pr.p > 80) return QLRA_E_UNSUPPORTED;
     return QLRA_OK;
 }
 
@@ -527,9 +553,9 @@ int qlra_workspace_size(int64_t m, int64_t n, int k, int p, int pass_budget, int
     pr.m = m; pr.n = n; pr.k = k; pr.p = p; pr.v = pass_budget; pr.scheme = scheme;
     pr.lda = n; pr.aps = m * n; pr.ldu = k; pr.ups = m * k; pr.ldv = k; pr.vps = n * k;
     pr.estimate = opts ? opts->estimate_passes : 1;
+    pr.prec = opts ? opts->pass_precision : QLRA_FP32;
     int rc = check_problem(pr);
     if (rc) return rc;
-    if (opts && opts->pass_precision != QLRA_FP32) return QLRA_E_UNSUPPORTED;
     const Dims d = dims_of(m, n, k, p, pass_budget, scheme);
     size_t part, cnt, total;
     size_solve(pr, d, &part, &cnt, &total);
@@ -548,9 +574,9 @@ int qlra(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stri
     pr.V = V; pr.ldv = ldv; pr.vps = v_plane_stride;
     pr.pass_err = pass_err;
     pr.estimate = (opts->estimate_passes && pass_err) ? 1 : 0;
+    pr.prec = opts->pass_precision;
     int rc = check_problem(pr);
     if (rc) return rc;
-    if (opts->pass_precision != QLRA_FP32) return QLRA_E_UNSUPPORTED;
     if ((rc = check_layout(A, m, n, lda, a_plane_stride))) return rc;
     if ((rc = check_layout(U, m, k, ldu, u_plane_stride))) return rc;
     if ((rc = check_layout(V, n, k, ldv, v_plane_stride))) return rc;
@@ -589,6 +615,7 @@ int qlra(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stri
     if (hipGetDevice(&key.dev) != hipSuccess || key.dev < 0 || key.dev >= 64) return QLRA_E_HIP;
     key.A = A; key.m = m; key.n = n; key.lda = lda; key.aps = a_plane_stride;
     key.k = k; key.p = p; key.v = pass_budget; key.scheme = scheme; key.estimate = pr.estimate; key.seed = seed;
+    key.prec = pr.prec;
     key.U = U; key.ldu = ldu; key.ups = u_plane_stride; key.S = S; key.V = V; key.ldv = ldv;
     key.vps = v_plane_stride; key.pass_err = pass_err; key.ws = opts->workspace;
     std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -679,6 +706,53 @@ int qlra_qgemm(int op, const float* A, int64_t m, int64_t n, int64_t lda, int64_
     QgemmScratch s{};
     s.counters = (unsigned*)ar.take(std::max<size_t>(cnt, 1) * sizeof(unsigned));
     s.partial = ar.take(qgemm_partial_bytes(d));
+    return qgemm_launch(d, s, (hipStream_t)stream) == hipSuccess ? QLRA_OK : QLRA_E_HIP;
+}
+
+int qlra_lowp_copy(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_ps, int precision,
+                   const float* scale, void* Alo, void* Alo_t, void* stream) {
+    if (m < 0 || n < 0 || (precision != QLRA_BF16 && precision != QLRA_FP16)) return QLRA_E_ARG;
+    if (m * n == 0) return QLRA_OK;
+    int rc;
+    if ((rc = check_layout(A, m, n, lda, a_ps))) return rc;
+    if (!Alo || !Alo_t) return QLRA_E_ARG;
+    return lowp_copy_launch(A, m, n, lda, a_ps, precision, Alo, Alo_t, scale, (hipStream_t)stream) == hipSuccess
+               ? QLRA_OK
+               : QLRA_E_HIP;
+}
+
+static QgemmDesc lp_desc(int op, int precision, const void* Alo, int64_t m, int64_t n, const float* B, int64_t w,
+                         int64_t ldb, int64_t b_ps, float* C, int64_t ldc, int64_t c_ps, const float* inv_scale) {
+    const int64_t rows = op == 0 ? m : n, kdim = op == 0 ? n : m;
+    QgemmDesc d = desc(op == 0 ? OP_NN : OP_HN, precision == QLRA_BF16 ? MATH_BF16 : MATH_F16, Alo, kdim, m * n, 0, B,
+                       ldb, b_ps, 0, C, ldc, c_ps, 0, rows, w, kdim);
+    d.cscale = inv_scale;
+    return d;
+}
+
+int qlra_qgemm_lp_workspace_size(int op, int precision, int64_t m, int64_t n, int64_t w, size_t* bytes) {
+    if (!bytes || (op != 0 && op != 1) || m < 0 || n < 0 || w < 0 || w > 80) return QLRA_E_ARG;
+    if (precision != QLRA_BF16 && precision != QLRA_FP16) return QLRA_E_ARG;
+    const QgemmDesc d = lp_desc(op, precision, nullptr, m, n, nullptr, w, w, 0, nullptr, w, 0, nullptr);
+    *bytes = (m * n * w == 0) ? 0 : qgemm_partial_bytes(d);
+    return QLRA_OK;
+}
+
+int qlra_qgemm_lp(int op, int precision, const void* Alo, int64_t m, int64_t n, const float* B, int64_t w, int64_t ldb,
+                  int64_t b_ps, float* C, int64_t ldc, int64_t c_ps, const float* inv_scale, void* workspace,
+                  size_t workspace_bytes, void* stream) {
+    size_t need = 0;
+    int rc = qlra_qgemm_lp_workspace_size(op, precision, m, n, w, &need);
+    if (rc) return rc;
+    const int64_t kdim = op == 0 ? n : m, rows = op == 0 ? m : n;
+    if (rows == 0 || w == 0) return QLRA_OK;
+    if (!Alo) return QLRA_E_ARG;
+    if ((rc = check_layout(B, kdim, w, ldb, b_ps))) return rc;
+    if ((rc = check_layout(C, rows, w, ldc, c_ps))) return rc;
+    if (workspace_bytes < need || !workspace || ((uintptr_t)workspace & 255)) return QLRA_E_WORKSPACE;
+    const QgemmDesc d = lp_desc(op, precision, Alo, m, n, B, w, ldb, b_ps, C, ldc, c_ps, inv_scale);
+    QgemmScratch s{};
+    s.partial = workspace;
     return qgemm_launch(d, s, (hipStream_t)stream) == hipSuccess ? QLRA_OK : QLRA_E_HIP;
 }
 

@@ -56,17 +56,22 @@ _lib.qlra_omega.argtypes = [ctypes.c_uint64, _I64, _I64, _P, _I64, _I64, _P]
 _lib.qlra_qgemm_workspace_size.argtypes = [_I, _I64, _I64, _I64, _SZ]
 _lib.qlra_qgemm.argtypes = [_I, _P, _I64, _I64, _I64, _I64, _P, _I64, _I64, _I64, _P, _I64, _I64, _P,
                             ctypes.c_size_t, _P]
+_lib.qlra_lowp_copy.argtypes = [_P, _I64, _I64, _I64, _I64, _I, _P, _P, _P, _P]
+_lib.qlra_qgemm_lp_workspace_size.argtypes = [_I, _I, _I64, _I64, _I64, _SZ]
+_lib.qlra_qgemm_lp.argtypes = [_I, _I, _P, _I64, _I64, _P, _I64, _I64, _I64, _P, _I64, _I64, _P, _P,
+                               ctypes.c_size_t, _P]
 _lib.qlra_cholqr_workspace_size.argtypes = [_I64, _I64, _SZ]
 _lib.qlra_cholqr.argtypes = [_P, _I64, _I64, _I64, _I64, _P, _I64, _I64, _P, _P, ctypes.c_size_t, _P]
 _lib.qlra_qsvd_workspace_size.argtypes = [_I64, _SZ]
 _lib.qlra_qsvd.argtypes = [_P, _I64, _P, _P, _P, _P, ctypes.c_size_t, _P]
 for _name in ("qlra_workspace_size", "qlra", "qlra_status", "qlra_omega", "qlra_qgemm_workspace_size",
-              "qlra_qgemm", "qlra_cholqr_workspace_size", "qlra_cholqr", "qlra_qsvd_workspace_size", "qlra_qsvd"):
+              "qlra_qgemm", "qlra_lowp_copy", "qlra_qgemm_lp_workspace_size", "qlra_qgemm_lp",
+              "qlra_cholqr_workspace_size", "qlra_cholqr", "qlra_qsvd_workspace_size", "qlra_qsvd"):
     getattr(_lib, _name).restype = _I
 
 EXPORTS = ("qlra", "qlra_workspace_size", "qlra_status", "qlra_strerror", "qlra_omega", "qlra_qgemm",
-           "qlra_qgemm_workspace_size", "qlra_cholqr", "qlra_cholqr_workspace_size", "qlra_qsvd",
-           "qlra_qsvd_workspace_size")
+           "qlra_qgemm_workspace_size", "qlra_lowp_copy", "qlra_qgemm_lp", "qlra_qgemm_lp_workspace_size",
+           "qlra_cholqr", "qlra_cholqr_workspace_size", "qlra_qsvd", "qlra_qsvd_workspace_size")
 
 
 def strerror(code):
@@ -98,8 +103,8 @@ def _workspace(nbytes, device):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
-def qlra_workspace_size(m, n, k, p, pass_budget, scheme, estimate=True):
-    o = Opts(QLRA_FP32, 1 if estimate else 0, None, None, 0, 0)
+def qlra_workspace_size(m, n, k, p, pass_budget, scheme, estimate=True, precision=QLRA_FP32):
+    o = Opts(precision, 1 if estimate else 0, None, None, 0, 0)
     out = ctypes.c_size_t()
     _check(_lib.qlra_workspace_size(m, n, k, p, pass_budget, SCHEMES.get(scheme, scheme), ctypes.byref(o),
                                     ctypes.byref(out)), "qlra_workspace_size")
@@ -124,7 +129,7 @@ def qlra(A, k, p, pass_budget, scheme, seed, U=None, S=None, V=None, pass_err=No
         pass_err = torch.empty(pass_budget, dtype=torch.float64, device=dev)
     pu, ldu, ups = _planes(U, m, k, "U")
     pv, ldv, vps = _planes(V, n, k, "V")
-    need = qlra_workspace_size(m, n, k, p, pass_budget, scheme, estimate)
+    need = qlra_workspace_size(m, n, k, p, pass_budget, scheme, estimate, precision)
     if workspace is None or workspace.numel() < need:
         workspace = _workspace(need, dev)
     o = Opts(precision, 1 if estimate else 0, _stream_ptr(stream), ctypes.c_void_p(workspace.data_ptr()),
@@ -172,6 +177,49 @@ def qlra_qgemm(op, A, B, C=None, stream=None, workspace=None):
     ws = workspace if workspace is not None else qlra_qgemm_workspace(op, m, n, w, A.device)
     _check(_lib.qlra_qgemm(op, pa, m, n, lda, aps, pb, w, ldb, bps, pc, ldc, cps, ctypes.c_void_p(ws.data_ptr()),
                            ws.numel(), _stream_ptr(stream)), "qlra_qgemm")
+    return C
+
+
+_LP_DTYPES = {QLRA_BF16: torch.bfloat16, QLRA_FP16: torch.float16}
+
+
+def qlra_lowp_copy(A, precision, scale=None, stream=None):
+    """BF16 / FP16 copies of A (4, m, n): returns (Alo (4, m, n), Alo_t (4, n, m)), each scaled by
+    the device scalar `scale` (a one-element float32 tensor, or None for 1)."""
+    m, n = A.shape[1], A.shape[2]
+    pa, lda, aps = _planes(A, m, n, "A")
+    dt = _LP_DTYPES[precision]
+    Alo = torch.empty((4, m, n), dtype=dt, device=A.device)
+    Alo_t = torch.empty((4, n, m), dtype=dt, device=A.device)
+    _check(_lib.qlra_lowp_copy(pa, m, n, lda, aps, precision,
+                               ctypes.c_void_p(scale.data_ptr()) if scale is not None else None,
+                               ctypes.c_void_p(Alo.data_ptr()), ctypes.c_void_p(Alo_t.data_ptr()), _stream_ptr(stream)),
+           "qlra_lowp_copy")
+    return Alo, Alo_t
+
+
+def qlra_qgemm_lp_workspace(op, precision, m, n, w, device="cuda"):
+    need = ctypes.c_size_t()
+    _check(_lib.qlra_qgemm_lp_workspace_size(op, precision, m, n, w, ctypes.byref(need)),
+           "qlra_qgemm_lp_workspace_size")
+    return _workspace(need.value, device)
+
+
+def qlra_qgemm_lp(op, precision, Alo, m, n, B, C=None, inv_scale=None, stream=None, workspace=None):
+    """Reduced-precision view product: op 0: C = A B from the (4, m, n) copy; op 1: C = A^H B
+    from the transposed (4, n, m) copy.  B and C are FP32."""
+    rows, kdim = (m, n) if op == 0 else (n, m)
+    if Alo.dtype != _LP_DTYPES[precision] or tuple(Alo.shape) != (4, rows, kdim) or not Alo.is_contiguous():
+        raise ValueError("Alo: expected the contiguous copy made by qlra_lowp_copy for this op")
+    w = B.shape[2]
+    if C is None:
+        C = torch.empty((4, rows, w), dtype=torch.float32, device=B.device)
+    pb, ldb, bps = _planes(B, kdim, w, "B")
+    pc, ldc, cps = _planes(C, rows, w, "C")
+    ws = workspace if workspace is not None else qlra_qgemm_lp_workspace(op, precision, m, n, w, B.device)
+    _check(_lib.qlra_qgemm_lp(op, precision, ctypes.c_void_p(Alo.data_ptr()), m, n, pb, w, ldb, bps, pc, ldc, cps,
+                              ctypes.c_void_p(inv_scale.data_ptr()) if inv_scale is not None else None,
+                              ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)), "qlra_qgemm_lp")
     return C
 
 
