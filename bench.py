@@ -9,7 +9,9 @@ with per-pass error estimates.
 
 Printed: one JSON line with passes/s (value), the dominant kernel's roofline position (FP32
 MFMA view product, timed with HIP events on its own stream), the FP64 CPU oracle timed on the
-host as a baseline, and accuracy against the oracle.
+host as a baseline, and accuracy against the oracle.  The precision form (views 1 .. v-2 in
+BF16 / FP16 with FP32 accumulation, the last two views FP32) is timed on the same step and
+reported beside it with its error ratio to the oracle.
 """
 import argparse
 import hashlib
@@ -87,25 +89,54 @@ def cpu_baseline(A_np):
                       f"{dt:.1f} s wall"}
 
 
-def accuracy(Q, torch, A, A_np):
-    """Error of the GPU result and of the oracle against A for each budget (outside the timed region)."""
+def accuracy(Q, torch, A, A_np, precisions):
+    """Error of the GPU result (each precision) and of the oracle against A for each budget
+    (outside the timed region)."""
     import numpy as np
     from oracle import oracle as O
     A64 = A_np.astype(np.float64)
     nA = np.sqrt(np.sum(A64 ** 2))
-    rows = []
+    rows = {name: [] for name in precisions}
     for v in BUDGETS:
-        U, S, V, e, ws = Q.qlra(A, K_RANK, P_OVER, v, "subspace", SEED_SKETCH)
-        torch.cuda.synchronize()
-        Ug, Sg, Vg = (x.cpu().numpy().astype(np.float64) for x in (U, S, V))
         Uo, So, Vo, eo = O.qlra(A64, K_RANK, P_OVER, v, O.SUBSPACE, SEED_SKETCH)
-        Ag, Ao = O.reconstruct(Ug, Sg, Vg), O.reconstruct(Uo, So, Vo)
-        eg_ = np.sqrt(np.sum((A64 - Ag) ** 2)) / nA
+        Ao = O.reconstruct(Uo, So, Vo)
         eo_ = np.sqrt(np.sum((A64 - Ao) ** 2)) / nA
-        rows.append({"v": v, "rel_err_gpu": float(eg_), "rel_err_oracle": float(eo_), "ratio": float(eg_ / eo_),
-                     "ahat_diff": float(np.sqrt(np.sum((Ag - Ao) ** 2)) / nA),
-                     "pass_err_gpu_last": float(e.cpu().numpy()[-1])})
+        for name, prec in precisions.items():
+            U, S, V, e, ws = Q.qlra(A, K_RANK, P_OVER, v, "subspace", SEED_SKETCH, precision=prec)
+            torch.cuda.synchronize()
+            Ug, Sg, Vg = (x.cpu().numpy().astype(np.float64) for x in (U, S, V))
+            Ag = O.reconstruct(Ug, Sg, Vg)
+            eg_ = np.sqrt(np.sum((A64 - Ag) ** 2)) / nA
+            rows[name].append({"v": v, "rel_err_gpu": float(eg_), "rel_err_oracle": float(eo_),
+                               "ratio": float(eg_ / eo_), "ahat_diff": float(np.sqrt(np.sum((Ag - Ao) ** 2)) / nA),
+                               "pass_err_gpu_last": float(e.cpu().numpy()[-1])})
     return rows
+
+
+def time_lowp_view_kernels(Q, torch, A, prec, reps):
+    """Average duration of the reduced-precision view product (both orientations), HIP events on
+    its stream.  The copies of A are made once, outside the timed region."""
+    w = K_RANK + P_OVER
+    g = torch.Generator(device="cuda").manual_seed(0)
+    X = torch.randn((4, N, w), device="cuda", generator=g)
+    Alo, Alo_t = Q.qlra_lowp_copy(A, prec)
+    out = {}
+    st = torch.cuda.current_stream()
+    for op in (0, 1):
+        ws = Q.qlra_qgemm_lp_workspace(op, prec, M, N, w)
+        C = torch.empty((4, M if op == 0 else N, w), device="cuda")
+        src = Alo if op == 0 else Alo_t
+        for _ in range(3):
+            Q.qlra_qgemm_lp(op, prec, src, M, N, X, C, stream=st, workspace=ws)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            Q.qlra_qgemm_lp(op, prec, src, M, N, X, C, stream=st, workspace=ws)
+        e1.record(st)
+        e1.synchronize()
+        out[op] = e0.elapsed_time(e1) * 1e-3 / reps
+    return out
 
 
 def main():
@@ -122,48 +153,65 @@ def main():
     print("generating the 2048x2048 workload", file=sys.stderr, flush=True)
     A_np, _ = W.config1(seed=SEED_DATA, n=M, noise_std=0.01)
     A = torch.from_numpy(A_np).cuda()
+    precisions = {"fp32": Q.QLRA_FP32, "bf16": Q.QLRA_BF16, "fp16": Q.QLRA_FP16}
     outs = {}
-    for v in BUDGETS:
-        need = Q.qlra_workspace_size(M, N, K_RANK, P_OVER, v, "subspace")
-        outs[v] = dict(U=torch.empty((4, M, K_RANK), device="cuda"), V=torch.empty((4, N, K_RANK), device="cuda"),
-                       S=torch.empty(K_RANK, dtype=torch.float64, device="cuda"),
-                       e=torch.empty(v, dtype=torch.float64, device="cuda"),
-                       ws=torch.empty(need, dtype=torch.uint8, device="cuda"))
-
-    def step():
+    for name, prec in precisions.items():
         for v in BUDGETS:
-            o = outs[v]
-            Q.qlra(A, K_RANK, P_OVER, v, "subspace", SEED_SKETCH, U=o["U"], S=o["S"], V=o["V"],
-                   pass_err=o["e"], workspace=o["ws"], graph=True)
+            need = Q.qlra_workspace_size(M, N, K_RANK, P_OVER, v, "subspace", precision=prec)
+            outs[name, v] = dict(U=torch.empty((4, M, K_RANK), device="cuda"),
+                                 V=torch.empty((4, N, K_RANK), device="cuda"),
+                                 S=torch.empty(K_RANK, dtype=torch.float64, device="cuda"),
+                                 e=torch.empty(v, dtype=torch.float64, device="cuda"),
+                                 ws=torch.empty(need, dtype=torch.uint8, device="cuda"))
 
-    print(f"warmup {args.warmup} steps", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    for v in BUDGETS:
-        assert Q.qlra_status(outs[v]["ws"]) == Q.QLRA_OK
-    print(f"timing {args.steps} steps", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    def solve(name, v):
+        o = outs[name, v]
+        Q.qlra(A, K_RANK, P_OVER, v, "subspace", SEED_SKETCH, U=o["U"], S=o["S"], V=o["V"], pass_err=o["e"],
+               workspace=o["ws"], graph=True, precision=precisions[name])
+
+    def timed_steps(name, steps, warmup):
+        for _ in range(warmup):
+            for v in BUDGETS:
+                solve(name, v)
+        torch.cuda.synchronize()
+        for v in BUDGETS:
+            assert Q.qlra_status(outs[name, v]["ws"]) == Q.QLRA_OK
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for v in BUDGETS:
+                solve(name, v)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def per_budget(name):
+        res = {}
+        for v in BUDGETS:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(5):
+                solve(name, v)
+            torch.cuda.synchronize()
+            res[f"v{v}_ms"] = round((time.perf_counter() - t1) * 1e3 / 5, 4)
+        return res
+
+    print(f"warmup {args.warmup} steps, timing {args.steps} steps (FP32 views)", file=sys.stderr, flush=True)
+    dt = timed_steps("fp32", args.steps, args.warmup)
     ms_per_step = dt * 1e3 / args.steps
     passes = sum(BUDGETS) * args.steps
     value = passes / dt
+    per_v = per_budget("fp32")
 
-    # per-budget solve times (not part of the value)
-    per_v = {}
-    for v in BUDGETS:
-        o = outs[v]
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(5):
-            Q.qlra(A, K_RANK, P_OVER, v, "subspace", SEED_SKETCH, U=o["U"], S=o["S"], V=o["V"], pass_err=o["e"],
-                   workspace=o["ws"], graph=True)
-        torch.cuda.synchronize()
-        per_v[f"v{v}_ms"] = round((time.perf_counter() - t1) * 1e3 / 5, 4)
+    lowp = {}
+    for name in ("bf16", "fp16"):
+        print(f"timing {args.steps} steps ({name} views 1..v-2)", file=sys.stderr, flush=True)
+        dtl = timed_steps(name, args.steps, args.warmup)
+        kt_l = time_lowp_view_kernels(Q, torch, A, precisions[name], args.kernel_reps)
+        t_l = 0.5 * (kt_l[0] + kt_l[1])
+        lowp[name] = {"value": round(passes / dtl, 3), "unit": "A-passes/s", "ms_per_step": round(dtl * 1e3 / args.steps, 4),
+                      "speedup_vs_fp32": round(dt / dtl, 4), "solve_ms": per_budget(name),
+                      "view_kernel_us": {"forward": round(kt_l[0] * 1e6, 2), "adjoint": round(kt_l[1] * 1e6, 2)},
+                      "view_hbm_gbs": round(8.0 * M * N / t_l / 1e9, 1),
+                      "view_hbm_frac": round(8.0 * M * N / t_l / PEAK_HBM, 4)}
 
     print("timing the view kernels", file=sys.stderr, flush=True)
     kt = time_view_kernels(Q, torch, A, args.kernel_reps)
@@ -182,8 +230,15 @@ def main():
                 "t_forward_us": round(kt[0] * 1e6, 2), "t_adjoint_us": round(kt[1] * 1e6, 2),
                 "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": 16.0 * M * N + 2 * 16.0 * N * w}
 
+    for name in lowp:
+        lowp[name]["view_speedup_vs_fp32"] = round(t_view / (0.5 * (lowp[name]["view_kernel_us"]["forward"] +
+                                                                   lowp[name]["view_kernel_us"]["adjoint"]) * 1e-6), 3)
     print("accuracy against the oracle", file=sys.stderr, flush=True)
-    acc = accuracy(Q, torch, A, A_np)
+    acc_all = accuracy(Q, torch, A, A_np, precisions)
+    acc = acc_all["fp32"]
+    for name in lowp:
+        lowp[name]["accuracy"] = acc_all[name]
+        lowp[name]["max_error_ratio"] = round(max(r["ratio"] for r in acc_all[name]), 8)
     cpu = None if args.no_cpu_baseline else cpu_baseline(A_np)
     line = {"metric": "A-passes/s", "value": round(value, 3), "unit": "A-passes/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -194,7 +249,9 @@ def main():
                        "m": M, "n": N, "k": K_RANK, "p": P_OVER, "budgets": list(BUDGETS),
                        "passes_per_step": sum(BUDGETS)},
             "qgemm_tflops": round(achieved / 1e12, 3), "solve_ms": per_v, "accuracy": acc,
-            "roofline": roofline, "cpu_baseline": cpu}
+            "roofline": roofline, "cpu_baseline": cpu,
+            "precision_form": {"views": "1..v-2 reduced (FP32 accumulation), v-1 and v FP32; Gram/Cholesky/QSVD FP64",
+                               **lowp}}
     print(json.dumps(line))
 
 

@@ -29,7 +29,8 @@ enum QStore { ST_SET = 0, ST_SUB = 1 };   // C = R  |  C = C - R
 
 // Arithmetic of a qgemm launch.  MATH_BF16 / MATH_F16: A is a low-precision copy laid out as
 // the rows of the output (for OP_HN the transposed copy A^T; op then only selects the
-// conjugation signs), B is FP32 and converted per launch, C is FP32 and multiplied by *cscale.
+// conjugation signs) in the tiled layout of lowp_copy_launch (lda, aps unused), B is FP32 and
+// converted per launch, C is FP32 and multiplied by *cscale.
 enum QMath { MATH_F32 = 0, MATH_F64 = 1, MATH_BF16 = 2, MATH_F16 = 3 };
 
 struct QgemmDesc {
@@ -69,9 +70,11 @@ size_t qgemm_partial_bytes(const QgemmDesc& d);   // split-K partials (+ the con
 size_t qgemm_counter_count(const QgemmDesc& d);
 hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t st);
 
-// Low-precision copies of A (m x n, four FP32 planes): Alo (m x n, ld n) and Alo_t = A^T (n x m,
-// ld m), both scaled by *scale (read on the device; null: 1); elements are TL = bf16 or fp16
-// by prec (QLRA_BF16 / QLRA_FP16).
+// Low-precision copies of A (m x n, four FP32 planes): Alo (rows m, reduction n) and Alo_t =
+// A^T (rows n, reduction m), both scaled by *scale (read on the device; null: 1), elements
+// bf16 or fp16 by prec (QLRA_BF16 / QLRA_FP16), in the tiled MFMA-operand layout (16 x 64 tiles,
+// four planes per tile; lowp_copy_elems(rows, k) elements each, padding zero).
+size_t lowp_copy_elems(int64_t rows, int64_t k);
 hipError_t lowp_copy_launch(const float* A, int64_t m, int64_t n, int64_t lda, int64_t aps, int prec, void* Alo,
                             void* Alo_t, const float* scale, hipStream_t st);
 // FP16 scale from ||A||_F^2 (nA2): scale = 2^e with e = 14 - ceil(log2 ||A||_F) (so that every

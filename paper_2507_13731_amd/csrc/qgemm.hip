@@ -25,6 +25,7 @@
 #include "common.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace qlra_impl {
 namespace {
@@ -300,6 +301,39 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const T* __restrict__ par
     }
 }
 
+// The same sum for FP32 partials and outputs whose rows are 16-byte aligned: one thread per
+// four consecutive outputs, the splits added in order (deterministic).
+__global__ __launch_bounds__(256) void k_splitk_reduce4(const float* __restrict__ part, int splits, int64_t Mp,
+                                                        int64_t Np, float* __restrict__ C, int64_t ldc, int64_t cps,
+                                                        int64_t M, int64_t N, int store, const int* skip) {
+    if (skip && *skip == 0) return;
+    const int64_t nq = N / 4;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 4 * M * nq) return;
+    const int64_t p = e / (M * nq), rem = e - p * M * nq, r = rem / nq, c = 4 * (rem - r * nq);
+    const int64_t stride = 4 * Mp * Np;
+    const float* src = part + (p * Mp + r) * Np + c;
+    f32x4 s = *reinterpret_cast<const f32x4*>(src);
+    for (int sp = 1; sp < splits; sp++) s += *reinterpret_cast<const f32x4*>(src + sp * stride);
+    f32x4* dst = reinterpret_cast<f32x4*>(C + p * cps + r * ldc + c);
+    *dst = store == ST_SUB ? *dst - s : s;
+}
+
+// C = sum of the partial tiles, with the vector form when the layout allows it
+hipError_t reduce_f32(const float* part, int splits, int64_t Mp, int64_t Np, float* C, int64_t ldc, int64_t cps,
+                      int64_t M, int64_t N, int store, const int* skip, hipStream_t st) {
+    if (N % 4 == 0 && ldc % 4 == 0 && cps % 4 == 0 && ((uintptr_t)C % 16) == 0) {
+        const int64_t total = 4 * M * (N / 4);
+        hipLaunchKernelGGL(k_splitk_reduce4, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, part, splits,
+                           Mp, Np, C, ldc, cps, M, N, store, skip);
+    } else {
+        const int64_t total = 8 * 4 * M * N;
+        hipLaunchKernelGGL((k_splitk_reduce<float, float>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                           part, splits, Mp, Np, C, ldc, cps, M, N, store, skip);
+    }
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------------------------
 // configuration choice
 
@@ -355,6 +389,9 @@ hipError_t launch_t(const Plan& pl, const KParams& kp, hipStream_t st) {
     hipLaunchKernelGGL((k_qgemm<T, WM, WN, RM, CN, BK, ADJ, TA, TB, TC>), grid, dim3(256), 0, st, kp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || pl.splits == 1) return e;
+    if constexpr (std::is_same<T, float>::value && std::is_same<TC, float>::value)
+        return reduce_f32((const float*)kp.part, (int)pl.splits, pl.Mp, pl.Np, (float*)kp.C, kp.ldc, kp.cps, kp.M,
+                          kp.N, kp.store, kp.skip, st);
     const int64_t total = 8 * 4 * kp.M * kp.N;
     hipLaunchKernelGGL((k_splitk_reduce<T, TC>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
                        (const T*)kp.part, (int)pl.splits, pl.Mp, pl.Np, (TC*)kp.C, kp.ldc, kp.cps, kp.M, kp.N,
@@ -376,9 +413,10 @@ hipError_t launch_f32(const Plan& pl, const KParams& kp, hipStream_t st) {
 // Low-precision views: BF16 / FP16 operands, v_mfma_f32_16x16x32_{bf16,f16}, FP32 accumulation.
 //
 // A is a low-precision copy laid out as the rows of the output (A itself for A B, the
-// transposed copy A^T for A^H B), so the MFMA A operand (row l % 16, eight consecutive k at
-// 8 (l / 16)) is one 16-byte load per lane straight from global memory: every A element is used
-// by exactly one wave, so it bypasses LDS.  The thin operand is converted once per launch into
+// transposed copy A^T for A^H B) in the tiled MFMA-operand order of lowp_copy_launch, so the
+// MFMA A operand (row l % 16, eight consecutive k at 8 (l / 16)) is one 16-byte load per lane
+// straight from global memory, 1 KB contiguous per instruction: every A element is used by
+// exactly one wave, so it bypasses LDS.  The thin operand is converted once per launch into
 // Bt[plane][column][k] (low precision, columns padded to 16, k padded to LBK) and each K step's
 // tile is staged through LDS for the four waves.  Each wave owns 16 rows of the output and all
 // its column tiles in the four planes.
@@ -416,7 +454,7 @@ constexpr int LBK = 64;    // K per step: two MFMA k-blocks of 32
 constexpr int LBM = 64;    // output rows per workgroup (16 per wave)
 
 struct LpParams {
-    const void* A; int64_t lda, aps;
+    const void* A; int64_t akt, art;      // tiled copy: reduction tiles per row tile, row tiles
     const void* Bt; int64_t bkp;          // converted thin operand: [4][Np][bkp]
     float* C; int64_t ldc, cps;
     int64_t M, N, K;
@@ -439,67 +477,86 @@ __global__ __launch_bounds__(256) void k_lp_thin(const float* __restrict__ B, in
     Bt[e] = (TL)x;
 }
 
-template <class TL, bool ADJ, int CN>
-__global__ __launch_bounds__(256) void k_qgemm_lp(LpParams P) {
+// Workgroup: 4 row groups of 16 rows x NCG column groups of CNW column tiles (16 columns each).
+// Software pipeline: an iteration covers two K steps (LKS = 128 reduction elements).  Its thin
+// tile was loaded into registers during the previous iteration and sits in LDS; the A fragments
+// of a step are loaded two steps ahead into the ping-pong register sets aX (even steps) and aY
+// (odd steps), always issued after the thin-tile loads, so that waiting for those (vmcnt counts
+// in issue order) never waits for A.  Every load is unconditional (addresses clamped into the
+// copies; a step past the end of K meets zero rows of the padded thin tile), so the wait
+// counts stay exact across iterations.
+constexpr int LKS = 2 * LBK;
+template <class TL, bool ADJ, int CN, int NCG, int CNW>
+__global__ __launch_bounds__(256 * NCG) void k_qgemm_lp(LpParams P) {
     using L = LpMma<TL>;
     using v8 = typename L::v8;
     constexpr int NP = 16 * CN;
-    constexpr int SK = LBK + 8;   // LDS row stride of the staged tile (elements)
+    constexpr int SK = LKS + 8;                   // LDS row stride of the staged tile (elements)
+    constexpr int NT = 256 * NCG;
+    constexpr int CH = 4 * NP * (LKS / 8);        // 16-byte chunks of one thin tile
+    constexpr int CPT = CH / NT;                  // chunks per thread
+    static_assert(CH % NT == 0, "whole chunks per thread");
     __shared__ __attribute__((aligned(16))) TL sB[4 * NP * SK];
     if (P.skip && *P.skip == 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int rg = wave & 3, cg = wave >> 2;
     const int split = blockIdx.z;
     const int64_t kb = (int64_t)split * P.kchunk;
     const int64_t ke = kb + P.kchunk < P.K ? kb + P.kchunk : P.K;
     const int ar = lane & 15, ak = 8 * (lane >> 4);
-    const int64_t rbase = (int64_t)blockIdx.x * LBM + 16 * wave;
-    const int64_t arow = rbase + ar;
-    const bool arow_ok = arow < P.M;
-    const TL* __restrict__ Ab = (const TL*)P.A + (arow_ok ? arow : 0) * P.lda;
+    const int64_t rt = (int64_t)blockIdx.x * (LBM / 16) + rg;   // this wave's row tile
+    const int64_t rbase = 16 * rt;
+    // a row tile past the copy reads the last one: its rows are never stored
+    const TL* __restrict__ Ab = (const TL*)P.A + (rt < P.art ? rt : P.art - 1) * P.akt * 4096 + 8 * lane;
     const TL* __restrict__ Bt = (const TL*)P.Bt;
-    const bool avec = (P.lda % 8) == 0 && (P.aps % 8) == 0 && ((uintptr_t)P.A % 16) == 0;
+    const int64_t kt_last = P.akt - 1;
 
-    f32x4 acc[4][CN];
-#pragma unroll
-    for (int p = 0; p < 4; p++)
-#pragma unroll
-        for (int cn = 0; cn < CN; cn++) acc[p][cn] = f32x4{0, 0, 0, 0};
-
-    for (int64_t k0 = kb; k0 < ke; k0 += LBK) {
-        // A fragments for both k-blocks of this step
-        v8 a[4][2];
+    auto load_a = [&](int64_t k0, v8 (&a)[4][2]) {
+        const int64_t kt = (k0 >> 6) < kt_last ? (k0 >> 6) : kt_last;
+        const TL* src = Ab + kt * 4096;
 #pragma unroll
         for (int q = 0; q < 4; q++)
 #pragma unroll
-            for (int h = 0; h < 2; h++) {
-                const int64_t kk = k0 + 32 * h + ak;
-                const TL* src = Ab + q * P.aps + kk;
-                if (arow_ok && avec && kk + 8 <= ke) {
-                    a[q][h] = *reinterpret_cast<const v8*>(src);
-                } else {
-                    v8 t;
+            for (int h = 0; h < 2; h++) a[q][h] = *reinterpret_cast<const v8*>(src + q * 1024 + h * 512);
+    };
+    // the thin tile of reduction elements [k0, k0 + LKS): chunk e -> row (p * NP + c), 8 elements
+    // at 8 * ch (Bt is padded to a multiple of LKS)
+    auto load_b = [&](int64_t k0, v8 (&bt)[CPT]) {
 #pragma unroll
-                    for (int u = 0; u < 8; u++) t[u] = (arow_ok && kk + u < ke) ? src[u] : (TL)0.0f;
-                    a[q][h] = t;
-                }
-            }
-        __syncthreads();   // the previous tile is consumed
-        // stage Bt[:, :, k0 .. k0 + LBK): 16-byte chunks, 8 per (plane, column) row
-        for (int e = tid; e < 4 * NP * (LBK / 8); e += 256) {
-            const int row = e / (LBK / 8), ch = e - row * (LBK / 8);   // row = p * NP + c
+        for (int u = 0; u < CPT; u++) {
+            const int e = tid + u * NT;
+            const int row = e / (LKS / 8), ch = e - row * (LKS / 8);
             const int p = row / NP, c = row - p * NP;
-            const v8 v = *reinterpret_cast<const v8*>(Bt + ((int64_t)p * P.Np + c) * P.bkp + k0 + 8 * ch);
-            *reinterpret_cast<v8*>(&sB[row * SK + 8 * ch]) = v;
+            bt[u] = *reinterpret_cast<const v8*>(Bt + ((int64_t)p * P.Np + c) * P.bkp + k0 + 8 * ch);
         }
-        __syncthreads();
+    };
+    auto store_b = [&](const v8 (&bt)[CPT]) {
+#pragma unroll
+        for (int u = 0; u < CPT; u++) {
+            const int e = tid + u * NT;
+            const int row = e / (LKS / 8), ch = e - row * (LKS / 8);
+            *reinterpret_cast<v8*>(&sB[row * SK + 8 * ch]) = bt[u];
+        }
+    };
+
+    f32x4 acc[4][CNW];
+#pragma unroll
+    for (int p = 0; p < 4; p++)
+#pragma unroll
+        for (int j = 0; j < CNW; j++) acc[p][j] = f32x4{0, 0, 0, 0};
+
+    // MFMAs of one K step whose thin tile sits at offset kofs of the staged tile
+    auto step = [&](const v8 (&a)[4][2], int kofs) {
 #pragma unroll
         for (int h = 0; h < 2; h++)
 #pragma unroll
-            for (int cn = 0; cn < CN; cn++) {
+            for (int j = 0; j < CNW; j++) {
+                const int cn = cg * CNW + j;
+                if (cn >= CN) continue;                        // uniform per wave
                 v8 b[4], nb[4];
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
-                    b[r] = *reinterpret_cast<const v8*>(&sB[(r * NP + cn * 16 + ar) * SK + 32 * h + ak]);
+                    b[r] = *reinterpret_cast<const v8*>(&sB[(r * NP + cn * 16 + ar) * SK + kofs + 32 * h + ak]);
                     nb[r] = neg8(b[r]);
                 }
 #pragma unroll
@@ -507,13 +564,36 @@ __global__ __launch_bounds__(256) void k_qgemm_lp(LpParams P) {
 #pragma unroll
                     for (int p = 0; p < 4; p++) {
                         const int r = p ^ q;
-                        acc[p][cn] = L::mma(a[q][h], term_sign<ADJ>(p, q) > 0 ? b[r] : nb[r], acc[p][cn]);
+                        acc[p][j] = L::mma(a[q][h], term_sign<ADJ>(p, q) > 0 ? b[r] : nb[r], acc[p][j]);
                     }
             }
+    };
+
+    if (kb >= ke) return;   // uniform: an empty split (no partial tile is read for it)
+    v8 aX[4][2], aY[4][2], bt[CPT];
+    load_b(kb, bt);
+    load_a(kb, aX);
+    load_a(kb + LBK, aY);
+    store_b(bt);
+    __syncthreads();
+    for (int64_t k0 = kb; k0 < ke; k0 += LKS) {
+        const bool more = k0 + LKS < ke;
+        load_b(more ? k0 + LKS : k0, bt);
+        step(aX, 0);
+        load_a(k0 + LKS, aX);
+        step(aY, LBK);
+        load_a(k0 + LKS + LBK, aY);
+        if (more) {
+            __syncthreads();   // every wave is done with the staged tile
+            store_b(bt);
+            __syncthreads();
+        }
     }
     const float sc = P.cscale ? *P.cscale : 1.0f;
 #pragma unroll
-    for (int cn = 0; cn < CN; cn++)
+    for (int j = 0; j < CNW; j++) {
+        const int cn = cg * CNW + j;
+        if (cn >= CN) continue;
 #pragma unroll
         for (int i = 0; i < 4; i++) {
             const int64_t r = rbase + 4 * (lane >> 4) + i;
@@ -521,14 +601,19 @@ __global__ __launch_bounds__(256) void k_qgemm_lp(LpParams P) {
             if (P.splits == 1) {
                 if (r < P.M && c < P.N)
 #pragma unroll
-                    for (int p = 0; p < 4; p++) P.C[p * P.cps + r * P.ldc + c] = acc[p][cn][i] * sc;
+                    for (int p = 0; p < 4; p++) P.C[p * P.cps + r * P.ldc + c] = acc[p][j][i] * sc;
             } else {
 #pragma unroll
                 for (int p = 0; p < 4; p++)
-                    P.part[(((int64_t)split * 4 + p) * P.Mp + r) * P.Np + c] = acc[p][cn][i] * sc;
+                    P.part[(((int64_t)split * 4 + p) * P.Mp + r) * P.Np + c] = acc[p][j][i] * sc;
             }
         }
+    }
 }
+
+// column groups per workgroup and column tiles per wave for CN column tiles
+constexpr int lp_ncg(int cn) { return cn <= 2 ? 1 : 2; }
+constexpr int lp_cnw(int cn) { return (cn + lp_ncg(cn) - 1) / lp_ncg(cn); }
 
 struct LpPlan {
     int CN;
@@ -541,13 +626,14 @@ LpPlan make_lp_plan(const QgemmDesc& d) {
     p.Np = 16 * (int64_t)p.CN;
     p.gx = (d.M + LBM - 1) / LBM;
     p.Mp = p.gx * LBM;
-    p.Kp = ((d.K + LBK - 1) / LBK) * LBK;
-    // split K for about 2 workgroups per CU, each over at least 2 K steps
+    p.Kp = ((d.K + LKS - 1) / LKS) * LKS;
+    // split K so that every CU gets a workgroup, each over at least 2 K steps; no more splits than
+    // that, since the partial tiles (splits x the output) add traffic next to A
     int64_t splits = 1;
-    if (p.gx < 2 * kCUs) splits = std::min<int64_t>((2 * kCUs + p.gx - 1) / p.gx, (d.K + 2 * LBK - 1) / (2 * LBK));
+    if (p.gx < kCUs) splits = std::min<int64_t>((kCUs + p.gx - 1) / p.gx, (d.K + 2 * LBK - 1) / (2 * LBK));
     splits = std::max<int64_t>(splits, 1);
     int64_t kchunk = (d.K + splits - 1) / splits;
-    kchunk = ((kchunk + LBK - 1) / LBK) * LBK;
+    kchunk = ((kchunk + LKS - 1) / LKS) * LKS;
     p.splits = (d.K + kchunk - 1) / kchunk;
     if (p.splits < 1) p.splits = 1;
     p.kchunk = kchunk;
@@ -566,7 +652,7 @@ hipError_t launch_lp(const QgemmDesc& d, const LpPlan& pl, void* scratch, hipStr
     hipLaunchKernelGGL(k_lp_thin<TL>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, (const float*)d.B, d.ldb,
                        d.bps, d.K, d.N, Bt, pl.Np, pl.Kp);
     LpParams P{};
-    P.A = d.A; P.lda = d.lda; P.aps = d.aps;
+    P.A = d.A; P.akt = (d.K + LBK - 1) / LBK; P.art = (d.M + 15) / 16;
     P.Bt = Bt; P.bkp = pl.Kp;
     P.C = (float*)d.C; P.ldc = d.ldc; P.cps = d.cps;
     P.M = d.M; P.N = d.N; P.K = d.K;
@@ -576,16 +662,15 @@ hipError_t launch_lp(const QgemmDesc& d, const LpPlan& pl, void* scratch, hipStr
     P.cscale = d.cscale;
     dim3 grid((unsigned)pl.gx, 1, (unsigned)pl.splits);
 #define QL_LP(CN_) \
-    if (pl.CN == CN_) hipLaunchKernelGGL((k_qgemm_lp<TL, ADJ, CN_>), grid, dim3(256), 0, st, P); else
+    if (pl.CN == CN_) \
+        hipLaunchKernelGGL((k_qgemm_lp<TL, ADJ, CN_, lp_ncg(CN_), lp_cnw(CN_)>), grid, dim3(256 * lp_ncg(CN_)), 0, st, P); \
+    else
     QL_LP(1) QL_LP(2) QL_LP(3) QL_LP(4) QL_LP(5) return hipErrorInvalidValue;
 #undef QL_LP
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || pl.splits == 1) return e;
-    const int64_t total = 8 * 4 * d.M * d.N;
-    hipLaunchKernelGGL((k_splitk_reduce<float, float>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                       (const float*)part, (int)pl.splits, pl.Mp, pl.Np, (float*)d.C, d.ldc, d.cps, d.M, d.N,
-                       (int)ST_SET, d.skip_flag);
-    return hipGetLastError();
+    return reduce_f32(part, (int)pl.splits, pl.Mp, pl.Np, (float*)d.C, d.ldc, d.cps, d.M, d.N, (int)ST_SET,
+                      d.skip_flag, st);
 }
 
 bool vec_ok(const void* p, int64_t ld, int64_t ps, size_t el) {

@@ -235,8 +235,8 @@ void carve(const Problem& pr, const Dims& d, Arena& ar, Bufs& b, size_t part_byt
     b.Gs = batched && nest ? (double*)ar.take((size_t)nest * 4 * l2 * sizeof(double)) : nullptr;
     b.est_work = batched && nest ? (double*)ar.take(heig_work_doubles(nest) * sizeof(double)) : nullptr;
     const bool lowp = pr.prec != QLRA_FP32 && pr.v > 2;
-    b.Alo = lowp ? ar.take((size_t)4 * pr.m * pr.n * 2) : nullptr;
-    b.Alo_t = lowp ? ar.take((size_t)4 * pr.m * pr.n * 2) : nullptr;
+    b.Alo = lowp ? ar.take(lowp_copy_elems(pr.m, pr.n) * 2) : nullptr;
+    b.Alo_t = lowp ? ar.take(lowp_copy_elems(pr.n, pr.m) * 2) : nullptr;
     b.lp_scale = (float*)ar.take(2 * sizeof(float));
     b.partial = part_bytes ? ar.take(part_bytes) : nullptr;
 }
@@ -707,6 +707,13 @@ int qlra_qgemm(int op, const float* A, int64_t m, int64_t n, int64_t lda, int64_
     s.counters = (unsigned*)ar.take(std::max<size_t>(cnt, 1) * sizeof(unsigned));
     s.partial = ar.take(qgemm_partial_bytes(d));
     return qgemm_launch(d, s, (hipStream_t)stream) == hipSuccess ? QLRA_OK : QLRA_E_HIP;
+}
+
+int qlra_lowp_copy_bytes(int64_t m, int64_t n, size_t* alo_bytes, size_t* alo_t_bytes) {
+    if (m < 0 || n < 0 || !alo_bytes || !alo_t_bytes) return QLRA_E_ARG;
+    *alo_bytes = lowp_copy_elems(m, n) * 2;
+    *alo_t_bytes = lowp_copy_elems(n, m) * 2;
+    return QLRA_OK;
 }
 
 int qlra_lowp_copy(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_ps, int precision,

@@ -56,6 +56,7 @@ _lib.qlra_omega.argtypes = [ctypes.c_uint64, _I64, _I64, _P, _I64, _I64, _P]
 _lib.qlra_qgemm_workspace_size.argtypes = [_I, _I64, _I64, _I64, _SZ]
 _lib.qlra_qgemm.argtypes = [_I, _P, _I64, _I64, _I64, _I64, _P, _I64, _I64, _I64, _P, _I64, _I64, _P,
                             ctypes.c_size_t, _P]
+_lib.qlra_lowp_copy_bytes.argtypes = [_I64, _I64, _SZ, _SZ]
 _lib.qlra_lowp_copy.argtypes = [_P, _I64, _I64, _I64, _I64, _I, _P, _P, _P, _P]
 _lib.qlra_qgemm_lp_workspace_size.argtypes = [_I, _I, _I64, _I64, _I64, _SZ]
 _lib.qlra_qgemm_lp.argtypes = [_I, _I, _P, _I64, _I64, _P, _I64, _I64, _I64, _P, _I64, _I64, _P, _P,
@@ -65,12 +66,12 @@ _lib.qlra_cholqr.argtypes = [_P, _I64, _I64, _I64, _I64, _P, _I64, _I64, _P, _P,
 _lib.qlra_qsvd_workspace_size.argtypes = [_I64, _SZ]
 _lib.qlra_qsvd.argtypes = [_P, _I64, _P, _P, _P, _P, ctypes.c_size_t, _P]
 for _name in ("qlra_workspace_size", "qlra", "qlra_status", "qlra_omega", "qlra_qgemm_workspace_size",
-              "qlra_qgemm", "qlra_lowp_copy", "qlra_qgemm_lp_workspace_size", "qlra_qgemm_lp",
+              "qlra_qgemm", "qlra_lowp_copy_bytes", "qlra_lowp_copy", "qlra_qgemm_lp_workspace_size", "qlra_qgemm_lp",
               "qlra_cholqr_workspace_size", "qlra_cholqr", "qlra_qsvd_workspace_size", "qlra_qsvd"):
     getattr(_lib, _name).restype = _I
 
 EXPORTS = ("qlra", "qlra_workspace_size", "qlra_status", "qlra_strerror", "qlra_omega", "qlra_qgemm",
-           "qlra_qgemm_workspace_size", "qlra_lowp_copy", "qlra_qgemm_lp", "qlra_qgemm_lp_workspace_size",
+           "qlra_qgemm_workspace_size", "qlra_lowp_copy_bytes", "qlra_lowp_copy", "qlra_qgemm_lp", "qlra_qgemm_lp_workspace_size",
            "qlra_cholqr", "qlra_cholqr_workspace_size", "qlra_qsvd", "qlra_qsvd_workspace_size")
 
 
@@ -183,14 +184,22 @@ def qlra_qgemm(op, A, B, C=None, stream=None, workspace=None):
 _LP_DTYPES = {QLRA_BF16: torch.bfloat16, QLRA_FP16: torch.float16}
 
 
+def qlra_lowp_copy_bytes(m, n):
+    a, t = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(_lib.qlra_lowp_copy_bytes(m, n, ctypes.byref(a), ctypes.byref(t)), "qlra_lowp_copy_bytes")
+    return a.value, t.value
+
+
 def qlra_lowp_copy(A, precision, scale=None, stream=None):
-    """BF16 / FP16 copies of A (4, m, n): returns (Alo (4, m, n), Alo_t (4, n, m)), each scaled by
-    the device scalar `scale` (a one-element float32 tensor, or None for 1)."""
+    """BF16 / FP16 copies of A (4, m, n) in the tiled layout of include/qlra.h: returns flat tensors
+    (Alo, Alo_t), each scaled by the device scalar `scale` (a one-element float32 tensor, or None
+    for 1)."""
     m, n = A.shape[1], A.shape[2]
     pa, lda, aps = _planes(A, m, n, "A")
     dt = _LP_DTYPES[precision]
-    Alo = torch.empty((4, m, n), dtype=dt, device=A.device)
-    Alo_t = torch.empty((4, n, m), dtype=dt, device=A.device)
+    na, nt = qlra_lowp_copy_bytes(m, n)
+    Alo = torch.empty(na // 2, dtype=dt, device=A.device)
+    Alo_t = torch.empty(nt // 2, dtype=dt, device=A.device)
     _check(_lib.qlra_lowp_copy(pa, m, n, lda, aps, precision,
                                ctypes.c_void_p(scale.data_ptr()) if scale is not None else None,
                                ctypes.c_void_p(Alo.data_ptr()), ctypes.c_void_p(Alo_t.data_ptr()), _stream_ptr(stream)),
@@ -206,11 +215,12 @@ def qlra_qgemm_lp_workspace(op, precision, m, n, w, device="cuda"):
 
 
 def qlra_qgemm_lp(op, precision, Alo, m, n, B, C=None, inv_scale=None, stream=None, workspace=None):
-    """Reduced-precision view product: op 0: C = A B from the (4, m, n) copy; op 1: C = A^H B
-    from the transposed (4, n, m) copy.  B and C are FP32."""
+    """Reduced-precision view product: op 0: C = A B from the copy of A; op 1: C = A^H B from the
+    copy of A^T (both from qlra_lowp_copy).  B and C are FP32."""
     rows, kdim = (m, n) if op == 0 else (n, m)
-    if Alo.dtype != _LP_DTYPES[precision] or tuple(Alo.shape) != (4, rows, kdim) or not Alo.is_contiguous():
-        raise ValueError("Alo: expected the contiguous copy made by qlra_lowp_copy for this op")
+    need = qlra_lowp_copy_bytes(m, n)[op] // 2
+    if Alo.dtype != _LP_DTYPES[precision] or Alo.numel() < need or not Alo.is_contiguous():
+        raise ValueError("Alo: expected the copy made by qlra_lowp_copy for this op")
     w = B.shape[2]
     if C is None:
         C = torch.empty((4, rows, w), dtype=torch.float32, device=B.device)

@@ -58,6 +58,17 @@ def rounded(x32, prec, scale=1.0):
 PREC = {"bf16": 1, "fp16": 2}
 
 
+def tiled(x):
+    """(4, R, K) array -> the flat tiled order of include/qlra.h: tiles of 16 rows x 64
+    reduction elements, the four planes of a tile adjacent, inside a tile [h][kq][r][8]."""
+    _, R, K = x.shape
+    RT, KT = -(-R // 16), -(-K // 64)
+    pad = np.zeros((4, RT * 16, KT * 64), dtype=x.dtype)
+    pad[:, :R, :K] = x
+    t = pad.reshape(4, RT, 16, KT, 2, 4, 8)          # p, rt, r, kt, h, kq, e
+    return np.ascontiguousarray(t.transpose(1, 3, 0, 4, 5, 2, 6)).reshape(-1)
+
+
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 @pytest.mark.parametrize("m,n", [(300, 200), (129, 67)])
 def test_lowp_copy_bit_exact(gq, prec, m, n):
@@ -75,8 +86,8 @@ def test_lowp_copy_bit_exact(gq, prec, m, n):
         want = round_bf16_bits(xs)
     else:
         want = xs.astype(np.float16).view(np.uint16)
-    assert np.array_equal(got, want)
-    assert np.array_equal(got_t, np.ascontiguousarray(want.transpose(0, 2, 1)))
+    assert np.array_equal(got, tiled(want))
+    assert np.array_equal(got_t, tiled(np.ascontiguousarray(want.transpose(0, 2, 1))))
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
