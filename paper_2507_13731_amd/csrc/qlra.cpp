@@ -8,10 +8,18 @@
 // and one batched eigenvalue launch on a side stream (fork/join with events) turns all of
 // them into estimates while the final QSVD runs on the main stream.
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
 #include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -40,6 +48,14 @@ struct Ctx {
     float* T2 = nullptr;            // CholQR intermediate, rows x wmax
     int64_t T2_rows = 0;
     double* Rjunk = nullptr;        // R of QRs whose factor is not needed
+    // Step mode: a solve is v steps, step s holding view s + 1 (the first also the set-up, the
+    // last also the final QSVD).  step_only >= 0 enqueues that step's launches only, so that a
+    // scheduler can advance many solves one view at a time.
+    int views = 0;                  // views begun so far
+    int step_only = -1;
+    bool forked = false;            // this step forked work to the side stream
+    int step_now() const { return views > 0 ? views - 1 : 0; }
+    bool live() const { return !dry && (step_only < 0 || step_now() == step_only); }
 };
 
 void note(Ctx& c, hipError_t e) {
@@ -52,6 +68,7 @@ void qg(Ctx& c, const QgemmDesc& d) {
         c.cnt_need = std::max(c.cnt_need, qgemm_counter_count(d));
         return;
     }
+    if (!c.live()) return;
     note(c, qgemm_launch(d, c.scr, c.st));
 }
 
@@ -102,14 +119,14 @@ void cholqr(Ctx& c, const float* Y, int64_t rows, int64_t w, int64_t ldy, int64_
         if (small) {
             // this round's own factor; the product R2 R1 is formed at the end when R is wanted
             double* Rr = (rounds == 1 && R) ? R : (round == 0 ? c.R1 : c.R2);
-            if (!c.dry) {
+            if (c.live()) {
                 note(c, chol_reg_launch(G, w, Rr, c.status, round == 0 ? shifted : nullptr, nullptr, round == 0 ? 1 : 0,
                                         shift_scale(rows, w), c.st));
                 note(c, trsm_launch(src, lds, sps, dst, ldd, dps, Rr, w, rows, nullptr, c.st));
             }
         } else {
             double* Rout = last ? (R ? R : c.Rjunk) : (round == 0 ? c.R1 : c.R2);
-            if (!c.dry)
+            if (c.live())
                 note(c, chol_launch(G, w, Rout, c.Rinv, Rprev, c.chol_work, c.status, round == 0 ? shifted : nullptr,
                                     nullptr, round == 0 ? 1 : 0, shift_scale(rows, w), nullptr, 0.0, c.st));
             qg(c, desc(OP_NN, MATH_F64, src, lds, sps, 0, c.Rinv, w, w * w, 1, dst, ldd, dps, 0, rows, w, w));
@@ -117,7 +134,7 @@ void cholqr(Ctx& c, const float* Y, int64_t rows, int64_t w, int64_t ldy, int64_
         }
         src = dst; lds = ldd; sps = dps;
     }
-    if (small && rounds == 2 && R && !c.dry) note(c, rmul_launch(c.R2, c.R1, R, w, nullptr, c.st));
+    if (small && rounds == 2 && R && c.live()) note(c, rmul_launch(c.R2, c.R1, R, w, nullptr, c.st));
 }
 
 // Orthonormalise the columns of a stack of blocks (rows x W, ld W) of width l: CholeskyQR2 of
@@ -306,7 +323,8 @@ double* gram_slot(const Bufs& b, const Problem& pr, int64_t l, int i) {
 
 // Estimates of views 2 .. v-1 from their Grams, one batched launch on the side stream.
 void fork_estimates(Ctx& c, const Bufs& b, const Problem& pr, int64_t l) {
-    if (c.dry || !pr.estimate || !b.Gs) return;
+    if (!c.live() || !pr.estimate || !b.Gs) return;
+    c.forked = true;
     note(c, hipEventRecord(c.ev_fork, c.st));
     note(c, hipStreamWaitEvent(c.side, c.ev_fork, 0));
     note(c, estimate_batch_launch(b.Gs, 4 * l * l, l, pr.v - 2, pr.k, b.nA2, pr.pass_err + 1, b.est_work, c.side));
@@ -315,7 +333,8 @@ void fork_estimates(Ctx& c, const Bufs& b, const Problem& pr, int64_t l) {
 // Side-stream estimate of view `i` (1-based) from its R (l x l), for widths above the batched
 // eigensolver's limit.
 void fork_estimate(Ctx& c, const Bufs& b, const Problem& pr, const double* R, int64_t l, int i) {
-    if (c.dry || !pr.estimate || b.Gs || i >= pr.v) return;
+    if (!c.live() || !pr.estimate || b.Gs || i >= pr.v) return;
+    c.forked = true;
     note(c, hipEventRecord(c.ev_fork, c.st));
     note(c, hipStreamWaitEvent(c.side, c.ev_fork, 0));
     note(c, qsvd_launch(R, l, nullptr, b.side_S, nullptr, b.side_work, 0, c.side));
@@ -328,7 +347,7 @@ void fork_estimate(Ctx& c, const Bufs& b, const Problem& pr, const double* R, in
 void finish(Ctx& c, const Bufs& b, const Problem& pr, const double* R, int64_t w, const float* Q1, int64_t ldq1,
             const float* Q2, int64_t ldq2, bool r_is_r2) {
     const int k = pr.k;
-    if (!c.dry) {
+    if (c.live()) {
         note(c, qsvd_launch(R, w, b.Lh, b.Sw, b.Rh, b.qsvd_work, 1, c.st));
         if (pr.estimate) note(c, estimate_launch(b.Sw, k, b.nA2, pr.pass_err + (pr.v - 1), c.st));
     }
@@ -336,7 +355,7 @@ void finish(Ctx& c, const Bufs& b, const Problem& pr, const double* R, int64_t w
     const double* Vh = r_is_r2 ? b.Lh : b.Rh;
     qg(c, desc(OP_NN, MATH_F64, Q1, ldq1, pr.m * ldq1, 0, Uh, w, w * w, 1, pr.U, pr.ldu, pr.ups, 0, pr.m, k, w));
     qg(c, desc(OP_NN, MATH_F64, Q2, ldq2, pr.n * ldq2, 0, Vh, w, w * w, 1, pr.V, pr.ldv, pr.vps, 0, pr.n, k, w));
-    if (!c.dry) {
+    if (c.live()) {
         note(c, phase_launch(pr.U, pr.m, pr.ldu, pr.ups, pr.V, pr.n, pr.ldv, pr.vps, k, c.st));
         note(c, copy_f64_launch(b.Sw, pr.S, k, c.st));
     }
@@ -351,7 +370,7 @@ void finish_gram(Ctx& c, const Bufs& b, const Problem& pr, const float* Y, int64
                  int64_t ldx, int64_t rows_x, int64_t w, bool y_is_u) {
     const int k = pr.k;
     qg(c, desc(OP_HN, MATH_F64, Y, w, rows_y * w, 0, Y, w, rows_y * w, 0, c.G, w, w * w, 1, w, w, rows_y));
-    if (!c.dry) {
+    if (c.live()) {
         note(c, heig_launch(c.G, w, b.Sw, b.Rh, b.qsvd_work, c.st));
         note(c, svals_launch(b.Sw, b.Rh, w, k, pr.S, b.Lh, c.st));
         if (pr.estimate) note(c, estimate_launch(pr.S, k, b.nA2, pr.pass_err + (pr.v - 1), c.st));
@@ -362,13 +381,14 @@ void finish_gram(Ctx& c, const Bufs& b, const Problem& pr, const float* Y, int64
     const int64_t ldox = y_is_u ? pr.ldv : pr.ldu, psox = y_is_u ? pr.vps : pr.ups;
     qg(c, desc(OP_NN, MATH_F64, Y, w, rows_y * w, 0, b.Lh, k, w * k, 1, Oy, ldoy, psoy, 0, rows_y, k, w));
     qg(c, desc(OP_NN, MATH_F64, X, ldx, rows_x * ldx, 0, b.Rh, w, w * w, 1, Ox, ldox, psox, 0, rows_x, k, w));
-    if (!c.dry) note(c, phase_launch(pr.U, pr.m, pr.ldu, pr.ups, pr.V, pr.n, pr.ldv, pr.vps, k, c.st));
+    if (c.live()) note(c, phase_launch(pr.U, pr.m, pr.ldu, pr.ups, pr.V, pr.n, pr.ldv, pr.vps, k, c.st));
 }
 
 // The product of a view alone: T = A X (forward, m x w) or T = A^H X (adjoint, n x w), ld w.
 // lowp: from the BF16 / FP16 copies (A for the forward product, A^T for the adjoint one).
 void view_product(Ctx& c, const Problem& pr, const Bufs& b, bool adjoint, const float* X, int64_t ldx, int64_t w,
                   float* T, bool lowp = false) {
+    c.views++;
     const int64_t rows_out = adjoint ? pr.n : pr.m;
     const int64_t kdim = adjoint ? pr.m : pr.n;
     if (lowp) {
@@ -393,7 +413,7 @@ void view(Ctx& c, const Problem& pr, const Bufs& b, bool adjoint, const float* X
 
 void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
     const int64_t l = d.l, l2 = l * l;
-    if (!c.dry) {
+    if (c.live()) {
         note(c, fill_int_launch(b.status, 16, 0, c.st));
         note(c, fill_u32_launch(b.counters, (int64_t)std::max<size_t>(c.cnt_need, 1), c.st));
         note(c, fro2_launch(pr.A, pr.m, pr.n, pr.lda, pr.aps, b.fro_part, b.nA2, c.st));
@@ -436,7 +456,7 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
     int i = 0;
     auto stack_in = [&](const float* Qb, int slot) {
         const int64_t c0 = (int64_t)slot * l;
-        if (c.dry || c0 >= Wk) return;
+        if (!c.live() || c0 >= Wk) return;
         note(c, copy_planes_launch(Qb, l, rs * l, b.stack + c0, Wk, sps, rs, std::min(l, Wk - c0), nullptr, c.st));
     };
     const bool keepR = pr.estimate && !b.Gs;
@@ -526,6 +546,214 @@ int check_layout(const void* P, int64_t rows, int64_t cols, int64_t ld, int64_t 
     return QLRA_OK;
 }
 
+
+// ---------------------------------------------------------------------------------------
+// Continuous-batching server: a scheduler thread admits requests in arrival order while a slot
+// and enough of the HBM arena are free, then advances every admitted request by one view-step
+// per tick (the view's product, its QR and, on the last step, the final QSVD), each request on
+// its own stream pair so that steps of different requests overlap on the device.  A request's
+// workspace (its bases, factors and Grams) lives in the arena from admission to completion.
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// First-fit allocator over [0, cap) with 256-byte granules; adjacent free ranges merge.
+class ArenaAlloc {
+  public:
+    explicit ArenaAlloc(size_t cap) { if (cap) free_[0] = cap; }
+    bool alloc(size_t bytes, size_t* off) {
+        bytes = (bytes + 255) & ~size_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes, at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                used_ += bytes;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = (bytes + 255) & ~size_t(255);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    size_t used() const { return used_; }
+
+  private:
+    std::map<size_t, size_t> free_;
+    size_t used_ = 0;
+};
+
+struct SrvRequest {
+    qlra_request_t r{};
+    uint64_t ticket = 0;
+    Problem pr{};
+    Dims d{};
+    size_t part = 0, cnt = 0, bytes = 0, off = 0;
+    int slot = -1;
+    int next_step = 0;
+    bool all_enqueued = false;
+    int done = 0;              // 0 pending / running, 1 finished
+    int status = QLRA_OK;
+    double t_arrival = 0, t_admit = 0, t_done = 0;
+    std::vector<hipGraphExec_t> graphs;
+};
+
+struct SrvSlot {
+    hipStream_t st = nullptr, side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr, done = nullptr;
+    int* status_host = nullptr;   // pinned: the request's status word, copied after its last step
+    SrvRequest* req = nullptr;
+};
+
+}  // namespace
+}  // namespace qlra_impl
+
+struct qlra_server {
+    int dev = 0;
+    int graphs = 0;
+    char* arena = nullptr;
+    size_t cap = 0;
+    qlra_impl::ArenaAlloc alloc{0};
+    std::vector<qlra_impl::SrvSlot> slots;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<qlra_impl::SrvRequest*> pending;
+    std::unordered_map<uint64_t, std::unique_ptr<qlra_impl::SrvRequest>> reqs;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    int active = 0, max_active_seen = 0;
+    size_t max_used_seen = 0;
+    int64_t ticks = 0;
+    hipError_t err = hipSuccess;
+    std::thread th;
+};
+
+namespace qlra_impl {
+namespace {
+
+// Enqueue step s of a request on its slot's streams (captured as a graph when asked).
+void srv_enqueue_step(qlra_server* sv, SrvRequest* q, int s) {
+    SrvSlot& sl = sv->slots[q->slot];
+    Arena ar{sv->arena + q->off, q->bytes, 0, false};
+    Bufs b{};
+    carve(q->pr, q->d, ar, b, q->part, q->cnt);
+    Ctx c;
+    c.cnt_need = q->cnt;
+    bind_ctx(c, b, q->d);
+    c.side = sl.side; c.ev_fork = sl.fork; c.ev_join = sl.join;
+    c.step_only = s;
+    const bool last = s == q->pr.v - 1;
+    hipGraph_t g = nullptr;
+    const bool cap = sv->graphs != 0;
+    c.st = sl.st;
+    if (cap && hipStreamBeginCapture(sl.st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        q->status = QLRA_E_HIP;
+        return;
+    }
+    run_solve(c, q->pr, q->d, b);
+    // a step rejoins whatever it forked (a captured step must, and the slot's events are reused)
+    if (c.forked) {
+        note(c, hipEventRecord(c.ev_join, c.side));
+        note(c, hipStreamWaitEvent(c.st, c.ev_join, 0));
+    }
+    if (cap) {
+        const hipError_t ee = hipStreamEndCapture(sl.st, &g);
+        hipGraphExec_t ex = nullptr;
+        if (ee == hipSuccess && g && c.err == hipSuccess && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess) {
+            note(c, hipGraphLaunch(ex, sl.st));
+            q->graphs.push_back(ex);
+        } else {
+            c.err = c.err == hipSuccess ? hipErrorUnknown : c.err;
+        }
+        if (g) (void)hipGraphDestroy(g);
+    }
+    if (last) {
+        note(c, hipMemcpyAsync(sl.status_host, b.status, sizeof(int), hipMemcpyDeviceToHost, sl.st));
+        note(c, hipEventRecord(sl.done, sl.st));
+    }
+    if (c.err != hipSuccess) q->status = QLRA_E_HIP;
+}
+
+void srv_loop(qlra_server* sv) {
+    if (hipSetDevice(sv->dev) != hipSuccess) { sv->err = hipErrorInvalidDevice; return; }
+    std::unique_lock<std::mutex> lk(sv->mu);
+    while (true) {
+        // admission: arrival order, a free slot and room in the arena
+        while (!sv->pending.empty()) {
+            SrvRequest* q = sv->pending.front();
+            int slot = -1;
+            for (size_t i = 0; i < sv->slots.size(); i++)
+                if (!sv->slots[i].req) { slot = (int)i; break; }
+            size_t off = 0;
+            if (slot < 0 || !sv->alloc.alloc(q->bytes, &off)) break;
+            sv->pending.pop_front();
+            q->off = off;
+            q->slot = slot;
+            q->t_admit = now_s();
+            sv->slots[slot].req = q;
+            sv->active++;
+            sv->max_active_seen = std::max(sv->max_active_seen, sv->active);
+            sv->max_used_seen = std::max(sv->max_used_seen, sv->alloc.used());
+        }
+        bool work = false;
+        // one view-step per admitted request
+        for (auto& sl : sv->slots) {
+            SrvRequest* q = sl.req;
+            if (!q || q->all_enqueued) continue;
+            lk.unlock();
+            srv_enqueue_step(sv, q, q->next_step);
+            lk.lock();
+            q->next_step++;
+            if (q->next_step >= q->pr.v) q->all_enqueued = true;
+            work = true;
+        }
+        // completions
+        for (auto& sl : sv->slots) {
+            SrvRequest* q = sl.req;
+            if (!q || !q->all_enqueued) continue;
+            const hipError_t e = hipEventQuery(sl.done);
+            if (e == hipErrorNotReady) continue;
+            q->t_done = now_s();
+            if (e != hipSuccess) q->status = QLRA_E_HIP;
+            else if (q->status == QLRA_OK && (*sl.status_host & 2)) q->status = QLRA_E_NUMERIC;
+            for (auto ex : q->graphs) (void)hipGraphExecDestroy(ex);
+            q->graphs.clear();
+            sv->alloc.release(q->off, q->bytes);
+            sl.req = nullptr;
+            sv->active--;
+            q->done = 1;
+            work = true;
+            sv->cv.notify_all();
+        }
+        sv->ticks++;
+        if (sv->stop && sv->pending.empty() && sv->active == 0) break;
+        if (!work) sv->cv.wait_for(lk, std::chrono::microseconds(50));
+    }
+}
+
+}  // namespace
+}  // namespace qlra_impl
+
+namespace qlra_impl {
+namespace {
 }  // namespace
 }  // namespace qlra_impl
 
@@ -835,5 +1063,125 @@ int qlra_qsvd(const double* R, int64_t w, double* Uh, double* S, double* Vh, voi
                ? QLRA_OK
                : QLRA_E_HIP;
 }
+
+int qlra_server_create(const qlra_server_opts_t* opts, qlra_server_t** out) {
+    if (!opts || !out || opts->max_active < 1 || opts->max_active > 64 || opts->hbm_bytes < 256) return QLRA_E_ARG;
+    auto sv = std::make_unique<qlra_server>();
+    if (hipGetDevice(&sv->dev) != hipSuccess) return QLRA_E_HIP;
+    sv->graphs = opts->graphs;
+    sv->cap = opts->hbm_bytes;
+    if (hipMalloc((void**)&sv->arena, sv->cap) != hipSuccess) return QLRA_E_HIP;
+    sv->alloc = ArenaAlloc(sv->cap);
+    sv->slots.resize(opts->max_active);
+    for (auto& sl : sv->slots) {
+        if (hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&sl.side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.join, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+            hipHostMalloc((void**)&sl.status_host, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+            qlra_server_destroy(sv.release());
+            return QLRA_E_HIP;
+        }
+        *sl.status_host = 0;
+    }
+    qlra_server* raw = sv.release();
+    raw->th = std::thread(srv_loop, raw);
+    *out = raw;
+    return QLRA_OK;
+}
+
+int qlra_server_submit(qlra_server_t* sv, const qlra_request_t* r, uint64_t* ticket) {
+    if (!sv || !r || !ticket) return QLRA_E_ARG;
+    auto q = std::make_unique<SrvRequest>();
+    q->r = *r;
+    Problem& pr = q->pr;
+    pr.A = r->A; pr.m = r->m; pr.n = r->n; pr.lda = r->lda; pr.aps = r->a_plane_stride;
+    pr.k = r->k; pr.p = r->p; pr.v = r->pass_budget; pr.scheme = r->scheme; pr.seed = r->seed;
+    pr.U = r->U; pr.ldu = r->ldu; pr.ups = r->u_plane_stride; pr.S = r->S;
+    pr.V = r->V; pr.ldv = r->ldv; pr.vps = r->v_plane_stride;
+    pr.pass_err = r->pass_err;
+    pr.estimate = r->pass_err ? 1 : 0;
+    pr.prec = r->pass_precision;
+    int rc = check_problem(pr);
+    if (rc) return rc;
+    if ((rc = check_layout(r->A, r->m, r->n, r->lda, r->a_plane_stride))) return rc;
+    if ((rc = check_layout(r->U, r->m, r->k, r->ldu, r->u_plane_stride))) return rc;
+    if ((rc = check_layout(r->V, r->n, r->k, r->ldv, r->v_plane_stride))) return rc;
+    if (!r->S) return QLRA_E_ARG;
+    q->d = dims_of(pr.m, pr.n, pr.k, pr.p, pr.v, pr.scheme);
+    size_solve(pr, q->d, &q->part, &q->cnt, &q->bytes);
+    if (q->bytes > sv->cap) return QLRA_E_TOO_LARGE;
+    q->t_arrival = r->arrival_time > 0 ? r->arrival_time : now_s();
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stop) return QLRA_E_ARG;
+    q->ticket = sv->next_ticket++;
+    *ticket = q->ticket;
+    sv->pending.push_back(q.get());
+    sv->reqs.emplace(q->ticket, std::move(q));
+    sv->cv.notify_all();
+    return QLRA_OK;
+}
+
+int qlra_server_poll(qlra_server_t* sv, uint64_t ticket, int wait, int* done, int* status, double* latency_s) {
+    if (!sv || !done) return QLRA_E_ARG;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->reqs.find(ticket);
+    if (it == sv->reqs.end()) return QLRA_E_ARG;
+    SrvRequest* q = it->second.get();
+    if (wait) sv->cv.wait(lk, [&] { return q->done != 0; });
+    *done = q->done;
+    if (q->done) {
+        if (status) *status = q->status;
+        if (latency_s) *latency_s = q->t_done - q->t_arrival;
+        sv->reqs.erase(it);
+    }
+    return QLRA_OK;
+}
+
+int qlra_server_drain(qlra_server_t* sv) {
+    if (!sv) return QLRA_E_ARG;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->cv.wait(lk, [&] { return sv->pending.empty() && sv->active == 0; });
+    return sv->err == hipSuccess ? QLRA_OK : QLRA_E_HIP;
+}
+
+int qlra_server_stats(qlra_server_t* sv, qlra_server_stats_t* st) {
+    if (!sv || !st) return QLRA_E_ARG;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    st->pending = (int)sv->pending.size();
+    st->active = sv->active;
+    st->max_active_seen = sv->max_active_seen;
+    st->arena_bytes = sv->cap;
+    st->arena_used = sv->alloc.used();
+    st->max_arena_used = sv->max_used_seen;
+    st->ticks = sv->ticks;
+    return QLRA_OK;
+}
+
+int qlra_server_destroy(qlra_server_t* sv) {
+    if (!sv) return QLRA_E_ARG;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+        sv->cv.notify_all();
+    }
+    if (sv->th.joinable()) sv->th.join();
+    for (auto& sl : sv->slots) {
+        if (sl.st) (void)hipStreamSynchronize(sl.st);
+        if (sl.side) (void)hipStreamSynchronize(sl.side);
+        if (sl.st) (void)hipStreamDestroy(sl.st);
+        if (sl.side) (void)hipStreamDestroy(sl.side);
+        if (sl.fork) (void)hipEventDestroy(sl.fork);
+        if (sl.join) (void)hipEventDestroy(sl.join);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.status_host) (void)hipHostFree(sl.status_host);
+    }
+    if (sv->arena) (void)hipFree(sv->arena);
+    delete sv;
+    return QLRA_OK;
+}
+
+double qlra_server_clock(void) { return now_s(); }
 
 }  // extern "C"

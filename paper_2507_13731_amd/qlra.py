@@ -28,6 +28,26 @@ class QlraError(RuntimeError):
         self.code = code
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int), ("graphs", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("lda", ctypes.c_int64),
+                ("a_plane_stride", ctypes.c_int64), ("k", ctypes.c_int), ("p", ctypes.c_int),
+                ("pass_budget", ctypes.c_int), ("scheme", ctypes.c_int), ("seed", ctypes.c_uint64),
+                ("pass_precision", ctypes.c_int), ("U", ctypes.c_void_p), ("ldu", ctypes.c_int64),
+                ("u_plane_stride", ctypes.c_int64), ("S", ctypes.c_void_p), ("V", ctypes.c_void_p),
+                ("ldv", ctypes.c_int64), ("v_plane_stride", ctypes.c_int64), ("pass_err", ctypes.c_void_p),
+                ("arrival_time", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("pending", ctypes.c_int), ("active", ctypes.c_int), ("max_active_seen", ctypes.c_int),
+                ("arena_bytes", ctypes.c_size_t), ("arena_used", ctypes.c_size_t),
+                ("max_arena_used", ctypes.c_size_t), ("ticks", ctypes.c_int64)]
+
+
 class Opts(ctypes.Structure):
     _fields_ = [("pass_precision", ctypes.c_int),
                 ("estimate_passes", ctypes.c_int),
@@ -65,6 +85,18 @@ _lib.qlra_cholqr_workspace_size.argtypes = [_I64, _I64, _SZ]
 _lib.qlra_cholqr.argtypes = [_P, _I64, _I64, _I64, _I64, _P, _I64, _I64, _P, _P, ctypes.c_size_t, _P]
 _lib.qlra_qsvd_workspace_size.argtypes = [_I64, _SZ]
 _lib.qlra_qsvd.argtypes = [_P, _I64, _P, _P, _P, _P, ctypes.c_size_t, _P]
+_lib.qlra_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)]
+_lib.qlra_server_submit.argtypes = [_P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+_lib.qlra_server_poll.argtypes = [_P, ctypes.c_uint64, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                                  ctypes.POINTER(ctypes.c_double)]
+_lib.qlra_server_drain.argtypes = [_P]
+_lib.qlra_server_stats.argtypes = [_P, ctypes.POINTER(ServerStats)]
+_lib.qlra_server_destroy.argtypes = [_P]
+_lib.qlra_server_clock.argtypes = []
+_lib.qlra_server_clock.restype = ctypes.c_double
+for _name in ("qlra_server_create", "qlra_server_submit", "qlra_server_poll", "qlra_server_drain",
+              "qlra_server_stats", "qlra_server_destroy"):
+    getattr(_lib, _name).restype = _I
 for _name in ("qlra_workspace_size", "qlra", "qlra_status", "qlra_omega", "qlra_qgemm_workspace_size",
               "qlra_qgemm", "qlra_lowp_copy_bytes", "qlra_lowp_copy", "qlra_qgemm_lp_workspace_size", "qlra_qgemm_lp",
               "qlra_cholqr_workspace_size", "qlra_cholqr", "qlra_qsvd_workspace_size", "qlra_qsvd"):
@@ -72,7 +104,9 @@ for _name in ("qlra_workspace_size", "qlra", "qlra_status", "qlra_omega", "qlra_
 
 EXPORTS = ("qlra", "qlra_workspace_size", "qlra_status", "qlra_strerror", "qlra_omega", "qlra_qgemm",
            "qlra_qgemm_workspace_size", "qlra_lowp_copy_bytes", "qlra_lowp_copy", "qlra_qgemm_lp", "qlra_qgemm_lp_workspace_size",
-           "qlra_cholqr", "qlra_cholqr_workspace_size", "qlra_qsvd", "qlra_qsvd_workspace_size")
+           "qlra_cholqr", "qlra_cholqr_workspace_size", "qlra_qsvd", "qlra_qsvd_workspace_size",
+           "qlra_server_create", "qlra_server_submit", "qlra_server_poll", "qlra_server_drain",
+           "qlra_server_stats", "qlra_server_destroy", "qlra_server_clock")
 
 
 def strerror(code):
@@ -266,3 +300,69 @@ def qlra_qsvd(R, vectors=True, stream=None):
                           ctypes.c_void_p(Vh.data_ptr()) if vectors else None,
                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)), "qlra_qsvd")
     return Uh, S, Vh
+
+
+def server_clock():
+    return _lib.qlra_server_clock()
+
+
+class Server:
+    """Continuous-batching server of the library (include/qlra.h).  submit() returns a ticket;
+    the caller keeps A and the outputs alive until poll() reports the request done."""
+
+    def __init__(self, hbm_bytes, max_active=8, graphs=False):
+        o = ServerOpts(int(hbm_bytes), int(max_active), 1 if graphs else 0)
+        h = ctypes.c_void_p()
+        _check(_lib.qlra_server_create(ctypes.byref(o), ctypes.byref(h)), "qlra_server_create")
+        self._h = h
+        self._keep = {}
+
+    def submit(self, A, k, p, pass_budget, scheme, seed, U=None, S=None, V=None, pass_err=None, estimate=True,
+               precision=QLRA_FP32, arrival_time=0.0):
+        scheme = SCHEMES.get(scheme, scheme)
+        m, n = A.shape[1], A.shape[2]
+        dev = A.device
+        pa, lda, aps = _planes(A, m, n, "A")
+        U = U if U is not None else torch.empty((4, m, k), dtype=torch.float32, device=dev)
+        V = V if V is not None else torch.empty((4, n, k), dtype=torch.float32, device=dev)
+        S = S if S is not None else torch.empty(k, dtype=torch.float64, device=dev)
+        if estimate and pass_err is None:
+            pass_err = torch.empty(pass_budget, dtype=torch.float64, device=dev)
+        pu, ldu, ups = _planes(U, m, k, "U")
+        pv, ldv, vps = _planes(V, n, k, "V")
+        r = Request(pa, m, n, lda, aps, k, p, pass_budget, scheme, ctypes.c_uint64(seed), precision, pu, ldu, ups,
+                    ctypes.c_void_p(S.data_ptr()), pv, ldv, vps,
+                    ctypes.c_void_p(pass_err.data_ptr()) if pass_err is not None else None, float(arrival_time))
+        t = ctypes.c_uint64()
+        _check(_lib.qlra_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)), "qlra_server_submit")
+        self._keep[t.value] = (A, U, S, V, pass_err)
+        return t.value
+
+    def poll(self, ticket, wait=False):
+        """None while running; (status, latency_s, (U, S, V, pass_err)) once done."""
+        done, st, lat = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(_lib.qlra_server_poll(self._h, ctypes.c_uint64(ticket), 1 if wait else 0, ctypes.byref(done),
+                                     ctypes.byref(st), ctypes.byref(lat)), "qlra_server_poll")
+        if not done.value:
+            return None
+        A, U, S, V, e = self._keep.pop(ticket)
+        return st.value, lat.value, (U, S, V, e)
+
+    def drain(self):
+        _check(_lib.qlra_server_drain(self._h), "qlra_server_drain")
+
+    def stats(self):
+        s = ServerStats()
+        _check(_lib.qlra_server_stats(self._h, ctypes.byref(s)), "qlra_server_stats")
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            _check(_lib.qlra_server_destroy(self._h), "qlra_server_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared():
     src = open(os.path.join(ROOT, "include", "qlra.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(qlra\w*)\s*\(", src, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|double|const char\*)\s+(qlra\w*)\s*\(", src, flags=re.M)))
 
 
 def test_header_declares_the_boundary():
