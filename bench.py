@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--no-serve", action="store_true")
     return ap.parse_args()
 
 
@@ -70,6 +72,70 @@ def time_view_kernels(Q, torch, A, reps):
         e1.record(st)
         e1.synchronize()
         out[op] = e0.elapsed_time(e1) * 1e-3 / reps
+    return out
+
+
+def serving(Q, torch, nreq, seed=3):
+    """The serving stream: nreq requests of mixed sizes, ranks, budgets and schemes through the
+    library's continuous-batching server.  First all at once (closed loop) to find the FP32
+    saturation rate, then Poisson arrivals at 0.7 of it, FP32 and FP16 views on the same
+    arrival times.  Latency = completion - arrival on the server's clock."""
+    import numpy as np
+    from workloads import gpu as WG
+    reqs = WG.serving_stream(seed, nreq)
+    for r in reqs:
+        r["U"] = torch.empty((4, r["m"], r["k"]), device="cuda")
+        r["V"] = torch.empty((4, r["n"], r["k"]), device="cuda")
+        r["S"] = torch.empty(r["k"], dtype=torch.float64, device="cuda")
+        r["e"] = torch.empty(r["v"], dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    hbm = 24 << 30
+    passes = sum(r["v"] for r in reqs)
+
+    def run(prec, arrivals, graphs=False, subset=None):
+        rs = reqs if subset is None else reqs[:subset]
+        srv = Q.Server(hbm, max_active=16, graphs=graphs)
+        t0 = Q.server_clock() + 0.005
+        tickets = []
+        for i, r in enumerate(rs):
+            ta = t0 + arrivals[i]
+            while Q.server_clock() < ta:
+                pass
+            tickets.append(srv.submit(r["A"], r["k"], r["p"], r["v"], r["scheme"], r["seed"], U=r["U"], S=r["S"],
+                                      V=r["V"], pass_err=r["e"], precision=prec, arrival_time=ta))
+        srv.drain()
+        lats, done = [], []
+        for i, t in enumerate(tickets):
+            st, lat, _ = srv.poll(t, wait=True)
+            assert st == Q.QLRA_OK, st
+            lats.append(lat)
+            done.append(t0 + arrivals[i] + lat)
+        stats = srv.stats()
+        srv.close()
+        return np.array(lats), max(done) - t0, stats
+
+    zeros = np.zeros(nreq)
+    run(Q.QLRA_FP32, zeros, subset=min(32, nreq))           # warm-up (first launches of every kernel)
+    run(Q.QLRA_FP16, zeros, subset=min(32, nreq))
+    _, span32, _ = run(Q.QLRA_FP32, zeros)
+    _, span32g, _ = run(Q.QLRA_FP32, zeros, graphs=True)
+    rate = nreq / span32
+    lam = 0.7 * rate
+    arrivals = np.cumsum(np.random.default_rng(seed).exponential(1.0 / lam, nreq))
+    out = {"requests": nreq, "workload": "m, n in {256..2048 step 128}, sigma_i = i^-1, dense/pure 50/50, "
+                                         "k in {8..64}, p = k/4, v in {2..6}, subspace/Krylov 50/50 (seeded)",
+           "passes": int(passes), "slots": 16, "arena_gb": hbm / 2 ** 30,
+           "closed_loop": {"fp32_req_per_s": round(rate, 2), "fp32_passes_per_s": round(passes / span32, 1),
+                           "fp32_graphs_req_per_s": round(nreq / span32g, 2)},
+           "poisson_rate_req_per_s": round(lam, 2)}
+    for name, prec in (("fp32", Q.QLRA_FP32), ("fp16", Q.QLRA_FP16)):
+        lat, span, stats = run(prec, arrivals)
+        out[name] = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                     "mean_ms": round(float(lat.mean()) * 1e3, 3),
+                     "throughput_req_per_s": round(nreq / span, 2), "passes_per_s": round(passes / span, 1),
+                     "max_in_flight": stats["max_active_seen"],
+                     "max_arena_gb": round(stats["max_arena_used"] / 2 ** 30, 3)}
     return out
 
 
@@ -239,6 +305,10 @@ def main():
     for name in lowp:
         lowp[name]["accuracy"] = acc_all[name]
         lowp[name]["max_error_ratio"] = round(max(r["ratio"] for r in acc_all[name]), 8)
+    serve = None
+    if not args.no_serve:
+        print(f"serving stream ({args.serve_requests} requests)", file=sys.stderr, flush=True)
+        serve = serving(Q, torch, args.serve_requests)
     cpu = None if args.no_cpu_baseline else cpu_baseline(A_np)
     line = {"metric": "A-passes/s", "value": round(value, 3), "unit": "A-passes/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -251,7 +321,8 @@ def main():
             "qgemm_tflops": round(achieved / 1e12, 3), "solve_ms": per_v, "accuracy": acc,
             "roofline": roofline, "cpu_baseline": cpu,
             "precision_form": {"views": "1..v-2 reduced (FP32 accumulation), v-1 and v FP32; Gram/Cholesky/QSVD FP64",
-                               **lowp}}
+                               **lowp},
+            "serving": serve}
     print(json.dumps(line))
 
 
