@@ -173,9 +173,10 @@ __global__ __launch_bounds__(kThreads) void k_chol_lds(const double* __restrict_
 }
 
 // ------------------------------------------------------------------------------------------
-// Factors of order w <= kRegMax: the matrix in registers (1024 threads, 2 x 2 entries each:
-// rows ty, ty + 32, columns tx, tx + 32), one barrier per elimination step.
-constexpr int kRegMax = 64;
+// Factors of order w <= kRegMax: the matrix in registers (1024 threads, NB x NB entries each:
+// rows ty + 32 i, columns tx + 32 j; NB = 2 up to 64, 3 up to 96), one barrier per elimination
+// step.
+constexpr int kRegMax = 96;
 
 __device__ __forceinline__ Q4 qadd(Q4 a, Q4 b) { return Q4{a.w + b.w, a.x + b.x, a.y + b.y, a.z + b.z}; }
 template <int S>
@@ -196,10 +197,10 @@ __device__ __forceinline__ double bcast(double v, int i) {
 // Right-looking Cholesky G + shift I = R^H R (R upper triangular with real positive diagonal):
 // step j scales row j by 1 / r_jj (the half wave that owns row j, double-buffered row in LDS),
 // then every owner of an entry (a, b), j < a <= b, subtracts conj(r_ja) r_jb.
-template <int H>
-__device__ __forceinline__ void chol_row(Q4 (&g)[2][2], int j, int w, int tx, double* rb, double rjj, double inv) {
+template <int NB, int H>
+__device__ __forceinline__ void chol_row(Q4 (&g)[NB][NB], int j, int w, int tx, double* rb, double rjj, double inv) {
 #pragma unroll
-    for (int ci = 0; ci < 2; ci++) {
+    for (int ci = H; ci < NB; ci++) {
         const int c = tx + 32 * ci;
         if (c == j) g[H][ci] = Q4{rjj, 0, 0, 0};
         else if (c > j && c < w) {
@@ -210,6 +211,16 @@ __device__ __forceinline__ void chol_row(Q4 (&g)[2][2], int j, int w, int tx, do
     }
 }
 
+template <int NB, int H = 0>
+__device__ __forceinline__ void chol_row_at(Q4 (&g)[NB][NB], int jh, int j, int w, int tx, double* rb, double rjj,
+                                            double inv) {
+    if constexpr (H < NB) {
+        if (jh == H) chol_row<NB, H>(g, j, w, tx, rb, rjj, inv);
+        else chol_row_at<NB, H + 1>(g, jh, j, w, tx, rb, rjj, inv);
+    }
+}
+
+template <int NB>
 __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict__ G, int w, double* __restrict__ Rout,
                                                         int* status, int* shift_out, const int* gate, int allow_shift,
                                                         double shift_scale) {
@@ -218,14 +229,15 @@ __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict_
     if (gate && *gate == 0) return;
     const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
     const int64_t ps = (int64_t)w * w;
-    Q4 g[2][2];
+    Q4 g[NB][NB];
     double shift = 0.0;
     int shifted = 0, failed = 0;
     for (int attempt = 0; attempt < 2; attempt++) {
 #pragma unroll
-        for (int ri = 0; ri < 2; ri++)
+        for (int ri = 0; ri < NB; ri++)
 #pragma unroll
-            for (int ci = 0; ci < 2; ci++) {
+            for (int ci = 0; ci < NB; ci++) {
+                if (ci < ri) continue;                 // blocks below the diagonal hold no entry a <= b
                 const int a = ty + 32 * ri, b = tx + 32 * ci;
                 Q4 v{0, 0, 0, 0};
                 if (a < w && b < w && b >= a) {
@@ -241,24 +253,28 @@ __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict_
             double* rb = rowb[j & 1];
             if (ty == jr) {
                 // the pivot (j, j) is register g[jh][jh] of lane (ty & 1) * 32 + jr of this wave
-                const double d = bcast(jh ? g[1][1].w : g[0][0].w, ((ty & 1) << 5) | jr);
+                double piv = 0.0;
+#pragma unroll
+                for (int h = 0; h < NB; h++)
+                    if (h == jh) piv = g[h][h].w;
+                const double d = bcast(piv, ((ty & 1) << 5) | jr);
                 if (!(d > 0.0) || !(d < 1e300)) {     // breakdown or non-finite pivot
                     if (tx == 0) s_fail = 1;
                 } else {
                     const double rjj = sqrt(d), inv = 1.0 / rjj;
-                    if (jh) chol_row<1>(g, j, w, tx, rb, rjj, inv);
-                    else chol_row<0>(g, j, w, tx, rb, rjj, inv);
+                    chol_row_at<NB>(g, jh, j, w, tx, rb, rjj, inv);
                 }
             }
             __syncthreads();
             if (s_fail) break;                         // uniform: read after the barrier
 #pragma unroll
-            for (int ri = 0; ri < 2; ri++) {
+            for (int ri = 0; ri < NB; ri++) {
                 const int a = ty + 32 * ri;
                 if (a <= j || a >= w) continue;
                 const Q4 rja = qconj(ldp<kRegMax>(rb, a));
 #pragma unroll
-                for (int ci = 0; ci < 2; ci++) {
+                for (int ci = 0; ci < NB; ci++) {
+                    if (ci < ri) continue;
                     const int b = tx + 32 * ci;
                     if (b < a || b >= w) continue;
                     Q4 v = qsub(g[ri][ci], qmul(rja, ldp<kRegMax>(rb, b)));
@@ -283,11 +299,11 @@ __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict_
         if (failed) atomicOr(status, 2);
     }
 #pragma unroll
-    for (int ri = 0; ri < 2; ri++)
+    for (int ri = 0; ri < NB; ri++)
 #pragma unroll
-        for (int ci = 0; ci < 2; ci++) {
+        for (int ci = 0; ci < NB; ci++) {
             const int a = ty + 32 * ri, b = tx + 32 * ci;
-            if (a < w && b < w) st4(Rout, ps, (int64_t)a * w + b, b >= a ? g[ri][ci] : Q4{0, 0, 0, 0});
+            if (a < w && b < w) st4(Rout, ps, (int64_t)a * w + b, (ci >= ri && b >= a) ? g[ri][ci] : Q4{0, 0, 0, 0});
         }
 }
 
@@ -306,39 +322,51 @@ __device__ __forceinline__ Q4 row_bcast(Q4 q) {
 
 // Q = Y R^{-1} by forward substitution along each row (q R = y): R upper triangular FP64
 // (w x w planes, ld w, w <= kRegMax), Y and Q FP32 planes (Q may alias Y).  One 16-lane group
-// per row, lane s owning columns s, s + 16, s + 32, s + 48; the finished q_t is broadcast to
-// the group and subtracted, times row t of R, from the later columns.
+// per row, lane s owning columns s + 16 u (u < NU); the finished q_t is broadcast to the group
+// and subtracted, times row t of R, from the later columns.  R's upper triangle is staged in
+// LDS packed by rows (dynamic size, w (w + 1) / 2 entries per plane).
 constexpr int kTrsmRows = 16;   // rows per 256-thread workgroup
-constexpr int kRegPacked = kRegMax * (kRegMax + 1) / 2;
-// upper triangle packed by rows: (t, c), c >= t
-__device__ __forceinline__ int upk(int t, int c) { return t * (2 * kRegMax - t + 1) / 2 + (c - t); }
+// upper triangle of order w packed by rows: (t, c), c >= t
+__device__ __forceinline__ int upk(int t, int c, int w) { return t * (2 * w - t + 1) / 2 + (c - t); }
+__device__ __forceinline__ Q4 ldr(const double* p, int ps, int i) { return Q4{p[i], p[ps + i], p[2 * ps + i], p[3 * ps + i]}; }
 
 // columns t = 16 TB + TT of the substitution: q_t = acc_t / r_tt on lane TT, broadcast over the
 // row's 16 lanes, then acc_c -= q_t r_tc for the later columns c > t.
-template <int TB, int TT>
-__device__ __forceinline__ void trsm_step(Q4 (&acc)[4], const double* sR, const double* sinv, int s, int w) {
+template <int NU, int TB, int TT>
+__device__ __forceinline__ void trsm_step(Q4 (&acc)[NU], const double* sR, int pps, const double* sinv, int s, int w) {
     constexpr int t = 16 * TB + TT;
     const Q4 q = row_bcast<TT>(qscale(acc[TB], sinv[t]));
     if (s == TT) acc[TB] = q;
 #pragma unroll
-    for (int u = TB; u < 4; u++) {
+    for (int u = TB; u < NU; u++) {
         const int c = s + 16 * u;
-        if (c > t && c < w) acc[u] = qsub(acc[u], qmul(q, ldp<kRegPacked>(sR, upk(t, c))));
+        if (c > t && c < w) acc[u] = qsub(acc[u], qmul(q, ldr(sR, pps, upk(t, c, w))));
     }
 }
-template <int TB, int TT = 0>
-__device__ __forceinline__ void trsm_block(Q4 (&acc)[4], const double* sR, const double* sinv, int s, int w) {
+template <int NU, int TB, int TT = 0>
+__device__ __forceinline__ void trsm_block(Q4 (&acc)[NU], const double* sR, int pps, const double* sinv, int s, int w) {
     if constexpr (TT < 16) {
         if (16 * TB + TT >= w) return;
-        trsm_step<TB, TT>(acc, sR, sinv, s, w);
-        trsm_block<TB, TT + 1>(acc, sR, sinv, s, w);
+        trsm_step<NU, TB, TT>(acc, sR, pps, sinv, s, w);
+        trsm_block<NU, TB, TT + 1>(acc, sR, pps, sinv, s, w);
     }
 }
+template <int NU, int TB = 0>
+__device__ __forceinline__ void trsm_all(Q4 (&acc)[NU], const double* sR, int pps, const double* sinv, int s, int w) {
+    if constexpr (TB < NU) {
+        trsm_block<NU, TB>(acc, sR, pps, sinv, s, w);
+        trsm_all<NU, TB + 1>(acc, sR, pps, sinv, s, w);
+    }
+}
+
+template <int NU>
 __global__ __launch_bounds__(256) void k_trsm(const float* Y, int64_t ldy, int64_t yps, float* Q, int64_t ldq,
                                               int64_t qps, const double* __restrict__ R, int w, int64_t rows,
                                               const int* gate) {
-    __shared__ double sR[4 * kRegPacked];   // upper triangle, packed by rows
-    __shared__ double sinv[kRegMax];
+    extern __shared__ double dyn[];
+    const int pps = w * (w + 1) / 2;
+    double* sR = dyn;               // 4 planes of pps
+    double* sinv = dyn + 4 * pps;   // w
     if (gate && *gate == 0) return;
     const int tid = threadIdx.x, s = tid & 15;
     const int64_t ps = (int64_t)w * w;
@@ -352,16 +380,19 @@ __global__ __launch_bounds__(256) void k_trsm(const float* Y, int64_t ldy, int64
         for (int u = 0; u < 8; u++) {
             const int e = base + u * 256 + tid;
             const int t = e / w, c = e - t * w;
-            if (e < n && c >= t) stp<kRegPacked>(sR, upk(t, c), v[u]);
+            if (e < n && c >= t) {
+                const int i = upk(t, c, w);
+                sR[i] = v[u].w; sR[pps + i] = v[u].x; sR[2 * pps + i] = v[u].y; sR[3 * pps + i] = v[u].z;
+            }
         }
     }
     for (int t = tid; t < w; t += 256) sinv[t] = 1.0 / R[(int64_t)t * w + t];
     __syncthreads();
     const int64_t row = (int64_t)blockIdx.x * kTrsmRows + (tid >> 4);
     const bool act = row < rows;
-    Q4 acc[4];
+    Q4 acc[NU];
 #pragma unroll
-    for (int u = 0; u < 4; u++) {
+    for (int u = 0; u < NU; u++) {
         const int c = s + 16 * u;
         acc[u] = Q4{0, 0, 0, 0};
         if (act && c < w) {
@@ -369,13 +400,10 @@ __global__ __launch_bounds__(256) void k_trsm(const float* Y, int64_t ldy, int64
             acc[u] = Q4{(double)Y[o], (double)Y[yps + o], (double)Y[2 * yps + o], (double)Y[3 * yps + o]};
         }
     }
-    trsm_block<0>(acc, sR, sinv, s, w);
-    trsm_block<1>(acc, sR, sinv, s, w);
-    trsm_block<2>(acc, sR, sinv, s, w);
-    trsm_block<3>(acc, sR, sinv, s, w);
+    trsm_all<NU>(acc, sR, pps, sinv, s, w);
     if (act) {
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
+        for (int u = 0; u < NU; u++) {
             const int c = s + 16 * u;
             if (c < w) {
                 const int64_t o = row * ldq + c;
@@ -560,8 +588,12 @@ int chol_reg_max() { return kRegMax; }
 hipError_t chol_reg_launch(const double* G, int64_t w, double* R, int* status, int* shift_out, const int* gate,
                            int allow_shift, double shift_scale, hipStream_t st) {
     if (w < 1 || w > kRegMax) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_chol_reg, dim3(1), dim3(kThreads), 0, st, G, (int)w, R, status, shift_out, gate,
-                       allow_shift, shift_scale);
+    if (w <= 64)
+        hipLaunchKernelGGL(k_chol_reg<2>, dim3(1), dim3(kThreads), 0, st, G, (int)w, R, status, shift_out, gate,
+                           allow_shift, shift_scale);
+    else
+        hipLaunchKernelGGL(k_chol_reg<3>, dim3(1), dim3(kThreads), 0, st, G, (int)w, R, status, shift_out, gate,
+                           allow_shift, shift_scale);
     return hipGetLastError();
 }
 
@@ -570,8 +602,13 @@ hipError_t trsm_launch(const float* Y, int64_t ldy, int64_t yps, float* Q, int64
     if (w < 1 || w > kRegMax || rows < 0) return hipErrorInvalidValue;
     if (rows == 0) return hipSuccess;
     const int64_t blocks = (rows + kTrsmRows - 1) / kTrsmRows;
-    hipLaunchKernelGGL(k_trsm, dim3((unsigned)blocks), dim3(256), 0, st, Y, ldy, yps, Q, ldq, qps, R, (int)w, rows,
-                       gate);
+    const size_t lds = (size_t)(4 * (w * (w + 1) / 2) + w) * sizeof(double);
+    if (w <= 64)
+        hipLaunchKernelGGL(k_trsm<4>, dim3((unsigned)blocks), dim3(256), lds, st, Y, ldy, yps, Q, ldq, qps, R, (int)w,
+                           rows, gate);
+    else
+        hipLaunchKernelGGL(k_trsm<6>, dim3((unsigned)blocks), dim3(256), lds, st, Y, ldy, yps, Q, ldq, qps, R, (int)w,
+                           rows, gate);
     return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@
 namespace qlra_impl {
 namespace {
 
-constexpr int kW = 64;                          // largest order
+constexpr int kW = 96;                          // largest order
 constexpr int kPacked = kW * (kW + 1) / 2;      // packed lower triangle, (i, t) at i (i + 1) / 2 + t
 constexpr int ET = 256;                         // eigenvalue / eigenvector workgroups
 constexpr int kPer = ET / 16;                   // eigenvalues (vectors) per workgroup, 16 lanes each
@@ -105,19 +105,30 @@ __device__ __forceinline__ double wave_total(double v) {
 // ------------------------------------------------------------------------------------------
 // 1. tridiagonalisation
 //
-// 1024 threads: row r = tid / 16 of G is held by one 16-lane DPP row, lane s owning the
-// columns c = s + 16 kk (kk = 0 .. 3), so matrix-vector products reduce on the VALU and every
-// step skips the column blocks and waves that lie left of / above the active part.
-// Step j: the wave holding row j forms the reflector from that row (the column below the
-// diagonal by Hermitian symmetry); barrier; p = tau G v per row with the wave's share of
-// K = tau/2 v^H p; barrier; the rank-2 update.  v, p and the K shares are double-buffered, so
-// the next reflector needs no third barrier.
+// Row r of G is held by LPR consecutive lanes (one DPP row of 16, or half of one), lane s owning
+// the columns c = s + LPR kk (kk < NCOL): 1024 threads x 4 columns for w <= 64, 768 threads x
+// 12 columns for w <= 96.  Matrix-vector products reduce on the VALU and every step skips the
+// column blocks and waves that lie left of / above the active part.  Step j: the wave holding
+// row j forms the reflector from that row (the column below the diagonal by Hermitian
+// symmetry); barrier; p = tau G v per row with the wave's share of K = tau/2 v^H p; barrier; the
+// rank-2 update.  v, p and the K shares are double-buffered, so the next reflector needs no
+// third barrier.
 
-constexpr int TT = 1024;
-constexpr int TW = TT / 64;                 // waves
+// sum over groups of LPR consecutive lanes (LPR = 8 or 16)
+template <int LPR>
+__device__ __forceinline__ double lpr_sum(double v) {
+    v = quad_sum(v);
+    v += dpp<0x141>(v);      // row_half_mirror: 8 lanes
+    if constexpr (LPR == 16) v += dpp<0x140>(v);   // row_mirror: 16 lanes
+    return v;
+}
 
-__global__ __launch_bounds__(TT) void k_tridiag(const double* __restrict__ Gall, int64_t gstride, int w,
-                                                double* __restrict__ triall, int store_refl) {
+template <int LPR, int NCOL>
+__global__ __launch_bounds__(LPR == 16 ? 1024 : 768)
+void k_tridiag(const double* __restrict__ Gall, int64_t gstride, int w, double* __restrict__ triall, int store_refl) {
+    constexpr int NT = LPR == 16 ? 1024 : 768;
+    constexpr int RPW = 64 / LPR;           // rows per wave
+    constexpr int TW = NT / 64;             // waves
     __shared__ double xb[4 * kW];           // column j below the diagonal
     __shared__ double vb[2][4 * kW];        // reflector v (zero outside rows j+1 .. w-1)
     __shared__ double pb[2][4 * kW];        // p = tau G v
@@ -126,15 +137,15 @@ __global__ __launch_bounds__(TT) void k_tridiag(const double* __restrict__ Gall,
     __shared__ double sq[4 * kW];           // quaternion subdiagonal s_j
     __shared__ double dg[kW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int r = tid >> 4, s = tid & 15;
+    const int r = tid / LPR, s = tid % LPR;
     const double* G = Gall + (int64_t)blockIdx.x * gstride;
     double* tri = triall + (int64_t)blockIdx.x * kTriStride;
     const int64_t gps = (int64_t)w * w;
 
-    Q4 g[4];
+    Q4 g[NCOL];
 #pragma unroll
-    for (int kk = 0; kk < 4; kk++) {
-        const int c = s + 16 * kk;
+    for (int kk = 0; kk < NCOL; kk++) {
+        const int c = s + LPR * kk;
         Q4 v{0, 0, 0, 0};
         if (r < w && c < w) {
             const int64_t e = (int64_t)r * w + c;
@@ -148,29 +159,35 @@ __global__ __launch_bounds__(TT) void k_tridiag(const double* __restrict__ Gall,
         const int bsel = j & 1;
         double* vbj = vb[bsel];
         double* pbj = pb[bsel];
-        const int kk0 = (j + 1) >> 4;                          // first column block with c > j
-        if (wave == (j >> 2)) {
+        if (wave == j / RPW) {
             // the row-j lanes publish x_c = G(c, j) = conj(G(j, c)), c > j
             if (r == j) {
 #pragma unroll
-                for (int kk = 0; kk < 4; kk++) {
-                    const int c = s + 16 * kk;
-                    if (kk >= kk0 && c > j && c < w) stq<kW>(xb, c, qconj(g[kk]));
+                for (int kk = 0; kk < NCOL; kk++) {
+                    const int c = s + LPR * kk;
+                    if (LPR * kk + LPR - 1 <= j) continue;     // uniform
+                    if (c > j && c < w) stq<kW>(xb, c, qconj(g[kk]));
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // lane handles entries lane and lane + 64
+            const int c1 = lane + 64;
             const Q4 x = (lane > j && lane < w) ? ldq<kW>(xb, lane) : Q4{0, 0, 0, 0};
-            const double alpha = sqrt(wave_total(qn2(x)));
+            const Q4 x2 = (c1 > j && c1 < w) ? ldq<kW>(xb, c1) : Q4{0, 0, 0, 0};
+            const double alpha = sqrt(wave_total(qn2(x) + qn2(x2)));
             const Q4 x1 = ldq<kW>(xb, j + 1);
             const double ax1 = sqrt(qn2(x1));
             const Q4 phi = ax1 > 0.0 ? qscale(x1, 1.0 / ax1) : Q4{1, 0, 0, 0};
             const double tau = alpha > 0.0 ? 1.0 / (alpha * (alpha + ax1)) : 0.0;
-            Q4 v = x;
+            Q4 v = x, v2 = x2;
             if (lane == j + 1) v = qadd(x, qscale(phi, alpha));   // H x = -alpha phi e_1
+            if (c1 == j + 1) v2 = qadd(x2, qscale(phi, alpha));
             stq<kW>(vbj, lane, v);
+            if (c1 < kW) stq<kW>(vbj, c1, v2);
             if (store_refl && lane > j && lane < w) stq<kPacked>(tri + OFF_REFL, lane * (lane + 1) / 2 + j, v);
+            if (store_refl && c1 > j && c1 < w) stq<kPacked>(tri + OFF_REFL, c1 * (c1 + 1) / 2 + j, v2);
             if (lane == 0) {
                 tb[bsel] = tau;
                 stq<kW>(sq, j, qscale(phi, -alpha));
@@ -179,37 +196,41 @@ __global__ __launch_bounds__(TT) void k_tridiag(const double* __restrict__ Gall,
         }
         __syncthreads();
         const double tau = tb[bsel];
-        const bool wave_live = 4 * wave + 3 > j;                // some row of this wave is active
+        const bool wave_live = RPW * wave + RPW - 1 > j;        // some row of this wave is active
         if (wave_live) {
-            Q4 vc[4];
-#pragma unroll
-            for (int kk = 0; kk < 4; kk++) vc[kk] = kk >= kk0 ? ldq<kW>(vbj, s + 16 * kk) : Q4{0, 0, 0, 0};
             Q4 acc{0, 0, 0, 0};
 #pragma unroll
-            for (int kk = 0; kk < 4; kk++)
-                if (kk >= kk0) acc = qadd(acc, qmul(g[kk], vc[kk]));
-            acc.w = row_sum(acc.w); acc.x = row_sum(acc.x); acc.y = row_sum(acc.y); acc.z = row_sum(acc.z);
+            for (int kk = 0; kk < NCOL; kk++) {
+                if (LPR * kk + LPR - 1 <= j) continue;          // v vanishes there
+                acc = qadd(acc, qmul(g[kk], ldq<kW>(vbj, s + LPR * kk)));
+            }
+            acc.w = lpr_sum<LPR>(acc.w); acc.x = lpr_sum<LPR>(acc.x);
+            acc.y = lpr_sum<LPR>(acc.y); acc.z = lpr_sum<LPR>(acc.z);
             const Q4 p = qscale(acc, tau);
             double kp = 0.0;
             if (s == 0 && r < w) {
                 stq<kW>(pbj, r, p);
                 if (r > j) kp = qdot(ldq<kW>(vbj, r), p);
             }
-            kp = bcast(kp, 0) + bcast(kp, 16) + bcast(kp, 32) + bcast(kp, 48);
-            if (lane == 0) kr[bsel][wave] = kp;
+            double ks = 0.0;
+#pragma unroll
+            for (int q = 0; q < RPW; q++) ks += bcast(kp, q * LPR);
+            if (lane == 0) kr[bsel][wave] = ks;
         } else if (lane == 0) {
             kr[bsel][wave] = 0.0;
         }
         __syncthreads();
         if (wave_live) {
-            const double K = 0.5 * tau * row_sum(kr[bsel][s]);
+            double kq = 0.0;
+            for (int q = s; q < TW; q += LPR) kq += kr[bsel][q];
+            const double K = 0.5 * tau * lpr_sum<LPR>(kq);
             const bool row_live = r > j && r < w;
             const Q4 vr = ldq<kW>(vbj, r);
             const Q4 qr = qsub(ldq<kW>(pbj, r), qscale(vr, K));
 #pragma unroll
-            for (int kk = 0; kk < 4; kk++) {
-                const int c = s + 16 * kk;
-                if (kk < kk0) continue;                         // uniform
+            for (int kk = 0; kk < NCOL; kk++) {
+                const int c = s + LPR * kk;
+                if (LPR * kk + LPR - 1 <= j) continue;          // uniform
                 const Q4 vc = ldq<kW>(vbj, c);
                 const Q4 qc = qsub(ldq<kW>(pbj, c), qscale(vc, K));
                 if (row_live && c > j && c < w) {
@@ -222,8 +243,8 @@ __global__ __launch_bounds__(TT) void k_tridiag(const double* __restrict__ Gall,
     }
     // diagonal and the last subdiagonal entry s_{w-2} = G(w-1, w-2)
 #pragma unroll
-    for (int kk = 0; kk < 4; kk++) {
-        const int c = s + 16 * kk;
+    for (int kk = 0; kk < NCOL; kk++) {
+        const int c = s + LPR * kk;
         if (r < w && c == r) dg[r] = g[kk].w;
         if (w >= 2 && r == w - 1 && c == w - 2) stq<kW>(sq, w - 2, g[kk]);
     }
@@ -261,8 +282,9 @@ __global__ __launch_bounds__(TT) void k_tridiag(const double* __restrict__ Gall,
 
 // Number of eigenvalues of T below x: sign changes of the Sturm sequence p_0 = 1,
 // p_1 = d_0 - x, p_i = (d_{i-1} - x) p_{i-1} - b_{i-2}^2 p_{i-2}.  Lane i of the wave holds d_i
-// and b_i^2, scaled so that |d_i - x| <= 2 and b_i^2 <= 4: |p| grows at most 6-fold per step,
-// so a rescale every fourth step keeps it in range, and only one FMA per step is on the chain.
+// and b_i^2 in (dv, b2v) and d_{64+i}, b_{64+i}^2 in (dv2, b2v2), scaled so that |d_i - x| <= 2
+// and b_i^2 <= 4: |p| grows at most 6-fold per step, so a rescale every fourth step keeps it in
+// range, and only one FMA per step is on the chain.
 __device__ __forceinline__ void sturm_step(double di, double bi, double x, double& pm, double& pc, int& prev,
                                            int& cnt) {
     const double pn = fma(di - x, pc, -bi * pm);
@@ -275,20 +297,37 @@ __device__ __forceinline__ void sturm_step(double di, double bi, double x, doubl
     prev = neg;
 }
 
-__device__ int sturm_count(double dv, double b2v, int w, double x) {
+__device__ __forceinline__ void sturm_rescale(double& pm, double& pc) {
+    const double a = fmax(fabs(pc), fabs(pm));
+    const double sc = a > 1e150 ? 1e-150 : (a < 1e-150 ? 1e150 : 1.0);
+    pc *= sc;
+    pm *= sc;
+}
+
+__device__ int sturm_count(double dv, double dv2, double b2v, double b2v2, int w, double x) {
     double pm = 1.0, pc = bcast(dv, 0) - x;
     int prev = pc < 0.0 ? 1 : 0;
     int cnt = prev;
+    const int w1 = w < 64 ? w : 64;
     int i = 1;
-    for (; i + 3 < w; i += 4) {
+    for (; i + 3 < w1; i += 4) {
 #pragma unroll
         for (int u = 0; u < 4; u++) sturm_step(bcast(dv, i + u), bcast(b2v, i + u - 1), x, pm, pc, prev, cnt);
-        const double a = fmax(fabs(pc), fabs(pm));
-        const double sc = a > 1e150 ? 1e-150 : (a < 1e-150 ? 1e150 : 1.0);
-        pc *= sc;
-        pm *= sc;
+        sturm_rescale(pm, pc);
     }
-    for (; i < w; i++) sturm_step(bcast(dv, i), bcast(b2v, i - 1), x, pm, pc, prev, cnt);
+    for (; i < w1; i++) sturm_step(bcast(dv, i), bcast(b2v, i - 1), x, pm, pc, prev, cnt);
+    if (w > 64) {
+        sturm_rescale(pm, pc);
+        sturm_step(bcast(dv2, 0), bcast(b2v, 63), x, pm, pc, prev, cnt);
+        i = 65;
+        for (; i + 3 < w; i += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                sturm_step(bcast(dv2, i + u - 64), bcast(b2v2, i + u - 65), x, pm, pc, prev, cnt);
+            sturm_rescale(pm, pc);
+        }
+        for (; i < w; i++) sturm_step(bcast(dv2, i - 64), bcast(b2v2, i - 65), x, pm, pc, prev, cnt);
+    }
     return cnt;
 }
 
@@ -303,11 +342,13 @@ __global__ __launch_bounds__(ET) void k_eigvals(double* __restrict__ triall, int
     frexp(fmax(fabs(tri[OFF_BND]), fabs(tri[OFF_BND + 1])), &ex);
     const double dv = lane < w ? ldexp(tri[OFF_D + lane], -ex) : 0.0;
     const double b2v = lane < w ? ldexp(tri[OFF_B2 + lane], -2 * ex) : 0.0;
+    const double dv2 = lane + 64 < w ? ldexp(tri[OFF_D + 64 + lane], -ex) : 0.0;
+    const double b2v2 = lane + 64 < w ? ldexp(tri[OFF_B2 + 64 + lane], -2 * ex) : 0.0;
     const int k = blockIdx.x * kPer + (tid >> 4);          // ascending index
     double a = ldexp(tri[OFF_BND], -ex), bb = ldexp(tri[OFF_BND + 1], -ex);
     for (int round = 0; round < kRounds; round++) {
         const double x = a + (bb - a) * (double)(s16 + 1) / 17.0;
-        const int c = sturm_count(dv, b2v, w, x);
+        const int c = sturm_count(dv, dv2, b2v, b2v2, w, x);
         const unsigned long long m = __ballot(c > k);
         const unsigned grp = (unsigned)((m >> (lane & ~15)) & 0xFFFFull);
         const int first = grp ? __builtin_ctz(grp) : 16;    // first section point above eigenvalue k
@@ -329,7 +370,6 @@ __global__ __launch_bounds__(ET) void k_eigvals(double* __restrict__ triall, int
 // 3. eigenvectors
 
 struct VecLds {
-    double refl[4 * kPacked];
     double ph[4 * kW];
     double dg[kW], b[kW], b2[kW], lam[kW], tau[kW];
     double X[kW * kW];        // eigenvectors of T, ascending index k at X + k * kW
@@ -354,23 +394,6 @@ __device__ __forceinline__ double fdiv(double x, double y) {
 __global__ __launch_bounds__(ET) void k_eigvecs(const double* __restrict__ tri, int w, double* __restrict__ E) {
     __shared__ VecLds L;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int np = w * (w + 1) / 2;
-    for (int base = 0; base < np; base += 4 * ET) {
-        double v[4][4];
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const int e = min(base + u * ET + tid, np - 1);
-#pragma unroll
-            for (int p = 0; p < 4; p++) v[u][p] = tri[OFF_REFL + p * kPacked + e];
-        }
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const int e = base + u * ET + tid;
-            if (e < np)
-#pragma unroll
-                for (int p = 0; p < 4; p++) L.refl[p * kPacked + e] = v[u][p];
-        }
-    }
     for (int i = tid; i < w; i += ET) {
         L.dg[i] = tri[OFF_D + i];
         L.b[i] = tri[OFF_B + i];
@@ -468,27 +491,43 @@ __global__ __launch_bounds__(ET) void k_eigvecs(const double* __restrict__ tri, 
         }
     }
     __syncthreads();
-    // back-transformation y = H_0 ... H_{w-3} D x: one wave per eigenvector, lane i = row i,
-    // the reflector of the next step loaded while the current one is applied
+    // back-transformation y = H_0 ... H_{w-3} D x: one wave per eigenvector, lane i holding rows
+    // i and i + 64; the reflectors are read from the record (L2), the next step's while the
+    // current one is applied
     const int k = k0 + wave;
     if (k >= k1) return;                                   // uniform per wave
-    const int i = lane;
-    Q4 y{0, 0, 0, 0};
+    const int i = lane, i2 = lane + 64;
+    Q4 y{0, 0, 0, 0}, y2{0, 0, 0, 0};
     if (i < w) y = qscale(ldq<kW>(L.ph, i), L.X[k * kW + i]);
-    auto refl = [&](int j) { return (i > j && i < w) ? ldq<kPacked>(L.refl, i * (i + 1) / 2 + j) : Q4{0, 0, 0, 0}; };
-    Q4 vn = w >= 3 ? refl(w - 3) : Q4{0, 0, 0, 0};
+    if (i2 < w) y2 = qscale(ldq<kW>(L.ph, i2), L.X[k * kW + i2]);
+    const double* refl = tri + OFF_REFL;
+    auto rv = [&](int row, int j) {
+        return (row > j && row < w) ? ldq<kPacked>(refl, row * (row + 1) / 2 + j) : Q4{0, 0, 0, 0};
+    };
+    Q4 vn = w >= 3 ? rv(i, w - 3) : Q4{0, 0, 0, 0};
+    Q4 vn2 = w >= 3 ? rv(i2, w - 3) : Q4{0, 0, 0, 0};
     for (int j = w - 3; j >= 0; j--) {
-        const Q4 v = vn;
-        if (j > 0) vn = refl(j - 1);
+        const Q4 v = vn, v2 = vn2;
+        if (j > 0) {
+            vn = rv(i, j - 1);
+            vn2 = rv(i2, j - 1);
+        }
         const double tj = L.tau[j];
-        Q4 s = qmul(qconj(v), y);
+        Q4 s = qadd(qmul(qconj(v), y), qmul(qconj(v2), y2));
         s.w = wave_total(s.w); s.x = wave_total(s.x); s.y = wave_total(s.y); s.z = wave_total(s.z);
-        y = qsub(y, qmul(v, qscale(s, tj)));
+        s = qscale(s, tj);
+        y = qsub(y, qmul(v, s));
+        y2 = qsub(y2, qmul(v2, s));
     }
+    const int64_t gps = (int64_t)w * w;
+    const int col = w - 1 - k;
     if (i < w) {
-        const int64_t gps = (int64_t)w * w;
-        const int64_t o = (int64_t)i * w + (w - 1 - k);
+        const int64_t o = (int64_t)i * w + col;
         E[o] = y.w; E[gps + o] = y.x; E[2 * gps + o] = y.y; E[3 * gps + o] = y.z;
+    }
+    if (i2 < w) {
+        const int64_t o = (int64_t)i2 * w + col;
+        E[o] = y2.w; E[gps + o] = y2.x; E[2 * gps + o] = y2.y; E[3 * gps + o] = y2.z;
     }
 }
 
@@ -596,7 +635,10 @@ size_t heig_work_doubles(int64_t nprob) { return (size_t)nprob * kTriStride; }
 
 hipError_t heig_launch(const double* G, int64_t w, double* lam, double* E, double* work, hipStream_t st) {
     if (w < 1 || w > kW) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(TT), 0, st, G, (int64_t)0, (int)w, work, E ? 1 : 0);
+    if (w <= 64)
+        hipLaunchKernelGGL((k_tridiag<16, 4>), dim3(1), dim3(1024), 0, st, G, (int64_t)0, (int)w, work, E ? 1 : 0);
+    else
+        hipLaunchKernelGGL((k_tridiag<8, 12>), dim3(1), dim3(768), 0, st, G, (int64_t)0, (int)w, work, E ? 1 : 0);
     const unsigned slices = (unsigned)((w + kPer - 1) / kPer);
     hipLaunchKernelGGL(k_eigvals, dim3(slices, 1), dim3(ET), 0, st, work, (int)w, lam, (int64_t)0);
     if (E)
@@ -609,7 +651,10 @@ hipError_t estimate_batch_launch(const double* G, int64_t gstride, int64_t w, in
                                  double* e, double* work, hipStream_t st) {
     if (nprob <= 0) return hipSuccess;
     if (w < 1 || w > kW) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_tridiag, dim3((unsigned)nprob), dim3(TT), 0, st, G, gstride, (int)w, work, 0);
+    if (w <= 64)
+        hipLaunchKernelGGL((k_tridiag<16, 4>), dim3((unsigned)nprob), dim3(1024), 0, st, G, gstride, (int)w, work, 0);
+    else
+        hipLaunchKernelGGL((k_tridiag<8, 12>), dim3((unsigned)nprob), dim3(768), 0, st, G, gstride, (int)w, work, 0);
     const unsigned slices = (unsigned)((w + kPer - 1) / kPer);
     hipLaunchKernelGGL(k_eigvals, dim3(slices, (unsigned)nprob), dim3(ET), 0, st, work, (int)w, (double*)nullptr,
                        (int64_t)0);

@@ -665,7 +665,7 @@ hipError_t launch_lp(const QgemmDesc& d, const LpPlan& pl, void* scratch, hipStr
     if (pl.CN == CN_) \
         hipLaunchKernelGGL((k_qgemm_lp<TL, ADJ, CN_, lp_ncg(CN_), lp_cnw(CN_)>), grid, dim3(256 * lp_ncg(CN_)), 0, st, P); \
     else
-    QL_LP(1) QL_LP(2) QL_LP(3) QL_LP(4) QL_LP(5) return hipErrorInvalidValue;
+    QL_LP(1) QL_LP(2) QL_LP(3) QL_LP(4) QL_LP(5) QL_LP(6) return hipErrorInvalidValue;
 #undef QL_LP
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || pl.splits == 1) return e;
@@ -695,7 +695,7 @@ size_t qgemm_counter_count(const QgemmDesc&) { return 0; }
 hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t st) {
     if (d.M <= 0 || d.N <= 0) return hipSuccess;
     if (d.math == MATH_BF16 || d.math == MATH_F16) {
-        if (d.b_f64 || d.c_f64 || d.store != ST_SET || d.N > 80 || !s.partial) return hipErrorInvalidValue;
+        if (d.b_f64 || d.c_f64 || d.store != ST_SET || d.N > 96 || !s.partial) return hipErrorInvalidValue;
         const LpPlan lp = make_lp_plan(d);
         if (d.math == MATH_BF16)
             return d.op == OP_HN ? launch_lp<__bf16, true>(d, lp, s.partial, st) : launch_lp<__bf16, false>(d, lp, s.partial, st);

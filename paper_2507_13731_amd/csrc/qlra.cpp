@@ -536,7 +536,7 @@ int check_problem(const Problem& pr) {
     if (pr.v > 64) return QLRA_E_TOO_LARGE;
     if (pr.prec != QLRA_FP32 && pr.prec != QLRA_BF16 && pr.prec != QLRA_FP16) return QLRA_E_UNSUPPORTED;
     // the low-precision view kernel keeps all output columns of a view in one workgroup
-    if (pr.prec != QLRA_FP32 && pr.v > 2 && (int64_t)pr.k + pr.p > 80) return QLRA_E_UNSUPPORTED;
+    if (pr.prec != QLRA_FP32 && pr.v > 2 && (int64_t)pr.k + pr.p > 96) return QLRA_E_UNSUPPORTED;
     return QLRA_OK;
 }
 
@@ -966,7 +966,7 @@ static QgemmDesc lp_desc(int op, int precision, const void* Alo, int64_t m, int6
 }
 
 int qlra_qgemm_lp_workspace_size(int op, int precision, int64_t m, int64_t n, int64_t w, size_t* bytes) {
-    if (!bytes || (op != 0 && op != 1) || m < 0 || n < 0 || w < 0 || w > 80) return QLRA_E_ARG;
+    if (!bytes || (op != 0 && op != 1) || m < 0 || n < 0 || w < 0 || w > 96) return QLRA_E_ARG;
     if (precision != QLRA_BF16 && precision != QLRA_FP16) return QLRA_E_ARG;
     const QgemmDesc d = lp_desc(op, precision, nullptr, m, n, nullptr, w, w, 0, nullptr, w, 0, nullptr);
     *bytes = (m * n * w == 0) ? 0 : qgemm_partial_bytes(d);

@@ -100,7 +100,7 @@ def test_qgemm_config1_view_sampled(gq, oracle):
 
 
 @pytest.mark.parametrize("m,w", [(37, 1), (500, 15), (333, 33), (2048, 60), (1001, 64), (64, 64), (1024, 80), (80, 80),
-                                 (3000, 160)])
+                                 (777, 96), (500, 97), (3000, 160)])
 def test_cholqr_matches_householder(gq, oracle, m, w):
     print(f"cholqr m={m} w={w}", flush=True)
     rng = np.random.default_rng(m + w)
@@ -135,7 +135,7 @@ def test_cholqr_rank_deficient_uses_shift(gq, oracle):
     assert (flags[0] & 2) == 0    # and the factorization did not fail
 
 
-@pytest.mark.parametrize("w", [1, 2, 15, 60, 81])
+@pytest.mark.parametrize("w", [1, 2, 15, 60, 64, 65, 81, 96, 97])
 def test_qsvd_against_oracle(gq, oracle, w):
     print(f"qsvd w={w}", flush=True)
     R = W.random_quat(w + 1000, w, w)
@@ -151,7 +151,7 @@ def test_qsvd_against_oracle(gq, oracle, w):
 
 def test_qsvd_upper_triangular_graded(gq, oracle):
     """The solve feeds the QSVD upper triangular R factors with graded diagonals.  For
-    w <= 64 the GPU takes the QSVD from the eigendecomposition of R^H R, whose eigenvalues
+    w <= 96 the GPU takes the QSVD from the eigendecomposition of R^H R, whose eigenvalues
     carry an absolute error ~ eps sigma_1^2: sigma_j is then accurate to
     ~ eps sigma_1^2 / sigma_j, and to ~ sqrt(eps) sigma_1 for the tiniest ones."""
     w = 40

@@ -92,7 +92,7 @@ def test_lowp_copy_bit_exact(gq, prec, m, n):
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 @pytest.mark.parametrize("op", [0, 1])
-@pytest.mark.parametrize("m,n,w", [(300, 200, 15), (512, 1024, 60), (1000, 777, 80), (64, 2048, 1)])
+@pytest.mark.parametrize("m,n,w", [(300, 200, 15), (512, 1024, 60), (1000, 777, 80), (640, 900, 96), (64, 2048, 1)])
 def test_qgemm_lp_against_rounded_oracle(gq, oracle, prec, op, m, n, w):
     import torch
     print(f"qgemm_lp {prec} op={op} {m}x{n} w={w}", flush=True)
