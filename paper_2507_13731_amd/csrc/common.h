@@ -134,9 +134,17 @@ hipError_t heig_launch(const double* G, int64_t w, double* lam, double* E, doubl
 hipError_t qsvd_gram_launch(const double* X, int64_t w, double* U, double* S, double* V, double* work,
                             hipStream_t st);
 size_t qsvd_gram_work_doubles(int64_t w);
-// S_j = sqrt(max(lam_j, 0)) (j < k) and Wk = E[:, :k] diag(1 / S) (w x k FP64 planes, ld k),
-// from lam (descending) and E (w x w, ld w) of a Gram's eigendecomposition.
-hipError_t svals_launch(const double* lam, const double* E, int64_t w, int k, double* S, double* Wk, hipStream_t st);
+// S_j = sqrt(max(lam_j, 0)) (j < k) and, when E is given, Wk = E[:, :k] diag(1 / S) (w x k FP64
+// planes, ld k), from lam (descending) and E (w x >= k, ld lde) of a Gram's eigendecomposition.
+hipError_t svals_launch(const double* lam, const double* E, int64_t lde, int64_t w, int k, double* S, double* Wk,
+                        hipStream_t st);
+// Larger orders (up to heig_big_max()): lam (W, descending) and, if E, the nout eigenvectors of
+// the largest eigenvalues (W x nout, ld nout).  work: heig_big_work_doubles(W, nvec) doubles with
+// nvec >= nout vector slots (0 without vectors).
+int heig_big_max();
+size_t heig_big_work_doubles(int64_t W, int64_t nvec);
+hipError_t heig_big_launch(const double* G, int64_t W, double* lam, double* E, int64_t nout, double* work,
+                           int64_t nvec, hipStream_t st);
 // Estimates of nprob problems from their Grams (problem b at G + b * gstride, w <= heig_max()):
 // e[b] = sqrt(max(0, nA2 - sum of the k largest eigenvalues of G_b) / nA2).
 // work: heig_work_doubles(nprob).

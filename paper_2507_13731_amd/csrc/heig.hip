@@ -601,15 +601,16 @@ __global__ __launch_bounds__(256) void k_left_vectors(const double* __restrict__
 
 // From the eigendecomposition G = E diag(lam) E^H of a view's Gram Y^H Y (lam descending):
 // S_j = sqrt(max(lam_j, 0)) and W = E_k diag(1 / S) (w x k, ld k; zero columns where S_j = 0).
-__global__ __launch_bounds__(256) void k_svals(const double* __restrict__ lam, const double* __restrict__ E, int w,
-                                               int k, double* __restrict__ S, double* __restrict__ Wk) {
+__global__ __launch_bounds__(256) void k_svals(const double* __restrict__ lam, const double* __restrict__ E,
+                                               int64_t lde, int w, int k, double* __restrict__ S,
+                                               double* __restrict__ Wk) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < k) S[e] = sqrt(fmax(lam[e], 0.0));
-    if (e >= (int64_t)w * k) return;
+    if (!E || e >= (int64_t)w * k) return;
     const int i = (int)(e / k), j = (int)(e % k);
     const double sj = sqrt(fmax(lam[j], 0.0));
     const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
-    const int64_t eps = (int64_t)w * w, wps = (int64_t)w * k, src = (int64_t)i * w + j;
+    const int64_t eps = (int64_t)w * lde, wps = (int64_t)w * k, src = (int64_t)i * lde + j;
 #pragma unroll
     for (int p = 0; p < 4; p++) Wk[p * wps + e] = E[p * eps + src] * inv;
 }
@@ -683,9 +684,10 @@ hipError_t qsvd_gram_launch(const double* X, int64_t w, double* U, double* S, do
     return hipGetLastError();
 }
 
-hipError_t svals_launch(const double* lam, const double* E, int64_t w, int k, double* S, double* Wk, hipStream_t st) {
+hipError_t svals_launch(const double* lam, const double* E, int64_t lde, int64_t w, int k, double* S, double* Wk,
+                        hipStream_t st) {
     const int64_t n = std::max<int64_t>(w * k, k);
-    hipLaunchKernelGGL(k_svals, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, lam, E, (int)w, k, S, Wk);
+    hipLaunchKernelGGL(k_svals, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, lam, E, lde, (int)w, k, S, Wk);
     return hipGetLastError();
 }
 

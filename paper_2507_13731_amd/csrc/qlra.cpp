@@ -86,6 +86,10 @@ QgemmDesc desc(QOp op, QMath math, const void* A, int64_t lda, int64_t aps, int 
     return d;
 }
 
+// eigenvector slots of the large-order solver: the k wanted ones and as many again below them,
+// so that a cluster reaching under the k-th eigenvalue is orthogonalised whole
+int64_t big_nvec(int64_t w, int64_t k) { return std::min<int64_t>(w, 2 * k); }
+
 double shift_scale(int64_t rows, int64_t w) {
     // Shifted CholeskyQR (Fukaya, Kannan, Nakatsukasa, Yamamoto, Yanagisawa 2020):
     // s = 11 (m w + w (w + 1)) u ||Y||_2^2, with ||Y||_F^2 = trace(Y^H Y) as the bound.
@@ -215,6 +219,8 @@ struct Bufs {
     double* side_S; double* side_work;
     double* Gs;             // Grams of views 2 .. v-1, (v - 2) x (l x l)
     double* est_work;
+    double* side_lam;       // l eigenvalues (estimates from the large-order solver)
+    double* big_work;       // the large-order eigensolver of the final view
     void* Alo; void* Alo_t;  // low-precision copies of A and A^T (views 1 .. v-2)
     float* lp_scale;        // [scale, 1 / scale]
     void* partial;
@@ -245,12 +251,23 @@ void carve(const Problem& pr, const Dims& d, Arena& ar, Bufs& b, size_t part_byt
     b.Rh = (double*)ar.take(4 * w2 * sizeof(double));
     b.Sw = (double*)ar.take(d.wmax * sizeof(double));
     b.qsvd_work = (double*)ar.take(qsvd_work_doubles(d.wmax) * sizeof(double));
-    const bool batched = d.l <= heig_max();
+    // estimates from the Grams of views 2 .. v-1: batched for l <= heig_max(), one after another
+    // with the large-order solver up to heig_big_max(), otherwise from R by the Jacobi QSVD
+    const bool batched = d.l <= heig_big_max();
+    const bool small_l = d.l <= heig_max();
     const int64_t nest = pr.v > 2 ? pr.v - 2 : 0;
-    b.side_S = batched ? nullptr : (double*)ar.take(d.l * sizeof(double));
+    b.side_S = (double*)ar.take(d.l * sizeof(double));
+    b.side_lam = (double*)ar.take(d.l * sizeof(double));
     b.side_work = batched ? nullptr : (double*)ar.take(qsvd_work_doubles(d.l) * sizeof(double));
     b.Gs = batched && nest ? (double*)ar.take((size_t)nest * 4 * l2 * sizeof(double)) : nullptr;
-    b.est_work = batched && nest ? (double*)ar.take(heig_work_doubles(nest) * sizeof(double)) : nullptr;
+    b.est_work = batched && nest ? (double*)ar.take((small_l ? heig_work_doubles(nest) : heig_big_work_doubles(d.l, 0)) *
+                                                    sizeof(double))
+                                 : nullptr;
+    // the final QSVD of a view wider than heig_max()
+    const int64_t wf = d.krylov ? d.Wk : d.l;
+    b.big_work = (wf > heig_max() && wf <= heig_big_max())
+                     ? (double*)ar.take(heig_big_work_doubles(wf, big_nvec(wf, pr.k)) * sizeof(double))
+                     : nullptr;
     const bool lowp = pr.prec != QLRA_FP32 && pr.v > 2;
     b.Alo = lowp ? ar.take(lowp_copy_elems(pr.m, pr.n) * 2) : nullptr;
     b.Alo_t = lowp ? ar.take(lowp_copy_elems(pr.n, pr.m) * 2) : nullptr;
@@ -321,13 +338,22 @@ double* gram_slot(const Bufs& b, const Problem& pr, int64_t l, int i) {
     return b.Gs + (size_t)(i - 2) * 4 * l * l;
 }
 
-// Estimates of views 2 .. v-1 from their Grams, one batched launch on the side stream.
+// Estimates of views 2 .. v-1 from their Grams on the side stream: one batched launch, or the
+// large-order solver (values only) one Gram after another.
 void fork_estimates(Ctx& c, const Bufs& b, const Problem& pr, int64_t l) {
     if (!c.live() || !pr.estimate || !b.Gs) return;
     c.forked = true;
     note(c, hipEventRecord(c.ev_fork, c.st));
     note(c, hipStreamWaitEvent(c.side, c.ev_fork, 0));
-    note(c, estimate_batch_launch(b.Gs, 4 * l * l, l, pr.v - 2, pr.k, b.nA2, pr.pass_err + 1, b.est_work, c.side));
+    if (l <= heig_max()) {
+        note(c, estimate_batch_launch(b.Gs, 4 * l * l, l, pr.v - 2, pr.k, b.nA2, pr.pass_err + 1, b.est_work, c.side));
+        return;
+    }
+    for (int i = 0; i < pr.v - 2; i++) {
+        note(c, heig_big_launch(b.Gs + (size_t)i * 4 * l * l, l, b.side_lam, nullptr, 0, b.est_work, 0, c.side));
+        note(c, svals_launch(b.side_lam, nullptr, 0, l, pr.k, b.side_S, nullptr, c.side));
+        note(c, estimate_launch(b.side_S, pr.k, b.nA2, pr.pass_err + 1 + i, c.side));
+    }
 }
 
 // Side-stream estimate of view `i` (1-based) from its R (l x l), for widths above the batched
@@ -365,14 +391,17 @@ void finish(Ctx& c, const Bufs& b, const Problem& pr, const double* R, int64_t w
 // QSVD of R (Alg. 2 and Alg. 4, last lines) follows from the eigendecomposition
 // Y^H Y = E diag(lam) E^H: S = sqrt(lam_k), the Y-side factor Q Uh = Y E_k S^{-1} and the
 // X-side factor X E_k.  y_is_u: odd budget (Y = A Q2 gives U, X = Q2 gives V); otherwise Y gives
-// V and X = Q1 gives U.  For w <= heig_max().
+// V and X = Q1 gives U.  For w <= heig_big_max() (the single-workgroup solver up to heig_max()).
 void finish_gram(Ctx& c, const Bufs& b, const Problem& pr, const float* Y, int64_t rows_y, const float* X,
                  int64_t ldx, int64_t rows_x, int64_t w, bool y_is_u) {
     const int k = pr.k;
+    const bool big = w > heig_max();
+    const int64_t lde = big ? k : w;     // eigenvectors in b.Rh: all w, or the k largest
     qg(c, desc(OP_HN, MATH_F64, Y, w, rows_y * w, 0, Y, w, rows_y * w, 0, c.G, w, w * w, 1, w, w, rows_y));
     if (c.live()) {
-        note(c, heig_launch(c.G, w, b.Sw, b.Rh, b.qsvd_work, c.st));
-        note(c, svals_launch(b.Sw, b.Rh, w, k, pr.S, b.Lh, c.st));
+        if (big) note(c, heig_big_launch(c.G, w, b.Sw, b.Rh, k, b.big_work, big_nvec(w, k), c.st));
+        else note(c, heig_launch(c.G, w, b.Sw, b.Rh, b.qsvd_work, c.st));
+        note(c, svals_launch(b.Sw, b.Rh, lde, w, k, pr.S, b.Lh, c.st));
         if (pr.estimate) note(c, estimate_launch(pr.S, k, b.nA2, pr.pass_err + (pr.v - 1), c.st));
     }
     float* Oy = y_is_u ? pr.U : pr.V;
@@ -380,7 +409,7 @@ void finish_gram(Ctx& c, const Bufs& b, const Problem& pr, const float* Y, int64
     const int64_t ldoy = y_is_u ? pr.ldu : pr.ldv, psoy = y_is_u ? pr.ups : pr.vps;
     const int64_t ldox = y_is_u ? pr.ldv : pr.ldu, psox = y_is_u ? pr.vps : pr.ups;
     qg(c, desc(OP_NN, MATH_F64, Y, w, rows_y * w, 0, b.Lh, k, w * k, 1, Oy, ldoy, psoy, 0, rows_y, k, w));
-    qg(c, desc(OP_NN, MATH_F64, X, ldx, rows_x * ldx, 0, b.Rh, w, w * w, 1, Ox, ldox, psox, 0, rows_x, k, w));
+    qg(c, desc(OP_NN, MATH_F64, X, ldx, rows_x * ldx, 0, b.Rh, lde, w * lde, 1, Ox, ldox, psox, 0, rows_x, k, w));
     if (c.live()) note(c, phase_launch(pr.U, pr.m, pr.ldu, pr.ups, pr.V, pr.n, pr.ldv, pr.vps, k, c.st));
 }
 
@@ -429,7 +458,7 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
     const float* Q2cur = b.Om;
     if (!d.krylov) {
         // Alg. 2: odd views [Q1, R1] = QR(A Q2), even views [Q2, R2] = QR(A^H Q1)
-        const bool gram_final = l <= heig_max();
+        const bool gram_final = l <= heig_big_max();
         for (int i = 1; i <= pr.v; i++) {
             if (i == pr.v && gram_final) {
                 fork_estimates(c, b, pr, l);
@@ -481,7 +510,7 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
         stack_in(b.Q1, d.s);
         fork_estimates(c, b, pr, l);
         orth_stack(c, b.stack, pr.m, Wk, l, b.Cbuf);
-        if (Wk <= heig_max()) {
+        if (Wk <= heig_big_max()) {
             view_product(c, pr, b, true, b.stack, Wk, Wk, b.T);
             finish_gram(c, b, pr, b.T, pr.n, b.stack, Wk, pr.m, Wk, false);
         } else {
@@ -491,7 +520,7 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
     } else {
         fork_estimates(c, b, pr, l);
         orth_stack(c, b.stack, pr.n, Wk, l, b.Cbuf);
-        if (Wk <= heig_max()) {
+        if (Wk <= heig_big_max()) {
             view_product(c, pr, b, false, b.stack, Wk, Wk, b.T);
             finish_gram(c, b, pr, b.T, pr.m, b.stack, Wk, pr.n, Wk, true);
         } else {

@@ -178,3 +178,36 @@ def test_argument_errors(gq):
     with pytest.raises(gq.QlraError) as ei:
         gq.qlra(B, 80, 20, 4, 0, 0, precision=gq.QLRA_BF16)
     assert ei.value.code == gq.QLRA_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("v", [4, 6])
+def test_wide_krylov_final(gq, oracle, v):
+    """Block Krylov with k = 40, p = 8: the final view stacks up to 3 blocks (144 columns), past
+    the single-workgroup eigensolver; the wide one must agree with the oracle as well."""
+    print(f"wide krylov v={v}", flush=True)
+    A, _ = W.config0()
+    A32 = A.astype(np.float32)
+    Ug, Sg, Vg, eg, st = run_gpu(gq, A32, 40, 8, v, 1, 5)
+    assert st == gq.QLRA_OK
+    Uo, So, Vo, eo = oracle.qlra(A32.astype(np.float64), 40, 8, v, 1, 5)
+    assert ahat_diff(A, (Ug, Sg, Vg), (Uo, So, Vo)) <= 1e-5
+    np.testing.assert_allclose(Sg, So, rtol=1e-4, atol=1e-6 * So[0])
+    # e^2 = 1 - sum sigma_j^2 / ||A||^2: FP32 rounding of the view outputs moves the sum of
+    # squares by a few units of FP32 roundoff relative to ||A||^2, whatever the size of e
+    assert np.all(np.abs(eg[1:] ** 2 - eo[1:] ** 2) <= 4 * 2.0 ** -24)
+
+
+def test_wide_subspace_final(gq, oracle):
+    """Subspace scheme with k + p = 108 columns (past the single-workgroup eigensolver) on a
+    spectrum with a clear gap after sigma_100."""
+    print("wide subspace", flush=True)
+    m, n = 400, 360
+    sigma = np.concatenate([np.linspace(1.0, 0.5, 100), 1e-3 / np.arange(1, n - 99)])
+    A = W.spectrum_matrix(17, m, n, sigma, dtype=np.float64)
+    A32 = np.ascontiguousarray(A, dtype=np.float32)
+    Ug, Sg, Vg, eg, st = run_gpu(gq, A32, 100, 8, 3, 0, 9)
+    assert st == gq.QLRA_OK
+    A64 = A32.astype(np.float64)
+    Uo, So, Vo, eo = oracle.qlra(A64, 100, 8, 3, 0, 9)
+    assert ahat_diff(A64, (Ug, Sg, Vg), (Uo, So, Vo)) <= 1e-5
+    np.testing.assert_allclose(Sg, So, rtol=1e-5)
