@@ -4,8 +4,11 @@ Workload (the 2048 x 2048 configuration): dense quaternion FP32 matrix
 A = U diag(sigma) V^H + E, sigma_i = exp(-i/20), Haar quaternion unitaries, E i.i.d. N(0, 1e-4)
 per real component (synthetic, seeded).  k = 50, p = 10, subspace scheme (Alg. 2).  One step
 = one solve for each pass budget v in {2, 3, 4, 6}: 15 passes over A, each a quaternion view
-product A X or A^H X followed by CholeskyQR2, then the small QSVD and the back-multiplication,
-with per-pass error estimates.
+product A X or A^H X followed by its CholeskyQR, then the small QSVD and the
+back-multiplication, with per-pass error estimates.  The four solves are independent and run
+concurrently, each on a stream of its own, so that the latency-bound small steps of one overlap
+the views of the others; the same step with the solves one after another is reported beside it
+(sequential_value), and the latency of each solve alone (solve_ms).
 
 Printed: one JSON line with passes/s (value), the dominant kernel's roofline position (FP32
 MFMA view product, timed with HIP events on its own stream), the FP64 CPU oracle timed on the
@@ -41,19 +44,115 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--counters", action="store_true",
+                    help="launch sequence for hardware-counter runs only (view products and calibration copies)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn the counter CSVs of two --counters runs into the traffic record under profiles/")
     return ap.parse_args()
 
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("qgemm.hip", "common.h"):
-        h.update(open(os.path.join(ROOT, "paper_2507_13731_amd", "csrc", f), "rb").read())
+    h.update(open(os.path.join(ROOT, "paper_2507_13731_amd", "csrc", "qgemm.hip"), "rb").read())
     return h.hexdigest()[:16]
 
 
+COPY_BYTES = 256 << 20
+COUNTER_REPS = 5
+
+
+def counters_run(Q, torch, A):
+    """The launch sequence the traffic counters are read on: COUNTER_REPS forward and adjoint
+    FP32 view products (2048 x 2048 by 60), then COUNTER_REPS elementwise passes over 256 MiB
+    (read once, written once) whose counter readings calibrate the scale of FETCH_SIZE and
+    WRITE_SIZE."""
+    w = K_RANK + P_OVER
+    g = torch.Generator(device="cuda").manual_seed(0)
+    X = torch.randn((4, N, w), device="cuda", generator=g)
+    for op in (0, 1):
+        ws = Q.qlra_qgemm_workspace(op, M, N, w)
+        C = torch.empty((4, M if op == 0 else N, w), device="cuda")
+        for _ in range(COUNTER_REPS):
+            Q.qlra_qgemm(op, A, X, C, stream=torch.cuda.current_stream(), workspace=ws)
+            torch.cuda.synchronize()
+    src = torch.ones(COPY_BYTES // 4, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(COUNTER_REPS):
+        torch.neg(src, out=dst)            # an elementwise kernel: reads and writes COPY_BYTES
+        torch.cuda.synchronize()
+    print(json.dumps({"counters_run": "done", "view_launches_per_op": COUNTER_REPS, "copy_bytes": COPY_BYTES}))
+
+
+def pmc_summary(fetch_csv, write_csv):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) from two rocprofv3 --pmc runs of --counters.
+    The view product is its product kernel plus the ordered split-K reduction; the copy kernel's
+    readings give the factor that turns each counter into bytes."""
+    import csv
+    import statistics
+
+    def read(path, counter):
+        rows = {}
+        for r in csv.DictReader(open(path)):
+            if r.get("Counter_Name") != counter:
+                continue
+            key = int(r["Dispatch_Id"])
+            rows[key] = (r["Kernel_Name"], rows.get(key, ("", 0.0))[1] + float(r["Counter_Value"]))
+        return [rows[k] for k in sorted(rows)]
+
+    out = {}
+    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        seq = read(path, counter)
+        view = [(n, v) for n, v in seq if "k_qgemm" in n or "k_splitk_reduce" in n]
+        copies = [v for _, v in seq[-COUNTER_REPS:]]     # the calibration copies end the sequence
+        kib_copy = statistics.median(copies)
+        scale = COPY_BYTES / (kib_copy * 1024.0)
+        per_op = {}
+        for op, name in ((0, "forward"), (1, "adjoint")):
+            part = view[op * len(view) // 2:(op + 1) * len(view) // 2]
+            kib = sum(v for _, v in part) / COUNTER_REPS
+            per_op[name] = {"kib_per_launch": round(kib, 1), "bytes_per_launch": round(kib * 1024.0 * scale),
+                            "kernels": sorted({n.split("(")[0][-60:] for n, _ in part})}
+        out[counter] = {"copy_kib": round(kib_copy, 1), "scale": round(scale, 4), **per_op}
+    hbm = 0.5 * sum(out[c][o]["bytes_per_launch"] for c in ("FETCH_SIZE", "WRITE_SIZE") for o in ("forward", "adjoint"))
+    rec = {"kernel": "FP32 view product 2048x2048 by 60 (product kernel + split-K reduction), mean of A X and A^H X",
+           "kernel_source_hash": kernel_source_hash(), "hbm_bytes_per_launch": round(hbm),
+           "algorithmic_bytes_per_launch": 16 * M * N + 2 * 16 * N * (K_RANK + P_OVER), **out}
+    os.makedirs(os.path.dirname(PMC_FILE), exist_ok=True)
+    json.dump(rec, open(PMC_FILE, "w"), indent=1)
+    print(json.dumps(rec))
+
+
+def graph_time(torch, fn, reps):
+    """Average GPU time of fn() (library launches on the current stream): reps calls captured
+    in one HIP graph, replayed between two events on the stream the graph runs on, so that host
+    call overhead between launches is not counted."""
+    st = torch.cuda.Stream()
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        for _ in range(3):
+            fn()
+    torch.cuda.current_stream().wait_stream(st)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(reps):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    g.replay()
+    e1.record(st)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
 def time_view_kernels(Q, torch, A, reps):
-    """Average duration of the FP32 view product kernel (both orientations) with HIP events
-    on the stream the kernel runs on."""
+    """Average duration of the FP32 view product (both orientations; the product kernel and, for
+    split K, its ordered reduction) with HIP events on the stream the kernels run on."""
     w = K_RANK + P_OVER
     g = torch.Generator(device="cuda").manual_seed(0)
     X = torch.randn((4, N, w), device="cuda", generator=g)
@@ -61,17 +160,8 @@ def time_view_kernels(Q, torch, A, reps):
     for op in (0, 1):
         ws = Q.qlra_qgemm_workspace(op, M, N, w)
         C = torch.empty((4, M if op == 0 else N, w), device="cuda")
-        st = torch.cuda.current_stream()
-        for _ in range(3):
-            Q.qlra_qgemm(op, A, X, C, stream=st, workspace=ws)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        for _ in range(reps):
-            Q.qlra_qgemm(op, A, X, C, stream=st, workspace=ws)
-        e1.record(st)
-        e1.synchronize()
-        out[op] = e0.elapsed_time(e1) * 1e-3 / reps
+        out[op] = graph_time(torch, lambda: Q.qlra_qgemm(op, A, X, C, stream=torch.cuda.current_stream(), workspace=ws),
+                             reps)
     return out
 
 
@@ -181,32 +271,27 @@ def accuracy(Q, torch, A, A_np, precisions):
 
 def time_lowp_view_kernels(Q, torch, A, prec, reps):
     """Average duration of the reduced-precision view product (both orientations), HIP events on
-    its stream.  The copies of A are made once, outside the timed region."""
+    its stream around a graph of reps launches.  The copies of A are made once, outside the
+    timed region."""
     w = K_RANK + P_OVER
     g = torch.Generator(device="cuda").manual_seed(0)
     X = torch.randn((4, N, w), device="cuda", generator=g)
     Alo, Alo_t = Q.qlra_lowp_copy(A, prec)
     out = {}
-    st = torch.cuda.current_stream()
     for op in (0, 1):
         ws = Q.qlra_qgemm_lp_workspace(op, prec, M, N, w)
         C = torch.empty((4, M if op == 0 else N, w), device="cuda")
         src = Alo if op == 0 else Alo_t
-        for _ in range(3):
-            Q.qlra_qgemm_lp(op, prec, src, M, N, X, C, stream=st, workspace=ws)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        for _ in range(reps):
-            Q.qlra_qgemm_lp(op, prec, src, M, N, X, C, stream=st, workspace=ws)
-        e1.record(st)
-        e1.synchronize()
-        out[op] = e0.elapsed_time(e1) * 1e-3 / reps
+        out[op] = graph_time(torch, lambda: Q.qlra_qgemm_lp(op, prec, src, M, N, X, C, stream=torch.cuda.current_stream(),
+                                                            workspace=ws), reps)
     return out
 
 
 def main():
     args = parse()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1",
                           "n_gpus_requested": args.gpus}))
@@ -219,6 +304,9 @@ def main():
     print("generating the 2048x2048 workload", file=sys.stderr, flush=True)
     A_np, _ = W.config1(seed=SEED_DATA, n=M, noise_std=0.01)
     A = torch.from_numpy(A_np).cuda()
+    if args.counters:
+        counters_run(Q, torch, A)
+        return
     precisions = {"fp32": Q.QLRA_FP32, "bf16": Q.QLRA_BF16, "fp16": Q.QLRA_FP16}
     outs = {}
     for name, prec in precisions.items():
@@ -230,22 +318,33 @@ def main():
                                  e=torch.empty(v, dtype=torch.float64, device="cuda"),
                                  ws=torch.empty(need, dtype=torch.uint8, device="cuda"))
 
-    def solve(name, v):
+    # one step = the solves of the four budgets, independent of each other: each on a stream of
+    # its own (default priority), so that one solve's latency-bound small steps overlap the
+    # others' views
+    streams = {v: torch.cuda.Stream() for v in BUDGETS}
+
+    def solve(name, v, stream=None):
         o = outs[name, v]
         Q.qlra(A, K_RANK, P_OVER, v, "subspace", SEED_SKETCH, U=o["U"], S=o["S"], V=o["V"], pass_err=o["e"],
-               workspace=o["ws"], graph=True, precision=precisions[name])
+               workspace=o["ws"], graph=True, precision=precisions[name], stream=stream)
+
+    def step(name):
+        cur = torch.cuda.current_stream()
+        for v in BUDGETS:
+            streams[v].wait_stream(cur)
+            solve(name, v, streams[v])
+        for v in BUDGETS:
+            cur.wait_stream(streams[v])
 
     def timed_steps(name, steps, warmup):
         for _ in range(warmup):
-            for v in BUDGETS:
-                solve(name, v)
+            step(name)
         torch.cuda.synchronize()
         for v in BUDGETS:
             assert Q.qlra_status(outs[name, v]["ws"]) == Q.QLRA_OK
         t0 = time.perf_counter()
         for _ in range(steps):
-            for v in BUDGETS:
-                solve(name, v)
+            step(name)
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
@@ -266,6 +365,14 @@ def main():
     passes = sum(BUDGETS) * args.steps
     value = passes / dt
     per_v = per_budget("fp32")
+    # the same step with the four solves one after another on one stream (latency view)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        for v in BUDGETS:
+            solve("fp32", v)
+    torch.cuda.synchronize()
+    sequential_value = passes / (time.perf_counter() - t1)
 
     lowp = {}
     for name in ("bf16", "fp16"):
@@ -318,6 +425,8 @@ def main():
                                    "k=50, p=10, subspace scheme (Alg. 2), budgets v=2,3,4,6 per step",
                        "m": M, "n": N, "k": K_RANK, "p": P_OVER, "budgets": list(BUDGETS),
                        "passes_per_step": sum(BUDGETS)},
+            "step": "the solves of the four budgets, concurrently on four streams",
+            "sequential_value": round(sequential_value, 3),
             "qgemm_tflops": round(achieved / 1e12, 3), "solve_ms": per_v, "accuracy": acc,
             "roofline": roofline, "cpu_baseline": cpu,
             "precision_form": {"views": "1..v-2 reduced (FP32 accumulation), v-1 and v FP32; Gram/Cholesky/QSVD FP64",

@@ -44,6 +44,7 @@ struct QgemmDesc {
     int64_t M, N, K;           // C is M x N, reduction length K
     const int* skip_flag;      // if non-null and *skip_flag == 0 the launch does nothing
     const float* cscale;       // low-precision math: device scalar the result is multiplied by
+    double* fro2_part;         // FP32 A X only (optional): per-wave sums of squares of A, fro2_slots(d) entries
 };
 
 // Device workspace carved into aligned regions.
@@ -66,7 +67,8 @@ struct QgemmScratch {
     unsigned* counters;     // qgemm_counter_count entries, zero at rest
 };
 
-size_t qgemm_partial_bytes(const QgemmDesc& d);   // split-K partials (+ the converted B, low precision)
+size_t qgemm_partial_bytes(const QgemmDesc& d);
+size_t fro2_slots(const QgemmDesc& d);            // entries of fro2_part written by an FP32 A X launch   // split-K partials (+ the converted B, low precision)
 size_t qgemm_counter_count(const QgemmDesc& d);
 hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t st);
 
@@ -156,12 +158,15 @@ hipError_t estimate_launch(const double* S, int k, const double* nA2, double* e,
 hipError_t nan_launch(double* e, hipStream_t st);
 
 // ||A||_F^2 (FP64) into *out; partial: 1024 doubles.
+// ||A||_F^2 = the sum, in order, of nb partial sums (deterministic)
+hipError_t fro2_final_launch(const double* partial, int64_t nb, double* out, hipStream_t st);
 hipError_t fro2_launch(const float* A, int64_t m, int64_t n, int64_t lda, int64_t aps,
                        double* partial, double* out, hipStream_t st);
 
 // Canonical phase: for each column j < k of V (n x k), the entry of largest modulus (lowest row
 // on ties) is made real positive by right-multiplying columns j of U and V by its conjugate phase.
-hipError_t phase_launch(float* U, int64_t m, int64_t ldu, int64_t ups, float* V, int64_t n,
-                        int64_t ldv, int64_t vps, int k, hipStream_t st);
+size_t phase_work_bytes(int64_t n, int k);
+hipError_t phase_launch(float* U, int64_t m, int64_t ldu, int64_t ups, float* V, int64_t n, int64_t ldv,
+                        int64_t vps, int k, void* work, hipStream_t st);
 
 }  // namespace qlra_impl

@@ -6,22 +6,23 @@
 // where e_q e_{p^q} = s(p, q) e_p is the Hamilton product of the units (eq. (1)).  All 16
 // plane products are real GEMMs that share operands: each A_q fragment feeds four output
 // planes and each B_r fragment feeds four, so one pass over A computes the whole quaternion
-// product with A read once.  Signs are applied to the thin operand (a negated register copy),
-// never to A.
+// product with A read once.
 //
-// Tiling (gfx950, wave64): a workgroup of 4 waves owns a BM x BN tile of all four output
-// planes; wave (wm, wn) owns RM x CN MFMA sub-tiles of 16 x 16 in every plane.  Per K step of
-// BK the four planes of an A tile and of a B tile are staged through LDS; the global loads of
-// step t+1 are issued into registers before the MFMAs of step t so that their latency hides
-// behind the matrix cores.  The MFMA A operand always comes from the A tile, stored row-major
-// for A B and k-major for A^H B (the transpose happens in the LDS staging), so one kernel
-// serves both orientations.  When the output tiles cannot fill 256 CUs, K is split across
-// workgroups; partial tiles go to scratch and a separate element-parallel kernel adds them in
-// split order (deterministic, no floating-point atomics).
-//
-// math = MATH_F32: FP32 operands, v_mfma_f32_16x16x4f32, FP32 accumulation.
-// math = MATH_F64: operands converted to FP64 in LDS (exact for FP32 data),
-//                  v_mfma_f64_16x16x4f64; used for Gram matrices and small products.
+// Three kernel families:
+//  - k_qview (math = MATH_F32): the views.  FP32 operands loaded straight from global memory
+//    in MFMA operand order (the thin block transposed first by k_thin_t), v_mfma_f32_16x16x4f32,
+//    FP32 accumulation; see the section below.
+//  - k_qgemm (math = MATH_F64): Gram matrices, CholeskyQR applies, Krylov projections and the
+//    back-multiplication.  A workgroup of 4 waves owns a BM x BN tile of all four output planes;
+//    per K step the four planes of an A tile and of a B tile are staged through LDS (converted
+//    to FP64 there: exact for FP32 data) and multiplied with v_mfma_f64_16x16x4f64; the global
+//    loads of step t+1 are in flight during the MFMAs of step t.  The MFMA A operand always
+//    comes from the A tile, stored row-major for A B and k-major for A^H B, so one kernel serves
+//    both orientations.  Signs go on a negated register copy of the thin operand.
+//  - k_qgemm_lp (MATH_BF16 / MATH_F16): the reduced-precision views.
+// When the output tiles cannot fill the chip, K is split across workgroups; partial tiles go to
+// scratch and an element-parallel kernel adds them in split order (deterministic, no
+// floating-point atomics).
 #include "common.h"
 
 #include <algorithm>
@@ -335,6 +336,262 @@ hipError_t reduce_f32(const float* part, int splits, int64_t Mp, int64_t Np, flo
 }
 
 // ------------------------------------------------------------------------------------------
+// FP32 views: operands straight from global memory, no LDS in the K loop.
+//
+// Each wave owns one output tile of 16 rows x 16 CN columns in all four planes (4 CN
+// accumulators of 16 x 16) over a contiguous stretch of K, and loads both operands in the
+// order the MFMA consumes them.  Lane (r, g) = (l % 16, l / 16) supplies, for the j-th of the
+// four MFMAs of a 16-wide K step, reduction index k0 + 4 g + j:
+//  - A X:    A_q[row r][k0 + 4 g .. + 3], one 16-byte load per plane (element j feeds MFMA j);
+//  - A^H X:  the same elements of A^T, A_q[k0 + 4 g + j][row r]: four loads per plane, the 16
+//            lanes of a group reading 64 contiguous bytes of a row of A;
+//  - B:      the thin block is first transposed to Bt[q][column][k] (k contiguous, zero padded
+//            to Kp and Np), so that B_q[k0 + 4 g .. + 3][column r] is one 16-byte load.
+// Every A element is loaded by exactly one wave, once; Bt is re-read from L2 by every row tile.
+// There is no barrier in the K loop: each wave streams on its own, operands one step ahead in
+// ping-pong registers (A^H X: A slice j refilled right after its use).  The signs of eq. (1)
+// go on the A operand (one negated copy per plane), shared by all output planes and column
+// tiles.  KW waves of a workgroup may share an output tile, each over 1/KW of the workgroup's
+// K range; their sums are added in wave order through LDS (deterministic), and K splits across
+// workgroups go through the ordered split-K reduction.
+
+constexpr int VBK = 16;   // K per step: four MFMAs of k = 4
+
+struct VParams {
+    const float* A; int64_t lda, aps;
+    const float* Bt; int64_t kp, bps;   // Bt[q][c][k]: column stride kp, plane stride bps
+    float* C; int64_t ldc, cps;
+    int64_t M, N, K;
+    int64_t kchunk;      // K per workgroup, a multiple of VBK * kw
+    int splits;
+    int kw;              // waves per output tile: 1, 2 or 4
+    int64_t tiles, gy;   // output tiles (row tiles x column tiles) and column tiles
+    float* part; int64_t Mp, Np;
+    int store;
+    const int* skip;
+    double* fro;         // FRO: per-wave sums of squares of the A elements (slot = wave of the grid)
+};
+
+// B (K x N, four planes, row-major) -> Bt[q][c][k] (Np x Kp per plane), zero outside K x N;
+// tiles of 16 reduction rows x 64 columns through LDS (reads coalesced along the columns,
+// writes 64-byte runs along k), enough workgroups to spread over the chip
+__global__ __launch_bounds__(256) void k_thin_t(const float* __restrict__ B, int64_t ldb, int64_t bps, int64_t K,
+                                                int64_t N, float* __restrict__ Bt, int64_t Np, int64_t Kp,
+                                                const int* skip) {
+    __shared__ float t[16][65];
+    if (skip && *skip == 0) return;
+    const int64_t k0 = (int64_t)blockIdx.x * 16, c0 = (int64_t)blockIdx.y * 64;
+    const int q = blockIdx.z, tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = ty; i < 16; i += 4) {
+        const int64_t k = k0 + i, c = c0 + tx;
+        t[i][tx] = (k < K && c < N) ? B[q * bps + k * ldb + c] : 0.0f;
+    }
+    __syncthreads();
+    const int kk = threadIdx.x & 15, cc = threadIdx.x >> 4;
+#pragma unroll
+    for (int i = cc; i < 64; i += 16) {
+        const int64_t c = c0 + i, k = k0 + kk;
+        if (c < Np && k < Kp) Bt[((int64_t)q * Np + c) * Kp + k] = t[kk][i];
+    }
+}
+
+template <int CN, bool ADJ, bool AVEC, bool FRO>
+__global__ __launch_bounds__(256, CN <= 3 ? 2 : 1) void k_qview(VParams P) {
+    __shared__ f32x4 xch[4][CN * 4][64];
+    if (P.skip && *P.skip == 0) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kw = P.kw;
+    const int64_t tile_raw = (int64_t)blockIdx.x * (4 / kw) + wave / kw;
+    const bool tile_ok = tile_raw < P.tiles;
+    const int64_t tile = tile_ok ? tile_raw : P.tiles - 1;
+    const int kpart = wave % kw;
+    const int64_t rt = tile / P.gy, ct = tile % P.gy;
+    const int64_t row0 = rt * 16, col0 = ct * 16 * CN;
+    const int64_t kc0 = (int64_t)blockIdx.z * P.kchunk;
+    const int64_t kc1 = P.K < kc0 + P.kchunk ? P.K : kc0 + P.kchunk;
+    const int64_t sub = P.kchunk / kw;
+    const int64_t kb = kc0 + kpart * sub < kc1 ? kc0 + kpart * sub : kc1;
+    const int64_t ke = kb + sub < kc1 ? kb + sub : kc1;
+    const int r = lane & 15, g = lane >> 4;
+    // rows past the edge are clamped (never stored); Bt is zero past K and N, so only A needs
+    // masking in a ragged last step
+    const int64_t arow = row0 + r < P.M ? row0 + r : P.M - 1;
+    const float* __restrict__ A = P.A;
+    const float* bcol[CN];
+#pragma unroll
+    for (int cn = 0; cn < CN; cn++) bcol[cn] = P.Bt + (col0 + 16 * cn + r) * P.kp + 4 * g;
+    const int64_t klast = ke - 1;
+
+    f32x4 acc[CN][4];
+#pragma unroll
+    for (int cn = 0; cn < CN; cn++)
+#pragma unroll
+        for (int p = 0; p < 4; p++) acc[cn][p] = f32x4{0, 0, 0, 0};
+    // FRO (A X): ||A||_F^2 on the side, from the first column tile's waves, rows inside A only
+    double fro = 0.0;
+    const double fro_w = (FRO && ct == 0 && row0 + r < P.M) ? 1.0 : 0.0;
+
+    constexpr bool A4 = AVEC && !ADJ;   // A as 16-byte loads
+    auto a_elem = [&](int q, int64_t k) -> const float* {
+        return ADJ ? A + q * P.aps + k * P.lda + arow : A + q * P.aps + arow * P.lda + k;
+    };
+    auto load_a = [&](int64_t k0, f32x4 (&a)[4]) {
+        if constexpr (A4) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) a[q] = *reinterpret_cast<const f32x4*>(a_elem(q, k0 + 4 * g));
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+#pragma unroll
+                for (int q = 0; q < 4; q++) a[q][j] = *a_elem(q, k0 + 4 * g + j);
+        }
+    };
+    auto load_b = [&](int64_t k0, f32x4 (&b)[CN][4]) {
+#pragma unroll
+        for (int cn = 0; cn < CN; cn++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) b[cn][q] = *reinterpret_cast<const f32x4*>(bcol[cn] + q * P.bps + k0);
+    };
+    auto mma_slice = [&](const f32x4 (&a)[4], int j, const f32x4 (&b)[CN][4]) {
+        float av[4], nav[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) { av[q] = a[q][j]; nav[q] = -av[q]; }
+        if constexpr (FRO) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) fro = fma((double)av[q], (double)av[q], fro);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+            for (int cn = 0; cn < CN; cn++)
+#pragma unroll
+                for (int pp = 0; pp < 4; pp++)
+                    acc[cn][pp] = __builtin_amdgcn_mfma_f32_16x16x4f32(term_sign<ADJ>(pp, q) > 0 ? av[q] : nav[q],
+                                                                       b[cn][pp ^ q][j], acc[cn][pp], 0, 0, 0);
+    };
+    // one full step from registers; the loads of the step `kn` go out a quarter after each slice
+    // of MFMAs, so that no burst of loads stalls the issue of the matrix instructions
+    // (A^H X: A slice j refilled right after slice j is used)
+    auto step = [&](f32x4 (&a)[4], const f32x4 (&b)[CN][4], f32x4 (&an)[4], f32x4 (&bn)[CN][4], int64_t kn) {
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            __builtin_amdgcn_sched_barrier(0);
+            mma_slice(a, j, b);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int e = j * CN; e < (j + 1) * CN; e++) {
+                const int cn = e / 4, q = e % 4;
+                bn[cn][q] = *reinterpret_cast<const f32x4*>(bcol[cn] + q * P.bps + kn);
+            }
+            if constexpr (A4) {
+                an[j] = *reinterpret_cast<const f32x4*>(a_elem(j, kn + 4 * g));
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; q++) a[q][j] = *a_elem(q, kn + 4 * g + j);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+
+    const int64_t len = (tile_ok && ke > kb) ? ke - kb : 0;
+    const int64_t nfull = len / VBK;
+    if (nfull > 0) {
+        f32x4 a0[4], a1[4], b0[CN][4], b1[CN][4];
+        load_a(kb, a0);
+        load_b(kb, b0);
+        // steps in pairs with ping-pong registers (no copies); a step past the last full one
+        // reloads the last (in bounds, unused)
+        const int64_t kl = kb + (nfull - 1) * VBK;
+#pragma unroll 4
+        for (int64_t st = 0; st < nfull; st += 2) {
+            const int64_t k0 = kb + st * VBK;
+            const int64_t k1 = k0 + VBK <= kl ? k0 + VBK : kl;
+            const int64_t k2 = k0 + 2 * VBK <= kl ? k0 + 2 * VBK : kl;
+            if constexpr (A4) {
+                step(a0, b0, a1, b1, k1);
+                if (st + 1 < nfull) step(a1, b1, a0, b0, k2);
+            } else {
+                // the A ring refills a in place: both steps use the same registers
+                step(a0, b0, a0, b1, k1);
+                if (st + 1 < nfull) step(a0, b1, a0, b0, k2);
+            }
+        }
+    }
+    if (len % VBK) {
+        // ragged last step: A clamped and zeroed past ke (Bt is zero there already)
+        const int64_t k0 = kb + nfull * VBK;
+        f32x4 a[4], b[CN][4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const int64_t k = k0 + 4 * g + j;
+            const int64_t kk = k < ke ? k : klast;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const float v = *a_elem(q, kk);
+                a[q][j] = k < ke ? v : 0.0f;
+            }
+        }
+        load_b(k0, b);
+#pragma unroll
+        for (int j = 0; j < 4; j++) mma_slice(a, j, b);
+    }
+
+    if constexpr (FRO) {
+        fro *= fro_w;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) fro += __shfl_xor(fro, o, 64);
+        if (lane == 0) P.fro[((int64_t)blockIdx.z * gridDim.x + blockIdx.x) * 4 + wave] = fro;
+    }
+
+    if (kw > 1) {
+        if (kpart > 0) {
+#pragma unroll
+            for (int cn = 0; cn < CN; cn++)
+#pragma unroll
+                for (int pp = 0; pp < 4; pp++) xch[wave][cn * 4 + pp][lane] = acc[cn][pp];
+        }
+        __syncthreads();
+        if (kpart == 0) {
+            for (int t = 1; t < kw; t++) {
+#pragma unroll
+                for (int cn = 0; cn < CN; cn++)
+#pragma unroll
+                    for (int pp = 0; pp < 4; pp++) acc[cn][pp] += xch[wave + t][cn * 4 + pp][lane];
+            }
+        }
+    }
+    if (kpart != 0 || !tile_ok) return;
+
+    // D element (lane, i) of the 16 x 16 x 4 FP32 MFMA sits at row 4 (lane / 16) + i, column lane % 16
+    if (P.splits == 1) {
+#pragma unroll
+        for (int cn = 0; cn < CN; cn++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int64_t row = row0 + 4 * g + i, col = col0 + 16 * cn + r;
+                if (row < P.M && col < P.N) {
+#pragma unroll
+                    for (int pp = 0; pp < 4; pp++) {
+                        float* dst = P.C + pp * P.cps + row * P.ldc + col;
+                        *dst = P.store == ST_SUB ? *dst - acc[cn][pp][i] : acc[cn][pp][i];
+                    }
+                }
+            }
+        return;
+    }
+#pragma unroll
+    for (int cn = 0; cn < CN; cn++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int64_t row = row0 + 4 * g + i, col = col0 + 16 * cn + r;
+#pragma unroll
+            for (int pp = 0; pp < 4; pp++)
+                P.part[(((int64_t)blockIdx.z * 4 + pp) * P.Mp + row) * P.Np + col] = acc[cn][pp][i];
+        }
+}
+
+// ------------------------------------------------------------------------------------------
 // configuration choice
 
 struct Plan {
@@ -346,13 +603,7 @@ constexpr int kCUs = 256;
 
 Plan make_plan(const QgemmDesc& d) {
     Plan p{};
-    if (d.math == MATH_F32) {
-        p.WM = 4; p.WN = 1; p.BK = 32;
-        const int64_t cn_needed = (std::min<int64_t>(d.N, 80) + 15) / 16;
-        p.CN = (int)std::max<int64_t>(1, cn_needed);
-        const int64_t gy = (d.N + 16 * p.CN - 1) / (16 * p.CN);
-        p.RM = ((d.M + 127) / 128) * gy >= kCUs ? 2 : 1;
-    } else if (d.op == OP_HN) {
+    if (d.op == OP_HN) {
         // Gram-like products: small M x N output, long K; 32 x 32 tiles so that K splits
         // spread the FP64 MFMA work over many CUs
         p.BK = 16; p.WM = 2; p.WN = 2; p.RM = 1; p.CN = 1;
@@ -366,11 +617,12 @@ Plan make_plan(const QgemmDesc& d) {
     p.Mp = p.gx * BM;
     p.Np = p.gy * BN;
     const int64_t tiles = p.gx * p.gy;
-    // split K so that about 256 workgroups run, each over at least 4 (F32) or 2 (F64) K steps
-    const int64_t min_steps = d.math == MATH_F32 ? 4 : 2;
+    // split K so that about one workgroup per CU runs, each over at least 2 K steps
+    const int64_t min_steps = 2;
+    const int64_t target = kCUs;
     int64_t splits = 1;
-    if (tiles < kCUs) {
-        splits = std::min<int64_t>((kCUs + tiles - 1) / tiles, (d.K + min_steps * p.BK - 1) / (min_steps * p.BK));
+    if (tiles < target) {
+        splits = std::min<int64_t>((target + tiles - 1) / tiles, (d.K + min_steps * p.BK - 1) / (min_steps * p.BK));
         splits = std::max<int64_t>(splits, 1);
     }
     int64_t kchunk = (d.K + splits - 1) / splits;
@@ -399,14 +651,93 @@ hipError_t launch_t(const Plan& pl, const KParams& kp, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <bool ADJ>
-hipError_t launch_f32(const Plan& pl, const KParams& kp, hipStream_t st) {
-#define QL_F32(RM_, CN_) \
-    if (pl.RM == RM_ && pl.CN == CN_) return launch_t<float, 4, 1, RM_, CN_, 32, ADJ, float, float, float>(pl, kp, st);
-    QL_F32(1, 1) QL_F32(1, 2) QL_F32(1, 3) QL_F32(1, 4) QL_F32(1, 5)
-    QL_F32(2, 1) QL_F32(2, 2) QL_F32(2, 3) QL_F32(2, 4) QL_F32(2, 5)
-#undef QL_F32
-    return hipErrorInvalidValue;
+struct VPlan {
+    int CN, kw;
+    int64_t gy, tiles, splits, kchunk, Mp, Np, Kp, gx;
+};
+
+VPlan make_vplan(const QgemmDesc& d) {
+    VPlan p{};
+    if (d.N <= 64) {
+        p.CN = (int)std::max<int64_t>(1, (d.N + 15) / 16);
+    } else {
+        // column tiles of at most 80, as even as possible (96 = 2 x 48, 160 = 2 x 80)
+        const int64_t gy0 = (d.N + 79) / 80;
+        p.CN = (int)((d.N + 16 * gy0 - 1) / (16 * gy0));
+    }
+    p.gy = (d.N + 16 * p.CN - 1) / (16 * p.CN);
+    const int64_t rt = (d.M + 15) / 16;
+    p.tiles = rt * p.gy;
+    p.Mp = rt * 16;
+    p.Np = p.gy * 16 * p.CN;
+    p.Kp = (d.K + VBK - 1) / VBK * VBK;
+    // one round of waves over the chip: two per SIMD where the registers allow it (CN <= 3), one
+    // otherwise, so that every wave streams a long K range; the K range of a tile is cut into
+    // parts of at least 4 steps, up to 4 parts inside a workgroup (combined in LDS), the rest
+    // across workgroups
+    const int64_t waves = (p.CN <= 3 ? 8 : 4) * kCUs;
+    const int64_t need = (waves + p.tiles - 1) / p.tiles;
+    const int64_t maxparts = std::max<int64_t>(1, d.K / (4 * VBK));
+    const int64_t parts = std::min(need, maxparts);
+    p.kw = parts >= 4 ? 4 : (parts >= 2 ? 2 : 1);
+    const int64_t splits = (parts + p.kw - 1) / p.kw;
+    const int64_t unit = VBK * p.kw;
+    int64_t kchunk = (d.K + splits - 1) / splits;
+    kchunk = std::max<int64_t>(unit, (kchunk + unit - 1) / unit * unit);
+    p.kchunk = kchunk;
+    p.splits = std::max<int64_t>(1, (d.K + kchunk - 1) / kchunk);
+    p.gx = (p.tiles + 4 / p.kw - 1) / (4 / p.kw);
+    return p;
+}
+
+size_t vplan_slots(const VPlan& p) { return (size_t)p.gx * 4 * (size_t)p.splits; }
+size_t vplan_thin_bytes(const VPlan& p) { return ((size_t)4 * p.Np * p.Kp * sizeof(float) + 255) & ~size_t(255); }
+size_t vplan_part_bytes(const VPlan& p) { return p.splits > 1 ? (size_t)p.splits * 4 * p.Mp * p.Np * sizeof(float) : 0; }
+
+template <int CN, bool ADJ, bool AVEC, bool FRO = false>
+hipError_t launch_v(const VPlan& pl, const VParams& vp, hipStream_t st) {
+    hipLaunchKernelGGL((k_qview<CN, ADJ, AVEC, FRO>), dim3((unsigned)pl.gx, 1, (unsigned)pl.splits), dim3(256), 0, st, vp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || pl.splits == 1) return e;
+    return reduce_f32(vp.part, (int)pl.splits, pl.Mp, pl.Np, vp.C, vp.ldc, vp.cps, vp.M, vp.N, vp.store, vp.skip, st);
+}
+
+template <int CN>
+hipError_t launch_v_cn(const VPlan& pl, const VParams& vp, bool adj, bool avec, hipStream_t st) {
+    if (adj) return launch_v<CN, true, false>(pl, vp, st);
+    if (vp.fro) return avec ? launch_v<CN, false, true, true>(pl, vp, st) : launch_v<CN, false, false, true>(pl, vp, st);
+    return avec ? launch_v<CN, false, true>(pl, vp, st) : launch_v<CN, false, false>(pl, vp, st);
+}
+
+hipError_t launch_view(const QgemmDesc& d, void* scratch, hipStream_t st) {
+    const VPlan pl = make_vplan(d);
+    if (!scratch) return hipErrorInvalidValue;
+    float* Bt = (float*)scratch;
+    float* part = (float*)((char*)scratch + vplan_thin_bytes(pl));
+    hipLaunchKernelGGL(k_thin_t, dim3((unsigned)((pl.Kp + 15) / 16), (unsigned)((pl.Np + 63) / 64), 4), dim3(256), 0, st,
+                       (const float*)d.B, d.ldb, d.bps, d.K, d.N, Bt, pl.Np, pl.Kp, d.skip_flag);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    VParams vp{};
+    vp.A = (const float*)d.A; vp.lda = d.lda; vp.aps = d.aps;
+    vp.Bt = Bt; vp.kp = pl.Kp; vp.bps = pl.Np * pl.Kp;
+    vp.C = (float*)d.C; vp.ldc = d.ldc; vp.cps = d.cps;
+    vp.M = d.M; vp.N = d.N; vp.K = d.K;
+    vp.kchunk = pl.kchunk; vp.splits = (int)pl.splits; vp.kw = pl.kw;
+    vp.tiles = pl.tiles; vp.gy = pl.gy;
+    vp.part = part; vp.Mp = pl.Mp; vp.Np = pl.Np;
+    vp.store = d.store; vp.skip = d.skip_flag;
+    vp.fro = d.op == OP_NN ? d.fro2_part : nullptr;
+    const bool adj = d.op == OP_HN;
+    const bool avec = ((uintptr_t)d.A % 16) == 0 && d.lda % 4 == 0 && d.aps % 4 == 0;
+    switch (pl.CN) {
+        case 1: return launch_v_cn<1>(pl, vp, adj, avec, st);
+        case 2: return launch_v_cn<2>(pl, vp, adj, avec, st);
+        case 3: return launch_v_cn<3>(pl, vp, adj, avec, st);
+        case 4: return launch_v_cn<4>(pl, vp, adj, avec, st);
+        case 5: return launch_v_cn<5>(pl, vp, adj, avec, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -506,6 +837,7 @@ __global__ __launch_bounds__(256 * NCG) void k_qgemm_lp(LpParams P) {
     const int ar = lane & 15, ak = 8 * (lane >> 4);
     const int64_t rt = (int64_t)blockIdx.x * (LBM / 16) + rg;   // this wave's row tile
     const int64_t rbase = 16 * rt;
+    const int64_t col0 = (int64_t)blockIdx.y * NP;                 // this workgroup's column tile
     // a row tile past the copy reads the last one: its rows are never stored
     const TL* __restrict__ Ab = (const TL*)P.A + (rt < P.art ? rt : P.art - 1) * P.akt * 4096 + 8 * lane;
     const TL* __restrict__ Bt = (const TL*)P.Bt;
@@ -527,7 +859,7 @@ __global__ __launch_bounds__(256 * NCG) void k_qgemm_lp(LpParams P) {
             const int e = tid + u * NT;
             const int row = e / (LKS / 8), ch = e - row * (LKS / 8);
             const int p = row / NP, c = row - p * NP;
-            bt[u] = *reinterpret_cast<const v8*>(Bt + ((int64_t)p * P.Np + c) * P.bkp + k0 + 8 * ch);
+            bt[u] = *reinterpret_cast<const v8*>(Bt + ((int64_t)p * P.Np + col0 + c) * P.bkp + k0 + 8 * ch);
         }
     };
     auto store_b = [&](const v8 (&bt)[CPT]) {
@@ -597,7 +929,7 @@ __global__ __launch_bounds__(256 * NCG) void k_qgemm_lp(LpParams P) {
 #pragma unroll
         for (int i = 0; i < 4; i++) {
             const int64_t r = rbase + 4 * (lane >> 4) + i;
-            const int64_t c = cn * 16 + ar;
+            const int64_t c = col0 + cn * 16 + ar;
             if (P.splits == 1) {
                 if (r < P.M && c < P.N)
 #pragma unroll
@@ -616,21 +948,28 @@ constexpr int lp_ncg(int cn) { return cn <= 2 ? 1 : 2; }
 constexpr int lp_cnw(int cn) { return (cn + lp_ncg(cn) - 1) / lp_ncg(cn); }
 
 struct LpPlan {
-    int CN;
-    int64_t gx, splits, kchunk, Mp, Np, Kp;
+    int CN;                 // column tiles of 16 per workgroup
+    int64_t gx, gy, splits, kchunk, Mp, Np, Kp;
 };
+
+// up to 96 columns per workgroup (wider thin blocks: column tiles as even as possible, A read
+// once per column tile)
+constexpr int kLpMaxCols = 96;
 
 LpPlan make_lp_plan(const QgemmDesc& d) {
     LpPlan p{};
-    p.CN = (int)std::max<int64_t>(1, (d.N + 15) / 16);
-    p.Np = 16 * (int64_t)p.CN;
+    const int64_t gy0 = std::max<int64_t>(1, (d.N + kLpMaxCols - 1) / kLpMaxCols);
+    p.CN = (int)std::max<int64_t>(1, (d.N + 16 * gy0 - 1) / (16 * gy0));
+    p.gy = (d.N + 16 * p.CN - 1) / (16 * p.CN);
+    p.Np = p.gy * 16 * (int64_t)p.CN;
     p.gx = (d.M + LBM - 1) / LBM;
     p.Mp = p.gx * LBM;
     p.Kp = ((d.K + LKS - 1) / LKS) * LKS;
     // split K so that every CU gets a workgroup, each over at least 2 K steps; no more splits than
     // that, since the partial tiles (splits x the output) add traffic next to A
+    const int64_t tiles = p.gx * p.gy;
     int64_t splits = 1;
-    if (p.gx < kCUs) splits = std::min<int64_t>((kCUs + p.gx - 1) / p.gx, (d.K + 2 * LBK - 1) / (2 * LBK));
+    if (tiles < kCUs) splits = std::min<int64_t>((kCUs + tiles - 1) / tiles, (d.K + 2 * LBK - 1) / (2 * LBK));
     splits = std::max<int64_t>(splits, 1);
     int64_t kchunk = (d.K + splits - 1) / splits;
     kchunk = ((kchunk + LKS - 1) / LKS) * LKS;
@@ -660,7 +999,7 @@ hipError_t launch_lp(const QgemmDesc& d, const LpPlan& pl, void* scratch, hipStr
     P.part = part; P.Mp = pl.Mp; P.Np = pl.Np;
     P.skip = d.skip_flag;
     P.cscale = d.cscale;
-    dim3 grid((unsigned)pl.gx, 1, (unsigned)pl.splits);
+    dim3 grid((unsigned)pl.gx, (unsigned)pl.gy, (unsigned)pl.splits);
 #define QL_LP(CN_) \
     if (pl.CN == CN_) \
         hipLaunchKernelGGL((k_qgemm_lp<TL, ADJ, CN_, lp_ncg(CN_), lp_cnw(CN_)>), grid, dim3(256 * lp_ncg(CN_)), 0, st, P); \
@@ -684,22 +1023,32 @@ size_t qgemm_partial_bytes(const QgemmDesc& d) {
         const LpPlan lp = make_lp_plan(d);
         return ((lp_thin_bytes(lp) + 255) & ~size_t(255)) + lp_part_bytes(lp);
     }
+    if (d.math == MATH_F32) {
+        const VPlan vp = make_vplan(d);
+        return vplan_thin_bytes(vp) + vplan_part_bytes(vp);
+    }
     const Plan p = make_plan(d);
     if (p.splits <= 1) return 0;
-    const size_t el = d.math == MATH_F32 ? sizeof(float) : sizeof(double);
+    const size_t el = sizeof(double);
     return (size_t)p.splits * 4 * (size_t)p.Mp * (size_t)p.Np * el;
 }
 
 size_t qgemm_counter_count(const QgemmDesc&) { return 0; }
 
+size_t fro2_slots(const QgemmDesc& d) { return d.math == MATH_F32 ? vplan_slots(make_vplan(d)) : 0; }
+
 hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t st) {
     if (d.M <= 0 || d.N <= 0) return hipSuccess;
     if (d.math == MATH_BF16 || d.math == MATH_F16) {
-        if (d.b_f64 || d.c_f64 || d.store != ST_SET || d.N > 96 || !s.partial) return hipErrorInvalidValue;
+        if (d.b_f64 || d.c_f64 || d.store != ST_SET || !s.partial) return hipErrorInvalidValue;
         const LpPlan lp = make_lp_plan(d);
         if (d.math == MATH_BF16)
             return d.op == OP_HN ? launch_lp<__bf16, true>(d, lp, s.partial, st) : launch_lp<__bf16, false>(d, lp, s.partial, st);
         return d.op == OP_HN ? launch_lp<_Float16, true>(d, lp, s.partial, st) : launch_lp<_Float16, false>(d, lp, s.partial, st);
+    }
+    if (d.math == MATH_F32) {
+        if (d.a_f64 || d.b_f64 || d.c_f64) return hipErrorInvalidValue;
+        return launch_view(d, s.partial, st);
     }
     const Plan pl = make_plan(d);
     KParams kp{};
@@ -714,10 +1063,6 @@ hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t s
     kp.avec = vec_ok(d.A, d.lda, d.aps, d.a_f64 ? 8 : 4);
     kp.bvec = vec_ok(d.B, d.ldb, d.bps, d.b_f64 ? 8 : 4);
     if (pl.splits > 1 && !s.partial) return hipErrorInvalidValue;
-    if (d.math == MATH_F32) {
-        if (d.a_f64 || d.b_f64 || d.c_f64) return hipErrorInvalidValue;
-        return d.op == OP_HN ? launch_f32<true>(pl, kp, st) : launch_f32<false>(pl, kp, st);
-    }
     // FP64 arithmetic
     if (d.op == OP_HN) {
         if (!d.a_f64 && !d.b_f64 && d.c_f64)

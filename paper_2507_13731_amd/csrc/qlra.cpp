@@ -54,6 +54,7 @@ struct Ctx {
     int views = 0;                  // views begun so far
     int step_only = -1;
     bool forked = false;            // this step forked work to the side stream
+    bool fro_next = false;          // the next FP32 A X view also forms ||A||_F^2
     int step_now() const { return views > 0 ? views - 1 : 0; }
     bool live() const { return !dry && (step_only < 0 || step_now() == step_only); }
 };
@@ -223,6 +224,7 @@ struct Bufs {
     double* big_work;       // the large-order eigensolver of the final view
     void* Alo; void* Alo_t;  // low-precision copies of A and A^T (views 1 .. v-2)
     float* lp_scale;        // [scale, 1 / scale]
+    void* phase_work;       // partial arg-max of the phase normalisation
     void* partial;
 };
 
@@ -231,7 +233,12 @@ void carve(const Problem& pr, const Dims& d, Arena& ar, Bufs& b, size_t part_byt
     b.status = (int*)ar.take(16 * sizeof(int));
     b.counters = (unsigned*)ar.take(std::max<size_t>(cnt, 1) * sizeof(unsigned));
     b.nA2 = (double*)ar.take(sizeof(double));
-    b.fro_part = (double*)ar.take(1024 * sizeof(double));
+    {
+        // ||A||_F^2: partial sums of the separate pass (<= 1024) or of the first view's waves
+        QgemmDesc v1{};
+        v1.op = OP_NN; v1.math = MATH_F32; v1.M = pr.m; v1.N = d.l; v1.K = pr.n;
+        b.fro_part = (double*)ar.take(std::max<size_t>(1024, fro2_slots(v1)) * sizeof(double));
+    }
     b.Om = (float*)ar.take(4 * pr.n * d.l * sizeof(float));
     b.Q1 = (float*)ar.take(4 * pr.m * d.wmax * sizeof(float));
     b.Q2 = (float*)ar.take(4 * pr.n * d.wmax * sizeof(float));
@@ -272,6 +279,7 @@ void carve(const Problem& pr, const Dims& d, Arena& ar, Bufs& b, size_t part_byt
     b.Alo = lowp ? ar.take(lowp_copy_elems(pr.m, pr.n) * 2) : nullptr;
     b.Alo_t = lowp ? ar.take(lowp_copy_elems(pr.n, pr.m) * 2) : nullptr;
     b.lp_scale = (float*)ar.take(2 * sizeof(float));
+    b.phase_work = ar.take(phase_work_bytes(pr.n, pr.k));
     b.partial = part_bytes ? ar.take(part_bytes) : nullptr;
 }
 
@@ -382,7 +390,7 @@ void finish(Ctx& c, const Bufs& b, const Problem& pr, const double* R, int64_t w
     qg(c, desc(OP_NN, MATH_F64, Q1, ldq1, pr.m * ldq1, 0, Uh, w, w * w, 1, pr.U, pr.ldu, pr.ups, 0, pr.m, k, w));
     qg(c, desc(OP_NN, MATH_F64, Q2, ldq2, pr.n * ldq2, 0, Vh, w, w * w, 1, pr.V, pr.ldv, pr.vps, 0, pr.n, k, w));
     if (c.live()) {
-        note(c, phase_launch(pr.U, pr.m, pr.ldu, pr.ups, pr.V, pr.n, pr.ldv, pr.vps, k, c.st));
+        note(c, phase_launch(pr.U, pr.m, pr.ldu, pr.ups, pr.V, pr.n, pr.ldv, pr.vps, k, b.phase_work, c.st));
         note(c, copy_f64_launch(b.Sw, pr.S, k, c.st));
     }
 }
@@ -410,7 +418,7 @@ void finish_gram(Ctx& c, const Bufs& b, const Problem& pr, const float* Y, int64
     const int64_t ldox = y_is_u ? pr.ldv : pr.ldu, psox = y_is_u ? pr.vps : pr.ups;
     qg(c, desc(OP_NN, MATH_F64, Y, w, rows_y * w, 0, b.Lh, k, w * k, 1, Oy, ldoy, psoy, 0, rows_y, k, w));
     qg(c, desc(OP_NN, MATH_F64, X, ldx, rows_x * ldx, 0, b.Rh, lde, w * lde, 1, Ox, ldox, psox, 0, rows_x, k, w));
-    if (c.live()) note(c, phase_launch(pr.U, pr.m, pr.ldu, pr.ups, pr.V, pr.n, pr.ldv, pr.vps, k, c.st));
+    if (c.live()) note(c, phase_launch(pr.U, pr.m, pr.ldu, pr.ups, pr.V, pr.n, pr.ldv, pr.vps, k, b.phase_work, c.st));
 }
 
 // The product of a view alone: T = A X (forward, m x w) or T = A^H X (adjoint, n x w), ld w.
@@ -428,8 +436,15 @@ void view_product(Ctx& c, const Problem& pr, const Bufs& b, bool adjoint, const 
         qg(c, d);
         return;
     }
-    qg(c, desc(adjoint ? OP_HN : OP_NN, MATH_F32, pr.A, pr.lda, pr.aps, 0, X, ldx, kdim * ldx, 0, T, w, rows_out * w, 0,
-               rows_out, w, kdim));
+    QgemmDesc d = desc(adjoint ? OP_HN : OP_NN, MATH_F32, pr.A, pr.lda, pr.aps, 0, X, ldx, kdim * ldx, 0, T, w,
+                       rows_out * w, 0, rows_out, w, kdim);
+    const bool fro = c.fro_next && !adjoint;
+    if (fro) {
+        d.fro2_part = b.fro_part;
+        c.fro_next = false;
+    }
+    qg(c, d);
+    if (fro && c.live()) note(c, fro2_final_launch(b.fro_part, (int64_t)fro2_slots(d), b.nA2, c.st));
 }
 
 // One view: C = A X (forward) or C = A^H X (adjoint), then its QR.
@@ -442,10 +457,13 @@ void view(Ctx& c, const Problem& pr, const Bufs& b, bool adjoint, const float* X
 
 void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
     const int64_t l = d.l, l2 = l * l;
+    // ||A||_F^2: fused into the first view when that is an FP32 A X, else (the reduced-precision
+    // form, whose scale needs it first) one separate pass
+    c.fro_next = !b.Alo;
     if (c.live()) {
         note(c, fill_int_launch(b.status, 16, 0, c.st));
         note(c, fill_u32_launch(b.counters, (int64_t)std::max<size_t>(c.cnt_need, 1), c.st));
-        note(c, fro2_launch(pr.A, pr.m, pr.n, pr.lda, pr.aps, b.fro_part, b.nA2, c.st));
+        if (b.Alo) note(c, fro2_launch(pr.A, pr.m, pr.n, pr.lda, pr.aps, b.fro_part, b.nA2, c.st));
         note(c, omega_launch(pr.seed, pr.n, l, b.Om, l, pr.n * l, c.st));
         if (pr.estimate) note(c, nan_launch(pr.pass_err, c.st));
         if (b.Alo) {
@@ -565,7 +583,6 @@ int check_problem(const Problem& pr) {
     if (pr.v > 64) return QLRA_E_TOO_LARGE;
     if (pr.prec != QLRA_FP32 && pr.prec != QLRA_BF16 && pr.prec != QLRA_FP16) return QLRA_E_UNSUPPORTED;
     // the low-precision view kernel keeps all output columns of a view in one workgroup
-    if (pr.prec != QLRA_FP32 && pr.v > 2 && (int64_t)pr.k + pr.p > 96) return QLRA_E_UNSUPPORTED;
     return QLRA_OK;
 }
 
@@ -995,7 +1012,7 @@ static QgemmDesc lp_desc(int op, int precision, const void* Alo, int64_t m, int6
 }
 
 int qlra_qgemm_lp_workspace_size(int op, int precision, int64_t m, int64_t n, int64_t w, size_t* bytes) {
-    if (!bytes || (op != 0 && op != 1) || m < 0 || n < 0 || w < 0 || w > 96) return QLRA_E_ARG;
+    if (!bytes || (op != 0 && op != 1) || m < 0 || n < 0 || w < 0) return QLRA_E_ARG;
     if (precision != QLRA_BF16 && precision != QLRA_FP16) return QLRA_E_ARG;
     const QgemmDesc d = lp_desc(op, precision, nullptr, m, n, nullptr, w, w, 0, nullptr, w, 0, nullptr);
     *bytes = (m * n * w == 0) ? 0 : qgemm_partial_bytes(d);

@@ -200,55 +200,99 @@ __global__ __launch_bounds__(256) void k_fro2_final(const double* __restrict__ p
     if (threadIdx.x == 0) *out = red[0];
 }
 
-// One workgroup per column j of V: the entry of largest modulus (lowest row on ties) gives
-// nu; columns j of U and V are right-multiplied by conj(nu / |nu|).
-__global__ __launch_bounds__(256) void k_phase(float* U, int64_t m, int64_t ldu, int64_t ups, float* V,
-                                               int64_t n, int64_t ldv, int64_t vps) {
-    __shared__ double s_val[256];
-    __shared__ int64_t s_idx[256];
-    const int j = blockIdx.x;
+// Phase normalisation of the returned singular vectors: column j of U and V is right-multiplied
+// by conj(nu / |nu|), nu the entry of largest modulus of V(:, j) (lowest row on ties).  Two
+// coalesced passes: partial arg-max over row blocks of V (64 columns per block, a row read
+// whole), then each apply block combines the partials of its 64 columns in block order and
+// rotates its rows of U and V.
+struct PhasePart {
+    double val;
+    int64_t idx;
+    float q[4];
+};
+
+__device__ __forceinline__ bool phase_better(double v, int64_t i, double bv, int64_t bi) {
+    return v > bv || (v == bv && i < bi);
+}
+
+__global__ __launch_bounds__(256) void k_phase_part(const float* __restrict__ V, int64_t n, int64_t ldv, int64_t vps,
+                                                    int k, int64_t rows_per, PhasePart* __restrict__ part) {
+    __shared__ double sv[4][64];
+    __shared__ int64_t si[4][64];
+    const int c = threadIdx.x & 63, rs = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.y * 64 + c;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per;
+    const int64_t r1 = r0 + rows_per < n ? r0 + rows_per : n;
     double best = -1.0;
-    int64_t bi = 0;
-    for (int64_t i = threadIdx.x; i < n; i += 256) {
-        const float* v = V + i * ldv + j;
-        const double a = (double)v[0] * v[0] + (double)v[vps] * v[vps] + (double)v[2 * vps] * v[2 * vps] +
-                         (double)v[3 * vps] * v[3 * vps];
-        if (a > best) { best = a; bi = i; }
+    int64_t bi = r0;
+    if (j < k) {
+        for (int64_t i = r0 + rs; i < r1; i += 4) {
+            const float* v = V + i * ldv + j;
+            const double a = (double)v[0] * v[0] + (double)v[vps] * v[vps] + (double)v[2 * vps] * v[2 * vps] +
+                             (double)v[3 * vps] * v[3 * vps];
+            if (a > best) { best = a; bi = i; }
+        }
     }
-    s_val[threadIdx.x] = best;
-    s_idx[threadIdx.x] = bi;
+    sv[rs][c] = best;
+    si[rs][c] = bi;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) {
-            const double ov = s_val[threadIdx.x + o];
-            const int64_t oi = s_idx[threadIdx.x + o];
-            if (ov > s_val[threadIdx.x] || (ov == s_val[threadIdx.x] && oi < s_idx[threadIdx.x])) {
-                s_val[threadIdx.x] = ov;
-                s_idx[threadIdx.x] = oi;
+    if (rs == 0 && j < k) {
+        for (int t = 1; t < 4; t++)
+            if (phase_better(sv[t][c], si[t][c], best, bi)) { best = sv[t][c]; bi = si[t][c]; }
+        PhasePart pp;
+        pp.val = best;
+        pp.idx = bi;
+        const bool ok = best >= 0.0;
+        for (int t = 0; t < 4; t++) pp.q[t] = ok ? V[t * vps + bi * ldv + j] : 0.0f;
+        part[(int64_t)blockIdx.x * k + j] = pp;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_phase_apply(float* U, int64_t m, int64_t ldu, int64_t ups, float* V, int64_t n,
+                                                     int64_t ldv, int64_t vps, int k, const PhasePart* __restrict__ part,
+                                                     int nparts, int64_t rows_per_block) {
+    __shared__ double ph[4][64];
+    __shared__ int okf[64];
+    const int c = threadIdx.x & 63, rs = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.y * 64 + c;
+    if (rs == 0) {
+        double best = -1.0;
+        int64_t bi = 0;
+        float q[4] = {0, 0, 0, 0};
+        if (j < k) {
+            for (int t = 0; t < nparts; t++) {
+                const PhasePart pp = part[(int64_t)t * k + j];
+                if (pp.val >= 0.0 && phase_better(pp.val, pp.idx, best, bi)) {
+                    best = pp.val; bi = pp.idx;
+                    q[0] = pp.q[0]; q[1] = pp.q[1]; q[2] = pp.q[2]; q[3] = pp.q[3];
+                }
             }
         }
-        __syncthreads();
+        const bool ok = best > 0.0;
+        const double nrm = ok ? sqrt(best) : 1.0;
+        // conj(phase)
+        ph[0][c] = q[0] / nrm; ph[1][c] = -q[1] / nrm; ph[2][c] = -q[2] / nrm; ph[3][c] = -q[3] / nrm;
+        okf[c] = ok;
     }
-    const double bv = s_val[0];
-    if (!(bv > 0.0)) return;
-    const int64_t ib = s_idx[0];
-    const double nrm = sqrt(bv);
-    const float* vb = V + ib * ldv + j;
-    // conj(phase)
-    const double p0 = vb[0] / nrm, p1 = -vb[vps] / nrm, p2 = -vb[2 * vps] / nrm, p3 = -vb[3 * vps] / nrm;
     __syncthreads();
-    for (int side = 0; side < 2; side++) {
-        float* X = side ? V : U;
-        const int64_t rows = side ? n : m, ld = side ? ldv : ldu, ps = side ? vps : ups;
-        for (int64_t i = threadIdx.x; i < rows; i += 256) {
-            float* x = X + i * ld + j;
-            const double x0 = x[0], x1 = x[ps], x2 = x[2 * ps], x3 = x[3 * ps];
-            x[0] = (float)(x0 * p0 - x1 * p1 - x2 * p2 - x3 * p3);
-            x[ps] = (float)(x0 * p1 + x1 * p0 + x2 * p3 - x3 * p2);
-            x[2 * ps] = (float)(x0 * p2 - x1 * p3 + x2 * p0 + x3 * p1);
-            x[3 * ps] = (float)(x0 * p3 + x1 * p2 - x2 * p1 + x3 * p0);
-        }
+    if (j >= k || !okf[c]) return;
+    const double p0 = ph[0][c], p1 = ph[1][c], p2 = ph[2][c], p3 = ph[3][c];
+    const int64_t t0 = (int64_t)blockIdx.x * rows_per_block;
+    for (int64_t t = t0 + rs; t < t0 + rows_per_block && t < m + n; t += 4) {
+        const bool on_u = t < m;
+        float* x = on_u ? U + t * ldu + j : V + (t - m) * ldv + j;
+        const int64_t ps = on_u ? ups : vps;
+        const double x0 = x[0], x1 = x[ps], x2 = x[2 * ps], x3 = x[3 * ps];
+        x[0] = (float)(x0 * p0 - x1 * p1 - x2 * p2 - x3 * p3);
+        x[ps] = (float)(x0 * p1 + x1 * p0 + x2 * p3 - x3 * p2);
+        x[2 * ps] = (float)(x0 * p2 - x1 * p3 + x2 * p0 + x3 * p1);
+        x[3 * ps] = (float)(x0 * p3 + x1 * p2 - x2 * p1 + x3 * p0);
     }
+}
+
+int64_t phase_rows_per(int64_t n) {
+    const int64_t r = (n + 255) / 256;
+    return r < 64 ? 64 : r;
 }
 
 }  // namespace
@@ -292,10 +336,27 @@ hipError_t fro2_launch(const float* A, int64_t m, int64_t n, int64_t lda, int64_
     return hipGetLastError();
 }
 
+hipError_t fro2_final_launch(const double* partial, int64_t nb, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_fro2_final, dim3(1), dim3(256), 0, st, partial, (int)nb, out);
+    return hipGetLastError();
+}
+
+size_t phase_work_bytes(int64_t n, int k) {
+    const int64_t rp = phase_rows_per(n);
+    return (size_t)((n + rp - 1) / rp) * (size_t)k * sizeof(PhasePart);
+}
+
 hipError_t phase_launch(float* U, int64_t m, int64_t ldu, int64_t ups, float* V, int64_t n, int64_t ldv,
-                        int64_t vps, int k, hipStream_t st) {
-    if (k <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_phase, dim3((unsigned)k), dim3(256), 0, st, U, m, ldu, ups, V, n, ldv, vps);
+                        int64_t vps, int k, void* work, hipStream_t st) {
+    if (k <= 0 || n <= 0) return hipSuccess;
+    const int64_t rp = phase_rows_per(n);
+    const int64_t nparts = (n + rp - 1) / rp;
+    const unsigned gyc = (unsigned)((k + 63) / 64);
+    PhasePart* part = (PhasePart*)work;
+    hipLaunchKernelGGL(k_phase_part, dim3((unsigned)nparts, gyc), dim3(256), 0, st, V, n, ldv, vps, k, rp, part);
+    const int64_t rb = 64;
+    hipLaunchKernelGGL(k_phase_apply, dim3((unsigned)((m + n + rb - 1) / rb), gyc), dim3(256), 0, st, U, m, ldu, ups,
+                       V, n, ldv, vps, k, (const PhasePart*)part, (int)nparts, rb);
     return hipGetLastError();
 }
 

@@ -1,0 +1,160 @@
+"""The 16384 x 16384 workload at full size: dense quaternion FP32, sigma_i = i^-1/2, block Krylov
+(Alg. 4) with k = 128, p = 32 and a budget of 8 views (final stack of 4 x 160 = 640 columns).
+
+The FP64 oracle cannot run at this size inside a test, so parity is checked on sampled outputs
+the oracle computes one by one, and on properties that hold at any size, evaluated in FP64 on
+the device from A itself:
+- the sketch Omega (16384 x 160) is bit-exact with the oracle's;
+- sampled rows of A X and columns of A^H X agree with the oracle's products of the same rows /
+  columns, to FP32 accumulation error;
+- U and V have orthonormal columns;
+- U^H A V = diag(S): the returned factors are the exact truncated projection (U = Q Uh and
+  V = Q2 Vh with TSVD(R2) = Vh S Uh^H, so Uh^H R2^H Vh = S), up to FP32 rounding;
+- the last estimate e_v is ||A - U S V^H||_F / ||A||_F, here computed directly from
+  ||A||^2 - 2 sum_j S_j Re(U^H A V)_jj + sum_j S_j^2;
+- Eckart-Young: e_v is at least the optimal rank-k error sqrt(sum_{i>k} sigma_i^2) / ||A||, and
+  no returned singular value exceeds the true one (the spectrum is known exactly).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+NN = 16384
+K, P, V = 128, 32, 8
+L = K + P
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def gq():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_13731_amd import qlra as Q
+    return Q
+
+
+@pytest.fixture(scope="module")
+def big():
+    import torch
+    from workloads import gpu as WG
+    print("generating the 16384 x 16384 matrix", flush=True)
+    sigma = np.arange(1, NN + 1, dtype=np.float64) ** -0.5
+    A = WG.spectrum_matrix(4, NN, NN, sigma)
+    torch.cuda.synchronize()
+    return A, sigma
+
+
+def as_pair(X):
+    """(4, r, c) real planes -> complex128 pair (a, b) with X = a + b j."""
+    import torch
+    X = X.to(torch.float64)
+    return torch.complex(X[0], X[1]), torch.complex(X[2], X[3])
+
+
+def qmul(Xa, Xb, Ya, Yb):
+    import torch
+    return Xa @ Ya - Xb @ torch.conj(Yb), Xa @ Yb + Xb @ torch.conj(Ya)
+
+
+def qadj(Xa, Xb):
+    import torch
+    return torch.conj(Xa.T).contiguous(), (-Xb.T).contiguous()
+
+
+def test_omega_full_size(gq, oracle):
+    print(f"omega {NN} x {L}", flush=True)
+    got = gq.qlra_omega(7, NN, L).cpu().numpy()
+    assert np.array_equal(got, oracle.omega(7, NN, L))
+
+
+@pytest.mark.parametrize("op", [0, 1])
+def test_view_full_size_sampled(gq, oracle, big, op):
+    import torch
+    A, _ = big
+    print(f"view op={op} {NN} x {NN} by {L}, sampled", flush=True)
+    X = torch.from_numpy(oracle.omega(3, NN, L)).cuda()
+    C = gq.qlra_qgemm(op, A, X)
+    torch.cuda.synchronize()
+    idx = np.array([0, 1, 777, 4095, 8191, 12000, NN - 2, NN - 1])
+    Xh = X.cpu().numpy().astype(np.float64)
+    if op == 0:
+        As = A[:, idx, :].cpu().numpy().astype(np.float64)          # rows of A
+        ref = oracle.qgemm(As, Xh)
+        bound = np.abs(As).sum(0) @ np.abs(Xh).sum(0)
+    else:
+        As = A[:, :, idx].cpu().numpy().astype(np.float64)          # columns of A
+        ref = oracle.qgemm_adj(As, Xh)
+        bound = np.abs(As).sum(0).T @ np.abs(Xh).sum(0)
+    got = C[:, idx, :].cpu().numpy().astype(np.float64)
+    tol = 8 * U32 * np.sqrt(4 * NN) * bound
+    assert np.all(np.abs(got - ref) <= tol[None])
+
+
+def solve(gq, A, precision):
+    import torch
+    print(f"solve {NN} x {NN} k={K} p={P} v={V} krylov precision={precision}", flush=True)
+    U, S, Vm, e, ws = gq.qlra(A, K, P, V, 1, 11, precision=precision, graph=False)
+    st = gq.qlra_status(ws)
+    torch.cuda.synchronize()
+    del ws
+    return U, S, Vm, e, st
+
+
+def properties(A, sigma, U, S, Vm, e):
+    """Orthonormality, U^H A V = diag(S), the direct residual and Eckart-Young; returns the
+    direct relative error."""
+    import torch
+    Ua, Ub = as_pair(U)
+    Va, Vb = as_pair(Vm)
+    for Xa, Xb in ((Ua, Ub), (Va, Vb)):
+        Ga, Gb = qmul(*qadj(Xa, Xb), Xa, Xb)
+        eye = torch.eye(K, dtype=torch.complex128, device=Ga.device)
+        assert float(torch.abs(Ga - eye).max()) < 1e-4 and float(torch.abs(Gb).max()) < 1e-4
+    Aa, Ab = as_pair(A)
+    nA2 = float(torch.sum(torch.abs(Aa) ** 2 + torch.abs(Ab) ** 2))
+    Ta, Tb = qmul(Aa, Ab, Va, Vb)                  # A V, 16384 x 128
+    del Aa, Ab
+    Da, Db = qmul(*qadj(Ua, Ub), Ta, Tb)           # U^H A V, 128 x 128
+    Sd = S.to(torch.float64)
+    diag = torch.diag(Sd).to(torch.complex128)
+    off = max(float(torch.abs(Da - diag).max()), float(torch.abs(Db).max()))
+    assert off <= 1e-4 * float(Sd[0])
+    s = S.cpu().numpy()
+    assert np.all(np.diff(s) <= 0) and s[-1] > 0
+    assert np.all(s <= sigma[:K] * (1 + 1e-5))
+    direct2 = nA2 - 2 * float(torch.sum(Sd * Da.diagonal().real)) + float(torch.sum(Sd * Sd))
+    direct = np.sqrt(max(direct2, 0.0) / nA2)
+    ev = e.cpu().numpy()
+    assert np.isnan(ev[0]) and np.all(np.isfinite(ev[1:]))
+    # e_v^2 = 1 - sum S^2 / ||A||^2 differs from direct^2 by 2 sum S (S - Re D_jj) / ||A||^2, plus
+    # FP32 roundoff of ||A||^2 and of the S_j
+    gap = 2 * float(torch.sum(Sd * torch.abs(Sd - Da.diagonal().real))) / nA2
+    assert abs(ev[-1] ** 2 - direct ** 2) <= gap + 64 * U32
+    opt = np.sqrt(np.sum(sigma[K:] ** 2) / np.sum(sigma ** 2))
+    assert direct >= opt * (1 - 1e-5)
+    print(f"  e_v {ev[-1]:.8f} direct {direct:.8f} optimum {opt:.8f}", flush=True)
+    return direct
+
+
+_ERR = {}
+
+
+def test_solve_full_size_fp32(gq, big):
+    A, sigma = big
+    U, S, Vm, e, st = solve(gq, A, gq.QLRA_FP32)
+    assert st == gq.QLRA_OK
+    _ERR["fp32"] = properties(A, sigma, U, S, Vm, e)
+
+
+def test_solve_full_size_bf16(gq, big):
+    """Views 1 .. 6 on the BF16 copies (two column tiles of 80), views 7 and 8 FP32: the same
+    properties, and an error within 5 % of the FP32 path's."""
+    A, sigma = big
+    U, S, Vm, e, st = solve(gq, A, gq.QLRA_BF16)
+    assert st == gq.QLRA_OK
+    err = properties(A, sigma, U, S, Vm, e)
+    if "fp32" in _ERR:
+        print(f"  error ratio to FP32 {err / _ERR['fp32']:.8f}", flush=True)
+        assert err / _ERR["fp32"] <= 1.05

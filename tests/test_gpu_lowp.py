@@ -92,7 +92,8 @@ def test_lowp_copy_bit_exact(gq, prec, m, n):
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 @pytest.mark.parametrize("op", [0, 1])
-@pytest.mark.parametrize("m,n,w", [(300, 200, 15), (512, 1024, 60), (1000, 777, 80), (640, 900, 96), (64, 2048, 1)])
+@pytest.mark.parametrize("m,n,w", [(300, 200, 15), (512, 1024, 60), (1000, 777, 80), (640, 900, 96), (64, 2048, 1),
+                                   (700, 500, 100), (400, 1300, 160)])
 def test_qgemm_lp_against_rounded_oracle(gq, oracle, prec, op, m, n, w):
     import torch
     print(f"qgemm_lp {prec} op={op} {m}x{n} w={w}", flush=True)
@@ -188,6 +189,22 @@ def test_lowp_solve_config1_error_ratio(gq, oracle, prec, v):
     assert st == gq.QLRA_OK
     A = A32.astype(np.float64)
     Uo, So, Vo, eo = oracle.qlra(A, 50, 10, v, 0, 1)
+    ratio = rel_err(oracle, A, Ug, Sg, Vg) / rel_err(oracle, A, Uo, So, Vo)
+    print(f"  error ratio {ratio:.8f}", flush=True)
+    assert ratio <= 1.05
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_lowp_solve_wide_views(gq, oracle, prec):
+    """k + p = 110 (views of two column tiles): error ratio to the FP64 oracle <= 1.05."""
+    print(f"lowp wide views {prec}", flush=True)
+    m, n = 500, 420
+    sigma = np.concatenate([np.linspace(1.0, 0.3, 100), 1e-2 / np.arange(1, n - 99)])
+    A32 = np.ascontiguousarray(W.spectrum_matrix(23, m, n, sigma, nrefl=6), dtype=np.float32)
+    Ug, Sg, Vg, eg, st = run_gpu(gq, A32, 100, 10, 5, 0, 4, PREC[prec])
+    assert st == gq.QLRA_OK
+    A = A32.astype(np.float64)
+    Uo, So, Vo, eo = oracle.qlra(A, 100, 10, 5, 0, 4)
     ratio = rel_err(oracle, A, Ug, Sg, Vg) / rel_err(oracle, A, Uo, So, Vo)
     print(f"  error ratio {ratio:.8f}", flush=True)
     assert ratio <= 1.05
