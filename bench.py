@@ -18,6 +18,7 @@ reported beside it with its error ratio to the oracle.
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -85,9 +86,10 @@ def counters_run(Q, torch, A):
 
 
 def pmc_summary(fetch_csv, write_csv):
-    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) from two rocprofv3 --pmc runs of --counters.
-    The view product is its product kernel plus the ordered split-K reduction; the copy kernel's
-    readings give the factor that turns each counter into bytes."""
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) from two rocprofv3 --pmc runs of --counters
+    (CSV output).  A view is the thin-block transpose, the product kernel and the ordered split-K
+    reduction; the elementwise pass's readings give the factor that turns each counter into
+    bytes."""
     import csv
     import statistics
 
@@ -103,7 +105,7 @@ def pmc_summary(fetch_csv, write_csv):
     out = {}
     for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         seq = read(path, counter)
-        view = [(n, v) for n, v in seq if "k_qgemm" in n or "k_splitk_reduce" in n]
+        view = [(n, v) for n, v in seq if any(t in n for t in ("k_thin_t", "k_qview", "k_splitk_reduce"))]
         copies = [v for _, v in seq[-COUNTER_REPS:]]     # the calibration copies end the sequence
         kib_copy = statistics.median(copies)
         scale = COPY_BYTES / (kib_copy * 1024.0)
@@ -112,10 +114,17 @@ def pmc_summary(fetch_csv, write_csv):
             part = view[op * len(view) // 2:(op + 1) * len(view) // 2]
             kib = sum(v for _, v in part) / COUNTER_REPS
             per_op[name] = {"kib_per_launch": round(kib, 1), "bytes_per_launch": round(kib * 1024.0 * scale),
-                            "kernels": sorted({n.split("(")[0][-60:] for n, _ in part})}
+                            "kernels": sorted({re.search(r"k_\w+", n).group(0) for n, _ in part})}
         out[counter] = {"copy_kib": round(kib_copy, 1), "scale": round(scale, 4), **per_op}
     hbm = 0.5 * sum(out[c][o]["bytes_per_launch"] for c in ("FETCH_SIZE", "WRITE_SIZE") for o in ("forward", "adjoint"))
-    rec = {"kernel": "FP32 view product 2048x2048 by 60 (product kernel + split-K reduction), mean of A X and A^H X",
+    rec = {"kernel": "FP32 view product 2048x2048 by 60 (transpose + product kernel + split-K reduction), "
+                     "mean of A X and A^H X",
+           "commands": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d <repo>/gpurun_out/"
+                        "pmc_fetch -o f -- python3 <repo>/bench.py --counters",
+                        "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d <repo>/gpurun_out/"
+                        "pmc_write -o w -- python3 <repo>/bench.py --counters",
+                        "python bench.py --pmc-summary gpurun_out/pmc_fetch/f_counter_collection.csv "
+                        "gpurun_out/pmc_write/w_counter_collection.csv"],
            "kernel_source_hash": kernel_source_hash(), "hbm_bytes_per_launch": round(hbm),
            "algorithmic_bytes_per_launch": 16 * M * N + 2 * 16 * N * (K_RANK + P_OVER), **out}
     os.makedirs(os.path.dirname(PMC_FILE), exist_ok=True)

@@ -402,7 +402,11 @@ __global__ __launch_bounds__(256, CN <= 3 ? 2 : 1) void k_qview(VParams P) {
     if (P.skip && *P.skip == 0) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kw = P.kw;
-    const int64_t tile_raw = (int64_t)blockIdx.x * (4 / kw) + wave / kw;
+    // workgroups go round-robin to the 8 XCDs; give each XCD a contiguous run of row tiles so that
+    // neighbouring tiles (which share 128-byte lines of A in A^H X) meet in the same L2
+    const int64_t G = gridDim.x;
+    const int64_t bx = (G % 8 == 0) ? (int64_t)(blockIdx.x % 8) * (G / 8) + blockIdx.x / 8 : (int64_t)blockIdx.x;
+    const int64_t tile_raw = bx * (4 / kw) + wave / kw;
     const bool tile_ok = tile_raw < P.tiles;
     const int64_t tile = tile_ok ? tile_raw : P.tiles - 1;
     const int kpart = wave % kw;
@@ -541,7 +545,7 @@ __global__ __launch_bounds__(256, CN <= 3 ? 2 : 1) void k_qview(VParams P) {
         fro *= fro_w;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) fro += __shfl_xor(fro, o, 64);
-        if (lane == 0) P.fro[((int64_t)blockIdx.z * gridDim.x + blockIdx.x) * 4 + wave] = fro;
+        if (lane == 0) P.fro[((int64_t)blockIdx.z * gridDim.x + bx) * 4 + wave] = fro;
     }
 
     if (kw > 1) {
