@@ -302,6 +302,23 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const T* __restrict__ par
     }
 }
 
+// Few splits (<= 8): one thread per output, the splits added in order.
+template <class T, class TC>
+__global__ __launch_bounds__(256) void k_splitk_reduce_few(const T* __restrict__ part, int splits, int64_t Mp,
+                                                           int64_t Np, TC* __restrict__ C, int64_t ldc, int64_t cps,
+                                                           int64_t M, int64_t N, int store, const int* skip) {
+    if (skip && *skip == 0) return;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 4 * M * N) return;
+    const int64_t p = e / (M * N), rem = e - p * M * N, r = rem / N, c = rem - r * N;
+    const int64_t stride = 4 * Mp * Np;
+    const T* src = part + (p * Mp + r) * Np + c;
+    T s = src[0];
+    for (int sp = 1; sp < splits; sp++) s += src[sp * stride];
+    TC* dst = C + p * cps + r * ldc + c;
+    *dst = store == ST_SUB ? (TC)((T)*dst - s) : (TC)s;
+}
+
 // The same sum for FP32 partials and outputs whose rows are 16-byte aligned: one thread per
 // four consecutive outputs, the splits added in order (deterministic).
 __global__ __launch_bounds__(256) void k_splitk_reduce4(const float* __restrict__ part, int splits, int64_t Mp,
@@ -648,6 +665,13 @@ hipError_t launch_t(const Plan& pl, const KParams& kp, hipStream_t st) {
     if constexpr (std::is_same<T, float>::value && std::is_same<TC, float>::value)
         return reduce_f32((const float*)kp.part, (int)pl.splits, pl.Mp, pl.Np, (float*)kp.C, kp.ldc, kp.cps, kp.M,
                           kp.N, kp.store, kp.skip, st);
+    if (pl.splits <= 8) {
+        const int64_t total = 4 * kp.M * kp.N;
+        hipLaunchKernelGGL((k_splitk_reduce_few<T, TC>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                           (const T*)kp.part, (int)pl.splits, pl.Mp, pl.Np, (TC*)kp.C, kp.ldc, kp.cps, kp.M, kp.N,
+                           kp.store, kp.skip);
+        return hipGetLastError();
+    }
     const int64_t total = 8 * 4 * kp.M * kp.N;
     hipLaunchKernelGGL((k_splitk_reduce<T, TC>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
                        (const T*)kp.part, (int)pl.splits, pl.Mp, pl.Np, (TC*)kp.C, kp.ldc, kp.cps, kp.M, kp.N,

@@ -251,16 +251,20 @@ __global__ __launch_bounds__(256) void k_phase_part(const float* __restrict__ V,
 __global__ __launch_bounds__(256) void k_phase_apply(float* U, int64_t m, int64_t ldu, int64_t ups, float* V, int64_t n,
                                                      int64_t ldv, int64_t vps, int k, const PhasePart* __restrict__ part,
                                                      int nparts, int64_t rows_per_block) {
+    __shared__ double sv[4][64];
+    __shared__ int64_t si[4][64];
+    __shared__ float sq[4][4][64];
     __shared__ double ph[4][64];
     __shared__ int okf[64];
     const int c = threadIdx.x & 63, rs = threadIdx.x >> 6;
     const int64_t j = (int64_t)blockIdx.y * 64 + c;
-    if (rs == 0) {
+    {
+        // the four row groups scan interleaved quarters of the partial arg-maxes
         double best = -1.0;
         int64_t bi = 0;
         float q[4] = {0, 0, 0, 0};
         if (j < k) {
-            for (int t = 0; t < nparts; t++) {
+            for (int t = rs; t < nparts; t += 4) {
                 const PhasePart pp = part[(int64_t)t * k + j];
                 if (pp.val >= 0.0 && phase_better(pp.val, pp.idx, best, bi)) {
                     best = pp.val; bi = pp.idx;
@@ -268,10 +272,22 @@ __global__ __launch_bounds__(256) void k_phase_apply(float* U, int64_t m, int64_
                 }
             }
         }
+        sv[rs][c] = best;
+        si[rs][c] = bi;
+        for (int t = 0; t < 4; t++) sq[rs][t][c] = q[t];
+    }
+    __syncthreads();
+    if (rs == 0) {
+        double best = sv[0][c];
+        int64_t bi = si[0][c];
+        int from = 0;
+        for (int t = 1; t < 4; t++)
+            if (sv[t][c] >= 0.0 && phase_better(sv[t][c], si[t][c], best, bi)) { best = sv[t][c]; bi = si[t][c]; from = t; }
         const bool ok = best > 0.0;
         const double nrm = ok ? sqrt(best) : 1.0;
         // conj(phase)
-        ph[0][c] = q[0] / nrm; ph[1][c] = -q[1] / nrm; ph[2][c] = -q[2] / nrm; ph[3][c] = -q[3] / nrm;
+        ph[0][c] = sq[from][0][c] / nrm; ph[1][c] = -sq[from][1][c] / nrm;
+        ph[2][c] = -sq[from][2][c] / nrm; ph[3][c] = -sq[from][3][c] / nrm;
         okf[c] = ok;
     }
     __syncthreads();
@@ -292,7 +308,7 @@ __global__ __launch_bounds__(256) void k_phase_apply(float* U, int64_t m, int64_
 
 int64_t phase_rows_per(int64_t n) {
     const int64_t r = (n + 255) / 256;
-    return r < 64 ? 64 : r;
+    return r < 32 ? 32 : r;
 }
 
 }  // namespace
