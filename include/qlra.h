@@ -69,11 +69,20 @@ typedef struct {
     int graph;               /* nonzero: capture the solve as a HIP graph on first use and
                                 replay it when a later call has identical arguments (same
                                 pointers, sizes, seed); the library keeps up to 32 graphs  */
+    int transpose;           /* nonzero: run the scheme on A^H (the sketch is m x l and the
+                                first view is A^H Omega, cheaper when n > m); U and V are
+                                still the left and right factors of A.  The results differ
+                                from transpose = 0 (another sketch), not the guarantees     */
 } qlra_opts_t;
 
 /* Bytes of device workspace a qlra() call with these sizes needs (written to
- * *bytes).  Depends only on m, n, k, p, pass_budget, scheme and
- * opts->pass_precision (opts may be NULL: FP32 with estimates). */
+ * *bytes).  Depends only on m, n, k, p, pass_budget, scheme, opts->pass_precision
+ * and opts->transpose (opts may be NULL: FP32 with estimates, A as given).
+ *
+ * The classical forms are budgets of these two schemes: randomized subspace
+ * iteration with q power iterations (Alg. 1) is QLRA_SUBSPACE with
+ * pass_budget = 2q + 2, and the block Krylov method with q iterations (Alg. 3)
+ * spans the same subspace as QLRA_BLOCK_KRYLOV with pass_budget = 2q + 2. */
 int qlra_workspace_size(int64_t m, int64_t n, int k, int p, int pass_budget, int scheme,
                         const qlra_opts_t* opts, size_t* bytes);
 

@@ -123,10 +123,10 @@ __device__ __forceinline__ double lpr_sum(double v) {
     return v;
 }
 
-template <int LPR, int NCOL>
-__global__ __launch_bounds__(LPR == 16 ? 1024 : 768)
+template <int LPR, int NCOL, int NT>
+__global__ __launch_bounds__(NT)
 void k_tridiag(const double* __restrict__ Gall, int64_t gstride, int w, double* __restrict__ triall, int store_refl) {
-    constexpr int NT = LPR == 16 ? 1024 : 768;
+    static_assert(NT / LPR == LPR * NCOL, "the thread grid covers a square of rows x columns");
     constexpr int RPW = 64 / LPR;           // rows per wave
     constexpr int TW = NT / 64;             // waves
     __shared__ double xb[4 * kW];           // column j below the diagonal
@@ -637,9 +637,9 @@ size_t heig_work_doubles(int64_t nprob) { return (size_t)nprob * kTriStride; }
 hipError_t heig_launch(const double* G, int64_t w, double* lam, double* E, double* work, hipStream_t st) {
     if (w < 1 || w > kW) return hipErrorInvalidValue;
     if (w <= 64)
-        hipLaunchKernelGGL((k_tridiag<16, 4>), dim3(1), dim3(1024), 0, st, G, (int64_t)0, (int)w, work, E ? 1 : 0);
+        hipLaunchKernelGGL((k_tridiag<16, 4, 1024>), dim3(1), dim3(1024), 0, st, G, (int64_t)0, (int)w, work, E ? 1 : 0);
     else
-        hipLaunchKernelGGL((k_tridiag<8, 12>), dim3(1), dim3(768), 0, st, G, (int64_t)0, (int)w, work, E ? 1 : 0);
+        hipLaunchKernelGGL((k_tridiag<8, 12, 768>), dim3(1), dim3(768), 0, st, G, (int64_t)0, (int)w, work, E ? 1 : 0);
     const unsigned slices = (unsigned)((w + kPer - 1) / kPer);
     hipLaunchKernelGGL(k_eigvals, dim3(slices, 1), dim3(ET), 0, st, work, (int)w, lam, (int64_t)0);
     if (E)
@@ -653,9 +653,9 @@ hipError_t estimate_batch_launch(const double* G, int64_t gstride, int64_t w, in
     if (nprob <= 0) return hipSuccess;
     if (w < 1 || w > kW) return hipErrorInvalidValue;
     if (w <= 64)
-        hipLaunchKernelGGL((k_tridiag<16, 4>), dim3((unsigned)nprob), dim3(1024), 0, st, G, gstride, (int)w, work, 0);
+        hipLaunchKernelGGL((k_tridiag<16, 4, 1024>), dim3((unsigned)nprob), dim3(1024), 0, st, G, gstride, (int)w, work, 0);
     else
-        hipLaunchKernelGGL((k_tridiag<8, 12>), dim3((unsigned)nprob), dim3(768), 0, st, G, gstride, (int)w, work, 0);
+        hipLaunchKernelGGL((k_tridiag<8, 12, 768>), dim3((unsigned)nprob), dim3(768), 0, st, G, gstride, (int)w, work, 0);
     const unsigned slices = (unsigned)((w + kPer - 1) / kPer);
     hipLaunchKernelGGL(k_eigvals, dim3(slices, (unsigned)nprob), dim3(ET), 0, st, work, (int)w, (double*)nullptr,
                        (int64_t)0);

@@ -164,7 +164,11 @@ void orth_stack(Ctx& c, float* K, int64_t rows, int64_t W, int64_t l, double* Cb
 // solve layout
 
 struct Problem {
+    // m, n, U, V: the matrix the scheme runs on (A, or A^H when transpose is set) and its factors;
+    // A, mr, nr, lda, aps: A as stored
     const float* A; int64_t m, n, lda, aps;
+    int transpose;
+    int64_t mr, nr;
     int k, p, v, scheme;
     uint64_t seed;
     float* U; int64_t ldu, ups;
@@ -174,6 +178,18 @@ struct Problem {
     int estimate;
     int prec;               // QLRA_FP32, QLRA_BF16 or QLRA_FP16 for views 1 .. v-2
 };
+
+// Run the scheme on A^H: swap the logical sizes and the two factors (A^H = V S U^H).
+void orient(Problem& pr, int transpose) {
+    pr.mr = pr.m;
+    pr.nr = pr.n;
+    pr.transpose = transpose ? 1 : 0;
+    if (!pr.transpose) return;
+    std::swap(pr.m, pr.n);
+    std::swap(pr.U, pr.V);
+    std::swap(pr.ldu, pr.ldv);
+    std::swap(pr.ups, pr.vps);
+}
 
 struct Dims {
     int64_t l, Wk, wmax, rows_max, stack_rows;
@@ -276,8 +292,8 @@ void carve(const Problem& pr, const Dims& d, Arena& ar, Bufs& b, size_t part_byt
                      ? (double*)ar.take(heig_big_work_doubles(wf, big_nvec(wf, pr.k)) * sizeof(double))
                      : nullptr;
     const bool lowp = pr.prec != QLRA_FP32 && pr.v > 2;
-    b.Alo = lowp ? ar.take(lowp_copy_elems(pr.m, pr.n) * 2) : nullptr;
-    b.Alo_t = lowp ? ar.take(lowp_copy_elems(pr.n, pr.m) * 2) : nullptr;
+    b.Alo = lowp ? ar.take(lowp_copy_elems(pr.mr, pr.nr) * 2) : nullptr;
+    b.Alo_t = lowp ? ar.take(lowp_copy_elems(pr.nr, pr.mr) * 2) : nullptr;
     b.lp_scale = (float*)ar.take(2 * sizeof(float));
     b.phase_work = ar.take(phase_work_bytes(pr.n, pr.k));
     b.partial = part_bytes ? ar.take(part_bytes) : nullptr;
@@ -311,7 +327,7 @@ hipError_t get_side(Side* out) {
 struct GraphKey {
     int dev;
     const void* A; int64_t m, n, lda, aps;
-    int k, p, v, scheme, estimate, prec;
+    int k, p, v, scheme, estimate, prec, transpose;
     uint64_t seed;
     const void* U; int64_t ldu, ups;
     const void* S;
@@ -428,17 +444,19 @@ void view_product(Ctx& c, const Problem& pr, const Bufs& b, bool adjoint, const 
     c.views++;
     const int64_t rows_out = adjoint ? pr.n : pr.m;
     const int64_t kdim = adjoint ? pr.m : pr.n;
+    // the product with A as stored: a view of A^H is the other orientation of A
+    const bool adj = adjoint != (pr.transpose != 0);
     if (lowp) {
-        QgemmDesc d = desc(adjoint ? OP_HN : OP_NN, pr.prec == QLRA_BF16 ? MATH_BF16 : MATH_F16,
-                           adjoint ? b.Alo_t : b.Alo, kdim, pr.m * pr.n, 0, X, ldx, kdim * ldx, 0, T, w, rows_out * w, 0,
+        QgemmDesc d = desc(adj ? OP_HN : OP_NN, pr.prec == QLRA_BF16 ? MATH_BF16 : MATH_F16,
+                           adj ? b.Alo_t : b.Alo, kdim, pr.m * pr.n, 0, X, ldx, kdim * ldx, 0, T, w, rows_out * w, 0,
                            rows_out, w, kdim);
         d.cscale = b.lp_scale ? b.lp_scale + 1 : nullptr;
         qg(c, d);
         return;
     }
-    QgemmDesc d = desc(adjoint ? OP_HN : OP_NN, MATH_F32, pr.A, pr.lda, pr.aps, 0, X, ldx, kdim * ldx, 0, T, w,
+    QgemmDesc d = desc(adj ? OP_HN : OP_NN, MATH_F32, pr.A, pr.lda, pr.aps, 0, X, ldx, kdim * ldx, 0, T, w,
                        rows_out * w, 0, rows_out, w, kdim);
-    const bool fro = c.fro_next && !adjoint;
+    const bool fro = c.fro_next && !adj;
     if (fro) {
         d.fro2_part = b.fro_part;
         c.fro_next = false;
@@ -458,17 +476,18 @@ void view(Ctx& c, const Problem& pr, const Bufs& b, bool adjoint, const float* X
 void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
     const int64_t l = d.l, l2 = l * l;
     // ||A||_F^2: fused into the first view when that is an FP32 A X, else (the reduced-precision
-    // form, whose scale needs it first) one separate pass
-    c.fro_next = !b.Alo;
+    // form, whose scale needs it first, or the scheme on A^H) one separate pass
+    const bool fro_apart = b.Alo || pr.transpose;
+    c.fro_next = !fro_apart;
     if (c.live()) {
         note(c, fill_int_launch(b.status, 16, 0, c.st));
         note(c, fill_u32_launch(b.counters, (int64_t)std::max<size_t>(c.cnt_need, 1), c.st));
-        if (b.Alo) note(c, fro2_launch(pr.A, pr.m, pr.n, pr.lda, pr.aps, b.fro_part, b.nA2, c.st));
+        if (fro_apart) note(c, fro2_launch(pr.A, pr.mr, pr.nr, pr.lda, pr.aps, b.fro_part, b.nA2, c.st));
         note(c, omega_launch(pr.seed, pr.n, l, b.Om, l, pr.n * l, c.st));
         if (pr.estimate) note(c, nan_launch(pr.pass_err, c.st));
         if (b.Alo) {
             note(c, lowp_scale_launch(b.nA2, pr.prec, b.lp_scale, b.lp_scale + 1, c.st));
-            note(c, lowp_copy_launch(pr.A, pr.m, pr.n, pr.lda, pr.aps, pr.prec, b.Alo, b.Alo_t, b.lp_scale, c.st));
+            note(c, lowp_copy_launch(pr.A, pr.mr, pr.nr, pr.lda, pr.aps, pr.prec, b.Alo, b.Alo_t, b.lp_scale, c.st));
         }
     }
     // views 1 .. v-2 in reduced precision when asked; the last two keep FP32
@@ -828,9 +847,10 @@ int qlra_workspace_size(int64_t m, int64_t n, int k, int p, int pass_budget, int
     pr.lda = n; pr.aps = m * n; pr.ldu = k; pr.ups = m * k; pr.ldv = k; pr.vps = n * k;
     pr.estimate = opts ? opts->estimate_passes : 1;
     pr.prec = opts ? opts->pass_precision : QLRA_FP32;
+    orient(pr, opts ? opts->transpose : 0);
     int rc = check_problem(pr);
     if (rc) return rc;
-    const Dims d = dims_of(m, n, k, p, pass_budget, scheme);
+    const Dims d = dims_of(pr.m, pr.n, k, p, pass_budget, scheme);
     size_t part, cnt, total;
     size_solve(pr, d, &part, &cnt, &total);
     *bytes = total;
@@ -855,7 +875,8 @@ int qlra(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stri
     if ((rc = check_layout(U, m, k, ldu, u_plane_stride))) return rc;
     if ((rc = check_layout(V, n, k, ldv, v_plane_stride))) return rc;
     if (!S) return QLRA_E_ARG;
-    const Dims d = dims_of(m, n, k, p, pass_budget, scheme);
+    orient(pr, opts->transpose);
+    const Dims d = dims_of(pr.m, pr.n, k, p, pass_budget, scheme);
     size_t part, cnt, total;
     size_solve(pr, d, &part, &cnt, &total);
     if (!opts->workspace || opts->workspace_bytes < total || ((uintptr_t)opts->workspace & 255))
@@ -890,6 +911,7 @@ int qlra(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stri
     key.A = A; key.m = m; key.n = n; key.lda = lda; key.aps = a_plane_stride;
     key.k = k; key.p = p; key.v = pass_budget; key.scheme = scheme; key.estimate = pr.estimate; key.seed = seed;
     key.prec = pr.prec;
+    key.transpose = pr.transpose;
     key.U = U; key.ldu = ldu; key.ups = u_plane_stride; key.S = S; key.V = V; key.ldv = ldv;
     key.vps = v_plane_stride; key.pass_err = pass_err; key.ws = opts->workspace;
     std::lock_guard<std::mutex> lk(g_graph_mu);
@@ -1149,6 +1171,7 @@ int qlra_server_submit(qlra_server_t* sv, const qlra_request_t* r, uint64_t* tic
     pr.pass_err = r->pass_err;
     pr.estimate = r->pass_err ? 1 : 0;
     pr.prec = r->pass_precision;
+    orient(pr, 0);
     int rc = check_problem(pr);
     if (rc) return rc;
     if ((rc = check_layout(r->A, r->m, r->n, r->lda, r->a_plane_stride))) return rc;

@@ -54,7 +54,8 @@ class Opts(ctypes.Structure):
                 ("stream", ctypes.c_void_p),
                 ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t),
-                ("graph", ctypes.c_int)]
+                ("graph", ctypes.c_int),
+                ("transpose", ctypes.c_int)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -138,8 +139,8 @@ def _workspace(nbytes, device):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
-def qlra_workspace_size(m, n, k, p, pass_budget, scheme, estimate=True, precision=QLRA_FP32):
-    o = Opts(precision, 1 if estimate else 0, None, None, 0, 0)
+def qlra_workspace_size(m, n, k, p, pass_budget, scheme, estimate=True, precision=QLRA_FP32, transpose=False):
+    o = Opts(precision, 1 if estimate else 0, None, None, 0, 0, 1 if transpose else 0)
     out = ctypes.c_size_t()
     _check(_lib.qlra_workspace_size(m, n, k, p, pass_budget, SCHEMES.get(scheme, scheme), ctypes.byref(o),
                                     ctypes.byref(out)), "qlra_workspace_size")
@@ -147,9 +148,10 @@ def qlra_workspace_size(m, n, k, p, pass_budget, scheme, estimate=True, precisio
 
 
 def qlra(A, k, p, pass_budget, scheme, seed, U=None, S=None, V=None, pass_err=None, workspace=None,
-         estimate=True, stream=None, precision=QLRA_FP32, graph=False):
+         estimate=True, stream=None, precision=QLRA_FP32, graph=False, transpose=False):
     """Truncated QSVD of A (4, m, n) FP32 on the GPU: returns (U, S, V, pass_err, workspace).
-    Enqueued on `stream` (default: torch's current stream); no synchronisation."""
+    Enqueued on `stream` (default: torch's current stream); no synchronisation.  transpose: run
+    the scheme on A^H (U and V stay the factors of A)."""
     scheme = SCHEMES.get(scheme, scheme)
     m, n = A.shape[1], A.shape[2]
     dev = A.device
@@ -164,16 +166,28 @@ def qlra(A, k, p, pass_budget, scheme, seed, U=None, S=None, V=None, pass_err=No
         pass_err = torch.empty(pass_budget, dtype=torch.float64, device=dev)
     pu, ldu, ups = _planes(U, m, k, "U")
     pv, ldv, vps = _planes(V, n, k, "V")
-    need = qlra_workspace_size(m, n, k, p, pass_budget, scheme, estimate, precision)
+    need = qlra_workspace_size(m, n, k, p, pass_budget, scheme, estimate, precision, transpose)
     if workspace is None or workspace.numel() < need:
         workspace = _workspace(need, dev)
     o = Opts(precision, 1 if estimate else 0, _stream_ptr(stream), ctypes.c_void_p(workspace.data_ptr()),
-             workspace.numel(), 1 if graph else 0)
+             workspace.numel(), 1 if graph else 0, 1 if transpose else 0)
     rc = _lib.qlra(pa, m, n, lda, aps, k, p, pass_budget, scheme, ctypes.c_uint64(seed), ctypes.byref(o),
                    pu, ldu, ups, ctypes.c_void_p(S.data_ptr()), pv, ldv, vps,
                    ctypes.c_void_p(pass_err.data_ptr()) if pass_err is not None else None)
     _check(rc, "qlra")
     return U, S, V, pass_err, workspace
+
+
+def qlra_power_iteration(A, k, p, q, seed, **kw):
+    """Randomized subspace iteration with q power iterations (Alg. 1): the subspace scheme with
+    a budget of 2 q + 2 passes."""
+    return qlra(A, k, p, 2 * q + 2, QLRA_SUBSPACE, seed, **kw)
+
+
+def qlra_block_krylov_q(A, k, p, q, seed, **kw):
+    """Block Krylov with q iterations (Alg. 3): the pass-efficient block Krylov scheme with a
+    budget of 2 q + 2 passes, which spans the same subspace."""
+    return qlra(A, k, p, 2 * q + 2, QLRA_BLOCK_KRYLOV, seed, **kw)
 
 
 def qlra_status(workspace, stream=None):

@@ -207,3 +207,41 @@ def test_wide_subspace_final(gq, oracle):
     Uo, So, Vo, eo = oracle.qlra(A64, 100, 8, 3, 0, 9)
     assert ahat_diff(A64, (Ug, Sg, Vg), (Uo, So, Vo)) <= 1e-5
     np.testing.assert_allclose(Sg, So, rtol=1e-5)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("v", [3, 4])
+def test_transpose_runs_the_scheme_on_the_adjoint(gq, oracle, scheme, v):
+    """transpose = 1 applies the scheme to A^H (sketch m x l, first view A^H Omega): the result is
+    the oracle's on A^H with the two factors exchanged, since A = (A^H)^H = V S U^H."""
+    print(f"transpose scheme={scheme} v={v}", flush=True)
+    import torch
+    m, n = 200, 320
+    sigma = np.arange(1, m + 1, dtype=np.float64) ** -2.0
+    A32 = np.ascontiguousarray(W.spectrum_matrix(31, m, n, sigma, nrefl=4), dtype=np.float32)
+    U, S, V, e, ws = gq.qlra(torch.from_numpy(A32).cuda(), 10, 5, v, scheme, 3, transpose=True)
+    assert gq.qlra_status(ws) == gq.QLRA_OK
+    torch.cuda.synchronize()
+    Ug, Sg, Vg, eg = (x.cpu().numpy().astype(np.float64) for x in (U, S, V, e))
+    assert Ug.shape == (4, m, 10) and Vg.shape == (4, n, 10)
+    A64 = A32.astype(np.float64)
+    Ub, Sb, Vb, eb = oracle.qlra(np.ascontiguousarray(qref.adj(A64)), 10, 5, v, scheme, 3)
+    Uo, So, Vo = Vb, Sb, Ub                       # the factors of A
+    assert ahat_diff(A64, (Ug, Sg, Vg), (Uo, So, Vo)) <= 1e-5
+    np.testing.assert_allclose(Sg, So, rtol=2e-5)
+    assert np.abs(Ug - Uo).max() < 1e-3 and np.abs(Vg - Vo).max() < 1e-3
+    assert np.isnan(eg[0]) and np.all(np.abs(eg[1:] ** 2 - eb[1:] ** 2) <= 4 * 2.0 ** -24)
+
+
+def test_classical_forms_are_budgets(gq):
+    """Alg. 1 with q power iterations is the subspace scheme at 2 q + 2 passes, and Alg. 3 with q
+    iterations is the block Krylov scheme at 2 q + 2 passes (the oracle pins both equivalences):
+    the aliases give bitwise the same results as the budget calls."""
+    import torch
+    A = torch.from_numpy(W.random_quat(9, 300, 260).astype(np.float32)).cuda()
+    for alias, scheme in ((gq.qlra_power_iteration, 0), (gq.qlra_block_krylov_q, 1)):
+        r1 = alias(A, 12, 4, 1, 5)
+        r2 = gq.qlra(A, 12, 4, 4, scheme, 5)
+        torch.cuda.synchronize()
+        for a, b in zip(r1[:4], r2[:4]):
+            assert np.array_equal(a.cpu().numpy(), b.cpu().numpy(), equal_nan=True)
