@@ -60,6 +60,13 @@ enum { QLRA_SUBSPACE = 0, QLRA_BLOCK_KRYLOV = 1 };
  * Gram, Cholesky and small QSVD steps are always FP64. */
 enum { QLRA_FP32 = 0, QLRA_BF16 = 1, QLRA_FP16 = 2 };
 
+/* The sketch.  QLRA_SKETCH_QUATERNION: the Gaussian quaternion test matrix of
+ * Sec. 2 (four independent N(0, 1) planes; see qlra_omega()).  QLRA_SKETCH_REAL:
+ * a real Gaussian test matrix, as the experiments of Sec. 8 use; it is the real
+ * plane of the quaternion sketch with the other three planes zero, and its
+ * first view costs a quarter of the matrix products. */
+enum { QLRA_SKETCH_QUATERNION = 0, QLRA_SKETCH_REAL = 1 };
+
 typedef struct {
     int pass_precision;      /* QLRA_FP32, QLRA_BF16 or QLRA_FP16 (see above)         */
     int estimate_passes;     /* nonzero: compute the per-pass error estimates         */
@@ -73,6 +80,7 @@ typedef struct {
                                 first view is A^H Omega, cheaper when n > m); U and V are
                                 still the left and right factors of A.  The results differ
                                 from transpose = 0 (another sketch), not the guarantees     */
+    int sketch;              /* QLRA_SKETCH_QUATERNION (0) or QLRA_SKETCH_REAL             */
 } qlra_opts_t;
 
 /* Bytes of device workspace a qlra() call with these sizes needs (written to

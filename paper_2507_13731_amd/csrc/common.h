@@ -45,6 +45,7 @@ struct QgemmDesc {
     const int* skip_flag;      // if non-null and *skip_flag == 0 the launch does nothing
     const float* cscale;       // low-precision math: device scalar the result is multiplied by
     double* fro2_part;         // FP32 A X only (optional): per-wave sums of squares of A, fro2_slots(d) entries
+    int b_real;                // FP32 views: B has zero imaginary planes (only its real plane is read)
 };
 
 // Device workspace carved into aligned regions.
@@ -84,7 +85,7 @@ hipError_t lowp_copy_launch(const float* A, int64_t m, int64_t n, int64_t lda, i
 hipError_t lowp_scale_launch(const double* nA2, int prec, float* scale, float* inv, hipStream_t st);
 
 hipError_t omega_launch(uint64_t seed, int64_t n, int64_t l, float* Om, int64_t ld, int64_t ps,
-                        hipStream_t st);
+                        hipStream_t st, int real_only = 0);
 
 // Cholesky of a Hermitian quaternion Gram G (w x w FP64 planes, ld = w): G (+ shift I) = R^H R,
 // Rout = R * Rprev (Rprev null: Rout = R) and Rinv = R^{-1} (if non-null).  If the unshifted

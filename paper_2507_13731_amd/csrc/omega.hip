@@ -134,7 +134,7 @@ __device__ __forceinline__ double unit_open(uint32_t x) {
 }
 
 __global__ __launch_bounds__(256) void k_omega(uint32_t k0, uint32_t k1, int64_t n, int64_t l,
-                                               float* Om, int64_t ld, int64_t ps) {
+                                               float* Om, int64_t ld, int64_t ps, int real_only) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n * l) return;
     const int64_t i = idx / l, j = idx - i * l;
@@ -153,20 +153,20 @@ __global__ __launch_bounds__(256) void k_omega(uint32_t k0, uint32_t k1, int64_t
     }
     float* o = Om + i * ld + j;
     o[0] = z[0];
-    o[ps] = z[1];
-    o[2 * ps] = z[2];
-    o[3 * ps] = z[3];
+    o[ps] = real_only ? 0.0f : z[1];
+    o[2 * ps] = real_only ? 0.0f : z[2];
+    o[3 * ps] = real_only ? 0.0f : z[3];
 }
 
 }  // namespace
 
 hipError_t omega_launch(uint64_t seed, int64_t n, int64_t l, float* Om, int64_t ld, int64_t ps,
-                        hipStream_t st) {
+                        hipStream_t st, int real_only) {
     const int64_t total = n * l;
     if (total == 0) return hipSuccess;
     const int64_t blocks = (total + 255) / 256;
     hipLaunchKernelGGL(k_omega, dim3((unsigned)blocks), dim3(256), 0, st,
-                       (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), n, l, Om, ld, ps);
+                       (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), n, l, Om, ld, ps, real_only);
     return hipGetLastError();
 }
 

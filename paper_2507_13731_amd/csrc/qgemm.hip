@@ -413,7 +413,7 @@ __global__ __launch_bounds__(256) void k_thin_t(const float* __restrict__ B, int
     }
 }
 
-template <int CN, bool ADJ, bool AVEC, bool FRO>
+template <int CN, bool ADJ, bool AVEC, bool FRO, bool REALB>
 __global__ __launch_bounds__(256, CN <= 3 ? 2 : 1) void k_qview(VParams P) {
     __shared__ f32x4 xch[4][CN * 4][64];
     if (P.skip && *P.skip == 0) return;
@@ -468,11 +468,14 @@ __global__ __launch_bounds__(256, CN <= 3 ? 2 : 1) void k_qview(VParams P) {
                 for (int q = 0; q < 4; q++) a[q][j] = *a_elem(q, k0 + 4 * g + j);
         }
     };
+    // REALB: the thin block is real (a real sketch); only its real plane is read and only the
+    // q = p terms of eq. (1) remain, a quarter of the MFMAs
     auto load_b = [&](int64_t k0, f32x4 (&b)[CN][4]) {
 #pragma unroll
         for (int cn = 0; cn < CN; cn++)
 #pragma unroll
-            for (int q = 0; q < 4; q++) b[cn][q] = *reinterpret_cast<const f32x4*>(bcol[cn] + q * P.bps + k0);
+            for (int q = 0; q < (REALB ? 1 : 4); q++)
+                b[cn][q] = *reinterpret_cast<const f32x4*>(bcol[cn] + q * P.bps + k0);
     };
     auto mma_slice = [&](const f32x4 (&a)[4], int j, const f32x4 (&b)[CN][4]) {
         float av[4], nav[4];
@@ -487,9 +490,11 @@ __global__ __launch_bounds__(256, CN <= 3 ? 2 : 1) void k_qview(VParams P) {
 #pragma unroll
             for (int cn = 0; cn < CN; cn++)
 #pragma unroll
-                for (int pp = 0; pp < 4; pp++)
+                for (int pp = 0; pp < 4; pp++) {
+                    if (REALB && pp != q) continue;
                     acc[cn][pp] = __builtin_amdgcn_mfma_f32_16x16x4f32(term_sign<ADJ>(pp, q) > 0 ? av[q] : nav[q],
                                                                        b[cn][pp ^ q][j], acc[cn][pp], 0, 0, 0);
+                }
     };
     // one full step from registers; the loads of the step `kn` go out a quarter after each slice
     // of MFMAs, so that no burst of loads stalls the issue of the matrix instructions
@@ -503,6 +508,7 @@ __global__ __launch_bounds__(256, CN <= 3 ? 2 : 1) void k_qview(VParams P) {
 #pragma unroll
             for (int e = j * CN; e < (j + 1) * CN; e++) {
                 const int cn = e / 4, q = e % 4;
+                if (REALB && q != 0) continue;
                 bn[cn][q] = *reinterpret_cast<const f32x4*>(bcol[cn] + q * P.bps + kn);
             }
             if constexpr (A4) {
@@ -722,19 +728,24 @@ size_t vplan_slots(const VPlan& p) { return (size_t)p.gx * 4 * (size_t)p.splits;
 size_t vplan_thin_bytes(const VPlan& p) { return ((size_t)4 * p.Np * p.Kp * sizeof(float) + 255) & ~size_t(255); }
 size_t vplan_part_bytes(const VPlan& p) { return p.splits > 1 ? (size_t)p.splits * 4 * p.Mp * p.Np * sizeof(float) : 0; }
 
-template <int CN, bool ADJ, bool AVEC, bool FRO = false>
+template <int CN, bool ADJ, bool AVEC, bool FRO, bool REALB>
 hipError_t launch_v(const VPlan& pl, const VParams& vp, hipStream_t st) {
-    hipLaunchKernelGGL((k_qview<CN, ADJ, AVEC, FRO>), dim3((unsigned)pl.gx, 1, (unsigned)pl.splits), dim3(256), 0, st, vp);
+    hipLaunchKernelGGL((k_qview<CN, ADJ, AVEC, FRO, REALB>), dim3((unsigned)pl.gx, 1, (unsigned)pl.splits), dim3(256), 0, st, vp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || pl.splits == 1) return e;
     return reduce_f32(vp.part, (int)pl.splits, pl.Mp, pl.Np, vp.C, vp.ldc, vp.cps, vp.M, vp.N, vp.store, vp.skip, st);
 }
 
+template <int CN, bool REALB>
+hipError_t launch_v_cr(const VPlan& pl, const VParams& vp, bool adj, bool avec, hipStream_t st) {
+    if (adj) return launch_v<CN, true, false, false, REALB>(pl, vp, st);
+    if (vp.fro)
+        return avec ? launch_v<CN, false, true, true, REALB>(pl, vp, st) : launch_v<CN, false, false, true, REALB>(pl, vp, st);
+    return avec ? launch_v<CN, false, true, false, REALB>(pl, vp, st) : launch_v<CN, false, false, false, REALB>(pl, vp, st);
+}
 template <int CN>
-hipError_t launch_v_cn(const VPlan& pl, const VParams& vp, bool adj, bool avec, hipStream_t st) {
-    if (adj) return launch_v<CN, true, false>(pl, vp, st);
-    if (vp.fro) return avec ? launch_v<CN, false, true, true>(pl, vp, st) : launch_v<CN, false, false, true>(pl, vp, st);
-    return avec ? launch_v<CN, false, true>(pl, vp, st) : launch_v<CN, false, false>(pl, vp, st);
+hipError_t launch_v_cn(const VPlan& pl, const VParams& vp, bool adj, bool avec, bool realb, hipStream_t st) {
+    return realb ? launch_v_cr<CN, true>(pl, vp, adj, avec, st) : launch_v_cr<CN, false>(pl, vp, adj, avec, st);
 }
 
 hipError_t launch_view(const QgemmDesc& d, void* scratch, hipStream_t st) {
@@ -742,7 +753,8 @@ hipError_t launch_view(const QgemmDesc& d, void* scratch, hipStream_t st) {
     if (!scratch) return hipErrorInvalidValue;
     float* Bt = (float*)scratch;
     float* part = (float*)((char*)scratch + vplan_thin_bytes(pl));
-    hipLaunchKernelGGL(k_thin_t, dim3((unsigned)((pl.Kp + 15) / 16), (unsigned)((pl.Np + 63) / 64), 4), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_thin_t, dim3((unsigned)((pl.Kp + 15) / 16), (unsigned)((pl.Np + 63) / 64), d.b_real ? 1 : 4),
+                       dim3(256), 0, st,
                        (const float*)d.B, d.ldb, d.bps, d.K, d.N, Bt, pl.Np, pl.Kp, d.skip_flag);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -758,12 +770,13 @@ hipError_t launch_view(const QgemmDesc& d, void* scratch, hipStream_t st) {
     vp.fro = d.op == OP_NN ? d.fro2_part : nullptr;
     const bool adj = d.op == OP_HN;
     const bool avec = ((uintptr_t)d.A % 16) == 0 && d.lda % 4 == 0 && d.aps % 4 == 0;
+    const bool realb = d.b_real != 0;
     switch (pl.CN) {
-        case 1: return launch_v_cn<1>(pl, vp, adj, avec, st);
-        case 2: return launch_v_cn<2>(pl, vp, adj, avec, st);
-        case 3: return launch_v_cn<3>(pl, vp, adj, avec, st);
-        case 4: return launch_v_cn<4>(pl, vp, adj, avec, st);
-        case 5: return launch_v_cn<5>(pl, vp, adj, avec, st);
+        case 1: return launch_v_cn<1>(pl, vp, adj, avec, realb, st);
+        case 2: return launch_v_cn<2>(pl, vp, adj, avec, realb, st);
+        case 3: return launch_v_cn<3>(pl, vp, adj, avec, realb, st);
+        case 4: return launch_v_cn<4>(pl, vp, adj, avec, realb, st);
+        case 5: return launch_v_cn<5>(pl, vp, adj, avec, realb, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -177,6 +177,7 @@ struct Problem {
     double* pass_err;
     int estimate;
     int prec;               // QLRA_FP32, QLRA_BF16 or QLRA_FP16 for views 1 .. v-2
+    int sketch;             // QLRA_SKETCH_QUATERNION or QLRA_SKETCH_REAL
 };
 
 // Run the scheme on A^H: swap the logical sizes and the two factors (A^H = V S U^H).
@@ -327,7 +328,7 @@ hipError_t get_side(Side* out) {
 struct GraphKey {
     int dev;
     const void* A; int64_t m, n, lda, aps;
-    int k, p, v, scheme, estimate, prec, transpose;
+    int k, p, v, scheme, estimate, prec, transpose, sketch;
     uint64_t seed;
     const void* U; int64_t ldu, ups;
     const void* S;
@@ -456,6 +457,7 @@ void view_product(Ctx& c, const Problem& pr, const Bufs& b, bool adjoint, const 
     }
     QgemmDesc d = desc(adj ? OP_HN : OP_NN, MATH_F32, pr.A, pr.lda, pr.aps, 0, X, ldx, kdim * ldx, 0, T, w,
                        rows_out * w, 0, rows_out, w, kdim);
+    d.b_real = (pr.sketch == QLRA_SKETCH_REAL && X == b.Om) ? 1 : 0;    // the first view of a real sketch
     const bool fro = c.fro_next && !adj;
     if (fro) {
         d.fro2_part = b.fro_part;
@@ -483,7 +485,7 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
         note(c, fill_int_launch(b.status, 16, 0, c.st));
         note(c, fill_u32_launch(b.counters, (int64_t)std::max<size_t>(c.cnt_need, 1), c.st));
         if (fro_apart) note(c, fro2_launch(pr.A, pr.mr, pr.nr, pr.lda, pr.aps, b.fro_part, b.nA2, c.st));
-        note(c, omega_launch(pr.seed, pr.n, l, b.Om, l, pr.n * l, c.st));
+        note(c, omega_launch(pr.seed, pr.n, l, b.Om, l, pr.n * l, c.st, pr.sketch == QLRA_SKETCH_REAL ? 1 : 0));
         if (pr.estimate) note(c, nan_launch(pr.pass_err, c.st));
         if (b.Alo) {
             note(c, lowp_scale_launch(b.nA2, pr.prec, b.lp_scale, b.lp_scale + 1, c.st));
@@ -601,7 +603,7 @@ int check_problem(const Problem& pr) {
     if (l > pr.m || l > pr.n) return QLRA_E_ARG;
     if (pr.v > 64) return QLRA_E_TOO_LARGE;
     if (pr.prec != QLRA_FP32 && pr.prec != QLRA_BF16 && pr.prec != QLRA_FP16) return QLRA_E_UNSUPPORTED;
-    // the low-precision view kernel keeps all output columns of a view in one workgroup
+    if (pr.sketch != QLRA_SKETCH_QUATERNION && pr.sketch != QLRA_SKETCH_REAL) return QLRA_E_UNSUPPORTED;
     return QLRA_OK;
 }
 
@@ -847,6 +849,7 @@ int qlra_workspace_size(int64_t m, int64_t n, int k, int p, int pass_budget, int
     pr.lda = n; pr.aps = m * n; pr.ldu = k; pr.ups = m * k; pr.ldv = k; pr.vps = n * k;
     pr.estimate = opts ? opts->estimate_passes : 1;
     pr.prec = opts ? opts->pass_precision : QLRA_FP32;
+    pr.sketch = opts ? opts->sketch : QLRA_SKETCH_QUATERNION;
     orient(pr, opts ? opts->transpose : 0);
     int rc = check_problem(pr);
     if (rc) return rc;
@@ -869,6 +872,7 @@ int qlra(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stri
     pr.pass_err = pass_err;
     pr.estimate = (opts->estimate_passes && pass_err) ? 1 : 0;
     pr.prec = opts->pass_precision;
+    pr.sketch = opts->sketch;
     int rc = check_problem(pr);
     if (rc) return rc;
     if ((rc = check_layout(A, m, n, lda, a_plane_stride))) return rc;
@@ -912,6 +916,7 @@ int qlra(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stri
     key.k = k; key.p = p; key.v = pass_budget; key.scheme = scheme; key.estimate = pr.estimate; key.seed = seed;
     key.prec = pr.prec;
     key.transpose = pr.transpose;
+    key.sketch = pr.sketch;
     key.U = U; key.ldu = ldu; key.ups = u_plane_stride; key.S = S; key.V = V; key.ldv = ldv;
     key.vps = v_plane_stride; key.pass_err = pass_err; key.ws = opts->workspace;
     std::lock_guard<std::mutex> lk(g_graph_mu);

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libqlra.so")
 
 QLRA_OK, QLRA_E_ARG, QLRA_E_WORKSPACE, QLRA_E_HIP, QLRA_E_NUMERIC, QLRA_E_TOO_LARGE, QLRA_E_UNSUPPORTED = range(7)
 QLRA_SUBSPACE, QLRA_BLOCK_KRYLOV = 0, 1
+QLRA_SKETCH_QUATERNION, QLRA_SKETCH_REAL = 0, 1
 QLRA_FP32, QLRA_BF16, QLRA_FP16 = 0, 1, 2
 SCHEMES = {"subspace": QLRA_SUBSPACE, "block_krylov": QLRA_BLOCK_KRYLOV, "krylov": QLRA_BLOCK_KRYLOV}
 
@@ -55,7 +56,8 @@ class Opts(ctypes.Structure):
                 ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t),
                 ("graph", ctypes.c_int),
-                ("transpose", ctypes.c_int)]
+                ("transpose", ctypes.c_int),
+                ("sketch", ctypes.c_int)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -139,8 +141,9 @@ def _workspace(nbytes, device):
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
 
-def qlra_workspace_size(m, n, k, p, pass_budget, scheme, estimate=True, precision=QLRA_FP32, transpose=False):
-    o = Opts(precision, 1 if estimate else 0, None, None, 0, 0, 1 if transpose else 0)
+def qlra_workspace_size(m, n, k, p, pass_budget, scheme, estimate=True, precision=QLRA_FP32, transpose=False,
+                        sketch=QLRA_SKETCH_QUATERNION):
+    o = Opts(precision, 1 if estimate else 0, None, None, 0, 0, 1 if transpose else 0, sketch)
     out = ctypes.c_size_t()
     _check(_lib.qlra_workspace_size(m, n, k, p, pass_budget, SCHEMES.get(scheme, scheme), ctypes.byref(o),
                                     ctypes.byref(out)), "qlra_workspace_size")
@@ -148,7 +151,8 @@ def qlra_workspace_size(m, n, k, p, pass_budget, scheme, estimate=True, precisio
 
 
 def qlra(A, k, p, pass_budget, scheme, seed, U=None, S=None, V=None, pass_err=None, workspace=None,
-         estimate=True, stream=None, precision=QLRA_FP32, graph=False, transpose=False):
+         estimate=True, stream=None, precision=QLRA_FP32, graph=False, transpose=False,
+         sketch=QLRA_SKETCH_QUATERNION):
     """Truncated QSVD of A (4, m, n) FP32 on the GPU: returns (U, S, V, pass_err, workspace).
     Enqueued on `stream` (default: torch's current stream); no synchronisation.  transpose: run
     the scheme on A^H (U and V stay the factors of A)."""
@@ -166,11 +170,11 @@ def qlra(A, k, p, pass_budget, scheme, seed, U=None, S=None, V=None, pass_err=No
         pass_err = torch.empty(pass_budget, dtype=torch.float64, device=dev)
     pu, ldu, ups = _planes(U, m, k, "U")
     pv, ldv, vps = _planes(V, n, k, "V")
-    need = qlra_workspace_size(m, n, k, p, pass_budget, scheme, estimate, precision, transpose)
+    need = qlra_workspace_size(m, n, k, p, pass_budget, scheme, estimate, precision, transpose, sketch)
     if workspace is None or workspace.numel() < need:
         workspace = _workspace(need, dev)
     o = Opts(precision, 1 if estimate else 0, _stream_ptr(stream), ctypes.c_void_p(workspace.data_ptr()),
-             workspace.numel(), 1 if graph else 0, 1 if transpose else 0)
+             workspace.numel(), 1 if graph else 0, 1 if transpose else 0, sketch)
     rc = _lib.qlra(pa, m, n, lda, aps, k, p, pass_budget, scheme, ctypes.c_uint64(seed), ctypes.byref(o),
                    pu, ldu, ups, ctypes.c_void_p(S.data_ptr()), pv, ldv, vps,
                    ctypes.c_void_p(pass_err.data_ptr()) if pass_err is not None else None)

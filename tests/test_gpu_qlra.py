@@ -245,3 +245,45 @@ def test_classical_forms_are_budgets(gq):
         torch.cuda.synchronize()
         for a, b in zip(r1[:4], r2[:4]):
             assert np.array_equal(a.cpu().numpy(), b.cpu().numpy(), equal_nan=True)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+@pytest.mark.parametrize("v", [2, 3, 4])
+def test_real_sketch(gq, oracle, scheme, v):
+    """The real Gaussian sketch (the real plane of the quaternion sketch, the other planes zero):
+    the first view uses only the q = p terms of eq. (1); the result equals the oracle's with the
+    same sketch."""
+    print(f"real sketch scheme={scheme} v={v}", flush=True)
+    import torch
+    A, _ = W.config0()
+    A32 = A.astype(np.float32)
+    U, S, V, e, ws = gq.qlra(torch.from_numpy(A32).cuda(), 10, 5, v, scheme, 4, sketch=gq.QLRA_SKETCH_REAL)
+    assert gq.qlra_status(ws) == gq.QLRA_OK
+    torch.cuda.synchronize()
+    Ug, Sg, Vg, eg = (x.cpu().numpy().astype(np.float64) for x in (U, S, V, e))
+    Om = oracle.omega(4, 256, 15).astype(np.float64)
+    Om[1:] = 0.0
+    Uo, So, Vo, eo = oracle.qlra_sketch(A32.astype(np.float64), 10, 5, v, scheme, Om)
+    assert ahat_diff(A, (Ug, Sg, Vg), (Uo, So, Vo)) <= 1e-5
+    np.testing.assert_allclose(Sg, So, rtol=2e-5)
+    assert np.abs(Ug - Uo).max() < 1e-3 and np.abs(Vg - Vo).max() < 1e-3
+    assert np.isnan(eg[0]) and np.all(np.abs(eg[1:] ** 2 - eo[1:] ** 2) <= 4 * 2.0 ** -24)
+
+
+def test_real_sketch_on_the_adjoint(gq, oracle):
+    """Real sketch with transpose = 1: the first view is A^H Omega with a real Omega (m x l)."""
+    import torch
+    m, n = 200, 320
+    sigma = np.arange(1, m + 1, dtype=np.float64) ** -2.0
+    A32 = np.ascontiguousarray(W.spectrum_matrix(33, m, n, sigma, nrefl=4), dtype=np.float32)
+    U, S, V, e, ws = gq.qlra(torch.from_numpy(A32).cuda(), 10, 5, 3, 0, 6, transpose=True,
+                             sketch=gq.QLRA_SKETCH_REAL)
+    assert gq.qlra_status(ws) == gq.QLRA_OK
+    torch.cuda.synchronize()
+    Ug, Sg, Vg = (x.cpu().numpy().astype(np.float64) for x in (U, S, V))
+    Om = oracle.omega(6, m, 15).astype(np.float64)
+    Om[1:] = 0.0
+    A64 = A32.astype(np.float64)
+    Ub, Sb, Vb, _ = oracle.qlra_sketch(np.ascontiguousarray(qref.adj(A64)), 10, 5, 3, 0, Om)
+    assert ahat_diff(A64, (Ug, Sg, Vg), (Vb, Sb, Ub)) <= 1e-5
+    np.testing.assert_allclose(Sg, Sb, rtol=2e-5)
