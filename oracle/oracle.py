@@ -199,3 +199,55 @@ def reconstruct(U, S, V):
     Vh = np.asarray(V, dtype=np.float64).transpose(0, 2, 1).copy()
     Vh[1:] *= -1.0                     # (V^H) planes: V0^T, -V1^T, -V2^T, -V3^T
     return qgemm(US, Vh)
+
+
+# ------------------------------------------------------------------------------------------
+# Quaternion matrix completion (Sec. 7, the alternating updates of the completion problem):
+#   X^(t) <- L(C^(t)),   C^(t+1) <- mask . M + (1 - mask) . X^(t)
+# with L the rank-R approximation by the randomized scheme (one sketch, drawn from `seed`, for
+# every iteration), and, as in the image experiments of Sec. 8, a Gaussian smoothing of X^(t)
+# before the update (sigma = 0: none).  Start: C^(0) = mask . M.
+
+def gauss_weights(sigma):
+    """Normalised Gaussian taps exp(-t^2 / (2 sigma^2)), t = -r .. r, r = ceil(3 sigma)."""
+    r = int(np.ceil(3.0 * sigma))
+    t = np.arange(-r, r + 1, dtype=np.float64)
+    w = np.exp(-t * t / (2.0 * sigma * sigma))
+    return w / w.sum()
+
+
+def smooth(X, sigma):
+    """Separable Gaussian smoothing of every plane of X (4, m, n), edges replicated: along the
+    rows, then along the columns; written as plain sums over the taps."""
+    if sigma <= 0:
+        return X.copy()
+    w = gauss_weights(sigma)
+    r = (len(w) - 1) // 2
+    m, n = X.shape[1:]
+    Y = np.zeros_like(X)
+    for t in range(-r, r + 1):                       # along each row (column index moves)
+        idx = np.clip(np.arange(n) + t, 0, n - 1)
+        Y += w[t + r] * X[:, :, idx]
+    Z = np.zeros_like(X)
+    for t in range(-r, r + 1):                       # along each column (row index moves)
+        idx = np.clip(np.arange(m) + t, 0, m - 1)
+        Z += w[t + r] * Y[:, idx, :]
+    return Z
+
+
+def complete(M, mask, rank, p, v, scheme, seed, iters, sigma):
+    """The completion iterations on FP64 planes M (4, m, n) with a 0/1 mask (m, n); returns the
+    last X and, per iteration, the relative misfit on the observed entries
+    ||mask . (X - M)||_F / ||mask . M||_F."""
+    M = _planes(M)
+    mk = np.asarray(mask, dtype=np.float64)[None]
+    C = mk * M
+    ref = np.sqrt(np.sum((mk * M) ** 2))
+    fit = []
+    X = C
+    for t in range(iters):
+        U, S, V, _ = qlra(C, rank, p, v, scheme, seed)
+        X = smooth(reconstruct(U, S, V), sigma)
+        fit.append(np.sqrt(np.sum((mk * (X - M)) ** 2)) / ref)
+        C = mk * M + (1.0 - mk) * X
+    return X, np.array(fit)
