@@ -124,6 +124,43 @@ int qlra(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stri
          float* V, int64_t ldv, int64_t v_plane_stride,
          double* pass_err);
 
+/* ---- quaternion matrix completion (Sec. 7) ----
+ *
+ * Fills in the unobserved entries of M (m x n, FP32 planes, read only) by the
+ * alternating updates of the completion problem:
+ *   C^(0) = mask . M;  for t = 0 .. iters-1:
+ *     X^(t)   = G_sigma * L(C^(t))
+ *     C^(t+1) = mask . M + (1 - mask) . X^(t)
+ * with L(C) = U diag(S) V^H the rank-`rank` approximation of C computed exactly
+ * as qlra(C, rank, p, pass_budget, scheme, seed, opts) computes it (the same
+ * sketch every iteration), and G_sigma the separable Gaussian smoothing the
+ * image experiments of Sec. 8 apply after each iteration: along every row and
+ * then every column of each plane, the normalised taps
+ * exp(-t^2 / (2 sigma^2)), t = -r .. r, r = ceil(3 sigma), edge entries
+ * replicated.  sigma <= 0: no smoothing; r must be <= 8 (sigma <= 8/3), else
+ * QLRA_E_UNSUPPORTED.
+ *
+ *   mask     m x n bytes (row-major, ld_mask >= n, device): nonzero = observed.
+ *   X        m x n FP32 planes, written: X^(iters-1).
+ *   fit      iters doubles (device) or NULL: fit[t] = ||mask . (X^(t) - M)||_F
+ *            / ||mask . M||_F (NaN when nothing is observed).
+ *   opts     pass_precision, transpose, sketch, stream and workspace as for
+ *            qlra(); estimate_passes is ignored; graph != 0 captures one
+ *            iteration as a HIP graph (cached under the call's arguments) and
+ *            replays it iters times.
+ * The workspace (qlra_complete_workspace_size() bytes) holds C, the factors and
+ * the solve's own pieces; qlra_status() on it reports QLRA_E_NUMERIC when any
+ * iteration's solve broke down (e.g. an all-zero C).  Argument codes as for
+ * qlra(); iters >= 1. */
+int qlra_complete_workspace_size(int64_t m, int64_t n, int rank, int p, int pass_budget, int scheme, double sigma,
+                                 const qlra_opts_t* opts, size_t* bytes);
+int qlra_complete(const float* M, int64_t m, int64_t n, int64_t ldm, int64_t m_plane_stride,
+                  const unsigned char* mask, int64_t ld_mask,
+                  int rank, int p, int pass_budget, int scheme, uint64_t seed,
+                  int iters, double sigma, const qlra_opts_t* opts,
+                  float* X, int64_t ldx, int64_t x_plane_stride,
+                  double* fit);
+
 /* ---- continuous-batching server ----
  *
  * A scheduler thread (one per server, on the device current at creation) serves qlra()
@@ -181,8 +218,8 @@ int qlra_server_destroy(qlra_server_t* server);
 /* Seconds on the server's monotonic clock (for arrival times). */
 double qlra_server_clock(void);
 
-/* Device status word of the last solve that used this workspace: QLRA_OK or
- * QLRA_E_NUMERIC.  Synchronises `stream` (hipStream_t, may be NULL) first. */
+/* Device status word of the last solve (or completion) that used this
+ * workspace: QLRA_OK or QLRA_E_NUMERIC.  Synchronises `stream` (hipStream_t, may be NULL) first. */
 int qlra_status(const void* workspace, void* stream, int* status);
 
 /* Human-readable text of a status code (static storage). */

@@ -235,10 +235,11 @@ def smooth(X, sigma):
     return Z
 
 
-def complete(M, mask, rank, p, v, scheme, seed, iters, sigma):
+def complete(M, mask, rank, p, v, scheme, seed, iters, sigma, Om=None, adjoint=False):
     """The completion iterations on FP64 planes M (4, m, n) with a 0/1 mask (m, n); returns the
     last X and, per iteration, the relative misfit on the observed entries
-    ||mask . (X - M)||_F / ||mask . M||_F."""
+    ||mask . (X - M)||_F / ||mask . M||_F.  Om: an explicit sketch instead of the seeded one;
+    adjoint: each rank-R step runs the scheme on C^H (C = V S U^H there)."""
     M = _planes(M)
     mk = np.asarray(mask, dtype=np.float64)[None]
     C = mk * M
@@ -246,7 +247,16 @@ def complete(M, mask, rank, p, v, scheme, seed, iters, sigma):
     fit = []
     X = C
     for t in range(iters):
-        U, S, V, _ = qlra(C, rank, p, v, scheme, seed)
+        Cs = C
+        if adjoint:
+            Cs = C.transpose(0, 2, 1).copy()
+            Cs[1:] *= -1.0
+        if Om is None:
+            U, S, V, _ = qlra(Cs, rank, p, v, scheme, seed)
+        else:
+            U, S, V, _ = qlra_sketch(Cs, rank, p, v, scheme, Om)
+        if adjoint:
+            U, V = V, U
         X = smooth(reconstruct(U, S, V), sigma)
         fit.append(np.sqrt(np.sum((mk * (X - M)) ** 2)) / ref)
         C = mk * M + (1.0 - mk) * X

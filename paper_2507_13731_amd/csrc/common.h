@@ -68,8 +68,8 @@ struct QgemmScratch {
     unsigned* counters;     // qgemm_counter_count entries, zero at rest
 };
 
-size_t qgemm_partial_bytes(const QgemmDesc& d);
-size_t fro2_slots(const QgemmDesc& d);            // entries of fro2_part written by an FP32 A X launch   // split-K partials (+ the converted B, low precision)
+size_t qgemm_partial_bytes(const QgemmDesc& d);    // split-K partials (+ the converted B, low precision)
+size_t fro2_slots(const QgemmDesc& d);             // entries of fro2_part written by an FP32 A X launch
 size_t qgemm_counter_count(const QgemmDesc& d);
 hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t st);
 
@@ -169,5 +169,37 @@ hipError_t fro2_launch(const float* A, int64_t m, int64_t n, int64_t lda, int64_
 size_t phase_work_bytes(int64_t n, int k);
 hipError_t phase_launch(float* U, int64_t m, int64_t ldu, int64_t ups, float* V, int64_t n, int64_t ldv,
                         int64_t vps, int k, void* work, hipStream_t st);
+
+// Quaternion matrix completion (Sec. 7), one iteration after the rank-R step: C = mask . M +
+// (1 - mask) . X with X = G_sigma * (U diag(S) V^H) (separable Gaussian, radius ceil(3 sigma) <=
+// kCompleteMaxRadius, edges replicated; sigma <= 0: no smoothing), X written to the output when
+// *iter == iters - 1, fit[*iter] = ||mask . (X - M)||_F / ||mask . M||_F (fit may be null), then
+// *iter += 1.  part: 2 * complete_blocks(m, n, radius) doubles.
+constexpr int kCompleteMaxRadius = 8;
+struct CompleteStep {
+    const float* U; int64_t ldu, ups;
+    const double* S;
+    const float* V; int64_t ldv, vps;
+    int R;
+    const float* M; int64_t ldm, mps;
+    const unsigned char* mask; int64_t ldk;
+    float* C; int64_t ldc, cps;
+    float* X; int64_t ldx, xps;
+    int64_t m, n;
+    double sigma;
+    int* iter; int iters;
+    double* part;
+    double* fit;
+};
+int complete_radius(double sigma);
+int complete_tile(int radius);
+int64_t complete_blocks(int64_t m, int64_t n, int radius);
+hipError_t complete_step_launch(const CompleteStep& s, hipStream_t st);
+// C = mask . M, *iter = 0, status[0] = 0.
+hipError_t complete_init_launch(const float* M, int64_t ldm, int64_t mps, const unsigned char* mask, int64_t ldk,
+                                int64_t m, int64_t n, float* C, int64_t ldc, int64_t cps, int* iter, int* status,
+                                hipStream_t st);
+// dst[0] |= src[0].
+hipError_t status_or_launch(int* dst, const int* src, hipStream_t st);
 
 }  // namespace qlra_impl

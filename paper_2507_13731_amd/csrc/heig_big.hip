@@ -126,7 +126,6 @@ __global__ __launch_bounds__(BT) void k_big_copy(const double* __restrict__ G, d
 __global__ __launch_bounds__(BT) void k_big_a(double* __restrict__ base, int W, int nvec, int j) {
     __shared__ double vs[4 * 1024];   // v, W <= 1024
     __shared__ double red[4];
-    __shared__ double s_tau;
     BigRec R = big_rec(base, W, nvec);
     const int64_t ps = (int64_t)W * W;
     const int tid = threadIdx.x;

@@ -335,6 +335,13 @@ struct GraphKey {
     const void* V; int64_t ldv, vps;
     const void* pass_err;
     const void* ws;
+    // completion iterations (zero for a solve): mask, output, misfit, smoothing, iteration count
+    int completion;
+    const void* mask; int64_t ldk;
+    const void* X; int64_t ldx, xps;
+    const void* fit;
+    double sigma;
+    int iters;
     bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
 };
 struct GraphEntry {
@@ -354,6 +361,46 @@ hipError_t get_capture_stream(int dev, hipStream_t* out) {
         if (e != hipSuccess) return e;
     }
     *out = g_capture[dev];
+    return hipSuccess;
+}
+
+// The executable graph cached under `key`, or a new capture of enqueue(stream) (which returns the
+// first launch error) cached under it, least recently used evicted.  Caller holds g_graph_mu.
+template <class F>
+hipError_t graph_for(const GraphKey& key, F enqueue, hipGraphExec_t* out) {
+    for (auto& ge : g_graphs) {
+        if (ge.key == key) {
+            ge.last = ++g_graph_clock;
+            *out = ge.exec;
+            return hipSuccess;
+        }
+    }
+    hipStream_t cap;
+    hipError_t e = get_capture_stream(key.dev, &cap);
+    if (e != hipSuccess) return e;
+    if ((e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+    const hipError_t le = enqueue(cap);
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(cap, &graph);
+    if (le != hipSuccess || ee != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return le != hipSuccess ? le : (ee != hipSuccess ? ee : hipErrorUnknown);
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    if (g_graphs.size() >= kMaxGraphs) {
+        size_t lru = 0;
+        for (size_t i = 1; i < g_graphs.size(); i++)
+            if (g_graphs[i].last < g_graphs[lru].last) lru = i;
+        // the evicted graph may still be in flight on some stream
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
+        (void)hipGraphExecDestroy(g_graphs[lru].exec);
+        g_graphs.erase(g_graphs.begin() + (long)lru);
+    }
+    g_graphs.push_back(GraphEntry{key, exec, ++g_graph_clock});
+    *out = exec;
     return hipSuccess;
 }
 
@@ -821,6 +868,64 @@ void srv_loop(qlra_server* sv) {
 
 namespace qlra_impl {
 namespace {
+
+// ---------------------------------------------------------------------------------------
+// Quaternion matrix completion (Sec. 7): every iteration is a full solve of the rank-R problem on
+// the current C (same sketch), followed by the fused reconstruct / smooth / update kernel.  The
+// workspace holds the completion's status word first (so that qlra_status() reads it), its
+// iteration counter, C, the factors and the misfit sums, then the solve's own pieces.
+
+struct Completion {
+    Problem pr;             // the solve on C (A = C), oriented
+    Dims d;
+    size_t part = 0, cnt = 0;
+    int* status = nullptr;
+    int* iter = nullptr;
+    float* C = nullptr;
+    float* U = nullptr;
+    float* V = nullptr;
+    double* S = nullptr;
+    double* fit_part = nullptr;
+    Bufs b{};
+};
+
+int completion_layout(int64_t m, int64_t n, int R, int p, int v, int scheme, double sigma, const qlra_opts_t* opts,
+                      char* base, size_t size, bool dry, Completion& cp, size_t* total) {
+    if (sigma != sigma || complete_radius(sigma) > kCompleteMaxRadius) return QLRA_E_UNSUPPORTED;
+    Problem& pr = cp.pr;
+    pr = Problem{};
+    pr.m = m; pr.n = n; pr.lda = n; pr.aps = m * n;
+    pr.k = R; pr.p = p; pr.v = v; pr.scheme = scheme;
+    pr.ldu = R; pr.ups = m * R; pr.ldv = R; pr.vps = n * R;
+    pr.estimate = 0;
+    pr.prec = opts ? opts->pass_precision : QLRA_FP32;
+    pr.sketch = opts ? opts->sketch : QLRA_SKETCH_QUATERNION;
+    int rc = check_problem(pr);
+    if (rc) return rc;
+    const int transpose = opts ? opts->transpose : 0;
+    {
+        Problem po = pr;
+        orient(po, transpose);
+        cp.d = dims_of(po.m, po.n, R, p, v, scheme);
+        size_t solve_total;
+        size_solve(po, cp.d, &cp.part, &cp.cnt, &solve_total);
+    }
+    Arena ar{base, size, 0, dry};
+    cp.status = (int*)ar.take(16 * sizeof(int));
+    cp.iter = (int*)ar.take(sizeof(int));
+    cp.C = (float*)ar.take(4 * m * n * sizeof(float));
+    cp.U = (float*)ar.take(4 * m * R * sizeof(float));
+    cp.V = (float*)ar.take(4 * n * R * sizeof(float));
+    cp.S = (double*)ar.take(R * sizeof(double));
+    cp.fit_part = (double*)ar.take(2 * complete_blocks(m, n, complete_radius(sigma)) * sizeof(double));
+    pr.A = cp.C;
+    pr.U = cp.U; pr.S = cp.S; pr.V = cp.V;
+    orient(pr, transpose);
+    carve(pr, cp.d, ar, cp.b, cp.part, cp.cnt);
+    *total = ar.used;
+    return QLRA_OK;
+}
+
 }  // namespace
 }  // namespace qlra_impl
 
@@ -920,37 +1025,9 @@ int qlra(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stri
     key.U = U; key.ldu = ldu; key.ups = u_plane_stride; key.S = S; key.V = V; key.ldv = ldv;
     key.vps = v_plane_stride; key.pass_err = pass_err; key.ws = opts->workspace;
     std::lock_guard<std::mutex> lk(g_graph_mu);
-    for (auto& ge : g_graphs) {
-        if (ge.key == key) {
-            ge.last = ++g_graph_clock;
-            return hipGraphLaunch(ge.exec, (hipStream_t)opts->stream) == hipSuccess ? QLRA_OK : QLRA_E_HIP;
-        }
-    }
-    hipStream_t cap;
-    if (get_capture_stream(key.dev, &cap) != hipSuccess) return QLRA_E_HIP;
-    c.st = cap;
-    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return QLRA_E_HIP;
-    enqueue();
-    hipGraph_t graph = nullptr;
-    const hipError_t ee = hipStreamEndCapture(cap, &graph);
-    if (c.err != hipSuccess || ee != hipSuccess || !graph) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return QLRA_E_HIP;
-    }
     hipGraphExec_t exec = nullptr;
-    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (ie != hipSuccess) return QLRA_E_HIP;
-    if (g_graphs.size() >= kMaxGraphs) {
-        size_t lru = 0;
-        for (size_t i = 1; i < g_graphs.size(); i++)
-            if (g_graphs[i].last < g_graphs[lru].last) lru = i;
-        // the evicted graph may still be in flight on some stream
-        if (hipDeviceSynchronize() != hipSuccess) return QLRA_E_HIP;
-        (void)hipGraphExecDestroy(g_graphs[lru].exec);
-        g_graphs.erase(g_graphs.begin() + (long)lru);
-    }
-    g_graphs.push_back(GraphEntry{key, exec, ++g_graph_clock});
+    const hipError_t ge = graph_for(key, [&](hipStream_t cap) { c.st = cap; enqueue(); return c.err; }, &exec);
+    if (ge != hipSuccess) return QLRA_E_HIP;
     return hipGraphLaunch(exec, (hipStream_t)opts->stream) == hipSuccess ? QLRA_OK : QLRA_E_HIP;
 }
 
@@ -960,6 +1037,90 @@ int qlra_status(const void* workspace, void* stream, int* status) {
     int word = 0;
     if (hipMemcpy(&word, workspace, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return QLRA_E_HIP;
     *status = (word & 2) ? QLRA_E_NUMERIC : QLRA_OK;
+    return QLRA_OK;
+}
+
+int qlra_complete_workspace_size(int64_t m, int64_t n, int rank, int p, int pass_budget, int scheme, double sigma,
+                                 const qlra_opts_t* opts, size_t* bytes) {
+    if (!bytes) return QLRA_E_ARG;
+    Completion cp;
+    size_t total = 0;
+    const int rc = completion_layout(m, n, rank, p, pass_budget, scheme, sigma, opts, nullptr, 0, true, cp, &total);
+    if (rc) return rc;
+    *bytes = total;
+    return QLRA_OK;
+}
+
+int qlra_complete(const float* M, int64_t m, int64_t n, int64_t ldm, int64_t m_plane_stride, const unsigned char* mask,
+                  int64_t ld_mask, int rank, int p, int pass_budget, int scheme, uint64_t seed, int iters, double sigma,
+                  const qlra_opts_t* opts, float* X, int64_t ldx, int64_t x_plane_stride, double* fit) {
+    if (!opts || iters < 1 || m < 1 || n < 1) return QLRA_E_ARG;
+    int rc;
+    if ((rc = check_layout(M, m, n, ldm, m_plane_stride))) return rc;
+    if ((rc = check_layout(X, m, n, ldx, x_plane_stride))) return rc;
+    if (!mask || ld_mask < n) return QLRA_E_ARG;
+    Completion cp;
+    size_t total = 0;
+    if ((rc = completion_layout(m, n, rank, p, pass_budget, scheme, sigma, opts, nullptr, 0, true, cp, &total)))
+        return rc;
+    if (!opts->workspace || opts->workspace_bytes < total || ((uintptr_t)opts->workspace & 255))
+        return QLRA_E_WORKSPACE;
+    if ((rc = completion_layout(m, n, rank, p, pass_budget, scheme, sigma, opts, (char*)opts->workspace,
+                                opts->workspace_bytes, false, cp, &total)))
+        return rc;
+    cp.pr.seed = seed;
+    CompleteStep cs{};
+    cs.U = cp.U; cs.ldu = rank; cs.ups = m * rank;
+    cs.S = cp.S;
+    cs.V = cp.V; cs.ldv = rank; cs.vps = n * rank;
+    cs.R = rank;
+    cs.M = M; cs.ldm = ldm; cs.mps = m_plane_stride;
+    cs.mask = mask; cs.ldk = ld_mask;
+    cs.C = cp.C; cs.ldc = n; cs.cps = m * n;
+    cs.X = X; cs.ldx = ldx; cs.xps = x_plane_stride;
+    cs.m = m; cs.n = n;
+    cs.sigma = sigma;
+    cs.iter = cp.iter; cs.iters = iters;
+    cs.part = cp.fit_part;
+    cs.fit = fit;
+    // one iteration: the rank-R solve on C, its status bits into the completion's, the update
+    auto iteration = [&](hipStream_t s) -> hipError_t {
+        Ctx c;
+        c.st = s;
+        c.cnt_need = cp.cnt;
+        bind_ctx(c, cp.b, cp.d);
+        run_solve(c, cp.pr, cp.d, cp.b);
+        note(c, status_or_launch(cp.status, cp.b.status, s));
+        note(c, complete_step_launch(cs, s));
+        return c.err;
+    };
+    const hipStream_t st = (hipStream_t)opts->stream;
+    if (complete_init_launch(M, ldm, m_plane_stride, mask, ld_mask, m, n, cp.C, n, m * n, cp.iter, cp.status, st) !=
+        hipSuccess)
+        return QLRA_E_HIP;
+    if (!opts->graph) {
+        for (int t = 0; t < iters; t++)
+            if (iteration(st) != hipSuccess) return QLRA_E_HIP;
+        return QLRA_OK;
+    }
+    // graph path: one captured iteration, replayed `iters` times (the iteration counter lives on
+    // the device), cached under the call's arguments like the solves
+    GraphKey key;
+    std::memset(&key, 0, sizeof(key));
+    if (hipGetDevice(&key.dev) != hipSuccess || key.dev < 0 || key.dev >= 64) return QLRA_E_HIP;
+    key.completion = 1;
+    key.A = M; key.m = m; key.n = n; key.lda = ldm; key.aps = m_plane_stride;
+    key.k = rank; key.p = p; key.v = pass_budget; key.scheme = scheme; key.seed = seed;
+    key.prec = cp.pr.prec; key.transpose = cp.pr.transpose; key.sketch = cp.pr.sketch;
+    key.ws = opts->workspace;
+    key.mask = mask; key.ldk = ld_mask;
+    key.X = X; key.ldx = ldx; key.xps = x_plane_stride;
+    key.fit = fit; key.sigma = sigma; key.iters = iters;
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    hipGraphExec_t exec = nullptr;
+    if (graph_for(key, iteration, &exec) != hipSuccess) return QLRA_E_HIP;
+    for (int t = 0; t < iters; t++)
+        if (hipGraphLaunch(exec, st) != hipSuccess) return QLRA_E_HIP;
     return QLRA_OK;
 }
 

@@ -75,6 +75,9 @@ _lib.qlra_workspace_size.argtypes = [_I64, _I64, _I, _I, _I, _I, ctypes.POINTER(
 _lib.qlra.argtypes = [_P, _I64, _I64, _I64, _I64, _I, _I, _I, _I, ctypes.c_uint64, ctypes.POINTER(Opts),
                       _P, _I64, _I64, _P, _P, _I64, _I64, _P]
 _lib.qlra_status.argtypes = [_P, _P, ctypes.POINTER(_I)]
+_lib.qlra_complete_workspace_size.argtypes = [_I64, _I64, _I, _I, _I, _I, ctypes.c_double, ctypes.POINTER(Opts), _SZ]
+_lib.qlra_complete.argtypes = [_P, _I64, _I64, _I64, _I64, _P, _I64, _I, _I, _I, _I, ctypes.c_uint64, _I,
+                               ctypes.c_double, ctypes.POINTER(Opts), _P, _I64, _I64, _P]
 _lib.qlra_omega.argtypes = [ctypes.c_uint64, _I64, _I64, _P, _I64, _I64, _P]
 _lib.qlra_qgemm_workspace_size.argtypes = [_I, _I64, _I64, _I64, _SZ]
 _lib.qlra_qgemm.argtypes = [_I, _P, _I64, _I64, _I64, _I64, _P, _I64, _I64, _I64, _P, _I64, _I64, _P,
@@ -100,12 +103,14 @@ _lib.qlra_server_clock.restype = ctypes.c_double
 for _name in ("qlra_server_create", "qlra_server_submit", "qlra_server_poll", "qlra_server_drain",
               "qlra_server_stats", "qlra_server_destroy"):
     getattr(_lib, _name).restype = _I
-for _name in ("qlra_workspace_size", "qlra", "qlra_status", "qlra_omega", "qlra_qgemm_workspace_size",
+for _name in ("qlra_workspace_size", "qlra", "qlra_status", "qlra_complete_workspace_size", "qlra_complete",
+              "qlra_omega", "qlra_qgemm_workspace_size",
               "qlra_qgemm", "qlra_lowp_copy_bytes", "qlra_lowp_copy", "qlra_qgemm_lp_workspace_size", "qlra_qgemm_lp",
               "qlra_cholqr_workspace_size", "qlra_cholqr", "qlra_qsvd_workspace_size", "qlra_qsvd"):
     getattr(_lib, _name).restype = _I
 
-EXPORTS = ("qlra", "qlra_workspace_size", "qlra_status", "qlra_strerror", "qlra_omega", "qlra_qgemm",
+EXPORTS = ("qlra", "qlra_workspace_size", "qlra_status", "qlra_strerror", "qlra_complete",
+           "qlra_complete_workspace_size", "qlra_omega", "qlra_qgemm",
            "qlra_qgemm_workspace_size", "qlra_lowp_copy_bytes", "qlra_lowp_copy", "qlra_qgemm_lp", "qlra_qgemm_lp_workspace_size",
            "qlra_cholqr", "qlra_cholqr_workspace_size", "qlra_qsvd", "qlra_qsvd_workspace_size",
            "qlra_server_create", "qlra_server_submit", "qlra_server_poll", "qlra_server_drain",
@@ -192,6 +197,49 @@ def qlra_block_krylov_q(A, k, p, q, seed, **kw):
     """Block Krylov with q iterations (Alg. 3): the pass-efficient block Krylov scheme with a
     budget of 2 q + 2 passes, which spans the same subspace."""
     return qlra(A, k, p, 2 * q + 2, QLRA_BLOCK_KRYLOV, seed, **kw)
+
+
+def qlra_complete_workspace_size(m, n, rank, p, pass_budget, scheme, sigma, precision=QLRA_FP32, transpose=False,
+                                 sketch=QLRA_SKETCH_QUATERNION):
+    o = Opts(precision, 0, None, None, 0, 0, 1 if transpose else 0, sketch)
+    out = ctypes.c_size_t()
+    _check(_lib.qlra_complete_workspace_size(m, n, rank, p, pass_budget, SCHEMES.get(scheme, scheme), float(sigma),
+                                             ctypes.byref(o), ctypes.byref(out)), "qlra_complete_workspace_size")
+    return out.value
+
+
+def qlra_complete(M, mask, rank, p, pass_budget, scheme, seed, iters, sigma=0.0, X=None, fit=None, workspace=None,
+                  stream=None, precision=QLRA_FP32, graph=False, transpose=False, sketch=QLRA_SKETCH_QUATERNION):
+    """Quaternion matrix completion (Sec. 7) of M (4, m, n) FP32 observed where the (m, n) uint8
+    `mask` is nonzero: `iters` alternating updates with the rank-`rank` approximation and, for
+    sigma > 0, Gaussian smoothing after each.  Returns (X, fit, workspace); enqueued on `stream`
+    without synchronisation.  fit=False skips the per-iteration misfits."""
+    scheme = SCHEMES.get(scheme, scheme)
+    m, n = M.shape[1], M.shape[2]
+    dev = M.device
+    pm, ldm, mps = _planes(M, m, n, "M")
+    if mask.dtype != torch.uint8 or tuple(mask.shape) != (m, n) or not mask.is_cuda:
+        raise ValueError(f"mask: expected a ({m}, {n}) uint8 device tensor")
+    if n > 1 and mask.stride(1) != 1:
+        raise ValueError("mask: the last dimension must be contiguous")
+    ldk = mask.stride(0) if m > 1 else n
+    if X is None:
+        X = torch.empty((4, m, n), dtype=torch.float32, device=dev)
+    px, ldx, xps = _planes(X, m, n, "X")
+    if fit is None:
+        fit = torch.empty(iters, dtype=torch.float64, device=dev)
+    elif fit is False:
+        fit = None
+    need = qlra_complete_workspace_size(m, n, rank, p, pass_budget, scheme, sigma, precision, transpose, sketch)
+    if workspace is None or workspace.numel() < need:
+        workspace = _workspace(need, dev)
+    o = Opts(precision, 0, _stream_ptr(stream), ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+             1 if graph else 0, 1 if transpose else 0, sketch)
+    rc = _lib.qlra_complete(pm, m, n, ldm, mps, ctypes.c_void_p(mask.data_ptr()), ldk, rank, p, pass_budget, scheme,
+                            ctypes.c_uint64(seed), iters, float(sigma), ctypes.byref(o), px, ldx, xps,
+                            ctypes.c_void_p(fit.data_ptr()) if fit is not None else None)
+    _check(rc, "qlra_complete")
+    return X, fit, workspace
 
 
 def qlra_status(workspace, stream=None):

@@ -41,3 +41,24 @@ def test_workspace_size_and_argument_errors_without_gpu():
         else:
             raise AssertionError(args)
     assert Q.strerror(Q.QLRA_E_NUMERIC).startswith("numerical")
+
+
+def test_completion_workspace_and_argument_errors_without_gpu():
+    from paper_2507_13731_amd import qlra as Q
+    small = Q.qlra_complete_workspace_size(256, 256, 30, 10, 2, "subspace", 0.6)
+    assert small > 4 * 256 * 256 * 4
+    assert Q.qlra_complete_workspace_size(256, 256, 30, 10, 2, "subspace", 0.0) > 0
+    assert Q.qlra_complete_workspace_size(300, 200, 20, 5, 4, "krylov", 8.0 / 3.0, transpose=True) > 0
+    for sigma in (2.7, float("nan")):          # radius ceil(3 sigma) > 8, or no number
+        try:
+            Q.qlra_complete_workspace_size(64, 64, 4, 2, 2, "subspace", sigma)
+        except Q.QlraError as e:
+            assert e.code == Q.QLRA_E_UNSUPPORTED
+        else:
+            raise AssertionError(sigma)
+    try:
+        Q.qlra_complete_workspace_size(10, 8, 7, 2, 2, "subspace", 0.6)
+    except Q.QlraError as e:
+        assert e.code == Q.QLRA_E_ARG
+    else:
+        raise AssertionError("rank + p > min(m, n)")

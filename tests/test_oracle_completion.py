@@ -39,3 +39,18 @@ def test_completion_with_everything_observed_is_one_approximation(oracle):
     U, S, V, _ = oracle.qlra(M, 6, 4, 3, 1, 2)
     assert np.abs(X - oracle.reconstruct(U, S, V)).max() < 1e-12
     assert np.allclose(fit, fit[0])
+
+
+def test_completion_on_the_adjoint_completes_the_adjoint(oracle):
+    """Running each rank-R step on C^H (and exchanging the factors) is the completion of M^H with
+    the mask transposed, transposed back."""
+    M = W.planted(6, 30, 44, 3)
+    mask = (np.random.default_rng(2).random((30, 44)) < 0.5).astype(np.uint8)
+    X, fit = oracle.complete(M, mask, 3, 3, 3, 0, 4, 4, 0.6, adjoint=True)
+    Mh = M.transpose(0, 2, 1).copy()
+    Mh[1:] *= -1
+    Xh, fith = oracle.complete(Mh, mask.T, 3, 3, 3, 0, 4, 4, 0.6)
+    Xb = Xh.transpose(0, 2, 1).copy()
+    Xb[1:] *= -1
+    assert np.abs(X - Xb).max() < 1e-12
+    assert np.allclose(fit, fith, rtol=1e-12)
