@@ -34,7 +34,6 @@ struct StepArgs {
     float* C; int64_t ldc, cps;
     float* X; int64_t ldx, xps;
     int64_t m, n;
-    int h, T;   // smoothing radius, output tile side
     float w[2 * kCompleteMaxRadius + 1];
     const int* iter; int iters;
     double* part;
@@ -42,15 +41,19 @@ struct StepArgs {
 
 __device__ __forceinline__ int64_t clampi(int64_t v, int64_t hi) { return v < 0 ? 0 : (v > hi ? hi : v); }
 
+// H: smoothing radius (0: none); output tile T = kZ - 2H, region kZ x kZ around it
+template <int H>
 __global__ __launch_bounds__(256) void k_complete_step(StepArgs a) {
+    constexpr int T = kZ - 2 * H, TAPS = 2 * H + 1;
+    static_assert(T >= 16 && (kRC * kZ) % 256 == 0, "tile");
     __shared__ f32x4 su[kRC][kZ];
     __shared__ f32x4 sv[kRC][kZ];
-    __shared__ float z[4][kZ][kZP];
+    __shared__ float z[H > 0 ? 4 : 1][H > 0 ? kZ : 1][H > 0 ? kZP : 1];
     __shared__ double red[2][4];
     const int tid = threadIdx.x;
     const int tx = tid & 15, ty = tid >> 4;
-    const int64_t oi = (int64_t)blockIdx.y * a.T, oj = (int64_t)blockIdx.x * a.T;   // output tile origin
-    const int64_t ri = oi - a.h, rj = oj - a.h;                                     // region origin
+    const int64_t oi = (int64_t)blockIdx.y * T, oj = (int64_t)blockIdx.x * T;   // output tile origin
+    const int64_t ri = oi - H, rj = oj - H;                                     // region origin
 
     float acc[3][3][4];
 #pragma unroll
@@ -62,44 +65,73 @@ __global__ __launch_bounds__(256) void k_complete_step(StepArgs a) {
 
     for (int r0 = 0; r0 < a.R; r0 += kRC) {
         __syncthreads();
-        // stage rows of U and of S V (16 consecutive ranks of a row per 16 threads), zero past R
-        for (int e = tid; e < kRC * kZ; e += 256) {
+        // stage rows of U and of S V (16 consecutive ranks of a row per 16 threads), zero past R;
+        // all loads of the round issued before the first store
+        f32x4 u[kRC * kZ / 256], v[kRC * kZ / 256];
+#pragma unroll
+        for (int s = 0; s < kRC * kZ / 256; s++) {
+            const int e = tid + 256 * s;
             const int r = e % kRC, t = e / kRC;
             const int rr = r0 + r;
-            f32x4 u = {0.f, 0.f, 0.f, 0.f}, v = {0.f, 0.f, 0.f, 0.f};
+            u[s] = f32x4{0.f, 0.f, 0.f, 0.f};
+            v[s] = f32x4{0.f, 0.f, 0.f, 0.f};
             if (rr < a.R) {
                 const float* up = a.U + clampi(ri + t, a.m - 1) * a.ldu + rr;
                 const float* vp = a.V + clampi(rj + t, a.n - 1) * a.ldv + rr;
-                const float s = (float)a.S[rr];
-                u = f32x4{up[0], up[a.ups], up[2 * a.ups], up[3 * a.ups]};
-                v = f32x4{s * vp[0], s * vp[a.vps], s * vp[2 * a.vps], s * vp[3 * a.vps]};
+                const float sc = (float)a.S[rr];
+                u[s] = f32x4{up[0], up[a.ups], up[2 * a.ups], up[3 * a.ups]};
+                v[s] = f32x4{sc * vp[0], sc * vp[a.vps], sc * vp[2 * a.vps], sc * vp[3 * a.vps]};
             }
-            su[r][t] = u;
-            sv[r][t] = v;
+        }
+#pragma unroll
+        for (int s = 0; s < kRC * kZ / 256; s++) {
+            const int e = tid + 256 * s;
+            su[e % kRC][e / kRC] = u[s];
+            sv[e % kRC][e / kRC] = v[s];
         }
         __syncthreads();
 #pragma unroll 4
         for (int r = 0; r < kRC; r++) {
-            f32x4 u[3], v[3];
+            f32x4 uu[3], vv[3];
 #pragma unroll
-            for (int i = 0; i < 3; i++) u[i] = su[r][ty + 16 * i];
+            for (int i = 0; i < 3; i++) uu[i] = su[r][ty + 16 * i];
 #pragma unroll
-            for (int j = 0; j < 3; j++) v[j] = sv[r][tx + 16 * j];
-            // x += u * conj(v): the Hamilton product with v's imaginary parts negated
+            for (int j = 0; j < 3; j++) vv[j] = sv[r][tx + 16 * j];
+            // x += p * conj(q): the Hamilton product with q's imaginary parts negated
 #pragma unroll
             for (int i = 0; i < 3; i++)
 #pragma unroll
                 for (int j = 0; j < 3; j++) {
-                    const f32x4 p = u[i], q = v[j];
-                    acc[i][j][0] += p[0] * q[0] + p[1] * q[1] + p[2] * q[2] + p[3] * q[3];
-                    acc[i][j][1] += p[1] * q[0] - p[0] * q[1] - p[2] * q[3] + p[3] * q[2];
-                    acc[i][j][2] += p[2] * q[0] - p[0] * q[2] + p[1] * q[3] - p[3] * q[1];
-                    acc[i][j][3] += p[3] * q[0] - p[0] * q[3] - p[1] * q[2] + p[2] * q[1];
+                    const f32x4 p = uu[i], q = vv[j];
+                    float* x = acc[i][j];
+                    x[0] = fmaf(p[0], q[0], x[0]); x[0] = fmaf(p[1], q[1], x[0]);
+                    x[0] = fmaf(p[2], q[2], x[0]); x[0] = fmaf(p[3], q[3], x[0]);
+                    x[1] = fmaf(p[1], q[0], x[1]); x[1] = fmaf(-p[0], q[1], x[1]);
+                    x[1] = fmaf(-p[2], q[3], x[1]); x[1] = fmaf(p[3], q[2], x[1]);
+                    x[2] = fmaf(p[2], q[0], x[2]); x[2] = fmaf(-p[0], q[2], x[2]);
+                    x[2] = fmaf(p[1], q[3], x[2]); x[2] = fmaf(-p[3], q[1], x[2]);
+                    x[3] = fmaf(p[3], q[0], x[3]); x[3] = fmaf(-p[0], q[3], x[3]);
+                    x[3] = fmaf(-p[1], q[2], x[3]); x[3] = fmaf(p[2], q[1], x[3]);
                 }
         }
     }
 
-    if (a.h > 0) {
+    // observed values and mask bits of this thread's outputs, loaded before the smoothing
+    float mv[3][3][4];
+    bool obs[3][3], out[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const int rw = ty + 16 * i, cl = tx + 16 * j;
+            const int64_t gi = oi + rw, gj = oj + cl;
+            out[i][j] = rw < T && cl < T && gi < a.m && gj < a.n;
+            obs[i][j] = out[i][j] && a.mask[gi * a.ldk + gj] != 0;
+#pragma unroll
+            for (int p = 0; p < 4; p++) mv[i][j][p] = obs[i][j] ? a.M[p * a.mps + gi * a.ldm + gj] : 0.f;
+        }
+
+    if constexpr (H > 0) {
         // separable Gaussian: along rows (column index moves), then along columns
 #pragma unroll
         for (int i = 0; i < 3; i++)
@@ -108,17 +140,17 @@ __global__ __launch_bounds__(256) void k_complete_step(StepArgs a) {
 #pragma unroll
                 for (int p = 0; p < 4; p++) z[p][ty + 16 * i][tx + 16 * j] = acc[i][j][p];
         __syncthreads();
-        const int taps = 2 * a.h + 1;
 #pragma unroll
         for (int i = 0; i < 3; i++)
 #pragma unroll
             for (int j = 0; j < 3; j++) {
                 const int rw = ty + 16 * i, cl = tx + 16 * j;
-                if (cl < a.T)
+                if (cl < T)
 #pragma unroll
                     for (int p = 0; p < 4; p++) {
                         float s = 0.f;
-                        for (int t = 0; t < taps; t++) s += a.w[t] * z[p][rw][cl + t];
+#pragma unroll
+                        for (int t = 0; t < TAPS; t++) s = fmaf(a.w[t], z[p][rw][cl + t], s);
                         acc[i][j][p] = s;
                     }
             }
@@ -127,7 +159,7 @@ __global__ __launch_bounds__(256) void k_complete_step(StepArgs a) {
         for (int i = 0; i < 3; i++)
 #pragma unroll
             for (int j = 0; j < 3; j++)
-                if (tx + 16 * j < a.T)
+                if (tx + 16 * j < T)
 #pragma unroll
                     for (int p = 0; p < 4; p++) z[p][ty + 16 * i][tx + 16 * j] = acc[i][j][p];
         __syncthreads();
@@ -136,11 +168,12 @@ __global__ __launch_bounds__(256) void k_complete_step(StepArgs a) {
 #pragma unroll
             for (int j = 0; j < 3; j++) {
                 const int rw = ty + 16 * i, cl = tx + 16 * j;
-                if (rw < a.T && cl < a.T)
+                if (rw < T && cl < T)
 #pragma unroll
                     for (int p = 0; p < 4; p++) {
                         float s = 0.f;
-                        for (int t = 0; t < taps; t++) s += a.w[t] * z[p][rw + t][cl];
+#pragma unroll
+                        for (int t = 0; t < TAPS; t++) s = fmaf(a.w[t], z[p][rw + t][cl], s);
                         acc[i][j][p] = s;
                     }
             }
@@ -153,20 +186,17 @@ __global__ __launch_bounds__(256) void k_complete_step(StepArgs a) {
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            const int rw = ty + 16 * i, cl = tx + 16 * j;
-            const int64_t gi = oi + rw, gj = oj + cl;
-            if (rw >= a.T || cl >= a.T || gi >= a.m || gj >= a.n) continue;
-            const bool obs = a.mask[gi * a.ldk + gj] != 0;
+            if (!out[i][j]) continue;
+            const int64_t gi = oi + ty + 16 * i, gj = oj + tx + 16 * j;
 #pragma unroll
             for (int p = 0; p < 4; p++) {
                 const float x = acc[i][j][p];
-                const float mv = a.M[p * a.mps + gi * a.ldm + gj];
-                a.C[p * a.cps + gi * a.ldc + gj] = obs ? mv : x;
+                a.C[p * a.cps + gi * a.ldc + gj] = obs[i][j] ? mv[i][j][p] : x;
                 if (last) a.X[p * a.xps + gi * a.ldx + gj] = x;
-                if (obs) {
-                    const double d = (double)x - (double)mv;
+                if (obs[i][j]) {
+                    const double d = (double)x - (double)mv[i][j][p];
                     mis += d * d;
-                    ref += (double)mv * (double)mv;
+                    ref += (double)mv[i][j][p] * (double)mv[i][j][p];
                 }
             }
         }
@@ -274,16 +304,27 @@ hipError_t complete_step_launch(const CompleteStep& s, hipStream_t st) {
     a.C = s.C; a.ldc = s.ldc; a.cps = s.cps;
     a.X = s.X; a.ldx = s.ldx; a.xps = s.xps;
     a.m = s.m; a.n = s.n;
-    a.h = h; a.T = complete_tile(h);
     // normalised taps exp(-t^2 / (2 sigma^2)), t = -h .. h, summed in FP64
     double w[2 * kCompleteMaxRadius + 1] = {0.0}, sum = 0.0;
     for (int t = -h; t <= h; t++) sum += (w[t + h] = h ? std::exp(-(double)t * t / (2.0 * s.sigma * s.sigma)) : 1.0);
     for (int t = 0; t <= 2 * h; t++) a.w[t] = (float)(w[t] / sum);
     a.iter = s.iter; a.iters = s.iters;
     a.part = s.part;
-    const int64_t gx = (s.n + a.T - 1) / a.T, gy = (s.m + a.T - 1) / a.T;
+    const int T = complete_tile(h);
+    const int64_t gx = (s.n + T - 1) / T, gy = (s.m + T - 1) / T;
     if (gx > 0x7fffffff || gy > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_complete_step, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, a);
+    const dim3 grid((unsigned)gx, (unsigned)gy);
+    switch (h) {
+        case 0: hipLaunchKernelGGL(k_complete_step<0>, grid, dim3(256), 0, st, a); break;
+        case 1: hipLaunchKernelGGL(k_complete_step<1>, grid, dim3(256), 0, st, a); break;
+        case 2: hipLaunchKernelGGL(k_complete_step<2>, grid, dim3(256), 0, st, a); break;
+        case 3: hipLaunchKernelGGL(k_complete_step<3>, grid, dim3(256), 0, st, a); break;
+        case 4: hipLaunchKernelGGL(k_complete_step<4>, grid, dim3(256), 0, st, a); break;
+        case 5: hipLaunchKernelGGL(k_complete_step<5>, grid, dim3(256), 0, st, a); break;
+        case 6: hipLaunchKernelGGL(k_complete_step<6>, grid, dim3(256), 0, st, a); break;
+        case 7: hipLaunchKernelGGL(k_complete_step<7>, grid, dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL(k_complete_step<8>, grid, dim3(256), 0, st, a); break;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_complete_fit, dim3(1), dim3(256), 0, st, (const double*)s.part, gx * gy, s.fit, s.iter,

@@ -24,10 +24,6 @@ def gq():
     return Q
 
 
-def rand_mask(seed, m, n, observed):
-    return (np.random.default_rng(seed).random((m, n)) < observed).astype(np.uint8)
-
-
 def run_gpu(gq, M32, mask, rank, p, v, scheme, seed, iters, sigma, **kw):
     import torch
     Md = torch.from_numpy(M32).cuda()
@@ -59,29 +55,19 @@ def test_completion_matches_oracle(gq, oracle, name):
     print(f"completion {name}: {m} x {n} rank {rank} p {p} v {v} scheme {scheme} sigma {sigma:.3f}", flush=True)
     M = W.planted(21, m, n, rank) + 0.01 * W.random_quat(22, m, n)
     M32 = M.astype(np.float32)
-    mask = rand_mask(23, m, n, observed)
+    mask = W.random_mask(23, m, n, observed)
     Xg, fg, st = run_gpu(gq, M32, mask, rank, p, v, scheme, 5, iters, sigma)
     assert st == gq.QLRA_OK
     Xo, fo = oracle.complete(M32.astype(np.float64), mask, rank, p, v, scheme, 5, iters, sigma)
     compare(Xg, fg, Xo, fo)
 
 
-def image_like(seed, m, n):
-    """Pure quaternion colour image stand-in: real plane 0, three smooth Gaussian random fields
-    (correlation 4 pixels) with a little uniform noise, in [0, 1]."""
-    rng = np.random.default_rng(seed)
-    A = np.zeros((4, m, n))
-    for q in range(1, 4):
-        A[q] = np.clip(W.grf_plane(rng, m, n, corr=4.0) + rng.uniform(-0.02, 0.02, (m, n)), 0.0, 1.0)
-    return A.astype(np.float32)
-
-
 def test_image_workload_matches_oracle(gq, oracle):
     """The inpainting set-up: 256 x 256 pure quaternion image, 70 % of the pixels missing, rank 30,
     oversampling 10, two passes (Alg. 2), Gaussian smoothing 0.6 after each iteration."""
     print("completion image 256 x 256, 70% missing, rank 30, 2 passes, sigma 0.6", flush=True)
-    M32 = image_like(31, 256, 256)
-    mask = rand_mask(32, 256, 256, 0.3)
+    M32 = W.image_like(31, 256, 256)
+    mask = W.random_mask(32, 256, 256, 0.3)
     Xg, fg, st = run_gpu(gq, M32, mask, 30, 10, 2, 0, 9, 10, 0.6)
     assert st == gq.QLRA_OK
     Xo, fo = oracle.complete(M32.astype(np.float64), mask, 30, 10, 2, 0, 9, 10, 0.6)
@@ -95,7 +81,7 @@ def test_real_sketch_on_the_adjoint(gq, oracle):
     m, n, rank, p = 60, 90, 4, 4
     print(f"completion real sketch on the adjoint {m} x {n}", flush=True)
     M32 = (W.planted(41, m, n, rank) + 0.01 * W.random_quat(42, m, n)).astype(np.float32)
-    mask = rand_mask(43, m, n, 0.5)
+    mask = W.random_mask(43, m, n, 0.5)
     Xg, fg, st = run_gpu(gq, M32, mask, rank, p, 2, 0, 6, 4, 0.6, transpose=True, sketch=gq.QLRA_SKETCH_REAL)
     assert st == gq.QLRA_OK
     Om = gq.qlra_omega(6, m, rank + p).cpu().numpy().astype(np.float64)
@@ -112,7 +98,7 @@ def test_graph_replays_equal_eager(gq):
     m, n = 88, 75
     print(f"completion graph vs eager {m} x {n}", flush=True)
     M = torch.from_numpy((W.planted(51, m, n, 4) + 0.01 * W.random_quat(52, m, n)).astype(np.float32)).cuda()
-    K = torch.from_numpy(rand_mask(53, m, n, 0.5)).cuda()
+    K = torch.from_numpy(W.random_mask(53, m, n, 0.5)).cuda()
     Xe, fe, _ = gq.qlra_complete(M, K, 4, 4, 3, 1, 8, 5, 0.6)
     X = torch.empty_like(M)
     fit = torch.empty(5, dtype=torch.float64, device="cuda")

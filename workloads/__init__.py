@@ -208,3 +208,18 @@ def planted(seed, m, n, r, dtype=np.float64):
 
 def random_quat(seed, r, c, dtype=np.float64):
     return qgauss(np.random.default_rng(seed), r, c, dtype)
+
+
+def image_like(seed, m, n, corr=4.0):
+    """Pure quaternion colour-image stand-in: real plane 0, three smooth Gaussian random fields
+    (correlation `corr` pixels) with U(-0.02, 0.02) noise, clipped to [0, 1]; FP32 planes."""
+    rng = np.random.default_rng(seed)
+    A = np.zeros((4, m, n))
+    for q in range(1, 4):
+        A[q] = np.clip(grf_plane(rng, m, n, corr=corr) + rng.uniform(-0.02, 0.02, (m, n)), 0.0, 1.0)
+    return A.astype(np.float32)
+
+
+def random_mask(seed, m, n, observed):
+    """0/1 uint8 mask, each entry observed independently with probability `observed`."""
+    return (np.random.default_rng(seed).random((m, n)) < observed).astype(np.uint8)
