@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-completion", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--only-large", action="store_true",
+                    help="run only the 16384 x 16384 solves and print their record")
     ap.add_argument("--only-completion", action="store_true",
                     help="run only the matrix-completion workloads (for a kernel trace) and print their record")
     ap.add_argument("--counters", action="store_true",
@@ -285,6 +288,51 @@ def completion(Q, torch, W):
     return out
 
 
+# The large single matrix: 16384 x 16384 dense FP32, sigma_i = i^-1/2, block Krylov k = 128,
+# p = 32, budget 8 (final view 640 columns wide), plain FP32 against the precision form
+LARGE_N, LARGE_K, LARGE_P, LARGE_V = 16384, 128, 32, 8
+
+
+def large(Q, torch):
+    """End-to-end solve time of the 16384 x 16384 workload for each view precision (the mean of 3
+    solves after a warm-up, synchronised around each) and the returned error estimate e_v, which
+    is ||A - U S V^H||_F / ||A||_F by an exact identity (checked against the direct residual by
+    the full-size tests)."""
+    import numpy as np
+    from workloads import gpu as WG
+    print(f"large solve {LARGE_N}x{LARGE_N}: generating", file=sys.stderr, flush=True)
+    sigma = np.arange(1, LARGE_N + 1, dtype=np.float64) ** -0.5
+    A = WG.spectrum_matrix(4, LARGE_N, LARGE_N, sigma)
+    torch.cuda.synchronize()
+    rec = {"workload": f"dense {LARGE_N}x{LARGE_N} FP32, sigma_i = i^-1/2, block Krylov (Alg. 4) k={LARGE_K}, "
+                       f"p={LARGE_P}, v={LARGE_V}", "solves": 3}
+    U = torch.empty((4, LARGE_N, LARGE_K), device="cuda")
+    V = torch.empty((4, LARGE_N, LARGE_K), device="cuda")
+    S = torch.empty(LARGE_K, dtype=torch.float64, device="cuda")
+    e = torch.empty(LARGE_V, dtype=torch.float64, device="cuda")
+    for name, prec in (("fp32", Q.QLRA_FP32), ("bf16", Q.QLRA_BF16)):
+        print(f"large solve {name}", file=sys.stderr, flush=True)
+        ws = None
+        _, _, _, _, ws = Q.qlra(A, LARGE_K, LARGE_P, LARGE_V, "krylov", 11, U=U, S=S, V=V, pass_err=e, precision=prec)
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            Q.qlra(A, LARGE_K, LARGE_P, LARGE_V, "krylov", 11, U=U, S=S, V=V, pass_err=e, workspace=ws, precision=prec)
+            torch.cuda.synchronize()
+            t.append(time.perf_counter() - t0)
+        assert Q.qlra_status(ws) == Q.QLRA_OK
+        rec[f"{name}_solve_ms"] = round(1e3 * sum(t) / len(t), 3)
+        rec[f"{name}_e_v"] = float(e[-1].item())
+        del ws
+    rec["bf16_speedup_vs_fp32"] = round(rec["fp32_solve_ms"] / rec["bf16_solve_ms"], 3)
+    rec["bf16_error_ratio"] = rec["bf16_e_v"] / rec["fp32_e_v"]
+    rec["optimum_rank_k_error"] = float(np.sqrt(np.sum(sigma[LARGE_K:] ** 2) / np.sum(sigma ** 2)))
+    del A
+    torch.cuda.empty_cache()
+    return rec
+
+
 def cpu_baseline(A_np):
     """The FP64 oracle on the host: one full step (v = 2, 3, 4, 6) on the same matrix."""
     from oracle import oracle as O
@@ -359,6 +407,9 @@ def main():
 
     if args.only_completion:
         print(json.dumps({"completion": completion(Q, torch, W)}))
+        return
+    if args.only_large:
+        print(json.dumps({"large": large(Q, torch)}))
         return
     print("generating the 2048x2048 workload", file=sys.stderr, flush=True)
     A_np, _ = W.config1(seed=SEED_DATA, n=M, noise_std=0.01)
@@ -476,6 +527,7 @@ def main():
         print(f"serving stream ({args.serve_requests} requests)", file=sys.stderr, flush=True)
         serve = serving(Q, torch, args.serve_requests)
     comp = None if args.no_completion else completion(Q, torch, W)
+    big = None if args.no_large else large(Q, torch)
     cpu = None if args.no_cpu_baseline else cpu_baseline(A_np)
     line = {"metric": "A-passes/s", "value": round(value, 3), "unit": "A-passes/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
@@ -491,7 +543,7 @@ def main():
             "roofline": roofline, "cpu_baseline": cpu,
             "precision_form": {"views": "1..v-2 reduced (FP32 accumulation), v-1 and v FP32; Gram/Cholesky/QSVD FP64",
                                **lowp},
-            "serving": serve, "completion": comp}
+            "serving": serve, "completion": comp, "large": big}
     print(json.dumps(line))
 
 

@@ -459,103 +459,6 @@ __global__ __launch_bounds__(256) void k_rmul_tile(const double* __restrict__ R2
     st4(Rout, ps, (int64_t)a * w + b, acc);
 }
 
-// Larger factors: the same algorithm on a scratch copy in global memory (L2 resident).
-__global__ __launch_bounds__(kThreads) void k_chol_global(const double* __restrict__ G, int w,
-                                                           double* __restrict__ Rout, double* __restrict__ Rinv,
-                                                           const double* __restrict__ Rprev, double* __restrict__ W,
-                                                           int* status, int* shift_out, const int* gate,
-                                                           int allow_shift, double shift_scale, int* cond_gate) {
-    __shared__ int s_fail;
-    if (gate && *gate == 0) return;
-    const int tid = threadIdx.x;
-    const int64_t ps = (int64_t)w * w;
-    double shift = 0.0;
-    int shifted = 0, failed = 0;
-    for (int attempt = 0; attempt < 2; attempt++) {
-        for (int64_t e = tid; e < ps; e += kThreads) {
-            const int a = (int)(e / w), b = (int)(e % w);
-            Q4 v = (b >= a) ? ld4(G, ps, e) : Q4{0, 0, 0, 0};
-            if (a == b) { v.w += shift; v.x = v.y = v.z = 0.0; }
-            st4(W, ps, e, v);
-        }
-        if (tid == 0) s_fail = 0;
-        __syncthreads();
-        for (int j = 0; j < w; j++) {
-            const double d = W[(int64_t)j * w + j];
-            if (!(d > 0.0) || !(d < 1e300)) {
-                if (tid == 0) s_fail = 1;
-                break;
-            }
-            const double rjj = sqrt(d), inv = 1.0 / rjj;
-            __syncthreads();
-            for (int c = j + 1 + tid; c < w; c += kThreads) {
-                const int64_t e = (int64_t)j * w + c;
-                st4(W, ps, e, qscale(ld4(W, ps, e), inv));
-            }
-            if (tid == 0) st4(W, ps, (int64_t)j * w + j, Q4{rjj, 0, 0, 0});
-            __syncthreads();
-            const int t = w - j - 1;
-            for (int64_t e = tid; e < (int64_t)t * t; e += kThreads) {
-                const int a = j + 1 + (int)(e / t), b = j + 1 + (int)(e % t);
-                if (b < a) continue;
-                const int64_t ab = (int64_t)a * w + b;
-                Q4 v = qsub(ld4(W, ps, ab), qmul(qconj(ld4(W, ps, (int64_t)j * w + a)), ld4(W, ps, (int64_t)j * w + b)));
-                if (a == b) v.x = v.y = v.z = 0.0;
-                st4(W, ps, ab, v);
-            }
-            __syncthreads();
-        }
-        __syncthreads();
-        if (!s_fail) break;
-        if (!allow_shift || attempt == 1) { failed = 1; break; }
-        double tr = 0.0;
-        for (int i = 0; i < w; i++) tr += G[(int64_t)i * w + i];
-        shift = shift_scale * tr;
-        if (!(shift > 0.0)) shift = 1e-300;
-        shifted = 1;
-        __syncthreads();
-    }
-    if (tid == 0) {
-        if (shift_out) *shift_out = shifted;
-        if (failed) atomicOr(status, 2);
-        if (cond_gate) *cond_gate = 1;    // large factors: always run the second round
-    }
-    for (int64_t e = tid; e < ps; e += kThreads) {
-        const int a = (int)(e / w), b = (int)(e % w);
-        Q4 v{0, 0, 0, 0};
-        if (b >= a) {
-            if (Rprev) {
-                for (int t = a; t <= b; t++) {
-                    const Q4 pr = qmul(ld4(W, ps, (int64_t)a * w + t), ld4(Rprev, ps, (int64_t)t * w + b));
-                    v.w += pr.w; v.x += pr.x; v.y += pr.y; v.z += pr.z;
-                }
-                if (a == b) v.x = v.y = v.z = 0.0;
-            } else {
-                v = ld4(W, ps, e);
-            }
-        }
-        st4(Rout, ps, e, v);
-    }
-    if (!Rinv) return;
-    __syncthreads();
-    for (int64_t e = tid; e < ps; e += kThreads) st4(Rinv, ps, e, Q4{0, 0, 0, 0});
-    __syncthreads();
-    for (int i = w - 1; i >= 0; i--) {
-        const double rii = W[(int64_t)i * w + i];
-        const double inv = rii > 0.0 ? 1.0 / rii : 0.0;
-        for (int c = i + tid; c < w; c += kThreads) {
-            if (c == i) { Rinv[(int64_t)i * w + i] = inv; continue; }
-            Q4 s{0, 0, 0, 0};
-            for (int t = i + 1; t <= c; t++) {
-                const Q4 pr = qmul(ld4(W, ps, (int64_t)i * w + t), ld4(Rinv, ps, (int64_t)t * w + c));
-                s.w += pr.w; s.x += pr.x; s.y += pr.y; s.z += pr.z;
-            }
-            st4(Rinv, ps, (int64_t)i * w + c, qscale(s, -inv));
-        }
-        __syncthreads();
-    }
-}
-
 // Rout = R2 * R1 for upper triangular factors (only the upper triangle is formed).
 __global__ __launch_bounds__(256) void k_rmul(const double* __restrict__ R2, const double* __restrict__ R1,
                                               double* __restrict__ Rout, int w, const int* gate) {
@@ -578,6 +481,50 @@ __global__ __launch_bounds__(256) void k_rcopy(const double* __restrict__ src, d
     if (gate && *gate == 0) return;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < count) dst[e] = src[e];
+}
+
+// ------------------------------------------------------------------------------------------
+// Pieces of the blocked factorization of orders above kLdsMax (the block steps are driven from
+// the host side of the library: diagonal blocks by k_chol_lds, the rest as FP64 products).
+
+// W = G with a real diagonal, plus shift I where shift = shift_scale * trace(G) (at least 1e-300)
+// when `shifted`; nothing when gate && *gate == 0.
+__global__ __launch_bounds__(256) void k_chol_prep(const double* __restrict__ G, int w, double* __restrict__ W,
+                                                   const int* gate, int shifted, double shift_scale) {
+    if (gate && *gate == 0) return;
+    double shift = 0.0;
+    if (shifted) {
+        double tr = 0.0;
+        for (int i = 0; i < w; i++) tr += G[(int64_t)i * w + i];
+        shift = shift_scale * tr;
+        if (!(shift > 0.0)) shift = 1e-300;
+    }
+    const int64_t ps = (int64_t)w * w;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < ps; e += (int64_t)gridDim.x * 256) {
+        Q4 v = ld4(G, ps, e);
+        if (e / w == e % w) { v.w += shift; v.x = v.y = v.z = 0.0; }
+        st4(W, ps, e, v);
+    }
+}
+
+// dst (rows x cols FP64 planes) = src; nothing when gate && *gate == 0.
+__global__ __launch_bounds__(256) void k_copy_f64_planes(const double* __restrict__ src, int64_t lds, int64_t sps,
+                                                         double* __restrict__ dst, int64_t ldd, int64_t dps,
+                                                         int64_t rows, int64_t cols, const int* gate) {
+    if (gate && *gate == 0) return;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < rows * cols; e += (int64_t)gridDim.x * 256) {
+        const int64_t r = e / cols, c = e - r * cols;
+        st4(dst, dps, r * ldd + c, ld4(src, sps, r * lds + c));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_zero_f64(double* __restrict__ p, int64_t count, const int* gate) {
+    if (gate && *gate == 0) return;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) p[e] = 0.0;
+}
+
+__global__ void k_flag_nonzero(int* dst, const int* src) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src != 0 ? 1 : 0;
 }
 
 }  // namespace
@@ -612,6 +559,37 @@ hipError_t trsm_launch(const float* Y, int64_t ldy, int64_t yps, float* Q, int64
     return hipGetLastError();
 }
 
+static unsigned grid_for(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    if (g > 1024) g = 1024;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+hipError_t chol_prep_launch(const double* G, int64_t w, double* W, const int* gate, int shifted, double shift_scale,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_chol_prep, dim3(grid_for(w * w)), dim3(256), 0, st, G, (int)w, W, gate, shifted, shift_scale);
+    return hipGetLastError();
+}
+
+hipError_t copy_f64_planes_launch(const double* src, int64_t lds, int64_t sps, double* dst, int64_t ldd, int64_t dps,
+                                  int64_t rows, int64_t cols, const int* gate, hipStream_t st) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_f64_planes, dim3(grid_for(rows * cols)), dim3(256), 0, st, src, lds, sps, dst, ldd, dps,
+                       rows, cols, gate);
+    return hipGetLastError();
+}
+
+hipError_t zero_f64_launch(double* p, int64_t count, const int* gate, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_f64, dim3(grid_for(count)), dim3(256), 0, st, p, count, gate);
+    return hipGetLastError();
+}
+
+hipError_t flag_nonzero_launch(int* dst, const int* src, hipStream_t st) {
+    hipLaunchKernelGGL(k_flag_nonzero, dim3(1), dim3(64), 0, st, dst, src);
+    return hipGetLastError();
+}
+
 hipError_t chol_launch(const double* G, int64_t w, double* R, double* Rinv, const double* Rprev, double* work,
                        int* status, int* shift_out, const int* gate, int allow_shift, double shift_scale,
                        int* cond_gate, double cond_limit, hipStream_t st) {
@@ -626,8 +604,7 @@ hipError_t chol_launch(const double* G, int64_t w, double* R, double* Rinv, cons
                                R, (int)w, gate);
         }
     } else {
-        hipLaunchKernelGGL(k_chol_global, dim3(1), dim3(kThreads), 0, st, G, (int)w, R, Rinv, Rprev, work, status,
-                           shift_out, gate, allow_shift, shift_scale, cond_gate);
+        return hipErrorInvalidValue;   // larger orders: the blocked factorization
     }
     return hipGetLastError();
 }

@@ -97,7 +97,18 @@ hipError_t omega_launch(uint64_t seed, int64_t n, int64_t l, float* Om, int64_t 
 hipError_t chol_launch(const double* G, int64_t w, double* Rout, double* Rinv, const double* Rprev,
                        double* work, int* status, int* shift_out, const int* gate, int allow_shift,
                        double shift_scale, int* cond_gate, double cond_limit, hipStream_t st);
-int chol_lds_max();
+int chol_lds_max();   // chol_launch handles w <= chol_lds_max(); larger orders are factored by blocks
+// Pieces of the blocked factorization (each does nothing when gate && *gate == 0):
+// W = G with a real diagonal (+ shift_scale * trace(G) on it when `shifted`);
+hipError_t chol_prep_launch(const double* G, int64_t w, double* W, const int* gate, int shifted, double shift_scale,
+                            hipStream_t st);
+// dst (rows x cols FP64 planes) = src;
+hipError_t copy_f64_planes_launch(const double* src, int64_t lds, int64_t sps, double* dst, int64_t ldd, int64_t dps,
+                                  int64_t rows, int64_t cols, const int* gate, hipStream_t st);
+// p[0..count) = 0;
+hipError_t zero_f64_launch(double* p, int64_t count, const int* gate, hipStream_t st);
+// *dst = (*src != 0).
+hipError_t flag_nonzero_launch(int* dst, const int* src, hipStream_t st);
 // Cholesky alone for w <= chol_reg_max(), factor to R (no inverse); same status, shift and gate
 // behaviour as chol_launch.
 int chol_reg_max();

@@ -43,7 +43,7 @@ struct Ctx {
     double* G = nullptr;            // Gram, wmax x wmax
     double* R1 = nullptr;
     double* R2 = nullptr;
-    double* Rt = nullptr;
+    double* blk = nullptr;          // blocked Cholesky: four (<= chol_lds_max())^2 FP64 blocks
     double* Rinv = nullptr;
     float* T2 = nullptr;            // CholQR intermediate, rows x wmax
     int64_t T2_rows = 0;
@@ -97,6 +97,67 @@ double shift_scale(int64_t rows, int64_t w) {
     return 11.0 * ((double)rows * w + (double)w * (w + 1)) * 1.1102230246251565e-16;
 }
 
+size_t chol_blk_doubles() { return (size_t)16 * chol_lds_max() * chol_lds_max(); }
+
+// Cholesky G (+ shift I) = R^H R and R^{-1} for orders above chol_lds_max(): right-looking by
+// diagonal blocks of at most chol_lds_max().  Block k: R_kk and R_kk^{-1} from the LDS kernel on
+// the updated diagonal block, the block row R_k,rest = R_kk^{-H} W_k,rest and the trailing update
+// W_rest -= R_k,rest^H R_k,rest as FP64 products; then the off-diagonal blocks of R^{-1}, column
+// by column from the diagonal up: X_ij = -X_ii (R_i,(i+1..j) X_(i+1..j),j).  With allow_shift a
+// breakdown of the unshifted pass (flag in status[2]) reruns everything, gated on that flag, on
+// G + shift_scale tr(G) I; a breakdown that remains ORs 2 into status[0].  Rout = R Rprev when
+// Rprev is given.  Scratch: chol_work (W), blk, and R2 when Rprev is given.
+void chol_blocked(Ctx& c, const double* G, int64_t w, double* Rout, double* Rinv, const double* Rprev, int* shift_out,
+                  int allow_shift, double sscale) {
+    const int64_t nb = (w + chol_lds_max() - 1) / chol_lds_max();
+    const int64_t b = (w + nb - 1) / nb;
+    const int64_t ps = w * w, bs = b * b;
+    double* W = c.chol_work;
+    double* Rw = Rprev ? c.R2 : Rout;
+    double* Gk = c.blk;
+    double* Rk = Gk + 4 * bs;
+    double* Ik = Rk + 4 * bs;
+    double* T = Ik + 4 * bs;
+    int* fail = c.status ? c.status + 2 : nullptr;
+    if (c.live() && allow_shift) note(c, fill_int_launch(fail, 1, 0, c.st));
+    for (int attempt = 0; attempt < (allow_shift ? 2 : 1); attempt++) {
+        const int* gate = attempt ? fail : nullptr;
+        int* st = (allow_shift && attempt == 0) ? fail : c.status;
+        if (c.live()) {
+            note(c, chol_prep_launch(G, w, W, gate, attempt, sscale, c.st));
+            note(c, zero_f64_launch(Rw, 4 * ps, gate, c.st));
+            note(c, zero_f64_launch(Rinv, 4 * ps, gate, c.st));
+        }
+        for (int64_t k0 = 0; k0 < w; k0 += b) {
+            const int64_t kb = std::min(b, w - k0), k1 = k0 + kb, rest = w - k1;
+            if (c.live()) {
+                note(c, copy_f64_planes_launch(W + k0 * w + k0, w, ps, Gk, kb, kb * kb, kb, kb, gate, c.st));
+                note(c, chol_launch(Gk, kb, Rk, Ik, nullptr, nullptr, st, nullptr, gate, 0, 0.0, nullptr, 0.0, c.st));
+                note(c, copy_f64_planes_launch(Rk, kb, kb * kb, Rw + k0 * w + k0, w, ps, kb, kb, gate, c.st));
+                note(c, copy_f64_planes_launch(Ik, kb, kb * kb, Rinv + k0 * w + k0, w, ps, kb, kb, gate, c.st));
+            }
+            if (rest > 0) {
+                qg(c, desc(OP_HN, MATH_F64, Ik, kb, kb * kb, 1, W + k0 * w + k1, w, ps, 1, Rw + k0 * w + k1, w, ps, 1,
+                           kb, rest, kb, ST_SET, gate));
+                qg(c, desc(OP_HN, MATH_F64, Rw + k0 * w + k1, w, ps, 1, Rw + k0 * w + k1, w, ps, 1, W + k1 * w + k1, w,
+                           ps, 1, rest, rest, kb, ST_SUB, gate));
+            }
+        }
+        for (int64_t j0 = b; j0 < w; j0 += b) {
+            const int64_t jb = std::min(b, w - j0);
+            for (int64_t i0 = j0 - b; i0 >= 0; i0 -= b) {
+                const int64_t t0 = i0 + b, tk = j0 + jb - t0;
+                qg(c, desc(OP_NN, MATH_F64, Rw + i0 * w + t0, w, ps, 1, Rinv + t0 * w + j0, w, ps, 1, T, jb, b * jb, 1,
+                           b, jb, tk, ST_SET, gate));
+                qg(c, desc(OP_NN, MATH_F64, Rinv + i0 * w + i0, w, ps, 1, T, jb, b * jb, 1, Rinv + i0 * w + j0, w, ps, 1,
+                           b, jb, b, ST_SUB, gate));
+            }
+        }
+    }
+    if (Rprev) qg(c, desc(OP_NN, MATH_F64, Rw, w, ps, 1, Rprev, w, ps, 1, Rout, w, ps, 1, w, w, w));
+    if (shift_out && allow_shift && c.live()) note(c, flag_nonzero_launch(shift_out, fail, c.st));
+}
+
 // Thin QR of Y (rows x w): Q (ld ldq, plane stride qps) and R (w x w FP64, ld w; may be null
 // when only Q is wanted), Q may alias Y.  Each round is CholeskyQR with an FP64 Gram (exact
 // products of FP32 data), FP64 Cholesky and an FP64 application of R^{-1}.  With an FP64
@@ -130,10 +191,16 @@ void cholqr(Ctx& c, const float* Y, int64_t rows, int64_t w, int64_t ldy, int64_
                 note(c, trsm_launch(src, lds, sps, dst, ldd, dps, Rr, w, rows, nullptr, c.st));
             }
         } else {
-            double* Rout = last ? (R ? R : c.Rjunk) : (round == 0 ? c.R1 : c.R2);
-            if (c.live())
-                note(c, chol_launch(G, w, Rout, c.Rinv, Rprev, c.chol_work, c.status, round == 0 ? shifted : nullptr,
-                                    nullptr, round == 0 ? 1 : 0, shift_scale(rows, w), nullptr, 0.0, c.st));
+            double* Rout = last ? (R ? R : c.Rjunk) : c.R1;
+            if (w <= chol_lds_max()) {
+                if (c.live())
+                    note(c, chol_launch(G, w, Rout, c.Rinv, Rprev, c.chol_work, c.status,
+                                        round == 0 ? shifted : nullptr, nullptr, round == 0 ? 1 : 0,
+                                        shift_scale(rows, w), nullptr, 0.0, c.st));
+            } else {
+                chol_blocked(c, G, w, Rout, c.Rinv, Rprev, round == 0 ? shifted : nullptr, round == 0 ? 1 : 0,
+                             shift_scale(rows, w));
+            }
             qg(c, desc(OP_NN, MATH_F64, src, lds, sps, 0, c.Rinv, w, w * w, 1, dst, ldd, dps, 0, rows, w, w));
             Rprev = Rout;
         }
@@ -229,7 +296,7 @@ struct Bufs {
     float* T;               // rows_max x wmax
     float* T2;              // rows_max x wmax
     float* stack;           // stack_rows x Wk
-    double* G; double* R1; double* R2; double* Rt; double* Rinv; double* chol_work;
+    double* G; double* R1; double* R2; double* blk; double* Rinv; double* chol_work;
     double* Rv;             // v x (l x l)
     double* Rfin;           // wmax x wmax
     double* Cbuf;           // Wk x l
@@ -265,7 +332,7 @@ void carve(const Problem& pr, const Dims& d, Arena& ar, Bufs& b, size_t part_byt
     b.G = (double*)ar.take(4 * w2 * sizeof(double));
     b.R1 = (double*)ar.take(4 * w2 * sizeof(double));
     b.R2 = (double*)ar.take(4 * w2 * sizeof(double));
-    b.Rt = (double*)ar.take(4 * w2 * sizeof(double));
+    b.blk = d.wmax > chol_lds_max() ? (double*)ar.take(chol_blk_doubles() * sizeof(double)) : nullptr;
     b.Rinv = (double*)ar.take(4 * w2 * sizeof(double));
     b.chol_work = (double*)ar.take(4 * w2 * sizeof(double));
     b.Rv = (double*)ar.take((size_t)pr.v * 4 * l2 * sizeof(double));
@@ -619,7 +686,7 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
 void bind_ctx(Ctx& c, const Bufs& b, const Dims& d) {
     c.status = b.status;
     c.chol_work = b.chol_work;
-    c.G = b.G; c.R1 = b.R1; c.R2 = b.R2; c.Rt = b.Rt; c.Rinv = b.Rinv;
+    c.G = b.G; c.R1 = b.R1; c.R2 = b.R2; c.blk = b.blk; c.Rinv = b.Rinv;
     c.T2 = b.T2; c.T2_rows = d.rows_max;
     c.Rjunk = b.Rfin;
     c.scr.partial = b.partial;
@@ -1233,7 +1300,7 @@ static void cholqr_carve(int64_t m, int64_t w, Arena& ar, Ctx& c, size_t part, s
     c.G = (double*)ar.take(4 * w2 * sizeof(double));
     c.R1 = (double*)ar.take(4 * w2 * sizeof(double));
     c.R2 = (double*)ar.take(4 * w2 * sizeof(double));
-    c.Rt = (double*)ar.take(4 * w2 * sizeof(double));
+    c.blk = w > chol_lds_max() ? (double*)ar.take(chol_blk_doubles() * sizeof(double)) : nullptr;
     c.Rinv = (double*)ar.take(4 * w2 * sizeof(double));
     c.chol_work = (double*)ar.take(4 * w2 * sizeof(double));
     c.T2 = (float*)ar.take(4 * m * w * sizeof(float));

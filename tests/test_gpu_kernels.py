@@ -100,7 +100,7 @@ def test_qgemm_config1_view_sampled(gq, oracle):
 
 
 @pytest.mark.parametrize("m,w", [(37, 1), (500, 15), (333, 33), (2048, 60), (1001, 64), (64, 64), (1024, 80), (80, 80),
-                                 (777, 96), (500, 97), (3000, 160)])
+                                 (777, 96), (500, 97), (3000, 160), (2500, 200), (1500, 289)])
 def test_cholqr_matches_householder(gq, oracle, m, w):
     print(f"cholqr m={m} w={w}", flush=True)
     rng = np.random.default_rng(m + w)
@@ -118,16 +118,18 @@ def test_cholqr_matches_householder(gq, oracle, m, w):
     np.testing.assert_allclose(qref.mul(Qg.astype(np.float64), Rg), Y, atol=1e-4 * np.abs(Y).max())
 
 
-def test_cholqr_rank_deficient_uses_shift(gq, oracle):
+@pytest.mark.parametrize("m,w", [(600, 20), (900, 130)])
+def test_cholqr_rank_deficient_uses_shift(gq, oracle, m, w):
     """Exactly rank-deficient input: plain CholeskyQR breaks down; the shifted round keeps Q
-    orthonormal and Q R = Y."""
-    B = W.random_quat(3, 600, 5)
-    C = W.random_quat(4, 5, 20)
+    orthonormal and Q R = Y (w = 130: the blocked factorization's gated rerun)."""
+    print(f"cholqr rank 5, m={m} w={w}", flush=True)
+    B = W.random_quat(3, m, 5)
+    C = W.random_quat(4, 5, w)
     Y = qref.mul(B, C).astype(np.float32)
     Qg, Rg, ws = gq.qlra_cholqr(dev(Y), return_workspace=True)
     Qg, Rg = host(Qg).astype(np.float64), host(Rg)
     gram = qref.mul(qref.adj(Qg), Qg)
-    eye = np.zeros_like(gram); eye[0] = np.eye(20)
+    eye = np.zeros_like(gram); eye[0] = np.eye(w)
     assert np.abs(gram - eye).max() < 1e-3
     np.testing.assert_allclose(qref.mul(Qg, Rg), Y, atol=1e-4 * np.abs(Y).max())
     flags = host(ws[:64].view(dtype=__import__("torch").int32))
