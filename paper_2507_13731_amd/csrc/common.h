@@ -165,6 +165,12 @@ hipError_t heig_big_launch(const double* G, int64_t W, double* lam, double* E, i
 hipError_t estimate_batch_launch(const double* G, int64_t gstride, int64_t w, int nprob, int k, const double* nA2,
                                  double* e, double* work, hipStream_t st);
 
+// The batched problems of estimate_batch_launch (nest of them) and one more, problem nest, whose
+// eigenvalues (descending, lam) and eigenvectors (E, may be null) are wanted, in one launch
+// sequence; work: heig_work_doubles(nest + 1).
+hipError_t heig_with_estimates_launch(const double* G, int64_t gstride, int64_t w, int nest, int k, const double* nA2,
+                                      double* e, double* lam, double* E, double* work, hipStream_t st);
+
 // e = sqrt(max(0, nA2 - sum_{j<k} S_j^2) / nA2)
 hipError_t estimate_launch(const double* S, int k, const double* nA2, double* e, hipStream_t st);
 hipError_t nan_launch(double* e, hipStream_t st);

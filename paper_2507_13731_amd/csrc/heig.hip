@@ -332,9 +332,10 @@ __device__ int sturm_count(double dv, double dv2, double b2v, double b2v2, int w
 }
 
 // grid (ceil(w / kPer), problems); lam_out (optional): descending eigenvalues of problem b at
-// lam_out + b * lam_stride.  The ascending ones go to the record.
+// lam_out + b * lam_stride, or with lam_prob >= 0 those of problem lam_prob alone at lam_out.  The
+// ascending ones go to the record.
 __global__ __launch_bounds__(ET) void k_eigvals(double* __restrict__ triall, int w, double* __restrict__ lam_out,
-                                                int64_t lam_stride) {
+                                                int64_t lam_stride, int lam_prob) {
     double* tri = triall + (int64_t)blockIdx.y * kTriStride;
     const int tid = threadIdx.x, lane = tid & 63, s16 = tid & 15;
     // exact power-of-two scaling: |bounds| <= 1 afterwards
@@ -362,7 +363,8 @@ __global__ __launch_bounds__(ET) void k_eigvals(double* __restrict__ triall, int
     if (k < w && s16 == 0) {
         const double lam = 0.5 * (a + bb);
         tri[OFF_LAM + k] = lam;
-        if (lam_out) lam_out[(int64_t)blockIdx.y * lam_stride + (w - 1 - k)] = lam;
+        if (lam_out && (lam_prob < 0 || (int)blockIdx.y == lam_prob))
+            lam_out[(lam_prob < 0 ? (int64_t)blockIdx.y * lam_stride : 0) + (w - 1 - k)] = lam;
     }
 }
 
@@ -641,7 +643,7 @@ hipError_t heig_launch(const double* G, int64_t w, double* lam, double* E, doubl
     else
         hipLaunchKernelGGL((k_tridiag<8, 12, 768>), dim3(1), dim3(768), 0, st, G, (int64_t)0, (int)w, work, E ? 1 : 0);
     const unsigned slices = (unsigned)((w + kPer - 1) / kPer);
-    hipLaunchKernelGGL(k_eigvals, dim3(slices, 1), dim3(ET), 0, st, work, (int)w, lam, (int64_t)0);
+    hipLaunchKernelGGL(k_eigvals, dim3(slices, 1), dim3(ET), 0, st, work, (int)w, lam, (int64_t)0, -1);
     if (E)
         hipLaunchKernelGGL(k_eigvecs, dim3((unsigned)((w + kVecPer - 1) / kVecPer)), dim3(ET), 0, st,
                            (const double*)work, (int)w, E);
@@ -658,9 +660,28 @@ hipError_t estimate_batch_launch(const double* G, int64_t gstride, int64_t w, in
         hipLaunchKernelGGL((k_tridiag<8, 12, 768>), dim3((unsigned)nprob), dim3(768), 0, st, G, gstride, (int)w, work, 0);
     const unsigned slices = (unsigned)((w + kPer - 1) / kPer);
     hipLaunchKernelGGL(k_eigvals, dim3(slices, (unsigned)nprob), dim3(ET), 0, st, work, (int)w, (double*)nullptr,
-                       (int64_t)0);
+                       (int64_t)0, -1);
     hipLaunchKernelGGL(k_estimate_batch, dim3((unsigned)((nprob + 63) / 64)), dim3(64), 0, st, (const double*)work,
                        nprob, (int)w, k, nA2, e);
+    return hipGetLastError();
+}
+
+hipError_t heig_with_estimates_launch(const double* G, int64_t gstride, int64_t w, int nest, int k, const double* nA2,
+                                      double* e, double* lam, double* E, double* work, hipStream_t st) {
+    if (w < 1 || w > kW || nest < 0) return hipErrorInvalidValue;
+    const unsigned np = (unsigned)nest + 1;
+    if (w <= 64)
+        hipLaunchKernelGGL((k_tridiag<16, 4, 1024>), dim3(np), dim3(1024), 0, st, G, gstride, (int)w, work, 1);
+    else
+        hipLaunchKernelGGL((k_tridiag<8, 12, 768>), dim3(np), dim3(768), 0, st, G, gstride, (int)w, work, 1);
+    const unsigned slices = (unsigned)((w + kPer - 1) / kPer);
+    hipLaunchKernelGGL(k_eigvals, dim3(slices, np), dim3(ET), 0, st, work, (int)w, lam, (int64_t)0, nest);
+    if (E)
+        hipLaunchKernelGGL(k_eigvecs, dim3((unsigned)((w + kVecPer - 1) / kVecPer)), dim3(ET), 0, st,
+                           (const double*)(work + (size_t)nest * kTriStride), (int)w, E);
+    if (nest > 0)
+        hipLaunchKernelGGL(k_estimate_batch, dim3((unsigned)((nest + 63) / 64)), dim3(64), 0, st, (const double*)work,
+                           nest, (int)w, k, nA2, e);
     return hipGetLastError();
 }
 

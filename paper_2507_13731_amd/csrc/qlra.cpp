@@ -285,6 +285,12 @@ Dims dims_of(int64_t m, int64_t n, int k, int p, int v, int scheme) {
     return d;
 }
 
+// Subspace scheme with l <= heig_max(): the estimates of views 2 .. v-1 ride along with the final
+// eigendecomposition (one batched launch sequence on the solve's own stream, no side stream).
+bool merged_estimates(const Problem& pr, const Dims& d) {
+    return pr.estimate && !d.krylov && pr.v > 2 && d.l <= heig_max();
+}
+
 struct Bufs {
     int* status;            // 16 ints
     unsigned* counters;
@@ -350,8 +356,10 @@ void carve(const Problem& pr, const Dims& d, Arena& ar, Bufs& b, size_t part_byt
     b.side_S = (double*)ar.take(d.l * sizeof(double));
     b.side_lam = (double*)ar.take(d.l * sizeof(double));
     b.side_work = batched ? nullptr : (double*)ar.take(qsvd_work_doubles(d.l) * sizeof(double));
-    b.Gs = batched && nest ? (double*)ar.take((size_t)nest * 4 * l2 * sizeof(double)) : nullptr;
-    b.est_work = batched && nest ? (double*)ar.take((small_l ? heig_work_doubles(nest) : heig_big_work_doubles(d.l, 0)) *
+    const int64_t extra = merged_estimates(pr, d) ? 1 : 0;   // the final Gram joins the batch
+    b.Gs = batched && nest ? (double*)ar.take((size_t)(nest + extra) * 4 * l2 * sizeof(double)) : nullptr;
+    b.est_work = batched && nest ? (double*)ar.take((small_l ? heig_work_doubles(nest + extra)
+                                                             : heig_big_work_doubles(d.l, 0)) *
                                                     sizeof(double))
                                  : nullptr;
     // the final QSVD of a view wider than heig_max()
@@ -367,21 +375,22 @@ void carve(const Problem& pr, const Dims& d, Arena& ar, Bufs& b, size_t part_byt
     b.partial = part_bytes ? ar.take(part_bytes) : nullptr;
 }
 
-// Per-device side stream and events (default priority).
+// Side stream and events for the estimates, one set per (device, caller stream) pair (default
+// priority): solves issued on different streams then share no side stream, so that one solve's
+// join never waits behind another solve's estimates.
 struct Side {
     hipStream_t s = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
 };
 std::mutex g_side_mu;
-Side g_side[64];
+std::map<std::pair<int, hipStream_t>, Side> g_sides;
 
-hipError_t get_side(Side* out) {
+hipError_t get_side(hipStream_t main, Side* out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
-    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
     std::lock_guard<std::mutex> lk(g_side_mu);
-    Side& sd = g_side[dev];
+    Side& sd = g_sides[std::make_pair(dev, main)];
     if (!sd.s) {
         if ((e = hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking)) != hipSuccess) return e;
         if ((e = hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming)) != hipSuccess) return e;
@@ -532,13 +541,19 @@ void finish(Ctx& c, const Bufs& b, const Problem& pr, const double* R, int64_t w
 // X-side factor X E_k.  y_is_u: odd budget (Y = A Q2 gives U, X = Q2 gives V); otherwise Y gives
 // V and X = Q1 gives U.  For w <= heig_big_max() (the single-workgroup solver up to heig_max()).
 void finish_gram(Ctx& c, const Bufs& b, const Problem& pr, const float* Y, int64_t rows_y, const float* X,
-                 int64_t ldx, int64_t rows_x, int64_t w, bool y_is_u) {
+                 int64_t ldx, int64_t rows_x, int64_t w, bool y_is_u, bool merge_est = false) {
     const int k = pr.k;
     const bool big = w > heig_max();
     const int64_t lde = big ? k : w;     // eigenvectors in b.Rh: all w, or the k largest
-    qg(c, desc(OP_HN, MATH_F64, Y, w, rows_y * w, 0, Y, w, rows_y * w, 0, c.G, w, w * w, 1, w, w, rows_y));
+    // merged: the Gram goes to the slot after the estimate Grams of views 2 .. v-1
+    const int nest = pr.v - 2;
+    double* Gf = merge_est ? b.Gs + (size_t)nest * 4 * w * w : c.G;
+    qg(c, desc(OP_HN, MATH_F64, Y, w, rows_y * w, 0, Y, w, rows_y * w, 0, Gf, w, w * w, 1, w, w, rows_y));
     if (c.live()) {
-        if (big) note(c, heig_big_launch(c.G, w, b.Sw, b.Rh, k, b.big_work, big_nvec(w, k), c.st));
+        if (merge_est)
+            note(c, heig_with_estimates_launch(b.Gs, 4 * w * w, w, nest, k, b.nA2, pr.pass_err + 1, b.Sw, b.Rh,
+                                               b.est_work, c.st));
+        else if (big) note(c, heig_big_launch(c.G, w, b.Sw, b.Rh, k, b.big_work, big_nvec(w, k), c.st));
         else note(c, heig_launch(c.G, w, b.Sw, b.Rh, b.qsvd_work, c.st));
         note(c, svals_launch(b.Sw, b.Rh, lde, w, k, pr.S, b.Lh, c.st));
         if (pr.estimate) note(c, estimate_launch(pr.S, k, b.nA2, pr.pass_err + (pr.v - 1), c.st));
@@ -614,10 +629,11 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
         const bool gram_final = l <= heig_big_max();
         for (int i = 1; i <= pr.v; i++) {
             if (i == pr.v && gram_final) {
-                fork_estimates(c, b, pr, l);
+                const bool merge = merged_estimates(pr, d) && b.Gs;
+                if (!merge) fork_estimates(c, b, pr, l);
                 const bool odd = i % 2 == 1;
                 view_product(c, pr, b, !odd, odd ? Q2cur : b.Q1, l, l, b.T);
-                finish_gram(c, b, pr, b.T, odd ? pr.m : pr.n, odd ? Q2cur : b.Q1, l, odd ? pr.n : pr.m, l, odd);
+                finish_gram(c, b, pr, b.T, odd ? pr.m : pr.n, odd ? Q2cur : b.Q1, l, odd ? pr.n : pr.m, l, odd, merge);
                 return;
             }
             // R is kept for the last view (the final QSVD) and for side-stream estimates from R
@@ -1065,13 +1081,14 @@ int qlra(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stri
     c.cnt_need = cnt;
     bind_ctx(c, b, d);
     Side sd;
-    if (pr.estimate) {
-        if (get_side(&sd) != hipSuccess) return QLRA_E_HIP;
+    const bool forks = pr.estimate && !merged_estimates(pr, d);
+    if (forks) {
+        if (get_side((hipStream_t)opts->stream, &sd) != hipSuccess) return QLRA_E_HIP;
         c.side = sd.s; c.ev_fork = sd.fork; c.ev_join = sd.join;
     }
     auto enqueue = [&]() {
         run_solve(c, pr, d, b);
-        if (pr.estimate) {
+        if (c.forked) {
             note(c, hipEventRecord(c.ev_join, c.side));
             note(c, hipStreamWaitEvent(c.st, c.ev_join, 0));
         }
