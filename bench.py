@@ -310,7 +310,7 @@ def large(Q, torch):
     V = torch.empty((4, LARGE_N, LARGE_K), device="cuda")
     S = torch.empty(LARGE_K, dtype=torch.float64, device="cuda")
     e = torch.empty(LARGE_V, dtype=torch.float64, device="cuda")
-    for name, prec in (("fp32", Q.QLRA_FP32), ("bf16", Q.QLRA_BF16)):
+    for name, prec in (("fp32", Q.QLRA_FP32), ("bf16", Q.QLRA_BF16), ("bf16_split", Q.QLRA_BF16_SPLIT)):
         print(f"large solve {name}", file=sys.stderr, flush=True)
         ws = None
         _, _, _, _, ws = Q.qlra(A, LARGE_K, LARGE_P, LARGE_V, "krylov", 11, U=U, S=S, V=V, pass_err=e, precision=prec)
@@ -325,8 +325,9 @@ def large(Q, torch):
         rec[f"{name}_solve_ms"] = round(1e3 * sum(t) / len(t), 3)
         rec[f"{name}_e_v"] = float(e[-1].item())
         del ws
-    rec["bf16_speedup_vs_fp32"] = round(rec["fp32_solve_ms"] / rec["bf16_solve_ms"], 3)
-    rec["bf16_error_ratio"] = rec["bf16_e_v"] / rec["fp32_e_v"]
+    for name in ("bf16", "bf16_split"):
+        rec[f"{name}_speedup_vs_fp32"] = round(rec["fp32_solve_ms"] / rec[f"{name}_solve_ms"], 3)
+        rec[f"{name}_error_ratio"] = rec[f"{name}_e_v"] / rec["fp32_e_v"]
     rec["optimum_rank_k_error"] = float(np.sqrt(np.sum(sigma[LARGE_K:] ** 2) / np.sum(sigma ** 2)))
     del A
     torch.cuda.empty_cache()

@@ -56,9 +56,15 @@ enum { QLRA_SUBSPACE = 0, QLRA_BLOCK_KRYLOV = 1 };
  * FP32 MFMA.  QLRA_BF16 / QLRA_FP16: views 1 .. v-2 multiply BF16 / FP16
  * copies of A (made once per solve; FP16 with a power-of-two scale from
  * ||A||_F) by a rounded copy of the thin operand on MFMA with FP32
- * accumulation; views v-1 and v stay FP32 (v = 2 is plain FP32).  The
- * Gram, Cholesky and small QSVD steps are always FP64. */
-enum { QLRA_FP32 = 0, QLRA_BF16 = 1, QLRA_FP16 = 2 };
+ * accumulation; views v-1 and v stay FP32 (v = 2 is plain FP32).
+ * QLRA_BF16_SPLIT / QLRA_FP16_SPLIT: views 1 .. v-2 as for QLRA_BF16 /
+ * QLRA_FP16, and views v-1 and v (every view when v = 2) as three products
+ * of the same type on MFMA, a_hi b_hi + a_hi b_lo + a_lo b_hi with x_hi the
+ * rounded x and x_lo the rounded residual x - x_hi, FP32 accumulation: about
+ * 16 (BF16) or 22 (FP16) significant bits per product instead of FP32's 24,
+ * at a fraction of the FP32 MFMA time.  The Gram, Cholesky and small QSVD
+ * steps are always FP64. */
+enum { QLRA_FP32 = 0, QLRA_BF16 = 1, QLRA_FP16 = 2, QLRA_BF16_SPLIT = 3, QLRA_FP16_SPLIT = 4 };
 
 /* The sketch.  QLRA_SKETCH_QUATERNION: the Gaussian quaternion test matrix of
  * Sec. 2 (four independent N(0, 1) planes; see qlra_omega()).  QLRA_SKETCH_REAL:
@@ -276,6 +282,26 @@ int qlra_qgemm_lp(int op, int precision, const void* Alo, int64_t m, int64_t n,
                   const float* B, int64_t w, int64_t ldb, int64_t b_ps,
                   float* C, int64_t ldc, int64_t c_ps, const float* inv_scale,
                   void* workspace, size_t workspace_bytes, void* stream);
+
+/* The split form's pieces (precisions QLRA_BF16_SPLIT / QLRA_FP16_SPLIT).
+ * qlra_lowp_copy_residual() writes, in the layout of qlra_lowp_copy() and
+ * with the same scale, the residual copies: each element s a minus its
+ * rounded value (FP32), rounded to BF16 (precision QLRA_BF16) or FP16
+ * (QLRA_FP16); buffers of qlra_lowp_copy_bytes() bytes.
+ * qlra_qgemm_split() is the view product of qlra_qgemm_lp() computed as
+ * Ahi Bhi + Ahi Blo + Alo Bhi (Sec. 2, eq. (1) for each product), with Ahi
+ * the copy (Alo argument), Alo the residual copy (Alo_res), Bhi the rounded
+ * B and Blo the rounded B - Bhi, FP32 accumulation, times *inv_scale.  Needs
+ * qlra_qgemm_split_workspace_size() bytes of workspace (the rounded B and its
+ * residual, and three sets of split-K partial tiles, summed in a fixed
+ * order). */
+int qlra_lowp_copy_residual(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_ps, int precision,
+                            const float* scale, void* Alo_res, void* Alo_t_res, void* stream);
+int qlra_qgemm_split_workspace_size(int op, int precision, int64_t m, int64_t n, int64_t w, size_t* bytes);
+int qlra_qgemm_split(int op, int precision, const void* Alo, const void* Alo_res, int64_t m, int64_t n,
+                     const float* B, int64_t w, int64_t ldb, int64_t b_ps,
+                     float* C, int64_t ldc, int64_t c_ps, const float* inv_scale,
+                     void* workspace, size_t workspace_bytes, void* stream);
 
 /* Thin quaternion QR (eq. (QQR)) of a tall Y (m x w, m >= w) by CholeskyQR2:
  * FP64 Gram Y^H Y, FP64 quaternion Cholesky, FP64 triangular inverse, applied

@@ -31,7 +31,10 @@ enum QStore { ST_SET = 0, ST_SUB = 1 };   // C = R  |  C = C - R
 // the rows of the output (for OP_HN the transposed copy A^T; op then only selects the
 // conjugation signs) in the tiled layout of lowp_copy_launch (lda, aps unused), B is FP32 and
 // converted per launch, C is FP32 and multiplied by *cscale.
-enum QMath { MATH_F32 = 0, MATH_F64 = 1, MATH_BF16 = 2, MATH_F16 = 3 };
+// MATH_BF16X3 / MATH_F16X3: the split form, A_hi B_hi + A_hi B_lo + A_lo B_hi with A = the
+// low-precision copy and A_lo its residual copy (same layout), B_hi / B_lo the rounded thin
+// operand and its rounded residual.
+enum QMath { MATH_F32 = 0, MATH_F64 = 1, MATH_BF16 = 2, MATH_F16 = 3, MATH_BF16X3 = 4, MATH_F16X3 = 5 };
 
 struct QgemmDesc {
     QOp op;
@@ -46,6 +49,7 @@ struct QgemmDesc {
     const float* cscale;       // low-precision math: device scalar the result is multiplied by
     double* fro2_part;         // FP32 A X only (optional): per-wave sums of squares of A, fro2_slots(d) entries
     int b_real;                // FP32 views: B has zero imaginary planes (only its real plane is read)
+    const void* A_lo;          // split forms: the residual copy of A
 };
 
 // Device workspace carved into aligned regions.
@@ -78,8 +82,10 @@ hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t s
 // bf16 or fp16 by prec (QLRA_BF16 / QLRA_FP16), in the tiled MFMA-operand layout (16 x 64 tiles,
 // four planes per tile; lowp_copy_elems(rows, k) elements each, padding zero).
 size_t lowp_copy_elems(int64_t rows, int64_t k);
+// Ar, Ar_t (both or neither): the residual copies (s a - (float)(rounded s a), rounded), written in
+// the same pass; Alo = Alo_t = null with Ar given: the residual copies alone.
 hipError_t lowp_copy_launch(const float* A, int64_t m, int64_t n, int64_t lda, int64_t aps, int prec, void* Alo,
-                            void* Alo_t, const float* scale, hipStream_t st);
+                            void* Alo_t, const float* scale, hipStream_t st, void* Ar = nullptr, void* Ar_t = nullptr);
 // FP16 scale from ||A||_F^2 (nA2): scale = 2^e with e = 14 - ceil(log2 ||A||_F) (so that every
 // |a| * scale <= 2^14), inv = 1 / scale; BF16: scale = inv = 1.
 hipError_t lowp_scale_launch(const double* nA2, int prec, float* scale, float* inv, hipStream_t st);

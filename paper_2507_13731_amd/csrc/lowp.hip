@@ -1,6 +1,7 @@
 // Low-precision copies of A for the reduced-precision views (the precision form of the
 // method: the intermediate views run in BF16 / FP16 with FP32 accumulation, the last two views
-// and all Gram, Cholesky and QSVD steps keep their precision).
+// and all Gram, Cholesky and QSVD steps keep their precision).  For the split form the residual
+// copies (s a - (s a rounded), rounded) are written in the same pass, in the same layout.
 //
 // Both orientations are written once per solve, Alo from A (rows m, reduction n) and Alo_t from
 // A^T (rows n, reduction m), in the order the view kernel's MFMA A operand is consumed: tiles
@@ -27,43 +28,56 @@ __device__ __forceinline__ int64_t tiled_index(int64_t row, int64_t k, int p, in
     return ((rt * KT + kt) * 4 + p) * 1024 + (kk >> 5) * 512 + ((kk >> 3) & 3) * 128 + r * 8 + (kk & 7);
 }
 
-// one 64 x 64 tile of A (rows r0.., columns c0..), all four planes; the grid covers the
-// padded extents (multiples of 64) so that padding is written as zeros
-template <class TL>
+// one 64 x 64 tile of A (rows r0.., columns c0..), one plane at a time through a 16.6 KB LDS
+// tile; the grid covers the padded extents (multiples of 64) so that padding is written as zeros.
+// MODE 0: the copies Alo / Alo_t; 1: also the residual copies (x - (float)(TL)x, rounded) into
+// Ar / Ar_t in the same pass; 2: the residual copies alone (into Ar / Ar_t).
+template <class TL, int MODE>
 __global__ __launch_bounds__(256) void k_lowp_copy(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda,
                                                    int64_t aps, TL* __restrict__ Alo, TL* __restrict__ Alo_t,
+                                                   TL* __restrict__ Ar, TL* __restrict__ Ar_t,
                                                    const float* __restrict__ scale) {
-    __shared__ float tile[4][kT][kT + 1];
+    __shared__ float tile[kT][kT + 1];
     const int64_t r0 = (int64_t)blockIdx.y * kT, c0 = (int64_t)blockIdx.x * kT;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;   // 64 x 4
     const float s = scale ? *scale : 1.0f;
     const int64_t KTn = (n + 63) / 64, KTm = (m + 63) / 64;      // reduction tiles of Alo, Alo_t
-    for (int p = 0; p < 4; p++)
-        for (int i = ty; i < kT; i += 4) {
-            const int64_t r = r0 + i, c = c0 + tx;
-            tile[p][i][tx] = (r < m && c < n) ? A[p * aps + r * lda + c] * s : 0.0f;
-        }
-    __syncthreads();
-    // Alo: row tiles r0/16 .. +3, reduction tile c0/64; each (row tile, plane) block of 1024
-    // elements is contiguous: thread tid writes offsets tid, tid + 256, ...
     const int rtiles_m = (int)(((m + 15) >> 4) - (r0 >> 4)) < 4 ? (int)(((m + 15) >> 4) - (r0 >> 4)) : 4;
-    for (int b = 0; b < 4 * rtiles_m; b++) {
-        const int rq = b >> 2, p = b & 3;                          // row tile within the 64, plane
-        for (int o = tid; o < 1024; o += 256) {
-            const int h = o >> 9, kq = (o >> 7) & 3, r = (o >> 3) & 15, t = o & 7;
-            const int il = rq * 16 + r, kl = h * 32 + kq * 8 + t;
-            Alo[tiled_index(r0 + il, c0 + kl, p, KTn)] = (TL)tile[p][il][kl];
-        }
-    }
-    // Alo_t: rows = columns of A (c0 ..), reduction = rows of A (r0 ..)
     const int rtiles_n = (int)(((n + 15) >> 4) - (c0 >> 4)) < 4 ? (int)(((n + 15) >> 4) - (c0 >> 4)) : 4;
-    for (int b = 0; b < 4 * rtiles_n; b++) {
-        const int rq = b >> 2, p = b & 3;
-        for (int o = tid; o < 1024; o += 256) {
-            const int h = o >> 9, kq = (o >> 7) & 3, r = (o >> 3) & 15, t = o & 7;
-            const int il = rq * 16 + r, kl = h * 32 + kq * 8 + t;   // il: column of A, kl: row of A
-            Alo_t[tiled_index(c0 + il, r0 + kl, p, KTm)] = (TL)tile[p][kl][il];
+    for (int p = 0; p < 4; p++) {
+        if (p) __syncthreads();                                  // the previous plane is written out
+        float v[kT / 4];
+#pragma unroll
+        for (int u = 0; u < kT / 4; u++) {
+            const int64_t r = r0 + ty + 4 * u, c = c0 + tx;
+            v[u] = (r < m && c < n) ? A[p * aps + r * lda + c] * s : 0.0f;
         }
+#pragma unroll
+        for (int u = 0; u < kT / 4; u++) tile[ty + 4 * u][tx] = v[u];
+        __syncthreads();
+        // Alo: row tiles r0/16 .. +3, reduction tile c0/64; each (row tile, plane) block of 1024
+        // elements is contiguous: thread tid writes offsets tid, tid + 256, ...
+        for (int rq = 0; rq < rtiles_m; rq++)
+            for (int o = tid; o < 1024; o += 256) {
+                const int h = o >> 9, kq = (o >> 7) & 3, r = (o >> 3) & 15, t = o & 7;
+                const int il = rq * 16 + r, kl = h * 32 + kq * 8 + t;
+                const float x = tile[il][kl];
+                const TL hi = (TL)x;
+                const int64_t at = tiled_index(r0 + il, c0 + kl, p, KTn);
+                if constexpr (MODE != 2) Alo[at] = hi;
+                if constexpr (MODE != 0) Ar[at] = (TL)(x - (float)hi);
+            }
+        // Alo_t: rows = columns of A (c0 ..), reduction = rows of A (r0 ..)
+        for (int rq = 0; rq < rtiles_n; rq++)
+            for (int o = tid; o < 1024; o += 256) {
+                const int h = o >> 9, kq = (o >> 7) & 3, r = (o >> 3) & 15, t = o & 7;
+                const int il = rq * 16 + r, kl = h * 32 + kq * 8 + t;   // il: column of A, kl: row of A
+                const float x = tile[kl][il];
+                const TL hi = (TL)x;
+                const int64_t at = tiled_index(c0 + il, r0 + kl, p, KTm);
+                if constexpr (MODE != 2) Alo_t[at] = hi;
+                if constexpr (MODE != 0) Ar_t[at] = (TL)(x - (float)hi);
+            }
     }
 }
 
@@ -87,24 +101,35 @@ __global__ void k_lowp_scale(const double* __restrict__ nA2, int fp16, float* __
 }  // namespace
 
 hipError_t lowp_copy_launch(const float* A, int64_t m, int64_t n, int64_t lda, int64_t aps, int prec, void* Alo,
-                            void* Alo_t, const float* scale, hipStream_t st) {
+                            void* Alo_t, const float* scale, hipStream_t st, void* Ar, void* Ar_t) {
     if (m <= 0 || n <= 0) return hipSuccess;
-    dim3 grid((unsigned)((n + kT - 1) / kT), (unsigned)((m + kT - 1) / kT), 1);
-    if (prec == QLRA_BF16)
-        hipLaunchKernelGGL(k_lowp_copy<__bf16>, grid, dim3(256), 0, st, A, m, n, lda, aps, (__bf16*)Alo,
-                           (__bf16*)Alo_t, scale);
-    else if (prec == QLRA_FP16)
-        hipLaunchKernelGGL(k_lowp_copy<_Float16>, grid, dim3(256), 0, st, A, m, n, lda, aps, (_Float16*)Alo,
-                           (_Float16*)Alo_t, scale);
-    else
+    if ((Ar == nullptr) != (Ar_t == nullptr) || (Alo == nullptr) != (Alo_t == nullptr) || (!Alo && !Ar))
         return hipErrorInvalidValue;
+    dim3 grid((unsigned)((n + kT - 1) / kT), (unsigned)((m + kT - 1) / kT), 1);
+    const int mode = !Ar ? 0 : (Alo ? 1 : 2);
+#define QL_COPY(TL_, M_) \
+    hipLaunchKernelGGL((k_lowp_copy<TL_, M_>), grid, dim3(256), 0, st, A, m, n, lda, aps, (TL_*)Alo, (TL_*)Alo_t, \
+                       (TL_*)Ar, (TL_*)Ar_t, scale)
+    if (prec == QLRA_BF16 || prec == QLRA_BF16_SPLIT) {
+        if (mode == 0) QL_COPY(__bf16, 0);
+        else if (mode == 1) QL_COPY(__bf16, 1);
+        else QL_COPY(__bf16, 2);
+    } else if (prec == QLRA_FP16 || prec == QLRA_FP16_SPLIT) {
+        if (mode == 0) QL_COPY(_Float16, 0);
+        else if (mode == 1) QL_COPY(_Float16, 1);
+        else QL_COPY(_Float16, 2);
+    } else {
+        return hipErrorInvalidValue;
+    }
+#undef QL_COPY
     return hipGetLastError();
 }
 
 size_t lowp_copy_elems(int64_t rows, int64_t k) { return (size_t)((rows + 15) / 16) * ((k + 63) / 64) * 4 * 1024; }
 
 hipError_t lowp_scale_launch(const double* nA2, int prec, float* scale, float* inv, hipStream_t st) {
-    hipLaunchKernelGGL(k_lowp_scale, dim3(1), dim3(64), 0, st, nA2, prec == QLRA_FP16 ? 1 : 0, scale, inv);
+    hipLaunchKernelGGL(k_lowp_scale, dim3(1), dim3(64), 0, st, nA2, (prec == QLRA_FP16 || prec == QLRA_FP16_SPLIT) ? 1 : 0,
+                       scale, inv);
     return hipGetLastError();
 }
 

@@ -19,7 +19,8 @@
 //    loads of step t+1 are in flight during the MFMAs of step t.  The MFMA A operand always
 //    comes from the A tile, stored row-major for A B and k-major for A^H B, so one kernel serves
 //    both orientations.  Signs go on a negated register copy of the thin operand.
-//  - k_qgemm_lp (MATH_BF16 / MATH_F16): the reduced-precision views.
+//  - k_qgemm_lp (MATH_BF16 / MATH_F16): the reduced-precision views, and three launches of it
+//    for the split forms (MATH_BF16X3 / MATH_F16X3).
 // When the output tiles cannot fill the chip, K is split across workgroups; partial tiles go to
 // scratch and an element-parallel kernel adds them in split order (deterministic, no
 // floating-point atomics).
@@ -849,6 +850,17 @@ __global__ __launch_bounds__(256) void k_lp_thin(const float* __restrict__ B, in
     Bt[e] = (TL)x;
 }
 
+// Bt[p][c][k] = (TL)(B[p][k][c] - (float)(TL)B[p][k][c]): the rounded residual of the thin operand
+template <class TL>
+__global__ __launch_bounds__(256) void k_lp_thin_res(const float* __restrict__ B, int64_t ldb, int64_t bps, int64_t K,
+                                                     int64_t N, TL* __restrict__ Bt, int64_t Np, int64_t Kp) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 4 * Np * Kp) return;
+    const int64_t p = e / (Np * Kp), rem = e - p * Np * Kp, c = rem / Kp, k = rem - c * Kp;
+    const float x = (k < K && c < N) ? B[p * bps + k * ldb + c] : 0.0f;
+    Bt[e] = (TL)(x - (float)(TL)x);
+}
+
 // Workgroup: 4 row groups of 16 rows x NCG column groups of CNW column tiles (16 columns each).
 // Software pipeline: an iteration covers two K steps (LKS = 128 reduction elements).  Its thin
 // tile was loaded into registers during the previous iteration and sits in LDS; the A fragments
@@ -1053,6 +1065,54 @@ hipError_t launch_lp(const QgemmDesc& d, const LpPlan& pl, void* scratch, hipStr
                       d.skip_flag, st);
 }
 
+// The split form: three launches of the reduced-precision kernel, (A, B_hi), (A, B_lo) and
+// (A_lo, B_hi), each into its own slice of split-K partial tiles (the kernel stores partial
+// tiles whenever its split count is above one), then one ordered sum of all 3 x splits tiles.
+// Scratch: B_hi, B_lo, then the partial tiles.
+size_t lp3_scratch_bytes(const LpPlan& p) {
+    return 2 * ((lp_thin_bytes(p) + 255) & ~size_t(255)) + (size_t)3 * p.splits * 4 * p.Mp * p.Np * sizeof(float);
+}
+
+template <class TL, bool ADJ>
+hipError_t launch_lp3(const QgemmDesc& d, const LpPlan& pl, void* scratch, hipStream_t st) {
+    char* base = (char*)scratch;
+    const size_t tb = (lp_thin_bytes(pl) + 255) & ~size_t(255);
+    TL* Bhi = (TL*)base;
+    TL* Blo = (TL*)(base + tb);
+    float* part = (float*)(base + 2 * tb);
+    const int64_t nt = 4 * pl.Np * pl.Kp;
+    const unsigned tg = (unsigned)((nt + 255) / 256);
+    hipLaunchKernelGGL(k_lp_thin<TL>, dim3(tg), dim3(256), 0, st, (const float*)d.B, d.ldb, d.bps, d.K, d.N, Bhi, pl.Np,
+                       pl.Kp);
+    hipLaunchKernelGGL(k_lp_thin_res<TL>, dim3(tg), dim3(256), 0, st, (const float*)d.B, d.ldb, d.bps, d.K, d.N, Blo,
+                       pl.Np, pl.Kp);
+    const size_t slice = (size_t)pl.splits * 4 * pl.Mp * pl.Np;
+    const void* As[3] = {d.A, d.A, d.A_lo};
+    const TL* Bs[3] = {Bhi, Blo, Bhi};
+    dim3 grid((unsigned)pl.gx, (unsigned)pl.gy, (unsigned)pl.splits);
+    for (int t = 0; t < 3; t++) {
+        LpParams P{};
+        P.A = As[t]; P.akt = (d.K + LBK - 1) / LBK; P.art = (d.M + 15) / 16;
+        P.Bt = Bs[t]; P.bkp = pl.Kp;
+        P.C = (float*)d.C; P.ldc = d.ldc; P.cps = d.cps;
+        P.M = d.M; P.N = d.N; P.K = d.K;
+        P.kchunk = pl.kchunk; P.splits = 3 * (int)pl.splits;   // above one: always partial tiles
+        P.part = part + t * slice; P.Mp = pl.Mp; P.Np = pl.Np;
+        P.skip = d.skip_flag;
+        P.cscale = d.cscale;
+#define QL_LP3(CN_) \
+        if (pl.CN == CN_) \
+            hipLaunchKernelGGL((k_qgemm_lp<TL, ADJ, CN_, lp_ncg(CN_), lp_cnw(CN_)>), grid, dim3(256 * lp_ncg(CN_)), 0, st, P); \
+        else
+        QL_LP3(1) QL_LP3(2) QL_LP3(3) QL_LP3(4) QL_LP3(5) QL_LP3(6) return hipErrorInvalidValue;
+#undef QL_LP3
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return reduce_f32(part, 3 * (int)pl.splits, pl.Mp, pl.Np, (float*)d.C, d.ldc, d.cps, d.M, d.N, (int)ST_SET,
+                      d.skip_flag, st);
+}
+
 bool vec_ok(const void* p, int64_t ld, int64_t ps, size_t el) {
     return ((uintptr_t)p % 16) == 0 && ld % 4 == 0 && ps % 4 == 0 && (el == 4 || el == 8);
 }
@@ -1060,6 +1120,7 @@ bool vec_ok(const void* p, int64_t ld, int64_t ps, size_t el) {
 }  // namespace
 
 size_t qgemm_partial_bytes(const QgemmDesc& d) {
+    if (d.math == MATH_BF16X3 || d.math == MATH_F16X3) return lp3_scratch_bytes(make_lp_plan(d));
     if (d.math == MATH_BF16 || d.math == MATH_F16) {
         const LpPlan lp = make_lp_plan(d);
         return ((lp_thin_bytes(lp) + 255) & ~size_t(255)) + lp_part_bytes(lp);
@@ -1080,6 +1141,13 @@ size_t fro2_slots(const QgemmDesc& d) { return d.math == MATH_F32 ? vplan_slots(
 
 hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t st) {
     if (d.M <= 0 || d.N <= 0) return hipSuccess;
+    if (d.math == MATH_BF16X3 || d.math == MATH_F16X3) {
+        if (d.b_f64 || d.c_f64 || d.store != ST_SET || !s.partial || !d.A_lo) return hipErrorInvalidValue;
+        const LpPlan lp = make_lp_plan(d);
+        if (d.math == MATH_BF16X3)
+            return d.op == OP_HN ? launch_lp3<__bf16, true>(d, lp, s.partial, st) : launch_lp3<__bf16, false>(d, lp, s.partial, st);
+        return d.op == OP_HN ? launch_lp3<_Float16, true>(d, lp, s.partial, st) : launch_lp3<_Float16, false>(d, lp, s.partial, st);
+    }
     if (d.math == MATH_BF16 || d.math == MATH_F16) {
         if (d.b_f64 || d.c_f64 || d.store != ST_SET || !s.partial) return hipErrorInvalidValue;
         const LpPlan lp = make_lp_plan(d);

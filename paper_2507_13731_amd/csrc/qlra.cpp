@@ -230,6 +230,10 @@ void orth_stack(Ctx& c, float* K, int64_t rows, int64_t W, int64_t l, double* Cb
 // ---------------------------------------------------------------------------------------
 // solve layout
 
+bool prec_split(int prec) { return prec == QLRA_BF16_SPLIT || prec == QLRA_FP16_SPLIT; }
+bool prec_bf(int prec) { return prec == QLRA_BF16 || prec == QLRA_BF16_SPLIT; }
+enum { VIEW_F32 = 0, VIEW_LOWP = 1, VIEW_SPLIT = 2 };
+
 struct Problem {
     // m, n, U, V: the matrix the scheme runs on (A, or A^H when transpose is set) and its factors;
     // A, mr, nr, lda, aps: A as stored
@@ -246,6 +250,14 @@ struct Problem {
     int prec;               // QLRA_FP32, QLRA_BF16 or QLRA_FP16 for views 1 .. v-2
     int sketch;             // QLRA_SKETCH_QUATERNION or QLRA_SKETCH_REAL
 };
+
+// Arithmetic of view i (1-based): the reduced-precision forms take views 1 .. v-2 from the
+// low-precision copies and views v-1 and v in FP32, or in the split form.
+int view_mode(const Problem& pr, int i) {
+    if (pr.prec == QLRA_FP32) return VIEW_F32;
+    if (pr.v > 2 && i <= pr.v - 2) return VIEW_LOWP;
+    return prec_split(pr.prec) ? VIEW_SPLIT : VIEW_F32;
+}
 
 // Run the scheme on A^H: swap the logical sizes and the two factors (A^H = V S U^H).
 void orient(Problem& pr, int transpose) {
@@ -313,6 +325,7 @@ struct Bufs {
     double* side_lam;       // l eigenvalues (estimates from the large-order solver)
     double* big_work;       // the large-order eigensolver of the final view
     void* Alo; void* Alo_t;  // low-precision copies of A and A^T (views 1 .. v-2)
+    void* Alo_lo; void* Alo_t_lo;  // split forms: their residual copies (views v-1 and v)
     float* lp_scale;        // [scale, 1 / scale]
     void* phase_work;       // partial arg-max of the phase normalisation
     void* partial;
@@ -367,9 +380,12 @@ void carve(const Problem& pr, const Dims& d, Arena& ar, Bufs& b, size_t part_byt
     b.big_work = (wf > heig_max() && wf <= heig_big_max())
                      ? (double*)ar.take(heig_big_work_doubles(wf, big_nvec(wf, pr.k)) * sizeof(double))
                      : nullptr;
-    const bool lowp = pr.prec != QLRA_FP32 && pr.v > 2;
+    const bool split = prec_split(pr.prec);
+    const bool lowp = pr.prec != QLRA_FP32 && (pr.v > 2 || split);
     b.Alo = lowp ? ar.take(lowp_copy_elems(pr.mr, pr.nr) * 2) : nullptr;
     b.Alo_t = lowp ? ar.take(lowp_copy_elems(pr.nr, pr.mr) * 2) : nullptr;
+    b.Alo_lo = split ? ar.take(lowp_copy_elems(pr.mr, pr.nr) * 2) : nullptr;
+    b.Alo_t_lo = split ? ar.take(lowp_copy_elems(pr.nr, pr.mr) * 2) : nullptr;
     b.lp_scale = (float*)ar.take(2 * sizeof(float));
     b.phase_work = ar.take(phase_work_bytes(pr.n, pr.k));
     b.partial = part_bytes ? ar.take(part_bytes) : nullptr;
@@ -568,18 +584,21 @@ void finish_gram(Ctx& c, const Bufs& b, const Problem& pr, const float* Y, int64
 }
 
 // The product of a view alone: T = A X (forward, m x w) or T = A^H X (adjoint, n x w), ld w.
-// lowp: from the BF16 / FP16 copies (A for the forward product, A^T for the adjoint one).
+// mode VIEW_LOWP: from the BF16 / FP16 copies (A for the forward product, A^T for the adjoint
+// one); VIEW_SPLIT: the split form from those copies and their residual copies.
 void view_product(Ctx& c, const Problem& pr, const Bufs& b, bool adjoint, const float* X, int64_t ldx, int64_t w,
-                  float* T, bool lowp = false) {
+                  float* T, int mode = VIEW_F32) {
     c.views++;
     const int64_t rows_out = adjoint ? pr.n : pr.m;
     const int64_t kdim = adjoint ? pr.m : pr.n;
     // the product with A as stored: a view of A^H is the other orientation of A
     const bool adj = adjoint != (pr.transpose != 0);
-    if (lowp) {
-        QgemmDesc d = desc(adj ? OP_HN : OP_NN, pr.prec == QLRA_BF16 ? MATH_BF16 : MATH_F16,
+    if (mode != VIEW_F32) {
+        const bool bf = prec_bf(pr.prec), sp = mode == VIEW_SPLIT;
+        QgemmDesc d = desc(adj ? OP_HN : OP_NN, sp ? (bf ? MATH_BF16X3 : MATH_F16X3) : (bf ? MATH_BF16 : MATH_F16),
                            adj ? b.Alo_t : b.Alo, kdim, pr.m * pr.n, 0, X, ldx, kdim * ldx, 0, T, w, rows_out * w, 0,
                            rows_out, w, kdim);
+        if (sp) d.A_lo = adj ? b.Alo_t_lo : b.Alo_lo;
         d.cscale = b.lp_scale ? b.lp_scale + 1 : nullptr;
         qg(c, d);
         return;
@@ -598,9 +617,9 @@ void view_product(Ctx& c, const Problem& pr, const Bufs& b, bool adjoint, const 
 
 // One view: C = A X (forward) or C = A^H X (adjoint), then its QR.
 void view(Ctx& c, const Problem& pr, const Bufs& b, bool adjoint, const float* X, int64_t ldx, int64_t w, float* T,
-          float* Q, int64_t ldq, double* R, int rounds = 1, double* G0 = nullptr, bool lowp = false) {
+          float* Q, int64_t ldq, double* R, int rounds = 1, double* G0 = nullptr, int mode = VIEW_F32) {
     const int64_t rows_out = adjoint ? pr.n : pr.m;
-    view_product(c, pr, b, adjoint, X, ldx, w, T, lowp);
+    view_product(c, pr, b, adjoint, X, ldx, w, T, mode);
     cholqr(c, T, rows_out, w, w, rows_out * w, Q, ldq, rows_out * ldq, R, rounds, G0);
 }
 
@@ -618,11 +637,12 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
         if (pr.estimate) note(c, nan_launch(pr.pass_err, c.st));
         if (b.Alo) {
             note(c, lowp_scale_launch(b.nA2, pr.prec, b.lp_scale, b.lp_scale + 1, c.st));
-            note(c, lowp_copy_launch(pr.A, pr.mr, pr.nr, pr.lda, pr.aps, pr.prec, b.Alo, b.Alo_t, b.lp_scale, c.st));
+            note(c, lowp_copy_launch(pr.A, pr.mr, pr.nr, pr.lda, pr.aps, pr.prec, b.Alo, b.Alo_t, b.lp_scale, c.st,
+                                     b.Alo_lo, b.Alo_t_lo));
         }
     }
     // views 1 .. v-2 in reduced precision when asked; the last two keep FP32
-    auto lowp_view = [&](int i) { return pr.prec != QLRA_FP32 && pr.v > 2 && i <= pr.v - 2; };
+    auto lowp_view = [&](int i) { return view_mode(pr, i); };
     const float* Q2cur = b.Om;
     if (!d.krylov) {
         // Alg. 2: odd views [Q1, R1] = QR(A Q2), even views [Q2, R2] = QR(A^H Q1)
@@ -632,7 +652,7 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
                 const bool merge = merged_estimates(pr, d) && b.Gs;
                 if (!merge) fork_estimates(c, b, pr, l);
                 const bool odd = i % 2 == 1;
-                view_product(c, pr, b, !odd, odd ? Q2cur : b.Q1, l, l, b.T);
+                view_product(c, pr, b, !odd, odd ? Q2cur : b.Q1, l, l, b.T, view_mode(pr, i));
                 finish_gram(c, b, pr, b.T, odd ? pr.m : pr.n, odd ? Q2cur : b.Q1, l, odd ? pr.n : pr.m, l, odd, merge);
                 return;
             }
@@ -680,20 +700,20 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
         fork_estimates(c, b, pr, l);
         orth_stack(c, b.stack, pr.m, Wk, l, b.Cbuf);
         if (Wk <= heig_big_max()) {
-            view_product(c, pr, b, true, b.stack, Wk, Wk, b.T);
+            view_product(c, pr, b, true, b.stack, Wk, Wk, b.T, view_mode(pr, pr.v));
             finish_gram(c, b, pr, b.T, pr.n, b.stack, Wk, pr.m, Wk, false);
         } else {
-            view(c, pr, b, true, b.stack, Wk, Wk, b.T, b.Q2, Wk, b.Rfin, 2);
+            view(c, pr, b, true, b.stack, Wk, Wk, b.T, b.Q2, Wk, b.Rfin, 2, nullptr, view_mode(pr, pr.v));
             finish(c, b, pr, b.Rfin, Wk, b.stack, Wk, b.Q2, Wk, true);
         }
     } else {
         fork_estimates(c, b, pr, l);
         orth_stack(c, b.stack, pr.n, Wk, l, b.Cbuf);
         if (Wk <= heig_big_max()) {
-            view_product(c, pr, b, false, b.stack, Wk, Wk, b.T);
+            view_product(c, pr, b, false, b.stack, Wk, Wk, b.T, view_mode(pr, pr.v));
             finish_gram(c, b, pr, b.T, pr.m, b.stack, Wk, pr.n, Wk, true);
         } else {
-            view(c, pr, b, false, b.stack, Wk, Wk, b.T, b.Q1, Wk, b.Rfin, 2);
+            view(c, pr, b, false, b.stack, Wk, Wk, b.T, b.Q1, Wk, b.Rfin, 2, nullptr, view_mode(pr, pr.v));
             finish(c, b, pr, b.Rfin, Wk, b.Q1, Wk, b.stack, Wk, false);
         }
     }
@@ -732,7 +752,8 @@ int check_problem(const Problem& pr) {
     const int64_t l = (int64_t)pr.k + pr.p;
     if (l > pr.m || l > pr.n) return QLRA_E_ARG;
     if (pr.v > 64) return QLRA_E_TOO_LARGE;
-    if (pr.prec != QLRA_FP32 && pr.prec != QLRA_BF16 && pr.prec != QLRA_FP16) return QLRA_E_UNSUPPORTED;
+    if (pr.prec != QLRA_FP32 && pr.prec != QLRA_BF16 && pr.prec != QLRA_FP16 && !prec_split(pr.prec))
+        return QLRA_E_UNSUPPORTED;
     if (pr.sketch != QLRA_SKETCH_QUATERNION && pr.sketch != QLRA_SKETCH_REAL) return QLRA_E_UNSUPPORTED;
     return QLRA_OK;
 }
@@ -1274,6 +1295,18 @@ int qlra_lowp_copy(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_
                : QLRA_E_HIP;
 }
 
+int qlra_lowp_copy_residual(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_ps, int precision,
+                            const float* scale, void* Alo_res, void* Alo_t_res, void* stream) {
+    if (m < 0 || n < 0 || (precision != QLRA_BF16 && precision != QLRA_FP16)) return QLRA_E_ARG;
+    if (m * n == 0) return QLRA_OK;
+    int rc;
+    if ((rc = check_layout(A, m, n, lda, a_ps))) return rc;
+    if (!Alo_res || !Alo_t_res) return QLRA_E_ARG;
+    return lowp_copy_launch(A, m, n, lda, a_ps, precision, nullptr, nullptr, scale, (hipStream_t)stream, Alo_res,
+                            Alo_t_res) == hipSuccess
+               ? QLRA_OK
+               : QLRA_E_HIP;
+}
 static QgemmDesc lp_desc(int op, int precision, const void* Alo, int64_t m, int64_t n, const float* B, int64_t w,
                          int64_t ldb, int64_t b_ps, float* C, int64_t ldc, int64_t c_ps, const float* inv_scale) {
     const int64_t rows = op == 0 ? m : n, kdim = op == 0 ? n : m;
@@ -1304,6 +1337,39 @@ int qlra_qgemm_lp(int op, int precision, const void* Alo, int64_t m, int64_t n, 
     if ((rc = check_layout(C, rows, w, ldc, c_ps))) return rc;
     if (workspace_bytes < need || !workspace || ((uintptr_t)workspace & 255)) return QLRA_E_WORKSPACE;
     const QgemmDesc d = lp_desc(op, precision, Alo, m, n, B, w, ldb, b_ps, C, ldc, c_ps, inv_scale);
+    QgemmScratch s{};
+    s.partial = workspace;
+    return qgemm_launch(d, s, (hipStream_t)stream) == hipSuccess ? QLRA_OK : QLRA_E_HIP;
+}
+
+static QgemmDesc split_desc(int op, int precision, const void* Alo, const void* Alo_res, int64_t m, int64_t n,
+                            const float* B, int64_t w, int64_t ldb, int64_t b_ps, float* C, int64_t ldc, int64_t c_ps,
+                            const float* inv_scale) {
+    QgemmDesc d = lp_desc(op, precision, Alo, m, n, B, w, ldb, b_ps, C, ldc, c_ps, inv_scale);
+    d.math = precision == QLRA_BF16 ? MATH_BF16X3 : MATH_F16X3;
+    d.A_lo = Alo_res;
+    return d;
+}
+int qlra_qgemm_split_workspace_size(int op, int precision, int64_t m, int64_t n, int64_t w, size_t* bytes) {
+    if (!bytes || (op != 0 && op != 1) || m < 0 || n < 0 || w < 0) return QLRA_E_ARG;
+    if (precision != QLRA_BF16 && precision != QLRA_FP16) return QLRA_E_ARG;
+    const QgemmDesc d = split_desc(op, precision, nullptr, nullptr, m, n, nullptr, w, w, 0, nullptr, w, 0, nullptr);
+    *bytes = (m * n * w == 0) ? 0 : qgemm_partial_bytes(d);
+    return QLRA_OK;
+}
+int qlra_qgemm_split(int op, int precision, const void* Alo, const void* Alo_res, int64_t m, int64_t n, const float* B,
+                     int64_t w, int64_t ldb, int64_t b_ps, float* C, int64_t ldc, int64_t c_ps, const float* inv_scale,
+                     void* workspace, size_t workspace_bytes, void* stream) {
+    size_t need = 0;
+    int rc = qlra_qgemm_split_workspace_size(op, precision, m, n, w, &need);
+    if (rc) return rc;
+    const int64_t kdim = op == 0 ? n : m, rows = op == 0 ? m : n;
+    if (rows == 0 || w == 0) return QLRA_OK;
+    if (!Alo || !Alo_res) return QLRA_E_ARG;
+    if ((rc = check_layout(B, kdim, w, ldb, b_ps))) return rc;
+    if ((rc = check_layout(C, rows, w, ldc, c_ps))) return rc;
+    if (workspace_bytes < need || !workspace || ((uintptr_t)workspace & 255)) return QLRA_E_WORKSPACE;
+    const QgemmDesc d = split_desc(op, precision, Alo, Alo_res, m, n, B, w, ldb, b_ps, C, ldc, c_ps, inv_scale);
     QgemmScratch s{};
     s.partial = workspace;
     return qgemm_launch(d, s, (hipStream_t)stream) == hipSuccess ? QLRA_OK : QLRA_E_HIP;

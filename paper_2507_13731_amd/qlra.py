@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libqlra.so")
 QLRA_OK, QLRA_E_ARG, QLRA_E_WORKSPACE, QLRA_E_HIP, QLRA_E_NUMERIC, QLRA_E_TOO_LARGE, QLRA_E_UNSUPPORTED = range(7)
 QLRA_SUBSPACE, QLRA_BLOCK_KRYLOV = 0, 1
 QLRA_SKETCH_QUATERNION, QLRA_SKETCH_REAL = 0, 1
-QLRA_FP32, QLRA_BF16, QLRA_FP16 = 0, 1, 2
+QLRA_FP32, QLRA_BF16, QLRA_FP16, QLRA_BF16_SPLIT, QLRA_FP16_SPLIT = 0, 1, 2, 3, 4
 SCHEMES = {"subspace": QLRA_SUBSPACE, "block_krylov": QLRA_BLOCK_KRYLOV, "krylov": QLRA_BLOCK_KRYLOV}
 
 
@@ -87,6 +87,10 @@ _lib.qlra_lowp_copy.argtypes = [_P, _I64, _I64, _I64, _I64, _I, _P, _P, _P, _P]
 _lib.qlra_qgemm_lp_workspace_size.argtypes = [_I, _I, _I64, _I64, _I64, _SZ]
 _lib.qlra_qgemm_lp.argtypes = [_I, _I, _P, _I64, _I64, _P, _I64, _I64, _I64, _P, _I64, _I64, _P, _P,
                                ctypes.c_size_t, _P]
+_lib.qlra_lowp_copy_residual.argtypes = [_P, _I64, _I64, _I64, _I64, _I, _P, _P, _P, _P]
+_lib.qlra_qgemm_split_workspace_size.argtypes = [_I, _I, _I64, _I64, _I64, _SZ]
+_lib.qlra_qgemm_split.argtypes = [_I, _I, _P, _P, _I64, _I64, _P, _I64, _I64, _I64, _P, _I64, _I64, _P, _P,
+                                  ctypes.c_size_t, _P]
 _lib.qlra_cholqr_workspace_size.argtypes = [_I64, _I64, _SZ]
 _lib.qlra_cholqr.argtypes = [_P, _I64, _I64, _I64, _I64, _P, _I64, _I64, _P, _P, ctypes.c_size_t, _P]
 _lib.qlra_qsvd_workspace_size.argtypes = [_I64, _SZ]
@@ -106,13 +110,15 @@ for _name in ("qlra_server_create", "qlra_server_submit", "qlra_server_poll", "q
 for _name in ("qlra_workspace_size", "qlra", "qlra_status", "qlra_complete_workspace_size", "qlra_complete",
               "qlra_omega", "qlra_qgemm_workspace_size",
               "qlra_qgemm", "qlra_lowp_copy_bytes", "qlra_lowp_copy", "qlra_qgemm_lp_workspace_size", "qlra_qgemm_lp",
-              "qlra_cholqr_workspace_size", "qlra_cholqr", "qlra_qsvd_workspace_size", "qlra_qsvd"):
+              "qlra_cholqr_workspace_size", "qlra_cholqr", "qlra_qsvd_workspace_size", "qlra_qsvd",
+              "qlra_lowp_copy_residual", "qlra_qgemm_split_workspace_size", "qlra_qgemm_split"):
     getattr(_lib, _name).restype = _I
 
 EXPORTS = ("qlra", "qlra_workspace_size", "qlra_status", "qlra_strerror", "qlra_complete",
            "qlra_complete_workspace_size", "qlra_omega", "qlra_qgemm",
            "qlra_qgemm_workspace_size", "qlra_lowp_copy_bytes", "qlra_lowp_copy", "qlra_qgemm_lp", "qlra_qgemm_lp_workspace_size",
            "qlra_cholqr", "qlra_cholqr_workspace_size", "qlra_qsvd", "qlra_qsvd_workspace_size",
+           "qlra_lowp_copy_residual", "qlra_qgemm_split", "qlra_qgemm_split_workspace_size",
            "qlra_server_create", "qlra_server_submit", "qlra_server_poll", "qlra_server_drain",
            "qlra_server_stats", "qlra_server_destroy", "qlra_server_clock")
 
@@ -330,6 +336,46 @@ def qlra_qgemm_lp(op, precision, Alo, m, n, B, C=None, inv_scale=None, stream=No
     _check(_lib.qlra_qgemm_lp(op, precision, ctypes.c_void_p(Alo.data_ptr()), m, n, pb, w, ldb, bps, pc, ldc, cps,
                               ctypes.c_void_p(inv_scale.data_ptr()) if inv_scale is not None else None,
                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)), "qlra_qgemm_lp")
+    return C
+
+
+def qlra_lowp_copy_residual(A, precision, scale=None, stream=None):
+    """The residual copies (s a minus its rounded value, rounded) of A (4, m, n) in the layout of
+    qlra_lowp_copy: returns flat tensors (Alo_res, Alo_t_res)."""
+    m, n = A.shape[1], A.shape[2]
+    pa, lda, aps = _planes(A, m, n, "A")
+    dt = _LP_DTYPES[precision]
+    na, nt = qlra_lowp_copy_bytes(m, n)
+    Ar = torch.empty(na // 2, dtype=dt, device=A.device)
+    Ar_t = torch.empty(nt // 2, dtype=dt, device=A.device)
+    _check(_lib.qlra_lowp_copy_residual(pa, m, n, lda, aps, precision,
+                                        ctypes.c_void_p(scale.data_ptr()) if scale is not None else None,
+                                        ctypes.c_void_p(Ar.data_ptr()), ctypes.c_void_p(Ar_t.data_ptr()),
+                                        _stream_ptr(stream)), "qlra_lowp_copy_residual")
+    return Ar, Ar_t
+
+
+def qlra_qgemm_split(op, precision, Alo, Alo_res, m, n, B, C=None, inv_scale=None, stream=None):
+    """Split-form view product (qlra_qgemm_lp's product as Ahi Bhi + Ahi Blo + Alo Bhi) from a
+    copy and its residual copy."""
+    rows, kdim = (m, n) if op == 0 else (n, m)
+    need = qlra_lowp_copy_bytes(m, n)[op] // 2
+    for t, what in ((Alo, "Alo"), (Alo_res, "Alo_res")):
+        if t.dtype != _LP_DTYPES[precision] or t.numel() < need or not t.is_contiguous():
+            raise ValueError(f"{what}: expected a copy made for this op")
+    w = B.shape[2]
+    if C is None:
+        C = torch.empty((4, rows, w), dtype=torch.float32, device=B.device)
+    pb, ldb, bps = _planes(B, kdim, w, "B")
+    pc, ldc, cps = _planes(C, rows, w, "C")
+    size = ctypes.c_size_t()
+    _check(_lib.qlra_qgemm_split_workspace_size(op, precision, m, n, w, ctypes.byref(size)),
+           "qlra_qgemm_split_workspace_size")
+    ws = torch.empty(max(size.value, 1), dtype=torch.uint8, device=B.device)
+    _check(_lib.qlra_qgemm_split(op, precision, ctypes.c_void_p(Alo.data_ptr()), ctypes.c_void_p(Alo_res.data_ptr()),
+                                 m, n, pb, w, ldb, bps, pc, ldc, cps,
+                                 ctypes.c_void_p(inv_scale.data_ptr()) if inv_scale is not None else None,
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)), "qlra_qgemm_split")
     return C
 
 

@@ -158,3 +158,15 @@ def test_solve_full_size_bf16(gq, big):
     if "fp32" in _ERR:
         print(f"  error ratio to FP32 {err / _ERR['fp32']:.8f}", flush=True)
         assert err / _ERR["fp32"] <= 1.05
+
+
+def test_solve_full_size_bf16_split(gq, big):
+    """Views 1 .. 6 BF16, views 7 and 8 (the last 640 wide) in the BF16 split form: the same
+    properties, and an error within 5 % of the FP32 path's."""
+    A, sigma = big
+    U, S, Vm, e, st = solve(gq, A, gq.QLRA_BF16_SPLIT)
+    assert st == gq.QLRA_OK
+    err = properties(A, sigma, U, S, Vm, e)
+    if "fp32" in _ERR:
+        print(f"  error ratio to FP32 {err / _ERR['fp32']:.8f}", flush=True)
+        assert err / _ERR["fp32"] <= 1.05

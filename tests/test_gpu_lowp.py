@@ -221,3 +221,94 @@ def test_lowp_solve_config2_error_ratio(gq, oracle):
     ratio = rel_err(oracle, A, Ug, Sg, Vg) / rel_err(oracle, A, Uo, So, Vo)
     print(f"  error ratio {ratio:.8f}", flush=True)
     assert ratio <= 1.05
+
+
+# ---- the split form: a_hi b_hi + a_hi b_lo + a_lo b_hi ----
+
+def residual(x32, prec, scale=1.0):
+    """The residual the kernel multiplies: s x minus its rounded value (exact in FP32), rounded."""
+    xs = (np.asarray(x32, dtype=np.float32) * np.float32(scale)).astype(np.float32)
+    r = (xs - rounded(xs, prec).astype(np.float32)).astype(np.float32)
+    return rounded(r, prec)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_lowp_residual_copy_bit_exact(gq, prec):
+    import torch
+    m, n = 200, 131
+    print(f"residual copy {prec} {m}x{n}", flush=True)
+    A = (W.random_quat(m + 2 * n, m, n) * 3.0).astype(np.float32)
+    Ar, Ar_t = gq.qlra_lowp_copy_residual(dev(A), PREC[prec])
+    torch.cuda.synchronize()
+    got = Ar.cpu().view(torch.int16).numpy().view(np.uint16)
+    got_t = Ar_t.cpu().view(torch.int16).numpy().view(np.uint16)
+    r = residual(A, prec).astype(np.float32)
+    want = round_bf16_bits(r) if prec == "bf16" else r.astype(np.float16).view(np.uint16)
+    assert np.array_equal(got, tiled(want))
+    assert np.array_equal(got_t, tiled(np.ascontiguousarray(want.transpose(0, 2, 1))))
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("op", [0, 1])
+@pytest.mark.parametrize("m,n,w", [(300, 200, 15), (1000, 777, 80), (700, 500, 100), (64, 2048, 1)])
+def test_qgemm_split_against_oracle(gq, oracle, prec, op, m, n, w):
+    """The three products from the rounded pieces, each the oracle's FP64 product, summed: equal up
+    to FP32 accumulation; and the sum is within the split's dropped terms (a_lo b_lo and the
+    residual roundings, about 3 u_lp^2 per product) of the exact product."""
+    import torch
+    print(f"qgemm_split {prec} op={op} {m}x{n} w={w}", flush=True)
+    A = W.random_quat(3 * m + n + w, m, n).astype(np.float32)
+    kdim = n if op == 0 else m
+    B = W.random_quat(w + 17, kdim, w).astype(np.float32)
+    Alo, Alo_t = gq.qlra_lowp_copy(dev(A), PREC[prec])
+    Ar, Ar_t = gq.qlra_lowp_copy_residual(dev(A), PREC[prec])
+    C = gq.qlra_qgemm_split(op, PREC[prec], Alo if op == 0 else Alo_t, Ar if op == 0 else Ar_t, m, n, dev(B))
+    torch.cuda.synchronize()
+    got = C.cpu().numpy().astype(np.float64)
+    Ah, Al, Bh, Bl = rounded(A, prec), residual(A, prec), rounded(B, prec), residual(B, prec)
+    prod = oracle.qgemm if op == 0 else oracle.qgemm_adj
+    ref = prod(Ah, Bh) + prod(Ah, Bl) + prod(Al, Bh)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    mag = (np.abs(A64).sum(0) if op == 0 else np.abs(A64).sum(0).T) @ np.abs(B64).sum(0)
+    assert np.all(np.abs(got - ref) <= 3 * 8 * U32 * np.sqrt(4 * kdim) * mag[None] + 1e-30)
+    ulp = 2.0 ** -8 if prec == "bf16" else 2.0 ** -11
+    exact = prod(A64, B64)
+    assert np.all(np.abs(got - exact) <= (4 * ulp * ulp + 8 * U32 * np.sqrt(4 * kdim)) * mag[None] + 1e-30)
+
+
+SPLIT = {"bf16": 3, "fp16": 4}
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("scheme,v", [(0, 2), (0, 3), (1, 4), (0, 6)])
+def test_split_solve_config0(gq, oracle, prec, scheme, v):
+    """The split precisions end to end (views v-1 and v in the split form; every view at v = 2):
+    error ratio to the FP64 oracle <= 1.05, and the approximation close to the oracle's."""
+    print(f"split config0 {prec} scheme={scheme} v={v}", flush=True)
+    A, _ = W.config0()
+    A32 = A.astype(np.float32)
+    Ug, Sg, Vg, eg, st = run_gpu(gq, A32, 10, 5, v, scheme, 0, SPLIT[prec])
+    assert st == gq.QLRA_OK
+    Uo, So, Vo, eo = oracle.qlra(A, 10, 5, v, scheme, 0)
+    Ag, Ao = oracle.reconstruct(Ug, Sg, Vg), oracle.reconstruct(Uo, So, Vo)
+    ratio = qref.fro(Ag - A) / qref.fro(Ao - A)
+    diff = qref.fro(Ag - Ao) / qref.fro(A)
+    print(f"  error ratio {ratio:.8f}, ahat diff {diff:.3e}", flush=True)
+    assert ratio <= 1.05
+    assert diff <= 1e-3
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_split_solve_config1(gq, oracle, prec):
+    """The 2048 x 2048 benchmark matrix at v = 4 in the split precision: error ratio <= 1.05."""
+    print(f"split config1 {prec}", flush=True)
+    if "A" not in _C1:
+        _C1["A"] = W.config1()[0]
+    A32 = _C1["A"]
+    Ug, Sg, Vg, eg, st = run_gpu(gq, A32, 50, 10, 4, 0, 1, SPLIT[prec])
+    assert st == gq.QLRA_OK
+    A = A32.astype(np.float64)
+    Uo, So, Vo, eo = oracle.qlra(A, 50, 10, 4, 0, 1)
+    ratio = rel_err(oracle, A, Ug, Sg, Vg) / rel_err(oracle, A, Uo, So, Vo)
+    print(f"  error ratio {ratio:.8f}", flush=True)
+    assert ratio <= 1.05
