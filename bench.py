@@ -374,6 +374,23 @@ def accuracy(Q, torch, A, A_np, precisions):
     return rows
 
 
+def time_split_view_kernels(Q, torch, A, prec, reps):
+    """Average duration of the split-form view product (both orientations), as above."""
+    w = K_RANK + P_OVER
+    g = torch.Generator(device="cuda").manual_seed(0)
+    X = torch.randn((4, N, w), device="cuda", generator=g)
+    Alo, Alo_t = Q.qlra_lowp_copy(A, prec)
+    Ar, Ar_t = Q.qlra_lowp_copy_residual(A, prec)
+    out = {}
+    for op in (0, 1):
+        ws = Q.qlra_qgemm_split_workspace(op, prec, M, N, w)
+        C = torch.empty((4, M if op == 0 else N, w), device="cuda")
+        a, r = (Alo, Ar) if op == 0 else (Alo_t, Ar_t)
+        out[op] = graph_time(torch, lambda: Q.qlra_qgemm_split(op, prec, a, r, M, N, X, C,
+                                                               stream=torch.cuda.current_stream(), workspace=ws), reps)
+    return out
+
+
 def time_lowp_view_kernels(Q, torch, A, prec, reps):
     """Average duration of the reduced-precision view product (both orientations), HIP events on
     its stream around a graph of reps launches.  The copies of A are made once, outside the
@@ -418,7 +435,7 @@ def main():
     if args.counters:
         counters_run(Q, torch, A)
         return
-    precisions = {"fp32": Q.QLRA_FP32, "bf16": Q.QLRA_BF16, "fp16": Q.QLRA_FP16}
+    precisions = {"fp32": Q.QLRA_FP32, "bf16": Q.QLRA_BF16, "fp16": Q.QLRA_FP16, "bf16_split": Q.QLRA_BF16_SPLIT}
     outs = {}
     for name, prec in precisions.items():
         for v in BUDGETS:
@@ -486,16 +503,20 @@ def main():
     sequential_value = passes / (time.perf_counter() - t1)
 
     lowp = {}
-    for name in ("bf16", "fp16"):
+    for name in ("bf16", "fp16", "bf16_split"):
         print(f"timing {args.steps} steps ({name} views 1..v-2)", file=sys.stderr, flush=True)
         dtl = timed_steps(name, args.steps, args.warmup)
-        kt_l = time_lowp_view_kernels(Q, torch, A, precisions[name], args.kernel_reps)
+        split = name.endswith("_split")
+        kt_l = time_lowp_view_kernels(Q, torch, A, precisions["bf16" if split else name], args.kernel_reps)
         t_l = 0.5 * (kt_l[0] + kt_l[1])
         lowp[name] = {"value": round(passes / dtl, 3), "unit": "A-passes/s", "ms_per_step": round(dtl * 1e3 / args.steps, 4),
                       "speedup_vs_fp32": round(dt / dtl, 4), "solve_ms": per_budget(name),
                       "view_kernel_us": {"forward": round(kt_l[0] * 1e6, 2), "adjoint": round(kt_l[1] * 1e6, 2)},
                       "view_hbm_gbs": round(8.0 * M * N / t_l / 1e9, 1),
                       "view_hbm_frac": round(8.0 * M * N / t_l / PEAK_HBM, 4)}
+        if split:
+            ks = time_split_view_kernels(Q, torch, A, Q.QLRA_BF16, args.kernel_reps)
+            lowp[name]["split_view_kernel_us"] = {"forward": round(ks[0] * 1e6, 2), "adjoint": round(ks[1] * 1e6, 2)}
 
     print("timing the view kernels", file=sys.stderr, flush=True)
     kt = time_view_kernels(Q, torch, A, args.kernel_reps)
@@ -542,7 +563,8 @@ def main():
             "sequential_value": round(sequential_value, 3),
             "qgemm_tflops": round(achieved / 1e12, 3), "solve_ms": per_v, "accuracy": acc,
             "roofline": roofline, "cpu_baseline": cpu,
-            "precision_form": {"views": "1..v-2 reduced (FP32 accumulation), v-1 and v FP32; Gram/Cholesky/QSVD FP64",
+            "precision_form": {"views": "1..v-2 reduced (FP32 accumulation), v-1 and v FP32 (split: v-1 and v as three "
+                                        "BF16 products of values and residuals); Gram/Cholesky/QSVD FP64",
                                **lowp},
             "serving": serve, "completion": comp, "large": big}
     print(json.dumps(line))

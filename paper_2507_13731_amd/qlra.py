@@ -355,7 +355,14 @@ def qlra_lowp_copy_residual(A, precision, scale=None, stream=None):
     return Ar, Ar_t
 
 
-def qlra_qgemm_split(op, precision, Alo, Alo_res, m, n, B, C=None, inv_scale=None, stream=None):
+def qlra_qgemm_split_workspace(op, precision, m, n, w, device="cuda"):
+    size = ctypes.c_size_t()
+    _check(_lib.qlra_qgemm_split_workspace_size(op, precision, m, n, w, ctypes.byref(size)),
+           "qlra_qgemm_split_workspace_size")
+    return torch.empty(max(size.value, 1), dtype=torch.uint8, device=device)
+
+
+def qlra_qgemm_split(op, precision, Alo, Alo_res, m, n, B, C=None, inv_scale=None, stream=None, workspace=None):
     """Split-form view product (qlra_qgemm_lp's product as Ahi Bhi + Ahi Blo + Alo Bhi) from a
     copy and its residual copy."""
     rows, kdim = (m, n) if op == 0 else (n, m)
@@ -368,10 +375,7 @@ def qlra_qgemm_split(op, precision, Alo, Alo_res, m, n, B, C=None, inv_scale=Non
         C = torch.empty((4, rows, w), dtype=torch.float32, device=B.device)
     pb, ldb, bps = _planes(B, kdim, w, "B")
     pc, ldc, cps = _planes(C, rows, w, "C")
-    size = ctypes.c_size_t()
-    _check(_lib.qlra_qgemm_split_workspace_size(op, precision, m, n, w, ctypes.byref(size)),
-           "qlra_qgemm_split_workspace_size")
-    ws = torch.empty(max(size.value, 1), dtype=torch.uint8, device=B.device)
+    ws = workspace if workspace is not None else qlra_qgemm_split_workspace(op, precision, m, n, w, B.device)
     _check(_lib.qlra_qgemm_split(op, precision, ctypes.c_void_p(Alo.data_ptr()), ctypes.c_void_p(Alo_res.data_ptr()),
                                  m, n, pb, w, ldb, bps, pc, ldc, cps,
                                  ctypes.c_void_p(inv_scale.data_ptr()) if inv_scale is not None else None,

@@ -32,7 +32,7 @@ def mix(count, seed=0):
         p = k // 4
         v = int(rng.integers(2, 7))
         scheme = i % 2
-        prec = [0, 1, 2][i % 3]
+        prec = [0, 1, 2, 3, 4][i % 5]          # FP32, BF16, FP16 and the two split forms
         sigma = np.arange(1, min(m, n) + 1, dtype=np.float64) ** -1.0
         A = W.spectrum_matrix(100 + i, m, n, sigma, nrefl=4)
         if i % 4 == 3:
