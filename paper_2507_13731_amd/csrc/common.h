@@ -115,6 +115,8 @@ hipError_t copy_f64_planes_launch(const double* src, int64_t lds, int64_t sps, d
 hipError_t zero_f64_launch(double* p, int64_t count, const int* gate, hipStream_t st);
 // *dst = (*src != 0).
 hipError_t flag_nonzero_launch(int* dst, const int* src, hipStream_t st);
+// *gate = 1 when max |G - I| (G: w x w FP64 planes) exceeds tol or is not finite, else 0.
+hipError_t orth_gate_launch(const double* G, int64_t w, double tol, int* gate, hipStream_t st);
 // Cholesky alone for w <= chol_reg_max(), factor to R (no inverse); same status, shift and gate
 // behaviour as chol_launch.
 int chol_reg_max();

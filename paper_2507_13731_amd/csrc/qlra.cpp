@@ -175,20 +175,29 @@ void cholqr(Ctx& c, const float* Y, int64_t rows, int64_t w, int64_t ldy, int64_
     const float* src = Y;
     int64_t lds = ldy, sps = yps;
     const bool small = w <= chol_reg_max();
+    // Without a wanted R, the second round of the small path runs only where the first left the
+    // basis measurably non-orthonormal: its Gram Q^H Q is formed anyway, and when max |Q^H Q - I|
+    // <= 1e-7 (a second round would move Q by less than its FP32 rounding) the Cholesky and the
+    // triangular solve of that round are skipped on the device.  The first round then writes Q
+    // directly and the second works in place.
+    const bool gated = small && rounds == 2 && !R && c.status;
+    int* gate = gated ? c.status + 3 : nullptr;
     const double* Rprev = nullptr;
     for (int round = 0; round < rounds; round++) {
         const bool last = round == rounds - 1;
-        float* dst = last ? Q : c.T2;
-        const int64_t ldd = last ? ldq : w, dps = last ? qps : tps;
+        float* dst = (last || gated) ? Q : c.T2;
+        const int64_t ldd = (last || gated) ? ldq : w, dps = (last || gated) ? qps : tps;
         double* G = (round == 0 && G0) ? G0 : c.G;
         qg(c, desc(OP_HN, MATH_F64, src, lds, sps, 0, src, lds, sps, 0, G, w, w * w, 1, w, w, rows));
         if (small) {
             // this round's own factor; the product R2 R1 is formed at the end when R is wanted
             double* Rr = (rounds == 1 && R) ? R : (round == 0 ? c.R1 : c.R2);
+            const int* g = (gated && round == 1) ? gate : nullptr;
             if (c.live()) {
-                note(c, chol_reg_launch(G, w, Rr, c.status, round == 0 ? shifted : nullptr, nullptr, round == 0 ? 1 : 0,
+                if (g) note(c, orth_gate_launch(G, w, 1e-7, gate, c.st));
+                note(c, chol_reg_launch(G, w, Rr, c.status, round == 0 ? shifted : nullptr, g, round == 0 ? 1 : 0,
                                         shift_scale(rows, w), c.st));
-                note(c, trsm_launch(src, lds, sps, dst, ldd, dps, Rr, w, rows, nullptr, c.st));
+                note(c, trsm_launch(src, lds, sps, dst, ldd, dps, Rr, w, rows, g, c.st));
             }
         } else {
             double* Rout = last ? (R ? R : c.Rjunk) : c.R1;
