@@ -109,6 +109,67 @@ def omega(seed, n, l):
     return out
 
 
+# ------------------------------------------------------------------------------------------
+# Structured sketch (the SRFT-like generator the paper's cost section mentions as a faster
+# alternative, footnote of Sec. 6; its bounds are not those of Lemma 1): a subsampled
+# randomized Hadamard transform Omega = D H S / sqrt(l), real, with
+#   n_pad = the smallest power of two >= n, H the +-1 Hadamard matrix of order n_pad
+#   (H[i, s] = (-1)^popcount(i & s)), rows i < n kept;
+#   D = diag(d_i), d_i = -1 when bit 0 of word 0 of Philox4x32-10 at counter (i, 0, 2, 0)
+#   (key (seed mod 2^32, seed div 2^32)) is set, else +1;
+#   S = the columns s_j = pi(j), j < l, of a keyed permutation pi of [0, n_pad): a four-round
+#   Feistel network on the bits of x (split into halves of h = ceil(log2 n_pad / 2) bits; round
+#   r maps (L, R) to (R, L xor F), F = word 0 of Philox at counter (R, r, 3, 0) masked to h
+#   bits), applied again while the result is >= n_pad (cycle walking).
+# The scale is the FP32 rounding of 1 / sqrt(l).
+
+def _key(seed):
+    return np.array([seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF], dtype=np.uint32)
+
+
+def srht_signs(seed, n):
+    k = _key(seed)
+    return np.array([-1.0 if philox4x32_10([i, 0, 2, 0], k)[0] & 1 else 1.0 for i in range(n)])
+
+
+def srht_pad(n):
+    p = 1
+    while p < n:
+        p *= 2
+    return p
+
+
+def srht_perm(seed, x, n_pad):
+    bits = n_pad.bit_length() - 1
+    h = (bits + 1) // 2
+    mask = (1 << h) - 1
+    k = _key(seed)
+
+    def rounds(v):
+        L, R = v >> h, v & mask
+        for r in range(4):
+            F = int(philox4x32_10([R, r, 3, 0], k)[0]) & mask
+            L, R = R, L ^ F
+        return (L << h) | R
+
+    y = rounds(x)
+    while y >= n_pad:
+        y = rounds(y)
+    return y
+
+
+def omega_srht(seed, n, l):
+    """The structured sketch as FP32 planes (4, n, l): real plane D H S / sqrt(l), others zero."""
+    n_pad = srht_pad(n)
+    d = srht_signs(seed, n)
+    cols = np.array([srht_perm(seed, j, n_pad) for j in range(l)], dtype=np.int64)
+    i = np.arange(n, dtype=np.int64)[:, None]
+    par = np.vectorize(lambda v: bin(int(v)).count("1") & 1)(i & cols[None, :])
+    out = np.zeros((4, n, l), dtype=np.float32)
+    out[0] = (d[:, None] * np.where(par == 1, -1.0, 1.0)).astype(np.float32) * np.float32(1.0 / np.sqrt(l))
+    return out
+
+
 def qgemm(A, B):
     A = _planes(A)
     B = _planes(B)
