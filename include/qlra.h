@@ -70,8 +70,11 @@ enum { QLRA_FP32 = 0, QLRA_BF16 = 1, QLRA_FP16 = 2, QLRA_BF16_SPLIT = 3, QLRA_FP
  * Sec. 2 (four independent N(0, 1) planes; see qlra_omega()).  QLRA_SKETCH_REAL:
  * a real Gaussian test matrix, as the experiments of Sec. 8 use; it is the real
  * plane of the quaternion sketch with the other three planes zero, and its
- * first view costs a quarter of the matrix products. */
-enum { QLRA_SKETCH_QUATERNION = 0, QLRA_SKETCH_REAL = 1 };
+ * first view costs a quarter of the matrix products.  QLRA_SKETCH_SRHT: a
+ * structured real sketch, the subsampled randomized Hadamard transform of
+ * qlra_omega_srht(), one of the faster generators the cost section (Sec. 6)
+ * mentions; the error bounds of Lemma 1 and Thm. 3 do not cover it. */
+enum { QLRA_SKETCH_QUATERNION = 0, QLRA_SKETCH_REAL = 1, QLRA_SKETCH_SRHT = 2 };
 
 typedef struct {
     int pass_precision;      /* QLRA_FP32, QLRA_BF16 or QLRA_FP16 (see above)         */
@@ -242,6 +245,20 @@ const char* qlra_strerror(int status);
  * series-based log/sin/cos and Newton square roots, rounded to FP32. */
 int qlra_omega(uint64_t seed, int64_t n, int64_t l, float* Om, int64_t ld, int64_t plane_stride,
                void* stream);
+
+/* The structured sketch: Om (n x l, l <= n <= 2^30) = D H S / sqrt(l) in the
+ * real plane, the other three planes zero.  n_pad = the smallest power of two
+ * >= n; H the +-1 Hadamard matrix of order n_pad, entry (i, s) =
+ * (-1)^popcount(i & s), rows i < n; D = diag(d_i) with d_i = -1 when bit 0 of
+ * word 0 of Philox4x32-10 at counter (i, 0, 2, 0) (key as for qlra_omega) is
+ * set, else +1; S picks the columns s_j = pi(j), j < l, where pi is a keyed
+ * permutation of [0, n_pad): with h = ceil(log2(n_pad) / 2), x = (L, R) in
+ * h-bit halves goes through four Feistel rounds (round r: (L, R) ->
+ * (R, L xor F), F = word 0 of Philox at counter (R, r, 3, 0) masked to h
+ * bits), repeated while the result is >= n_pad.  The scale is the FP32
+ * rounding of 1 / sqrt(l). */
+int qlra_omega_srht(uint64_t seed, int64_t n, int64_t l, float* Om, int64_t ld, int64_t plane_stride,
+                    void* stream);
 
 /* Quaternion product of one view (Sec. 2, eq. (1)):
  *   op = 0:  C (m x w) = A (m x n) * B (n x w)

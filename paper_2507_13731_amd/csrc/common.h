@@ -92,6 +92,8 @@ hipError_t lowp_scale_launch(const double* nA2, int prec, float* scale, float* i
 
 hipError_t omega_launch(uint64_t seed, int64_t n, int64_t l, float* Om, int64_t ld, int64_t ps,
                         hipStream_t st, int real_only = 0);
+// The structured sketch (subsampled randomized Hadamard transform, real plane; l <= n).
+hipError_t omega_srht_launch(uint64_t seed, int64_t n, int64_t l, float* Om, int64_t ld, int64_t ps, hipStream_t st);
 
 // Cholesky of a Hermitian quaternion Gram G (w x w FP64 planes, ld = w): G (+ shift I) = R^H R,
 // Rout = R * Rprev (Rprev null: Rout = R) and Rinv = R^{-1} (if non-null).  If the unshifted

@@ -7,6 +7,8 @@
 // sequence of IEEE operations (explicit fma, contraction off), so that any correct
 // implementation of the same definition on any IEEE machine produces the same FP32 values.
 // One thread per entry; the work is ALU-bound and tiny next to a pass over A.
+#include <cmath>
+
 #include "common.h"
 
 namespace qlra_impl {
@@ -158,7 +160,63 @@ __global__ __launch_bounds__(256) void k_omega(uint32_t k0, uint32_t k1, int64_t
     o[3 * ps] = real_only ? 0.0f : z[3];
 }
 
+// The structured sketch: a subsampled randomized Hadamard transform D H S / sqrt(l) (real plane;
+// the others zero).  d_i = -1 when bit 0 of word 0 of Philox at counter (i, 0, 2, 0) is set, else
+// +1; column j samples column s_j = pi(j) of the +-1 Hadamard matrix of order n_pad (entry
+// (-1)^popcount(i & s_j)), pi a keyed four-round Feistel permutation on 2h bits (round r maps
+// (L, R) to (R, L xor F), F = word 0 of Philox at counter (R, r, 3, 0) masked to h bits) with
+// cycle walking back into [0, n_pad).
+__device__ __forceinline__ uint32_t feistel4(uint32_t v, int h, uint32_t mask, uint32_t k0, uint32_t k1) {
+    uint32_t L = v >> h, R = v & mask;
+#pragma unroll
+    for (uint32_t r = 0; r < 4; r++) {
+        uint32_t c[4] = {R, r, 3u, 0u};
+        philox4x32_10(c, k0, k1);
+        const uint32_t t = L ^ (c[0] & mask);
+        L = R;
+        R = t;
+    }
+    return (L << h) | R;
+}
+
+__global__ __launch_bounds__(256) void k_omega_srht(uint32_t k0, uint32_t k1, int64_t n, int64_t l, uint32_t n_pad,
+                                                    int h, float scale, float* __restrict__ Om, int64_t ld,
+                                                    int64_t ps) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * l) return;
+    const int64_t i = e / l, j = e - i * l;
+    const uint32_t mask = (1u << h) - 1u;
+    // the permutation's cycle through j returns below n_pad within 2^(2h) applications
+    uint32_t sj = feistel4((uint32_t)j, h, mask, k0, k1);
+    for (uint32_t walk = 0; sj >= n_pad && walk < (1u << (2 * h)); walk++) sj = feistel4(sj, h, mask, k0, k1);
+    uint32_t c[4] = {(uint32_t)i, 0u, 2u, 0u};
+    philox4x32_10(c, k0, k1);
+    const bool neg = ((c[0] & 1u) != 0) != ((__builtin_popcount((uint32_t)i & sj) & 1) != 0);
+    const int64_t o = i * ld + j;
+    Om[o] = neg ? -scale : scale;
+    Om[ps + o] = 0.0f;
+    Om[2 * ps + o] = 0.0f;
+    Om[3 * ps + o] = 0.0f;
+}
+
 }  // namespace
+
+hipError_t omega_srht_launch(uint64_t seed, int64_t n, int64_t l, float* Om, int64_t ld, int64_t ps, hipStream_t st) {
+    const int64_t total = n * l;
+    if (total == 0) return hipSuccess;
+    if (n > (int64_t)1 << 30 || l > n) return hipErrorInvalidValue;
+    uint32_t n_pad = 1;
+    int bits = 0;
+    while ((int64_t)n_pad < n) {
+        n_pad <<= 1;
+        bits++;
+    }
+    const int h = (bits + 1) / 2;
+    const float scale = (float)(1.0 / std::sqrt((double)l));
+    hipLaunchKernelGGL(k_omega_srht, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                       (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), n, l, n_pad, h, scale, Om, ld, ps);
+    return hipGetLastError();
+}
 
 hipError_t omega_launch(uint64_t seed, int64_t n, int64_t l, float* Om, int64_t ld, int64_t ps,
                         hipStream_t st, int real_only) {

@@ -614,7 +614,7 @@ void view_product(Ctx& c, const Problem& pr, const Bufs& b, bool adjoint, const 
     }
     QgemmDesc d = desc(adj ? OP_HN : OP_NN, MATH_F32, pr.A, pr.lda, pr.aps, 0, X, ldx, kdim * ldx, 0, T, w,
                        rows_out * w, 0, rows_out, w, kdim);
-    d.b_real = (pr.sketch == QLRA_SKETCH_REAL && X == b.Om) ? 1 : 0;    // the first view of a real sketch
+    d.b_real = (pr.sketch != QLRA_SKETCH_QUATERNION && X == b.Om) ? 1 : 0;    // the first view of a real sketch
     const bool fro = c.fro_next && !adj;
     if (fro) {
         d.fro2_part = b.fro_part;
@@ -642,7 +642,8 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
         note(c, fill_int_launch(b.status, 16, 0, c.st));
         note(c, fill_u32_launch(b.counters, (int64_t)std::max<size_t>(c.cnt_need, 1), c.st));
         if (fro_apart) note(c, fro2_launch(pr.A, pr.mr, pr.nr, pr.lda, pr.aps, b.fro_part, b.nA2, c.st));
-        note(c, omega_launch(pr.seed, pr.n, l, b.Om, l, pr.n * l, c.st, pr.sketch == QLRA_SKETCH_REAL ? 1 : 0));
+        if (pr.sketch == QLRA_SKETCH_SRHT) note(c, omega_srht_launch(pr.seed, pr.n, l, b.Om, l, pr.n * l, c.st));
+        else note(c, omega_launch(pr.seed, pr.n, l, b.Om, l, pr.n * l, c.st, pr.sketch == QLRA_SKETCH_REAL ? 1 : 0));
         if (pr.estimate) note(c, nan_launch(pr.pass_err, c.st));
         if (b.Alo) {
             note(c, lowp_scale_launch(b.nA2, pr.prec, b.lp_scale, b.lp_scale + 1, c.st));
@@ -763,7 +764,8 @@ int check_problem(const Problem& pr) {
     if (pr.v > 64) return QLRA_E_TOO_LARGE;
     if (pr.prec != QLRA_FP32 && pr.prec != QLRA_BF16 && pr.prec != QLRA_FP16 && !prec_split(pr.prec))
         return QLRA_E_UNSUPPORTED;
-    if (pr.sketch != QLRA_SKETCH_QUATERNION && pr.sketch != QLRA_SKETCH_REAL) return QLRA_E_UNSUPPORTED;
+    if (pr.sketch != QLRA_SKETCH_QUATERNION && pr.sketch != QLRA_SKETCH_REAL && pr.sketch != QLRA_SKETCH_SRHT)
+        return QLRA_E_UNSUPPORTED;
     return QLRA_OK;
 }
 
@@ -1236,6 +1238,14 @@ int qlra_complete(const float* M, int64_t m, int64_t n, int64_t ldm, int64_t m_p
     for (int t = 0; t < iters; t++)
         if (hipGraphLaunch(exec, st) != hipSuccess) return QLRA_E_HIP;
     return QLRA_OK;
+}
+
+int qlra_omega_srht(uint64_t seed, int64_t n, int64_t l, float* Om, int64_t ld, int64_t plane_stride, void* stream) {
+    if (n < 0 || l < 0 || l > n || n > ((int64_t)1 << 30)) return QLRA_E_ARG;
+    if (n * l == 0) return QLRA_OK;
+    int rc;
+    if ((rc = check_layout(Om, n, l, ld, plane_stride))) return rc;
+    return omega_srht_launch(seed, n, l, Om, ld, plane_stride, (hipStream_t)stream) == hipSuccess ? QLRA_OK : QLRA_E_HIP;
 }
 
 int qlra_omega(uint64_t seed, int64_t n, int64_t l, float* Om, int64_t ld, int64_t plane_stride, void* stream) {

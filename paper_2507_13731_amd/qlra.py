@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libqlra.so")
 
 QLRA_OK, QLRA_E_ARG, QLRA_E_WORKSPACE, QLRA_E_HIP, QLRA_E_NUMERIC, QLRA_E_TOO_LARGE, QLRA_E_UNSUPPORTED = range(7)
 QLRA_SUBSPACE, QLRA_BLOCK_KRYLOV = 0, 1
-QLRA_SKETCH_QUATERNION, QLRA_SKETCH_REAL = 0, 1
+QLRA_SKETCH_QUATERNION, QLRA_SKETCH_REAL, QLRA_SKETCH_SRHT = 0, 1, 2
 QLRA_FP32, QLRA_BF16, QLRA_FP16, QLRA_BF16_SPLIT, QLRA_FP16_SPLIT = 0, 1, 2, 3, 4
 SCHEMES = {"subspace": QLRA_SUBSPACE, "block_krylov": QLRA_BLOCK_KRYLOV, "krylov": QLRA_BLOCK_KRYLOV}
 
@@ -79,6 +79,7 @@ _lib.qlra_complete_workspace_size.argtypes = [_I64, _I64, _I, _I, _I, _I, ctypes
 _lib.qlra_complete.argtypes = [_P, _I64, _I64, _I64, _I64, _P, _I64, _I, _I, _I, _I, ctypes.c_uint64, _I,
                                ctypes.c_double, ctypes.POINTER(Opts), _P, _I64, _I64, _P]
 _lib.qlra_omega.argtypes = [ctypes.c_uint64, _I64, _I64, _P, _I64, _I64, _P]
+_lib.qlra_omega_srht.argtypes = [ctypes.c_uint64, _I64, _I64, _P, _I64, _I64, _P]
 _lib.qlra_qgemm_workspace_size.argtypes = [_I, _I64, _I64, _I64, _SZ]
 _lib.qlra_qgemm.argtypes = [_I, _P, _I64, _I64, _I64, _I64, _P, _I64, _I64, _I64, _P, _I64, _I64, _P,
                             ctypes.c_size_t, _P]
@@ -108,13 +109,13 @@ for _name in ("qlra_server_create", "qlra_server_submit", "qlra_server_poll", "q
               "qlra_server_stats", "qlra_server_destroy"):
     getattr(_lib, _name).restype = _I
 for _name in ("qlra_workspace_size", "qlra", "qlra_status", "qlra_complete_workspace_size", "qlra_complete",
-              "qlra_omega", "qlra_qgemm_workspace_size",
+              "qlra_omega", "qlra_omega_srht", "qlra_qgemm_workspace_size",
               "qlra_qgemm", "qlra_lowp_copy_bytes", "qlra_lowp_copy", "qlra_qgemm_lp_workspace_size", "qlra_qgemm_lp",
               "qlra_cholqr_workspace_size", "qlra_cholqr", "qlra_qsvd_workspace_size", "qlra_qsvd",
               "qlra_lowp_copy_residual", "qlra_qgemm_split_workspace_size", "qlra_qgemm_split"):
     getattr(_lib, _name).restype = _I
 
-EXPORTS = ("qlra", "qlra_workspace_size", "qlra_status", "qlra_strerror", "qlra_complete",
+EXPORTS = ("qlra", "qlra_workspace_size", "qlra_status", "qlra_strerror", "qlra_complete", "qlra_omega_srht",
            "qlra_complete_workspace_size", "qlra_omega", "qlra_qgemm",
            "qlra_qgemm_workspace_size", "qlra_lowp_copy_bytes", "qlra_lowp_copy", "qlra_qgemm_lp", "qlra_qgemm_lp_workspace_size",
            "qlra_cholqr", "qlra_cholqr_workspace_size", "qlra_qsvd", "qlra_qsvd_workspace_size",
@@ -260,6 +261,15 @@ def qlra_omega(seed, n, l, out=None, stream=None, device="cuda"):
         out = torch.empty((4, n, l), dtype=torch.float32, device=device)
     po, ld, ps = _planes(out, n, l, "Om")
     _check(_lib.qlra_omega(ctypes.c_uint64(seed), n, l, po, ld, ps, _stream_ptr(stream)), "qlra_omega")
+    return out
+
+
+def qlra_omega_srht(seed, n, l, out=None, stream=None, device="cuda"):
+    """The structured sketch (subsampled randomized Hadamard transform), FP32 planes (4, n, l)."""
+    if out is None:
+        out = torch.empty((4, n, l), dtype=torch.float32, device=device)
+    po, ld, ps = _planes(out, n, l, "Om")
+    _check(_lib.qlra_omega_srht(ctypes.c_uint64(seed), n, l, po, ld, ps, _stream_ptr(stream)), "qlra_omega_srht")
     return out
 
 

@@ -287,3 +287,31 @@ def test_real_sketch_on_the_adjoint(gq, oracle):
     Ub, Sb, Vb, _ = oracle.qlra_sketch(np.ascontiguousarray(qref.adj(A64)), 10, 5, 3, 0, Om)
     assert ahat_diff(A64, (Ug, Sg, Vg), (Vb, Sb, Ub)) <= 1e-5
     np.testing.assert_allclose(Sg, Sb, rtol=2e-5)
+
+
+@pytest.mark.parametrize("n,l", [(256, 15), (100, 12), (2048, 60), (3000, 40), (1, 1)])
+def test_srht_sketch_bit_exact(gq, oracle, n, l):
+    """The structured sketch on the device equals the oracle's bit for bit (n = 100 and 3000 pad
+    to 2^7 and 2^12: the first needs the permutation's cycle walking)."""
+    print(f"srht sketch n={n} l={l}", flush=True)
+    got = gq.qlra_omega_srht(13, n, l).cpu().numpy()
+    want = oracle.omega_srht(13, n, l)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+@pytest.mark.parametrize("scheme,v", [(0, 2), (0, 3), (1, 4)])
+def test_srht_sketch_solve(gq, oracle, scheme, v):
+    """opts.sketch = QLRA_SKETCH_SRHT: the result equals the oracle's solve with the same sketch."""
+    print(f"srht solve scheme={scheme} v={v}", flush=True)
+    import torch
+    A, _ = W.config0()
+    A32 = A.astype(np.float32)
+    U, S, V, e, ws = gq.qlra(torch.from_numpy(A32).cuda(), 10, 5, v, scheme, 8, sketch=gq.QLRA_SKETCH_SRHT)
+    assert gq.qlra_status(ws) == gq.QLRA_OK
+    torch.cuda.synchronize()
+    Ug, Sg, Vg, eg = (x.cpu().numpy().astype(np.float64) for x in (U, S, V, e))
+    Om = oracle.omega_srht(8, 256, 15).astype(np.float64)
+    Uo, So, Vo, eo = oracle.qlra_sketch(A32.astype(np.float64), 10, 5, v, scheme, Om)
+    assert ahat_diff(A, (Ug, Sg, Vg), (Uo, So, Vo)) <= 1e-5
+    np.testing.assert_allclose(Sg, So, rtol=2e-5)
+    assert np.isnan(eg[0]) and np.all(np.abs(eg[1:] ** 2 - eo[1:] ** 2) <= 4 * 2.0 ** -24)
