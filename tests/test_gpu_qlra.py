@@ -315,3 +315,30 @@ def test_srht_sketch_solve(gq, oracle, scheme, v):
     assert ahat_diff(A, (Ug, Sg, Vg), (Uo, So, Vo)) <= 1e-5
     np.testing.assert_allclose(Sg, So, rtol=2e-5)
     assert np.isnan(eg[0]) and np.all(np.abs(eg[1:] ** 2 - eo[1:] ** 2) <= 4 * 2.0 ** -24)
+
+
+@pytest.mark.parametrize("m,n,transpose,prec", [(300, 200, False, 0), (200, 300, True, 0), (260, 180, False, 1)])
+def test_srht_sketch_solve_shapes(gq, oracle, m, n, transpose, prec):
+    """The structured sketch with n padded to a power of two, on A^H (an m x l sketch) and with
+    BF16 views: the result equals the oracle's solve with the same sketch."""
+    print(f"srht solve {m}x{n} transpose={transpose} prec={prec}", flush=True)
+    import torch
+    sigma = np.arange(1, min(m, n) + 1, dtype=np.float64) ** -1.5
+    A32 = np.ascontiguousarray(W.spectrum_matrix(44, m, n, sigma, nrefl=4), dtype=np.float32)
+    v = 4 if prec else 3
+    U, S, V, e, ws = gq.qlra(torch.from_numpy(A32).cuda(), 12, 4, v, 0, 21, transpose=transpose,
+                             sketch=gq.QLRA_SKETCH_SRHT, precision=prec)
+    assert gq.qlra_status(ws) == gq.QLRA_OK
+    torch.cuda.synchronize()
+    Ug, Sg, Vg = (x.cpu().numpy().astype(np.float64) for x in (U, S, V))
+    A64 = A32.astype(np.float64)
+    if transpose:
+        Om = oracle.omega_srht(21, m, 16).astype(np.float64)
+        Ub, Sb, Vb, _ = oracle.qlra_sketch(np.ascontiguousarray(qref.adj(A64)), 12, 4, v, 0, Om)
+        Uo, So, Vo = Vb, Sb, Ub
+    else:
+        Om = oracle.omega_srht(21, n, 16).astype(np.float64)
+        Uo, So, Vo, _ = oracle.qlra_sketch(A64, 12, 4, v, 0, Om)
+    d = ahat_diff(A64, (Ug, Sg, Vg), (Uo, So, Vo))
+    print(f"  ahat diff {d:.3e}", flush=True)
+    assert d <= (1e-5 if prec == 0 else 1e-2)
