@@ -149,9 +149,11 @@ def test_config2_krylov(gq, oracle):
 
 
 def test_ragged_and_degenerate_shapes(gq, oracle):
-    """Tall and wide, sizes off every tile boundary, p = 0, k + p = min(m, n)."""
+    """Tall and wide, sizes off every tile boundary, p = 0, k + p = min(m, n), rank 1 (k = 1,
+    l = 1) including a single row, a single column and 1 x 1."""
     for (m, n, k, p, v, sch) in [(97, 61, 5, 0, 2, 0), (61, 97, 7, 3, 3, 1), (130, 40, 30, 10, 2, 0),
-                                 (33, 40, 4, 4, 6, 1), (300, 17, 10, 7, 4, 1)]:
+                                 (33, 40, 4, 4, 6, 1), (300, 17, 10, 7, 4, 1), (50, 40, 1, 0, 2, 0),
+                                 (1, 7, 1, 0, 2, 0), (9, 1, 1, 0, 3, 1), (1, 1, 1, 0, 2, 0), (64, 64, 1, 0, 5, 1)]:
         print(f"ragged m={m} n={n} k={k} p={p} v={v} scheme={sch}", flush=True)
         A = W.random_quat(m + n, m, n).astype(np.float32)
         Ug, Sg, Vg, eg, st = run_gpu(gq, A, k, p, v, sch, 9)
@@ -161,6 +163,18 @@ def test_ragged_and_degenerate_shapes(gq, oracle):
         err_g = qref.fro(oracle_reconstruct(Ug, Sg, Vg) - A) / qref.fro(A)
         err_o = qref.fro(oracle_reconstruct(Uo, So, Vo) - A) / qref.fro(A)
         assert abs(err_g - err_o) < 1e-4
+
+
+@pytest.mark.parametrize("v,scheme", [(2, 0), (4, 1)])
+def test_zero_matrix_reports_breakdown(gq, v, scheme):
+    """A = 0: every view is zero, the CholeskyQR cannot produce a basis, and the status word says
+    QLRA_E_NUMERIC (the singular values come out zero, the factors are not valid)."""
+    import torch
+    print(f"zero matrix v={v} scheme={scheme}", flush=True)
+    A = torch.zeros((4, 64, 48), device="cuda")
+    U, S, V, e, ws = gq.qlra(A, 5, 3, v, scheme, 3)
+    assert gq.qlra_status(ws) == gq.QLRA_E_NUMERIC
+    assert np.all(S.cpu().numpy() == 0.0)
 
 
 def test_argument_errors(gq):
