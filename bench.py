@@ -125,12 +125,12 @@ def pmc_summary(fetch_csv, write_csv):
     hbm = 0.5 * sum(out[c][o]["bytes_per_launch"] for c in ("FETCH_SIZE", "WRITE_SIZE") for o in ("forward", "adjoint"))
     rec = {"kernel": "FP32 view product 2048x2048 by 60 (transpose + product kernel + split-K reduction), "
                      "mean of A X and A^H X",
-           "commands": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d <repo>/gpurun_out/"
+           "commands": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/"
                         "pmc_fetch -o f -- python3 <repo>/bench.py --counters",
-                        "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d <repo>/gpurun_out/"
+                        "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/"
                         "pmc_write -o w -- python3 <repo>/bench.py --counters",
-                        "python bench.py --pmc-summary gpurun_out/pmc_fetch/f_counter_collection.csv "
-                        "gpurun_out/pmc_write/w_counter_collection.csv"],
+                        "python bench.py --pmc-summary <out>/pmc_fetch/f_counter_collection.csv "
+                        "<out>/pmc_write/w_counter_collection.csv"],
            "kernel_source_hash": kernel_source_hash(), "hbm_bytes_per_launch": round(hbm),
            "algorithmic_bytes_per_launch": 16 * M * N + 2 * 16 * N * (K_RANK + P_OVER), **out}
     os.makedirs(os.path.dirname(PMC_FILE), exist_ok=True)
