@@ -189,7 +189,10 @@ typedef struct qlra_server qlra_server_t;
 
 typedef struct {
     size_t hbm_bytes;        /* device arena for request workspaces                        */
-    int max_active;          /* slots: requests in flight at once (1 .. 64)                */
+    int max_active;          /* slots: requests in flight at once (1 .. 64); each slot's
+                                stream runs on one of the process's hardware queues (4 by
+                                default on ROCm), and slots beyond that share queues and
+                                serialize: 4 slots gave the highest throughput here          */
     int graphs;              /* nonzero: launch each view-step as a captured HIP graph      */
 } qlra_server_opts_t;
 
