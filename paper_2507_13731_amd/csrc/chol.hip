@@ -194,6 +194,25 @@ __device__ __forceinline__ double bcast(double v, int i) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// sqrt(d) and 1 / sqrt(d) for a positive finite d: the hardware reciprocal square root refined
+// by two Newton steps (each doubles the correct bits: a short dependent chain next to a
+// square root followed by a division); tiny d take the plain route.
+__device__ __forceinline__ void sqrt_rsqrt(double d, double& s, double& r) {
+    if (d < 1e-280) {
+        s = sqrt(d);
+        r = 1.0 / s;
+        return;
+    }
+    double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+    for (int it = 0; it < 2; it++) {
+        const double e = fma(-(d * y), y, 1.0);     // 1 - d y^2
+        y = fma(0.5 * y, e, y);
+    }
+    r = y;
+    s = d * y;
+}
+
 // Right-looking Cholesky G + shift I = R^H R (R upper triangular with real positive diagonal):
 // step j scales row j by 1 / r_jj (the half wave that owns row j, double-buffered row in LDS),
 // then every owner of an entry (a, b), j < a <= b, subtracts conj(r_ja) r_jb.
@@ -224,8 +243,8 @@ template <int NB>
 __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict__ G, int w, double* __restrict__ Rout,
                                                         int* status, int* shift_out, const int* gate, int allow_shift,
                                                         double shift_scale) {
-    __shared__ double rowb[2][4 * kRegMax];
-    __shared__ int s_fail;
+    constexpr int kFlag = 4 * kRegMax;                 // breakdown flag behind the pivot row
+    __shared__ double rowb[2][4 * kRegMax + 1];
     if (gate && *gate == 0) return;
     const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
     const int64_t ps = (int64_t)w * w;
@@ -246,7 +265,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict_
                 }
                 g[ri][ci] = v;
             }
-        if (tid == 0) s_fail = 0;
+        bool fail = false;
         __syncthreads();
         for (int j = 0; j < w; j++) {
             const int jr = j & 31, jh = j >> 5;
@@ -258,33 +277,41 @@ __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict_
                 for (int h = 0; h < NB; h++)
                     if (h == jh) piv = g[h][h].w;
                 const double d = bcast(piv, ((ty & 1) << 5) | jr);
-                if (!(d > 0.0) || !(d < 1e300)) {     // breakdown or non-finite pivot
-                    if (tx == 0) s_fail = 1;
-                } else {
-                    const double rjj = sqrt(d), inv = 1.0 / rjj;
+                const bool bad = !(d > 0.0) || !(d < 1e300);     // breakdown or non-finite pivot
+                if (tx == 0) rb[kFlag] = bad ? 1.0 : 0.0;
+                if (!bad) {
+                    double rjj, inv;
+                    sqrt_rsqrt(d, rjj, inv);
                     chol_row_at<NB>(g, jh, j, w, tx, rb, rjj, inv);
                 }
             }
             __syncthreads();
-            if (s_fail) break;                         // uniform: read after the barrier
+            // the pivot row and the flag in one round of LDS reads (indices stay below kRegMax;
+            // entries of rows and columns that are not live are read and not used)
+            Q4 rja[NB], rjb[NB];
+#pragma unroll
+            for (int i = 0; i < NB; i++) {
+                rja[i] = qconj(ldp<kRegMax>(rb, ty + 32 * i));
+                rjb[i] = ldp<kRegMax>(rb, tx + 32 * i);
+            }
+            if (rb[kFlag] != 0.0) { fail = true; break; }    // uniform
 #pragma unroll
             for (int ri = 0; ri < NB; ri++) {
                 const int a = ty + 32 * ri;
                 if (a <= j || a >= w) continue;
-                const Q4 rja = qconj(ldp<kRegMax>(rb, a));
 #pragma unroll
                 for (int ci = 0; ci < NB; ci++) {
                     if (ci < ri) continue;
                     const int b = tx + 32 * ci;
                     if (b < a || b >= w) continue;
-                    Q4 v = qsub(g[ri][ci], qmul(rja, ldp<kRegMax>(rb, b)));
+                    Q4 v = qsub(g[ri][ci], qmul(rja[ri], rjb[ci]));
                     if (a == b) v.x = v.y = v.z = 0.0;
                     g[ri][ci] = v;
                 }
             }
         }
         __syncthreads();
-        if (!s_fail) break;
+        if (!fail) break;
         if (!allow_shift || attempt == 1) { failed = 1; break; }
         // shifted CholeskyQR (Fukaya et al.): add shift_scale * trace(G) to the diagonal
         double tr = 0.0;
