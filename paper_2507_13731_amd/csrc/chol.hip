@@ -172,6 +172,8 @@ __global__ __launch_bounds__(kThreads) void k_chol_lds(const double* __restrict_
     }
 }
 
+// upper triangle of order w packed by rows: (t, c), c >= t
+__device__ __forceinline__ int upk(int t, int c, int w) { return t * (2 * w - t + 1) / 2 + (c - t); }
 // ------------------------------------------------------------------------------------------
 // Factors of order w <= kRegMax: the matrix in registers (1024 threads, NB x NB entries each:
 // rows ty + 32 i, columns tx + 32 j; NB = 2 up to 64, 3 up to 96), one barrier per elimination
@@ -241,8 +243,8 @@ __device__ __forceinline__ void chol_row_at(Q4 (&g)[NB][NB], int jh, int j, int 
 
 template <int NB>
 __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict__ G, int w, double* __restrict__ Rout,
-                                                        int* status, int* shift_out, const int* gate, int allow_shift,
-                                                        double shift_scale) {
+                                                        double* __restrict__ Rpk, int* status, int* shift_out,
+                                                        const int* gate, int allow_shift, double shift_scale) {
     constexpr int kFlag = 4 * kRegMax;                 // breakdown flag behind the pivot row
     __shared__ double rowb[2][4 * kRegMax + 1];
     if (gate && *gate == 0) return;
@@ -325,12 +327,22 @@ __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict_
         if (shift_out) *shift_out = shifted;
         if (failed) atomicOr(status, 2);
     }
+    // R in planes, and its upper triangle packed by rows with the four components of an entry
+    // side by side (the layout the triangular solve stages)
+    typedef double d2 __attribute__((ext_vector_type(2)));
 #pragma unroll
     for (int ri = 0; ri < NB; ri++)
 #pragma unroll
         for (int ci = 0; ci < NB; ci++) {
             const int a = ty + 32 * ri, b = tx + 32 * ci;
-            if (a < w && b < w) st4(Rout, ps, (int64_t)a * w + b, (ci >= ri && b >= a) ? g[ri][ci] : Q4{0, 0, 0, 0});
+            if (a >= w || b >= w) continue;
+            const bool up = ci >= ri && b >= a;
+            st4(Rout, ps, (int64_t)a * w + b, up ? g[ri][ci] : Q4{0, 0, 0, 0});
+            if (up) {
+                d2* o = reinterpret_cast<d2*>(Rpk) + 2 * upk(a, b, w);
+                o[0] = d2{g[ri][ci].w, g[ri][ci].x};
+                o[1] = d2{g[ri][ci].y, g[ri][ci].z};
+            }
         }
 }
 
@@ -350,70 +362,85 @@ __device__ __forceinline__ Q4 row_bcast(Q4 q) {
 // Q = Y R^{-1} by forward substitution along each row (q R = y): R upper triangular FP64
 // (w x w planes, ld w, w <= kRegMax), Y and Q FP32 planes (Q may alias Y).  One 16-lane group
 // per row, lane s owning columns s + 16 u (u < NU); the finished q_t is broadcast to the group
-// and subtracted, times row t of R, from the later columns.  R's upper triangle is staged in
-// LDS packed by rows (dynamic size, w (w + 1) / 2 entries per plane).
+// and subtracted, times row t of R, from the later columns (16 fused multiply-adds per
+// quaternion).  R's upper triangle is staged in LDS packed by rows with the four components of
+// an entry side by side (two 16-byte reads per entry; dynamic size, w (w + 1) / 2 entries).
 constexpr int kTrsmRows = 16;   // rows per 256-thread workgroup
-// upper triangle of order w packed by rows: (t, c), c >= t
-__device__ __forceinline__ int upk(int t, int c, int w) { return t * (2 * w - t + 1) / 2 + (c - t); }
-__device__ __forceinline__ Q4 ldr(const double* p, int ps, int i) { return Q4{p[i], p[ps + i], p[2 * ps + i], p[3 * ps + i]}; }
+__device__ __forceinline__ Q4 ldr(const double* sR, int i) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 lo = reinterpret_cast<const d2*>(sR)[2 * i], hi = reinterpret_cast<const d2*>(sR)[2 * i + 1];
+    return Q4{lo[0], lo[1], hi[0], hi[1]};
+}
+// c ? a : b, component by component (a select of values, kept in registers)
+__device__ __forceinline__ Q4 qsel(bool c, Q4 a, Q4 b) {
+    return Q4{c ? a.w : b.w, c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z};
+}
+// acc - a b (eq. (1)), as four chains of fused multiply-adds into acc
+__device__ __forceinline__ Q4 qfms(Q4 acc, Q4 a, Q4 b) {
+    return Q4{fma(a.z, b.z, fma(a.y, b.y, fma(a.x, b.x, fma(-a.w, b.w, acc.w)))),
+              fma(a.z, b.y, fma(-a.y, b.z, fma(-a.x, b.w, fma(-a.w, b.x, acc.x)))),
+              fma(-a.z, b.x, fma(-a.y, b.w, fma(a.x, b.z, fma(-a.w, b.y, acc.y)))),
+              fma(-a.z, b.w, fma(a.y, b.x, fma(-a.x, b.y, fma(-a.w, b.z, acc.z))))};
+}
 
 // columns t = 16 TB + TT of the substitution: q_t = acc_t / r_tt on lane TT, broadcast over the
-// row's 16 lanes, then acc_c -= q_t r_tc for the later columns c > t.
+// row's 16 lanes, then acc_c -= q_t r_tc for the later columns c > t.  Branch-free, so that the
+// LDS reads of a step are issued together: the later blocks (u > TB) update every lane (lanes
+// past w read row t at column w - 1 and hold values that are never stored or broadcast), and
+// block TB keeps its finished columns by a select.
 template <int NU, int TB, int TT>
-__device__ __forceinline__ void trsm_step(Q4 (&acc)[NU], const double* sR, int pps, const double* sinv, int s, int w) {
+__device__ __forceinline__ void trsm_step(Q4 (&acc)[NU], const double* sR, const double* sinv, int s, int w) {
     constexpr int t = 16 * TB + TT;
-    const Q4 q = row_bcast<TT>(qscale(acc[TB], sinv[t]));
-    if (s == TT) acc[TB] = q;
+    Q4 r[NU];
 #pragma unroll
-    for (int u = TB; u < NU; u++) {
-        const int c = s + 16 * u;
-        if (c > t && c < w) acc[u] = qsub(acc[u], qmul(q, ldr(sR, pps, upk(t, c, w))));
-    }
+    for (int u = TB; u < NU; u++) r[u] = ldr(sR, upk(t, min(s + 16 * u, w - 1), w));
+    const Q4 q = row_bcast<TT>(qscale(acc[TB], sinv[t]));
+    const Q4 nb = qfms(acc[TB], q, r[TB]);
+    acc[TB] = qsel(s > TT, nb, qsel(s == TT, q, acc[TB]));
+#pragma unroll
+    for (int u = TB + 1; u < NU; u++) acc[u] = qfms(acc[u], q, r[u]);
 }
 template <int NU, int TB, int TT = 0>
-__device__ __forceinline__ void trsm_block(Q4 (&acc)[NU], const double* sR, int pps, const double* sinv, int s, int w) {
+__device__ __forceinline__ void trsm_block(Q4 (&acc)[NU], const double* sR, const double* sinv, int s, int w) {
     if constexpr (TT < 16) {
         if (16 * TB + TT >= w) return;
-        trsm_step<NU, TB, TT>(acc, sR, pps, sinv, s, w);
-        trsm_block<NU, TB, TT + 1>(acc, sR, pps, sinv, s, w);
+        trsm_step<NU, TB, TT>(acc, sR, sinv, s, w);
+        trsm_block<NU, TB, TT + 1>(acc, sR, sinv, s, w);
     }
 }
 template <int NU, int TB = 0>
-__device__ __forceinline__ void trsm_all(Q4 (&acc)[NU], const double* sR, int pps, const double* sinv, int s, int w) {
+__device__ __forceinline__ void trsm_all(Q4 (&acc)[NU], const double* sR, const double* sinv, int s, int w) {
     if constexpr (TB < NU) {
-        trsm_block<NU, TB>(acc, sR, pps, sinv, s, w);
-        trsm_all<NU, TB + 1>(acc, sR, pps, sinv, s, w);
+        trsm_block<NU, TB>(acc, sR, sinv, s, w);
+        trsm_all<NU, TB + 1>(acc, sR, sinv, s, w);
     }
 }
 
 template <int NU>
 __global__ __launch_bounds__(256) void k_trsm(const float* Y, int64_t ldy, int64_t yps, float* Q, int64_t ldq,
-                                              int64_t qps, const double* __restrict__ R, int w, int64_t rows,
+                                              int64_t qps, const double* __restrict__ Rpk, int w, int64_t rows,
                                               const int* gate) {
-    extern __shared__ double dyn[];
+    extern __shared__ __attribute__((aligned(16))) double dyn[];
     const int pps = w * (w + 1) / 2;
-    double* sR = dyn;               // 4 planes of pps
+    double* sR = dyn;               // pps entries of four components
     double* sinv = dyn + 4 * pps;   // w
     if (gate && *gate == 0) return;
     const int tid = threadIdx.x, s = tid & 15;
-    const int64_t ps = (int64_t)w * w;
-    // staging: eight loads in flight per thread (clamped addresses, guarded stores)
-    const int n = w * w;
-    for (int base = 0; base < n; base += 8 * 256) {
-        Q4 v[8];
+    // staging: a straight copy of the packed triangle, sixteen 16-byte loads in flight per
+    // thread (one round for w <= 63)
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2* src = reinterpret_cast<const d2*>(Rpk);
+    d2* dst = reinterpret_cast<d2*>(sR);
+    const int n2 = 2 * pps;
+    for (int base = 0; base < n2; base += 16 * 256) {
+        d2 v[16];
 #pragma unroll
-        for (int u = 0; u < 8; u++) v[u] = ld4(R, ps, min(base + u * 256 + tid, n - 1));
+        for (int u = 0; u < 16; u++) v[u] = src[min(base + u * 256 + tid, n2 - 1)];
 #pragma unroll
-        for (int u = 0; u < 8; u++) {
-            const int e = base + u * 256 + tid;
-            const int t = e / w, c = e - t * w;
-            if (e < n && c >= t) {
-                const int i = upk(t, c, w);
-                sR[i] = v[u].w; sR[pps + i] = v[u].x; sR[2 * pps + i] = v[u].y; sR[3 * pps + i] = v[u].z;
-            }
-        }
+        for (int u = 0; u < 16; u++)
+            if (base + u * 256 + tid < n2) dst[base + u * 256 + tid] = v[u];
     }
-    for (int t = tid; t < w; t += 256) sinv[t] = 1.0 / R[(int64_t)t * w + t];
+    for (int t = tid; t < w; t += 256) sinv[t] = 1.0 / Rpk[4 * upk(t, t, w)];
     __syncthreads();
     const int64_t row = (int64_t)blockIdx.x * kTrsmRows + (tid >> 4);
     const bool act = row < rows;
@@ -427,7 +454,7 @@ __global__ __launch_bounds__(256) void k_trsm(const float* Y, int64_t ldy, int64
             acc[u] = Q4{(double)Y[o], (double)Y[yps + o], (double)Y[2 * yps + o], (double)Y[3 * yps + o]};
         }
     }
-    trsm_all<NU>(acc, sR, pps, sinv, s, w);
+    trsm_all<NU>(acc, sR, sinv, s, w);
     if (act) {
 #pragma unroll
         for (int u = 0; u < NU; u++) {
@@ -586,29 +613,29 @@ __global__ void k_flag_nonzero(int* dst, const int* src) {
 int chol_lds_max() { return kLdsMax; }
 int chol_reg_max() { return kRegMax; }
 
-hipError_t chol_reg_launch(const double* G, int64_t w, double* R, int* status, int* shift_out, const int* gate,
-                           int allow_shift, double shift_scale, hipStream_t st) {
+hipError_t chol_reg_launch(const double* G, int64_t w, double* R, double* Rpk, int* status, int* shift_out,
+                           const int* gate, int allow_shift, double shift_scale, hipStream_t st) {
     if (w < 1 || w > kRegMax) return hipErrorInvalidValue;
     if (w <= 64)
-        hipLaunchKernelGGL(k_chol_reg<2>, dim3(1), dim3(kThreads), 0, st, G, (int)w, R, status, shift_out, gate,
+        hipLaunchKernelGGL(k_chol_reg<2>, dim3(1), dim3(kThreads), 0, st, G, (int)w, R, Rpk, status, shift_out, gate,
                            allow_shift, shift_scale);
     else
-        hipLaunchKernelGGL(k_chol_reg<3>, dim3(1), dim3(kThreads), 0, st, G, (int)w, R, status, shift_out, gate,
+        hipLaunchKernelGGL(k_chol_reg<3>, dim3(1), dim3(kThreads), 0, st, G, (int)w, R, Rpk, status, shift_out, gate,
                            allow_shift, shift_scale);
     return hipGetLastError();
 }
 
-hipError_t trsm_launch(const float* Y, int64_t ldy, int64_t yps, float* Q, int64_t ldq, int64_t qps, const double* R,
-                       int64_t w, int64_t rows, const int* gate, hipStream_t st) {
+hipError_t trsm_launch(const float* Y, int64_t ldy, int64_t yps, float* Q, int64_t ldq, int64_t qps,
+                       const double* Rpk, int64_t w, int64_t rows, const int* gate, hipStream_t st) {
     if (w < 1 || w > kRegMax || rows < 0) return hipErrorInvalidValue;
     if (rows == 0) return hipSuccess;
     const int64_t blocks = (rows + kTrsmRows - 1) / kTrsmRows;
     const size_t lds = (size_t)(4 * (w * (w + 1) / 2) + w) * sizeof(double);
     if (w <= 64)
-        hipLaunchKernelGGL(k_trsm<4>, dim3((unsigned)blocks), dim3(256), lds, st, Y, ldy, yps, Q, ldq, qps, R, (int)w,
+        hipLaunchKernelGGL(k_trsm<4>, dim3((unsigned)blocks), dim3(256), lds, st, Y, ldy, yps, Q, ldq, qps, Rpk, (int)w,
                            rows, gate);
     else
-        hipLaunchKernelGGL(k_trsm<6>, dim3((unsigned)blocks), dim3(256), lds, st, Y, ldy, yps, Q, ldq, qps, R, (int)w,
+        hipLaunchKernelGGL(k_trsm<6>, dim3((unsigned)blocks), dim3(256), lds, st, Y, ldy, yps, Q, ldq, qps, Rpk, (int)w,
                            rows, gate);
     return hipGetLastError();
 }

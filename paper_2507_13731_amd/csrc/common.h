@@ -119,15 +119,16 @@ hipError_t zero_f64_launch(double* p, int64_t count, const int* gate, hipStream_
 hipError_t flag_nonzero_launch(int* dst, const int* src, hipStream_t st);
 // *gate = 1 when max |G - I| (G: w x w FP64 planes) exceeds tol or is not finite, else 0.
 hipError_t orth_gate_launch(const double* G, int64_t w, double tol, int* gate, hipStream_t st);
-// Cholesky alone for w <= chol_reg_max(), factor to R (no inverse); same status, shift and gate
-// behaviour as chol_launch.
+// Cholesky alone for w <= chol_reg_max(), factor to R (no inverse) and to Rpk, R's upper
+// triangle packed by rows with the four components of an entry side by side (4 w (w + 1) / 2
+// doubles, the input of trsm_launch); same status, shift and gate behaviour as chol_launch.
 int chol_reg_max();
-hipError_t chol_reg_launch(const double* G, int64_t w, double* R, int* status, int* shift_out, const int* gate,
-                           int allow_shift, double shift_scale, hipStream_t st);
-// Q = Y R^{-1} (rows x w FP32 planes, Q may alias Y), R upper triangular FP64 (ld w),
-// w <= chol_reg_max().
-hipError_t trsm_launch(const float* Y, int64_t ldy, int64_t yps, float* Q, int64_t ldq, int64_t qps, const double* R,
-                       int64_t w, int64_t rows, const int* gate, hipStream_t st);
+hipError_t chol_reg_launch(const double* G, int64_t w, double* R, double* Rpk, int* status, int* shift_out,
+                           const int* gate, int allow_shift, double shift_scale, hipStream_t st);
+// Q = Y R^{-1} (rows x w FP32 planes, Q may alias Y), R upper triangular FP64 given packed as
+// chol_reg_launch writes it, w <= chol_reg_max().
+hipError_t trsm_launch(const float* Y, int64_t ldy, int64_t yps, float* Q, int64_t ldq, int64_t qps,
+                       const double* Rpk, int64_t w, int64_t rows, const int* gate, hipStream_t st);
 // Rout = R2 * R1 (upper triangular w x w); nothing if gate && !*gate.
 hipError_t rmul_launch(const double* R2, const double* R1, double* Rout, int64_t w,
                        const int* gate, hipStream_t st);

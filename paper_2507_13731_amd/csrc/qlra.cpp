@@ -195,9 +195,11 @@ void cholqr(Ctx& c, const float* Y, int64_t rows, int64_t w, int64_t ldy, int64_
             const int* g = (gated && round == 1) ? gate : nullptr;
             if (c.live()) {
                 if (g) note(c, orth_gate_launch(G, w, 1e-7, gate, c.st));
-                note(c, chol_reg_launch(G, w, Rr, c.status, round == 0 ? shifted : nullptr, g, round == 0 ? 1 : 0,
-                                        shift_scale(rows, w), c.st));
-                note(c, trsm_launch(src, lds, sps, dst, ldd, dps, Rr, w, rows, g, c.st));
+                // the packed copy of the factor for the triangular solve goes to chol_work, which
+                // only the larger orders use otherwise
+                note(c, chol_reg_launch(G, w, Rr, c.chol_work, c.status, round == 0 ? shifted : nullptr, g,
+                                        round == 0 ? 1 : 0, shift_scale(rows, w), c.st));
+                note(c, trsm_launch(src, lds, sps, dst, ldd, dps, c.chol_work, w, rows, g, c.st));
             }
         } else {
             double* Rout = last ? (R ? R : c.Rjunk) : c.R1;
