@@ -12,8 +12,9 @@
 //              K = tau/2 v^H p, q = p - K v.  The quaternion subdiagonal s_j is made real by a
 //              unitary diagonal D (phases), so T = D^H Q^H G Q D is real symmetric tridiagonal:
 //              the structure-preserving counterpart of reducing the complex adjoint.
-//  k_eigvals   eigenvalues of T by multisection with Sturm counts (16 lanes per eigenvalue,
-//              16 eigenvalues per workgroup, any number of problems in one launch).
+//  k_eigvals   eigenvalues of T by multisection with Sturm counts (one wave per eigenvalue,
+//              64 section points per round, 4 eigenvalues per workgroup, any number of
+//              problems in one launch).
 //  k_eigvecs   eigenvectors of T from twisted factorisations (forward and backward pivots of
 //              T - mu, twist index of least |gamma|), modified Gram-Schmidt inside clusters of
 //              close eigenvalues, and the back-transformation y = Q D x with the stored
@@ -28,8 +29,8 @@ namespace {
 constexpr int kW = 96;                          // largest order
 constexpr int kPacked = kW * (kW + 1) / 2;      // packed lower triangle, (i, t) at i (i + 1) / 2 + t
 constexpr int ET = 256;                         // eigenvalue / eigenvector workgroups
-constexpr int kPer = ET / 16;                   // eigenvalues (vectors) per workgroup, 16 lanes each
-constexpr int kRounds = 14;                     // 17-section rounds: width shrinks by 17^14 > 1e17
+constexpr int kPer = ET / 64;                   // eigenvalues per workgroup, one wave each
+constexpr int kRounds = 10;                     // 65-section rounds: width shrinks by 65^10 > 1e18
 
 // record layout (doubles)
 constexpr int OFF_D = 0, OFF_B = kW, OFF_B2 = 2 * kW, OFF_TAU = 3 * kW, OFF_PH = 4 * kW, OFF_BND = 8 * kW,
@@ -337,7 +338,7 @@ __device__ int sturm_count(double dv, double dv2, double b2v, double b2v2, int w
 __global__ __launch_bounds__(ET) void k_eigvals(double* __restrict__ triall, int w, double* __restrict__ lam_out,
                                                 int64_t lam_stride, int lam_prob) {
     double* tri = triall + (int64_t)blockIdx.y * kTriStride;
-    const int tid = threadIdx.x, lane = tid & 63, s16 = tid & 15;
+    const int tid = threadIdx.x, lane = tid & 63;
     // exact power-of-two scaling: |bounds| <= 1 afterwards
     int ex;
     frexp(fmax(fabs(tri[OFF_BND]), fabs(tri[OFF_BND + 1])), &ex);
@@ -345,22 +346,21 @@ __global__ __launch_bounds__(ET) void k_eigvals(double* __restrict__ triall, int
     const double b2v = lane < w ? ldexp(tri[OFF_B2 + lane], -2 * ex) : 0.0;
     const double dv2 = lane + 64 < w ? ldexp(tri[OFF_D + 64 + lane], -ex) : 0.0;
     const double b2v2 = lane + 64 < w ? ldexp(tri[OFF_B2 + 64 + lane], -2 * ex) : 0.0;
-    const int k = blockIdx.x * kPer + (tid >> 4);          // ascending index
+    const int k = blockIdx.x * kPer + (tid >> 6);          // ascending index
     double a = ldexp(tri[OFF_BND], -ex), bb = ldexp(tri[OFF_BND + 1], -ex);
     for (int round = 0; round < kRounds; round++) {
-        const double x = a + (bb - a) * (double)(s16 + 1) / 17.0;
+        const double x = a + (bb - a) * (double)(lane + 1) / 65.0;
         const int c = sturm_count(dv, dv2, b2v, b2v2, w, x);
         const unsigned long long m = __ballot(c > k);
-        const unsigned grp = (unsigned)((m >> (lane & ~15)) & 0xFFFFull);
-        const int first = grp ? __builtin_ctz(grp) : 16;    // first section point above eigenvalue k
-        const double xa = first == 0 ? a : a + (bb - a) * (double)first / 17.0;
-        const double xb = first == 16 ? bb : a + (bb - a) * (double)(first + 1) / 17.0;
+        const int first = m ? __builtin_ctzll(m) : 64;     // first section point above eigenvalue k
+        const double xa = first == 0 ? a : a + (bb - a) * (double)first / 65.0;
+        const double xb = first == 64 ? bb : a + (bb - a) * (double)(first + 1) / 65.0;
         a = xa;
         bb = xb;
     }
     a = ldexp(a, ex);
     bb = ldexp(bb, ex);
-    if (k < w && s16 == 0) {
+    if (k < w && lane == 0) {
         const double lam = 0.5 * (a + bb);
         tri[OFF_LAM + k] = lam;
         if (lam_out && (lam_prob < 0 || (int)blockIdx.y == lam_prob))
