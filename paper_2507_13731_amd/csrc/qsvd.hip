@@ -203,8 +203,9 @@ __global__ __launch_bounds__(256) void k_fro2_final(const double* __restrict__ p
 // Phase normalisation of the returned singular vectors: column j of U and V is right-multiplied
 // by conj(nu / |nu|), nu the entry of largest modulus of V(:, j) (lowest row on ties).  Two
 // coalesced passes: partial arg-max over row blocks of V (64 columns per block, a row read
-// whole), then each apply block combines the partials of its 64 columns in block order and
-// rotates its rows of U and V.
+// whole), then each apply block combines the partials of its 64 columns (the order on modulus
+// and row is strict, so the scan order does not change the pick) and rotates its 16 rows of U
+// and V, all loads of a thread issued before its stores.
 struct PhasePart {
     double val;
     int64_t idx;
@@ -248,61 +249,90 @@ __global__ __launch_bounds__(256) void k_phase_part(const float* __restrict__ V,
     }
 }
 
+template <int RPT>
 __global__ __launch_bounds__(256) void k_phase_apply(float* U, int64_t m, int64_t ldu, int64_t ups, float* V, int64_t n,
                                                      int64_t ldv, int64_t vps, int k, const PhasePart* __restrict__ part,
-                                                     int nparts, int64_t rows_per_block) {
+                                                     int nparts) {
     __shared__ double sv[4][64];
     __shared__ int64_t si[4][64];
-    __shared__ float sq[4][4][64];
+    __shared__ int sf[4][64];
     __shared__ double ph[4][64];
     __shared__ int okf[64];
     const int c = threadIdx.x & 63, rs = threadIdx.x >> 6;
     const int64_t j = (int64_t)blockIdx.y * 64 + c;
     {
-        // the four row groups scan interleaved quarters of the partial arg-maxes
+        // the four row groups scan interleaved quarters of the partial arg-maxes: the values and
+        // rows of eight partials are read together, then compared in order
         double best = -1.0;
         int64_t bi = 0;
-        float q[4] = {0, 0, 0, 0};
+        int bt = -1;
         if (j < k) {
-            for (int t = rs; t < nparts; t += 4) {
-                const PhasePart pp = part[(int64_t)t * k + j];
-                if (pp.val >= 0.0 && phase_better(pp.val, pp.idx, best, bi)) {
-                    best = pp.val; bi = pp.idx;
-                    q[0] = pp.q[0]; q[1] = pp.q[1]; q[2] = pp.q[2]; q[3] = pp.q[3];
+            for (int t0 = rs; t0 < nparts; t0 += 32) {
+                double pv[8];
+                int64_t pi[8];
+#pragma unroll
+                for (int u = 0; u < 8; u++) {
+                    const int t = t0 + 4 * u;
+                    pv[u] = t < nparts ? part[(int64_t)t * k + j].val : -1.0;
+                    pi[u] = t < nparts ? part[(int64_t)t * k + j].idx : 0;
                 }
+#pragma unroll
+                for (int u = 0; u < 8; u++)
+                    if (pv[u] >= 0.0 && phase_better(pv[u], pi[u], best, bi)) { best = pv[u]; bi = pi[u]; bt = t0 + 4 * u; }
             }
         }
         sv[rs][c] = best;
         si[rs][c] = bi;
-        for (int t = 0; t < 4; t++) sq[rs][t][c] = q[t];
+        sf[rs][c] = bt;
     }
     __syncthreads();
     if (rs == 0) {
         double best = sv[0][c];
         int64_t bi = si[0][c];
-        int from = 0;
+        int from = sf[0][c];
         for (int t = 1; t < 4; t++)
-            if (sv[t][c] >= 0.0 && phase_better(sv[t][c], si[t][c], best, bi)) { best = sv[t][c]; bi = si[t][c]; from = t; }
-        const bool ok = best > 0.0;
+            if (sv[t][c] >= 0.0 && phase_better(sv[t][c], si[t][c], best, bi)) { best = sv[t][c]; bi = si[t][c]; from = sf[t][c]; }
+        const bool ok = best > 0.0 && from >= 0 && j < k;
         const double nrm = ok ? sqrt(best) : 1.0;
+        float q[4] = {0, 0, 0, 0};
+        if (ok) {
+            const PhasePart& pp = part[(int64_t)from * k + j];
+            q[0] = pp.q[0]; q[1] = pp.q[1]; q[2] = pp.q[2]; q[3] = pp.q[3];
+        }
         // conj(phase)
-        ph[0][c] = sq[from][0][c] / nrm; ph[1][c] = -sq[from][1][c] / nrm;
-        ph[2][c] = -sq[from][2][c] / nrm; ph[3][c] = -sq[from][3][c] / nrm;
+        ph[0][c] = q[0] / nrm; ph[1][c] = -q[1] / nrm;
+        ph[2][c] = -q[2] / nrm; ph[3][c] = -q[3] / nrm;
         okf[c] = ok;
     }
     __syncthreads();
     if (j >= k || !okf[c]) return;
     const double p0 = ph[0][c], p1 = ph[1][c], p2 = ph[2][c], p3 = ph[3][c];
-    const int64_t t0 = (int64_t)blockIdx.x * rows_per_block;
-    for (int64_t t = t0 + rs; t < t0 + rows_per_block && t < m + n; t += 4) {
-        const bool on_u = t < m;
-        float* x = on_u ? U + t * ldu + j : V + (t - m) * ldv + j;
-        const int64_t ps = on_u ? ups : vps;
-        const double x0 = x[0], x1 = x[ps], x2 = x[2 * ps], x3 = x[3 * ps];
-        x[0] = (float)(x0 * p0 - x1 * p1 - x2 * p2 - x3 * p3);
-        x[ps] = (float)(x0 * p1 + x1 * p0 + x2 * p3 - x3 * p2);
-        x[2 * ps] = (float)(x0 * p2 - x1 * p3 + x2 * p0 + x3 * p1);
-        x[3 * ps] = (float)(x0 * p3 + x1 * p2 - x2 * p1 + x3 * p0);
+    // RPT rows per thread (rows t0 + rs + 4 u of U, then of V): all loads, then all stores
+    const int64_t t0 = (int64_t)blockIdx.x * 4 * RPT;
+    float xv[RPT][4];
+#pragma unroll
+    for (int u = 0; u < RPT; u++) {
+        const int64_t t = t0 + rs + 4 * u;
+        if (t < m + n) {
+            const bool on_u = t < m;
+            const float* x = on_u ? U + t * ldu + j : V + (t - m) * ldv + j;
+            const int64_t ps = on_u ? ups : vps;
+            xv[u][0] = x[0]; xv[u][1] = x[ps]; xv[u][2] = x[2 * ps]; xv[u][3] = x[3 * ps];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < RPT; u++) {
+        const int64_t t = t0 + rs + 4 * u;
+        if (t < m + n) {
+            const bool on_u = t < m;
+            float* x = on_u ? U + t * ldu + j : V + (t - m) * ldv + j;
+            const int64_t ps = on_u ? ups : vps;
+            const double x0 = xv[u][0], x1 = xv[u][1], x2 = xv[u][2], x3 = xv[u][3];
+            x[0] = (float)(x0 * p0 - x1 * p1 - x2 * p2 - x3 * p3);
+            x[ps] = (float)(x0 * p1 + x1 * p0 + x2 * p3 - x3 * p2);
+            x[2 * ps] = (float)(x0 * p2 - x1 * p3 + x2 * p0 + x3 * p1);
+            x[3 * ps] = (float)(x0 * p3 + x1 * p2 - x2 * p1 + x3 * p0);
+        }
     }
 }
 
@@ -370,9 +400,10 @@ hipError_t phase_launch(float* U, int64_t m, int64_t ldu, int64_t ups, float* V,
     const unsigned gyc = (unsigned)((k + 63) / 64);
     PhasePart* part = (PhasePart*)work;
     hipLaunchKernelGGL(k_phase_part, dim3((unsigned)nparts, gyc), dim3(256), 0, st, V, n, ldv, vps, k, rp, part);
-    const int64_t rb = 64;
-    hipLaunchKernelGGL(k_phase_apply, dim3((unsigned)((m + n + rb - 1) / rb), gyc), dim3(256), 0, st, U, m, ldu, ups,
-                       V, n, ldv, vps, k, (const PhasePart*)part, (int)nparts, rb);
+    constexpr int kRpt = 4;                      // rows per thread; 16 rows per workgroup
+    const int64_t rb = 4 * kRpt;
+    hipLaunchKernelGGL(k_phase_apply<kRpt>, dim3((unsigned)((m + n + rb - 1) / rb), gyc), dim3(256), 0, st, U, m, ldu,
+                       ups, V, n, ldv, vps, k, (const PhasePart*)part, (int)nparts);
     return hipGetLastError();
 }
 
