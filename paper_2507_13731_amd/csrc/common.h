@@ -142,7 +142,9 @@ hipError_t copy_planes_launch(const float* src, int64_t lds, int64_t sps, float*
 hipError_t copy_f64_launch(const double* src, double* dst, int64_t count, hipStream_t st);
 // p[0..count) = value.
 hipError_t fill_int_launch(int* p, int64_t count, int value, hipStream_t st);
-hipError_t fill_u32_launch(unsigned* p, int64_t count, hipStream_t st);
+// status[0 .. nstatus) = 0, counters[0 .. ncnt) = 0 and *nan_at = NaN (if nan_at) in one launch.
+hipError_t solve_prologue_launch(int* status, int nstatus, unsigned* counters, int64_t ncnt, double* nan_at,
+                                 hipStream_t st);
 
 // One-sided Jacobi QSVD of X (w x w FP64 planes): S descending, U = left vectors, V right
 // vectors (if want_vectors).  work: 8*w*w + 2*w doubles.
@@ -184,7 +186,6 @@ hipError_t heig_with_estimates_launch(const double* G, int64_t gstride, int64_t 
 
 // e = sqrt(max(0, nA2 - sum_{j<k} S_j^2) / nA2)
 hipError_t estimate_launch(const double* S, int k, const double* nA2, double* e, hipStream_t st);
-hipError_t nan_launch(double* e, hipStream_t st);
 
 // ||A||_F^2 (FP64) into *out; partial: 1024 doubles.
 // ||A||_F^2 = the sum, in order, of nb partial sums (deterministic)

@@ -641,12 +641,11 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
     const bool fro_apart = b.Alo || pr.transpose;
     c.fro_next = !fro_apart;
     if (c.live()) {
-        note(c, fill_int_launch(b.status, 16, 0, c.st));
-        note(c, fill_u32_launch(b.counters, (int64_t)std::max<size_t>(c.cnt_need, 1), c.st));
+        note(c, solve_prologue_launch(b.status, 16, b.counters, (int64_t)std::max<size_t>(c.cnt_need, 1),
+                                      pr.estimate ? pr.pass_err : nullptr, c.st));
         if (fro_apart) note(c, fro2_launch(pr.A, pr.mr, pr.nr, pr.lda, pr.aps, b.fro_part, b.nA2, c.st));
         if (pr.sketch == QLRA_SKETCH_SRHT) note(c, omega_srht_launch(pr.seed, pr.n, l, b.Om, l, pr.n * l, c.st));
         else note(c, omega_launch(pr.seed, pr.n, l, b.Om, l, pr.n * l, c.st, pr.sketch == QLRA_SKETCH_REAL ? 1 : 0));
-        if (pr.estimate) note(c, nan_launch(pr.pass_err, c.st));
         if (b.Alo) {
             note(c, lowp_scale_launch(b.nA2, pr.prec, b.lp_scale, b.lp_scale + 1, c.st));
             note(c, lowp_copy_launch(pr.A, pr.mr, pr.nr, pr.lda, pr.aps, pr.prec, b.Alo, b.Alo_t, b.lp_scale, c.st,
@@ -1447,8 +1446,7 @@ int qlra_cholqr(const float* Y, int64_t m, int64_t w, int64_t ldy, int64_t y_ps,
     Ctx c;
     c.st = (hipStream_t)stream;
     cholqr_carve(m, w, ar, c, part, cnt);
-    note(c, fill_int_launch(c.status, 16, 0, c.st));
-    note(c, fill_u32_launch(c.scr.counters, (int64_t)std::max<size_t>(cnt, 1), c.st));
+    note(c, solve_prologue_launch(c.status, 16, c.scr.counters, (int64_t)std::max<size_t>(cnt, 1), nullptr, c.st));
     cholqr(c, Y, m, w, ldy, y_ps, Q, ldq, q_ps, R, 2);
     return c.err == hipSuccess ? QLRA_OK : QLRA_E_HIP;
 }

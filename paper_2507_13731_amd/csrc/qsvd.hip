@@ -160,10 +160,6 @@ __global__ void k_estimate(const double* S, int k, const double* nA2, double* e)
     *e = a > 0.0 ? sqrt((r > 0.0 ? r : 0.0) / a) : 0.0;
 }
 
-__global__ void k_nan(double* e) {
-    if (threadIdx.x == 0) *e = __builtin_nan("");
-}
-
 // ||A||_F^2: block b sums rows [b*rows_per, ...) of all four planes in FP64.
 __global__ __launch_bounds__(256) void k_fro2_part(const float* __restrict__ A, int64_t m, int64_t n,
                                                    int64_t lda, int64_t aps, int64_t rows_per,
@@ -366,10 +362,6 @@ hipError_t estimate_launch(const double* S, int k, const double* nA2, double* e,
     return hipGetLastError();
 }
 
-hipError_t nan_launch(double* e, hipStream_t st) {
-    hipLaunchKernelGGL(k_nan, dim3(1), dim3(64), 0, st, e);
-    return hipGetLastError();
-}
 
 hipError_t fro2_launch(const float* A, int64_t m, int64_t n, int64_t lda, int64_t aps, double* partial,
                        double* out, hipStream_t st) {

@@ -1,5 +1,7 @@
 // Element-wise helpers: gated plane copies and fills used instead of memsets (they stay valid
 // inside captured HIP graphs).
+#include <algorithm>
+
 #include "common.h"
 
 namespace qlra_impl {
@@ -29,9 +31,14 @@ __global__ __launch_bounds__(256) void k_fill_int(int* p, int64_t count, int val
     if (e < count) p[e] = value;
 }
 
-__global__ __launch_bounds__(256) void k_fill_u32(unsigned* p, int64_t count) {
+// The set-up of a solve in one launch: status words and counters cleared, *nan_at (if given)
+// set to NaN.
+__global__ __launch_bounds__(256) void k_solve_prologue(int* status, int nstatus, unsigned* counters, int64_t ncnt,
+                                                        double* nan_at) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < count) p[e] = 0u;
+    if (e < nstatus) status[e] = 0;
+    if (e < ncnt) counters[e] = 0u;
+    if (e == 0 && nan_at) *nan_at = __builtin_nan("");
 }
 
 }  // namespace
@@ -59,9 +66,11 @@ hipError_t fill_int_launch(int* p, int64_t count, int value, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t fill_u32_launch(unsigned* p, int64_t count, hipStream_t st) {
-    if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, p, count);
+hipError_t solve_prologue_launch(int* status, int nstatus, unsigned* counters, int64_t ncnt, double* nan_at,
+                                 hipStream_t st) {
+    const int64_t n = std::max<int64_t>(std::max<int64_t>(nstatus, ncnt), 1);
+    hipLaunchKernelGGL(k_solve_prologue, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, status, nstatus, counters,
+                       ncnt, nan_at);
     return hipGetLastError();
 }
 
