@@ -162,9 +162,10 @@ hipError_t qsvd_gram_launch(const double* X, int64_t w, double* U, double* S, do
                             hipStream_t st);
 size_t qsvd_gram_work_doubles(int64_t w);
 // S_j = sqrt(max(lam_j, 0)) (j < k) and, when E is given, Wk = E[:, :k] diag(1 / S) (w x k FP64
-// planes, ld k), from lam (descending) and E (w x >= k, ld lde) of a Gram's eigendecomposition.
+// planes, ld k), from lam (descending) and E (w x >= k, ld lde) of a Gram's eigendecomposition;
+// with est also *est = sqrt(max(0, *nA2 - sum_{j<k} S_j^2) / *nA2) (as estimate_launch).
 hipError_t svals_launch(const double* lam, const double* E, int64_t lde, int64_t w, int k, double* S, double* Wk,
-                        hipStream_t st);
+                        hipStream_t st, const double* nA2 = nullptr, double* est = nullptr);
 // Larger orders (up to heig_big_max()): lam (W, descending) and, if E, the nout eigenvectors of
 // the largest eigenvalues (W x nout, ld nout).  work: heig_big_work_doubles(W, nvec) doubles with
 // nvec >= nout vector slots (0 without vectors).

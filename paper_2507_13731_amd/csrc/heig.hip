@@ -605,9 +605,20 @@ __global__ __launch_bounds__(256) void k_left_vectors(const double* __restrict__
 // S_j = sqrt(max(lam_j, 0)) and W = E_k diag(1 / S) (w x k, ld k; zero columns where S_j = 0).
 __global__ __launch_bounds__(256) void k_svals(const double* __restrict__ lam, const double* __restrict__ E,
                                                int64_t lde, int w, int k, double* __restrict__ S,
-                                               double* __restrict__ Wk) {
+                                               double* __restrict__ Wk, const double* __restrict__ nA2,
+                                               double* __restrict__ est) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < k) S[e] = sqrt(fmax(lam[e], 0.0));
+    if (est && e == 0) {
+        // the estimate of this pass, sqrt(max(0, ||A||^2 - sum_{j<k} S_j^2) / ||A||^2)
+        double top = 0.0;
+        for (int j = 0; j < k; j++) {
+            const double sj = sqrt(fmax(lam[j], 0.0));
+            top += sj * sj;
+        }
+        const double a = *nA2, r = a - top;
+        *est = a > 0.0 ? sqrt((r > 0.0 ? r : 0.0) / a) : 0.0;
+    }
     if (!E || e >= (int64_t)w * k) return;
     const int i = (int)(e / k), j = (int)(e % k);
     const double sj = sqrt(fmax(lam[j], 0.0));
@@ -706,9 +717,10 @@ hipError_t qsvd_gram_launch(const double* X, int64_t w, double* U, double* S, do
 }
 
 hipError_t svals_launch(const double* lam, const double* E, int64_t lde, int64_t w, int k, double* S, double* Wk,
-                        hipStream_t st) {
+                        hipStream_t st, const double* nA2, double* est) {
     const int64_t n = std::max<int64_t>(w * k, k);
-    hipLaunchKernelGGL(k_svals, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, lam, E, lde, (int)w, k, S, Wk);
+    hipLaunchKernelGGL(k_svals, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, lam, E, lde, (int)w, k, S, Wk,
+                       nA2, est);
     return hipGetLastError();
 }
 

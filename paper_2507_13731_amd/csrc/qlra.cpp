@@ -526,8 +526,7 @@ void fork_estimates(Ctx& c, const Bufs& b, const Problem& pr, int64_t l) {
     }
     for (int i = 0; i < pr.v - 2; i++) {
         note(c, heig_big_launch(b.Gs + (size_t)i * 4 * l * l, l, b.side_lam, nullptr, 0, b.est_work, 0, c.side));
-        note(c, svals_launch(b.side_lam, nullptr, 0, l, pr.k, b.side_S, nullptr, c.side));
-        note(c, estimate_launch(b.side_S, pr.k, b.nA2, pr.pass_err + 1 + i, c.side));
+        note(c, svals_launch(b.side_lam, nullptr, 0, l, pr.k, b.side_S, nullptr, c.side, b.nA2, pr.pass_err + 1 + i));
     }
 }
 
@@ -582,8 +581,8 @@ void finish_gram(Ctx& c, const Bufs& b, const Problem& pr, const float* Y, int64
                                                b.est_work, c.st));
         else if (big) note(c, heig_big_launch(c.G, w, b.Sw, b.Rh, k, b.big_work, big_nvec(w, k), c.st));
         else note(c, heig_launch(c.G, w, b.Sw, b.Rh, b.qsvd_work, c.st));
-        note(c, svals_launch(b.Sw, b.Rh, lde, w, k, pr.S, b.Lh, c.st));
-        if (pr.estimate) note(c, estimate_launch(pr.S, k, b.nA2, pr.pass_err + (pr.v - 1), c.st));
+        note(c, svals_launch(b.Sw, b.Rh, lde, w, k, pr.S, b.Lh, c.st, b.nA2,
+                             pr.estimate ? pr.pass_err + (pr.v - 1) : nullptr));
     }
     float* Oy = y_is_u ? pr.U : pr.V;
     float* Ox = y_is_u ? pr.V : pr.U;
