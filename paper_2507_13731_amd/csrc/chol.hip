@@ -172,6 +172,18 @@ __global__ __launch_bounds__(kThreads) void k_chol_lds(const double* __restrict_
     }
 }
 
+// c ? a : b, component by component (a select of values, kept in registers)
+__device__ __forceinline__ Q4 qsel(bool c, Q4 a, Q4 b) {
+    return Q4{c ? a.w : b.w, c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z};
+}
+// acc - a b (eq. (1)), as four chains of fused multiply-adds into acc
+__device__ __forceinline__ Q4 qfms(Q4 acc, Q4 a, Q4 b) {
+    return Q4{fma(a.z, b.z, fma(a.y, b.y, fma(a.x, b.x, fma(-a.w, b.w, acc.w)))),
+              fma(a.z, b.y, fma(-a.y, b.z, fma(-a.x, b.w, fma(-a.w, b.x, acc.x)))),
+              fma(-a.z, b.x, fma(-a.y, b.w, fma(a.x, b.z, fma(-a.w, b.y, acc.y)))),
+              fma(-a.z, b.w, fma(a.y, b.x, fma(-a.x, b.y, fma(-a.w, b.z, acc.z))))};
+}
+
 // upper triangle of order w packed by rows: (t, c), c >= t
 __device__ __forceinline__ int upk(int t, int c, int w) { return t * (2 * w - t + 1) / 2 + (c - t); }
 // ------------------------------------------------------------------------------------------
@@ -306,8 +318,8 @@ __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict_
                     if (ci < ri) continue;
                     const int b = tx + 32 * ci;
                     if (b < a || b >= w) continue;
-                    Q4 v = qsub(g[ri][ci], qmul(rja[ri], rjb[ci]));
-                    if (a == b) v.x = v.y = v.z = 0.0;
+                    Q4 v = qfms(g[ri][ci], rja[ri], rjb[ci]);
+                    if (ri == ci && a == b) v.x = v.y = v.z = 0.0;
                     g[ri][ci] = v;
                 }
             }
@@ -371,18 +383,6 @@ __device__ __forceinline__ Q4 ldr(const double* sR, int i) {
     const d2 lo = reinterpret_cast<const d2*>(sR)[2 * i], hi = reinterpret_cast<const d2*>(sR)[2 * i + 1];
     return Q4{lo[0], lo[1], hi[0], hi[1]};
 }
-// c ? a : b, component by component (a select of values, kept in registers)
-__device__ __forceinline__ Q4 qsel(bool c, Q4 a, Q4 b) {
-    return Q4{c ? a.w : b.w, c ? a.x : b.x, c ? a.y : b.y, c ? a.z : b.z};
-}
-// acc - a b (eq. (1)), as four chains of fused multiply-adds into acc
-__device__ __forceinline__ Q4 qfms(Q4 acc, Q4 a, Q4 b) {
-    return Q4{fma(a.z, b.z, fma(a.y, b.y, fma(a.x, b.x, fma(-a.w, b.w, acc.w)))),
-              fma(a.z, b.y, fma(-a.y, b.z, fma(-a.x, b.w, fma(-a.w, b.x, acc.x)))),
-              fma(-a.z, b.x, fma(-a.y, b.w, fma(a.x, b.z, fma(-a.w, b.y, acc.y)))),
-              fma(-a.z, b.w, fma(a.y, b.x, fma(-a.x, b.y, fma(-a.w, b.z, acc.z))))};
-}
-
 // columns t = 16 TB + TT of the substitution: q_t = acc_t / r_tt on lane TT, broadcast over the
 // row's 16 lanes, then acc_c -= q_t r_tc for the later columns c > t.  Branch-free, so that the
 // LDS reads of a step are issued together: the later blocks (u > TB) update every lane (lanes
