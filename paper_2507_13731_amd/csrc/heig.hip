@@ -51,6 +51,19 @@ __device__ __forceinline__ Q4 qadd(Q4 a, Q4 b) { return Q4{a.w + b.w, a.x + b.x,
 __device__ __forceinline__ Q4 qsub(Q4 a, Q4 b) { return Q4{a.w - b.w, a.x - b.x, a.y - b.y, a.z - b.z}; }
 __device__ __forceinline__ Q4 qscale(Q4 a, double s) { return Q4{a.w * s, a.x * s, a.y * s, a.z * s}; }
 __device__ __forceinline__ double qn2(Q4 a) { return a.w * a.w + a.x * a.x + a.y * a.y + a.z * a.z; }
+// acc + a b and acc - a b (eq. (1)) as four chains of fused multiply-adds into acc
+__device__ __forceinline__ Q4 qfma(Q4 acc, Q4 a, Q4 b) {
+    return Q4{fma(-a.z, b.z, fma(-a.y, b.y, fma(-a.x, b.x, fma(a.w, b.w, acc.w)))),
+              fma(-a.z, b.y, fma(a.y, b.z, fma(a.x, b.w, fma(a.w, b.x, acc.x)))),
+              fma(a.z, b.x, fma(a.y, b.w, fma(-a.x, b.z, fma(a.w, b.y, acc.y)))),
+              fma(a.z, b.w, fma(-a.y, b.x, fma(a.x, b.y, fma(a.w, b.z, acc.z))))};
+}
+__device__ __forceinline__ Q4 qfms(Q4 acc, Q4 a, Q4 b) {
+    return Q4{fma(a.z, b.z, fma(a.y, b.y, fma(a.x, b.x, fma(-a.w, b.w, acc.w)))),
+              fma(a.z, b.y, fma(-a.y, b.z, fma(-a.x, b.w, fma(-a.w, b.x, acc.x)))),
+              fma(-a.z, b.x, fma(-a.y, b.w, fma(a.x, b.z, fma(-a.w, b.y, acc.y)))),
+              fma(-a.z, b.w, fma(a.y, b.x, fma(-a.x, b.y, fma(-a.w, b.z, acc.z))))};
+}
 __device__ __forceinline__ double qdot(Q4 a, Q4 b) { return a.w * b.w + a.x * b.x + a.y * b.y + a.z * b.z; }
 
 // quaternion vectors stored as four planes of stride S
@@ -203,7 +216,7 @@ void k_tridiag(const double* __restrict__ Gall, int64_t gstride, int w, double* 
 #pragma unroll
             for (int kk = 0; kk < NCOL; kk++) {
                 if (LPR * kk + LPR - 1 <= j) continue;          // v vanishes there
-                acc = qadd(acc, qmul(g[kk], ldq<kW>(vbj, s + LPR * kk)));
+                acc = qfma(acc, g[kk], ldq<kW>(vbj, s + LPR * kk));
             }
             acc.w = lpr_sum<LPR>(acc.w); acc.x = lpr_sum<LPR>(acc.x);
             acc.y = lpr_sum<LPR>(acc.y); acc.z = lpr_sum<LPR>(acc.z);
@@ -235,7 +248,7 @@ void k_tridiag(const double* __restrict__ Gall, int64_t gstride, int w, double* 
                 const Q4 vc = ldq<kW>(vbj, c);
                 const Q4 qc = qsub(ldq<kW>(pbj, c), qscale(vc, K));
                 if (row_live && c > j && c < w) {
-                    Q4 t = qsub(qsub(g[kk], qmul(vr, qconj(qc))), qmul(qr, qconj(vc)));
+                    Q4 t = qfms(qfms(g[kk], vr, qconj(qc)), qr, qconj(vc));
                     if (r == c) t.x = t.y = t.z = 0.0;
                     g[kk] = t;
                 }
@@ -515,11 +528,11 @@ __global__ __launch_bounds__(ET) void k_eigvecs(const double* __restrict__ tri, 
             vn2 = rv(i2, j - 1);
         }
         const double tj = L.tau[j];
-        Q4 s = qadd(qmul(qconj(v), y), qmul(qconj(v2), y2));
+        Q4 s = qfma(qmul(qconj(v), y), qconj(v2), y2);
         s.w = wave_total(s.w); s.x = wave_total(s.x); s.y = wave_total(s.y); s.z = wave_total(s.z);
         s = qscale(s, tj);
-        y = qsub(y, qmul(v, s));
-        y2 = qsub(y2, qmul(v2, s));
+        y = qfms(y, v, s);
+        y2 = qfms(y2, v2, s);
     }
     const int64_t gps = (int64_t)w * w;
     const int col = w - 1 - k;
