@@ -356,3 +356,22 @@ def test_srht_sketch_solve_shapes(gq, oracle, m, n, transpose, prec):
     d = ahat_diff(A64, (Ug, Sg, Vg), (Uo, So, Vo))
     print(f"  ahat diff {d:.3e}", flush=True)
     assert d <= (1e-5 if prec == 0 else 1e-2)
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_phase_convention_tall(gq, oracle, scheme):
+    """The phase normalisation of the returned factors: in every column of V the entry of largest
+    modulus is real and positive.  n = 3000 rows give 94 partial arg-maxes per column, several
+    batches of the apply pass's scan; the factors also match the oracle's (same rule)."""
+    m, n, k = 400, 3000, 8
+    print(f"phase convention {m} x {n} scheme={scheme}", flush=True)
+    A32 = (W.planted(81, m, n, k) + 1e-3 * W.random_quat(82, m, n)).astype(np.float32)
+    Ug, Sg, Vg, _, st = run_gpu(gq, A32, k, 4, 3, scheme, 2)
+    assert st == gq.QLRA_OK
+    mod = (Vg ** 2).sum(axis=0)
+    for j in range(k):
+        q = Vg[:, int(np.argmax(mod[:, j])), j]
+        assert q[0] > 0.0 and np.abs(q[1:]).max() <= 1e-6 * q[0], (j, q)
+    Uo, So, Vo, _ = oracle.qlra(A32.astype(np.float64), k, 4, 3, scheme, 2)
+    assert np.abs(Vg - Vo).max() < 1e-4
+    assert np.abs(Ug - Uo).max() < 1e-4
