@@ -227,6 +227,18 @@ __device__ __forceinline__ void sqrt_rsqrt(double d, double& s, double& r) {
     s = d * y;
 }
 
+// the pivot row in LDS with the four components of an entry side by side (two 16-byte accesses)
+__device__ __forceinline__ void sti(double* p, int i, Q4 v) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    reinterpret_cast<d2*>(p)[2 * i] = d2{v.w, v.x};
+    reinterpret_cast<d2*>(p)[2 * i + 1] = d2{v.y, v.z};
+}
+__device__ __forceinline__ Q4 ldi(const double* p, int i) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 lo = reinterpret_cast<const d2*>(p)[2 * i], hi = reinterpret_cast<const d2*>(p)[2 * i + 1];
+    return Q4{lo[0], lo[1], hi[0], hi[1]};
+}
+
 // Right-looking Cholesky G + shift I = R^H R (R upper triangular with real positive diagonal):
 // step j scales row j by 1 / r_jj (the half wave that owns row j, double-buffered row in LDS),
 // then every owner of an entry (a, b), j < a <= b, subtracts conj(r_ja) r_jb.
@@ -239,7 +251,7 @@ __device__ __forceinline__ void chol_row(Q4 (&g)[NB][NB], int j, int w, int tx, 
         else if (c > j && c < w) {
             const Q4 r = qscale(g[H][ci], inv);
             g[H][ci] = r;
-            stp<kRegMax>(rb, c, r);
+            sti(rb, c, r);
         }
     }
 }
@@ -258,7 +270,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict_
                                                         double* __restrict__ Rpk, int* status, int* shift_out,
                                                         const int* gate, int allow_shift, double shift_scale) {
     constexpr int kFlag = 4 * kRegMax;                 // breakdown flag behind the pivot row
-    __shared__ double rowb[2][4 * kRegMax + 1];
+    __shared__ __attribute__((aligned(16))) double rowb[2][4 * kRegMax + 2];
     if (gate && *gate == 0) return;
     const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
     const int64_t ps = (int64_t)w * w;
@@ -305,8 +317,8 @@ __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict_
             Q4 rja[NB], rjb[NB];
 #pragma unroll
             for (int i = 0; i < NB; i++) {
-                rja[i] = qconj(ldp<kRegMax>(rb, ty + 32 * i));
-                rjb[i] = ldp<kRegMax>(rb, tx + 32 * i);
+                rja[i] = qconj(ldi(rb, ty + 32 * i));
+                rjb[i] = ldi(rb, tx + 32 * i);
             }
             if (rb[kFlag] != 0.0) { fail = true; break; }    // uniform
 #pragma unroll
