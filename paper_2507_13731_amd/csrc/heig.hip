@@ -74,6 +74,29 @@ __device__ __forceinline__ void stq(double* p, int i, Q4 v) {
     p[i] = v.w; p[S + i] = v.x; p[2 * S + i] = v.y; p[3 * S + i] = v.z;
 }
 
+// quaternion vectors with the four components of an entry side by side (16-byte aligned)
+__device__ __forceinline__ void sti(double* p, int i, Q4 v) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    reinterpret_cast<d2*>(p)[2 * i] = d2{v.w, v.x};
+    reinterpret_cast<d2*>(p)[2 * i + 1] = d2{v.y, v.z};
+}
+__device__ __forceinline__ Q4 ldi(const double* p, int i) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 lo = reinterpret_cast<const d2*>(p)[2 * i], hi = reinterpret_cast<const d2*>(p)[2 * i + 1];
+    return Q4{lo[0], lo[1], hi[0], hi[1]};
+}
+
+template <bool SIDE>
+__device__ __forceinline__ Q4 ldv(const double* p, int i) {
+    if constexpr (SIDE) return ldi(p, i);
+    else return ldq<kW>(p, i);
+}
+template <bool SIDE>
+__device__ __forceinline__ void stv(double* p, int i, Q4 v) {
+    if constexpr (SIDE) sti(p, i, v);
+    else stq<kW>(p, i, v);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -143,14 +166,18 @@ void k_tridiag(const double* __restrict__ Gall, int64_t gstride, int w, double* 
     static_assert(NT / LPR == LPR * NCOL, "the thread grid covers a square of rows x columns");
     constexpr int RPW = 64 / LPR;           // rows per wave
     constexpr int TW = NT / 64;             // waves
-    __shared__ double xb[4 * kW];           // column j below the diagonal
-    __shared__ double vb[2][4 * kW];        // reflector v (zero outside rows j+1 .. w-1)
-    __shared__ double pb[2][4 * kW];        // p = tau G v
+    // x (column j below the diagonal), v (the reflector, zero outside rows j+1 .. w-1) and
+    // p = tau G v; in the 1024-thread form the four components of an entry lie side by side
+    // (two 16-byte accesses), the 768-thread form keeps planes (its registers are full)
+    __shared__ __attribute__((aligned(16))) double xb[4 * kW];
+    __shared__ __attribute__((aligned(16))) double vb[2][4 * kW];
+    __shared__ __attribute__((aligned(16))) double pb[2][4 * kW];
     __shared__ double kr[2][TW];            // per-wave shares of v^H p
     __shared__ double tb[2];
     __shared__ double sq[4 * kW];           // quaternion subdiagonal s_j
     __shared__ double dg[kW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    constexpr bool kSide = NCOL <= 4;
     const int r = tid / LPR, s = tid % LPR;
     const double* G = Gall + (int64_t)blockIdx.x * gstride;
     double* tri = triall + (int64_t)blockIdx.x * kTriStride;
@@ -180,7 +207,7 @@ void k_tridiag(const double* __restrict__ Gall, int64_t gstride, int w, double* 
                 for (int kk = 0; kk < NCOL; kk++) {
                     const int c = s + LPR * kk;
                     if (LPR * kk + LPR - 1 <= j) continue;     // uniform
-                    if (c > j && c < w) stq<kW>(xb, c, qconj(g[kk]));
+                    if (c > j && c < w) stv<kSide>(xb, c, qconj(g[kk]));
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -188,18 +215,18 @@ void k_tridiag(const double* __restrict__ Gall, int64_t gstride, int w, double* 
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             // lane handles entries lane and lane + 64
             const int c1 = lane + 64;
-            const Q4 x = (lane > j && lane < w) ? ldq<kW>(xb, lane) : Q4{0, 0, 0, 0};
-            const Q4 x2 = (c1 > j && c1 < w) ? ldq<kW>(xb, c1) : Q4{0, 0, 0, 0};
+            const Q4 x = (lane > j && lane < w) ? ldv<kSide>(xb, lane) : Q4{0, 0, 0, 0};
+            const Q4 x2 = (c1 > j && c1 < w) ? ldv<kSide>(xb, c1) : Q4{0, 0, 0, 0};
             const double alpha = sqrt(wave_total(qn2(x) + qn2(x2)));
-            const Q4 x1 = ldq<kW>(xb, j + 1);
+            const Q4 x1 = ldv<kSide>(xb, j + 1);
             const double ax1 = sqrt(qn2(x1));
             const Q4 phi = ax1 > 0.0 ? qscale(x1, 1.0 / ax1) : Q4{1, 0, 0, 0};
             const double tau = alpha > 0.0 ? 1.0 / (alpha * (alpha + ax1)) : 0.0;
             Q4 v = x, v2 = x2;
             if (lane == j + 1) v = qadd(x, qscale(phi, alpha));   // H x = -alpha phi e_1
             if (c1 == j + 1) v2 = qadd(x2, qscale(phi, alpha));
-            stq<kW>(vbj, lane, v);
-            if (c1 < kW) stq<kW>(vbj, c1, v2);
+            stv<kSide>(vbj, lane, v);
+            if (c1 < kW) stv<kSide>(vbj, c1, v2);
             if (store_refl && lane > j && lane < w) stq<kPacked>(tri + OFF_REFL, lane * (lane + 1) / 2 + j, v);
             if (store_refl && c1 > j && c1 < w) stq<kPacked>(tri + OFF_REFL, c1 * (c1 + 1) / 2 + j, v2);
             if (lane == 0) {
@@ -216,15 +243,15 @@ void k_tridiag(const double* __restrict__ Gall, int64_t gstride, int w, double* 
 #pragma unroll
             for (int kk = 0; kk < NCOL; kk++) {
                 if (LPR * kk + LPR - 1 <= j) continue;          // v vanishes there
-                acc = qfma(acc, g[kk], ldq<kW>(vbj, s + LPR * kk));
+                acc = qfma(acc, g[kk], ldv<kSide>(vbj, s + LPR * kk));
             }
             acc.w = lpr_sum<LPR>(acc.w); acc.x = lpr_sum<LPR>(acc.x);
             acc.y = lpr_sum<LPR>(acc.y); acc.z = lpr_sum<LPR>(acc.z);
             const Q4 p = qscale(acc, tau);
             double kp = 0.0;
             if (s == 0 && r < w) {
-                stq<kW>(pbj, r, p);
-                if (r > j) kp = qdot(ldq<kW>(vbj, r), p);
+                stv<kSide>(pbj, r, p);
+                if (r > j) kp = qdot(ldv<kSide>(vbj, r), p);
             }
             double ks = 0.0;
 #pragma unroll
@@ -239,14 +266,14 @@ void k_tridiag(const double* __restrict__ Gall, int64_t gstride, int w, double* 
             for (int q = s; q < TW; q += LPR) kq += kr[bsel][q];
             const double K = 0.5 * tau * lpr_sum<LPR>(kq);
             const bool row_live = r > j && r < w;
-            const Q4 vr = ldq<kW>(vbj, r);
-            const Q4 qr = qsub(ldq<kW>(pbj, r), qscale(vr, K));
+            const Q4 vr = ldv<kSide>(vbj, r);
+            const Q4 qr = qsub(ldv<kSide>(pbj, r), qscale(vr, K));
 #pragma unroll
             for (int kk = 0; kk < NCOL; kk++) {
                 const int c = s + LPR * kk;
                 if (LPR * kk + LPR - 1 <= j) continue;          // uniform
-                const Q4 vc = ldq<kW>(vbj, c);
-                const Q4 qc = qsub(ldq<kW>(pbj, c), qscale(vc, K));
+                const Q4 vc = ldv<kSide>(vbj, c);
+                const Q4 qc = qsub(ldv<kSide>(pbj, c), qscale(vc, K));
                 if (row_live && c > j && c < w) {
                     Q4 t = qfms(qfms(g[kk], vr, qconj(qc)), qr, qconj(vc));
                     if (r == c) t.x = t.y = t.z = 0.0;
