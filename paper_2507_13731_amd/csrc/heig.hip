@@ -415,7 +415,7 @@ struct VecLds {
     double ph[4 * kW];
     double dg[kW], b[kW], b2[kW], lam[kW], tau[kW];
     double X[kW * kW];        // eigenvectors of T, ascending index k at X + k * kW
-    double dm[kW * kW];       // backward pivots of the twisted factorisations
+    alignas(16) double dm[kW * kW];   // backward pivots of the twisted factorisations; then staging
     double bnd[2];
 };
 
@@ -534,33 +534,53 @@ __global__ __launch_bounds__(ET) void k_eigvecs(const double* __restrict__ tri, 
     }
     __syncthreads();
     // back-transformation y = H_0 ... H_{w-3} D x: one wave per eigenvector, lane i holding rows
-    // i and i + 64; the reflectors are read from the record (L2), the next step's while the
-    // current one is applied
+    // i and i + 64.  The reflectors come from the record (written by another workgroup) in chunks
+    // of kChunk steps, loaded by the whole workgroup into LDS (the backward pivots' space, dead
+    // by now) with many loads in flight, then applied from LDS.
     const int k = k0 + wave;
-    if (k >= k1) return;                                   // uniform per wave
+    const bool act = k < k1;                               // uniform per wave
     const int i = lane, i2 = lane + 64;
     Q4 y{0, 0, 0, 0}, y2{0, 0, 0, 0};
-    if (i < w) y = qscale(ldq<kW>(L.ph, i), L.X[k * kW + i]);
-    if (i2 < w) y2 = qscale(ldq<kW>(L.ph, i2), L.X[k * kW + i2]);
+    if (act && i < w) y = qscale(ldq<kW>(L.ph, i), L.X[k * kW + i]);
+    if (act && i2 < w) y2 = qscale(ldq<kW>(L.ph, i2), L.X[k * kW + i2]);
     const double* refl = tri + OFF_REFL;
-    auto rv = [&](int row, int j) {
-        return (row > j && row < w) ? ldq<kPacked>(refl, row * (row + 1) / 2 + j) : Q4{0, 0, 0, 0};
-    };
-    Q4 vn = w >= 3 ? rv(i, w - 3) : Q4{0, 0, 0, 0};
-    Q4 vn2 = w >= 3 ? rv(i2, w - 3) : Q4{0, 0, 0, 0};
-    for (int j = w - 3; j >= 0; j--) {
-        const Q4 v = vn, v2 = vn2;
-        if (j > 0) {
-            vn = rv(i, j - 1);
-            vn2 = rv(i2, j - 1);
+    constexpr int kChunk = 16;                             // kChunk x kW entries fit in L.dm
+    static_assert(4 * kChunk * kW <= kW * kW, "staging area");
+    double* stage = L.dm;
+    for (int jhi = w - 3; jhi >= 0; jhi -= kChunk) {
+        const int jlo = jhi - kChunk + 1 > 0 ? jhi - kChunk + 1 : 0;
+        const int n = (jhi - jlo + 1) * w;                 // entries (step jhi - t, row) at t * w + row
+        __syncthreads();                                   // the previous chunk is consumed
+        for (int base = tid; base < n; base += 4 * ET) {
+            Q4 t[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int e = base + u * ET;
+                const int jj = jhi - e / w, row = e % w;
+                t[u] = (e < n && row > jj) ? ldq<kPacked>(refl, row * (row + 1) / 2 + jj) : Q4{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int e = base + u * ET;
+                if (e < n) sti(stage, (e / w) * kW + e % w, t[u]);
+            }
         }
-        const double tj = L.tau[j];
-        Q4 s = qfma(qmul(qconj(v), y), qconj(v2), y2);
-        s.w = wave_total(s.w); s.x = wave_total(s.x); s.y = wave_total(s.y); s.z = wave_total(s.z);
-        s = qscale(s, tj);
-        y = qfms(y, v, s);
-        y2 = qfms(y2, v2, s);
+        __syncthreads();
+        if (act) {
+            for (int j = jhi; j >= jlo; j--) {
+                const int o = (jhi - j) * kW;
+                const Q4 v = i < w ? ldi(stage, o + i) : Q4{0, 0, 0, 0};
+                const Q4 v2 = i2 < w ? ldi(stage, o + i2) : Q4{0, 0, 0, 0};
+                const double tj = L.tau[j];
+                Q4 s = qfma(qmul(qconj(v), y), qconj(v2), y2);
+                s.w = wave_total(s.w); s.x = wave_total(s.x); s.y = wave_total(s.y); s.z = wave_total(s.z);
+                s = qscale(s, tj);
+                y = qfms(y, v, s);
+                y2 = qfms(y2, v2, s);
+            }
+        }
     }
+    if (!act) return;
     const int64_t gps = (int64_t)w * w;
     const int col = w - 1 - k;
     if (i < w) {
