@@ -268,12 +268,37 @@ __device__ __forceinline__ void chol_row_at(Q4 (&g)[NB][NB], int jh, int j, int 
 template <int NB>
 __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict__ G, int w, double* __restrict__ Rout,
                                                         double* __restrict__ Rpk, int* status, int* shift_out,
-                                                        const int* gate, int allow_shift, double shift_scale) {
+                                                        const int* gate, int allow_shift, double shift_scale,
+                                                        int* gate_out, double gate_tol) {
     constexpr int kFlag = 4 * kRegMax;                 // breakdown flag behind the pivot row
     __shared__ __attribute__((aligned(16))) double rowb[2][4 * kRegMax + 2];
     if (gate && *gate == 0) return;
     const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
     const int64_t ps = (int64_t)w * w;
+    if (gate_out) {
+        // the gate of a second CholeskyQR round, formed here: *gate_out = 1 when max |G - I|
+        // exceeds gate_tol or is not finite (then factor), else 0 (and nothing more to do)
+        __shared__ double gred[kThreads / 64];
+        double mx = 0.0;
+        for (int64_t e = tid; e < ps; e += kThreads) {
+            const Q4 v = ld4(G, ps, e);
+            const double d = (e / w == e % w) ? v.w - 1.0 : v.w;
+            const double a = fmax(fmax(fabs(d), fabs(v.x)), fmax(fabs(v.y), fabs(v.z)));
+            mx = (a > mx || a != a) ? a : mx;     // a NaN sticks
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double t = __shfl_xor(mx, o, 64);
+            mx = (t > mx || t != t) ? t : mx;
+        }
+        if ((tid & 63) == 0) gred[tid >> 6] = mx;
+        __syncthreads();
+        double m = gred[0];
+        for (int i = 1; i < kThreads / 64; i++) m = (gred[i] > m || gred[i] != gred[i]) ? gred[i] : m;
+        const int go = (m <= gate_tol) ? 0 : 1;
+        if (tid == 0) *gate_out = go;
+        if (!go) return;                           // uniform
+    }
     Q4 g[NB][NB];
     double shift = 0.0;
     int shifted = 0, failed = 0;
@@ -591,30 +616,6 @@ __global__ __launch_bounds__(256) void k_zero_f64(double* __restrict__ p, int64_
 
 // *gate = 1 when max |G - I| over the four planes exceeds tol (or is not finite), else 0: G is
 // the Gram Q^H Q of a basis after one CholeskyQR round.
-__global__ __launch_bounds__(256) void k_orth_gate(const double* __restrict__ G, int w, double tol, int* gate) {
-    __shared__ double red[4];
-    const int tid = threadIdx.x;
-    const int64_t ps = (int64_t)w * w;
-    double mx = 0.0;
-    for (int64_t e = tid; e < ps; e += 256) {
-        const Q4 v = ld4(G, ps, e);
-        const double d = (e / w == e % w) ? v.w - 1.0 : v.w;
-        const double a = fmax(fmax(fabs(d), fabs(v.x)), fmax(fabs(v.y), fabs(v.z)));
-        mx = (a > mx || a != a) ? a : mx;     // a NaN sticks
-    }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const double t = __shfl_xor(mx, o, 64);
-        mx = (t > mx || t != t) ? t : mx;
-    }
-    if ((tid & 63) == 0) red[tid >> 6] = mx;
-    __syncthreads();
-    if (tid == 0) {
-        double m = red[0];
-        for (int i = 1; i < 4; i++) m = (red[i] > m || red[i] != red[i]) ? red[i] : m;
-        *gate = (m <= tol) ? 0 : 1;
-    }
-}
 
 __global__ void k_flag_nonzero(int* dst, const int* src) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src != 0 ? 1 : 0;
@@ -626,14 +627,15 @@ int chol_lds_max() { return kLdsMax; }
 int chol_reg_max() { return kRegMax; }
 
 hipError_t chol_reg_launch(const double* G, int64_t w, double* R, double* Rpk, int* status, int* shift_out,
-                           const int* gate, int allow_shift, double shift_scale, hipStream_t st) {
+                           const int* gate, int allow_shift, double shift_scale, hipStream_t st, int* gate_out,
+                           double gate_tol) {
     if (w < 1 || w > kRegMax) return hipErrorInvalidValue;
     if (w <= 64)
         hipLaunchKernelGGL(k_chol_reg<2>, dim3(1), dim3(kThreads), 0, st, G, (int)w, R, Rpk, status, shift_out, gate,
-                           allow_shift, shift_scale);
+                           allow_shift, shift_scale, gate_out, gate_tol);
     else
         hipLaunchKernelGGL(k_chol_reg<3>, dim3(1), dim3(kThreads), 0, st, G, (int)w, R, Rpk, status, shift_out, gate,
-                           allow_shift, shift_scale);
+                           allow_shift, shift_scale, gate_out, gate_tol);
     return hipGetLastError();
 }
 
@@ -678,10 +680,6 @@ hipError_t zero_f64_launch(double* p, int64_t count, const int* gate, hipStream_
     return hipGetLastError();
 }
 
-hipError_t orth_gate_launch(const double* G, int64_t w, double tol, int* gate, hipStream_t st) {
-    hipLaunchKernelGGL(k_orth_gate, dim3(1), dim3(256), 0, st, G, (int)w, tol, gate);
-    return hipGetLastError();
-}
 
 hipError_t flag_nonzero_launch(int* dst, const int* src, hipStream_t st) {
     hipLaunchKernelGGL(k_flag_nonzero, dim3(1), dim3(64), 0, st, dst, src);

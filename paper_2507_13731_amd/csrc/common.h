@@ -117,14 +117,15 @@ hipError_t copy_f64_planes_launch(const double* src, int64_t lds, int64_t sps, d
 hipError_t zero_f64_launch(double* p, int64_t count, const int* gate, hipStream_t st);
 // *dst = (*src != 0).
 hipError_t flag_nonzero_launch(int* dst, const int* src, hipStream_t st);
-// *gate = 1 when max |G - I| (G: w x w FP64 planes) exceeds tol or is not finite, else 0.
-hipError_t orth_gate_launch(const double* G, int64_t w, double tol, int* gate, hipStream_t st);
 // Cholesky alone for w <= chol_reg_max(), factor to R (no inverse) and to Rpk, R's upper
 // triangle packed by rows with the four components of an entry side by side (4 w (w + 1) / 2
 // doubles, the input of trsm_launch); same status, shift and gate behaviour as chol_launch.
+// With gate_out, the kernel first sets *gate_out = 1 when max |G - I| exceeds gate_tol or is not
+// finite, else 0, and factors only when it is 1.
 int chol_reg_max();
 hipError_t chol_reg_launch(const double* G, int64_t w, double* R, double* Rpk, int* status, int* shift_out,
-                           const int* gate, int allow_shift, double shift_scale, hipStream_t st);
+                           const int* gate, int allow_shift, double shift_scale, hipStream_t st,
+                           int* gate_out = nullptr, double gate_tol = 0.0);
 // Q = Y R^{-1} (rows x w FP32 planes, Q may alias Y), R upper triangular FP64 given packed as
 // chol_reg_launch writes it, w <= chol_reg_max().
 hipError_t trsm_launch(const float* Y, int64_t ldy, int64_t yps, float* Q, int64_t ldq, int64_t qps,

@@ -192,13 +192,12 @@ void cholqr(Ctx& c, const float* Y, int64_t rows, int64_t w, int64_t ldy, int64_
         if (small) {
             // this round's own factor; the product R2 R1 is formed at the end when R is wanted
             double* Rr = (rounds == 1 && R) ? R : (round == 0 ? c.R1 : c.R2);
-            const int* g = (gated && round == 1) ? gate : nullptr;
+            int* g = (gated && round == 1) ? gate : nullptr;
             if (c.live()) {
-                if (g) note(c, orth_gate_launch(G, w, 1e-7, gate, c.st));
                 // the packed copy of the factor for the triangular solve goes to chol_work, which
-                // only the larger orders use otherwise
-                note(c, chol_reg_launch(G, w, Rr, c.chol_work, c.status, round == 0 ? shifted : nullptr, g,
-                                        round == 0 ? 1 : 0, shift_scale(rows, w), c.st));
+                // only the larger orders use otherwise; a gated round's Cholesky forms the gate
+                note(c, chol_reg_launch(G, w, Rr, c.chol_work, c.status, round == 0 ? shifted : nullptr, nullptr,
+                                        round == 0 ? 1 : 0, shift_scale(rows, w), c.st, g, 1e-7));
                 note(c, trsm_launch(src, lds, sps, dst, ldd, dps, c.chol_work, w, rows, g, c.st));
             }
         } else {
