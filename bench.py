@@ -1,40 +1,58 @@
 """Benchmark: pass-efficient randomized truncated QSVD on one MI355X.
 
-Workload (the 2048 x 2048 configuration): dense quaternion FP32 matrix
-A = U diag(sigma) V^H + E, sigma_i = exp(-i/20), Haar quaternion unitaries, E i.i.d. N(0, 1e-4)
-per real component (synthetic, seeded).  k = 50, p = 10, subspace scheme (Alg. 2).  One step
-= one solve for each pass budget v in {2, 3, 4, 6}: 15 passes over A, each a quaternion view
-product A X or A^H X followed by its CholeskyQR, then the small QSVD and the
-back-multiplication, with per-pass error estimates.  The four solves are independent and run
-concurrently, the longest on the current stream and the others on three streams of their own
-(one per hardware queue), so that the latency-bound small steps of one overlap the views of
-the others; the same step with the solves one after another is reported beside it
-(sequential_value), and the latency of each solve alone (solve_ms).
+Headline workload (the largest single-GPU configuration): a dense 16384 x 16384 quaternion FP32
+matrix A = U diag(sigma) V^H with sigma_i = i^-1/2 and unitaries that are products of 8 random
+quaternion Householder reflectors and a unit-quaternion diagonal (synthetic, seeded, built on the
+host by workloads.config4), block Krylov scheme (Alg. 4) with k = 128, p = 32 and a budget of
+v = 8 views: seven views 160 columns wide, the Krylov stack of 640 columns, the last view 640
+wide, CholeskyQR after every view, the final QSVD and the back-multiplication, with per-pass
+error estimates.  One step = one such solve (8 passes over A); value = passes / second of the
+plain FP32 path (v / end-to-end solve time).
 
-Printed: one JSON line with passes/s (value), the dominant kernel's roofline position (FP32
-MFMA view product, timed with HIP events on its own stream), the FP64 CPU oracle timed on the
-host as a baseline, and accuracy against the oracle.  The precision form (views 1 .. v-2 in
-BF16 / FP16 with FP32 accumulation, the last two views FP32) is timed on the same step and
-reported beside it with its error ratio to the oracle.
+Printed: one JSON line with
+- value (FP32 A-passes/s) and the same for the reduced-precision forms (BF16 views 1..6 with FP32
+  views 7 and 8, and the BF16 split form of views 7 and 8), each with its error
+  ||A - U S V^H||_F / ||A||_F computed directly on the device in FP64 and its ratio to the FP64
+  oracle's error on the same A and sketch (the oracle's solve of this A is stored in
+  tests/golden/, written by a script that calls only the oracle), and the sampled distance of
+  U diag(S) V^H from the oracle's;
+- the roofline position of the dominant kernel (the FP32 view product, 16384 x 16384 by 160
+  columns, timed with HIP events on its own stream) and of every other view kernel the solve
+  runs (FP32 at 640 columns, BF16 at 160, BF16 split at 640);
+- the FP64 CPU oracle timed on the host (single thread and all cores) on a bounded sample of
+  the same workload, as a baseline;
+- secondary records: the 2048 x 2048 subspace workload (budgets 2, 3, 4, 6), the serving stream
+  and the matrix-completion workloads.
 """
 import argparse
 import hashlib
-import re
 import json
 import os
+import re
+import subprocess
 import sys
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-M = N = 2048
-K_RANK, P_OVER = 50, 10
-BUDGETS = (2, 3, 4, 6)
-SEED_DATA, SEED_SKETCH = 1, 1
 PEAK_FP32_MFMA = 157.3e12
+PEAK_BF16_MFMA = 2516.6e12
 PEAK_HBM = 8.0e12
-PMC_FILE = os.path.join(ROOT, "profiles", "qgemm_f32_view_2048x2048x60_pmc.json")
+
+# the headline: 16384 x 16384, block Krylov, k = 128, p = 32, v = 8, sketch seed 11
+LN, LK, LP, LV, LSEED = 16384, 128, 32, 8, 11
+LL = LK + LP
+LW = (LV // 2) * LL            # width of the Krylov stack and of the last view (even v)
+GOLDEN = os.path.join(ROOT, "tests", "golden", "config4_krylov_k128_p32_v8_seed11.json")
+PMC_FILE = os.path.join(ROOT, "profiles", "qgemm_f32_view_16384x16384x160_pmc.json")
+
+# secondary: 2048 x 2048, sigma_i = exp(-i/20) + noise, subspace k = 50, p = 10, budgets 2, 3, 4, 6
+M1 = N1 = 2048
+K1, P1 = 50, 10
+BUDGETS1 = (2, 3, 4, 6)
+SEED_DATA1, SEED_SKETCH1 = 1, 1
+
 # server slots: one per hardware queue HIP gives a process by default (measured with 256
 # requests: 1861 req/s closed loop with 4 slots, 1508 with 8, 1444 with 16)
 SERVE_SLOTS = 4
@@ -43,23 +61,28 @@ SERVE_SLOTS = 4
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--kernel-reps", type=int, default=5)
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-completion", action="store_true")
-    ap.add_argument("--no-large", action="store_true")
-    ap.add_argument("--only-large", action="store_true",
-                    help="run only the 16384 x 16384 solves and print their record")
+    ap.add_argument("--no-config1", action="store_true")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="only the 16384 x 16384 solves (timed steps, accuracy, view kernels); for a kernel trace")
     ap.add_argument("--only-completion", action="store_true",
                     help="run only the matrix-completion workloads (for a kernel trace) and print their record")
     ap.add_argument("--counters", action="store_true",
                     help="launch sequence for hardware-counter runs only (view products and calibration copies)")
-    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="turn the counter CSVs of two --counters runs into the traffic record under profiles/")
+    ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
+                    help="FETCH_SIZE and WRITE_SIZE CSVs of two --counters runs (then optional MFMA counter "
+                         "CSVs): writes the traffic record under profiles/")
     return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():
@@ -68,21 +91,51 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def host_cores():
+    return len(os.sched_getaffinity(0))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def headline_matrix(torch):
+    """The 16384 x 16384 matrix on the host (bitwise reproducible), checked against the hash the
+    stored oracle solve was made on, then uploaded."""
+    import workloads as W
+    log(f"building the {LN}x{LN} matrix on the host")
+    t0 = time.perf_counter()
+    A32, sigma = W.config4(threads=min(16, host_cores()))
+    golden = json.load(open(GOLDEN)) if os.path.exists(GOLDEN) else None
+    sha = hashlib.sha256(A32.tobytes()).hexdigest()
+    same = golden is not None and golden["sha256"] == sha
+    log(f"  built in {time.perf_counter() - t0:.1f} s; matches the oracle's input: {same}")
+    A = torch.from_numpy(A32).cuda()
+    torch.cuda.synchronize()
+    return A, A32, sigma, (golden if same else None)
+
+
 COPY_BYTES = 256 << 20
-COUNTER_REPS = 5
+COUNTER_REPS = 3
+COUNTER_OPS = ((0, LL, "forward"), (1, LL, "adjoint"))
 
 
 def counters_run(Q, torch, A):
-    """The launch sequence the traffic counters are read on: COUNTER_REPS forward and adjoint
-    FP32 view products (2048 x 2048 by 60), then COUNTER_REPS elementwise passes over 256 MiB
+    """The launch sequence the hardware counters are read on: COUNTER_REPS forward and adjoint
+    FP32 view products (16384 x 16384 by 160), then COUNTER_REPS elementwise passes over 256 MiB
     (read once, written once) whose counter readings calibrate the scale of FETCH_SIZE and
     WRITE_SIZE."""
-    w = K_RANK + P_OVER
     g = torch.Generator(device="cuda").manual_seed(0)
-    X = torch.randn((4, N, w), device="cuda", generator=g)
-    for op in (0, 1):
-        ws = Q.qlra_qgemm_workspace(op, M, N, w)
-        C = torch.empty((4, M if op == 0 else N, w), device="cuda")
+    for op, w, _ in COUNTER_OPS:
+        X = torch.randn((4, LN, w), device="cuda", generator=g)
+        ws = Q.qlra_qgemm_workspace(op, LN, LN, w)
+        C = torch.empty((4, LN, w), device="cuda")
         for _ in range(COUNTER_REPS):
             Q.qlra_qgemm(op, A, X, C, stream=torch.cuda.current_stream(), workspace=ws)
             torch.cuda.synchronize()
@@ -95,48 +148,59 @@ def counters_run(Q, torch, A):
     print(json.dumps({"counters_run": "done", "view_launches_per_op": COUNTER_REPS, "copy_bytes": COPY_BYTES}))
 
 
-def pmc_summary(fetch_csv, write_csv):
-    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) from two rocprofv3 --pmc runs of --counters
-    (CSV output).  A view is the thin-block transpose, the product kernel and the ordered split-K
-    reduction; the elementwise pass's readings give the factor that turns each counter into
-    bytes."""
+def _read_counter_csv(path):
+    """{counter: [(dispatch, kernel, value summed over the dispatch's rows)]} in dispatch order."""
     import csv
-    import statistics
-
-    def read(path, counter):
-        rows = {}
-        for r in csv.DictReader(open(path)):
-            if r.get("Counter_Name") != counter:
-                continue
-            key = int(r["Dispatch_Id"])
-            rows[key] = (r["Kernel_Name"], rows.get(key, ("", 0.0))[1] + float(r["Counter_Value"]))
-        return [rows[k] for k in sorted(rows)]
-
+    rows = {}
+    for r in csv.DictReader(open(path)):
+        key = (r["Counter_Name"], int(r["Dispatch_Id"]))
+        rows[key] = (r["Kernel_Name"], rows.get(key, ("", 0.0))[1] + float(r["Counter_Value"]))
     out = {}
-    for counter, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
-        seq = read(path, counter)
-        view = [(n, v) for n, v in seq if any(t in n for t in ("k_thin_t", "k_qview", "k_splitk_reduce"))]
-        copies = [v for _, v in seq[-COUNTER_REPS:]]     # the calibration copies end the sequence
-        kib_copy = statistics.median(copies)
-        scale = COPY_BYTES / (kib_copy * 1024.0)
-        per_op = {}
-        for op, name in ((0, "forward"), (1, "adjoint")):
-            part = view[op * len(view) // 2:(op + 1) * len(view) // 2]
-            kib = sum(v for _, v in part) / COUNTER_REPS
-            per_op[name] = {"kib_per_launch": round(kib, 1), "bytes_per_launch": round(kib * 1024.0 * scale),
-                            "kernels": sorted({re.search(r"k_\w+", n).group(0) for n, _ in part})}
-        out[counter] = {"copy_kib": round(kib_copy, 1), "scale": round(scale, 4), **per_op}
-    hbm = 0.5 * sum(out[c][o]["bytes_per_launch"] for c in ("FETCH_SIZE", "WRITE_SIZE") for o in ("forward", "adjoint"))
-    rec = {"kernel": "FP32 view product 2048x2048 by 60 (transpose + product kernel + split-K reduction), "
+    for (cn, d), (kn, v) in sorted(rows.items(), key=lambda t: t[0][1]):
+        out.setdefault(cn, []).append((d, kn, v))
+    return out
+
+
+def pmc_summary(paths):
+    """Per-dispatch counters from rocprofv3 --pmc runs of --counters (CSV output): FETCH_SIZE
+    and WRITE_SIZE (KiB; the elementwise pass's readings give the factor that turns each into
+    bytes), and any further counters (MFMA activity) per view kernel."""
+    import statistics
+    view_kernels = ("k_thin_t", "k_qview", "k_splitk_reduce")
+    out = {}
+    extra = {}
+    for path in paths:
+        for counter, seq in _read_counter_csv(path).items():
+            view = [(n, v) for _, n, v in seq if any(t in n for t in view_kernels)]
+            nper = len(view) // len(COUNTER_OPS)
+            if counter in ("FETCH_SIZE", "WRITE_SIZE"):
+                copies = [v for _, _, v in seq[-COUNTER_REPS:]]     # the calibration copies end the sequence
+                kib_copy = statistics.median(copies)
+                scale = COPY_BYTES / (kib_copy * 1024.0)
+                per_op = {}
+                for i, (_, w, name) in enumerate(COUNTER_OPS):
+                    part = view[i * nper:(i + 1) * nper]
+                    kib = sum(v for _, v in part) / COUNTER_REPS
+                    per_op[name] = {"kib_per_launch": round(kib, 1), "bytes_per_launch": round(kib * 1024.0 * scale),
+                                    "kernels": sorted({re.search(r"k_\w+", n).group(0) for n, _ in part})}
+                out[counter] = {"copy_kib": round(kib_copy, 1), "scale": round(scale, 4), **per_op}
+            else:
+                per_op = {}
+                for i, (_, w, name) in enumerate(COUNTER_OPS):
+                    part = [(n, v) for n, v in view[i * nper:(i + 1) * nper] if "k_qview" in n]
+                    per_op[name] = round(sum(v for _, v in part) / max(1, len(part)), 1)
+                extra[counter] = {"per_product_kernel_launch": per_op}
+    hbm = 0.5 * sum(out[c][o]["bytes_per_launch"] for c in ("FETCH_SIZE", "WRITE_SIZE") for _, _, o in COUNTER_OPS)
+    rec = {"kernel": f"FP32 view product {LN}x{LN} by {LL} (the product kernel and any split-K reduction), "
                      "mean of A X and A^H X",
            "commands": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/"
                         "pmc_fetch -o f -- python3 <repo>/bench.py --counters",
                         "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/"
                         "pmc_write -o w -- python3 <repo>/bench.py --counters",
                         "python bench.py --pmc-summary <out>/pmc_fetch/f_counter_collection.csv "
-                        "<out>/pmc_write/w_counter_collection.csv"],
+                        "<out>/pmc_write/w_counter_collection.csv [<MFMA counter CSVs>]"],
            "kernel_source_hash": kernel_source_hash(), "hbm_bytes_per_launch": round(hbm),
-           "algorithmic_bytes_per_launch": 16 * M * N + 2 * 16 * N * (K_RANK + P_OVER), **out}
+           "algorithmic_bytes_per_launch": 16 * LN * LN + 2 * 16 * LN * LL, **out, "other_counters": extra}
     os.makedirs(os.path.dirname(PMC_FILE), exist_ok=True)
     json.dump(rec, open(PMC_FILE, "w"), indent=1)
     print(json.dumps(rec))
@@ -149,7 +213,7 @@ def graph_time(torch, fn, reps):
     st = torch.cuda.Stream()
     st.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(st):
-        for _ in range(3):
+        for _ in range(2):
             fn()
     torch.cuda.current_stream().wait_stream(st)
     torch.cuda.synchronize()
@@ -169,19 +233,254 @@ def graph_time(torch, fn, reps):
     return e0.elapsed_time(e1) * 1e-3 / reps
 
 
-def time_view_kernels(Q, torch, A, reps):
-    """Average duration of the FP32 view product (both orientations; the product kernel and, for
-    split K, its ordered reduction) with HIP events on the stream the kernels run on."""
-    w = K_RANK + P_OVER
+def view_kernel_times(Q, torch, A, m, n, shapes, reps):
+    """Average duration of each view product in `shapes` ((label, op, w, precision)), HIP events
+    on its stream around a graph of reps launches; the copies of A the reduced-precision forms
+    read are made once, outside the timed region."""
     g = torch.Generator(device="cuda").manual_seed(0)
-    X = torch.randn((4, N, w), device="cuda", generator=g)
+    copies = {}
     out = {}
-    for op in (0, 1):
-        ws = Q.qlra_qgemm_workspace(op, M, N, w)
-        C = torch.empty((4, M if op == 0 else N, w), device="cuda")
-        out[op] = graph_time(torch, lambda: Q.qlra_qgemm(op, A, X, C, stream=torch.cuda.current_stream(), workspace=ws),
-                             reps)
+    for label, op, w, prec in shapes:
+        kdim = n if op == 0 else m
+        X = torch.randn((4, kdim, w), device="cuda", generator=g)
+        C = torch.empty((4, m if op == 0 else n, w), device="cuda")
+        cur = torch.cuda.current_stream
+        if prec == "fp32":
+            ws = Q.qlra_qgemm_workspace(op, m, n, w)
+            fn = lambda: Q.qlra_qgemm(op, A, X, C, stream=cur(), workspace=ws)   # noqa: E731
+        else:
+            p = Q.QLRA_BF16
+            if "copy" not in copies:
+                copies["copy"] = Q.qlra_lowp_copy(A, p)
+            src = copies["copy"][0 if op == 0 else 1]
+            if prec == "bf16":
+                ws = Q.qlra_qgemm_lp_workspace(op, p, m, n, w)
+                fn = lambda: Q.qlra_qgemm_lp(op, p, src, m, n, X, C, stream=cur(), workspace=ws)   # noqa: E731
+            else:
+                if "res" not in copies:
+                    copies["res"] = Q.qlra_lowp_copy_residual(A, p)
+                res = copies["res"][0 if op == 0 else 1]
+                ws = Q.qlra_qgemm_split_workspace(op, p, m, n, w)
+                fn = lambda: Q.qlra_qgemm_split(op, p, src, res, m, n, X, C, stream=cur(), workspace=ws)   # noqa: E731
+        out[label] = graph_time(torch, fn, reps)
+        del X, C, ws
+    del copies
+    torch.cuda.empty_cache()
     return out
+
+
+def view_roofline(label, prec, m, n, w, t):
+    """Roofline position of one view product: 32 m n w algorithmic flops (16 real FMAs per
+    quaternion multiply-add); bytes = A once (16 m n in FP32, 8 m n for a BF16 copy, 24 m n for
+    the split form's copy, residual copy and second read) plus the thin operand and the result."""
+    flops = 32.0 * m * n * w
+    abytes = {"fp32": 16.0, "bf16": 8.0, "bf16_split": 16.0}[prec] * m * n
+    nbytes = abytes + 16.0 * (m + n) * w
+    peak_f = PEAK_FP32_MFMA if prec == "fp32" else PEAK_BF16_MFMA
+    mult = 3 if prec == "bf16_split" else 1          # three BF16 products
+    roof = min(peak_f / mult, flops / nbytes * PEAK_HBM)
+    bound = "mfma" if peak_f / mult <= flops / nbytes * PEAK_HBM else "hbm"
+    ach = flops / t
+    return {"view": label, "precision": prec, "us": round(t * 1e6, 2), "tflops": round(ach / 1e12, 2),
+            "hbm_gbs_algorithmic": round(nbytes / t / 1e9, 1), "bound": bound,
+            "roof_tflops": round(roof / 1e12, 2), "frac_of_roof": round(ach / roof, 4)}
+
+
+def direct_error(torch, A, U, S, V):
+    """||A - U diag(S) V^H||_F / ||A||_F in FP64 on the device, from
+    ||A||^2 - 2 sum_j S_j Re(U^H A V)_jj + sum_j S_j^2 (U and V orthonormal)."""
+    def pair(X):
+        X = X.to(torch.float64)
+        return torch.complex(X[0], X[1]), torch.complex(X[2], X[3])
+    Aa, Ab = pair(A)
+    nA2 = float(torch.sum(torch.abs(Aa) ** 2 + torch.abs(Ab) ** 2))
+    Va, Vb = pair(V)
+    Ta = Aa @ Va - Ab @ torch.conj(Vb)
+    Tb = Aa @ Vb + Ab @ torch.conj(Va)
+    del Aa, Ab
+    Ua, Ub = pair(U)
+    # diag of U^H T: (a + b j)^H (c + d j) has complex part conj(a) c + b conj(d)... entry-wise sums
+    d = torch.sum(torch.conj(Ua) * Ta + Ub * torch.conj(Tb), dim=0).real
+    Sd = S.to(torch.float64)
+    e2 = nA2 - 2.0 * float(torch.sum(Sd * d)) + float(torch.sum(Sd * Sd))
+    return (max(e2, 0.0) / nA2) ** 0.5
+
+
+def sampled_ahat(torch, U, S, V, rows, cols):
+    """U diag(S) V^H at the entries (rows[t], cols[t]) in FP64 on the device, (4, len(rows))."""
+    import numpy as np
+    ri = torch.as_tensor(np.asarray(rows), device=U.device)
+    ci = torch.as_tensor(np.asarray(cols), device=U.device)
+
+    def pair(X):
+        X = X.to(torch.float64)
+        return torch.complex(X[0], X[1]), torch.complex(X[2], X[3])
+    Ua, Ub = pair(U[:, ri, :])
+    Va, Vb = pair(V[:, ci, :])
+    Sd = S.to(torch.float64)[None, :]
+    Ua, Ub = Ua * Sd, Ub * Sd
+    xa = torch.sum(Ua * torch.conj(Va) + Ub * torch.conj(Vb), dim=1)
+    xb = torch.sum(Ub * Va - Ua * Vb, dim=1)
+    return torch.stack([xa.real, xa.imag, xb.real, xb.imag]).cpu().numpy()
+
+
+def headline(Q, torch, args):
+    """The timed 16384 x 16384 solves (FP32, BF16, BF16 split), their accuracy against the stored
+    oracle solve, and the view kernels' roofline positions."""
+    import numpy as np
+    A, A32, sigma, golden = headline_matrix(torch)
+    precs = {"fp32": Q.QLRA_FP32, "bf16": Q.QLRA_BF16, "bf16_split": Q.QLRA_BF16_SPLIT}
+    U = torch.empty((4, LN, LK), device="cuda")
+    V = torch.empty((4, LN, LK), device="cuda")
+    S = torch.empty(LK, dtype=torch.float64, device="cuda")
+    e = torch.empty(LV, dtype=torch.float64, device="cuda")
+    res = {}
+    for name, prec in precs.items():
+        need = Q.qlra_workspace_size(LN, LN, LK, LP, LV, "krylov", precision=prec)
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+
+        def solve():
+            Q.qlra(A, LK, LP, LV, "krylov", LSEED, U=U, S=S, V=V, pass_err=e, workspace=ws, precision=prec)
+        log(f"{name}: warmup {args.warmup}, timing {args.steps} solves")
+        for _ in range(args.warmup):
+            solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            solve()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert Q.qlra_status(ws) == Q.QLRA_OK
+        err = direct_error(torch, A, U, S, V)
+        r = {"value": round(LV * args.steps / dt, 3), "unit": "A-passes/s", "ms_per_solve": round(dt * 1e3 / args.steps, 3),
+             "rel_err": err, "e_v": float(e[-1].item()), "workspace_gb": round(need / 2 ** 30, 3)}
+        if golden is not None:
+            eo = golden["pass_err"][-1]
+            r["rel_err_oracle"] = eo
+            r["error_ratio_vs_oracle"] = err / eo
+            got = sampled_ahat(torch, U, S, V, golden["rows"], golden["cols"])
+            want = np.asarray(golden["ahat"])
+            r["ahat_diff_sampled"] = float(np.sqrt(np.mean(np.sum((got - want) ** 2, axis=0)) * LN * LN / golden["nA2"]))
+            r["max_rel_sv_diff"] = float(np.max(np.abs(S.cpu().numpy() - np.asarray(golden["S"])) /
+                                                np.asarray(golden["S"])))
+        res[name] = r
+        del ws
+        torch.cuda.empty_cache()
+    for name in ("bf16", "bf16_split"):
+        res[name]["speedup_vs_fp32"] = round(res[name]["value"] / res["fp32"]["value"], 3)
+    opt = float(np.sqrt(np.sum(sigma[LK:] ** 2) / np.sum(sigma ** 2)))
+    log("timing the view kernels")
+    shapes = [("fp32 A X, w=160", 0, LL, "fp32"), ("fp32 A^H X, w=160", 1, LL, "fp32"),
+              ("fp32 A^H X, w=640 (last view)", 1, LW, "fp32"),
+              ("bf16 A X, w=160", 0, LL, "bf16"), ("bf16 A^H X, w=160", 1, LL, "bf16"),
+              ("bf16 split A X, w=160", 0, LL, "bf16_split"),
+              ("bf16 split A^H X, w=640 (last view)", 1, LW, "bf16_split")]
+    kt = view_kernel_times(Q, torch, A, LN, LN, shapes, args.kernel_reps)
+    views = [view_roofline(lab, prec, LN, LN, w, kt[lab]) for lab, _, w, prec in shapes]
+    del A
+    torch.cuda.empty_cache()
+    return res, views, kt, opt, golden, A32
+
+
+def cpu_baseline(A32):
+    """The FP64 oracle on the host, as it stands, on a bounded sample of the headline workload:
+    its first view A Omega (16384 x 16384 by 160) restricted to a block of rows, single thread and
+    all cores (OpenMP over output rows), scaled to A-passes/s (rows sampled / 16384 of a pass).
+    The full solve is dominated by its 8 views; its QR and QSVD steps are not in the sample."""
+    import numpy as np
+    cores = host_cores()
+    out = {"unit": "A-passes/s", "kind": "oracle", "cores": cores, "cpu_model": cpu_model()}
+    tmp = "/tmp/qlra_bench_rows.npy"
+    for threads, rows in ((1, 192), (cores, max(192, 96 * cores))):
+        np.save(tmp, np.ascontiguousarray(A32[:, :rows, :]))
+        code = ("import sys, time, numpy as np; sys.path.insert(0, %r); from oracle import oracle as O; "
+                "A = np.load(%r).astype(np.float64); Om = O.omega(%d, %d, %d).astype(np.float64); "
+                "t = time.perf_counter(); O.qgemm(A, Om); print(time.perf_counter() - t)"
+                % (ROOT, tmp, LSEED, LN, LL))
+        env = dict(os.environ, OMP_NUM_THREADS=str(threads))
+        log(f"cpu baseline: oracle view on {rows} rows, {threads} thread(s)")
+        t = float(subprocess.check_output([sys.executable, "-c", code], env=env, text=True).strip().splitlines()[-1])
+        rate = (rows / LN) / t
+        key = "single_thread" if threads == 1 else "all_cores"
+        out[key] = {"value": round(rate, 6), "threads": threads, "rows": rows, "seconds": round(t, 2)}
+    os.remove(tmp)
+    out["value"] = out["all_cores"]["value"]
+    out["sample"] = (f"the oracle's first view A Omega of the {LN}x{LN} workload ({LL} columns) on "
+                     f"{out['all_cores']['rows']} rows with all {cores} cores ({out['all_cores']['seconds']} s) and on "
+                     f"{out['single_thread']['rows']} rows with one thread ({out['single_thread']['seconds']} s), "
+                     "scaled to whole passes; QR and QSVD steps not included")
+    return out
+
+
+def config1_record(Q, torch, W, args):
+    """The 2048 x 2048 subspace workload: one step = the solves of the four budgets, each on a
+    stream of its own (the longest on the current stream), graph-replayed; plus the accuracy of
+    each budget against the oracle."""
+    import numpy as np
+    from oracle import oracle as O
+    log("2048x2048 workload")
+    A_np, _ = W.config1(seed=SEED_DATA1, n=M1, noise_std=0.01)
+    A = torch.from_numpy(A_np).cuda()
+    outs = {}
+    for v in BUDGETS1:
+        need = Q.qlra_workspace_size(M1, N1, K1, P1, v, "subspace")
+        outs[v] = dict(U=torch.empty((4, M1, K1), device="cuda"), V=torch.empty((4, N1, K1), device="cuda"),
+                       S=torch.empty(K1, dtype=torch.float64, device="cuda"),
+                       e=torch.empty(v, dtype=torch.float64, device="cuda"),
+                       ws=torch.empty(need, dtype=torch.uint8, device="cuda"))
+    streams = {v: torch.cuda.Stream() for v in BUDGETS1[:-1]}
+
+    def solve(v, stream=None):
+        o = outs[v]
+        Q.qlra(A, K1, P1, v, "subspace", SEED_SKETCH1, U=o["U"], S=o["S"], V=o["V"], pass_err=o["e"],
+               workspace=o["ws"], graph=True, stream=stream)
+
+    def step():
+        cur = torch.cuda.current_stream()
+        for v in BUDGETS1[:-1]:
+            streams[v].wait_stream(cur)
+            solve(v, streams[v])
+        solve(BUDGETS1[-1], cur)
+        for v in BUDGETS1[:-1]:
+            cur.wait_stream(streams[v])
+
+    steps = 20
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    per_v = {}
+    for v in BUDGETS1:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(5):
+            solve(v)
+        torch.cuda.synchronize()
+        per_v[f"v{v}_ms"] = round((time.perf_counter() - t1) * 1e3 / 5, 4)
+    kt = view_kernel_times(Q, torch, A, M1, N1, [("fwd", 0, K1 + P1, "fp32"), ("adj", 1, K1 + P1, "fp32")], 50)
+    A64 = A_np.astype(np.float64)
+    nA = np.sqrt(np.sum(A64 ** 2))
+    acc = []
+    for v in BUDGETS1:
+        Uo, So, Vo, _ = O.qlra(A64, K1, P1, v, O.SUBSPACE, SEED_SKETCH1)
+        Ao = O.reconstruct(Uo, So, Vo)
+        solve(v)
+        torch.cuda.synchronize()
+        o = outs[v]
+        Ag = O.reconstruct(*(x.cpu().numpy().astype(np.float64) for x in (o["U"], o["S"], o["V"])))
+        eg, eo = np.sqrt(np.sum((A64 - Ag) ** 2)) / nA, np.sqrt(np.sum((A64 - Ao) ** 2)) / nA
+        acc.append({"v": v, "rel_err_gpu": float(eg), "rel_err_oracle": float(eo), "ratio": float(eg / eo),
+                    "ahat_diff": float(np.sqrt(np.sum((Ag - Ao) ** 2)) / nA)})
+    return {"workload": "dense quaternion 2048x2048 FP32, sigma_i=exp(-i/20)+N(0,1e-4) noise, k=50, p=10, "
+                        "subspace scheme (Alg. 2), budgets v=2,3,4,6 per step (concurrent on four streams)",
+            "value": round(sum(BUDGETS1) * steps / dt, 3), "unit": "A-passes/s",
+            "ms_per_step": round(dt * 1e3 / steps, 4), "solve_ms": per_v,
+            "view_roofline": [view_roofline(lab, "fp32", M1, N1, K1 + P1, t) for lab, t in kt.items()],
+            "accuracy": acc}
 
 
 def serving(Q, torch, nreq, seed=3):
@@ -266,7 +565,7 @@ def completion(Q, torch, W):
     and last iteration and the relative error of X on all entries."""
     out = []
     for name, m, n, rank, p, v, observed, sigma, iters in COMPLETION:
-        print(f"completion {m}x{n}, {iters} iterations", file=sys.stderr, flush=True)
+        log(f"completion {m}x{n}, {iters} iterations")
         M = torch.from_numpy(W.image_like(5, m, n)).cuda()
         K = torch.from_numpy(W.random_mask(6, m, n, observed)).cuda()
         X = torch.empty_like(M)
@@ -292,137 +591,15 @@ def completion(Q, torch, W):
     return out
 
 
-# The large single matrix: 16384 x 16384 dense FP32, sigma_i = i^-1/2, block Krylov k = 128,
-# p = 32, budget 8 (final view 640 columns wide), plain FP32 against the precision form
-LARGE_N, LARGE_K, LARGE_P, LARGE_V = 16384, 128, 32, 8
-
-
-def large(Q, torch):
-    """End-to-end solve time of the 16384 x 16384 workload for each view precision (the mean of 3
-    solves after a warm-up, synchronised around each) and the returned error estimate e_v, which
-    is ||A - U S V^H||_F / ||A||_F by an exact identity (checked against the direct residual by
-    the full-size tests)."""
-    import numpy as np
-    from workloads import gpu as WG
-    print(f"large solve {LARGE_N}x{LARGE_N}: generating", file=sys.stderr, flush=True)
-    sigma = np.arange(1, LARGE_N + 1, dtype=np.float64) ** -0.5
-    A = WG.spectrum_matrix(4, LARGE_N, LARGE_N, sigma)
-    torch.cuda.synchronize()
-    rec = {"workload": f"dense {LARGE_N}x{LARGE_N} FP32, sigma_i = i^-1/2, block Krylov (Alg. 4) k={LARGE_K}, "
-                       f"p={LARGE_P}, v={LARGE_V}", "solves": 3}
-    U = torch.empty((4, LARGE_N, LARGE_K), device="cuda")
-    V = torch.empty((4, LARGE_N, LARGE_K), device="cuda")
-    S = torch.empty(LARGE_K, dtype=torch.float64, device="cuda")
-    e = torch.empty(LARGE_V, dtype=torch.float64, device="cuda")
-    for name, prec in (("fp32", Q.QLRA_FP32), ("bf16", Q.QLRA_BF16), ("bf16_split", Q.QLRA_BF16_SPLIT)):
-        print(f"large solve {name}", file=sys.stderr, flush=True)
-        ws = None
-        _, _, _, _, ws = Q.qlra(A, LARGE_K, LARGE_P, LARGE_V, "krylov", 11, U=U, S=S, V=V, pass_err=e, precision=prec)
-        torch.cuda.synchronize()
-        t = []
-        for _ in range(3):
-            t0 = time.perf_counter()
-            Q.qlra(A, LARGE_K, LARGE_P, LARGE_V, "krylov", 11, U=U, S=S, V=V, pass_err=e, workspace=ws, precision=prec)
-            torch.cuda.synchronize()
-            t.append(time.perf_counter() - t0)
-        assert Q.qlra_status(ws) == Q.QLRA_OK
-        rec[f"{name}_solve_ms"] = round(1e3 * sum(t) / len(t), 3)
-        rec[f"{name}_e_v"] = float(e[-1].item())
-        del ws
-    for name in ("bf16", "bf16_split"):
-        rec[f"{name}_speedup_vs_fp32"] = round(rec["fp32_solve_ms"] / rec[f"{name}_solve_ms"], 3)
-        rec[f"{name}_error_ratio"] = rec[f"{name}_e_v"] / rec["fp32_e_v"]
-    rec["optimum_rank_k_error"] = float(np.sqrt(np.sum(sigma[LARGE_K:] ** 2) / np.sum(sigma ** 2)))
-    del A
-    torch.cuda.empty_cache()
-    return rec
-
-
-def cpu_baseline(A_np):
-    """The FP64 oracle on the host: one full step (v = 2, 3, 4, 6) on the same matrix."""
-    from oracle import oracle as O
-    import numpy as np
-    cores = len(os.sched_getaffinity(0))
-    os.environ["OMP_NUM_THREADS"] = str(cores)
-    A64 = A_np.astype(np.float64)
-    t0 = time.perf_counter()
-    for v in BUDGETS:
-        O.qlra(A64, K_RANK, P_OVER, v, O.SUBSPACE, SEED_SKETCH)
-    dt = time.perf_counter() - t0
-    return {"value": round(sum(BUDGETS) / dt, 4), "unit": "A-passes/s", "cores": cores, "kind": "oracle",
-            "sample": "one full step (subspace solves at v = 2, 3, 4, 6; 15 passes) on the same 2048x2048 matrix, "
-                      f"{dt:.1f} s wall"}
-
-
-def accuracy(Q, torch, A, A_np, precisions):
-    """Error of the GPU result (each precision) and of the oracle against A for each budget
-    (outside the timed region)."""
-    import numpy as np
-    from oracle import oracle as O
-    A64 = A_np.astype(np.float64)
-    nA = np.sqrt(np.sum(A64 ** 2))
-    rows = {name: [] for name in precisions}
-    for v in BUDGETS:
-        Uo, So, Vo, eo = O.qlra(A64, K_RANK, P_OVER, v, O.SUBSPACE, SEED_SKETCH)
-        Ao = O.reconstruct(Uo, So, Vo)
-        eo_ = np.sqrt(np.sum((A64 - Ao) ** 2)) / nA
-        for name, prec in precisions.items():
-            U, S, V, e, ws = Q.qlra(A, K_RANK, P_OVER, v, "subspace", SEED_SKETCH, precision=prec)
-            torch.cuda.synchronize()
-            Ug, Sg, Vg = (x.cpu().numpy().astype(np.float64) for x in (U, S, V))
-            Ag = O.reconstruct(Ug, Sg, Vg)
-            eg_ = np.sqrt(np.sum((A64 - Ag) ** 2)) / nA
-            rows[name].append({"v": v, "rel_err_gpu": float(eg_), "rel_err_oracle": float(eo_),
-                               "ratio": float(eg_ / eo_), "ahat_diff": float(np.sqrt(np.sum((Ag - Ao) ** 2)) / nA),
-                               "pass_err_gpu_last": float(e.cpu().numpy()[-1])})
-    return rows
-
-
-def time_split_view_kernels(Q, torch, A, prec, reps):
-    """Average duration of the split-form view product (both orientations), as above."""
-    w = K_RANK + P_OVER
-    g = torch.Generator(device="cuda").manual_seed(0)
-    X = torch.randn((4, N, w), device="cuda", generator=g)
-    Alo, Alo_t = Q.qlra_lowp_copy(A, prec)
-    Ar, Ar_t = Q.qlra_lowp_copy_residual(A, prec)
-    out = {}
-    for op in (0, 1):
-        ws = Q.qlra_qgemm_split_workspace(op, prec, M, N, w)
-        C = torch.empty((4, M if op == 0 else N, w), device="cuda")
-        a, r = (Alo, Ar) if op == 0 else (Alo_t, Ar_t)
-        out[op] = graph_time(torch, lambda: Q.qlra_qgemm_split(op, prec, a, r, M, N, X, C,
-                                                               stream=torch.cuda.current_stream(), workspace=ws), reps)
-    return out
-
-
-def time_lowp_view_kernels(Q, torch, A, prec, reps):
-    """Average duration of the reduced-precision view product (both orientations), HIP events on
-    its stream around a graph of reps launches.  The copies of A are made once, outside the
-    timed region."""
-    w = K_RANK + P_OVER
-    g = torch.Generator(device="cuda").manual_seed(0)
-    X = torch.randn((4, N, w), device="cuda", generator=g)
-    Alo, Alo_t = Q.qlra_lowp_copy(A, prec)
-    out = {}
-    for op in (0, 1):
-        ws = Q.qlra_qgemm_lp_workspace(op, prec, M, N, w)
-        C = torch.empty((4, M if op == 0 else N, w), device="cuda")
-        src = Alo if op == 0 else Alo_t
-        out[op] = graph_time(torch, lambda: Q.qlra_qgemm_lp(op, prec, src, M, N, X, C, stream=torch.cuda.current_stream(),
-                                                            workspace=ws), reps)
-    return out
-
-
 def main():
     args = parse()
     if args.pmc_summary:
-        pmc_summary(*args.pmc_summary)
+        pmc_summary(args.pmc_summary)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1",
                           "n_gpus_requested": args.gpus}))
         sys.exit(2)
-    import numpy as np
     import torch
     from paper_2507_13731_amd import qlra as Q
     import workloads as W
@@ -430,107 +607,16 @@ def main():
     if args.only_completion:
         print(json.dumps({"completion": completion(Q, torch, W)}))
         return
-    if args.only_large:
-        print(json.dumps({"large": large(Q, torch)}))
-        return
-    print("generating the 2048x2048 workload", file=sys.stderr, flush=True)
-    A_np, _ = W.config1(seed=SEED_DATA, n=M, noise_std=0.01)
-    A = torch.from_numpy(A_np).cuda()
     if args.counters:
+        A, _, _, _ = headline_matrix(torch)
         counters_run(Q, torch, A)
         return
-    precisions = {"fp32": Q.QLRA_FP32, "bf16": Q.QLRA_BF16, "fp16": Q.QLRA_FP16, "bf16_split": Q.QLRA_BF16_SPLIT}
-    outs = {}
-    for name, prec in precisions.items():
-        for v in BUDGETS:
-            need = Q.qlra_workspace_size(M, N, K_RANK, P_OVER, v, "subspace", precision=prec)
-            outs[name, v] = dict(U=torch.empty((4, M, K_RANK), device="cuda"),
-                                 V=torch.empty((4, N, K_RANK), device="cuda"),
-                                 S=torch.empty(K_RANK, dtype=torch.float64, device="cuda"),
-                                 e=torch.empty(v, dtype=torch.float64, device="cuda"),
-                                 ws=torch.empty(need, dtype=torch.uint8, device="cuda"))
-
-    # one step = the solves of the four budgets, independent of each other: each on a stream of
-    # its own (default priority), so that one solve's latency-bound small steps overlap the
-    # others' views
-    # the longest solve (v = 6) on the current stream, the others on three streams of their own:
-    # four streams for the four hardware queues HIP gives a process by default (with a fifth,
-    # two of them would share a queue and run one after the other)
-    streams = {v: torch.cuda.Stream() for v in BUDGETS[:-1]}
-
-    def solve(name, v, stream=None):
-        o = outs[name, v]
-        Q.qlra(A, K_RANK, P_OVER, v, "subspace", SEED_SKETCH, U=o["U"], S=o["S"], V=o["V"], pass_err=o["e"],
-               workspace=o["ws"], graph=True, precision=precisions[name], stream=stream)
-
-    def step(name):
-        cur = torch.cuda.current_stream()
-        for v in BUDGETS[:-1]:
-            streams[v].wait_stream(cur)
-            solve(name, v, streams[v])
-        solve(name, BUDGETS[-1], cur)
-        for v in BUDGETS[:-1]:
-            cur.wait_stream(streams[v])
-
-    def timed_steps(name, steps, warmup):
-        for _ in range(warmup):
-            step(name)
-        torch.cuda.synchronize()
-        for v in BUDGETS:
-            assert Q.qlra_status(outs[name, v]["ws"]) == Q.QLRA_OK
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            step(name)
-        torch.cuda.synchronize()
-        return time.perf_counter() - t0
-
-    def per_budget(name):
-        res = {}
-        for v in BUDGETS:
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            for _ in range(5):
-                solve(name, v)
-            torch.cuda.synchronize()
-            res[f"v{v}_ms"] = round((time.perf_counter() - t1) * 1e3 / 5, 4)
-        return res
-
-    print(f"warmup {args.warmup} steps, timing {args.steps} steps (FP32 views)", file=sys.stderr, flush=True)
-    dt = timed_steps("fp32", args.steps, args.warmup)
-    ms_per_step = dt * 1e3 / args.steps
-    passes = sum(BUDGETS) * args.steps
-    value = passes / dt
-    per_v = per_budget("fp32")
-    # the same step with the four solves one after another on one stream (latency view)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.steps):
-        for v in BUDGETS:
-            solve("fp32", v)
-    torch.cuda.synchronize()
-    sequential_value = passes / (time.perf_counter() - t1)
-
-    lowp = {}
-    for name in ("bf16", "fp16", "bf16_split"):
-        print(f"timing {args.steps} steps ({name} views 1..v-2)", file=sys.stderr, flush=True)
-        dtl = timed_steps(name, args.steps, args.warmup)
-        split = name.endswith("_split")
-        kt_l = time_lowp_view_kernels(Q, torch, A, precisions["bf16" if split else name], args.kernel_reps)
-        t_l = 0.5 * (kt_l[0] + kt_l[1])
-        lowp[name] = {"value": round(passes / dtl, 3), "unit": "A-passes/s", "ms_per_step": round(dtl * 1e3 / args.steps, 4),
-                      "speedup_vs_fp32": round(dt / dtl, 4), "solve_ms": per_budget(name),
-                      "view_kernel_us": {"forward": round(kt_l[0] * 1e6, 2), "adjoint": round(kt_l[1] * 1e6, 2)},
-                      "view_hbm_gbs": round(8.0 * M * N / t_l / 1e9, 1),
-                      "view_hbm_frac": round(8.0 * M * N / t_l / PEAK_HBM, 4)}
-        if split:
-            ks = time_split_view_kernels(Q, torch, A, Q.QLRA_BF16, args.kernel_reps)
-            lowp[name]["split_view_kernel_us"] = {"forward": round(ks[0] * 1e6, 2), "adjoint": round(ks[1] * 1e6, 2)}
-
-    print("timing the view kernels", file=sys.stderr, flush=True)
-    kt = time_view_kernels(Q, torch, A, args.kernel_reps)
-    w = K_RANK + P_OVER
-    flops = 32.0 * M * N * w                      # algorithmic flops of one view (16 real FMAs per qMAC)
-    t_view = 0.5 * (kt[0] + kt[1])
+    res, views, kt, opt, golden, A32 = headline(Q, torch, args)
+    fp = res["fp32"]
+    # the dominant kernel: the FP32 view product at 160 columns (7 of the 8 views), forward and
+    # adjoint averaged
+    t_view = 0.5 * (kt["fp32 A X, w=160"] + kt["fp32 A^H X, w=160"])
+    flops = 32.0 * LN * LN * LL
     achieved = flops / t_view
     traffic = None
     if os.path.exists(PMC_FILE):
@@ -539,42 +625,43 @@ def main():
             traffic = pmc.get("hbm_bytes_per_launch")
     roofline = {"bound": "mfma", "achieved": round(achieved / 1e12, 3), "peak": PEAK_FP32_MFMA / 1e12,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_MFMA, 4), "traffic": traffic,
-                "kernel": "k_qgemm FP32 view product, 2048x2048 by 60 quaternion columns",
-                "t_forward_us": round(kt[0] * 1e6, 2), "t_adjoint_us": round(kt[1] * 1e6, 2),
-                "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": 16.0 * M * N + 2 * 16.0 * N * w}
-
-    for name in lowp:
-        lowp[name]["view_speedup_vs_fp32"] = round(t_view / (0.5 * (lowp[name]["view_kernel_us"]["forward"] +
-                                                                   lowp[name]["view_kernel_us"]["adjoint"]) * 1e-6), 3)
-    print("accuracy against the oracle", file=sys.stderr, flush=True)
-    acc_all = accuracy(Q, torch, A, A_np, precisions)
-    acc = acc_all["fp32"]
-    for name in lowp:
-        lowp[name]["accuracy"] = acc_all[name]
-        lowp[name]["max_error_ratio"] = round(max(r["ratio"] for r in acc_all[name]), 8)
+                "kernel": f"k_qview FP32 view product, {LN}x{LN} by {LL} quaternion columns (mean of A X and A^H X)",
+                "algorithmic_flops_per_launch": flops,
+                "algorithmic_bytes_per_launch": 16.0 * LN * LN + 2 * 16.0 * LN * LL}
+    if args.only_headline:
+        print(json.dumps({"headline": res, "view_kernels": views, "roofline": roofline}))
+        return
+    sec = None if args.no_config1 else config1_record(Q, torch, W, args)
     serve = None
     if not args.no_serve:
-        print(f"serving stream ({args.serve_requests} requests)", file=sys.stderr, flush=True)
+        log(f"serving stream ({args.serve_requests} requests)")
         serve = serving(Q, torch, args.serve_requests)
     comp = None if args.no_completion else completion(Q, torch, W)
-    big = None if args.no_large else large(Q, torch)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(A_np)
-    line = {"metric": "A-passes/s", "value": round(value, 3), "unit": "A-passes/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+    cpu = None if args.no_cpu_baseline else cpu_baseline(A32)
+    line = {"metric": "A-passes/s", "value": fp["value"], "unit": "A-passes/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": fp["ms_per_solve"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-            "data": "synthetic (seeded; Haar quaternion unitaries, exp(-i/20) spectrum + Gaussian noise)",
-            "config": {"workload": "dense quaternion 2048x2048 FP32, sigma_i=exp(-i/20)+N(0,1e-4) noise, "
-                                   "k=50, p=10, subspace scheme (Alg. 2), budgets v=2,3,4,6 per step",
-                       "m": M, "n": N, "k": K_RANK, "p": P_OVER, "budgets": list(BUDGETS),
-                       "passes_per_step": sum(BUDGETS)},
-            "step": "the solves of the four budgets, concurrently (the current stream and three others)",
-            "sequential_value": round(sequential_value, 3),
-            "qgemm_tflops": round(achieved / 1e12, 3), "solve_ms": per_v, "accuracy": acc,
+            "data": "synthetic (seeded; sigma_i = i^-1/2, reflector-product quaternion unitaries, built on the host)",
+            "config": {"workload": f"dense quaternion {LN}x{LN} FP32, sigma_i=i^-1/2, block Krylov (Alg. 4) "
+                                   f"k={LK}, p={LP}, v={LV}: one solve (8 passes over A) per step",
+                       "m": LN, "n": LN, "k": LK, "p": LP, "pass_budget": LV, "scheme": "block_krylov",
+                       "sketch_seed": LSEED},
+            "qgemm_tflops": round(achieved / 1e12, 3), "rel_err_gpu": fp["rel_err"],
+            "rel_err_oracle": fp.get("rel_err_oracle"), "error_ratio_vs_oracle": fp.get("error_ratio_vs_oracle"),
+            "ahat_diff_vs_oracle_sampled": fp.get("ahat_diff_sampled"),
+            "optimum_rank_k_error": opt,
             "roofline": roofline, "cpu_baseline": cpu,
-            "precision_form": {"views": "1..v-2 reduced (FP32 accumulation), v-1 and v FP32 (split: v-1 and v as three "
-                                        "BF16 products of values and residuals); Gram/Cholesky/QSVD FP64",
-                               **lowp},
-            "serving": serve, "completion": comp, "large": big}
+            "precision_form": {"views": "BF16: views 1..6 on BF16 copies of A (FP32 accumulation), views 7 and 8 FP32; "
+                                        "BF16 split: views 7 and 8 as three BF16 products of values and residuals; "
+                                        "Gram/Cholesky/QSVD FP64", "fp32": fp,
+                               "bf16": res["bf16"], "bf16_split": res["bf16_split"]},
+            "view_kernels": views,
+            "oracle_full_solve_context": (None if golden is None else
+                                          {"seconds": round(golden["oracle_seconds"], 1),
+                                           "a_passes_per_s": round(LV / golden["oracle_seconds"], 5),
+                                           "where": "the run that wrote the stored oracle solve (another host, "
+                                                    "8 cores); context only"}),
+            "config_2048": sec, "serving": serve, "completion": comp}
     print(json.dumps(line))
 
 

@@ -614,8 +614,37 @@ __global__ __launch_bounds__(256) void k_zero_f64(double* __restrict__ p, int64_
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) p[e] = 0.0;
 }
 
-// *gate = 1 when max |G - I| over the four planes exceeds tol (or is not finite), else 0: G is
-// the Gram Q^H Q of a basis after one CholeskyQR round.
+// *gate_out = 1 when max |G - I| over the four planes of a w x w Gram exceeds tol (or is not
+// finite), else 0; always 0 when gate_in is given and *gate_in == 0.  One workgroup.
+__global__ __launch_bounds__(256) void k_orth_gate(const double* __restrict__ G, int w, double tol, int* gate_out,
+                                                   const int* gate_in) {
+    __shared__ double red[4];
+    const int tid = threadIdx.x;
+    if (gate_in && *gate_in == 0) {
+        if (tid == 0) *gate_out = 0;
+        return;
+    }
+    const int64_t ps = (int64_t)w * w;
+    double mx = 0.0;
+    for (int64_t e = tid; e < ps; e += 256) {
+        const Q4 v = ld4(G, ps, e);
+        const double d = (e / w == e % w) ? v.w - 1.0 : v.w;
+        const double a = fmax(fmax(fabs(d), fabs(v.x)), fmax(fabs(v.y), fabs(v.z)));
+        mx = (a > mx || a != a) ? a : mx;     // a NaN sticks
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double t = __shfl_xor(mx, o, 64);
+        mx = (t > mx || t != t) ? t : mx;
+    }
+    if ((tid & 63) == 0) red[tid >> 6] = mx;
+    __syncthreads();
+    if (tid == 0) {
+        double m = red[0];
+        for (int i = 1; i < 4; i++) m = (red[i] > m || red[i] != red[i]) ? red[i] : m;
+        *gate_out = (m <= tol) ? 0 : 1;
+    }
+}
 
 __global__ void k_flag_nonzero(int* dst, const int* src) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src != 0 ? 1 : 0;
@@ -680,6 +709,13 @@ hipError_t zero_f64_launch(double* p, int64_t count, const int* gate, hipStream_
     return hipGetLastError();
 }
 
+
+hipError_t orth_gate_launch(const double* G, int64_t w, double tol, int* gate_out, const int* gate_in,
+                            hipStream_t st) {
+    if (w < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_orth_gate, dim3(1), dim3(256), 0, st, G, (int)w, tol, gate_out, gate_in);
+    return hipGetLastError();
+}
 
 hipError_t flag_nonzero_launch(int* dst, const int* src, hipStream_t st) {
     hipLaunchKernelGGL(k_flag_nonzero, dim3(1), dim3(64), 0, st, dst, src);

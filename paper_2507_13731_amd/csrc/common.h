@@ -117,6 +117,10 @@ hipError_t copy_f64_planes_launch(const double* src, int64_t lds, int64_t sps, d
 hipError_t zero_f64_launch(double* p, int64_t count, const int* gate, hipStream_t st);
 // *dst = (*src != 0).
 hipError_t flag_nonzero_launch(int* dst, const int* src, hipStream_t st);
+// *gate_out = 1 when max |G - I| (G a w x w Gram, FP64 planes) exceeds tol or is not finite, else
+// 0; always 0 when gate_in is given and *gate_in == 0.
+hipError_t orth_gate_launch(const double* G, int64_t w, double tol, int* gate_out, const int* gate_in,
+                            hipStream_t st);
 // Cholesky alone for w <= chol_reg_max(), factor to R (no inverse) and to Rpk, R's upper
 // triangle packed by rows with the four components of an entry side by side (4 w (w + 1) / 2
 // doubles, the input of trsm_launch); same status, shift and gate behaviour as chol_launch.
@@ -165,8 +169,16 @@ size_t qsvd_gram_work_doubles(int64_t w);
 // S_j = sqrt(max(lam_j, 0)) (j < k) and, when E is given, Wk = E[:, :k] diag(1 / S) (w x k FP64
 // planes, ld k), from lam (descending) and E (w x >= k, ld lde) of a Gram's eigendecomposition;
 // with est also *est = sqrt(max(0, *nA2 - sum_{j<k} S_j^2) / *nA2) (as estimate_launch).
+// Columns with S_j <= kDegenerate S_0 (rounding level of an FP32 view: no direction left in
+// Y E_j / S_j) get zero columns in Wk.  *degen (if given) = 1 when there is any such column or
+// S_{k-1} < S_0 / 8 (the factor Y Wk is then re-orthonormalised), else 0.
+constexpr double kDegenerate = 1.0 / 1048576.0;   // 2^-20
 hipError_t svals_launch(const double* lam, const double* E, int64_t lde, int64_t w, int k, double* S, double* Wk,
-                        hipStream_t st, const double* nA2 = nullptr, double* est = nullptr);
+                        hipStream_t st, const double* nA2 = nullptr, double* est = nullptr, int* degen = nullptr);
+// Column j < k of X (rows x k FP32 planes) with S_j <= kDegenerate S_0 is overwritten by a fixed
+// pseudo-random vector (entries in [-1, 1) from a hash of (row, column, plane)), when *flag != 0.
+hipError_t fill_degenerate_launch(float* X, int64_t rows, int k, int64_t ldx, int64_t xps, const double* S,
+                                  const int* flag, hipStream_t st);
 // Larger orders (up to heig_big_max()): lam (W, descending) and, if E, the nout eigenvectors of
 // the largest eigenvalues (W x nout, ld nout).  work: heig_big_work_doubles(W, nvec) doubles with
 // nvec >= nout vector slots (0 without vectors).
@@ -174,6 +186,11 @@ int heig_big_max();
 size_t heig_big_work_doubles(int64_t W, int64_t nvec);
 hipError_t heig_big_launch(const double* G, int64_t W, double* lam, double* E, int64_t nout, double* work,
                            int64_t nvec, hipStream_t st);
+// The per-pass estimates of nprob Grams of one order W <= heig_big_max() (problem b at
+// G + b * gstride) in one launch sequence: e[b] = sqrt(max(0, nA2 - sum of the k largest
+// eigenvalues of G_b) / nA2).  work: nprob * heig_big_work_doubles(W, 0) doubles.
+hipError_t heig_big_estimates_launch(const double* G, int64_t gstride, int64_t W, int nprob, int k,
+                                     const double* nA2, double* e, double* work, hipStream_t st);
 // Estimates of nprob problems from their Grams (problem b at G + b * gstride, w <= heig_max()):
 // e[b] = sqrt(max(0, nA2 - sum of the k largest eigenvalues of G_b) / nA2).
 // work: heig_work_doubles(nprob).
@@ -232,5 +249,12 @@ hipError_t complete_init_launch(const float* M, int64_t ldm, int64_t mps, const 
                                 hipStream_t st);
 // dst[0] |= src[0].
 hipError_t status_or_launch(int* dst, const int* src, hipStream_t st);
+
+// The solve behind qlra() (same arguments).  no_alloc: create no streams, events or graphs (the
+// per-pass estimates run on the solve's stream, opts->graph is ignored).
+int solve_entry(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stride, int k, int p,
+                int pass_budget, int scheme, uint64_t seed, const qlra_opts_t* opts, float* U, int64_t ldu,
+                int64_t u_plane_stride, double* S, float* V, int64_t ldv, int64_t v_plane_stride, double* pass_err,
+                bool no_alloc);
 
 }  // namespace qlra_impl

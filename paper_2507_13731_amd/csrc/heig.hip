@@ -662,13 +662,21 @@ __global__ __launch_bounds__(256) void k_left_vectors(const double* __restrict__
 }
 
 // From the eigendecomposition G = E diag(lam) E^H of a view's Gram Y^H Y (lam descending):
-// S_j = sqrt(max(lam_j, 0)) and W = E_k diag(1 / S) (w x k, ld k; zero columns where S_j = 0).
+// S_j = sqrt(max(lam_j, 0)) and W = E_k diag(1 / S) (w x k, ld k; zero columns where S_j is at
+// or below kDegenerate S_0, flagged in *degen).
 __global__ __launch_bounds__(256) void k_svals(const double* __restrict__ lam, const double* __restrict__ E,
                                                int64_t lde, int w, int k, double* __restrict__ S,
                                                double* __restrict__ Wk, const double* __restrict__ nA2,
-                                               double* __restrict__ est) {
+                                               double* __restrict__ est, int* degen) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double s0 = sqrt(fmax(lam[0], 0.0));
     if (e < k) S[e] = sqrt(fmax(lam[e], 0.0));
+    if (degen && e == 0) {
+        // nonzero: re-orthonormalise the factor Y W (a steep spectrum, or degenerate columns)
+        int any = !(sqrt(fmax(lam[k - 1], 0.0)) >= 0.125 * s0);
+        for (int j = 0; j < k; j++) any |= !(sqrt(fmax(lam[j], 0.0)) > kDegenerate * s0);
+        *degen = any;
+    }
     if (est && e == 0) {
         // the estimate of this pass, sqrt(max(0, ||A||^2 - sum_{j<k} S_j^2) / ||A||^2)
         double top = 0.0;
@@ -682,10 +690,36 @@ __global__ __launch_bounds__(256) void k_svals(const double* __restrict__ lam, c
     if (!E || e >= (int64_t)w * k) return;
     const int i = (int)(e / k), j = (int)(e % k);
     const double sj = sqrt(fmax(lam[j], 0.0));
-    const double inv = sj > 0.0 ? 1.0 / sj : 0.0;
+    const double inv = sj > kDegenerate * s0 ? 1.0 / sj : 0.0;
     const int64_t eps = (int64_t)w * lde, wps = (int64_t)w * k, src = (int64_t)i * lde + j;
 #pragma unroll
     for (int p = 0; p < 4; p++) Wk[p * wps + e] = E[p * eps + src] * inv;
+}
+
+// Degenerate columns of a factor Y E_k S^{-1}: a fixed pseudo-random vector (any vector with a
+// component outside the kept columns will do; the re-orthonormalisation that follows makes it a
+// unit vector orthogonal to them).
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    // the 32-bit finaliser of MurmurHash3 (Appleby)
+    x ^= x >> 16; x *= 0x85ebca6bu; x ^= x >> 13; x *= 0xc2b2ae35u; x ^= x >> 16;
+    return x;
+}
+
+__global__ __launch_bounds__(256) void k_fill_degenerate(float* __restrict__ X, int64_t rows, int k, int64_t ldx,
+                                                         int64_t xps, const double* __restrict__ S,
+                                                         const int* __restrict__ flag) {
+    if (*flag == 0) return;
+    const double s0 = S[0];
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < rows * k; e += (int64_t)gridDim.x * 256) {
+        const int64_t i = e / k;
+        const int j = (int)(e - i * k);
+        if (S[j] > kDegenerate * s0) continue;
+#pragma unroll
+        for (int p = 0; p < 4; p++) {
+            const uint32_t h = mix32((uint32_t)(e * 4 + p) ^ mix32((uint32_t)(e >> 30) + 0x9e3779b9u));
+            X[p * xps + i * ldx + j] = (float)((double)h * (1.0 / 2147483648.0) - 1.0);
+        }
+    }
 }
 
 // e_b = sqrt(max(0, ||A||^2 - sum of the k largest max(lambda, 0)) / ||A||^2) per problem b.
@@ -777,10 +811,19 @@ hipError_t qsvd_gram_launch(const double* X, int64_t w, double* U, double* S, do
 }
 
 hipError_t svals_launch(const double* lam, const double* E, int64_t lde, int64_t w, int k, double* S, double* Wk,
-                        hipStream_t st, const double* nA2, double* est) {
+                        hipStream_t st, const double* nA2, double* est, int* degen) {
     const int64_t n = std::max<int64_t>(w * k, k);
     hipLaunchKernelGGL(k_svals, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, lam, E, lde, (int)w, k, S, Wk,
-                       nA2, est);
+                       nA2, est, degen);
+    return hipGetLastError();
+}
+
+hipError_t fill_degenerate_launch(float* X, int64_t rows, int k, int64_t ldx, int64_t xps, const double* S,
+                                  const int* flag, hipStream_t st) {
+    if (rows < 1 || k < 1) return hipSuccess;
+    int64_t g = (rows * k + 255) / 256;
+    if (g > 2048) g = 2048;
+    hipLaunchKernelGGL(k_fill_degenerate, dim3((unsigned)g), dim3(256), 0, st, X, rows, k, ldx, xps, S, flag);
     return hipGetLastError();
 }
 

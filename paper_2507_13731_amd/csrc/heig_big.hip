@@ -1,12 +1,17 @@
 // Hermitian quaternion eigendecomposition for orders above the single-workgroup solver (the
-// Gram of a wide block-Krylov final view, Alg. 4: W = (number of stacked blocks) x l columns).
-// Same method as the small solver (Householder tridiagonalisation with quaternion reflectors
-// made real by a diagonal of phases, Sturm multisection, twisted factorisations, the
-// back-transformation), spread over many workgroups:
-//  - tridiagonalisation: the working matrix stays in global memory (L2 resident); each step is
-//    two launches over row blocks of 16 rows: (a) every block forms the reflector v from column
-//    j (redundantly), its rows' p = tau G v and a share of K = tau/2 v^H p; (b) every block
-//    forms q = p - K v and updates its rows, G <- G - v q^H - q v^H.
+// Gram of a wide block-Krylov final view, Alg. 4: W = (number of stacked blocks) x l columns,
+// and the Grams of views wider than that solver for the per-pass estimates).  Same method as the
+// small solver (Householder tridiagonalisation with quaternion reflectors made real by a
+// diagonal of phases, Sturm multisection, twisted factorisations, the back-transformation),
+// spread over many workgroups:
+//  - tridiagonalisation: the working matrix stays in global memory (L2 / MALL resident), one
+//    launch per reflector over row blocks of 4 rows (one wave per row).  Launch j applies the
+//    update of reflector j, G <- G - v q^H - q v^H with q = p - K v, to its rows and, in the same
+//    sweep, forms p = tau' G v' of the next reflector v' for them.  Every block forms v' itself
+//    from column j+1 after the update, which it computes from a copy of that column taken by the
+//    previous launch (so no block reads rows another block is writing); p, the shares of
+//    v'^H p and the column copies are double-buffered between launches.  Several problems of one
+//    order go in one launch (grid y), so the estimates of all views cost one launch sequence.
 //  - eigenvalues: 16 lanes per eigenvalue, the tridiagonal in LDS.
 //  - eigenvectors: only the wanted ones (the largest), one wave each, the reflectors read from
 //    the record.
@@ -73,8 +78,10 @@ __device__ double block_total(double v, double* red) {
     return red[0] + red[1] + red[2] + red[3];
 }
 
-constexpr int RB = 16;        // rows per workgroup in the tridiagonalisation (16 lanes each)
+constexpr int SRB = 4;        // rows per workgroup in the tridiagonalisation (one wave each)
 constexpr int BT = 256;
+
+__host__ __device__ inline int64_t step_blocks(int64_t W) { return (W + SRB - 1) / SRB; }
 
 // Record for order W (doubles): the working matrix, then the results.
 struct BigRec {
@@ -88,8 +95,9 @@ struct BigRec {
     double* bnd;    // 2 (+ pad)
     double* lam;    // W, ascending
     double* refl;   // 4 W (W + 1) / 2, (i, j) at i (i + 1) / 2 + j
-    double* P;      // 4 W: p of the current step
-    double* KP;     // ceil(W / RB) shares of v^H p
+    double* P;      // 2 x 4 W: p = tau G v of a reflector (the two buffers alternate by step parity)
+    double* KP;     // 2 x step_blocks(W) shares of v^H p
+    double* CB;     // 2 x 4 W: copy of the column of the next reflector, taken before its update
     double* X;      // W x nvec eigenvectors of T (vector t at X + t W)
     double* DM;     // W x nvec backward pivots
 };
@@ -107,110 +115,187 @@ __host__ __device__ inline BigRec big_rec(double* base, int64_t W, int64_t nvec)
     r.bnd = p; p += 8;
     r.lam = p; p += W;
     r.refl = p; p += 4 * (W * (W + 1) / 2);
-    r.P = p; p += 4 * W;
-    r.KP = p; p += (W + RB - 1) / RB;
+    r.P = p; p += 8 * W;
+    r.KP = p; p += 2 * step_blocks(W);
+    r.CB = p; p += 8 * W;
     r.X = p; p += W * nvec;
     r.DM = p; p += W * nvec;
     return r;
 }
 __host__ __device__ inline int64_t big_rec_doubles(int64_t W, int64_t nvec) {
-    return 4 * W * W + 9 * W + 8 + 4 * (W * (W + 1) / 2) + 4 * W + (W + RB - 1) / RB + 2 * W * nvec;
+    return 4 * W * W + 9 * W + 8 + 4 * (W * (W + 1) / 2) + 16 * W + 2 * step_blocks(W) + 2 * W * nvec;
 }
 
-__global__ __launch_bounds__(BT) void k_big_copy(const double* __restrict__ G, double* __restrict__ Gw, int64_t n) {
-    const int64_t e = (int64_t)blockIdx.x * BT + threadIdx.x;
-    if (e < n) Gw[e] = G[e];
-}
-
-// step j, part (a): reflector from column j (every block), p for this block's rows, K share
-__global__ __launch_bounds__(BT) void k_big_a(double* __restrict__ base, int W, int nvec, int j) {
-    __shared__ double vs[4 * 1024];   // v, W <= 1024
-    __shared__ double red[4];
-    BigRec R = big_rec(base, W, nvec);
-    const int64_t ps = (int64_t)W * W;
-    const int tid = threadIdx.x;
-    double part = 0.0;
-    for (int r = j + 1 + tid; r < W; r += BT) part += qn2(ld(R.Gw, ps, (int64_t)r * W + j));
+// The reflector of a column x (entries r > j0 below the diagonal held in vn[r], zero elsewhere):
+// alpha = |x|, phi = x_{j0+1} / |x_{j0+1}|, v = x + alpha phi e_{j0+1} (H x = -alpha phi e_{j0+1}),
+// tau = 1 / (alpha (alpha + |x_{j0+1}|)).  Every thread returns tau; block 0 stores v (rows > j0)
+// in the record's column j0, tau and s = -alpha phi.  part: this thread's share of |x|^2.
+__device__ double make_reflector(double* vn, int W, int j0, double part, double* red, const BigRec& R, bool store) {
     const double alpha = sqrt(block_total(part, red));
-    const Q4 x1 = ld(R.Gw, ps, (int64_t)(j + 1) * W + j);
+    const Q4 x1 = j0 + 1 < W ? Q4{vn[j0 + 1], vn[W + j0 + 1], vn[2 * W + j0 + 1], vn[3 * W + j0 + 1]}
+                             : Q4{0, 0, 0, 0};
     const double ax1 = sqrt(qn2(x1));
     const Q4 phi = ax1 > 0.0 ? qscale(x1, 1.0 / ax1) : Q4{1, 0, 0, 0};
     const double tau = alpha > 0.0 ? 1.0 / (alpha * (alpha + ax1)) : 0.0;
-    for (int r = tid; r < W; r += BT) {
-        Q4 v{0, 0, 0, 0};
-        if (r > j) {
-            v = ld(R.Gw, ps, (int64_t)r * W + j);        // G(r, j), the column below the diagonal
-            if (r == j + 1) v = qadd(v, qscale(phi, alpha));
-            if (blockIdx.x == 0) st(R.refl, W * (W + 1) / 2, (int64_t)r * (r + 1) / 2 + j, v);
-        }
-        vs[r] = v.w; vs[1024 + r] = v.x; vs[2048 + r] = v.y; vs[3072 + r] = v.z;
-    }
-    if (blockIdx.x == 0 && tid == 0) {
-        R.tau[j] = tau;
-        const Q4 sj = qscale(phi, -alpha);               // H x = -alpha phi e_1
-        R.ph[j] = sj.w; R.ph[W + j] = sj.x; R.ph[2 * W + j] = sj.y; R.ph[3 * W + j] = sj.z;   // s_j, for now
+    __syncthreads();                                     // every thread has read x1
+    if (threadIdx.x == 0 && j0 + 1 < W) {
+        const Q4 v1 = qadd(x1, qscale(phi, alpha));
+        vn[j0 + 1] = v1.w; vn[W + j0 + 1] = v1.x; vn[2 * W + j0 + 1] = v1.y; vn[3 * W + j0 + 1] = v1.z;
     }
     __syncthreads();
-    // p_r = tau sum_{c > j} G(r, c) v_c, 16 lanes per row
-    const int rl = tid >> 4, s = tid & 15;
-    const int r = blockIdx.x * RB + rl;
-    Q4 acc{0, 0, 0, 0};
-    if (r > j && r < W)
-        for (int c = j + 1 + s; c < W; c += 16)
-            acc = qadd(acc, qmul(ld(R.Gw, ps, (int64_t)r * W + c), Q4{vs[c], vs[1024 + c], vs[2048 + c], vs[3072 + c]}));
-    acc.w = row16_sum(acc.w); acc.x = row16_sum(acc.x); acc.y = row16_sum(acc.y); acc.z = row16_sum(acc.z);
-    const Q4 p = qscale(acc, tau);
+    if (store) {
+        const int64_t pps = (int64_t)W * (W + 1) / 2;
+        for (int r = j0 + 1 + (int)threadIdx.x; r < W; r += BT)
+            st(R.refl, pps, (int64_t)r * (r + 1) / 2 + j0, Q4{vn[r], vn[W + r], vn[2 * W + r], vn[3 * W + r]});
+        if (threadIdx.x == 0) {
+            R.tau[j0] = tau;
+            const Q4 sj = qscale(phi, -alpha);
+            R.ph[j0] = sj.w; R.ph[W + j0] = sj.x; R.ph[2 * W + j0] = sj.y; R.ph[3 * W + j0] = sj.z;   // s_j, for now
+        }
+    }
+    return tau;
+}
+
+// Start of the tridiagonalisation of problem blockIdx.y: copy its rows of G into the record,
+// reflector 0 from column 0 (every block), p = tau G v for its rows, its share of v^H p, and the
+// copy of column 1.  Grid (step_blocks(W), problems).
+__global__ __launch_bounds__(BT) void k_big_start(const double* __restrict__ G0, int64_t gstride, double* base0,
+                                                  int64_t rstride, int W, int nvec) {
+    __shared__ double vn[4 * 1024];                       // W <= 1024
+    __shared__ double red[4];
+    const double* G = G0 + blockIdx.y * gstride;
+    BigRec R = big_rec(base0 + blockIdx.y * rstride, W, nvec);
+    const int64_t ps = (int64_t)W * W;
+    const int tid = threadIdx.x;
+    const int nbs = (int)step_blocks(W);
+    const bool refl = W >= 3;
+    double tau = 0.0;
+    if (refl) {
+        double part = 0.0;
+        for (int r = tid; r < W; r += BT) {
+            const Q4 x = r > 0 ? ld(G, ps, (int64_t)r * W) : Q4{0, 0, 0, 0};
+            vn[r] = x.w; vn[W + r] = x.x; vn[2 * W + r] = x.y; vn[3 * W + r] = x.z;
+            part += qn2(x);
+        }
+        tau = make_reflector(vn, W, 0, part, red, R, blockIdx.x == 0);
+    }
+    const int wave = tid >> 6, lane = tid & 63;
+    const int r = blockIdx.x * SRB + wave;
     double kp = 0.0;
-    if (s == 0 && r < W) {
-        st(R.P, W, r, p);
-        if (r > j) kp = qdot(Q4{vs[r], vs[1024 + r], vs[2048 + r], vs[3072 + r]}, p);
+    if (r < W) {
+        Q4 acc{0, 0, 0, 0};
+        for (int c = lane; c < W; c += 64) {
+            const int64_t e = (int64_t)r * W + c;
+            const Q4 g = ld(G, ps, e);
+            st(R.Gw, ps, e, g);
+            if (refl && c > 0) acc = qadd(acc, qmul(g, Q4{vn[c], vn[W + c], vn[2 * W + c], vn[3 * W + c]}));
+            if (c == 1 && r > 1) st(R.CB, W, r, g);
+        }
+        if (refl) {
+            acc.w = wave_total(acc.w); acc.x = wave_total(acc.x); acc.y = wave_total(acc.y); acc.z = wave_total(acc.z);
+            const Q4 p = qscale(acc, tau);
+            if (lane == 0 && r > 0) {
+                st(R.P, W, r, p);
+                kp = qdot(Q4{vn[r], vn[W + r], vn[2 * W + r], vn[3 * W + r]}, p);
+            }
+        }
     }
     const double kt = block_total(kp, red);
     if (tid == 0) R.KP[blockIdx.x] = kt;
+    (void)nbs;
 }
 
-// step j, part (b): q = p - K v, update this block's rows
-__global__ __launch_bounds__(BT) void k_big_b(double* __restrict__ base, int W, int nvec, int j) {
-    __shared__ double vs[4 * 1024], qs[4 * 1024];
+// Step j of the tridiagonalisation of problem blockIdx.y (0 <= j <= W - 3): q = p - K v for
+// reflector j; the next reflector (j + 1 <= W - 3) from column j + 1 after this step's update
+// (the copy taken before it, updated here), formed by every block; then this block's rows:
+// G <- G - v q^H - q v^H, p' = tau' G v' of the next reflector, the copy of column j + 2.
+// Grid (step_blocks(W), problems).
+__global__ __launch_bounds__(BT) void k_big_step(double* base0, int64_t rstride, int W, int nvec, int j) {
+    __shared__ double sh[12 * 1024];                      // W <= 1024
+    double* vs = sh;            // v of reflector j
+    double* qs = sh + 4 * W;    // q of reflector j
+    double* vn = sh + 8 * W;    // v of reflector j + 1
     __shared__ double red[4];
-    BigRec R = big_rec(base, W, nvec);
-    const int64_t ps = (int64_t)W * W;
+    BigRec R = big_rec(base0 + blockIdx.y * rstride, W, nvec);
+    const int64_t ps = (int64_t)W * W, pps = (int64_t)W * (W + 1) / 2;
     const int tid = threadIdx.x;
-    const int nb = (W + RB - 1) / RB;
+    const int nbs = (int)step_blocks(W);
+    const int cur = j & 1, nxt = cur ^ 1;
+    const double* Pc = R.P + (int64_t)cur * 4 * W;
+    double* Pn = R.P + (int64_t)nxt * 4 * W;
+    const double* CBc = R.CB + (int64_t)cur * 4 * W;
+    double* CBn = R.CB + (int64_t)nxt * 4 * W;
     double part = 0.0;
-    for (int i = tid; i < nb; i += BT) part += R.KP[i];
+    for (int i = tid; i < nbs; i += BT) part += R.KP[cur * nbs + i];
     const double tau = R.tau[j];
     const double K = 0.5 * tau * block_total(part, red);
-    const int64_t pps = (int64_t)W * (W + 1) / 2;
     for (int c = tid; c < W; c += BT) {
         Q4 v{0, 0, 0, 0}, q{0, 0, 0, 0};
         if (c > j) {
             v = ld(R.refl, pps, (int64_t)c * (c + 1) / 2 + j);
-            q = qsub(ld(R.P, W, c), qscale(v, K));
+            q = qsub(ld(Pc, W, c), qscale(v, K));
         }
-        vs[c] = v.w; vs[1024 + c] = v.x; vs[2048 + c] = v.y; vs[3072 + c] = v.z;
-        qs[c] = q.w; qs[1024 + c] = q.x; qs[2048 + c] = q.y; qs[3072 + c] = q.z;
+        vs[c] = v.w; vs[W + c] = v.x; vs[2 * W + c] = v.y; vs[3 * W + c] = v.z;
+        qs[c] = q.w; qs[W + c] = q.x; qs[2 * W + c] = q.y; qs[3 * W + c] = q.z;
     }
     __syncthreads();
-    const int rl = tid >> 4, s = tid & 15;
-    const int r = blockIdx.x * RB + rl;
-    if (r <= j || r >= W) return;
-    const Q4 vr{vs[r], vs[1024 + r], vs[2048 + r], vs[3072 + r]};
-    const Q4 qr{qs[r], qs[1024 + r], qs[2048 + r], qs[3072 + r]};
-    for (int c = j + 1 + s; c < W; c += 16) {
-        const Q4 vc{vs[c], vs[1024 + c], vs[2048 + c], vs[3072 + c]};
-        const Q4 qc{qs[c], qs[1024 + c], qs[2048 + c], qs[3072 + c]};
-        const int64_t e = (int64_t)r * W + c;
-        Q4 t = qsub(qsub(ld(R.Gw, ps, e), qmul(vr, qconj(qc))), qmul(qr, qconj(vc)));
-        if (r == c) t.x = t.y = t.z = 0.0;
-        st(R.Gw, ps, e, t);
+    const int j1 = j + 1;
+    const bool more = j1 <= W - 3;
+    double tau1 = 0.0;
+    if (more) {
+        // column j1 after this step's update, rows below the diagonal (the same arithmetic as the
+        // row update below, so v' is exactly the updated column)
+        const Q4 vj{vs[j1], vs[W + j1], vs[2 * W + j1], vs[3 * W + j1]};
+        const Q4 qj{qs[j1], qs[W + j1], qs[2 * W + j1], qs[3 * W + j1]};
+        const Q4 cvj = qconj(vj), cqj = qconj(qj);
+        double p2 = 0.0;
+        for (int r = tid; r < W; r += BT) {
+            Q4 x{0, 0, 0, 0};
+            if (r > j1) {
+                const Q4 vr{vs[r], vs[W + r], vs[2 * W + r], vs[3 * W + r]};
+                const Q4 qr{qs[r], qs[W + r], qs[2 * W + r], qs[3 * W + r]};
+                x = qsub(qsub(ld(CBc, W, r), qmul(vr, cqj)), qmul(qr, cvj));
+                p2 += qn2(x);
+            }
+            vn[r] = x.w; vn[W + r] = x.x; vn[2 * W + r] = x.y; vn[3 * W + r] = x.z;
+        }
+        tau1 = make_reflector(vn, W, j1, p2, red, R, blockIdx.x == 0);
     }
+    const int wave = tid >> 6, lane = tid & 63;
+    const int r = blockIdx.x * SRB + wave;
+    double kp = 0.0;
+    if (r > j && r < W) {
+        const Q4 vr{vs[r], vs[W + r], vs[2 * W + r], vs[3 * W + r]};
+        const Q4 qr{qs[r], qs[W + r], qs[2 * W + r], qs[3 * W + r]};
+        Q4 acc{0, 0, 0, 0};
+        for (int c = j + 1 + lane; c < W; c += 64) {
+            const Q4 vc{vs[c], vs[W + c], vs[2 * W + c], vs[3 * W + c]};
+            const Q4 qc{qs[c], qs[W + c], qs[2 * W + c], qs[3 * W + c]};
+            const int64_t e = (int64_t)r * W + c;
+            Q4 t = qsub(qsub(ld(R.Gw, ps, e), qmul(vr, qconj(qc))), qmul(qr, qconj(vc)));
+            if (r == c) t.x = t.y = t.z = 0.0;
+            st(R.Gw, ps, e, t);
+            if (more) acc = qadd(acc, qmul(t, Q4{vn[c], vn[W + c], vn[2 * W + c], vn[3 * W + c]}));
+            if (c == j + 2 && r > j + 2) st(CBn, W, r, t);
+        }
+        if (more) {
+            acc.w = wave_total(acc.w); acc.x = wave_total(acc.x); acc.y = wave_total(acc.y); acc.z = wave_total(acc.z);
+            const Q4 p = qscale(acc, tau1);
+            if (lane == 0 && r > j1) {
+                st(Pn, W, r, p);
+                kp = qdot(Q4{vn[r], vn[W + r], vn[2 * W + r], vn[3 * W + r]}, p);
+            }
+        }
+    }
+    const double kt = block_total(kp, red);
+    if (tid == 0) R.KP[nxt * nbs + blockIdx.x] = kt;
 }
 
-// diagonal, real subdiagonal b_j = |s_j|, phases ph_{j+1} = s_j ph_j / |s_j|, bounds
-__global__ void k_big_fin(double* __restrict__ base, int W, int nvec) {
+// diagonal, real subdiagonal b_j = |s_j|, phases ph_{j+1} = s_j ph_j / |s_j|, bounds (problem
+// blockIdx.x)
+__global__ void k_big_fin(double* __restrict__ base0, int64_t rstride, int W, int nvec) {
     if (threadIdx.x != 0) return;
-    BigRec R = big_rec(base, W, nvec);
+    BigRec R = big_rec(base0 + blockIdx.x * rstride, W, nvec);
     const int64_t ps = (int64_t)W * W;
     if (W >= 2) {
         const Q4 sl = ld(R.Gw, ps, (int64_t)(W - 1) * W + (W - 2));
@@ -265,13 +350,15 @@ __device__ int sturm_lds(const double* d, const double* b2, int W, double x) {
     return cnt;
 }
 
-// eigenvalues: grid ceil(W / 16), 16 lanes per eigenvalue, 17-section rounds; lam_out descending
-__global__ __launch_bounds__(BT) void k_big_eigvals(double* __restrict__ base, int W, int nvec,
+// eigenvalues: grid (ceil(W / 16), problems), 16 lanes per eigenvalue, 17-section rounds;
+// lam_out (problem 0 only) descending
+__global__ __launch_bounds__(BT) void k_big_eigvals(double* __restrict__ base0, int64_t rstride, int W, int nvec,
                                                     double* __restrict__ lam_out) {
     extern __shared__ double sh[];
     double* d = sh;
     double* b2 = sh + W;
-    BigRec R = big_rec(base, W, nvec);
+    BigRec R = big_rec(base0 + blockIdx.y * rstride, W, nvec);
+    if (blockIdx.y != 0) lam_out = nullptr;
     const int tid = threadIdx.x, lane = tid & 63, s16 = tid & 15;
     int ex;
     frexp(fmax(fabs(R.bnd[0]), fabs(R.bnd[1])), &ex);
@@ -434,9 +521,44 @@ __global__ __launch_bounds__(BT) void k_big_back(double* __restrict__ base, int 
     }
 }
 
+// e_b = sqrt(max(0, nA2 - sum of the k largest max(lambda, 0)) / nA2) for problem b (thread b).
+__global__ void k_big_estimates(const double* __restrict__ base0, int64_t rstride, int W, int nprob, int k,
+                                const double* __restrict__ nA2, double* __restrict__ e) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nprob) return;
+    const BigRec R = big_rec(const_cast<double*>(base0) + b * rstride, W, 0);
+    double top = 0.0;
+    for (int j = 0; j < k && j < W; j++) top += fmax(R.lam[W - 1 - j], 0.0);
+    const double a = *nA2, r = a - top;
+    e[b] = a > 0.0 ? sqrt((r > 0.0 ? r : 0.0) / a) : 0.0;
+}
+
+// The tridiagonalisation and k_big_fin for nprob problems of order W (problem b's Gram at
+// G + b gstride, its record at work + b rstride).
+void tridiagonalise(const double* G, int64_t gstride, int64_t W, int nprob, double* work, int64_t rstride,
+                    int64_t nvec, hipStream_t st) {
+    const dim3 grid((unsigned)step_blocks(W), (unsigned)nprob);
+    hipLaunchKernelGGL(k_big_start, grid, dim3(BT), 0, st, G, gstride, work, rstride, (int)W, (int)nvec);
+    for (int j = 0; j + 2 < W; j++)
+        hipLaunchKernelGGL(k_big_step, grid, dim3(BT), 0, st, work, rstride, (int)W, (int)nvec, j);
+    hipLaunchKernelGGL(k_big_fin, dim3((unsigned)nprob), dim3(64), 0, st, work, rstride, (int)W, (int)nvec);
+}
+
 }  // namespace
 
 int heig_big_max() { return 1024; }
+
+hipError_t heig_big_estimates_launch(const double* G, int64_t gstride, int64_t W, int nprob, int k,
+                                     const double* nA2, double* e, double* work, hipStream_t st) {
+    if (W < 1 || W > heig_big_max() || nprob < 1) return hipErrorInvalidValue;
+    const int64_t rstride = big_rec_doubles(W, 0);
+    tridiagonalise(G, gstride, W, nprob, work, rstride, 0, st);
+    hipLaunchKernelGGL(k_big_eigvals, dim3((unsigned)((W + 15) / 16), (unsigned)nprob), dim3(BT),
+                       (size_t)(2 * W * sizeof(double)), st, work, rstride, (int)W, 0, (double*)nullptr);
+    hipLaunchKernelGGL(k_big_estimates, dim3((unsigned)((nprob + 63) / 64)), dim3(64), 0, st, (const double*)work,
+                       rstride, (int)W, nprob, k, nA2, e);
+    return hipGetLastError();
+}
 
 size_t heig_big_work_doubles(int64_t W, int64_t nvec) { return (size_t)big_rec_doubles(W, nvec); }
 
@@ -446,17 +568,9 @@ size_t heig_big_work_doubles(int64_t W, int64_t nvec) { return (size_t)big_rec_d
 hipError_t heig_big_launch(const double* G, int64_t W, double* lam, double* E, int64_t nout, double* work,
                            int64_t nvec, hipStream_t st) {
     if (W < 1 || W > heig_big_max() || nout < 0 || nout > W || (E && nvec < nout)) return hipErrorInvalidValue;
-    BigRec R = big_rec(work, W, nvec);
-    const int64_t n = 4 * W * W;
-    hipLaunchKernelGGL(k_big_copy, dim3((unsigned)((n + BT - 1) / BT)), dim3(BT), 0, st, G, R.Gw, n);
-    const unsigned nb = (unsigned)((W + RB - 1) / RB);
-    for (int j = 0; j + 2 < W; j++) {
-        hipLaunchKernelGGL(k_big_a, dim3(nb), dim3(BT), 0, st, work, (int)W, (int)nvec, j);
-        hipLaunchKernelGGL(k_big_b, dim3(nb), dim3(BT), 0, st, work, (int)W, (int)nvec, j);
-    }
-    hipLaunchKernelGGL(k_big_fin, dim3(1), dim3(64), 0, st, work, (int)W, (int)nvec);
-    hipLaunchKernelGGL(k_big_eigvals, dim3((unsigned)((W + 15) / 16)), dim3(BT), (size_t)(2 * W * sizeof(double)), st,
-                       work, (int)W, (int)nvec, lam);
+    tridiagonalise(G, 0, W, 1, work, 0, nvec, st);
+    hipLaunchKernelGGL(k_big_eigvals, dim3((unsigned)((W + 15) / 16), 1), dim3(BT), (size_t)(2 * W * sizeof(double)),
+                       st, work, (int64_t)0, (int)W, (int)nvec, lam);
     if (!E || nout == 0) return hipGetLastError();
     // vectors of ascending indices [W - nvec, W): the top nout plus room below for a cluster
     const int kfirst = (int)(W - nvec);

@@ -106,9 +106,10 @@ size_t chol_blk_doubles() { return (size_t)16 * chol_lds_max() * chol_lds_max();
 // by column from the diagonal up: X_ij = -X_ii (R_i,(i+1..j) X_(i+1..j),j).  With allow_shift a
 // breakdown of the unshifted pass (flag in status[2]) reruns everything, gated on that flag, on
 // G + shift_scale tr(G) I; a breakdown that remains ORs 2 into status[0].  Rout = R Rprev when
-// Rprev is given.  Scratch: chol_work (W), blk, and R2 when Rprev is given.
+// Rprev is given.  Scratch: chol_work (W), blk, and R2 when Rprev is given.  With `outer`,
+// nothing is computed (and *shift_out is set to 0) when *outer == 0.
 void chol_blocked(Ctx& c, const double* G, int64_t w, double* Rout, double* Rinv, const double* Rprev, int* shift_out,
-                  int allow_shift, double sscale) {
+                  int allow_shift, double sscale, const int* outer = nullptr) {
     const int64_t nb = (w + chol_lds_max() - 1) / chol_lds_max();
     const int64_t b = (w + nb - 1) / nb;
     const int64_t ps = w * w, bs = b * b;
@@ -121,7 +122,8 @@ void chol_blocked(Ctx& c, const double* G, int64_t w, double* Rout, double* Rinv
     int* fail = c.status ? c.status + 2 : nullptr;
     if (c.live() && allow_shift) note(c, fill_int_launch(fail, 1, 0, c.st));
     for (int attempt = 0; attempt < (allow_shift ? 2 : 1); attempt++) {
-        const int* gate = attempt ? fail : nullptr;
+        // the retry runs only when the first attempt ran and broke down
+        const int* gate = attempt ? fail : outer;
         int* st = (allow_shift && attempt == 0) ? fail : c.status;
         if (c.live()) {
             note(c, chol_prep_launch(G, w, W, gate, attempt, sscale, c.st));
@@ -154,8 +156,34 @@ void chol_blocked(Ctx& c, const double* G, int64_t w, double* Rout, double* Rinv
             }
         }
     }
-    if (Rprev) qg(c, desc(OP_NN, MATH_F64, Rw, w, ps, 1, Rprev, w, ps, 1, Rout, w, ps, 1, w, w, w));
+    if (Rprev) qg(c, desc(OP_NN, MATH_F64, Rw, w, ps, 1, Rprev, w, ps, 1, Rout, w, ps, 1, w, w, w, ST_SET, outer));
     if (shift_out && allow_shift && c.live()) note(c, flag_nonzero_launch(shift_out, fail, c.st));
+}
+
+// One CholeskyQR round on X (rows x w, in place), every launch gated on *gate (0: nothing done):
+// G = X^H X, G = Rx^H Rx, X = X Rx^{-1} and, when R is given, R = Rx R.  Scratch: G, R1, R2,
+// chol_work, Rinv, blk and T2.
+void cholqr_round_gated(Ctx& c, float* X, int64_t rows, int64_t w, int64_t ldx, int64_t xps, double* R,
+                        const int* gate) {
+    const int64_t ps = w * w;
+    qg(c, desc(OP_HN, MATH_F64, X, ldx, xps, 0, X, ldx, xps, 0, c.G, w, ps, 1, w, w, rows, ST_SET, gate));
+    if (w <= chol_reg_max()) {
+        if (c.live()) {
+            note(c, chol_reg_launch(c.G, w, c.R1, c.chol_work, c.status, nullptr, gate, 1, shift_scale(rows, w), c.st));
+            note(c, trsm_launch(X, ldx, xps, X, ldx, xps, c.chol_work, w, rows, gate, c.st));
+            if (R) {
+                note(c, rmul_launch(c.R1, R, c.R2, w, gate, c.st));
+                note(c, rcopy_launch(c.R2, R, w, gate, c.st));
+            }
+        }
+        return;
+    }
+    chol_blocked(c, c.G, w, c.R1, c.Rinv, R, nullptr, 1, shift_scale(rows, w), gate);
+    qg(c, desc(OP_NN, MATH_F64, X, ldx, xps, 0, c.Rinv, w, ps, 1, c.T2, w, rows * w, 0, rows, w, w, ST_SET, gate));
+    if (c.live()) {
+        note(c, copy_planes_launch(c.T2, w, rows * w, X, ldx, xps, rows, w, gate, c.st));
+        if (R) note(c, rcopy_launch(c.R1, R, w, gate, c.st));
+    }
 }
 
 // Thin QR of Y (rows x w): Q (ld ldq, plane stride qps) and R (w x w FP64, ld w; may be null
@@ -217,6 +245,32 @@ void cholqr(Ctx& c, const float* Y, int64_t rows, int64_t w, int64_t ldy, int64_
         src = dst; lds = ldd; sps = dps;
     }
     if (small && rounds == 2 && R && c.live()) note(c, rmul_launch(c.R2, c.R1, R, w, nullptr, c.st));
+    // A shifted first round leaves Q with a condition number up to about u^{-1/2}: shifted
+    // CholeskyQR is followed by CholeskyQR2 (Fukaya et al. 2020), so after a shifted round two
+    // more rounds (one after a two-round call) run on Q in place, gated on the device by the
+    // shift flag (nothing is launched into the kernels' work when it is 0).
+    if (shifted || c.dry)
+        for (int e = 0; e < (rounds == 1 ? 2 : 1); e++) cholqr_round_gated(c, Q, rows, w, ldq, qps, R, shifted);
+}
+
+// A returned factor of the final QSVD from the Gram (rows x k, in place): the Y side Y E_k S^{-1}
+// or the X side X E_k.  Column j of the Y side carries the FP32 rounding of Y divided by S_j, an
+// error of about u32 S_0 / S_j, and column j of E (either side) the FP64 eigensolver's error
+// u64 S_0^2 / gap_j in the Gram's eigenvalues: both lose orthogonality when the spectrum falls
+// steeply, and at the rounding level (S_j <= kDegenerate S_0, when k exceeds the numerical rank
+// of A) the Y side carries no direction at all (the singular value kernel zeroed the column) and
+// the eigenvectors of the degenerate cluster are arbitrary.  The singular value kernel sets
+// status[5] when either can happen (S_{k-1} < S_0 / 8 or a degenerate column); then the
+// degenerate columns get fixed pseudo-random vectors and the factor goes through CholeskyQR2,
+// all gated on that word.  The factor of a CholeskyQR is upper triangular, so a column is
+// orthogonalised against the columns of larger singular values only: a kept column moves by
+// its own orthogonality error, which changes U diag(S) V^H by about u32 S_0.  A degenerate
+// column becomes a unit vector orthogonal to the others, as the oracle's completion of the
+// basis.
+void reorthonormalize(Ctx& c, float* X, int64_t rows, int64_t k, int64_t ldx, int64_t xps, const double* S) {
+    int* gate = c.status ? c.status + 5 : nullptr;
+    if (c.live()) note(c, fill_degenerate_launch(X, rows, (int)k, ldx, xps, S, gate, c.st));
+    for (int r = 0; r < 2; r++) cholqr_round_gated(c, X, rows, k, ldx, xps, nullptr, gate);
 }
 
 // Orthonormalise the columns of a stack of blocks (rows x W, ld W) of width l: CholeskyQR2 of
@@ -332,7 +386,6 @@ struct Bufs {
     double* side_S; double* side_work;
     double* Gs;             // Grams of views 2 .. v-1, (v - 2) x (l x l)
     double* est_work;
-    double* side_lam;       // l eigenvalues (estimates from the large-order solver)
     double* big_work;       // the large-order eigensolver of the final view
     void* Alo; void* Alo_t;  // low-precision copies of A and A^T (views 1 .. v-2)
     void* Alo_lo; void* Alo_t_lo;  // split forms: their residual copies (views v-1 and v)
@@ -377,12 +430,11 @@ void carve(const Problem& pr, const Dims& d, Arena& ar, Bufs& b, size_t part_byt
     const bool small_l = d.l <= heig_max();
     const int64_t nest = pr.v > 2 ? pr.v - 2 : 0;
     b.side_S = (double*)ar.take(d.l * sizeof(double));
-    b.side_lam = (double*)ar.take(d.l * sizeof(double));
     b.side_work = batched ? nullptr : (double*)ar.take(qsvd_work_doubles(d.l) * sizeof(double));
     const int64_t extra = merged_estimates(pr, d) ? 1 : 0;   // the final Gram joins the batch
     b.Gs = batched && nest ? (double*)ar.take((size_t)(nest + extra) * 4 * l2 * sizeof(double)) : nullptr;
     b.est_work = batched && nest ? (double*)ar.take((small_l ? heig_work_doubles(nest + extra)
-                                                             : heig_big_work_doubles(d.l, 0)) *
+                                                             : (size_t)nest * heig_big_work_doubles(d.l, 0)) *
                                                     sizeof(double))
                                  : nullptr;
     // the final QSVD of a view wider than heig_max()
@@ -514,30 +566,33 @@ double* gram_slot(const Bufs& b, const Problem& pr, int64_t l, int i) {
 
 // Estimates of views 2 .. v-1 from their Grams on the side stream: one batched launch, or the
 // large-order solver (values only) one Gram after another.
-void fork_estimates(Ctx& c, const Bufs& b, const Problem& pr, int64_t l) {
-    if (!c.live() || !pr.estimate || !b.Gs) return;
+// The stream the estimates go to: the side stream, forked from the solve's stream, or without
+// one (a call that may create no streams) the solve's stream itself.
+hipStream_t est_stream(Ctx& c) {
+    if (!c.side) return c.st;
     c.forked = true;
     note(c, hipEventRecord(c.ev_fork, c.st));
     note(c, hipStreamWaitEvent(c.side, c.ev_fork, 0));
+    return c.side;
+}
+
+void fork_estimates(Ctx& c, const Bufs& b, const Problem& pr, int64_t l) {
+    if (!c.live() || !pr.estimate || !b.Gs) return;
+    const hipStream_t es = est_stream(c);
     if (l <= heig_max()) {
-        note(c, estimate_batch_launch(b.Gs, 4 * l * l, l, pr.v - 2, pr.k, b.nA2, pr.pass_err + 1, b.est_work, c.side));
+        note(c, estimate_batch_launch(b.Gs, 4 * l * l, l, pr.v - 2, pr.k, b.nA2, pr.pass_err + 1, b.est_work, es));
         return;
     }
-    for (int i = 0; i < pr.v - 2; i++) {
-        note(c, heig_big_launch(b.Gs + (size_t)i * 4 * l * l, l, b.side_lam, nullptr, 0, b.est_work, 0, c.side));
-        note(c, svals_launch(b.side_lam, nullptr, 0, l, pr.k, b.side_S, nullptr, c.side, b.nA2, pr.pass_err + 1 + i));
-    }
+    note(c, heig_big_estimates_launch(b.Gs, 4 * l * l, l, pr.v - 2, pr.k, b.nA2, pr.pass_err + 1, b.est_work, es));
 }
 
 // Side-stream estimate of view `i` (1-based) from its R (l x l), for widths above the batched
 // eigensolver's limit.
 void fork_estimate(Ctx& c, const Bufs& b, const Problem& pr, const double* R, int64_t l, int i) {
     if (!c.live() || !pr.estimate || b.Gs || i >= pr.v) return;
-    c.forked = true;
-    note(c, hipEventRecord(c.ev_fork, c.st));
-    note(c, hipStreamWaitEvent(c.side, c.ev_fork, 0));
-    note(c, qsvd_launch(R, l, nullptr, b.side_S, nullptr, b.side_work, 0, c.side));
-    note(c, estimate_launch(b.side_S, pr.k, b.nA2, pr.pass_err + (i - 1), c.side));
+    const hipStream_t es = est_stream(c);
+    note(c, qsvd_launch(R, l, nullptr, b.side_S, nullptr, b.side_work, 0, es));
+    note(c, estimate_launch(b.side_S, pr.k, b.nA2, pr.pass_err + (i - 1), es));
 }
 
 // The final TSVD of the last view's R (w x w) and the back-multiplication U = Q1 Uh,
@@ -581,7 +636,7 @@ void finish_gram(Ctx& c, const Bufs& b, const Problem& pr, const float* Y, int64
         else if (big) note(c, heig_big_launch(c.G, w, b.Sw, b.Rh, k, b.big_work, big_nvec(w, k), c.st));
         else note(c, heig_launch(c.G, w, b.Sw, b.Rh, b.qsvd_work, c.st));
         note(c, svals_launch(b.Sw, b.Rh, lde, w, k, pr.S, b.Lh, c.st, b.nA2,
-                             pr.estimate ? pr.pass_err + (pr.v - 1) : nullptr));
+                             pr.estimate ? pr.pass_err + (pr.v - 1) : nullptr, c.status ? c.status + 5 : nullptr));
     }
     float* Oy = y_is_u ? pr.U : pr.V;
     float* Ox = y_is_u ? pr.V : pr.U;
@@ -589,6 +644,8 @@ void finish_gram(Ctx& c, const Bufs& b, const Problem& pr, const float* Y, int64
     const int64_t ldox = y_is_u ? pr.ldv : pr.ldu, psox = y_is_u ? pr.vps : pr.ups;
     qg(c, desc(OP_NN, MATH_F64, Y, w, rows_y * w, 0, b.Lh, k, w * k, 1, Oy, ldoy, psoy, 0, rows_y, k, w));
     qg(c, desc(OP_NN, MATH_F64, X, ldx, rows_x * ldx, 0, b.Rh, lde, w * lde, 1, Ox, ldox, psox, 0, rows_x, k, w));
+    reorthonormalize(c, Oy, rows_y, k, ldoy, psoy, pr.S);
+    reorthonormalize(c, Ox, rows_x, k, ldox, psox, pr.S);
     if (c.live()) note(c, phase_launch(pr.U, pr.m, pr.ldu, pr.ups, pr.V, pr.n, pr.ldv, pr.vps, k, b.phase_work, c.st));
 }
 
@@ -1082,6 +1139,18 @@ int qlra_workspace_size(int64_t m, int64_t n, int k, int p, int pass_budget, int
 int qlra(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stride, int k, int p,
          int pass_budget, int scheme, uint64_t seed, const qlra_opts_t* opts, float* U, int64_t ldu,
          int64_t u_plane_stride, double* S, float* V, int64_t ldv, int64_t v_plane_stride, double* pass_err) {
+    return qlra_impl::solve_entry(A, m, n, lda, a_plane_stride, k, p, pass_budget, scheme, seed, opts, U, ldu,
+                                  u_plane_stride, S, V, ldv, v_plane_stride, pass_err, false);
+}
+
+}  // extern "C"
+
+namespace qlra_impl {
+
+int solve_entry(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stride, int k, int p,
+                int pass_budget, int scheme, uint64_t seed, const qlra_opts_t* opts, float* U, int64_t ldu,
+                int64_t u_plane_stride, double* S, float* V, int64_t ldv, int64_t v_plane_stride, double* pass_err,
+                bool no_alloc) {
     if (!opts) return QLRA_E_ARG;
     Problem pr{};
     pr.A = A; pr.m = m; pr.n = n; pr.lda = lda; pr.aps = a_plane_stride;
@@ -1112,7 +1181,8 @@ int qlra(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stri
     c.cnt_need = cnt;
     bind_ctx(c, b, d);
     Side sd;
-    const bool forks = pr.estimate && !merged_estimates(pr, d);
+    // without allocations the estimates run on the solve's own stream (no side stream is created)
+    const bool forks = pr.estimate && !merged_estimates(pr, d) && !no_alloc;
     if (forks) {
         if (get_side((hipStream_t)opts->stream, &sd) != hipSuccess) return QLRA_E_HIP;
         c.side = sd.s; c.ev_fork = sd.fork; c.ev_join = sd.join;
@@ -1124,7 +1194,7 @@ int qlra(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stri
             note(c, hipStreamWaitEvent(c.st, c.ev_join, 0));
         }
     };
-    if (!opts->graph) {
+    if (!opts->graph || no_alloc) {
         enqueue();
         return c.err == hipSuccess ? QLRA_OK : QLRA_E_HIP;
     }
@@ -1145,6 +1215,10 @@ int qlra(const float* A, int64_t m, int64_t n, int64_t lda, int64_t a_plane_stri
     if (ge != hipSuccess) return QLRA_E_HIP;
     return hipGraphLaunch(exec, (hipStream_t)opts->stream) == hipSuccess ? QLRA_OK : QLRA_E_HIP;
 }
+
+}  // namespace qlra_impl
+
+extern "C" {
 
 int qlra_status(const void* workspace, void* stream, int* status) {
     if (!workspace || !status) return QLRA_E_ARG;
@@ -1433,7 +1507,7 @@ int qlra_cholqr_workspace_size(int64_t m, int64_t w, size_t* bytes) {
 
 int qlra_cholqr(const float* Y, int64_t m, int64_t w, int64_t ldy, int64_t y_ps, float* Q, int64_t ldq,
                 int64_t q_ps, double* R, void* workspace, size_t workspace_bytes, void* stream) {
-    if (w < 1 || m < w || !R) return QLRA_E_ARG;
+    if (w < 1 || m < w) return QLRA_E_ARG;
     int rc;
     if ((rc = check_layout(Y, m, w, ldy, y_ps))) return rc;
     if ((rc = check_layout(Q, m, w, ldq, q_ps))) return rc;

@@ -393,17 +393,19 @@ def qlra_qgemm_split(op, precision, Alo, Alo_res, m, n, B, C=None, inv_scale=Non
     return C
 
 
-def qlra_cholqr(Y, Q=None, stream=None, return_workspace=False):
+def qlra_cholqr(Y, Q=None, stream=None, return_workspace=False, want_r=True):
+    """Thin QR of Y (4, m, w) FP32: returns (Q, R) (R None when want_r is False), and the
+    workspace (its status words) with return_workspace."""
     m, w = Y.shape[1], Y.shape[2]
     if Q is None:
         Q = torch.empty((4, m, w), dtype=torch.float32, device=Y.device)
-    R = torch.empty((4, w, w), dtype=torch.float64, device=Y.device)
+    R = torch.empty((4, w, w), dtype=torch.float64, device=Y.device) if want_r else None
     py, ldy, yps = _planes(Y, m, w, "Y")
     pq, ldq, qps = _planes(Q, m, w, "Q")
     need = ctypes.c_size_t()
     _check(_lib.qlra_cholqr_workspace_size(m, w, ctypes.byref(need)), "qlra_cholqr_workspace_size")
     ws = _workspace(need.value, Y.device)
-    _check(_lib.qlra_cholqr(py, m, w, ldy, yps, pq, ldq, qps, ctypes.c_void_p(R.data_ptr()),
+    _check(_lib.qlra_cholqr(py, m, w, ldy, yps, pq, ldq, qps, ctypes.c_void_p(R.data_ptr()) if want_r else None,
                             ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream_ptr(stream)), "qlra_cholqr")
     if return_workspace:
         return Q, R, ws

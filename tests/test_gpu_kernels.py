@@ -120,8 +120,9 @@ def test_cholqr_matches_householder(gq, oracle, m, w):
 
 @pytest.mark.parametrize("m,w", [(600, 20), (900, 130)])
 def test_cholqr_rank_deficient_uses_shift(gq, oracle, m, w):
-    """Exactly rank-deficient input: plain CholeskyQR breaks down; the shifted round keeps Q
-    orthonormal and Q R = Y (w = 130: the blocked factorization's gated rerun)."""
+    """Exactly rank-deficient input: plain CholeskyQR breaks down; the shifted round and the
+    rounds after it (gated on the shift flag) make Q orthonormal, and Q R = Y (w = 130: the
+    blocked factorization's gated rerun)."""
     print(f"cholqr rank 5, m={m} w={w}", flush=True)
     B = W.random_quat(3, m, 5)
     C = W.random_quat(4, 5, w)
@@ -130,7 +131,7 @@ def test_cholqr_rank_deficient_uses_shift(gq, oracle, m, w):
     Qg, Rg = host(Qg).astype(np.float64), host(Rg)
     gram = qref.mul(qref.adj(Qg), Qg)
     eye = np.zeros_like(gram); eye[0] = np.eye(w)
-    assert np.abs(gram - eye).max() < 1e-3
+    assert np.abs(gram - eye).max() < 1e-6
     np.testing.assert_allclose(qref.mul(Qg, Rg), Y, atol=1e-4 * np.abs(Y).max())
     flags = host(ws[:64].view(dtype=__import__("torch").int32))
     assert flags[1] == 1          # the first round was shifted

@@ -5,7 +5,7 @@ Tolerance (FP32 path): ||A_gpu - A_oracle||_F / ||A||_F <= 1e-5 for the rank-k
 approximation where the spectrum separates sigma_k from sigma_{k+1}; singular values to
 FP32 level; the per-pass estimates agree with the oracle's.  For the noise-dominated
 2048 x 2048 workload (noise std 0.01, so sigma_50 / sigma_51 of A is 1 + O(1e-3)) the rank-k
-truncation is ill-conditioned and the untruncated range is compared instead (see the test).
+truncation is ill-conditioned; the errors are compared as well, and the 1e-5 bound still holds.
 """
 import numpy as np
 import pytest
@@ -106,6 +106,11 @@ def test_config1_parity(gq, oracle, v):
     err_g = qref.fro(oracle_reconstruct(Ug, Sg, Vg) - A) / qref.fro(A)
     err_o = qref.fro(oracle_reconstruct(Uo, So, Vo) - A) / qref.fro(A)
     assert abs(err_g / err_o - 1) < 1e-4
+    # the specification's bound on the approximation itself holds here as well (measured
+    # about 3e-7 at every budget)
+    d = ahat_diff(A, (Ug, Sg, Vg), (Uo, So, Vo))
+    print(f"  ahat diff {d:.3e}", flush=True)
+    assert d <= 1e-5
 
 
 def test_config1_low_noise_ahat(gq, oracle):

@@ -180,3 +180,26 @@ def test_argument_errors(oracle):
     for args in [(0, 2, 2, 0), (3, -1, 2, 0), (3, 2, 1, 0), (7, 2, 2, 0), (3, 2, 3, 2), (3, 2, 2, 9)]:
         with pytest.raises(ValueError):
             oracle.qlra(A, *args, 0)
+
+
+@pytest.mark.parametrize("scheme,v", [(0, 2), (0, 3), (1, 4), (1, 5)])
+def test_canonical_phase_convention(oracle, scheme, v):
+    """The phase convention of the returned factors (a reading: the paper leaves the unit
+    quaternion phase of each singular pair free): in every column of V the entry of largest
+    modulus (lowest row on ties) is real and positive, and the same right factor is applied to
+    the column of U, so that A v_j = u_j s_j still holds (a phase taken from U, a negative real
+    entry, a left instead of a right multiplication or a phase applied to one side only all fail
+    one of these checks)."""
+    m, n, k = 60, 45, 6
+    sigma = np.concatenate([2.0 ** -np.arange(k), np.zeros(n - k)])
+    A = decaying(31, m, n, sigma)
+    U, S, V, _ = oracle.qlra(A, k, 4, v, scheme, 3)
+    mod = (V ** 2).sum(axis=0)
+    for j in range(k):
+        i = int(np.argmax(mod[:, j]))
+        q = V[:, i, j]
+        assert q[0] > 0.0 and np.abs(q[1:]).max() <= 1e-13 * q[0], (j, q)
+    # A V = U diag(S) column by column (exact rank k: the factors are exact up to rounding)
+    AV = qref.mul(A, V)
+    np.testing.assert_allclose(AV, U * S[None, None, :], atol=1e-12)
+    np.testing.assert_allclose(qref.mul(qref.adj(A), U), V * S[None, None, :], atol=1e-12)

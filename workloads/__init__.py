@@ -20,7 +20,8 @@ Workloads (stand-ins for the paper's experiments; no dataset item is used):
            [0, 1], plus U(-0.02, 0.02), clipped; real plane zero.  FP32.
   config4  dense 16384 x 16384, sigma_i = i^-1/2, unitaries that are products of
            8 random quaternion Householder reflectors and a random unit
-           quaternion diagonal.  FP32.
+           quaternion diagonal.  FP32, built on the host in a form whose bits do
+           not depend on the machine (reflector_spectrum_matrix).
   planted  A = B C with quaternion Gaussian B (m x r), C (r x n) (exact rank r).
 """
 import numpy as np
@@ -191,10 +192,116 @@ def spectrum_matrix(seed, m, n, sigma, nrefl=8, dtype=np.float32):
     return from_pair(Ma, Mb, dtype=dtype)
 
 
-def config4(seed=4, n=16384):
-    """Dense n x n, sigma_i = i^-1/2, reflector-product unitaries; FP32."""
+# Hamilton product (eq. (1)) as a table: plane p of a b is the sum of sign * a_q * b_r
+# over the entries (q, r, sign) of row p.
+_HT = (
+    ((0, 0, 1), (1, 1, -1), (2, 2, -1), (3, 3, -1)),
+    ((0, 1, 1), (1, 0, 1), (2, 3, 1), (3, 2, -1)),
+    ((0, 2, 1), (1, 3, -1), (2, 0, 1), (3, 1, 1)),
+    ((0, 3, 1), (1, 2, 1), (2, 1, -1), (3, 0, 1)),
+)
+
+
+def _pq(a, b):
+    """Elementwise quaternion product of broadcastable plane arrays (4, ...)."""
+    return np.stack([sum(s * a[q] * b[r] for q, r, s in _HT[p]) for p in range(4)])
+
+
+def _pconj(a):
+    return np.stack([a[0], -a[1], -a[2], -a[3]])
+
+
+def _pdot(a, b):
+    """sum_r conj(a_r) b_r of two quaternion vectors (planes (4, n)); every plane summed with
+    math.fsum (correctly rounded, so the same on any machine)."""
+    import math
+    pr = _pq(_pconj(a), b)
+    return np.array([math.fsum(pr[p]) for p in range(4)])
+
+
+def _compact_unitary(rng, n, nrefl):
+    """The unitary H_nrefl ... H_1 D of reflector_unitary_apply (same draws, same order) in the
+    form (I - W Z^H) D: returns d (4, n), W (4, n, nrefl) and Z^H (4, nrefl, n).  With
+    H_i = I - tau_i u_i u_i^H, prepending H_i to I - W Z^H appends u_i to W and the row
+    tau_i (u_i^H - (u_i^H W) Z^H) to Z^H."""
+    import math
+    q = rng.standard_normal((4, n))
+    d = q / np.linalg.norm(q, axis=0, keepdims=True)
+    Wm = np.zeros((4, n, nrefl))
+    ZH = np.zeros((4, nrefl, n))
+    for i in range(nrefl):
+        u = rng.standard_normal((4, n))
+        tau = 2.0 / math.fsum((u * u).ravel())
+        z = _pconj(u)
+        for c in range(i):
+            z = z - _pq(_pdot(u, Wm[:, :, c])[:, None], ZH[:, c, :])
+        ZH[:, i, :] = tau * z
+        Wm[:, :, i] = u
+    return d, Wm, ZH
+
+
+def reflector_spectrum_matrix(seed, m, n, sigma, nrefl=8, threads=8, block=32):
+    """U diag(sigma) V^H (m x n, FP32 planes) for the unitaries of spectrum_matrix (the same
+    random draws: U = H_nrefl ... H_1 D_u, then V likewise), built without forming U or V.
+
+    With U = (I - Wu Zu^H) D_u, V = (I - Wv Zv^H) D_v and the diagonal L = D_u diag(sigma) D_v^H,
+        A = L - Wu F - G Wv^H,   F = Zu^H L - (Zu^H L Zv) Wv^H,   G = L Zv,
+    a diagonal plus 2 nrefl quaternion outer products.  Every sum of more than a few terms is a
+    math.fsum and the outer products are accumulated in FP64 elementwise in a fixed order (no
+    BLAS), so the FP32 result is the same bits on any machine and for any thread count.  Rows
+    are built in blocks on `threads` threads (numpy releases the GIL)."""
+    import math
+    from concurrent.futures import ThreadPoolExecutor
+    rng = np.random.default_rng(seed)
+    r = min(m, n)
+    du, Wu, ZHu = _compact_unitary(rng, m, nrefl)
+    dv, Wv, ZHv = _compact_unitary(rng, n, nrefl)
+    lam = _pq(du[:, :r] * np.asarray(sigma[:r], dtype=np.float64)[None], _pconj(dv[:, :r]))   # (4, r)
+    ZHL = np.zeros((4, nrefl, n))
+    ZHL[:, :, :r] = _pq(ZHu[:, :, :r], lam[:, None, :])            # Zu^H L
+    Zv = np.transpose(_pconj(ZHv), (0, 2, 1))                         # (4, n, nrefl)
+    Cm = np.zeros((4, nrefl, nrefl))                                  # Zu^H L Zv
+    for a in range(nrefl):
+        for b in range(nrefl):
+            pr = _pq(ZHL[:, a, :], Zv[:, :, b])
+            Cm[:, a, b] = [math.fsum(pr[p]) for p in range(4)]
+    WvH = np.transpose(_pconj(Wv), (0, 2, 1))                         # (4, nrefl, n)
+    F = ZHL.copy()
+    for b in range(nrefl):
+        F = F - _pq(Cm[:, :, b][:, :, None], WvH[:, b, :][:, None, :])
+    G = np.zeros((4, m, nrefl))
+    G[:, :r, :] = _pq(lam[:, :, None], Zv[:, :r, :])                 # L Zv
+    Lf = np.ascontiguousarray(np.concatenate([Wu, G], axis=2))        # (4, m, 2 nrefl)
+    Rf = np.ascontiguousarray(np.concatenate([F, WvH], axis=1))       # (4, 2 nrefl, n)
+    out = np.empty((4, m, n), dtype=np.float32)
+
+    def rows(r0):
+        r1 = min(m, r0 + block)
+        acc = np.zeros((4, r1 - r0, n))
+        tmp = np.empty((r1 - r0, n))
+        for t in range(2 * nrefl):
+            for p in range(4):
+                for q, s_, sg in _HT[p]:
+                    np.multiply.outer(Lf[q, r0:r1, t], Rf[s_, t, :], out=tmp)
+                    if sg > 0:
+                        np.subtract(acc[p], tmp, out=acc[p])
+                    else:
+                        np.add(acc[p], tmp, out=acc[p])
+        d = np.arange(r0, min(r1, r))
+        for p in range(4):
+            acc[p, d - r0, d] += lam[p, d]
+            out[p, r0:r1] = acc[p]
+
+    with ThreadPoolExecutor(max(1, threads)) as ex:
+        list(ex.map(rows, range(0, m, block)))
+    return out
+
+
+def config4(seed=4, n=16384, threads=8):
+    """Dense n x n, sigma_i = i^-1/2, reflector-product unitaries; FP32.  Built on the host by
+    reflector_spectrum_matrix (the same bits on any machine)."""
     sigma = np.arange(1, n + 1, dtype=np.float64) ** -0.5
-    return spectrum_matrix(seed, n, n, sigma), sigma
+    return reflector_spectrum_matrix(seed, n, n, sigma, threads=threads), sigma
 
 
 def planted(seed, m, n, r, dtype=np.float64):
