@@ -222,6 +222,8 @@ int qlra_server_submit(qlra_server_t* server, const qlra_request_t* request, uin
  * which the ticket is forgotten. */
 int qlra_server_poll(qlra_server_t* server, uint64_t ticket, int wait, int* done, int* status,
                      double* latency_s);
+/* Block until the request is done, then report it as qlra_server_poll(wait = 1) does. */
+int qlra_server_wait(qlra_server_t* server, uint64_t ticket, int* status, double* latency_s);
 /* Block until every submitted request has completed. */
 int qlra_server_drain(qlra_server_t* server);
 int qlra_server_stats(qlra_server_t* server, qlra_server_stats_t* stats);
@@ -340,9 +342,15 @@ int qlra_cholqr(const float* Y, int64_t m, int64_t w, int64_t ldy, int64_t y_ps,
                 void* workspace, size_t workspace_bytes, void* stream);
 
 /* Full QSVD (eq. (qsvd)) of a small square quaternion matrix R (w x w, FP64
- * planes, ld = w, plane stride w*w) by one-sided Jacobi on its complex adjoint
- * kept in structure-preserving (quaternion) form: R = Uh diag(S) Vh^H, S
- * descending, Uh and Vh w x w (same layout).  FP64 throughout. */
+ * planes, ld = w, plane stride w*w): R = Uh diag(S) Vh^H, S descending, Uh and
+ * Vh w x w (same layout), FP64 throughout.  For w <= 96 it is taken from the
+ * Hermitian eigendecomposition of R^H R (Householder tridiagonalisation with
+ * quaternion reflectors): S_j = sqrt(lambda_j), Vh the eigenvectors, Uh =
+ * R Vh diag(1/S); the eigenvalues carry an absolute error of about
+ * u64 S_1^2, so S_j is accurate to about u64 S_1^2 / S_j (relative accuracy
+ * for S_j >> sqrt(u64) S_1) and Uh's columns of negligible S_j are not
+ * meaningful.  Above 96, by one-sided Jacobi on the complex adjoint kept in
+ * structure-preserving (quaternion) form, accurate to u64 S_1 in every S_j. */
 int qlra_qsvd_workspace_size(int64_t w, size_t* bytes);
 int qlra_qsvd(const double* R, int64_t w, double* Uh, double* S, double* Vh,
               void* workspace, size_t workspace_bytes, void* stream);

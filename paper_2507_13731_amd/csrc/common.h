@@ -50,6 +50,7 @@ struct QgemmDesc {
     double* fro2_part;         // FP32 A X only (optional): per-wave sums of squares of A, fro2_slots(d) entries
     int b_real;                // FP32 views: B has zero imaginary planes (only its real plane is read)
     const void* A_lo;          // split forms: the residual copy of A
+    int b_upper;               // FP64 A B: B is upper triangular (rows below a column's diagonal are not read)
 };
 
 // Device workspace carved into aligned regions.
@@ -57,13 +58,14 @@ struct Arena {
     char* base;
     size_t size;
     size_t used;
-    bool dry;   // sizing pass: count only
+    bool dry;   // sizing pass: count only; regions get placeholder addresses (never dereferenced)
     void* take(size_t bytes) {
         size_t off = (used + 255) & ~size_t(255);
         used = off + ((bytes + 255) & ~size_t(255));
-        if (dry) return nullptr;
+        if (dry) return reinterpret_cast<void*>(static_cast<uintptr_t>(kDryBase + off));
         return base + off;
     }
+    static constexpr uintptr_t kDryBase = uintptr_t(1) << 44;
 };
 
 // Scratch a qgemm launch needs: split-K partials and per-tile counters.
@@ -83,9 +85,12 @@ hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t s
 // four planes per tile; lowp_copy_elems(rows, k) elements each, padding zero).
 size_t lowp_copy_elems(int64_t rows, int64_t k);
 // Ar, Ar_t (both or neither): the residual copies (s a - (float)(rounded s a), rounded), written in
-// the same pass; Alo = Alo_t = null with Ar given: the residual copies alone.
+// the same pass; Alo = Alo_t = null with Ar given: the residual copies alone.  fro (optional):
+// lowp_copy_fro_slots(m, n) partial sums of squares of A, summed by fro2_final_launch.
+size_t lowp_copy_fro_slots(int64_t m, int64_t n);
 hipError_t lowp_copy_launch(const float* A, int64_t m, int64_t n, int64_t lda, int64_t aps, int prec, void* Alo,
-                            void* Alo_t, const float* scale, hipStream_t st, void* Ar = nullptr, void* Ar_t = nullptr);
+                            void* Alo_t, const float* scale, hipStream_t st, void* Ar = nullptr, void* Ar_t = nullptr,
+                            double* fro = nullptr);
 // FP16 scale from ||A||_F^2 (nA2): scale = 2^e with e = 14 - ceil(log2 ||A||_F) (so that every
 // |a| * scale <= 2^14), inv = 1 / scale; BF16: scale = inv = 1.
 hipError_t lowp_scale_launch(const double* nA2, int prec, float* scale, float* inv, hipStream_t st);

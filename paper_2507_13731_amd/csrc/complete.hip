@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void k_complete_step(StepArgs a) {
             sv[e % kRC][e / kRC] = v[s];
         }
         __syncthreads();
-#pragma unroll 4
+#pragma unroll 1
         for (int r = 0; r < kRC; r++) {
             f32x4 uu[3], vv[3];
 #pragma unroll

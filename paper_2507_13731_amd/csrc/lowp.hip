@@ -31,16 +31,20 @@ __device__ __forceinline__ int64_t tiled_index(int64_t row, int64_t k, int p, in
 // one 64 x 64 tile of A (rows r0.., columns c0..), one plane at a time through a 16.6 KB LDS
 // tile; the grid covers the padded extents (multiples of 64) so that padding is written as zeros.
 // MODE 0: the copies Alo / Alo_t; 1: also the residual copies (x - (float)(TL)x, rounded) into
-// Ar / Ar_t in the same pass; 2: the residual copies alone (into Ar / Ar_t).
+// Ar / Ar_t in the same pass; 2: the residual copies alone (into Ar / Ar_t).  fro (optional): the
+// tile's sum of squares of A (FP64, the values before scaling) into fro[blockIdx.y * gridDim.x +
+// blockIdx.x], so that the pass also yields ||A||_F^2.
 template <class TL, int MODE>
 __global__ __launch_bounds__(256) void k_lowp_copy(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda,
                                                    int64_t aps, TL* __restrict__ Alo, TL* __restrict__ Alo_t,
                                                    TL* __restrict__ Ar, TL* __restrict__ Ar_t,
-                                                   const float* __restrict__ scale) {
+                                                   const float* __restrict__ scale, double* __restrict__ fro) {
     __shared__ float tile[kT][kT + 1];
+    __shared__ double red[4];
     const int64_t r0 = (int64_t)blockIdx.y * kT, c0 = (int64_t)blockIdx.x * kT;
     const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;   // 64 x 4
     const float s = scale ? *scale : 1.0f;
+    double sq = 0.0;
     const int64_t KTn = (n + 63) / 64, KTm = (m + 63) / 64;      // reduction tiles of Alo, Alo_t
     const int rtiles_m = (int)(((m + 15) >> 4) - (r0 >> 4)) < 4 ? (int)(((m + 15) >> 4) - (r0 >> 4)) : 4;
     const int rtiles_n = (int)(((n + 15) >> 4) - (c0 >> 4)) < 4 ? (int)(((n + 15) >> 4) - (c0 >> 4)) : 4;
@@ -50,7 +54,9 @@ __global__ __launch_bounds__(256) void k_lowp_copy(const float* __restrict__ A, 
 #pragma unroll
         for (int u = 0; u < kT / 4; u++) {
             const int64_t r = r0 + ty + 4 * u, c = c0 + tx;
-            v[u] = (r < m && c < n) ? A[p * aps + r * lda + c] * s : 0.0f;
+            const float a = (r < m && c < n) ? A[p * aps + r * lda + c] : 0.0f;
+            if (fro) sq += (double)a * (double)a;
+            v[u] = a * s;
         }
 #pragma unroll
         for (int u = 0; u < kT / 4; u++) tile[ty + 4 * u][tx] = v[u];
@@ -79,6 +85,13 @@ __global__ __launch_bounds__(256) void k_lowp_copy(const float* __restrict__ A, 
                 if constexpr (MODE != 0) Ar_t[at] = (TL)(x - (float)hi);
             }
     }
+    if (fro) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = sq;
+        __syncthreads();
+        if (tid == 0) fro[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = ((red[0] + red[1]) + red[2]) + red[3];
+    }
 }
 
 __global__ void k_lowp_scale(const double* __restrict__ nA2, int fp16, float* __restrict__ scale,
@@ -100,8 +113,10 @@ __global__ void k_lowp_scale(const double* __restrict__ nA2, int fp16, float* __
 
 }  // namespace
 
+size_t lowp_copy_fro_slots(int64_t m, int64_t n) { return (size_t)((n + kT - 1) / kT) * ((m + kT - 1) / kT); }
+
 hipError_t lowp_copy_launch(const float* A, int64_t m, int64_t n, int64_t lda, int64_t aps, int prec, void* Alo,
-                            void* Alo_t, const float* scale, hipStream_t st, void* Ar, void* Ar_t) {
+                            void* Alo_t, const float* scale, hipStream_t st, void* Ar, void* Ar_t, double* fro) {
     if (m <= 0 || n <= 0) return hipSuccess;
     if ((Ar == nullptr) != (Ar_t == nullptr) || (Alo == nullptr) != (Alo_t == nullptr) || (!Alo && !Ar))
         return hipErrorInvalidValue;
@@ -109,7 +124,7 @@ hipError_t lowp_copy_launch(const float* A, int64_t m, int64_t n, int64_t lda, i
     const int mode = !Ar ? 0 : (Alo ? 1 : 2);
 #define QL_COPY(TL_, M_) \
     hipLaunchKernelGGL((k_lowp_copy<TL_, M_>), grid, dim3(256), 0, st, A, m, n, lda, aps, (TL_*)Alo, (TL_*)Alo_t, \
-                       (TL_*)Ar, (TL_*)Ar_t, scale)
+                       (TL_*)Ar, (TL_*)Ar_t, scale, fro)
     if (prec == QLRA_BF16 || prec == QLRA_BF16_SPLIT) {
         if (mode == 0) QL_COPY(__bf16, 0);
         else if (mode == 1) QL_COPY(__bf16, 1);

@@ -79,6 +79,9 @@ struct KParams {
     int store;
     int avec, bvec;      // 4-element vector loads allowed for A / B
     const int* skip;
+    int sym;             // Hermitian Gram A^H A (B = A, square tiles): only tiles on or above the
+                         // diagonal are computed, the others are their conjugate transposes
+    int b_upper;         // B upper triangular: a column tile's reduction stops at its last column
 };
 
 // Four consecutive elements (along the contiguous dimension) of a plane, zero outside
@@ -115,6 +118,7 @@ __global__ __launch_bounds__(256) void k_qgemm(KParams P) {
     __shared__ __attribute__((aligned(16))) T sB[4 * BK * BST];
 
     if (P.skip && *P.skip == 0) return;
+    if (P.sym && blockIdx.x > blockIdx.y) return;     // below the diagonal: the mirror of (y, x)
     using M_ = Mma<T>;
     using acc_t = typename M_::acc_t;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -122,7 +126,8 @@ __global__ __launch_bounds__(256) void k_qgemm(KParams P) {
     const int64_t row0 = (int64_t)blockIdx.x * BM, col0 = (int64_t)blockIdx.y * BN;
     const int split = blockIdx.z;
     const int64_t kb = (int64_t)split * P.kchunk;
-    const int64_t ke = P.K < kb + P.kchunk ? P.K : kb + P.kchunk;
+    int64_t ke = P.K < kb + P.kchunk ? P.K : kb + P.kchunk;
+    if (P.b_upper && ke > col0 + BN) ke = col0 + BN;   // B(k, c) = 0 for k > c
     const TA* __restrict__ A = (const TA*)P.A;
     const TB* __restrict__ B = (const TB*)P.B;
     const bool avec = P.avec != 0, bvec = P.bvec != 0;
@@ -251,6 +256,8 @@ __global__ __launch_bounds__(256) void k_qgemm(KParams P) {
                             TC* dst = C + p * P.cps + r * P.ldc + c;
                             const T v = acc[rm][cn][p][i];
                             *dst = P.store == ST_SUB ? (TC)((T)*dst - v) : (TC)v;
+                            // an off-diagonal tile of a Hermitian Gram also gives (c, r) = conj(r, c)
+                            if (P.sym && blockIdx.x < blockIdx.y) C[p * P.cps + c * P.ldc + r] = (TC)(p ? -v : v);
                         }
                     }
                 }
@@ -275,10 +282,12 @@ __global__ __launch_bounds__(256) void k_qgemm(KParams P) {
 // C (M x N, 4 planes) = sum over splits of the partial tiles.  Eight lanes per output entry
 // each add every eighth split in order, then the eight sums are combined in a fixed tree:
 // deterministic, and enough independent loads in flight to stream the partials.
+// sym_bm > 0 (a Hermitian Gram with square tiles of sym_bm): an entry whose tile lies below the
+// diagonal is the conjugate of its mirror entry, whose partials were computed.
 template <class T, class TC>
 __global__ __launch_bounds__(256) void k_splitk_reduce(const T* __restrict__ part, int splits, int64_t Mp, int64_t Np,
                                                        TC* __restrict__ C, int64_t ldc, int64_t cps, int64_t M,
-                                                       int64_t N, int store, const int* skip) {
+                                                       int64_t N, int store, const int* skip, int sym_bm) {
     if (skip && *skip == 0) return;
     const int64_t total = 4 * M * N;
     const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
@@ -286,17 +295,20 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const T* __restrict__ par
     const bool act = e < total;
     T s = 0;
     int64_t p = 0, r = 0, c = 0;
+    bool mirror = false;
     if (act) {
         p = e / (M * N);
         const int64_t rem = e - p * M * N;
         r = rem / N;
         c = rem - r * N;
+        mirror = sym_bm > 0 && r / sym_bm > c / sym_bm;
         const int64_t stride = 4 * Mp * Np;
-        const T* src = part + (p * Mp + r) * Np + c;
+        const T* src = part + (p * Mp + (mirror ? c : r)) * Np + (mirror ? r : c);
         for (int sp = sub; sp < splits; sp += 8) s += src[sp * stride];
     }
 #pragma unroll
     for (int o = 1; o < 8; o <<= 1) s += __shfl_xor(s, o, 64);
+    if (mirror && p != 0) s = -s;
     if (act && sub == 0) {
         TC* dst = C + p * cps + r * ldc + c;
         *dst = store == ST_SUB ? (TC)((T)*dst - s) : (TC)s;
@@ -307,15 +319,18 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const T* __restrict__ par
 template <class T, class TC>
 __global__ __launch_bounds__(256) void k_splitk_reduce_few(const T* __restrict__ part, int splits, int64_t Mp,
                                                            int64_t Np, TC* __restrict__ C, int64_t ldc, int64_t cps,
-                                                           int64_t M, int64_t N, int store, const int* skip) {
+                                                           int64_t M, int64_t N, int store, const int* skip,
+                                                           int sym_bm) {
     if (skip && *skip == 0) return;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= 4 * M * N) return;
     const int64_t p = e / (M * N), rem = e - p * M * N, r = rem / N, c = rem - r * N;
+    const bool mirror = sym_bm > 0 && r / sym_bm > c / sym_bm;
     const int64_t stride = 4 * Mp * Np;
-    const T* src = part + (p * Mp + r) * Np + c;
+    const T* src = part + (p * Mp + (mirror ? c : r)) * Np + (mirror ? r : c);
     T s = src[0];
     for (int sp = 1; sp < splits; sp++) s += src[sp * stride];
+    if (mirror && p != 0) s = -s;
     TC* dst = C + p * cps + r * ldc + c;
     *dst = store == ST_SUB ? (TC)((T)*dst - s) : (TC)s;
 }
@@ -348,7 +363,7 @@ hipError_t reduce_f32(const float* part, int splits, int64_t Mp, int64_t Np, flo
     } else {
         const int64_t total = 8 * 4 * M * N;
         hipLaunchKernelGGL((k_splitk_reduce<float, float>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                           part, splits, Mp, Np, C, ldc, cps, M, N, store, skip);
+                           part, splits, Mp, Np, C, ldc, cps, M, N, store, skip, 0);
     }
     return hipGetLastError();
 }
@@ -531,7 +546,7 @@ __global__ __launch_bounds__(256, CN <= 3 ? 2 : 1) void k_qview(VParams P) {
         // steps in pairs with ping-pong registers (no copies); a step past the last full one
         // reloads the last (in bounds, unused)
         const int64_t kl = kb + (nfull - 1) * VBK;
-#pragma unroll 4
+#pragma unroll 1
         for (int64_t st = 0; st < nfull; st += 2) {
             const int64_t k0 = kb + st * VBK;
             const int64_t k1 = k0 + VBK <= kl ? k0 + VBK : kl;
@@ -629,6 +644,12 @@ struct Plan {
 
 constexpr int kCUs = 256;
 
+// A Hermitian Gram X^H X: the same operand on both sides, a square output set outright.
+bool is_sym_gram(const QgemmDesc& d) {
+    return d.math == MATH_F64 && d.op == OP_HN && d.A == d.B && d.lda == d.ldb && d.aps == d.bps &&
+           d.a_f64 == d.b_f64 && d.M == d.N && d.store == ST_SET;
+}
+
 Plan make_plan(const QgemmDesc& d) {
     Plan p{};
     if (d.op == OP_HN) {
@@ -644,7 +665,8 @@ Plan make_plan(const QgemmDesc& d) {
     p.gy = (d.N + BN - 1) / BN;
     p.Mp = p.gx * BM;
     p.Np = p.gy * BN;
-    const int64_t tiles = p.gx * p.gy;
+    // a Hermitian Gram computes the tiles on and above the diagonal only
+    const int64_t tiles = is_sym_gram(d) ? p.gx * (p.gx + 1) / 2 : p.gx * p.gy;
     // split K so that about one workgroup per CU runs, each over at least 2 K steps
     const int64_t min_steps = 2;
     const int64_t target = kCUs;
@@ -672,17 +694,18 @@ hipError_t launch_t(const Plan& pl, const KParams& kp, hipStream_t st) {
     if constexpr (std::is_same<T, float>::value && std::is_same<TC, float>::value)
         return reduce_f32((const float*)kp.part, (int)pl.splits, pl.Mp, pl.Np, (float*)kp.C, kp.ldc, kp.cps, kp.M,
                           kp.N, kp.store, kp.skip, st);
+    const int sym_bm = kp.sym ? WM * RM * 16 : 0;
     if (pl.splits <= 8) {
         const int64_t total = 4 * kp.M * kp.N;
         hipLaunchKernelGGL((k_splitk_reduce_few<T, TC>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
                            (const T*)kp.part, (int)pl.splits, pl.Mp, pl.Np, (TC*)kp.C, kp.ldc, kp.cps, kp.M, kp.N,
-                           kp.store, kp.skip);
+                           kp.store, kp.skip, sym_bm);
         return hipGetLastError();
     }
     const int64_t total = 8 * 4 * kp.M * kp.N;
     hipLaunchKernelGGL((k_splitk_reduce<T, TC>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
                        (const T*)kp.part, (int)pl.splits, pl.Mp, pl.Np, (TC*)kp.C, kp.ldc, kp.cps, kp.M, kp.N,
-                       kp.store, kp.skip);
+                       kp.store, kp.skip, sym_bm);
     return hipGetLastError();
 }
 
@@ -862,22 +885,24 @@ __global__ __launch_bounds__(256) void k_lp_thin_res(const float* __restrict__ B
 }
 
 // Workgroup: 4 row groups of 16 rows x NCG column groups of CNW column tiles (16 columns each).
-// Software pipeline: an iteration covers two K steps (LKS = 128 reduction elements).  Its thin
-// tile was loaded into registers during the previous iteration and sits in LDS; the A fragments
-// of a step are loaded two steps ahead into the ping-pong register sets aX (even steps) and aY
-// (odd steps), always issued after the thin-tile loads, so that waiting for those (vmcnt counts
-// in issue order) never waits for A.  Every load is unconditional (addresses clamped into the
-// copies; a step past the end of K meets zero rows of the padded thin tile), so the wait
-// counts stay exact across iterations.
+// Software pipeline: an iteration covers two K steps (LKS = 128 reduction elements).  The thin
+// tile of LK reduction elements (LK = LKS: both steps; LK = LBK: one step, staged twice per
+// iteration, for wide column tiles whose two-step tile would not fit in LDS) was loaded into
+// registers before and sits in LDS; the A fragments of a step are loaded two steps ahead into
+// the ping-pong register sets aX (even steps) and aY (odd steps), always issued after the
+// thin-tile loads, so that waiting for those (vmcnt counts in issue order) never waits for A.
+// Every load is unconditional (addresses clamped into the copies; a step past the end of K
+// meets zero rows of the padded thin tile), so the wait counts stay exact across iterations.
 constexpr int LKS = 2 * LBK;
-template <class TL, bool ADJ, int CN, int NCG, int CNW>
+template <class TL, bool ADJ, int CN, int NCG, int CNW, int LK>
 __global__ __launch_bounds__(256 * NCG) void k_qgemm_lp(LpParams P) {
     using L = LpMma<TL>;
     using v8 = typename L::v8;
+    static_assert(LK == LKS || LK == LBK, "thin tile of one or two K steps");
     constexpr int NP = 16 * CN;
-    constexpr int SK = LKS + 8;                   // LDS row stride of the staged tile (elements)
+    constexpr int SK = LK + 8;                    // LDS row stride of the staged tile (elements)
     constexpr int NT = 256 * NCG;
-    constexpr int CH = 4 * NP * (LKS / 8);        // 16-byte chunks of one thin tile
+    constexpr int CH = 4 * NP * (LK / 8);         // 16-byte chunks of one thin tile
     constexpr int CPT = CH / NT;                  // chunks per thread
     static_assert(CH % NT == 0, "whole chunks per thread");
     __shared__ __attribute__((aligned(16))) TL sB[4 * NP * SK];
@@ -904,13 +929,13 @@ __global__ __launch_bounds__(256 * NCG) void k_qgemm_lp(LpParams P) {
 #pragma unroll
             for (int h = 0; h < 2; h++) a[q][h] = *reinterpret_cast<const v8*>(src + q * 1024 + h * 512);
     };
-    // the thin tile of reduction elements [k0, k0 + LKS): chunk e -> row (p * NP + c), 8 elements
+    // the thin tile of reduction elements [k0, k0 + LK): chunk e -> row (p * NP + c), 8 elements
     // at 8 * ch (Bt is padded to a multiple of LKS)
     auto load_b = [&](int64_t k0, v8 (&bt)[CPT]) {
 #pragma unroll
         for (int u = 0; u < CPT; u++) {
             const int e = tid + u * NT;
-            const int row = e / (LKS / 8), ch = e - row * (LKS / 8);
+            const int row = e / (LK / 8), ch = e - row * (LK / 8);
             const int p = row / NP, c = row - p * NP;
             bt[u] = *reinterpret_cast<const v8*>(Bt + ((int64_t)p * P.Np + col0 + c) * P.bkp + k0 + 8 * ch);
         }
@@ -919,7 +944,7 @@ __global__ __launch_bounds__(256 * NCG) void k_qgemm_lp(LpParams P) {
 #pragma unroll
         for (int u = 0; u < CPT; u++) {
             const int e = tid + u * NT;
-            const int row = e / (LKS / 8), ch = e - row * (LKS / 8);
+            const int row = e / (LK / 8), ch = e - row * (LK / 8);
             *reinterpret_cast<v8*>(&sB[row * SK + 8 * ch]) = bt[u];
         }
     };
@@ -963,15 +988,34 @@ __global__ __launch_bounds__(256 * NCG) void k_qgemm_lp(LpParams P) {
     __syncthreads();
     for (int64_t k0 = kb; k0 < ke; k0 += LKS) {
         const bool more = k0 + LKS < ke;
-        load_b(more ? k0 + LKS : k0, bt);
-        step(aX, 0);
-        load_a(k0 + LKS, aX);
-        step(aY, LBK);
-        load_a(k0 + LKS + LBK, aY);
-        if (more) {
-            __syncthreads();   // every wave is done with the staged tile
+        if constexpr (LK == LKS) {
+            load_b(more ? k0 + LKS : k0, bt);
+            step(aX, 0);
+            load_a(k0 + LKS, aX);
+            step(aY, LBK);
+            load_a(k0 + LKS + LBK, aY);
+            if (more) {
+                __syncthreads();   // every wave is done with the staged tile
+                store_b(bt);
+                __syncthreads();
+            }
+        } else {
+            // one K step per staged tile: the second step of the iteration (within the padded
+            // thin operand: kchunk is a multiple of LKS) is staged after the first
+            load_b(k0 + LBK, bt);
+            step(aX, 0);
+            load_a(k0 + LKS, aX);
+            __syncthreads();
             store_b(bt);
             __syncthreads();
+            load_b(more ? k0 + LKS : k0, bt);
+            step(aY, 0);
+            load_a(k0 + LKS + LBK, aY);
+            if (more) {
+                __syncthreads();
+                store_b(bt);
+                __syncthreads();
+            }
         }
     }
     const float sc = P.cscale ? *P.cscale : 1.0f;
@@ -996,18 +1040,20 @@ __global__ __launch_bounds__(256 * NCG) void k_qgemm_lp(LpParams P) {
     }
 }
 
-// column groups per workgroup and column tiles per wave for CN column tiles
+// column groups per workgroup, column tiles per wave and the staged reduction depth for CN
+// column tiles (beyond 6 tiles, one K step per staged tile keeps it within LDS)
 constexpr int lp_ncg(int cn) { return cn <= 2 ? 1 : 2; }
 constexpr int lp_cnw(int cn) { return (cn + lp_ncg(cn) - 1) / lp_ncg(cn); }
+constexpr int lp_lk(int cn) { return cn <= 6 ? LKS : LBK; }
 
 struct LpPlan {
     int CN;                 // column tiles of 16 per workgroup
     int64_t gx, gy, splits, kchunk, Mp, Np, Kp;
 };
 
-// up to 96 columns per workgroup (wider thin blocks: column tiles as even as possible, A read
+// up to 160 columns per workgroup (wider thin blocks: column tiles as even as possible, A read
 // once per column tile)
-constexpr int kLpMaxCols = 96;
+constexpr int kLpMaxCols = 160;
 
 LpPlan make_lp_plan(const QgemmDesc& d) {
     LpPlan p{};
@@ -1055,9 +1101,11 @@ hipError_t launch_lp(const QgemmDesc& d, const LpPlan& pl, void* scratch, hipStr
     dim3 grid((unsigned)pl.gx, (unsigned)pl.gy, (unsigned)pl.splits);
 #define QL_LP(CN_) \
     if (pl.CN == CN_) \
-        hipLaunchKernelGGL((k_qgemm_lp<TL, ADJ, CN_, lp_ncg(CN_), lp_cnw(CN_)>), grid, dim3(256 * lp_ncg(CN_)), 0, st, P); \
+        hipLaunchKernelGGL((k_qgemm_lp<TL, ADJ, CN_, lp_ncg(CN_), lp_cnw(CN_), lp_lk(CN_)>), grid, \
+                           dim3(256 * lp_ncg(CN_)), 0, st, P); \
     else
-    QL_LP(1) QL_LP(2) QL_LP(3) QL_LP(4) QL_LP(5) QL_LP(6) return hipErrorInvalidValue;
+    QL_LP(1) QL_LP(2) QL_LP(3) QL_LP(4) QL_LP(5) QL_LP(6) QL_LP(7) QL_LP(8) QL_LP(9) QL_LP(10)
+    return hipErrorInvalidValue;
 #undef QL_LP
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || pl.splits == 1) return e;
@@ -1102,9 +1150,11 @@ hipError_t launch_lp3(const QgemmDesc& d, const LpPlan& pl, void* scratch, hipSt
         P.cscale = d.cscale;
 #define QL_LP3(CN_) \
         if (pl.CN == CN_) \
-            hipLaunchKernelGGL((k_qgemm_lp<TL, ADJ, CN_, lp_ncg(CN_), lp_cnw(CN_)>), grid, dim3(256 * lp_ncg(CN_)), 0, st, P); \
+            hipLaunchKernelGGL((k_qgemm_lp<TL, ADJ, CN_, lp_ncg(CN_), lp_cnw(CN_), lp_lk(CN_)>), grid, \
+                               dim3(256 * lp_ncg(CN_)), 0, st, P); \
         else
-        QL_LP3(1) QL_LP3(2) QL_LP3(3) QL_LP3(4) QL_LP3(5) QL_LP3(6) return hipErrorInvalidValue;
+        QL_LP3(1) QL_LP3(2) QL_LP3(3) QL_LP3(4) QL_LP3(5) QL_LP3(6) QL_LP3(7) QL_LP3(8) QL_LP3(9) QL_LP3(10)
+        return hipErrorInvalidValue;
 #undef QL_LP3
     }
     hipError_t e = hipGetLastError();
@@ -1171,6 +1221,8 @@ hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t s
     kp.skip = d.skip_flag;
     kp.avec = vec_ok(d.A, d.lda, d.aps, d.a_f64 ? 8 : 4);
     kp.bvec = vec_ok(d.B, d.ldb, d.bps, d.b_f64 ? 8 : 4);
+    kp.sym = is_sym_gram(d) ? 1 : 0;
+    kp.b_upper = d.b_upper;
     if (pl.splits > 1 && !s.partial) return hipErrorInvalidValue;
     // FP64 arithmetic
     if (d.op == OP_HN) {

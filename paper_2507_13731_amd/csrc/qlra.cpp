@@ -22,6 +22,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "arena_alloc.h"
 #include "common.h"
 
 namespace qlra_impl {
@@ -179,7 +180,9 @@ void cholqr_round_gated(Ctx& c, float* X, int64_t rows, int64_t w, int64_t ldx, 
         return;
     }
     chol_blocked(c, c.G, w, c.R1, c.Rinv, R, nullptr, 1, shift_scale(rows, w), gate);
-    qg(c, desc(OP_NN, MATH_F64, X, ldx, xps, 0, c.Rinv, w, ps, 1, c.T2, w, rows * w, 0, rows, w, w, ST_SET, gate));
+    QgemmDesc ap = desc(OP_NN, MATH_F64, X, ldx, xps, 0, c.Rinv, w, ps, 1, c.T2, w, rows * w, 0, rows, w, w, ST_SET, gate);
+    ap.b_upper = 1;                            // R^{-1} is upper triangular
+    qg(c, ap);
     if (c.live()) {
         note(c, copy_planes_launch(c.T2, w, rows * w, X, ldx, xps, rows, w, gate, c.st));
         if (R) note(c, rcopy_launch(c.R1, R, w, gate, c.st));
@@ -239,18 +242,20 @@ void cholqr(Ctx& c, const float* Y, int64_t rows, int64_t w, int64_t ldy, int64_
                 chol_blocked(c, G, w, Rout, c.Rinv, Rprev, round == 0 ? shifted : nullptr, round == 0 ? 1 : 0,
                              shift_scale(rows, w));
             }
-            qg(c, desc(OP_NN, MATH_F64, src, lds, sps, 0, c.Rinv, w, w * w, 1, dst, ldd, dps, 0, rows, w, w));
+            QgemmDesc ap = desc(OP_NN, MATH_F64, src, lds, sps, 0, c.Rinv, w, w * w, 1, dst, ldd, dps, 0, rows, w, w);
+            ap.b_upper = 1;                        // R^{-1} is upper triangular
+            qg(c, ap);
             Rprev = Rout;
         }
         src = dst; lds = ldd; sps = dps;
     }
     if (small && rounds == 2 && R && c.live()) note(c, rmul_launch(c.R2, c.R1, R, w, nullptr, c.st));
-    // A shifted first round leaves Q with a condition number up to about u^{-1/2}: shifted
-    // CholeskyQR is followed by CholeskyQR2 (Fukaya et al. 2020), so after a shifted round two
-    // more rounds (one after a two-round call) run on Q in place, gated on the device by the
-    // shift flag (nothing is launched into the kernels' work when it is 0).
-    if (shifted || c.dry)
-        for (int e = 0; e < (rounds == 1 ? 2 : 1); e++) cholqr_round_gated(c, Q, rows, w, ldq, qps, R, shifted);
+    // A shifted first round leaves Q with a condition number up to about
+    // (11 (rows w + w (w + 1)) u64)^{-1/2}, 1e4 to 1e5 at the sizes here: one more round, in place
+    // and gated on the device by the shift flag (its launches do nothing when it is 0), brings
+    // the loss of orthogonality to about u64 cond^2 (shifted CholeskyQR followed by CholeskyQR,
+    // three rounds in all for the two-round calls as in Fukaya et al. 2020).
+    if (shifted || c.dry) cholqr_round_gated(c, Q, rows, w, ldq, qps, R, shifted);
 }
 
 // A returned factor of the final QSVD from the Gram (rows x k, in place): the Y side Y E_k S^{-1}
@@ -335,6 +340,12 @@ void orient(Problem& pr, int transpose) {
     std::swap(pr.ups, pr.vps);
 }
 
+// The reduced-precision forms copy A once at the start; for BF16 (scale 1, not derived from the
+// norm) that pass also forms ||A||_F^2.
+bool fro_in_copy(const Problem& pr) {
+    return (pr.prec == QLRA_BF16 && pr.v > 2) || pr.prec == QLRA_BF16_SPLIT;
+}
+
 struct Dims {
     int64_t l, Wk, wmax, rows_max, stack_rows;
     bool krylov, even;
@@ -403,7 +414,9 @@ void carve(const Problem& pr, const Dims& d, Arena& ar, Bufs& b, size_t part_byt
         // ||A||_F^2: partial sums of the separate pass (<= 1024) or of the first view's waves
         QgemmDesc v1{};
         v1.op = OP_NN; v1.math = MATH_F32; v1.M = pr.m; v1.N = d.l; v1.K = pr.n;
-        b.fro_part = (double*)ar.take(std::max<size_t>(1024, fro2_slots(v1)) * sizeof(double));
+        size_t slots = std::max<size_t>(1024, fro2_slots(v1));
+        if (fro_in_copy(pr)) slots = std::max(slots, lowp_copy_fro_slots(pr.mr, pr.nr));
+        b.fro_part = (double*)ar.take(slots * sizeof(double));
     }
     b.Om = (float*)ar.take(4 * pr.n * d.l * sizeof(float));
     b.Q1 = (float*)ar.take(4 * pr.m * d.wmax * sizeof(float));
@@ -698,13 +711,16 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
     if (c.live()) {
         note(c, solve_prologue_launch(b.status, 16, b.counters, (int64_t)std::max<size_t>(c.cnt_need, 1),
                                       pr.estimate ? pr.pass_err : nullptr, c.st));
-        if (fro_apart) note(c, fro2_launch(pr.A, pr.mr, pr.nr, pr.lda, pr.aps, b.fro_part, b.nA2, c.st));
+        const bool in_copy = b.Alo && fro_in_copy(pr);
+        if (fro_apart && !in_copy) note(c, fro2_launch(pr.A, pr.mr, pr.nr, pr.lda, pr.aps, b.fro_part, b.nA2, c.st));
         if (pr.sketch == QLRA_SKETCH_SRHT) note(c, omega_srht_launch(pr.seed, pr.n, l, b.Om, l, pr.n * l, c.st));
         else note(c, omega_launch(pr.seed, pr.n, l, b.Om, l, pr.n * l, c.st, pr.sketch == QLRA_SKETCH_REAL ? 1 : 0));
         if (b.Alo) {
             note(c, lowp_scale_launch(b.nA2, pr.prec, b.lp_scale, b.lp_scale + 1, c.st));
             note(c, lowp_copy_launch(pr.A, pr.mr, pr.nr, pr.lda, pr.aps, pr.prec, b.Alo, b.Alo_t, b.lp_scale, c.st,
-                                     b.Alo_lo, b.Alo_t_lo));
+                                     b.Alo_lo, b.Alo_t_lo, in_copy ? b.fro_part : nullptr));
+            if (in_copy)
+                note(c, fro2_final_launch(b.fro_part, (int64_t)lowp_copy_fro_slots(pr.mr, pr.nr), b.nA2, c.st));
         }
     }
     // views 1 .. v-2 in reduced precision when asked; the last two keep FP32
@@ -844,48 +860,6 @@ double now_s() {
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-// First-fit allocator over [0, cap) with 256-byte granules; adjacent free ranges merge.
-class ArenaAlloc {
-  public:
-    explicit ArenaAlloc(size_t cap) { if (cap) free_[0] = cap; }
-    bool alloc(size_t bytes, size_t* off) {
-        bytes = (bytes + 255) & ~size_t(255);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= bytes) {
-                *off = it->first;
-                const size_t rest = it->second - bytes, at = it->first + bytes;
-                free_.erase(it);
-                if (rest) free_[at] = rest;
-                used_ += bytes;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = (bytes + 255) & ~size_t(255);
-        used_ -= bytes;
-        auto it = free_.emplace(off, bytes).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
-    size_t used() const { return used_; }
-
-  private:
-    std::map<size_t, size_t> free_;
-    size_t used_ = 0;
-};
-
 struct SrvRequest {
     qlra_request_t r{};
     uint64_t ticket = 0;
@@ -947,12 +921,9 @@ void srv_enqueue_step(qlra_server* sv, SrvRequest* q, int s) {
     c.step_only = s;
     const bool last = s == q->pr.v - 1;
     hipGraph_t g = nullptr;
-    const bool cap = sv->graphs != 0;
+    // a step whose capture cannot begin is launched eagerly (the same launches, in order)
+    const bool cap = sv->graphs != 0 && hipStreamBeginCapture(sl.st, hipStreamCaptureModeThreadLocal) == hipSuccess;
     c.st = sl.st;
-    if (cap && hipStreamBeginCapture(sl.st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-        q->status = QLRA_E_HIP;
-        return;
-    }
     run_solve(c, q->pr, q->d, b);
     // a step rejoins whatever it forked (a captured step must, and the slot's events are reused)
     if (c.forked) {
@@ -1613,6 +1584,11 @@ int qlra_server_poll(qlra_server_t* sv, uint64_t ticket, int wait, int* done, in
         sv->reqs.erase(it);
     }
     return QLRA_OK;
+}
+
+int qlra_server_wait(qlra_server_t* sv, uint64_t ticket, int* status, double* latency_s) {
+    int done = 0;
+    return qlra_server_poll(sv, ticket, 1, &done, status, latency_s);
 }
 
 int qlra_server_drain(qlra_server_t* sv) {

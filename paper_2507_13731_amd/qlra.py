@@ -100,12 +100,13 @@ _lib.qlra_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(_
 _lib.qlra_server_submit.argtypes = [_P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
 _lib.qlra_server_poll.argtypes = [_P, ctypes.c_uint64, _I, ctypes.POINTER(_I), ctypes.POINTER(_I),
                                   ctypes.POINTER(ctypes.c_double)]
+_lib.qlra_server_wait.argtypes = [_P, ctypes.c_uint64, ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double)]
 _lib.qlra_server_drain.argtypes = [_P]
 _lib.qlra_server_stats.argtypes = [_P, ctypes.POINTER(ServerStats)]
 _lib.qlra_server_destroy.argtypes = [_P]
 _lib.qlra_server_clock.argtypes = []
 _lib.qlra_server_clock.restype = ctypes.c_double
-for _name in ("qlra_server_create", "qlra_server_submit", "qlra_server_poll", "qlra_server_drain",
+for _name in ("qlra_server_create", "qlra_server_submit", "qlra_server_poll", "qlra_server_wait", "qlra_server_drain",
               "qlra_server_stats", "qlra_server_destroy"):
     getattr(_lib, _name).restype = _I
 for _name in ("qlra_workspace_size", "qlra", "qlra_status", "qlra_complete_workspace_size", "qlra_complete",
@@ -120,7 +121,7 @@ EXPORTS = ("qlra", "qlra_workspace_size", "qlra_status", "qlra_strerror", "qlra_
            "qlra_qgemm_workspace_size", "qlra_lowp_copy_bytes", "qlra_lowp_copy", "qlra_qgemm_lp", "qlra_qgemm_lp_workspace_size",
            "qlra_cholqr", "qlra_cholqr_workspace_size", "qlra_qsvd", "qlra_qsvd_workspace_size",
            "qlra_lowp_copy_residual", "qlra_qgemm_split", "qlra_qgemm_split_workspace_size",
-           "qlra_server_create", "qlra_server_submit", "qlra_server_poll", "qlra_server_drain",
+           "qlra_server_create", "qlra_server_submit", "qlra_server_poll", "qlra_server_wait", "qlra_server_drain",
            "qlra_server_stats", "qlra_server_destroy", "qlra_server_clock")
 
 
@@ -473,6 +474,14 @@ class Server:
                                      ctypes.byref(st), ctypes.byref(lat)), "qlra_server_poll")
         if not done.value:
             return None
+        A, U, S, V, e = self._keep.pop(ticket)
+        return st.value, lat.value, (U, S, V, e)
+
+    def wait(self, ticket):
+        """Block until the request is done: (status, latency_s, (U, S, V, pass_err))."""
+        st, lat = ctypes.c_int(), ctypes.c_double()
+        _check(_lib.qlra_server_wait(self._h, ctypes.c_uint64(ticket), ctypes.byref(st), ctypes.byref(lat)),
+               "qlra_server_wait")
         A, U, S, V, e = self._keep.pop(ticket)
         return st.value, lat.value, (U, S, V, e)
 

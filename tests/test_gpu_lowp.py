@@ -93,6 +93,7 @@ def test_lowp_copy_bit_exact(gq, prec, m, n):
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 @pytest.mark.parametrize("op", [0, 1])
 @pytest.mark.parametrize("m,n,w", [(300, 200, 15), (512, 1024, 60), (1000, 777, 80), (640, 900, 96), (64, 2048, 1),
+                                   (900, 700, 112), (333, 1500, 160), (520, 260, 200),
                                    (700, 500, 100), (400, 1300, 160)])
 def test_qgemm_lp_against_rounded_oracle(gq, oracle, prec, op, m, n, w):
     import torch
@@ -250,7 +251,8 @@ def test_lowp_residual_copy_bit_exact(gq, prec):
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 @pytest.mark.parametrize("op", [0, 1])
-@pytest.mark.parametrize("m,n,w", [(300, 200, 15), (1000, 777, 80), (700, 500, 100), (64, 2048, 1)])
+@pytest.mark.parametrize("m,n,w", [(300, 200, 15), (1000, 777, 80), (700, 500, 100), (64, 2048, 1), (450, 900, 160),
+                                   (600, 300, 320)])
 def test_qgemm_split_against_oracle(gq, oracle, prec, op, m, n, w):
     """The three products from the rounded pieces, each the oracle's FP64 product, summed: equal up
     to FP32 accumulation; and the sum is within the split's dropped terms (a_lo b_lo and the

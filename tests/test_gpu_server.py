@@ -49,17 +49,18 @@ def alone(gq, r):
     return [x.cpu().numpy() for x in (U, S, V, e)]
 
 
-def serve(gq, reqs, hbm, max_active, graphs):
+def serve(gq, reqs, hbm, max_active, graphs, use_wait=False):
     import torch
     srv = gq.Server(hbm, max_active=max_active, graphs=graphs)
     tickets = []
     for r in reqs:
         tickets.append(srv.submit(torch.from_numpy(r["A"]).cuda(), r["k"], r["p"], r["v"], r["scheme"], r["seed"],
                                   precision=r["prec"]))
-    srv.drain()
+    if not use_wait:
+        srv.drain()
     out = []
     for t in tickets:
-        st, lat, (U, S, V, e) = srv.poll(t, wait=True)
+        st, lat, (U, S, V, e) = srv.wait(t) if use_wait else srv.poll(t, wait=True)
         torch.cuda.synchronize()
         out.append((st, lat, [x.cpu().numpy() for x in (U, S, V, e)]))
     stats = srv.stats()
@@ -91,7 +92,7 @@ def test_server_admission_by_footprint(gq):
     sizes = [gq.qlra_workspace_size(r["A"].shape[1], r["A"].shape[2], r["k"], r["p"], r["v"], r["scheme"],
                                     precision=r["prec"]) for r in reqs]
     hbm = int(max(sizes) * 1.2)
-    out, stats = serve(gq, reqs, hbm, 8, False)
+    out, stats = serve(gq, reqs, hbm, 8, False, use_wait=True)
     assert stats["max_arena_used"] <= hbm
     assert stats["max_active_seen"] <= 8
     for r, (st, lat, got) in zip(reqs, out):
