@@ -15,7 +15,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqlra.so")
 
-SOURCES = ["omega.hip", "qgemm.hip", "lowp.hip", "chol.hip", "qsvd.hip", "heig.hip", "heig_big.hip", "util.hip", "complete.hip", "qlra.cpp"]
+SOURCES = ["omega.hip", "qgemm.hip", "lowp.hip", "chol.hip", "qsvd.hip", "heig.hip", "heig_big.hip", "util.hip",
+           "complete.hip", "qlra.cpp", "noalloc.hip"]
 COMMON = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]

@@ -7,10 +7,10 @@ import re
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared():
-    src = open(os.path.join(ROOT, "include", "qlra.h")).read()
+def declared(header="qlra.h"):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:int|double|const char\*)\s+(qlra\w*)\s*\(", src, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|double|size_t|const char\*)\s+(qlra\w*)\s*\(", src, flags=re.M)))
 
 
 def test_header_declares_the_boundary():
@@ -26,6 +26,16 @@ def test_library_exports_every_declared_symbol():
     missing = [n for n in declared() if not hasattr(lib, n)]
     assert not missing, missing
     assert set(declared()) == set(Q.EXPORTS)
+
+
+def test_library_exports_the_no_alloc_entry_points():
+    from paper_2507_13731_amd import qlra as Q
+    names = declared("qlra_noalloc.h")
+    assert names == ["qlra_noalloc", "qlra_noalloc_max_bytes", "qlra_noalloc_status"]
+    lib = ctypes.CDLL(Q.LIB_PATH)
+    assert all(hasattr(lib, n) for n in names)
+    lib.qlra_noalloc_max_bytes.restype = ctypes.c_size_t
+    assert lib.qlra_noalloc_max_bytes() == 128 << 20
 
 
 def test_workspace_size_and_argument_errors_without_gpu():
