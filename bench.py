@@ -39,6 +39,8 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_MFMA = 157.3e12
 PEAK_BF16_MFMA = 2516.6e12
 PEAK_HBM = 8.0e12
+SIMDS = 256 * 4
+XCDS = 8
 
 # the headline: 16384 x 16384, block Krylov, k = 128, p = 32, v = 8, sketch seed 11
 LN, LK, LP, LV, LSEED = 16384, 128, 32, 8, 11
@@ -149,15 +151,25 @@ def counters_run(Q, torch, A):
 
 
 def _read_counter_csv(path):
-    """{counter: [(dispatch, kernel, value summed over the dispatch's rows)]} in dispatch order."""
+    """{counter: [(dispatch, kernel, value, duration_ns)]} in dispatch order: a counter's rows of
+    one dispatch summed (per-SE and per-channel instances), GRBM counters maximised."""
     import csv
     rows = {}
     for r in csv.DictReader(open(path)):
         key = (r["Counter_Name"], int(r["Dispatch_Id"]))
-        rows[key] = (r["Kernel_Name"], rows.get(key, ("", 0.0))[1] + float(r["Counter_Value"]))
+        v = float(r["Counter_Value"])
+        dur = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        old = rows.get(key, ("", None, 0))[1]
+        if old is None:
+            new = v
+        elif r["Counter_Name"].startswith("GRBM"):
+            new = max(old, v)
+        else:
+            new = old + v
+        rows[key] = (r["Kernel_Name"], new, dur)
     out = {}
-    for (cn, d), (kn, v) in sorted(rows.items(), key=lambda t: t[0][1]):
-        out.setdefault(cn, []).append((d, kn, v))
+    for (cn, d), (kn, v, dur) in sorted(rows.items(), key=lambda t: t[0][1]):
+        out.setdefault(cn, []).append((d, kn, v, dur))
     return out
 
 
@@ -171,36 +183,58 @@ def pmc_summary(paths):
     extra = {}
     for path in paths:
         for counter, seq in _read_counter_csv(path).items():
-            view = [(n, v) for _, n, v in seq if any(t in n for t in view_kernels)]
+            view = [(n, v, t) for _, n, v, t in seq if any(k in n for k in view_kernels)]
             nper = len(view) // len(COUNTER_OPS)
             if counter in ("FETCH_SIZE", "WRITE_SIZE"):
-                copies = [v for _, _, v in seq[-COUNTER_REPS:]]     # the calibration copies end the sequence
+                copies = [v for _, _, v, _ in seq[-COUNTER_REPS:]]  # the calibration copies end the sequence
                 kib_copy = statistics.median(copies)
                 scale = COPY_BYTES / (kib_copy * 1024.0)
                 per_op = {}
                 for i, (_, w, name) in enumerate(COUNTER_OPS):
                     part = view[i * nper:(i + 1) * nper]
-                    kib = sum(v for _, v in part) / COUNTER_REPS
+                    kib = sum(v for _, v, _ in part) / COUNTER_REPS
                     per_op[name] = {"kib_per_launch": round(kib, 1), "bytes_per_launch": round(kib * 1024.0 * scale),
-                                    "kernels": sorted({re.search(r"k_\w+", n).group(0) for n, _ in part})}
+                                    "kernels": sorted({re.search(r"k_\w+", n).group(0) for n, _, _ in part})}
                 out[counter] = {"copy_kib": round(kib_copy, 1), "scale": round(scale, 4), **per_op}
             else:
-                per_op = {}
+                per_op, dur_op = {}, {}
                 for i, (_, w, name) in enumerate(COUNTER_OPS):
-                    part = [(n, v) for n, v in view[i * nper:(i + 1) * nper] if "k_qview" in n]
-                    per_op[name] = round(sum(v for _, v in part) / max(1, len(part)), 1)
-                extra[counter] = {"per_product_kernel_launch": per_op}
+                    part = [(n, v, t) for n, v, t in view[i * nper:(i + 1) * nper] if "k_qview" in n]
+                    per_op[name] = round(sum(v for _, v, _ in part) / max(1, len(part)), 1)
+                    dur_op[name] = round(sum(t for _, _, t in part) / max(1, len(part)))
+                extra[counter] = {"per_product_kernel_launch": per_op, "duration_ns": dur_op}
     hbm = 0.5 * sum(out[c][o]["bytes_per_launch"] for c in ("FETCH_SIZE", "WRITE_SIZE") for _, _, o in COUNTER_OPS)
+    # MFMA activity of the product kernel: busy cycles over (active cycles x SIMDs), and the FLOPs
+    # the MFMA pipes executed (512 per MOPS unit) against the algorithmic 32 m n w.  GRBM_GUI_ACTIVE
+    # reads as the sum over the XCDs (it is about XCDS x the dispatch's duration x the clock), so
+    # one XCD's active cycles are a XCDS-th of it; the implied clock is recorded as the check.
+    mfma = {}
+    if "SQ_VALU_MFMA_BUSY_CYCLES" in extra and "GRBM_GUI_ACTIVE" in extra:
+        for _, w, name in COUNTER_OPS:
+            busy = extra["SQ_VALU_MFMA_BUSY_CYCLES"]["per_product_kernel_launch"][name]
+            act = extra["GRBM_GUI_ACTIVE"]["per_product_kernel_launch"][name] / XCDS
+            dur = extra["GRBM_GUI_ACTIVE"]["duration_ns"][name]
+            rec_op = {"mfma_busy_frac": round(busy / (act * SIMDS), 4), "active_cycles_per_xcd": round(act),
+                      "dispatch_ns": dur, "implied_clock_ghz": round(act / dur, 3) if dur else None}
+            if "SQ_INSTS_VALU_MFMA_MOPS_F32" in extra:
+                fl = 512.0 * extra["SQ_INSTS_VALU_MFMA_MOPS_F32"]["per_product_kernel_launch"][name]
+                rec_op["mfma_f32_flops"] = fl
+                rec_op["mfma_flops_over_algorithmic"] = round(fl / (32.0 * LN * LN * w), 4)
+            mfma[name] = rec_op
     rec = {"kernel": f"FP32 view product {LN}x{LN} by {LL} (the product kernel and any split-K reduction), "
                      "mean of A X and A^H X",
            "commands": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/"
                         "pmc_fetch -o f -- python3 <repo>/bench.py --counters",
                         "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/"
                         "pmc_write -o w -- python3 <repo>/bench.py --counters",
+                        "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES "
+                        "SQ_INSTS_VALU_MFMA_MOPS_F32 GRBM_GUI_ACTIVE --output-format csv -d <out>/pmc_mfma -o m -- "
+                        "python3 <repo>/bench.py --counters",
                         "python bench.py --pmc-summary <out>/pmc_fetch/f_counter_collection.csv "
-                        "<out>/pmc_write/w_counter_collection.csv [<MFMA counter CSVs>]"],
+                        "<out>/pmc_write/w_counter_collection.csv <out>/pmc_mfma/m_counter_collection.csv"],
            "kernel_source_hash": kernel_source_hash(), "hbm_bytes_per_launch": round(hbm),
-           "algorithmic_bytes_per_launch": 16 * LN * LN + 2 * 16 * LN * LL, **out, "other_counters": extra}
+           "algorithmic_bytes_per_launch": 16 * LN * LN + 2 * 16 * LN * LL, **out, "mfma": mfma,
+           "other_counters": extra}
     os.makedirs(os.path.dirname(PMC_FILE), exist_ok=True)
     json.dump(rec, open(PMC_FILE, "w"), indent=1)
     print(json.dumps(rec))

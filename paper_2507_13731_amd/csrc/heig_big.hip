@@ -83,6 +83,10 @@ constexpr int BT = 256;
 
 __host__ __device__ inline int64_t step_blocks(int64_t W) { return (W + SRB - 1) / SRB; }
 
+// packed strictly-lower storage of the reflectors by columns: column j (rows j+1 .. W-1) starts
+// at j (2 W - j - 1) / 2, so that a reflector is one contiguous run (coalesced reads)
+__host__ __device__ inline int64_t refl_at(int64_t W, int64_t i, int64_t j) { return j * (2 * W - j - 1) / 2 + (i - j - 1); }
+
 // Record for order W (doubles): the working matrix, then the results.
 struct BigRec {
     int64_t W;
@@ -94,7 +98,7 @@ struct BigRec {
     double* ph;     // 4 W
     double* bnd;    // 2 (+ pad)
     double* lam;    // W, ascending
-    double* refl;   // 4 W (W + 1) / 2, (i, j) at i (i + 1) / 2 + j
+    double* refl;   // 4 W (W + 1) / 2, reflector j's entry i > j at refl_at(W, i, j): columns contiguous
     double* P;      // 2 x 4 W: p = tau G v of a reflector (the two buffers alternate by step parity)
     double* KP;     // 2 x step_blocks(W) shares of v^H p
     double* CB;     // 2 x 4 W: copy of the column of the next reflector, taken before its update
@@ -146,7 +150,7 @@ __device__ double make_reflector(double* vn, int W, int j0, double part, double*
     if (store) {
         const int64_t pps = (int64_t)W * (W + 1) / 2;
         for (int r = j0 + 1 + (int)threadIdx.x; r < W; r += BT)
-            st(R.refl, pps, (int64_t)r * (r + 1) / 2 + j0, Q4{vn[r], vn[W + r], vn[2 * W + r], vn[3 * W + r]});
+            st(R.refl, pps, refl_at(W, r, j0), Q4{vn[r], vn[W + r], vn[2 * W + r], vn[3 * W + r]});
         if (threadIdx.x == 0) {
             R.tau[j0] = tau;
             const Q4 sj = qscale(phi, -alpha);
@@ -232,7 +236,7 @@ __global__ __launch_bounds__(BT) void k_big_step(double* base0, int64_t rstride,
     for (int c = tid; c < W; c += BT) {
         Q4 v{0, 0, 0, 0}, q{0, 0, 0, 0};
         if (c > j) {
-            v = ld(R.refl, pps, (int64_t)c * (c + 1) / 2 + j);
+            v = ld(R.refl, pps, refl_at(W, c, j));
             q = qsub(ld(Pc, W, c), qscale(v, K));
         }
         vs[c] = v.w; vs[W + c] = v.x; vs[2 * W + c] = v.y; vs[3 * W + c] = v.z;
@@ -503,14 +507,14 @@ __global__ __launch_bounds__(BT) void k_big_back(double* __restrict__ base, int 
         for (int u = 0; u < kBigRows; u++) {
             const int i = lane + 64 * u;
             if (64 * u < W && i > j && i < W)                    // the first test is uniform
-                s = qadd(s, qmul(qconj(ld(R.refl, pps, (int64_t)i * (i + 1) / 2 + j)), y[u]));
+                s = qadd(s, qmul(qconj(ld(R.refl, pps, refl_at(W, i, j))), y[u]));
         }
         s.w = wave_total(s.w); s.x = wave_total(s.x); s.y = wave_total(s.y); s.z = wave_total(s.z);
         s = qscale(s, tj);
 #pragma unroll
         for (int u = 0; u < kBigRows; u++) {
             const int i = lane + 64 * u;
-            if (64 * u < W && i > j && i < W) y[u] = qsub(y[u], qmul(ld(R.refl, pps, (int64_t)i * (i + 1) / 2 + j), s));
+            if (64 * u < W && i > j && i < W) y[u] = qsub(y[u], qmul(ld(R.refl, pps, refl_at(W, i, j)), s));
         }
     }
     const int64_t eps = (int64_t)W * nout;

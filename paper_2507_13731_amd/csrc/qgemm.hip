@@ -1042,7 +1042,7 @@ __global__ __launch_bounds__(256 * NCG) void k_qgemm_lp(LpParams P) {
 
 // column groups per workgroup, column tiles per wave and the staged reduction depth for CN
 // column tiles (beyond 6 tiles, one K step per staged tile keeps it within LDS)
-constexpr int lp_ncg(int cn) { return cn <= 2 ? 1 : 2; }
+constexpr int lp_ncg(int cn) { return cn <= 2 || cn > 6 ? 1 : 2; }
 constexpr int lp_cnw(int cn) { return (cn + lp_ncg(cn) - 1) / lp_ncg(cn); }
 constexpr int lp_lk(int cn) { return cn <= 6 ? LKS : LBK; }
 
