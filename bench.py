@@ -48,6 +48,7 @@ LL = LK + LP
 LW = (LV // 2) * LL            # width of the Krylov stack and of the last view (even v)
 GOLDEN = os.path.join(ROOT, "tests", "golden", "config4_krylov_k128_p32_v8_seed11.json")
 PMC_FILE = os.path.join(ROOT, "profiles", "qgemm_f32_view_16384x16384x160_pmc.json")
+TRACE_FILE = os.path.join(ROOT, "profiles", "solve_16384x16384_krylov_k128_p32_v8_trace.md")
 
 # secondary: 2048 x 2048, sigma_i = exp(-i/20) + noise, subspace k = 50, p = 10, budgets 2, 3, 4, 6
 M1 = N1 = 2048
@@ -77,6 +78,9 @@ def parse():
                     help="run only the matrix-completion workloads (for a kernel trace) and print their record")
     ap.add_argument("--counters", action="store_true",
                     help="launch sequence for hardware-counter runs only (view products and calibration copies)")
+    ap.add_argument("--trace-summary", metavar="CSV",
+                    help="kernel trace CSV of a rocprofv3 --kernel-trace run of the default bench: writes the "
+                         "per-kernel summary of the headline solves under profiles/")
     ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
                     help="FETCH_SIZE and WRITE_SIZE CSVs of two --counters runs (then optional MFMA counter "
                          "CSVs): writes the traffic record under profiles/")
@@ -238,6 +242,97 @@ def pmc_summary(paths):
     os.makedirs(os.path.dirname(PMC_FILE), exist_ok=True)
     json.dump(rec, open(PMC_FILE, "w"), indent=1)
     print(json.dumps(rec))
+
+
+def _kshort(name):
+    """k_name<template args> of a kernel symbol (library kernels), else the first 40 characters."""
+    m = re.search(r"(k_\w+?)(<[^()]*>)?\(", name)
+    if m:
+        return m.group(1) + (m.group(2) or "")
+    m = re.search(r"(k_\w+)", name)
+    return m.group(1) if m else name[:40]
+
+
+def trace_summary(path):
+    """Summary of a rocprofv3 kernel trace (CSV) of the default bench run: the roofline kernel's
+    launches at the headline shape, and per-kernel totals of one timed solve of each precision.
+    The headline solves come first in the run (warmup + steps each for FP32, BF16, BF16 split);
+    a solve starts at its k_solve_prologue and holds the library's kernels up to the next one."""
+    import csv
+    import statistics
+    rows = []
+    for r in csv.DictReader(open(path)):
+        rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"], int(r["Grid_Size_X"]),
+                     int(r["Grid_Size_Y"]), int(r["Grid_Size_Z"])))
+    rows.sort()
+    lib = [r for r in rows if "qlra_impl" in r[2]]
+    starts = [i for i, r in enumerate(lib) if "k_solve_prologue" in r[2]]
+    starts.append(len(lib))
+    per = None
+    out = ["# Kernel trace: 16384 x 16384 block Krylov solve (k = 128, p = 32, v = 8), default bench run", "",
+           "Commands (repository root on one MI355X; `<out>` a scratch folder):", "",
+           "    cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
+           "-d <out>/trace -o bench -- python3 <repo>/bench.py",
+           "    python bench.py --trace-summary <out>/trace/bench_kernel_trace.csv", ""]
+    # the roofline kernel: FP32 views at 160 columns (grid of 512 workgroups of 256 threads)
+    out += ["## The roofline kernel (FP32 view product, 16384 x 16384 by 160)", "",
+            "Every launch in the run at this shape (in the solves and in the bench's graph-timed view loop).", "",
+            "| kernel | launches | mean us | median us | TFLOP/s (32 m n w / mean) | of 157.3 |", "|---|---|---|---|---|---|"]
+    flops = 32.0 * LN * LN * LL
+    means = []
+    for label, pat in (("A X", "k_qview<5, false, true, false, false>"), ("A^H X", "k_qview<5, true, false, false, false>")):
+        d = [(b - a) / 1e3 for a, b, n, gx, gy, gz in rows if _kshort(n) == pat and gx == 512 * 256 and gz == 1]
+        if not d:
+            continue
+        mu = statistics.mean(d)
+        means.append(mu)
+        out.append(f"| `{pat}` ({label}) | {len(d)} | {mu:.1f} | {statistics.median(d):.1f} | "
+                   f"{flops / mu / 1e6:.1f} | {flops / mu / 1e6 / 157.3:.3f} |")
+    thin = [(b - a) / 1e3 for a, b, n, gx, gy, gz in rows if _kshort(n) == "k_thin_t" and gx == 1024 * 256 and gy == 3]
+    if thin:
+        out.append(f"| `k_thin_t` (the thin operand's transpose, per view) | {len(thin)} | {statistics.mean(thin):.1f} | "
+                   f"{statistics.median(thin):.1f} | | |")
+    if means:
+        mu = statistics.mean(means) + (statistics.mean(thin) if thin else 0.0)
+        out += ["", f"Mean of the two products plus the transpose: {mu:.1f} us per view, "
+                    f"{flops / mu / 1e6:.1f} TFLOP/s, {flops / mu / 1e6 / 157.3:.3f} of the FP32 MFMA peak "
+                    "(the bench's `roofline` times the same launch sequence with HIP events).", ""]
+    names = ("FP32", "BF16", "BF16 split")
+    nsolve = len(starts) - 1
+    per = nsolve // 3 if nsolve >= 3 else 0
+    if per:
+        out += [f"## One timed solve of each precision (the last of {per} per precision)", ""]
+        for pi, pname in enumerate(names):
+            i0, i1 = starts[(pi + 1) * per - 1], starts[(pi + 1) * per]
+            seg = lib[i0:i1]
+            # the solve ends with its phase normalisation (the view timing loop follows the last one)
+            ends = [i for i, r in enumerate(seg) if "k_phase_apply" in r[2]]
+            if ends:
+                seg = seg[:ends[-1] + 1]
+            span = (max(r[1] for r in seg) - seg[0][0]) / 1e6
+            agg = {}
+            for a, b, n, gx, gy, gz in seg:
+                k = _kshort(n)
+                c, t = agg.get(k, (0, 0.0))
+                agg[k] = (c + 1, t + (b - a) / 1e6)
+            busy = sum(t for _, t in agg.values())
+            out += [f"### {pname}: span {span:.2f} ms, kernel time {busy:.2f} ms (the estimates overlap on a side stream), "
+                    f"{len(seg)} launches", "", "| kernel | launches | total ms | mean us |", "|---|---|---|---|"]
+            for k, (c, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:22]:
+                out.append(f"| `{k}` | {c} | {t:.3f} | {1e3 * t / c:.1f} |")
+            out.append("")
+    total = {}
+    for a, b, n, *_ in rows:
+        k = _kshort(n)
+        c, t = total.get(k, (0, 0.0))
+        total[k] = (c + 1, t + (b - a) / 1e6)
+    out += ["## Whole run: kernels by total time", "", "| kernel | launches | total ms | mean us |", "|---|---|---|---|"]
+    for k, (c, t) in sorted(total.items(), key=lambda kv: -kv[1][1])[:30]:
+        out.append(f"| `{k}` | {c} | {t:.2f} | {1e3 * t / c:.1f} |")
+    os.makedirs(os.path.dirname(TRACE_FILE), exist_ok=True)
+    with open(TRACE_FILE, "w") as f:
+        f.write("\n".join(out) + "\n")
+    print("\n".join(out))
 
 
 def graph_time(torch, fn, reps):
@@ -629,6 +724,9 @@ def main():
     args = parse()
     if args.pmc_summary:
         pmc_summary(args.pmc_summary)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1",

@@ -2,8 +2,9 @@
 // R^H R = Y^H Y): the Hermitian quaternion Cholesky with a shifted retry, the triangular
 // inverse, and products of triangular factors.  One workgroup per factorization: the matrices
 // are l x l with l = k + p, tiny next to a pass over A; the chain of dependent steps is what
-// costs, so for l <= kLdsMax the whole factor lives in LDS (packed upper triangle, four FP64
-// planes) and each step is one barrier-separated parallel update.
+// costs, so for l <= kRegMax the factor lives in the registers of one 1024-thread workgroup
+// (one barrier per elimination step) and its inverse is formed column by column from a packed
+// copy in LDS without barriers.
 #include "common.h"
 
 namespace qlra_impl {
@@ -21,6 +22,7 @@ __device__ __forceinline__ Q4 qmul(Q4 a, Q4 b) {   // eq. (1)
 __device__ __forceinline__ Q4 qconj(Q4 a) { return Q4{a.w, -a.x, -a.y, -a.z}; }
 __device__ __forceinline__ Q4 qsub(Q4 a, Q4 b) { return Q4{a.w - b.w, a.x - b.x, a.y - b.y, a.z - b.z}; }
 __device__ __forceinline__ Q4 qscale(Q4 a, double s) { return Q4{a.w * s, a.x * s, a.y * s, a.z * s}; }
+__device__ __forceinline__ double qn2(Q4 a) { return a.w * a.w + a.x * a.x + a.y * a.y + a.z * a.z; }
 __device__ __forceinline__ Q4 ld4(const double* P, int64_t ps, int64_t i) {
     return Q4{P[i], P[ps + i], P[2 * ps + i], P[3 * ps + i]};
 }
@@ -29,148 +31,6 @@ __device__ __forceinline__ void st4(double* P, int64_t ps, int64_t i, Q4 v) {
 }
 
 constexpr int kThreads = 1024;
-constexpr int kLdsMax = 96;                        // packed upper triangle of 96 x 96 in LDS
-constexpr int kPacked = kLdsMax * (kLdsMax + 1) / 2;
-
-// LDS copy of an upper triangular quaternion matrix, packed by rows, four planes.
-struct Tri {
-    double* p;   // 4 * np doubles
-    int w, np;
-    __device__ __forceinline__ int idx(int a, int b) const { return a * w - (a * (a - 1)) / 2 + (b - a); }
-    __device__ __forceinline__ Q4 get(int a, int b) const {
-        const int i = idx(a, b);
-        return Q4{p[i], p[np + i], p[2 * np + i], p[3 * np + i]};
-    }
-    __device__ __forceinline__ void set(int a, int b, Q4 v) {
-        const int i = idx(a, b);
-        p[i] = v.w; p[np + i] = v.x; p[2 * np + i] = v.y; p[3 * np + i] = v.z;
-    }
-};
-
-// Cholesky and triangular inverse, all in LDS.
-//   G (w x w Hermitian, full storage, FP64 planes):  G + shift I = R^H R
-//   R_out = R;  Rinv = R^{-1}
-//   cond_gate (if non-null) := 1 when ||R||_F ||R^{-1}||_F > cond_limit, else 0.
-// Thread layout: 32 x 32 for element-wise updates (row ty, column tx), and 128 groups of 8
-// lanes for the dot products of the inverse.
-__global__ __launch_bounds__(kThreads) void k_chol_lds(const double* __restrict__ G, int w,
-                                                        double* __restrict__ Rout, double* __restrict__ Rinv,
-                                                        int* status,
-                                                        int* shift_out, const int* gate, int allow_shift,
-                                                        double shift_scale, int* cond_gate, double cond_limit) {
-    __shared__ double lds[4 * kPacked];
-    __shared__ int s_fail;
-    __shared__ double s_red[kThreads / 64][2];
-    if (gate && *gate == 0) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int ty = tid >> 5, tx = tid & 31;        // 32 x 32
-    const int grp = tid >> 3, sub = tid & 7;       // 128 groups of 8
-    const int64_t ps = (int64_t)w * w;
-    const int np = w * (w + 1) / 2;
-    Tri T{lds, w, np};
-    double shift = 0.0;
-    int shifted = 0, failed = 0;
-    for (int attempt = 0; attempt < 2; attempt++) {
-        for (int a = ty; a < w; a += 32)
-            for (int b = a + tx; b < w; b += 32) {
-                Q4 v = ld4(G, ps, (int64_t)a * w + b);
-                if (a == b) { v.w += shift; v.x = v.y = v.z = 0.0; }
-                T.set(a, b, v);
-            }
-        if (tid == 0) s_fail = 0;
-        __syncthreads();
-        for (int j = 0; j < w; j++) {
-            const double d = T.get(j, j).w;
-            if (!(d > 0.0) || !(d < 1e300)) {   // breakdown or non-finite pivot (uniform branch)
-                if (tid == 0) s_fail = 1;
-                break;
-            }
-            const double rjj = sqrt(d), inv = 1.0 / rjj;
-            for (int b = j + 1 + tid; b < w; b += kThreads) T.set(j, b, qscale(T.get(j, b), inv));
-            __syncthreads();
-            // trailing update; the pivot entry itself is written here (nobody reads it now)
-            if (tid == 0) T.set(j, j, Q4{rjj, 0, 0, 0});
-            for (int a = j + 1 + ty; a < w; a += 32) {
-                const Q4 rja = qconj(T.get(j, a));
-                for (int b = a + tx; b < w; b += 32) {
-                    Q4 v = qsub(T.get(a, b), qmul(rja, T.get(j, b)));
-                    if (a == b) v.x = v.y = v.z = 0.0;
-                    T.set(a, b, v);
-                }
-            }
-            __syncthreads();
-        }
-        __syncthreads();
-        if (!s_fail) break;
-        if (!allow_shift || attempt == 1) { failed = 1; break; }
-        // shifted CholeskyQR (Fukaya et al.): add shift_scale * trace(G) to the diagonal
-        double tr = 0.0;
-        for (int i = 0; i < w; i++) tr += G[(int64_t)i * w + i];
-        shift = shift_scale * tr;
-        if (!(shift > 0.0)) shift = 1e-300;
-        shifted = 1;
-        __syncthreads();
-    }
-    if (tid == 0) {
-        if (shift_out) *shift_out = shifted;
-        if (failed) atomicOr(status, 2);
-    }
-    // R_out = R (the product with an earlier factor, if any, is formed by k_rmul afterwards)
-    for (int a = ty; a < w; a += 32)
-        for (int b = tx; b < w; b += 32) st4(Rout, ps, (int64_t)a * w + b, b >= a ? T.get(a, b) : Q4{0, 0, 0, 0});
-    // ||R||_F^2 for the conditioning estimate
-    double nr = 0.0;
-    for (int e = tid; e < np; e += kThreads) {
-        nr += lds[e] * lds[e] + lds[np + e] * lds[np + e] + lds[2 * np + e] * lds[2 * np + e] +
-              lds[3 * np + e] * lds[3 * np + e];
-    }
-    __syncthreads();
-    // In-place inverse, rows from the bottom: X_ii = 1/r_ii, X_ic = -(1/r_ii) sum_{t=i+1}^{c} R_it X_tc.
-    // Row i of R is read before it is overwritten (compute, barrier, write); each X_ic is one
-    // 8-lane group's dot product.
-    for (int i = w - 1; i >= 0; i--) {
-        const double rii = T.get(i, i).w;
-        const double inv = rii > 0.0 ? 1.0 / rii : 0.0;
-        const int c = i + 1 + grp;
-        Q4 s{0, 0, 0, 0};
-        if (c < w) {
-            for (int t = i + 1 + sub; t <= c; t += 8) {
-                const Q4 pr = qmul(T.get(i, t), T.get(t, c));
-                s.w += pr.w; s.x += pr.x; s.y += pr.y; s.z += pr.z;
-            }
-        }
-#pragma unroll
-        for (int o = 4; o > 0; o >>= 1) {
-            s.w += __shfl_xor(s.w, o, 64); s.x += __shfl_xor(s.x, o, 64);
-            s.y += __shfl_xor(s.y, o, 64); s.z += __shfl_xor(s.z, o, 64);
-        }
-        __syncthreads();
-        if (c < w && sub == 0) T.set(i, c, qscale(s, -inv));
-        if (tid == 0) T.set(i, i, Q4{inv, 0, 0, 0});
-        __syncthreads();
-    }
-    double ni = 0.0;
-    for (int a = ty; a < w; a += 32)
-        for (int b = tx; b < w; b += 32) {
-            const Q4 v = b >= a ? T.get(a, b) : Q4{0, 0, 0, 0};
-            if (Rinv) st4(Rinv, ps, (int64_t)a * w + b, v);
-            ni += v.w * v.w + v.x * v.x + v.y * v.y + v.z * v.z;
-        }
-    if (cond_gate) {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            nr += __shfl_xor(nr, o, 64);
-            ni += __shfl_xor(ni, o, 64);
-        }
-        if (lane == 0) { s_red[wave][0] = nr; s_red[wave][1] = ni; }
-        __syncthreads();
-        if (tid == 0) {
-            double a = 0, b = 0;
-            for (int i = 0; i < kThreads / 64; i++) { a += s_red[i][0]; b += s_red[i][1]; }
-            *cond_gate = (failed || shifted || !(a * b <= cond_limit * cond_limit)) ? 1 : 0;
-        }
-    }
-}
 
 // c ? a : b, component by component (a select of values, kept in registers)
 __device__ __forceinline__ Q4 qsel(bool c, Q4 a, Q4 b) {
@@ -265,13 +125,104 @@ __device__ __forceinline__ void chol_row_at(Q4 (&g)[NB][NB], int jh, int j, int 
     }
 }
 
+constexpr int kFlag = 4 * kRegMax;                     // breakdown flag behind the pivot row
+typedef double RowBuf[4 * kRegMax + 2];                  // pivot row, components side by side
+
+// The factorization of G + shift I (G w x w Hermitian, FP64 planes with row stride ldg and plane
+// stride gps; w <= 32 NB) into the registers of a 1024-thread workgroup: thread (ty, tx) holds the
+// entries (ty + 32 i, tx + 32 j), j >= i, and ends with those of R.  A breakdown (or non-finite
+// pivot) with allow_shift set is redone once with shift = shift_scale * trace(G) (shifted = 1);
+// one that remains sets failed = 1.
+template <int NB>
+__device__ void chol_factor(Q4 (&g)[NB][NB], const double* __restrict__ G, int64_t ldg, int64_t gps, int w,
+                            int allow_shift, double shift_scale, RowBuf* rowb, int& shifted, int& failed) {
+    const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
+    double shift = 0.0;
+    shifted = 0;
+    failed = 0;
+    for (int attempt = 0; attempt < 2; attempt++) {
+#pragma unroll
+        for (int ri = 0; ri < NB; ri++)
+#pragma unroll
+            for (int ci = 0; ci < NB; ci++) {
+                if (ci < ri) continue;                 // blocks below the diagonal hold no entry a <= b
+                const int a = ty + 32 * ri, b = tx + 32 * ci;
+                Q4 v{0, 0, 0, 0};
+                if (a < w && b < w && b >= a) {
+                    v = ld4(G, gps, (int64_t)a * ldg + b);
+                    if (a == b) { v.w += shift; v.x = v.y = v.z = 0.0; }
+                }
+                g[ri][ci] = v;
+            }
+        bool fail = false;
+        __syncthreads();
+        for (int j = 0; j < w; j++) {
+            const int jr = j & 31, jh = j >> 5;
+            double* rb = rowb[j & 1];
+            if (ty == jr) {
+                // the pivot (j, j) is register g[jh][jh] of lane (ty & 1) * 32 + jr of this wave
+                double piv = 0.0;
+#pragma unroll
+                for (int h = 0; h < NB; h++)
+                    if (h == jh) piv = g[h][h].w;
+                const double d = bcast(piv, ((ty & 1) << 5) | jr);
+                const bool bad = !(d > 0.0) || !(d < 1e300);     // breakdown or non-finite pivot
+                if (tx == 0) rb[kFlag] = bad ? 1.0 : 0.0;
+                if (!bad) {
+                    double rjj, inv;
+                    sqrt_rsqrt(d, rjj, inv);
+                    chol_row_at<NB>(g, jh, j, w, tx, rb, rjj, inv);
+                }
+            }
+            __syncthreads();
+            // the pivot row's entries of this thread's rows and columns and the flag in one round
+            // of LDS reads (indices stay below kRegMax; entries of rows and columns that are not
+            // live are read and not used); at NB = 3 the row entries are read per row block, which
+            // keeps the register count within what 16 waves of 128 registers hold
+            Q4 rjb[NB], rja_all[NB];
+#pragma unroll
+            for (int i = 0; i < NB; i++) {
+                rjb[i] = ldi(rb, tx + 32 * i);
+                if constexpr (NB <= 2) rja_all[i] = qconj(ldi(rb, ty + 32 * i));
+            }
+            if (rb[kFlag] != 0.0) { fail = true; break; }    // uniform
+#pragma unroll
+            for (int ri = 0; ri < NB; ri++) {
+                const int a = ty + 32 * ri;
+                if (a <= j || a >= w) continue;
+                Q4 rja;
+                if constexpr (NB <= 2) rja = rja_all[ri];
+                else rja = qconj(ldi(rb, a));
+#pragma unroll
+                for (int ci = 0; ci < NB; ci++) {
+                    if (ci < ri) continue;
+                    const int b = tx + 32 * ci;
+                    if (b < a || b >= w) continue;
+                    Q4 v = qfms(g[ri][ci], rja, rjb[ci]);
+                    if (ri == ci && a == b) v.x = v.y = v.z = 0.0;
+                    g[ri][ci] = v;
+                }
+            }
+        }
+        __syncthreads();
+        if (!fail) break;
+        if (!allow_shift || attempt == 1) { failed = 1; break; }
+        // shifted CholeskyQR (Fukaya et al.): add shift_scale * trace(G) to the diagonal
+        double tr = 0.0;
+        for (int i = 0; i < w; i++) tr += G[(int64_t)i * ldg + i];
+        shift = shift_scale * tr;
+        if (!(shift > 0.0)) shift = 1e-300;
+        shifted = 1;
+        __syncthreads();
+    }
+}
+
 template <int NB>
 __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict__ G, int w, double* __restrict__ Rout,
                                                         double* __restrict__ Rpk, int* status, int* shift_out,
                                                         const int* gate, int allow_shift, double shift_scale,
                                                         int* gate_out, double gate_tol) {
-    constexpr int kFlag = 4 * kRegMax;                 // breakdown flag behind the pivot row
-    __shared__ __attribute__((aligned(16))) double rowb[2][4 * kRegMax + 2];
+    __shared__ __attribute__((aligned(16))) RowBuf rowb[2];
     if (gate && *gate == 0) return;
     const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
     const int64_t ps = (int64_t)w * w;
@@ -300,78 +251,8 @@ __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict_
         if (!go) return;                           // uniform
     }
     Q4 g[NB][NB];
-    double shift = 0.0;
-    int shifted = 0, failed = 0;
-    for (int attempt = 0; attempt < 2; attempt++) {
-#pragma unroll
-        for (int ri = 0; ri < NB; ri++)
-#pragma unroll
-            for (int ci = 0; ci < NB; ci++) {
-                if (ci < ri) continue;                 // blocks below the diagonal hold no entry a <= b
-                const int a = ty + 32 * ri, b = tx + 32 * ci;
-                Q4 v{0, 0, 0, 0};
-                if (a < w && b < w && b >= a) {
-                    v = ld4(G, ps, (int64_t)a * w + b);
-                    if (a == b) { v.w += shift; v.x = v.y = v.z = 0.0; }
-                }
-                g[ri][ci] = v;
-            }
-        bool fail = false;
-        __syncthreads();
-        for (int j = 0; j < w; j++) {
-            const int jr = j & 31, jh = j >> 5;
-            double* rb = rowb[j & 1];
-            if (ty == jr) {
-                // the pivot (j, j) is register g[jh][jh] of lane (ty & 1) * 32 + jr of this wave
-                double piv = 0.0;
-#pragma unroll
-                for (int h = 0; h < NB; h++)
-                    if (h == jh) piv = g[h][h].w;
-                const double d = bcast(piv, ((ty & 1) << 5) | jr);
-                const bool bad = !(d > 0.0) || !(d < 1e300);     // breakdown or non-finite pivot
-                if (tx == 0) rb[kFlag] = bad ? 1.0 : 0.0;
-                if (!bad) {
-                    double rjj, inv;
-                    sqrt_rsqrt(d, rjj, inv);
-                    chol_row_at<NB>(g, jh, j, w, tx, rb, rjj, inv);
-                }
-            }
-            __syncthreads();
-            // the pivot row and the flag in one round of LDS reads (indices stay below kRegMax;
-            // entries of rows and columns that are not live are read and not used)
-            Q4 rja[NB], rjb[NB];
-#pragma unroll
-            for (int i = 0; i < NB; i++) {
-                rja[i] = qconj(ldi(rb, ty + 32 * i));
-                rjb[i] = ldi(rb, tx + 32 * i);
-            }
-            if (rb[kFlag] != 0.0) { fail = true; break; }    // uniform
-#pragma unroll
-            for (int ri = 0; ri < NB; ri++) {
-                const int a = ty + 32 * ri;
-                if (a <= j || a >= w) continue;
-#pragma unroll
-                for (int ci = 0; ci < NB; ci++) {
-                    if (ci < ri) continue;
-                    const int b = tx + 32 * ci;
-                    if (b < a || b >= w) continue;
-                    Q4 v = qfms(g[ri][ci], rja[ri], rjb[ci]);
-                    if (ri == ci && a == b) v.x = v.y = v.z = 0.0;
-                    g[ri][ci] = v;
-                }
-            }
-        }
-        __syncthreads();
-        if (!fail) break;
-        if (!allow_shift || attempt == 1) { failed = 1; break; }
-        // shifted CholeskyQR (Fukaya et al.): add shift_scale * trace(G) to the diagonal
-        double tr = 0.0;
-        for (int i = 0; i < w; i++) tr += G[(int64_t)i * w + i];
-        shift = shift_scale * tr;
-        if (!(shift > 0.0)) shift = 1e-300;
-        shifted = 1;
-        __syncthreads();
-    }
+    int shifted, failed;
+    chol_factor<NB>(g, G, w, ps, w, allow_shift, shift_scale, rowb, shifted, failed);
     if (tid == 0) {
         if (shift_out) *shift_out = shifted;
         if (failed) atomicOr(status, 2);
@@ -393,6 +274,122 @@ __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict_
                 o[1] = d2{g[ri][ci].y, g[ri][ci].z};
             }
         }
+}
+
+// Cholesky and triangular inverse of order w <= 32 NB, in place inside larger matrices:
+//   G (row stride ldg, plane stride gps):  G + shift I = R^H R
+//   R into Rout and R^{-1} into Rinv (row strides ldr / ldx, plane strides rps / xps), zeros
+//   below the diagonal; with band_w > 0 the block sits at column band_off of a row band of
+//   width band_w, whose other columns (rows 0 .. w-1 of the block) are set to zero in both.
+// The factor comes from chol_factor; R's upper triangle then goes to LDS (packed by rows,
+// components side by side) and the inverse is formed by columns, each by back substitution
+// R x = e_c in one 16-lane group (column c and column w - 1 - c per group, so that every group
+// takes w + 1 steps): step t finishes x_t = acc_t / r_tt on its owner lane, broadcasts it over the
+// group, and every lane takes r_it x_t off its later rows i < t (slots i = s + 16 u).  No barrier
+// after the staging; R^{-1} is accurate to about u64 cond(R) relative, as a substitution.
+// cond_gate (if non-null) := 1 when ||R||_F ||R^{-1}||_F > cond_limit, the shift was taken or the
+// factorization failed, else 0.
+template <int NB>
+__global__ __launch_bounds__(kThreads) void k_chol_inv(const double* __restrict__ G, int64_t ldg, int64_t gps, int w,
+                                                        double* __restrict__ Rout, int64_t ldr, int64_t rps,
+                                                        double* __restrict__ Rinv, int64_t ldx, int64_t xps,
+                                                        int64_t band_off, int64_t band_w, int* status, int* shift_out,
+                                                        const int* gate, int allow_shift, double shift_scale,
+                                                        int* cond_gate, double cond_limit) {
+    constexpr int NP = 32 * NB * (32 * NB + 1) / 2;
+    constexpr int NU = 2 * NB;                       // slots per lane of a 16-lane group
+    __shared__ __attribute__((aligned(16))) RowBuf rowb[2];
+    __shared__ __attribute__((aligned(16))) double sR[4 * NP];
+    __shared__ double sdi[32 * NB];
+    __shared__ double s_red[kThreads / 64][2];
+    if (gate && *gate == 0) return;
+    const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31, lane = tid & 63;
+    Q4 g[NB][NB];
+    int shifted, failed;
+    chol_factor<NB>(g, G, ldg, gps, w, allow_shift, shift_scale, rowb, shifted, failed);
+    if (tid == 0) {
+        if (shift_out) *shift_out = shifted;
+        if (failed) atomicOr(status, 2);
+    }
+    double nr = 0.0;
+#pragma unroll
+    for (int ri = 0; ri < NB; ri++)
+#pragma unroll
+        for (int ci = 0; ci < NB; ci++) {
+            const int a = ty + 32 * ri, b = tx + 32 * ci;
+            if (a >= w || b >= w) continue;
+            const bool up = ci >= ri && b >= a;
+            const Q4 v = up ? g[ri][ci] : Q4{0, 0, 0, 0};
+            st4(Rout, rps, (int64_t)a * ldr + b, v);
+            if (up) {
+                sti(sR, upk(a, b, w), v);
+                nr += qn2(v);
+                if (a == b) sdi[a] = v.w > 0.0 ? 1.0 / v.w : 0.0;
+            }
+        }
+    // the rest of the row band
+    if (band_w > 0) {
+        const int64_t other = band_w - w;
+        for (int64_t e = tid; e < (int64_t)w * other; e += kThreads) {
+            const int64_t a = e / other, o = e - a * other;
+            const int64_t cb = o < band_off ? o - band_off : o - band_off + w;   // column relative to the block
+            st4(Rout, rps, a * ldr + cb, Q4{0, 0, 0, 0});
+            st4(Rinv, xps, a * ldx + cb, Q4{0, 0, 0, 0});
+        }
+    }
+    __syncthreads();
+    const int grp = tid >> 4, s = tid & 15;
+    double ni = 0.0;
+    if (grp < (w + 1) / 2) {
+        for (int pass = 0; pass < 2; pass++) {
+            const int c = pass == 0 ? grp : w - 1 - grp;
+            if (pass == 1 && c == grp) break;        // the middle column of an odd order
+            Q4 acc[NU];
+#pragma unroll
+            for (int u = 0; u < NU; u++) acc[u] = (s + 16 * u == c) ? Q4{1, 0, 0, 0} : Q4{0, 0, 0, 0};
+            for (int t = c; t >= 0; t--) {
+                const int ut = t >> 4, src = (lane & ~15) | (t & 15);
+                Q4 r[NU];
+#pragma unroll
+                for (int u = 0; u < NU; u++) r[u] = ldi(sR, upk(min(s + 16 * u, t), t, w));
+                Q4 v{0, 0, 0, 0};
+#pragma unroll
+                for (int u = 0; u < NU; u++)
+                    if (u == ut) v = acc[u];
+                v = qscale(v, sdi[t]);
+                const Q4 x{__shfl(v.w, src, 64), __shfl(v.x, src, 64), __shfl(v.y, src, 64), __shfl(v.z, src, 64)};
+#pragma unroll
+                for (int u = 0; u < NU; u++) {
+                    const int i = s + 16 * u;
+                    const Q4 nb = qfms(acc[u], r[u], x);
+                    acc[u] = qsel(i < t, nb, qsel(i == t, x, acc[u]));
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < NU; u++) {
+                const int i = s + 16 * u;
+                if (i < w) {
+                    const Q4 v = i <= c ? acc[u] : Q4{0, 0, 0, 0};
+                    st4(Rinv, xps, (int64_t)i * ldx + c, v);
+                    ni += qn2(v);
+                }
+            }
+        }
+    }
+    if (cond_gate) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            nr += __shfl_xor(nr, o, 64);
+            ni += __shfl_xor(ni, o, 64);
+        }
+        if (lane == 0) { s_red[tid >> 6][0] = nr; s_red[tid >> 6][1] = ni; }
+        __syncthreads();
+        if (tid == 0) {
+            double a = 0, b = 0;
+            for (int i = 0; i < kThreads / 64; i++) { a += s_red[i][0]; b += s_red[i][1]; }
+            *cond_gate = (failed || shifted || !(a * b <= cond_limit * cond_limit)) ? 1 : 0;
+        }
+    }
 }
 
 template <int CTRL>
@@ -575,8 +572,8 @@ __global__ __launch_bounds__(256) void k_rcopy(const double* __restrict__ src, d
 }
 
 // ------------------------------------------------------------------------------------------
-// Pieces of the blocked factorization of orders above kLdsMax (the block steps are driven from
-// the host side of the library: diagonal blocks by k_chol_lds, the rest as FP64 products).
+// Pieces of the blocked factorization of orders above kRegMax (the block steps are driven from
+// the host side of the library: diagonal blocks by k_chol_inv, the rest as FP64 products).
 
 // W = G with a real diagonal, plus shift I where shift = shift_scale * trace(G) (at least 1e-300)
 // when `shifted`; nothing when gate && *gate == 0.
@@ -652,7 +649,7 @@ __global__ void k_flag_nonzero(int* dst, const int* src) {
 
 }  // namespace
 
-int chol_lds_max() { return kLdsMax; }
+int chol_lds_max() { return kRegMax; }
 int chol_reg_max() { return kRegMax; }
 
 hipError_t chol_reg_launch(const double* G, int64_t w, double* R, double* Rpk, int* status, int* shift_out,
@@ -722,22 +719,36 @@ hipError_t flag_nonzero_launch(int* dst, const int* src, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t chol_inv_launch(const double* G, int64_t ldg, int64_t gps, int64_t w, double* R, int64_t ldr, int64_t rps,
+                           double* Rinv, int64_t ldi, int64_t ips, int64_t band_off, int64_t band_w, int* status,
+                           int* shift_out, const int* gate, int allow_shift, double shift_scale, int* cond_gate,
+                           double cond_limit, hipStream_t st) {
+    if (w < 1 || w > kRegMax || !R || !Rinv || (band_w > 0 && (band_off < 0 || band_off + w > band_w)))
+        return hipErrorInvalidValue;
+    if (w <= 64)
+        hipLaunchKernelGGL(k_chol_inv<2>, dim3(1), dim3(kThreads), 0, st, G, ldg, gps, (int)w, R, ldr, rps, Rinv, ldi,
+                           ips, band_off, band_w, status, shift_out, gate, allow_shift, shift_scale, cond_gate,
+                           cond_limit);
+    else
+        hipLaunchKernelGGL(k_chol_inv<3>, dim3(1), dim3(kThreads), 0, st, G, ldg, gps, (int)w, R, ldr, rps, Rinv, ldi,
+                           ips, band_off, band_w, status, shift_out, gate, allow_shift, shift_scale, cond_gate,
+                           cond_limit);
+    return hipGetLastError();
+}
+
 hipError_t chol_launch(const double* G, int64_t w, double* R, double* Rinv, const double* Rprev, double* work,
                        int* status, int* shift_out, const int* gate, int allow_shift, double shift_scale,
                        int* cond_gate, double cond_limit, hipStream_t st) {
-    if (w <= kLdsMax) {
-        // with an earlier factor: the new factor goes to `work`, then R = work * Rprev
-        double* Rnew = Rprev ? work : R;
-        hipLaunchKernelGGL(k_chol_lds, dim3(1), dim3(kThreads), 0, st, G, (int)w, Rnew, Rinv, status,
-                           shift_out, gate, allow_shift, shift_scale, cond_gate, cond_limit);
-        if (Rprev) {
-            const int64_t n = w * w;
-            hipLaunchKernelGGL(k_rmul, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const double*)Rnew, Rprev,
-                               R, (int)w, gate);
-        }
-    } else {
-        return hipErrorInvalidValue;   // larger orders: the blocked factorization
-    }
+    if (w < 1 || w > kRegMax) return hipErrorInvalidValue;   // larger orders: the blocked factorization
+    // with an earlier factor: the new factor goes to `work`, then R = work * Rprev
+    double* Rnew = Rprev ? work : R;
+    const int64_t ps = w * w;
+    hipError_t e = chol_inv_launch(G, w, ps, w, Rnew, w, ps, Rinv ? Rinv : work + 4 * ps, w, ps, 0, 0, status,
+                                   shift_out, gate, allow_shift, shift_scale, cond_gate, cond_limit, st);
+    if (e != hipSuccess || !Rprev) return e;
+    const int64_t n = w * w;
+    hipLaunchKernelGGL(k_rmul, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const double*)Rnew, Rprev, R,
+                       (int)w, gate);
     return hipGetLastError();
 }
 

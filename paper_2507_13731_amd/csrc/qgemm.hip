@@ -643,6 +643,7 @@ struct Plan {
 };
 
 constexpr int kCUs = 256;
+constexpr int kGramWgPerCU = 4;   // split-K workgroups per CU for Gram-like (A^H B) products
 
 // A Hermitian Gram X^H X: the same operand on both sides, a square output set outright.
 bool is_sym_gram(const QgemmDesc& d) {
@@ -652,9 +653,11 @@ bool is_sym_gram(const QgemmDesc& d) {
 
 Plan make_plan(const QgemmDesc& d) {
     Plan p{};
-    if (d.op == OP_HN) {
+    if (d.op == OP_HN || d.b_upper) {
         // Gram-like products: small M x N output, long K; 32 x 32 tiles so that K splits
-        // spread the FP64 MFMA work over many CUs
+        // spread the FP64 MFMA work over many CUs.  Products with an upper triangular right
+        // operand (Y R^{-1}) take them too: a column tile's reduction then stops 32 columns
+        // apart, and w = 160 needs no padded columns.
         p.BK = 16; p.WM = 2; p.WN = 2; p.RM = 1; p.CN = 1;
     } else {
         // tall times small (applies, projections, back-multiplication)
@@ -667,9 +670,11 @@ Plan make_plan(const QgemmDesc& d) {
     p.Np = p.gy * BN;
     // a Hermitian Gram computes the tiles on and above the diagonal only
     const int64_t tiles = is_sym_gram(d) ? p.gx * (p.gx + 1) / 2 : p.gx * p.gy;
-    // split K so that about one workgroup per CU runs, each over at least 2 K steps
+    // split K so that several workgroups per CU run (Gram-like products: about four, which hide
+    // the latency of one another's strided loads; the others about one), each over at least 2 K
+    // steps
     const int64_t min_steps = 2;
-    const int64_t target = kCUs;
+    const int64_t target = d.op == OP_HN ? kGramWgPerCU * kCUs : kCUs;
     int64_t splits = 1;
     if (tiles < target) {
         splits = std::min<int64_t>((target + tiles - 1) / tiles, (d.K + min_steps * p.BK - 1) / (min_steps * p.BK));
@@ -1232,10 +1237,13 @@ hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t s
             return launch_t<double, 2, 2, 1, 1, 16, true, double, double, double>(pl, kp, st);
         return hipErrorInvalidValue;
     }
+    const bool square = pl.WN == 2;
     if (!d.a_f64 && d.b_f64 && !d.c_f64)
-        return launch_t<double, 1, 4, 1, 1, 16, false, float, double, float>(pl, kp, st);
+        return square ? launch_t<double, 2, 2, 1, 1, 16, false, float, double, float>(pl, kp, st)
+                      : launch_t<double, 1, 4, 1, 1, 16, false, float, double, float>(pl, kp, st);
     if (d.a_f64 && d.b_f64 && d.c_f64)
-        return launch_t<double, 1, 4, 1, 1, 16, false, double, double, double>(pl, kp, st);
+        return square ? launch_t<double, 2, 2, 1, 1, 16, false, double, double, double>(pl, kp, st)
+                      : launch_t<double, 1, 4, 1, 1, 16, false, double, double, double>(pl, kp, st);
     return hipErrorInvalidValue;
 }
 

@@ -44,7 +44,7 @@ struct Ctx {
     double* G = nullptr;            // Gram, wmax x wmax
     double* R1 = nullptr;
     double* R2 = nullptr;
-    double* blk = nullptr;          // blocked Cholesky: four (<= chol_lds_max())^2 FP64 blocks
+    double* blk = nullptr;          // blocked Cholesky: one (<= chol_lds_max())^2 quaternion FP64 block
     double* Rinv = nullptr;
     float* T2 = nullptr;            // CholQR intermediate, rows x wmax
     int64_t T2_rows = 0;
@@ -98,11 +98,12 @@ double shift_scale(int64_t rows, int64_t w) {
     return 11.0 * ((double)rows * w + (double)w * (w + 1)) * 1.1102230246251565e-16;
 }
 
-size_t chol_blk_doubles() { return (size_t)16 * chol_lds_max() * chol_lds_max(); }
+size_t chol_blk_doubles() { return (size_t)4 * chol_lds_max() * chol_lds_max(); }
 
 // Cholesky G (+ shift I) = R^H R and R^{-1} for orders above chol_lds_max(): right-looking by
-// diagonal blocks of at most chol_lds_max().  Block k: R_kk and R_kk^{-1} from the LDS kernel on
-// the updated diagonal block, the block row R_k,rest = R_kk^{-H} W_k,rest and the trailing update
+// diagonal blocks of at most chol_lds_max().  Block k: R_kk and R_kk^{-1} from the register
+// kernel on the updated diagonal block, in place (it also clears the rest of its row band in R
+// and R^{-1}), the block row R_k,rest = R_kk^{-H} W_k,rest and the trailing update
 // W_rest -= R_k,rest^H R_k,rest as FP64 products; then the off-diagonal blocks of R^{-1}, column
 // by column from the diagonal up: X_ij = -X_ii (R_i,(i+1..j) X_(i+1..j),j).  With allow_shift a
 // breakdown of the unshifted pass (flag in status[2]) reruns everything, gated on that flag, on
@@ -113,34 +114,25 @@ void chol_blocked(Ctx& c, const double* G, int64_t w, double* Rout, double* Rinv
                   int allow_shift, double sscale, const int* outer = nullptr) {
     const int64_t nb = (w + chol_lds_max() - 1) / chol_lds_max();
     const int64_t b = (w + nb - 1) / nb;
-    const int64_t ps = w * w, bs = b * b;
+    const int64_t ps = w * w;
     double* W = c.chol_work;
     double* Rw = Rprev ? c.R2 : Rout;
-    double* Gk = c.blk;
-    double* Rk = Gk + 4 * bs;
-    double* Ik = Rk + 4 * bs;
-    double* T = Ik + 4 * bs;
+    double* T = c.blk;
     int* fail = c.status ? c.status + 2 : nullptr;
     if (c.live() && allow_shift) note(c, fill_int_launch(fail, 1, 0, c.st));
     for (int attempt = 0; attempt < (allow_shift ? 2 : 1); attempt++) {
         // the retry runs only when the first attempt ran and broke down
         const int* gate = attempt ? fail : outer;
         int* st = (allow_shift && attempt == 0) ? fail : c.status;
-        if (c.live()) {
-            note(c, chol_prep_launch(G, w, W, gate, attempt, sscale, c.st));
-            note(c, zero_f64_launch(Rw, 4 * ps, gate, c.st));
-            note(c, zero_f64_launch(Rinv, 4 * ps, gate, c.st));
-        }
+        if (c.live()) note(c, chol_prep_launch(G, w, W, gate, attempt, sscale, c.st));
         for (int64_t k0 = 0; k0 < w; k0 += b) {
             const int64_t kb = std::min(b, w - k0), k1 = k0 + kb, rest = w - k1;
-            if (c.live()) {
-                note(c, copy_f64_planes_launch(W + k0 * w + k0, w, ps, Gk, kb, kb * kb, kb, kb, gate, c.st));
-                note(c, chol_launch(Gk, kb, Rk, Ik, nullptr, nullptr, st, nullptr, gate, 0, 0.0, nullptr, 0.0, c.st));
-                note(c, copy_f64_planes_launch(Rk, kb, kb * kb, Rw + k0 * w + k0, w, ps, kb, kb, gate, c.st));
-                note(c, copy_f64_planes_launch(Ik, kb, kb * kb, Rinv + k0 * w + k0, w, ps, kb, kb, gate, c.st));
-            }
+            double* Ik = Rinv + k0 * w + k0;
+            if (c.live())
+                note(c, chol_inv_launch(W + k0 * w + k0, w, ps, kb, Rw + k0 * w + k0, w, ps, Ik, w, ps, k0, w, st,
+                                        nullptr, gate, 0, 0.0, nullptr, 0.0, c.st));
             if (rest > 0) {
-                qg(c, desc(OP_HN, MATH_F64, Ik, kb, kb * kb, 1, W + k0 * w + k1, w, ps, 1, Rw + k0 * w + k1, w, ps, 1,
+                qg(c, desc(OP_HN, MATH_F64, Ik, w, ps, 1, W + k0 * w + k1, w, ps, 1, Rw + k0 * w + k1, w, ps, 1,
                            kb, rest, kb, ST_SET, gate));
                 qg(c, desc(OP_HN, MATH_F64, Rw + k0 * w + k1, w, ps, 1, Rw + k0 * w + k1, w, ps, 1, W + k1 * w + k1, w,
                            ps, 1, rest, rest, kb, ST_SUB, gate));

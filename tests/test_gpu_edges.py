@@ -11,6 +11,8 @@
 - non-finite input (one NaN or one Inf entry): the status word reports QLRA_E_NUMERIC;
 - ragged shapes on a spectrum with gaps (sigma_i = 1 / i), compared element by element: the
   singular values, the factors themselves (canonical phases), U diag(S) V^H and the estimates;
+- per-pass estimates of views wider than the single-workgroup eigensolver (l = 97, 160) beside
+  l = 96, on a slowly decaying spectrum;
 - the orthogonality gate of the second CholeskyQR round, in both branches.
 """
 import numpy as np
@@ -157,6 +159,29 @@ def test_ragged_gapped_elementwise(gq, oracle, m, n, k, p, v, scheme):
     assert np.abs(Vg - Vo).max() <= 1e-4
     assert ahat_rel(A64, (Ug, Sg, Vg), (Uo, So, Vo)) <= 1e-5
     assert np.isnan(eg[0]) and np.all(np.abs(eg[1:] ** 2 - eo[1:] ** 2) <= 16 * U32)
+
+
+@pytest.mark.parametrize("k,p", [(80, 16), (81, 16), (128, 32)])
+def test_wide_view_estimates(gq, oracle, k, p):
+    """Per-pass estimates of views of width l = 96 (the single-workgroup eigensolver), 97 and 160
+    (the large-order solver's batched values-only path), subspace scheme with a budget of 6, on a
+    slowly decaying spectrum (sigma_i = i^-1/2, reflector-product unitaries, 1024 x 768); the
+    budgets 3 .. 5 end with the final QSVD on the same views, whose last estimate is the error
+    of the returned factors.  Estimate bound as at full size: 4 (i - 1) u32 sqrt(n) on e_i^2
+    (measured here: below 1e-7)."""
+    m, n = 1024, 768
+    print(f"wide estimates {m} x {n} k={k} p={p}", flush=True)
+    sigma = np.arange(1, n + 1) ** -0.5
+    A = W.reflector_spectrum_matrix(4, m, n, sigma)
+    Uo, So, Vo, eo = oracle.qlra(A.astype(np.float64), k, p, 6, 0, 11)
+    tol = 4 * np.arange(1, 6) * U32 * np.sqrt(n)
+    Ug, Sg, Vg, eg, st = run_gpu(gq, A, k, p, 6, 0, 11)
+    assert st == gq.QLRA_OK
+    assert np.isnan(eg[0]) and np.all(np.abs(eg[1:] ** 2 - eo[1:] ** 2) <= tol)
+    for v in (3, 4, 5):
+        _, _, _, ev, st = run_gpu(gq, A, k, p, v, 0, 11)
+        assert st == gq.QLRA_OK
+        assert abs(ev[-1] ** 2 - eo[v - 1] ** 2) <= tol[v - 2]
 
 
 def test_cholqr_orthogonality_gate(gq):
