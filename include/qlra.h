@@ -330,10 +330,11 @@ int qlra_qgemm_split(int op, int precision, const void* Alo, const void* Alo_res
  * twice; a shifted first round replaces a failed one (shifted CholeskyQR), and
  * one more round follows it.  Q (m x w, FP32) has orthonormal columns; R
  * (w x w, FP64 planes, ld = w, plane stride w*w) is upper triangular with a
- * real positive diagonal and Y = Q R.  Q may alias Y.  R may be NULL: then,
- * for w <= 96, the second round's Cholesky and triangular solve run only when
- * the first round left max |Q^H Q - I| above 1e-7 (decided on the device; the
- * decision is int 3 of the workspace, 1 = ran).  Int 1 of the workspace is 1
+ * real positive diagonal and Y = Q R.  Q may alias Y.  R may be NULL: then
+ * the second round's Cholesky and triangular solve (w <= 96) or product with
+ * R^{-1} (larger w) run only when the first round left max |Q^H Q - I| above
+ * 1e-7 (decided on the device; the decision is int 3 of the workspace, 1 =
+ * ran; for w > 96 int 4 holds its opposite).  Int 1 of the workspace is 1
  * when the first round was shifted, int 0 has bit 1 (value 2) set when the
  * factorization failed even with the shift. */
 int qlra_cholqr_workspace_size(int64_t m, int64_t w, size_t* bytes);

@@ -281,7 +281,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict_
 //   R into Rout and R^{-1} into Rinv (row strides ldr / ldx, plane strides rps / xps), zeros
 //   below the diagonal; with band_w > 0 the block sits at column band_off of a row band of
 //   width band_w, whose other columns (rows 0 .. w-1 of the block) are set to zero in both.
-// The factor comes from chol_factor; R's upper triangle then goes to LDS (packed by rows,
+// The factor comes from chol_factor; R's upper triangle then goes to LDS (packed by columns,
 // components side by side) and the inverse is formed by columns, each by back substitution
 // R x = e_c in one 16-lane group (column c and column w - 1 - c per group, so that every group
 // takes w + 1 steps): step t finishes x_t = acc_t / r_tt on its owner lane, broadcasts it over the
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_inv(const double* __restrict_
             const Q4 v = up ? g[ri][ci] : Q4{0, 0, 0, 0};
             st4(Rout, rps, (int64_t)a * ldr + b, v);
             if (up) {
-                sti(sR, upk(a, b, w), v);
+                sti(sR, b * (b + 1) / 2 + a, v);          // packed by columns
                 nr += qn2(v);
                 if (a == b) sdi[a] = v.w > 0.0 ? 1.0 / v.w : 0.0;
             }
@@ -349,20 +349,19 @@ __global__ __launch_bounds__(kThreads) void k_chol_inv(const double* __restrict_
             for (int u = 0; u < NU; u++) acc[u] = (s + 16 * u == c) ? Q4{1, 0, 0, 0} : Q4{0, 0, 0, 0};
             for (int t = c; t >= 0; t--) {
                 const int ut = t >> 4, src = (lane & ~15) | (t & 15);
-                Q4 r[NU];
-#pragma unroll
-                for (int u = 0; u < NU; u++) r[u] = ldi(sR, upk(min(s + 16 * u, t), t, w));
+                const int cb = t * (t + 1) / 2;         // column t of R: rows 0 .. t contiguous
                 Q4 v{0, 0, 0, 0};
 #pragma unroll
                 for (int u = 0; u < NU; u++)
                     if (u == ut) v = acc[u];
                 v = qscale(v, sdi[t]);
                 const Q4 x{__shfl(v.w, src, 64), __shfl(v.x, src, 64), __shfl(v.y, src, 64), __shfl(v.z, src, 64)};
+                // only the rows above t read R (consecutive lanes, consecutive entries)
 #pragma unroll
                 for (int u = 0; u < NU; u++) {
                     const int i = s + 16 * u;
-                    const Q4 nb = qfms(acc[u], r[u], x);
-                    acc[u] = qsel(i < t, nb, qsel(i == t, x, acc[u]));
+                    if (i < t) acc[u] = qfms(acc[u], ldi(sR, cb + i), x);
+                    else if (i == t) acc[u] = x;
                 }
             }
 #pragma unroll
@@ -612,13 +611,17 @@ __global__ __launch_bounds__(256) void k_zero_f64(double* __restrict__ p, int64_
 }
 
 // *gate_out = 1 when max |G - I| over the four planes of a w x w Gram exceeds tol (or is not
-// finite), else 0; always 0 when gate_in is given and *gate_in == 0.  One workgroup.
+// finite), else 0; always 0 when gate_in is given and *gate_in == 0.  *gate_not (if given) is
+// the opposite.  One workgroup.
 __global__ __launch_bounds__(256) void k_orth_gate(const double* __restrict__ G, int w, double tol, int* gate_out,
-                                                   const int* gate_in) {
+                                                   const int* gate_in, int* gate_not) {
     __shared__ double red[4];
     const int tid = threadIdx.x;
     if (gate_in && *gate_in == 0) {
-        if (tid == 0) *gate_out = 0;
+        if (tid == 0) {
+            *gate_out = 0;
+            if (gate_not) *gate_not = 1;
+        }
         return;
     }
     const int64_t ps = (int64_t)w * w;
@@ -640,6 +643,7 @@ __global__ __launch_bounds__(256) void k_orth_gate(const double* __restrict__ G,
         double m = red[0];
         for (int i = 1; i < 4; i++) m = (red[i] > m || red[i] != red[i]) ? red[i] : m;
         *gate_out = (m <= tol) ? 0 : 1;
+        if (gate_not) *gate_not = (m <= tol) ? 1 : 0;
     }
 }
 
@@ -708,9 +712,9 @@ hipError_t zero_f64_launch(double* p, int64_t count, const int* gate, hipStream_
 
 
 hipError_t orth_gate_launch(const double* G, int64_t w, double tol, int* gate_out, const int* gate_in,
-                            hipStream_t st) {
+                            hipStream_t st, int* gate_not) {
     if (w < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_orth_gate, dim3(1), dim3(256), 0, st, G, (int)w, tol, gate_out, gate_in);
+    hipLaunchKernelGGL(k_orth_gate, dim3(1), dim3(256), 0, st, G, (int)w, tol, gate_out, gate_in, gate_not);
     return hipGetLastError();
 }
 

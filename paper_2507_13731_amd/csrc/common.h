@@ -131,9 +131,9 @@ hipError_t zero_f64_launch(double* p, int64_t count, const int* gate, hipStream_
 // *dst = (*src != 0).
 hipError_t flag_nonzero_launch(int* dst, const int* src, hipStream_t st);
 // *gate_out = 1 when max |G - I| (G a w x w Gram, FP64 planes) exceeds tol or is not finite, else
-// 0; always 0 when gate_in is given and *gate_in == 0.
+// 0; always 0 when gate_in is given and *gate_in == 0.  *gate_not (if given) = 1 - *gate_out.
 hipError_t orth_gate_launch(const double* G, int64_t w, double tol, int* gate_out, const int* gate_in,
-                            hipStream_t st);
+                            hipStream_t st, int* gate_not = nullptr);
 // Cholesky alone for w <= chol_reg_max(), factor to R (no inverse) and to Rpk, R's upper
 // triangle packed by rows with the four components of an entry side by side (4 w (w + 1) / 2
 // doubles, the input of trsm_launch); same status, shift and gate behaviour as chol_launch.

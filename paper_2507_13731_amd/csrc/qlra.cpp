@@ -203,13 +203,20 @@ void cholqr(Ctx& c, const float* Y, int64_t rows, int64_t w, int64_t ldy, int64_
     // <= 1e-7 (a second round would move Q by less than its FP32 rounding) the Cholesky and the
     // triangular solve of that round are skipped on the device.  The first round then writes Q
     // directly and the second works in place.
-    const bool gated = small && rounds == 2 && !R && c.status;
+    // The larger orders gate their second round the same way: the first round writes T2, whose
+    // Gram goes through the orthogonality test (a separate launch, gate in status[3], its
+    // opposite in status[4]); then either the factorization and the product T2 R^{-1} into Q run,
+    // or T2 is copied to Q.  (The product cannot work in place: other column tiles still read
+    // the rows it writes.)
+    const bool gated = rounds == 2 && !R && c.status;
     int* gate = gated ? c.status + 3 : nullptr;
+    int* gate_not = gated ? c.status + 4 : nullptr;
     const double* Rprev = nullptr;
     for (int round = 0; round < rounds; round++) {
         const bool last = round == rounds - 1;
-        float* dst = (last || gated) ? Q : c.T2;
-        const int64_t ldd = (last || gated) ? ldq : w, dps = (last || gated) ? qps : tps;
+        const bool to_q = last || (gated && small);
+        float* dst = to_q ? Q : c.T2;
+        const int64_t ldd = to_q ? ldq : w, dps = to_q ? qps : tps;
         double* G = (round == 0 && G0) ? G0 : c.G;
         qg(c, desc(OP_HN, MATH_F64, src, lds, sps, 0, src, lds, sps, 0, G, w, w * w, 1, w, w, rows));
         if (small) {
@@ -225,16 +232,24 @@ void cholqr(Ctx& c, const float* Y, int64_t rows, int64_t w, int64_t ldy, int64_
             }
         } else {
             double* Rout = last ? (R ? R : c.Rjunk) : c.R1;
+            // the product R = R2 R1 only when R is wanted
+            const double* rp = R ? Rprev : nullptr;
+            const int* g = (gated && round == 1) ? gate : nullptr;
+            if (g && c.live()) {
+                note(c, orth_gate_launch(G, w, 1e-7, gate, nullptr, c.st, gate_not));
+                note(c, copy_planes_launch(src, lds, sps, Q, ldq, qps, rows, w, gate_not, c.st));
+            }
             if (w <= chol_lds_max()) {
                 if (c.live())
-                    note(c, chol_launch(G, w, Rout, c.Rinv, Rprev, c.chol_work, c.status,
-                                        round == 0 ? shifted : nullptr, nullptr, round == 0 ? 1 : 0,
+                    note(c, chol_launch(G, w, Rout, c.Rinv, rp, c.chol_work, c.status,
+                                        round == 0 ? shifted : nullptr, g, round == 0 ? 1 : 0,
                                         shift_scale(rows, w), nullptr, 0.0, c.st));
             } else {
-                chol_blocked(c, G, w, Rout, c.Rinv, Rprev, round == 0 ? shifted : nullptr, round == 0 ? 1 : 0,
-                             shift_scale(rows, w));
+                chol_blocked(c, G, w, Rout, c.Rinv, rp, round == 0 ? shifted : nullptr, round == 0 ? 1 : 0,
+                             shift_scale(rows, w), g);
             }
-            QgemmDesc ap = desc(OP_NN, MATH_F64, src, lds, sps, 0, c.Rinv, w, w * w, 1, dst, ldd, dps, 0, rows, w, w);
+            QgemmDesc ap = desc(OP_NN, MATH_F64, src, lds, sps, 0, c.Rinv, w, w * w, 1, dst, ldd, dps, 0, rows, w, w,
+                                ST_SET, g);
             ap.b_upper = 1;                        // R^{-1} is upper triangular
             qg(c, ap);
             Rprev = Rout;
@@ -1438,6 +1453,7 @@ static void cholqr_carve(int64_t m, int64_t w, Arena& ar, Ctx& c, size_t part, s
     c.G = (double*)ar.take(4 * w2 * sizeof(double));
     c.R1 = (double*)ar.take(4 * w2 * sizeof(double));
     c.R2 = (double*)ar.take(4 * w2 * sizeof(double));
+    c.Rjunk = (double*)ar.take(4 * w2 * sizeof(double));   // the last factor when R is not wanted
     c.blk = w > chol_lds_max() ? (double*)ar.take(chol_blk_doubles() * sizeof(double)) : nullptr;
     c.Rinv = (double*)ar.take(4 * w2 * sizeof(double));
     c.chol_work = (double*)ar.take(4 * w2 * sizeof(double));

@@ -184,19 +184,30 @@ def test_wide_view_estimates(gq, oracle, k, p):
         assert abs(ev[-1] ** 2 - eo[v - 1] ** 2) <= tol[v - 2]
 
 
-def test_cholqr_orthogonality_gate(gq):
+@pytest.mark.parametrize("w", [60, 160])
+def test_cholqr_orthogonality_gate(gq, w):
     """Without R the second CholeskyQR round runs only when the first left max |Q^H Q - I| above
     1e-7: skipped for a well-conditioned Y, taken for cond(Y) ~ 1e6 (one round in FP64 leaves an
-    error up to about u64 cond^2), Q orthonormal either way."""
+    error up to about u64 cond^2), Q orthonormal and Q R = Y either way (w = 160: the blocked
+    factorization, whose second round goes through a copy; Q aliases Y there, as in the Krylov
+    stack)."""
     import torch
-    m, w = 2048, 60
+    m = 2048
     for sv, want in ((np.ones(w), 0), (np.logspace(0, -6, w), 1)):
         # singular values sv between reflector-product unitaries (column scaling alone would not
         # do: CholeskyQR is invariant to it)
         Ys = np.ascontiguousarray(W.spectrum_matrix(3, m, w, sv, nrefl=4), dtype=np.float32)
-        Q, R, ws = gq.qlra_cholqr(torch.from_numpy(Ys).cuda(), return_workspace=True, want_r=False)
+        Y = torch.from_numpy(Ys).cuda()
+        Q, R, ws = gq.qlra_cholqr(Y, Q=Y if w > 96 else None, return_workspace=True, want_r=False)
         assert R is None
         torch.cuda.synchronize()
         flags = ws[:64].view(torch.int32).cpu().numpy()
-        assert flags[3] == want, (flags[:4], want)
-        assert orth_err(Q.cpu().numpy().astype(np.float64)) <= 2e-6
+        assert flags[3] == want, (flags[:5], want)
+        if w > 96:
+            assert flags[4] == 1 - want, flags[:5]
+        Qh = Q.cpu().numpy().astype(np.float64)
+        assert orth_err(Qh) <= 2e-6
+        # the same range: Q Q^H Y = Y
+        Y64 = Ys.astype(np.float64)
+        P = qref.mul(Qh, qref.mul(qref.adj(Qh), Y64))
+        assert np.abs(P - Y64).max() <= 1e-5 * np.abs(Y64).max()
