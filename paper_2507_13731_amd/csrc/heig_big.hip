@@ -102,8 +102,8 @@ struct BigRec {
     double* P;      // 2 x 4 W: p = tau G v of a reflector (the two buffers alternate by step parity)
     double* KP;     // 2 x step_blocks(W) shares of v^H p
     double* CB;     // 2 x 4 W: copy of the column of the next reflector, taken before its update
-    double* X;      // W x nvec eigenvectors of T (vector t at X + t W)
-    double* DM;     // W x nvec backward pivots
+    double* X;      // W x nvec eigenvectors of T (entry i of vector t at X[i nvec + t])
+    double* DM;     // W x nvec backward pivots (the same layout)
 };
 
 __host__ __device__ inline BigRec big_rec(double* base, int64_t W, int64_t nvec) {
@@ -296,27 +296,32 @@ __global__ __launch_bounds__(BT) void k_big_step(double* base0, int64_t rstride,
 }
 
 // diagonal, real subdiagonal b_j = |s_j|, phases ph_{j+1} = s_j ph_j / |s_j|, bounds (problem
-// blockIdx.x)
-__global__ void k_big_fin(double* __restrict__ base0, int64_t rstride, int W, int nvec) {
-    if (threadIdx.x != 0) return;
+// blockIdx.x): the diagonal of the working matrix and the s_j are first staged in LDS by the
+// whole wave (independent loads), then one lane runs the chain of phases from LDS.
+__global__ __launch_bounds__(64) void k_big_fin(double* __restrict__ base0, int64_t rstride, int W, int nvec) {
+    __shared__ double sd[1024], ss[4 * 1024];          // W <= 1024
     BigRec R = big_rec(base0 + blockIdx.x * rstride, W, nvec);
     const int64_t ps = (int64_t)W * W;
-    if (W >= 2) {
-        const Q4 sl = ld(R.Gw, ps, (int64_t)(W - 1) * W + (W - 2));
-        R.ph[W - 2] = sl.w; R.ph[W + W - 2] = sl.x; R.ph[2 * W + W - 2] = sl.y; R.ph[3 * W + W - 2] = sl.z;
-        R.tau[W - 2] = 0.0;
+    for (int i = threadIdx.x; i < W; i += 64) {
+        sd[i] = R.Gw[(int64_t)i * W + i];
+        Q4 sj{0, 0, 0, 0};
+        if (i + 2 < W) sj = Q4{R.ph[i], R.ph[W + i], R.ph[2 * W + i], R.ph[3 * W + i]};
+        else if (i + 2 == W) sj = ld(R.Gw, ps, (int64_t)(W - 1) * W + (W - 2));   // the last subdiagonal entry
+        ss[i] = sj.w; ss[W + i] = sj.x; ss[2 * W + i] = sj.y; ss[3 * W + i] = sj.z;
     }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    if (W >= 2) R.tau[W - 2] = 0.0;
     R.tau[W - 1] = 0.0;
     Q4 pj{1, 0, 0, 0};
     double lo = 1e300, hi = -1e300, bl = 0.0;
     for (int i = 0; i < W; i++) {
-        const double dd = R.Gw[(int64_t)i * W + i];
+        const double dd = sd[i];
         R.d[i] = dd;
         double br = 0.0;
-        Q4 sj{0, 0, 0, 0};
-        if (i + 1 < W) sj = Q4{R.ph[i], R.ph[W + i], R.ph[2 * W + i], R.ph[3 * W + i]};
         R.ph[i] = pj.w; R.ph[W + i] = pj.x; R.ph[2 * W + i] = pj.y; R.ph[3 * W + i] = pj.z;
         if (i + 1 < W) {
+            const Q4 sj{ss[i], ss[W + i], ss[2 * W + i], ss[3 * W + i]};
             br = sqrt(qn2(sj));
             pj = br > 0.0 ? qscale(qmul(sj, pj), 1.0 / br) : Q4{1, 0, 0, 0};
         }
@@ -400,57 +405,73 @@ __device__ __forceinline__ double fdiv(double x, double y) {
 
 // eigenvectors of T for the ascending indices [c0, W) (c0 = W - nvec extended down to the start
 // of its cluster, computed on the host side of the launch by every block alike): twisted
-// factorisations, one thread each
+// factorisations, one thread each.  The tridiagonal is staged in LDS; vector t's entry i sits at
+// X[i nvec + t] (and its backward pivots at DM[i nvec + t]), so that the threads' accesses of a
+// step are one coalesced run.
 __global__ __launch_bounds__(BT) void k_big_twisted(double* __restrict__ base, int W, int nvec, int kfirst) {
+    __shared__ double sd[1024], sb[1024], sb2[1024];    // W <= 1024
     BigRec R = big_rec(base, W, nvec);
+    for (int i = threadIdx.x; i < W; i += BT) {
+        sd[i] = R.d[i];
+        sb[i] = R.b[i];
+        sb2[i] = R.b2[i];
+    }
+    __syncthreads();
     const double tnorm = fmax(fabs(R.bnd[0]), fabs(R.bnd[1])) + 1e-300;
     const double tiny = 1e-300 + 2.220446049250313e-16 * tnorm * 1e-3;
     const int t = blockIdx.x * BT + threadIdx.x;     // vector slot
     const int k = kfirst + t;
     if (t >= nvec || k >= W) return;
     const double mu = R.lam[k];
-    double* x = R.X + (int64_t)t * W;
-    double* dm = R.DM + (int64_t)t * W;
-    double fp = R.d[0] - mu, bp = R.d[W - 1] - mu;
+    double* x = R.X + t;
+    double* dm = R.DM + t;
+    const int64_t sv = nvec;                         // stride between entries of one vector
+    double fp = sd[0] - mu, bp = sd[W - 1] - mu;
     if (fabs(fp) < tiny) fp = -tiny;
     if (fabs(bp) < tiny) bp = -tiny;
     x[0] = fp;
-    dm[W - 1] = bp;
+    dm[(int64_t)(W - 1) * sv] = bp;
     for (int i = 1; i < W; i++) {
         const int ib = W - 1 - i;
-        double f = (R.d[i] - mu) - fdiv(R.b2[i - 1], fp);
-        double g = (R.d[ib] - mu) - fdiv(R.b2[ib], bp);
+        double f = (sd[i] - mu) - fdiv(sb2[i - 1], fp);
+        double g = (sd[ib] - mu) - fdiv(sb2[ib], bp);
         if (fabs(f) < tiny) f = -tiny;
         if (fabs(g) < tiny) g = -tiny;
-        x[i] = f;
-        dm[ib] = g;
+        x[(int64_t)i * sv] = f;
+        dm[(int64_t)ib * sv] = g;
         fp = f;
         bp = g;
     }
     int r = W - 1;
-    double best = fabs(x[W - 1]);
+    double best = fabs(x[(int64_t)(W - 1) * sv]);
     for (int i = W - 2; i >= 0; i--) {
-        const double gam = fabs(x[i] + dm[i] - (R.d[i] - mu));
+        const double gam = fabs(x[(int64_t)i * sv] + dm[(int64_t)i * sv] - (sd[i] - mu));
         if (gam < best) { best = gam; r = i; }
     }
+    // x_{r +- s} from x_{r +- (s - 1)}; the pivots of the next step are loaded one step ahead
     double xd = 1.0, xu = 1.0, nrm = 1.0;
     const int steps = max(W - 1 - r, r);
+    double dn = r + 1 < W ? dm[(int64_t)(r + 1) * sv] : 1.0;
+    double up = r - 1 >= 0 ? x[(int64_t)(r - 1) * sv] : 1.0;
     for (int s = 1; s <= steps; s++) {
         const int id = r + s, iu = r - s;
+        const double dcur = dn, ucur = up;
+        dn = id + 1 < W ? dm[(int64_t)(id + 1) * sv] : 1.0;
+        up = iu - 1 >= 0 ? x[(int64_t)(iu - 1) * sv] : 1.0;
         if (id < W) {
-            xd = -fdiv(R.b[id - 1] * xd, dm[id]);
-            x[id] = xd;
+            xd = -fdiv(sb[id - 1] * xd, dcur);
+            x[(int64_t)id * sv] = xd;
             nrm += xd * xd;
         }
         if (iu >= 0) {
-            xu = -fdiv(R.b[iu] * xu, x[iu]);
-            x[iu] = xu;
+            xu = -fdiv(sb[iu] * xu, ucur);
+            x[(int64_t)iu * sv] = xu;
             nrm += xu * xu;
         }
     }
-    x[r] = 1.0;
+    x[(int64_t)r * sv] = 1.0;
     nrm = 1.0 / sqrt(nrm);
-    for (int i = 0; i < W; i++) x[i] *= nrm;
+    for (int i = 0; i < W; i++) x[(int64_t)i * sv] *= nrm;
 }
 
 // modified Gram-Schmidt inside clusters of close eigenvalues among the computed vectors (one wave)
@@ -463,63 +484,75 @@ __global__ void k_big_mgs(double* __restrict__ base, int W, int nvec, int kfirst
     for (int t = 1; t <= kcount; t++) {
         if (t < kcount && R.lam[kfirst + t] - R.lam[kfirst + t - 1] <= ctol) continue;
         for (int a = cs + 1; a < t; a++) {
-            double* xa = R.X + (int64_t)a * W;
+            double* xa = R.X + a;                       // entry i at xa[i nvec]
             for (int bq = cs; bq < a; bq++) {
-                const double* xb = R.X + (int64_t)bq * W;
+                const double* xb = R.X + bq;
                 double dot = 0.0;
-                for (int i = lane; i < W; i += 64) dot += xa[i] * xb[i];
+                for (int i = lane; i < W; i += 64) dot += xa[(int64_t)i * nvec] * xb[(int64_t)i * nvec];
                 dot = wave_total(dot);
-                for (int i = lane; i < W; i += 64) xa[i] -= dot * xb[i];
+                for (int i = lane; i < W; i += 64) xa[(int64_t)i * nvec] -= dot * xb[(int64_t)i * nvec];
             }
             double nr2 = 0.0;
-            for (int i = lane; i < W; i += 64) nr2 += xa[i] * xa[i];
+            for (int i = lane; i < W; i += 64) nr2 += xa[(int64_t)i * nvec] * xa[(int64_t)i * nvec];
             nr2 = wave_total(nr2);
             const double inv = nr2 > 0.0 ? 1.0 / sqrt(nr2) : 0.0;
-            for (int i = lane; i < W; i += 64) xa[i] *= inv;
+            for (int i = lane; i < W; i += 64) xa[(int64_t)i * nvec] *= inv;
         }
         cs = t;
     }
 }
 
 // back-transformation y = H_0 ... H_{W-3} D x for the nout largest eigenvalues, one wave each,
-// lane holding rows lane + 64 u; E (W x nout, ld nout) gets them in descending order
-constexpr int kBigRows = 16;   // rows per lane: W <= 1024
+// lane holding rows lane + 64 u (u < NR, W <= 64 NR); E (W x nout, ld nout) gets them in
+// descending order.  The reflector of the next step is loaded (into the other of two register
+// sets) while the current one is applied; rows at or above a reflector's pivot hold zeros.
+template <int NR>
 __global__ __launch_bounds__(BT) void k_big_back(double* __restrict__ base, int W, int nvec, int kfirst, int nout,
                                                  double* __restrict__ E) {
     BigRec R = big_rec(base, W, nvec);
     const int lane = threadIdx.x & 63;
     const int o = blockIdx.x * (BT / 64) + (threadIdx.x >> 6);   // output column
     if (o >= nout) return;
-    const int k = W - 1 - o;                                    // ascending index
-    const double* xk = R.X + (int64_t)(k - kfirst) * W;
+    const int slot = W - 1 - o - kfirst;                        // ascending index W - 1 - o
     const int64_t pps = (int64_t)W * (W + 1) / 2;
-    Q4 y[kBigRows];
+    Q4 y[NR];
 #pragma unroll
-    for (int u = 0; u < kBigRows; u++) {
+    for (int u = 0; u < NR; u++) {
         const int i = lane + 64 * u;
-        y[u] = i < W ? qscale(Q4{R.ph[i], R.ph[W + i], R.ph[2 * W + i], R.ph[3 * W + i]}, xk[i]) : Q4{0, 0, 0, 0};
+        y[u] = i < W ? qscale(Q4{R.ph[i], R.ph[W + i], R.ph[2 * W + i], R.ph[3 * W + i]},
+                              R.X[(int64_t)i * nvec + slot])
+                     : Q4{0, 0, 0, 0};
     }
-    for (int j = W - 3; j >= 0; j--) {
+    auto load_v = [&](int j, Q4 (&v)[NR]) {
+#pragma unroll
+        for (int u = 0; u < NR; u++) {
+            const int i = lane + 64 * u;
+            v[u] = (i > j && i < W) ? ld(R.refl, pps, refl_at(W, i, j)) : Q4{0, 0, 0, 0};
+        }
+    };
+    auto apply = [&](int j, const Q4 (&v)[NR]) {
         const double tj = R.tau[j];
-        if (tj == 0.0) continue;
         Q4 s{0, 0, 0, 0};
 #pragma unroll
-        for (int u = 0; u < kBigRows; u++) {
-            const int i = lane + 64 * u;
-            if (64 * u < W && i > j && i < W)                    // the first test is uniform
-                s = qadd(s, qmul(qconj(ld(R.refl, pps, refl_at(W, i, j))), y[u]));
-        }
+        for (int u = 0; u < NR; u++) s = qadd(s, qmul(qconj(v[u]), y[u]));
         s.w = wave_total(s.w); s.x = wave_total(s.x); s.y = wave_total(s.y); s.z = wave_total(s.z);
         s = qscale(s, tj);
 #pragma unroll
-        for (int u = 0; u < kBigRows; u++) {
-            const int i = lane + 64 * u;
-            if (64 * u < W && i > j && i < W) y[u] = qsub(y[u], qmul(ld(R.refl, pps, refl_at(W, i, j)), s));
-        }
+        for (int u = 0; u < NR; u++) y[u] = qsub(y[u], qmul(v[u], s));
+    };
+    Q4 va[NR], vb[NR];
+    int j = W - 3;
+    if (j >= 0) load_v(j, va);
+    for (; j >= 1; j -= 2) {
+        load_v(j - 1, vb);
+        apply(j, va);
+        if (j >= 2) load_v(j - 2, va);
+        apply(j - 1, vb);
     }
+    if (j == 0) apply(0, va);
     const int64_t eps = (int64_t)W * nout;
 #pragma unroll
-    for (int u = 0; u < kBigRows; u++) {
+    for (int u = 0; u < NR; u++) {
         const int i = lane + 64 * u;
         if (i < W) st(E, eps, (int64_t)i * nout + o, y[u]);
     }
@@ -581,8 +614,17 @@ hipError_t heig_big_launch(const double* G, int64_t W, double* lam, double* E, i
     hipLaunchKernelGGL(k_big_twisted, dim3((unsigned)((nvec + BT - 1) / BT)), dim3(BT), 0, st, work, (int)W,
                        (int)nvec, kfirst);
     hipLaunchKernelGGL(k_big_mgs, dim3(1), dim3(64), 0, st, work, (int)W, (int)nvec, kfirst, (int)nvec);
-    hipLaunchKernelGGL(k_big_back, dim3((unsigned)((nout + 3) / 4)), dim3(BT), 0, st, work, (int)W, (int)nvec, kfirst,
-                       (int)nout, E);
+    const dim3 gb((unsigned)((nout + 3) / 4));
+    if (W <= 256)
+        hipLaunchKernelGGL(k_big_back<4>, gb, dim3(BT), 0, st, work, (int)W, (int)nvec, kfirst, (int)nout, E);
+    else if (W <= 512)
+        hipLaunchKernelGGL(k_big_back<8>, gb, dim3(BT), 0, st, work, (int)W, (int)nvec, kfirst, (int)nout, E);
+    else if (W <= 640)
+        hipLaunchKernelGGL(k_big_back<10>, gb, dim3(BT), 0, st, work, (int)W, (int)nvec, kfirst, (int)nout, E);
+    else if (W <= 768)
+        hipLaunchKernelGGL(k_big_back<12>, gb, dim3(BT), 0, st, work, (int)W, (int)nvec, kfirst, (int)nout, E);
+    else
+        hipLaunchKernelGGL(k_big_back<16>, gb, dim3(BT), 0, st, work, (int)W, (int)nvec, kfirst, (int)nout, E);
     return hipGetLastError();
 }
 
