@@ -857,6 +857,8 @@ constexpr int LBM = 64;    // output rows per workgroup (16 per wave)
 struct LpParams {
     const void* A; int64_t akt, art;      // tiled copy: reduction tiles per row tile, row tiles
     const void* Bt; int64_t bkp;          // converted thin operand: [4][Np][bkp]
+    const void* A2;                       // split form: the residual copy of A (same tiling)
+    const void* Bt2;                      // split form: the residual of the thin operand
     float* C; int64_t ldc, cps;
     int64_t M, N, K;
     int64_t kchunk;
@@ -898,8 +900,12 @@ __global__ __launch_bounds__(256) void k_lp_thin_res(const float* __restrict__ B
 // thin-tile loads, so that waiting for those (vmcnt counts in issue order) never waits for A.
 // Every load is unconditional (addresses clamped into the copies; a step past the end of K
 // meets zero rows of the padded thin tile), so the wait counts stay exact across iterations.
+// SPL (the split form fused): the residual copies of A and of the thin operand come along, the
+// residual tile staged next to the value tile, and every step issues the three products
+// A_hi B_hi + A_hi B_lo + A_lo B_hi into the same accumulators (three times the MFMA work per
+// staged tile and per barrier; one read of each copy).
 constexpr int LKS = 2 * LBK;
-template <class TL, bool ADJ, int CN, int NCG, int CNW, int LK>
+template <class TL, bool ADJ, int CN, int NCG, int CNW, int LK, bool SPL = false>
 __global__ __launch_bounds__(256 * NCG) void k_qgemm_lp(LpParams P) {
     using L = LpMma<TL>;
     using v8 = typename L::v8;
@@ -909,8 +915,9 @@ __global__ __launch_bounds__(256 * NCG) void k_qgemm_lp(LpParams P) {
     constexpr int NT = 256 * NCG;
     constexpr int CH = 4 * NP * (LK / 8);         // 16-byte chunks of one thin tile
     constexpr int CPT = CH / NT;                  // chunks per thread
+    constexpr int NTILE = SPL ? 2 : 1;            // staged tiles: the value, and the residual
     static_assert(CH % NT == 0, "whole chunks per thread");
-    __shared__ __attribute__((aligned(16))) TL sB[4 * NP * SK];
+    __shared__ __attribute__((aligned(16))) TL sB[NTILE * 4 * NP * SK];
     if (P.skip && *P.skip == 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int rg = wave & 3, cg = wave >> 2;
@@ -922,36 +929,45 @@ __global__ __launch_bounds__(256 * NCG) void k_qgemm_lp(LpParams P) {
     const int64_t rbase = 16 * rt;
     const int64_t col0 = (int64_t)blockIdx.y * NP;                 // this workgroup's column tile
     // a row tile past the copy reads the last one: its rows are never stored
-    const TL* __restrict__ Ab = (const TL*)P.A + (rt < P.art ? rt : P.art - 1) * P.akt * 4096 + 8 * lane;
-    const TL* __restrict__ Bt = (const TL*)P.Bt;
+    const int64_t aoff = (rt < P.art ? rt : P.art - 1) * P.akt * 4096 + 8 * lane;
+    const TL* __restrict__ Abase[2] = {(const TL*)P.A + aoff, SPL ? (const TL*)P.A2 + aoff : nullptr};
+    const TL* __restrict__ Btile[2] = {(const TL*)P.Bt, SPL ? (const TL*)P.Bt2 : nullptr};
     const int64_t kt_last = P.akt - 1;
 
-    auto load_a = [&](int64_t k0, v8 (&a)[4][2]) {
+    // the A fragments of one K step: a[t][q][h] for copy t (value, residual)
+    auto load_a = [&](int64_t k0, v8 (&a)[NTILE][4][2]) {
         const int64_t kt = (k0 >> 6) < kt_last ? (k0 >> 6) : kt_last;
-        const TL* src = Ab + kt * 4096;
 #pragma unroll
-        for (int q = 0; q < 4; q++)
+        for (int t = 0; t < NTILE; t++) {
+            const TL* src = Abase[t] + kt * 4096;
 #pragma unroll
-            for (int h = 0; h < 2; h++) a[q][h] = *reinterpret_cast<const v8*>(src + q * 1024 + h * 512);
+            for (int q = 0; q < 4; q++)
+#pragma unroll
+                for (int h = 0; h < 2; h++) a[t][q][h] = *reinterpret_cast<const v8*>(src + q * 1024 + h * 512);
+        }
     };
     // the thin tile of reduction elements [k0, k0 + LK): chunk e -> row (p * NP + c), 8 elements
     // at 8 * ch (Bt is padded to a multiple of LKS)
-    auto load_b = [&](int64_t k0, v8 (&bt)[CPT]) {
+    auto load_b = [&](int64_t k0, v8 (&bt)[NTILE][CPT]) {
 #pragma unroll
-        for (int u = 0; u < CPT; u++) {
-            const int e = tid + u * NT;
-            const int row = e / (LK / 8), ch = e - row * (LK / 8);
-            const int p = row / NP, c = row - p * NP;
-            bt[u] = *reinterpret_cast<const v8*>(Bt + ((int64_t)p * P.Np + col0 + c) * P.bkp + k0 + 8 * ch);
-        }
+        for (int t = 0; t < NTILE; t++)
+#pragma unroll
+            for (int u = 0; u < CPT; u++) {
+                const int e = tid + u * NT;
+                const int row = e / (LK / 8), ch = e - row * (LK / 8);
+                const int p = row / NP, c = row - p * NP;
+                bt[t][u] = *reinterpret_cast<const v8*>(Btile[t] + ((int64_t)p * P.Np + col0 + c) * P.bkp + k0 + 8 * ch);
+            }
     };
-    auto store_b = [&](const v8 (&bt)[CPT]) {
+    auto store_b = [&](const v8 (&bt)[NTILE][CPT]) {
 #pragma unroll
-        for (int u = 0; u < CPT; u++) {
-            const int e = tid + u * NT;
-            const int row = e / (LK / 8), ch = e - row * (LK / 8);
-            *reinterpret_cast<v8*>(&sB[row * SK + 8 * ch]) = bt[u];
-        }
+        for (int t = 0; t < NTILE; t++)
+#pragma unroll
+            for (int u = 0; u < CPT; u++) {
+                const int e = tid + u * NT;
+                const int row = e / (LK / 8), ch = e - row * (LK / 8);
+                *reinterpret_cast<v8*>(&sB[(t * 4 * NP + row) * SK + 8 * ch]) = bt[t][u];
+            }
     };
 
     f32x4 acc[4][CNW];
@@ -960,32 +976,42 @@ __global__ __launch_bounds__(256 * NCG) void k_qgemm_lp(LpParams P) {
 #pragma unroll
         for (int j = 0; j < CNW; j++) acc[p][j] = f32x4{0, 0, 0, 0};
 
-    // MFMAs of one K step whose thin tile sits at offset kofs of the staged tile
-    auto step = [&](const v8 (&a)[4][2], int kofs) {
+    // MFMAs of one K step whose thin tile sits at offset kofs of the staged tile(s)
+    auto step = [&](const v8 (&a)[NTILE][4][2], int kofs) {
 #pragma unroll
         for (int h = 0; h < 2; h++)
 #pragma unroll
             for (int j = 0; j < CNW; j++) {
                 const int cn = cg * CNW + j;
                 if (cn >= CN) continue;                        // uniform per wave
-                v8 b[4], nb[4];
+                v8 b[NTILE][4], nb[NTILE][4];
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    b[r] = *reinterpret_cast<const v8*>(&sB[(r * NP + cn * 16 + ar) * SK + kofs + 32 * h + ak]);
-                    nb[r] = neg8(b[r]);
-                }
+                for (int t = 0; t < NTILE; t++)
 #pragma unroll
-                for (int q = 0; q < 4; q++)
-#pragma unroll
-                    for (int p = 0; p < 4; p++) {
-                        const int r = p ^ q;
-                        acc[p][j] = L::mma(a[q][h], term_sign<ADJ>(p, q) > 0 ? b[r] : nb[r], acc[p][j]);
+                    for (int r = 0; r < 4; r++) {
+                        b[t][r] = *reinterpret_cast<const v8*>(
+                            &sB[(t * 4 * NP + r * NP + cn * 16 + ar) * SK + kofs + 32 * h + ak]);
+                        nb[t][r] = neg8(b[t][r]);
                     }
+                // products (value, value), then (value, residual), (residual, value); consecutive
+                // MFMAs update different accumulators
+#pragma unroll
+                for (int x = 0; x < (SPL ? 3 : 1); x++) {
+                    const int ta = x == 2 ? 1 : 0, tb = x == 1 ? 1 : 0;
+#pragma unroll
+                    for (int q = 0; q < 4; q++)
+#pragma unroll
+                        for (int p = 0; p < 4; p++) {
+                            const int r = p ^ q;
+                            acc[p][j] = L::mma(a[ta][q][h], term_sign<ADJ>(p, q) > 0 ? b[tb][r] : nb[tb][r],
+                                               acc[p][j]);
+                        }
+                }
             }
     };
 
     if (kb >= ke) return;   // uniform: an empty split (no partial tile is read for it)
-    v8 aX[4][2], aY[4][2], bt[CPT];
+    v8 aX[NTILE][4][2], aY[NTILE][4][2], bt[NTILE][CPT];
     load_b(kb, bt);
     load_a(kb, aX);
     load_a(kb + LBK, aY);
@@ -1060,9 +1086,14 @@ struct LpPlan {
 // once per column tile)
 constexpr int kLpMaxCols = 160;
 
+// the split form stages the value and the residual tile together: up to 80 columns
+constexpr int kLpMaxColsSplit = 80;
+
 LpPlan make_lp_plan(const QgemmDesc& d) {
     LpPlan p{};
-    const int64_t gy0 = std::max<int64_t>(1, (d.N + kLpMaxCols - 1) / kLpMaxCols);
+    const bool split = d.math == MATH_BF16X3 || d.math == MATH_F16X3;
+    const int64_t cap = split ? kLpMaxColsSplit : kLpMaxCols;
+    const int64_t gy0 = std::max<int64_t>(1, (d.N + cap - 1) / cap);
     p.CN = (int)std::max<int64_t>(1, (d.N + 16 * gy0 - 1) / (16 * gy0));
     p.gy = (d.N + 16 * p.CN - 1) / (16 * p.CN);
     p.Np = p.gy * 16 * (int64_t)p.CN;
@@ -1118,12 +1149,11 @@ hipError_t launch_lp(const QgemmDesc& d, const LpPlan& pl, void* scratch, hipStr
                       d.skip_flag, st);
 }
 
-// The split form: three launches of the reduced-precision kernel, (A, B_hi), (A, B_lo) and
-// (A_lo, B_hi), each into its own slice of split-K partial tiles (the kernel stores partial
-// tiles whenever its split count is above one), then one ordered sum of all 3 x splits tiles.
-// Scratch: B_hi, B_lo, then the partial tiles.
+// The split form in one launch of the reduced-precision kernel with the residual copies (SPL):
+// A_hi B_hi + A_hi B_lo + A_lo B_hi accumulated together, then (when K is split) the ordered sum
+// of the partial tiles.  Scratch: B_hi, B_lo, then the partial tiles.
 size_t lp3_scratch_bytes(const LpPlan& p) {
-    return 2 * ((lp_thin_bytes(p) + 255) & ~size_t(255)) + (size_t)3 * p.splits * 4 * p.Mp * p.Np * sizeof(float);
+    return 2 * ((lp_thin_bytes(p) + 255) & ~size_t(255)) + lp_part_bytes(p);
 }
 
 template <class TL, bool ADJ>
@@ -1139,32 +1169,26 @@ hipError_t launch_lp3(const QgemmDesc& d, const LpPlan& pl, void* scratch, hipSt
                        pl.Kp);
     hipLaunchKernelGGL(k_lp_thin_res<TL>, dim3(tg), dim3(256), 0, st, (const float*)d.B, d.ldb, d.bps, d.K, d.N, Blo,
                        pl.Np, pl.Kp);
-    const size_t slice = (size_t)pl.splits * 4 * pl.Mp * pl.Np;
-    const void* As[3] = {d.A, d.A, d.A_lo};
-    const TL* Bs[3] = {Bhi, Blo, Bhi};
+    LpParams P{};
+    P.A = d.A; P.A2 = d.A_lo; P.akt = (d.K + LBK - 1) / LBK; P.art = (d.M + 15) / 16;
+    P.Bt = Bhi; P.Bt2 = Blo; P.bkp = pl.Kp;
+    P.C = (float*)d.C; P.ldc = d.ldc; P.cps = d.cps;
+    P.M = d.M; P.N = d.N; P.K = d.K;
+    P.kchunk = pl.kchunk; P.splits = (int)pl.splits;
+    P.part = part; P.Mp = pl.Mp; P.Np = pl.Np;
+    P.skip = d.skip_flag;
+    P.cscale = d.cscale;
     dim3 grid((unsigned)pl.gx, (unsigned)pl.gy, (unsigned)pl.splits);
-    for (int t = 0; t < 3; t++) {
-        LpParams P{};
-        P.A = As[t]; P.akt = (d.K + LBK - 1) / LBK; P.art = (d.M + 15) / 16;
-        P.Bt = Bs[t]; P.bkp = pl.Kp;
-        P.C = (float*)d.C; P.ldc = d.ldc; P.cps = d.cps;
-        P.M = d.M; P.N = d.N; P.K = d.K;
-        P.kchunk = pl.kchunk; P.splits = 3 * (int)pl.splits;   // above one: always partial tiles
-        P.part = part + t * slice; P.Mp = pl.Mp; P.Np = pl.Np;
-        P.skip = d.skip_flag;
-        P.cscale = d.cscale;
 #define QL_LP3(CN_) \
-        if (pl.CN == CN_) \
-            hipLaunchKernelGGL((k_qgemm_lp<TL, ADJ, CN_, lp_ncg(CN_), lp_cnw(CN_), lp_lk(CN_)>), grid, \
-                               dim3(256 * lp_ncg(CN_)), 0, st, P); \
-        else
-        QL_LP3(1) QL_LP3(2) QL_LP3(3) QL_LP3(4) QL_LP3(5) QL_LP3(6) QL_LP3(7) QL_LP3(8) QL_LP3(9) QL_LP3(10)
-        return hipErrorInvalidValue;
+    if (pl.CN == CN_) \
+        hipLaunchKernelGGL((k_qgemm_lp<TL, ADJ, CN_, 1, CN_, LBK, true>), grid, dim3(256), 0, st, P); \
+    else
+    QL_LP3(1) QL_LP3(2) QL_LP3(3) QL_LP3(4) QL_LP3(5)
+    return hipErrorInvalidValue;
 #undef QL_LP3
-    }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return reduce_f32(part, 3 * (int)pl.splits, pl.Mp, pl.Np, (float*)d.C, d.ldc, d.cps, d.M, d.N, (int)ST_SET,
+    if (e != hipSuccess || pl.splits == 1) return e;
+    return reduce_f32(part, (int)pl.splits, pl.Mp, pl.Np, (float*)d.C, d.ldc, d.cps, d.M, d.N, (int)ST_SET,
                       d.skip_flag, st);
 }
 
