@@ -675,9 +675,9 @@ def serving(Q, torch, nreq, seed=3):
 
     for name, prec in (("fp32", Q.QLRA_FP32), ("fp16", Q.QLRA_FP16)):
         out[name] = record(*run(prec, arrivals))
-    # the same arrivals through an arena that holds only a few of the larger requests at a time:
-    # admission is then bound by HBM, not by the slots
-    small = max(Q.qlra_workspace_size(r["m"], r["n"], r["k"], r["p"], r["v"], r["scheme"]) for r in reqs) * 2
+    # the same arrivals through an arena that holds the largest request and little else: admission
+    # is then bound by HBM, not by the slots, whenever a large request is in flight
+    small = int(max(Q.qlra_workspace_size(r["m"], r["n"], r["k"], r["p"], r["v"], r["scheme"]) for r in reqs) * 1.05)
     out["fp32_hbm_bound"] = {"arena_gb": round(small / 2 ** 30, 4), **record(*run(Q.QLRA_FP32, arrivals, arena=small))}
     return out
 

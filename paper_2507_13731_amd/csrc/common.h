@@ -184,7 +184,7 @@ size_t qsvd_gram_work_doubles(int64_t w);
 // with est also *est = sqrt(max(0, *nA2 - sum_{j<k} S_j^2) / *nA2) (as estimate_launch).
 // Columns with S_j <= kDegenerate S_0 (rounding level of an FP32 view: no direction left in
 // Y E_j / S_j) get zero columns in Wk.  *degen (if given) = 1 when there is any such column or
-// S_{k-1} < S_0 / 8 (the factor Y Wk is then re-orthonormalised), else 0.
+// S_{k-1} < S_0 / 64 (the factor Y Wk is then re-orthonormalised), else 0.
 constexpr double kDegenerate = 1.0 / 1048576.0;   // 2^-20
 hipError_t svals_launch(const double* lam, const double* E, int64_t lde, int64_t w, int k, double* S, double* Wk,
                         hipStream_t st, const double* nA2 = nullptr, double* est = nullptr, int* degen = nullptr);

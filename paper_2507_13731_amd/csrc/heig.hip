@@ -673,7 +673,7 @@ __global__ __launch_bounds__(256) void k_svals(const double* __restrict__ lam, c
     if (e < k) S[e] = sqrt(fmax(lam[e], 0.0));
     if (degen && e == 0) {
         // nonzero: re-orthonormalise the factor Y W (a steep spectrum, or degenerate columns)
-        int any = !(sqrt(fmax(lam[k - 1], 0.0)) >= 0.125 * s0);
+        int any = !(sqrt(fmax(lam[k - 1], 0.0)) >= 0.015625 * s0);
         for (int j = 0; j < k; j++) any |= !(sqrt(fmax(lam[j], 0.0)) > kDegenerate * s0);
         *degen = any;
     }

@@ -272,7 +272,8 @@ void cholqr(Ctx& c, const float* Y, int64_t rows, int64_t w, int64_t ldy, int64_
 // steeply, and at the rounding level (S_j <= kDegenerate S_0, when k exceeds the numerical rank
 // of A) the Y side carries no direction at all (the singular value kernel zeroed the column) and
 // the eigenvectors of the degenerate cluster are arbitrary.  The singular value kernel sets
-// status[5] when either can happen (S_{k-1} < S_0 / 8 or a degenerate column); then the
+// status[5] when either can happen (S_{k-1} < S_0 / 64, where the first error reaches about
+// 64 u32 = 4e-6, or a degenerate column); then the
 // degenerate columns get fixed pseudo-random vectors and the factor goes through CholeskyQR2,
 // all gated on that word.  The factor of a CholeskyQR is upper triangular, so a column is
 // orthogonalised against the columns of larger singular values only: a kept column moves by

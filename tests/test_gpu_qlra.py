@@ -111,6 +111,11 @@ def test_config1_parity(gq, oracle, v):
     d = ahat_diff(A, (Ug, Sg, Vg), (Uo, So, Vo))
     print(f"  ahat diff {d:.3e}", flush=True)
     assert d <= 1e-5
+    # S_49 / S_0 = 0.086 is above the re-orthonormalisation trigger (1/64): the factors come
+    # straight from the Gram form, orthonormal to about u32 S_0 / S_49
+    for X in (Ug, Vg):
+        g = qref.mul(qref.adj(X), X)
+        assert np.abs(g[0] - np.eye(50)).max() < 1e-5 and np.abs(g[1:]).max() < 1e-5
 
 
 def test_config1_low_noise_ahat(gq, oracle):
