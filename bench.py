@@ -78,9 +78,9 @@ def parse():
                     help="run only the matrix-completion workloads (for a kernel trace) and print their record")
     ap.add_argument("--counters", action="store_true",
                     help="launch sequence for hardware-counter runs only (view products and calibration copies)")
-    ap.add_argument("--trace-summary", metavar="CSV",
-                    help="kernel trace CSV of a rocprofv3 --kernel-trace run of the default bench: writes the "
-                         "per-kernel summary of the headline solves under profiles/")
+    ap.add_argument("--trace-summary", nargs="+", metavar="FILE",
+                    help="kernel trace CSV of a rocprofv3 --kernel-trace run of the default bench (then, optionally, "
+                         "that run's output): writes the per-kernel summary of the headline solves under profiles/")
     ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
                     help="FETCH_SIZE and WRITE_SIZE CSVs of two --counters runs (then optional MFMA counter "
                          "CSVs): writes the traffic record under profiles/")
@@ -253,7 +253,7 @@ def _kshort(name):
     return m.group(1) if m else name[:40]
 
 
-def trace_summary(path):
+def trace_summary(path, bench_out=None):
     """Summary of a rocprofv3 kernel trace (CSV) of the default bench run: the roofline kernel's
     launches at the headline shape, and per-kernel totals of one timed solve of each precision.
     The headline solves come first in the run (warmup + steps each for FP32, BF16, BF16 split);
@@ -272,20 +272,22 @@ def trace_summary(path):
     out = ["# Kernel trace: 16384 x 16384 block Krylov solve (k = 128, p = 32, v = 8), default bench run", "",
            "Commands (repository root on one MI355X; `<out>` a scratch folder):", "",
            "    cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
-           "-d <out>/trace -o bench -- python3 <repo>/bench.py",
-           "    python bench.py --trace-summary <out>/trace/bench_kernel_trace.csv", ""]
+           "-d <out>/trace -o bench -- python3 <repo>/bench.py > <out>/bench.log",
+           "    grep '^{' <out>/bench.log | tail -1 > <out>/bench.json",
+           "    python bench.py --trace-summary <out>/trace/bench_kernel_trace.csv <out>/bench.json", ""]
     # the roofline kernel: FP32 views at 160 columns (grid of 512 workgroups of 256 threads)
     out += ["## The roofline kernel (FP32 view product, 16384 x 16384 by 160)", "",
             "Every launch in the run at this shape (in the solves and in the bench's graph-timed view loop).", "",
             "| kernel | launches | mean us | median us | TFLOP/s (32 m n w / mean) | of 157.3 |", "|---|---|---|---|---|---|"]
     flops = 32.0 * LN * LN * LL
-    means = []
+    means, medians = [], []
     for label, pat in (("A X", "k_qview<5, false, true, false, false>"), ("A^H X", "k_qview<5, true, false, false, false>")):
         d = [(b - a) / 1e3 for a, b, n, gx, gy, gz in rows if _kshort(n) == pat and gx == 512 * 256 and gz == 1]
         if not d:
             continue
         mu = statistics.mean(d)
         means.append(mu)
+        medians.append(statistics.median(d))
         out.append(f"| `{pat}` ({label}) | {len(d)} | {mu:.1f} | {statistics.median(d):.1f} | "
                    f"{flops / mu / 1e6:.1f} | {flops / mu / 1e6 / 157.3:.3f} |")
     thin = [(b - a) / 1e3 for a, b, n, gx, gy, gz in rows if _kshort(n) == "k_thin_t" and gx == 1024 * 256 and gy == 3]
@@ -294,11 +296,27 @@ def trace_summary(path):
                    f"{statistics.median(thin):.1f} | | |")
     if means:
         mu = statistics.mean(means) + (statistics.mean(thin) if thin else 0.0)
+        md = statistics.mean(medians) + (statistics.median(thin) if thin else 0.0)
         out += ["", f"Mean of the two products plus the transpose: {mu:.1f} us per view, "
-                    f"{flops / mu / 1e6:.1f} TFLOP/s, {flops / mu / 1e6 / 157.3:.3f} of the FP32 MFMA peak "
-                    "(the bench's `roofline` times the same launch sequence with HIP events).", ""]
+                    f"{flops / mu / 1e6:.1f} TFLOP/s, {flops / mu / 1e6 / 157.3:.3f} of the FP32 MFMA peak; "
+                    f"with the medians (the launches inside solves run beside the estimates' side stream now and "
+                    f"then): {md:.1f} us, {flops / md / 1e6:.1f} TFLOP/s, {flops / md / 1e6 / 157.3:.3f}.  The "
+                    "bench's `roofline` times the same launch sequence in its own graph-replayed loop with HIP "
+                    "events.", ""]
+    if bench_out:
+        lines = [ln for ln in open(bench_out) if ln.startswith("{")]
+        if lines:
+            rec = json.loads(lines[-1])
+            rf = rec.get("roofline", {})
+            out += [f"The bench line of this (traced) run: value {rec.get('value')} {rec.get('unit')}, "
+                    f"{rec.get('ms_per_step')} ms per solve; roofline achieved {rf.get('achieved')} TFLOP/s, "
+                    f"frac {rf.get('frac')}.", ""]
     names = ("FP32", "BF16", "BF16 split")
-    nsolve = len(starts) - 1
+    # the headline solves open the run and take tens of milliseconds each; the solves of the
+    # other records (2048 x 2048, serving, completion) take about one
+    nsolve = 0
+    while nsolve + 1 < len(starts) and lib[starts[nsolve + 1] - 1][1] - lib[starts[nsolve]][0] > 10_000_000:
+        nsolve += 1
     per = nsolve // 3 if nsolve >= 3 else 0
     if per:
         out += [f"## One timed solve of each precision (the last of {per} per precision)", ""]
@@ -732,7 +750,7 @@ def main():
         pmc_summary(args.pmc_summary)
         return
     if args.trace_summary:
-        trace_summary(args.trace_summary)
+        trace_summary(*args.trace_summary[:2])
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; --gpus must be 1",
