@@ -19,8 +19,8 @@
 //    loads of step t+1 are in flight during the MFMAs of step t.  The MFMA A operand always
 //    comes from the A tile, stored row-major for A B and k-major for A^H B, so one kernel serves
 //    both orientations.  Signs go on a negated register copy of the thin operand.
-//  - k_qgemm_lp (MATH_BF16 / MATH_F16): the reduced-precision views, and three launches of it
-//    for the split forms (MATH_BF16X3 / MATH_F16X3).
+//  - k_qgemm_lp (MATH_BF16 / MATH_F16): the reduced-precision views, and (with the residual
+//    copies staged beside the values) the split forms (MATH_BF16X3 / MATH_F16X3).
 // When the output tiles cannot fill the chip, K is split across workgroups; partial tiles go to
 // scratch and an element-parallel kernel adds them in split order (deterministic, no
 // floating-point atomics).
@@ -813,14 +813,22 @@ hipError_t launch_view(const QgemmDesc& d, void* scratch, hipStream_t st) {
 // ------------------------------------------------------------------------------------------
 // Low-precision views: BF16 / FP16 operands, v_mfma_f32_16x16x32_{bf16,f16}, FP32 accumulation.
 //
-// A is a low-precision copy laid out as the rows of the output (A itself for A B, the
-// transposed copy A^T for A^H B) in the tiled MFMA-operand order of lowp_copy_launch, so the
-// MFMA A operand (row l % 16, eight consecutive k at 8 (l / 16)) is one 16-byte load per lane
-// straight from global memory, 1 KB contiguous per instruction: every A element is used by
-// exactly one wave, so it bypasses LDS.  The thin operand is converted once per launch into
-// Bt[plane][column][k] (low precision, columns padded to 16, k padded to LBK) and each K step's
-// tile is staged through LDS for the four waves.  Each wave owns 16 rows of the output and all
-// its column tiles in the four planes.
+// Both operands are in MFMA operand order before the product starts.  A fragment is 16 rows (or
+// columns) by 32 reduction elements of one plane, 1 KB, lane l holding row (column) l % 16 and
+// reduction elements 8 (l / 16) .. + 7:
+//  - A: the low-precision copy laid out as the rows of the output (A itself for A B, the
+//    transposed copy A^T for A^H B) in the tiled order of lowp_copy_launch.  Every A element is
+//    used by exactly one wave, so its fragments go from HBM straight into registers.
+//  - the thin operand: converted once per launch (k_lp_thin) into fragments ordered by K step,
+//    plane, column tile and half step, so that the fragments of one K step, one plane and a
+//    workgroup's column tiles are one contiguous run.
+// A workgroup is four waves; each owns 16 rows of the output and all of the workgroup's CN column
+// tiles in the four planes.  The thin fragments of a K step go from global memory into LDS by
+// direct loads (global_load_lds_dwordx4: 1 KB per instruction, no registers), into one of two
+// stage buffers: the copy of step s + 1 is in flight during the MFMAs of step s, and one barrier
+// per step both publishes it and frees step s's buffer.  The A fragments of step s + 2 are loaded
+// (into the ping-pong register sets aX, aY) once step s's MFMAs are issued.  The signs of eq. (1)
+// go on a negated copy of the A fragments, made once per step.
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
@@ -851,12 +859,13 @@ __device__ __forceinline__ V neg8(V v) {
     return __builtin_bit_cast(V, u);
 }
 
-constexpr int LBK = 64;    // K per step: two MFMA k-blocks of 32
-constexpr int LBM = 64;    // output rows per workgroup (16 per wave)
+constexpr int LBK = 64;        // K per step: two MFMA k-blocks of 32
+constexpr int LBM = 64;        // output rows per workgroup (16 per wave)
+constexpr int LKS = 2 * LBK;   // K per loop iteration (two steps); K chunks and padding are multiples
 
 struct LpParams {
     const void* A; int64_t akt, art;      // tiled copy: reduction tiles per row tile, row tiles
-    const void* Bt; int64_t bkp;          // converted thin operand: [4][Np][bkp]
+    const void* Bt; int64_t bnt;          // thin operand in fragment order: column tiles of 16
     const void* A2;                       // split form: the residual copy of A (same tiling)
     const void* Bt2;                      // split form: the residual of the thin operand
     float* C; int64_t ldc, cps;
@@ -869,74 +878,81 @@ struct LpParams {
     const float* cscale;
 };
 
-// Bt[p][c][k] = (TL) B[p][k][c] (zero padded to Np x Kp)
-template <class TL>
+// The thin operand in fragment order.  Fragment (s, p, n, h) (K step s, plane p, column tile n
+// of NT, half step h) starts at element 512 (((s * 4 + p) * NT + n) * 2 + h); lane l's eight
+// elements are B_p(64 s + 32 h + 8 (l / 16) + i, 16 n + l % 16), i = 0..7, zero outside K x N.
+// RES: the rounded residual B - (float)(TL)B instead (the split form).  One thread per lane of
+// a fragment; S K steps.
+template <class TL, bool RES>
 __global__ __launch_bounds__(256) void k_lp_thin(const float* __restrict__ B, int64_t ldb, int64_t bps, int64_t K,
-                                                 int64_t N, TL* __restrict__ Bt, int64_t Np, int64_t Kp) {
+                                                 int64_t N, TL* __restrict__ Bt, int64_t NT, int64_t S) {
+    using v8 = typename LpMma<TL>::v8;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= 4 * Np * Kp) return;
-    const int64_t p = e / (Np * Kp), rem = e - p * Np * Kp, c = rem / Kp, k = rem - c * Kp;
-    const float x = (k < K && c < N) ? B[p * bps + k * ldb + c] : 0.0f;
-    Bt[e] = (TL)x;
+    if (e >= S * 4 * NT * 128) return;
+    const int l = (int)(e & 63);
+    const int64_t f = e >> 6;
+    const int h = (int)(f & 1);
+    const int64_t n = (f >> 1) % NT, sp = (f >> 1) / NT;
+    const int p = (int)(sp & 3);
+    const int64_t s = sp >> 2;
+    const int64_t c = 16 * n + (l & 15), k0 = 64 * s + 32 * h + 8 * (l >> 4);
+    v8 out;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const int64_t k = k0 + i;
+        const float x = (k < K && c < N) ? B[p * bps + k * ldb + c] : 0.0f;
+        out[i] = RES ? (TL)(x - (float)(TL)x) : (TL)x;
+    }
+    *reinterpret_cast<v8*>(Bt + 8 * e) = out;
 }
 
-// Bt[p][c][k] = (TL)(B[p][k][c] - (float)(TL)B[p][k][c]): the rounded residual of the thin operand
-template <class TL>
-__global__ __launch_bounds__(256) void k_lp_thin_res(const float* __restrict__ B, int64_t ldb, int64_t bps, int64_t K,
-                                                     int64_t N, TL* __restrict__ Bt, int64_t Np, int64_t Kp) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= 4 * Np * Kp) return;
-    const int64_t p = e / (Np * Kp), rem = e - p * Np * Kp, c = rem / Kp, k = rem - c * Kp;
-    const float x = (k < K && c < N) ? B[p * bps + k * ldb + c] : 0.0f;
-    Bt[e] = (TL)(x - (float)(TL)x);
+// 16 bytes per lane from global memory straight into LDS: lane l's bytes land at dst + 16 l
+// (dst uniform over the wave); counted by vmcnt like any vector load
+typedef __attribute__((address_space(1))) const void* global_cptr;
+typedef __attribute__((address_space(3))) void* lds_ptr;
+__device__ __forceinline__ void lds_copy16(const void* src, void* dst) {
+    __builtin_amdgcn_global_load_lds((global_cptr)src, (lds_ptr)dst, 16, 0, 0);
 }
 
-// Workgroup: 4 row groups of 16 rows x NCG column groups of CNW column tiles (16 columns each).
-// Software pipeline: an iteration covers two K steps (LKS = 128 reduction elements).  The thin
-// tile of LK reduction elements (LK = LKS: both steps; LK = LBK: one step, staged twice per
-// iteration, for wide column tiles whose two-step tile would not fit in LDS) was loaded into
-// registers before and sits in LDS; the A fragments of a step are loaded two steps ahead into
-// the ping-pong register sets aX (even steps) and aY (odd steps), always issued after the
-// thin-tile loads, so that waiting for those (vmcnt counts in issue order) never waits for A.
-// Every load is unconditional (addresses clamped into the copies; a step past the end of K
-// meets zero rows of the padded thin tile), so the wait counts stay exact across iterations.
-// SPL (the split form fused): the residual copies of A and of the thin operand come along, the
-// residual tile staged next to the value tile, and every step issues the three products
-// A_hi B_hi + A_hi B_lo + A_lo B_hi into the same accumulators (three times the MFMA work per
-// staged tile and per barrier; one read of each copy).
-constexpr int LKS = 2 * LBK;
-template <class TL, bool ADJ, int CN, int NCG, int CNW, int LK, bool SPL = false>
-__global__ __launch_bounds__(256 * NCG) void k_qgemm_lp(LpParams P) {
+// s_waitcnt bounding only the vector-memory count (vmcnt in bits 3:0 and 15:14; expcnt and
+// lgkmcnt at their maxima)
+constexpr int vmcnt_imm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | ((n >> 4) << 14); }
+
+// SPL (the split form fused): the residual copies of A and of the thin operand come along; the
+// residual fragments are staged next to the value fragments, and every step issues the three
+// products A_hi B_hi + A_hi B_lo + A_lo B_hi into the same accumulators.
+template <class TL, bool ADJ, int CN, bool SPL>
+__global__ __launch_bounds__(256, SPL ? 1 : 2) void k_qgemm_lp(LpParams P) {
     using L = LpMma<TL>;
     using v8 = typename L::v8;
-    static_assert(LK == LKS || LK == LBK, "thin tile of one or two K steps");
-    constexpr int NP = 16 * CN;
-    constexpr int SK = LK + 8;                    // LDS row stride of the staged tile (elements)
-    constexpr int NT = 256 * NCG;
-    constexpr int CH = 4 * NP * (LK / 8);         // 16-byte chunks of one thin tile
-    constexpr int CPT = CH / NT;                  // chunks per thread
-    constexpr int NTILE = SPL ? 2 : 1;            // staged tiles: the value, and the residual
-    static_assert(CH % NT == 0, "whole chunks per thread");
-    __shared__ __attribute__((aligned(16))) TL sB[NTILE * 4 * NP * SK];
+    constexpr int NTILE = SPL ? 2 : 1;           // the value, and the residual
+    constexpr int SLAB = 2 * CN;                 // fragments of one plane of one copy per K step
+    constexpr int STAGE = NTILE * 4 * SLAB;      // fragments per K step
+    constexpr int NA = NTILE * 8;                // A fragment loads per K step and wave
+    static_assert(2 * STAGE * 1024 <= 163840, "two stages within LDS");
+    __shared__ __attribute__((aligned(16))) v8 sB0[STAGE * 64];
+    __shared__ __attribute__((aligned(16))) v8 sB1[STAGE * 64];
     if (P.skip && *P.skip == 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int rg = wave & 3, cg = wave >> 2;
     const int split = blockIdx.z;
     const int64_t kb = (int64_t)split * P.kchunk;
     const int64_t ke = kb + P.kchunk < P.K ? kb + P.kchunk : P.K;
-    const int ar = lane & 15, ak = 8 * (lane >> 4);
-    const int64_t rt = (int64_t)blockIdx.x * (LBM / 16) + rg;   // this wave's row tile
+    if (kb >= ke) return;   // uniform: an empty split (no partial tile is read for it)
+    // steps [s0, s1): an even number, within the padded thin operand (kb is a multiple of LKS)
+    const int64_t s0 = kb / LBK, s1 = s0 + 2 * ((ke - kb + LKS - 1) / LKS);
+    const int64_t rt = (int64_t)blockIdx.x * (LBM / 16) + wave;   // this wave's row tile
     const int64_t rbase = 16 * rt;
-    const int64_t col0 = (int64_t)blockIdx.y * NP;                 // this workgroup's column tile
+    const int64_t n0 = (int64_t)blockIdx.y * CN;                   // the workgroup's first column tile
     // a row tile past the copy reads the last one: its rows are never stored
     const int64_t aoff = (rt < P.art ? rt : P.art - 1) * P.akt * 4096 + 8 * lane;
     const TL* __restrict__ Abase[2] = {(const TL*)P.A + aoff, SPL ? (const TL*)P.A2 + aoff : nullptr};
     const TL* __restrict__ Btile[2] = {(const TL*)P.Bt, SPL ? (const TL*)P.Bt2 : nullptr};
     const int64_t kt_last = P.akt - 1;
 
-    // the A fragments of one K step: a[t][q][h] for copy t (value, residual)
-    auto load_a = [&](int64_t k0, v8 (&a)[NTILE][4][2]) {
-        const int64_t kt = (k0 >> 6) < kt_last ? (k0 >> 6) : kt_last;
+    // the A fragments of step s: a[t][q][h] for copy t (a step past the copy reads its last
+    // reduction tile, which meets zero rows of the padded thin operand)
+    auto load_a = [&](int64_t s, v8 (&a)[NTILE][4][2]) {
+        const int64_t kt = s < kt_last ? s : kt_last;
 #pragma unroll
         for (int t = 0; t < NTILE; t++) {
             const TL* src = Abase[t] + kt * 4096;
@@ -946,118 +962,102 @@ __global__ __launch_bounds__(256 * NCG) void k_qgemm_lp(LpParams P) {
                 for (int h = 0; h < 2; h++) a[t][q][h] = *reinterpret_cast<const v8*>(src + q * 1024 + h * 512);
         }
     };
-    // the thin tile of reduction elements [k0, k0 + LK): chunk e -> row (p * NP + c), 8 elements
-    // at 8 * ch (Bt is padded to a multiple of LKS)
-    auto load_b = [&](int64_t k0, v8 (&bt)[NTILE][CPT]) {
+    // this wave's share of step s's thin fragments into a stage: slab wave * NTILE + u (copy t,
+    // plane p), fragment 2 j + h of a slab for column tile n0 + j, half h
+    auto copy_b = [&](int64_t s, v8* stage) {
 #pragma unroll
-        for (int t = 0; t < NTILE; t++)
+        for (int u = 0; u < NTILE; u++) {
+            const int sig = wave * NTILE + u, t = sig >> 2, p = sig & 3;
+            const TL* src = Btile[t] + (((s * 4 + p) * P.bnt + n0) * 128 + lane) * 8;
+            v8* dst = stage + sig * SLAB * 64;
 #pragma unroll
-            for (int u = 0; u < CPT; u++) {
-                const int e = tid + u * NT;
-                const int row = e / (LK / 8), ch = e - row * (LK / 8);
-                const int p = row / NP, c = row - p * NP;
-                bt[t][u] = *reinterpret_cast<const v8*>(Btile[t] + ((int64_t)p * P.Np + col0 + c) * P.bkp + k0 + 8 * ch);
-            }
-    };
-    auto store_b = [&](const v8 (&bt)[NTILE][CPT]) {
-#pragma unroll
-        for (int t = 0; t < NTILE; t++)
-#pragma unroll
-            for (int u = 0; u < CPT; u++) {
-                const int e = tid + u * NT;
-                const int row = e / (LK / 8), ch = e - row * (LK / 8);
-                *reinterpret_cast<v8*>(&sB[(t * 4 * NP + row) * SK + 8 * ch]) = bt[t][u];
-            }
+            for (int i = 0; i < SLAB; i++) lds_copy16(src + i * 512, dst + i * 64);
+        }
     };
 
-    f32x4 acc[4][CNW];
+    f32x4 acc[4][CN];
 #pragma unroll
     for (int p = 0; p < 4; p++)
 #pragma unroll
-        for (int j = 0; j < CNW; j++) acc[p][j] = f32x4{0, 0, 0, 0};
+        for (int j = 0; j < CN; j++) acc[p][j] = f32x4{0, 0, 0, 0};
 
-    // MFMAs of one K step whose thin tile sits at offset kofs of the staged tile(s)
-    auto step = [&](const v8 (&a)[NTILE][4][2], int kofs) {
+    // the MFMAs of one step: for each half step and column tile, the four thin fragments of
+    // each copy from LDS, then (value, value), (value, residual), (residual, value) products;
+    // consecutive MFMAs update different accumulators
+    auto step = [&](const v8 (&a)[NTILE][4][2], const v8* stage) {
+        v8 na[NTILE][4][2];
+#pragma unroll
+        for (int t = 0; t < NTILE; t++)
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+#pragma unroll
+                for (int h = 0; h < 2; h++) na[t][q][h] = neg8(a[t][q][h]);
+        const v8* sb = stage + lane;
 #pragma unroll
         for (int h = 0; h < 2; h++)
 #pragma unroll
-            for (int j = 0; j < CNW; j++) {
-                const int cn = cg * CNW + j;
-                if (cn >= CN) continue;                        // uniform per wave
-                v8 b[NTILE][4], nb[NTILE][4];
+            for (int j = 0; j < CN; j++) {
+                v8 b[NTILE][4];
 #pragma unroll
                 for (int t = 0; t < NTILE; t++)
 #pragma unroll
-                    for (int r = 0; r < 4; r++) {
-                        b[t][r] = *reinterpret_cast<const v8*>(
-                            &sB[(t * 4 * NP + r * NP + cn * 16 + ar) * SK + kofs + 32 * h + ak]);
-                        nb[t][r] = neg8(b[t][r]);
-                    }
-                // products (value, value), then (value, residual), (residual, value); consecutive
-                // MFMAs update different accumulators
+                    for (int r = 0; r < 4; r++) b[t][r] = sb[((t * 4 + r) * SLAB + 2 * j + h) * 64];
 #pragma unroll
                 for (int x = 0; x < (SPL ? 3 : 1); x++) {
                     const int ta = x == 2 ? 1 : 0, tb = x == 1 ? 1 : 0;
 #pragma unroll
                     for (int q = 0; q < 4; q++)
 #pragma unroll
-                        for (int p = 0; p < 4; p++) {
-                            const int r = p ^ q;
-                            acc[p][j] = L::mma(a[ta][q][h], term_sign<ADJ>(p, q) > 0 ? b[tb][r] : nb[tb][r],
+                        for (int p = 0; p < 4; p++)
+                            acc[p][j] = L::mma(term_sign<ADJ>(p, q) > 0 ? a[ta][q][h] : na[ta][q][h], b[tb][p ^ q],
                                                acc[p][j]);
-                        }
                 }
             }
     };
 
-    if (kb >= ke) return;   // uniform: an empty split (no partial tile is read for it)
-    v8 aX[NTILE][4][2], aY[NTILE][4][2], bt[NTILE][CPT];
-    load_b(kb, bt);
-    load_a(kb, aX);
-    load_a(kb + LBK, aY);
-    store_b(bt);
-    __syncthreads();
-    for (int64_t k0 = kb; k0 < ke; k0 += LKS) {
-        const bool more = k0 + LKS < ke;
-        if constexpr (LK == LKS) {
-            load_b(more ? k0 + LKS : k0, bt);
-            step(aX, 0);
-            load_a(k0 + LKS, aX);
-            step(aY, LBK);
-            load_a(k0 + LKS + LBK, aY);
-            if (more) {
-                __syncthreads();   // every wave is done with the staged tile
-                store_b(bt);
-                __syncthreads();
-            }
-        } else {
-            // one K step per staged tile: the second step of the iteration (within the padded
-            // thin operand: kchunk is a multiple of LKS) is staged after the first
-            load_b(k0 + LBK, bt);
-            step(aX, 0);
-            load_a(k0 + LKS, aX);
-            __syncthreads();
-            store_b(bt);
-            __syncthreads();
-            load_b(more ? k0 + LKS : k0, bt);
-            step(aY, 0);
-            load_a(k0 + LKS + LBK, aY);
-            if (more) {
-                __syncthreads();
-                store_b(bt);
-                __syncthreads();
-            }
-        }
+    // prologue: A(s0), the thin copy of s0, A(s0 + 1); the wait leaves A(s0 + 1) in flight, the
+    // same loads as at the end of every iteration (so the loop head sees one state)
+    v8 aX[NTILE][4][2], aY[NTILE][4][2];
+    load_a(s0, aX);
+    __builtin_amdgcn_sched_barrier(0);
+    copy_b(s0, sB0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_a(s0 + 1, aY);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(NA));   // this wave's copy of step s0 has landed,
+    __builtin_amdgcn_s_barrier();                // and every other wave's
+    __builtin_amdgcn_sched_barrier(0);
+    // Issue order per step: the next step's thin copy, this step's MFMAs, the A loads of the
+    // step after next; then a wait that leaves only those A loads in flight, and the barrier.
+    // The order is pinned (sched_barrier): the wait counts rely on it.
+    for (int64_t s = s0; s < s1; s += 2) {
+        copy_b(s + 1, sB1);
+        __builtin_amdgcn_sched_barrier(0);
+        step(aX, sB0);
+        __builtin_amdgcn_sched_barrier(0);
+        load_a(s + 2, aX);
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(NA));
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
+        if (s + 2 < s1) copy_b(s + 2, sB0);
+        __builtin_amdgcn_sched_barrier(0);
+        step(aY, sB1);
+        __builtin_amdgcn_sched_barrier(0);
+        load_a(s + 3, aY);
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm(NA));
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_sched_barrier(0);
     }
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
     const float sc = P.cscale ? *P.cscale : 1.0f;
 #pragma unroll
-    for (int j = 0; j < CNW; j++) {
-        const int cn = cg * CNW + j;
-        if (cn >= CN) continue;
+    for (int j = 0; j < CN; j++) {
 #pragma unroll
         for (int i = 0; i < 4; i++) {
             const int64_t r = rbase + 4 * (lane >> 4) + i;
-            const int64_t c = col0 + cn * 16 + ar;
+            const int64_t c = (n0 + j) * 16 + (lane & 15);
             if (P.splits == 1) {
                 if (r < P.M && c < P.N)
 #pragma unroll
@@ -1071,22 +1071,16 @@ __global__ __launch_bounds__(256 * NCG) void k_qgemm_lp(LpParams P) {
     }
 }
 
-// column groups per workgroup, column tiles per wave and the staged reduction depth for CN
-// column tiles (beyond 6 tiles, one K step per staged tile keeps it within LDS)
-constexpr int lp_ncg(int cn) { return cn <= 2 || cn > 6 ? 1 : 2; }
-constexpr int lp_cnw(int cn) { return (cn + lp_ncg(cn) - 1) / lp_ncg(cn); }
-constexpr int lp_lk(int cn) { return cn <= 6 ? LKS : LBK; }
-
 struct LpPlan {
     int CN;                 // column tiles of 16 per workgroup
     int64_t gx, gy, splits, kchunk, Mp, Np, Kp;
 };
 
-// up to 160 columns per workgroup (wider thin blocks: column tiles as even as possible, A read
-// once per column tile)
-constexpr int kLpMaxCols = 160;
+// up to 80 columns per workgroup (wider thin blocks: column tiles as even as possible): two
+// stages of 80 columns take 80 KB of LDS, so two workgroups share a CU (two waves per SIMD)
+constexpr int kLpMaxCols = 80;
 
-// the split form stages the value and the residual tile together: up to 80 columns
+// the split form stages the value and the residual fragments together: up to 80 columns
 constexpr int kLpMaxColsSplit = 80;
 
 LpPlan make_lp_plan(const QgemmDesc& d) {
@@ -1117,61 +1111,45 @@ LpPlan make_lp_plan(const QgemmDesc& d) {
 size_t lp_thin_bytes(const LpPlan& p) { return (size_t)4 * p.Np * p.Kp * 2; }
 size_t lp_part_bytes(const LpPlan& p) { return p.splits > 1 ? (size_t)p.splits * 4 * p.Mp * p.Np * sizeof(float) : 0; }
 
-template <class TL, bool ADJ>
+// The thin operand(s) in fragment order, the product, then (when K is split) the ordered sum of
+// the partial tiles.  Scratch: the converted thin operand (and its residual for the split form),
+// then the partial tiles.  The split form is one launch with the residual copies (SPL).
+size_t lp_scratch_bytes(const LpPlan& p, bool split) {
+    return (split ? 2 : 1) * ((lp_thin_bytes(p) + 255) & ~size_t(255)) + lp_part_bytes(p);
+}
+
+// the product kernel for CN column tiles (false: no such variant)
+template <class TL, bool ADJ, int CN, bool SPL>
+bool lp_product_cn(int cn, dim3 grid, const LpParams& P, hipStream_t st) {
+    if (cn != CN) return false;
+    hipLaunchKernelGGL((k_qgemm_lp<TL, ADJ, CN, SPL>), grid, dim3(256), 0, st, P);
+    return true;
+}
+template <class TL, bool ADJ, bool SPL>
+bool lp_product(int cn, dim3 g, const LpParams& P, hipStream_t st) {
+    static_assert(kLpMaxCols == 80 && kLpMaxColsSplit == 80, "variants up to 5 column tiles");
+    return lp_product_cn<TL, ADJ, 1, SPL>(cn, g, P, st) || lp_product_cn<TL, ADJ, 2, SPL>(cn, g, P, st) ||
+           lp_product_cn<TL, ADJ, 3, SPL>(cn, g, P, st) || lp_product_cn<TL, ADJ, 4, SPL>(cn, g, P, st) ||
+           lp_product_cn<TL, ADJ, 5, SPL>(cn, g, P, st);
+}
+
+template <class TL, bool ADJ, bool SPL>
 hipError_t launch_lp(const QgemmDesc& d, const LpPlan& pl, void* scratch, hipStream_t st) {
-    char* base = (char*)scratch;
-    TL* Bt = (TL*)base;
-    float* part = (float*)(base + ((lp_thin_bytes(pl) + 255) & ~size_t(255)));
-    const int64_t nt = 4 * pl.Np * pl.Kp;
-    hipLaunchKernelGGL(k_lp_thin<TL>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, (const float*)d.B, d.ldb,
-                       d.bps, d.K, d.N, Bt, pl.Np, pl.Kp);
-    LpParams P{};
-    P.A = d.A; P.akt = (d.K + LBK - 1) / LBK; P.art = (d.M + 15) / 16;
-    P.Bt = Bt; P.bkp = pl.Kp;
-    P.C = (float*)d.C; P.ldc = d.ldc; P.cps = d.cps;
-    P.M = d.M; P.N = d.N; P.K = d.K;
-    P.kchunk = pl.kchunk; P.splits = (int)pl.splits;
-    P.part = part; P.Mp = pl.Mp; P.Np = pl.Np;
-    P.skip = d.skip_flag;
-    P.cscale = d.cscale;
-    dim3 grid((unsigned)pl.gx, (unsigned)pl.gy, (unsigned)pl.splits);
-#define QL_LP(CN_) \
-    if (pl.CN == CN_) \
-        hipLaunchKernelGGL((k_qgemm_lp<TL, ADJ, CN_, lp_ncg(CN_), lp_cnw(CN_), lp_lk(CN_)>), grid, \
-                           dim3(256 * lp_ncg(CN_)), 0, st, P); \
-    else
-    QL_LP(1) QL_LP(2) QL_LP(3) QL_LP(4) QL_LP(5) QL_LP(6) QL_LP(7) QL_LP(8) QL_LP(9) QL_LP(10)
-    return hipErrorInvalidValue;
-#undef QL_LP
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || pl.splits == 1) return e;
-    return reduce_f32(part, (int)pl.splits, pl.Mp, pl.Np, (float*)d.C, d.ldc, d.cps, d.M, d.N, (int)ST_SET,
-                      d.skip_flag, st);
-}
-
-// The split form in one launch of the reduced-precision kernel with the residual copies (SPL):
-// A_hi B_hi + A_hi B_lo + A_lo B_hi accumulated together, then (when K is split) the ordered sum
-// of the partial tiles.  Scratch: B_hi, B_lo, then the partial tiles.
-size_t lp3_scratch_bytes(const LpPlan& p) {
-    return 2 * ((lp_thin_bytes(p) + 255) & ~size_t(255)) + lp_part_bytes(p);
-}
-
-template <class TL, bool ADJ>
-hipError_t launch_lp3(const QgemmDesc& d, const LpPlan& pl, void* scratch, hipStream_t st) {
     char* base = (char*)scratch;
     const size_t tb = (lp_thin_bytes(pl) + 255) & ~size_t(255);
     TL* Bhi = (TL*)base;
-    TL* Blo = (TL*)(base + tb);
-    float* part = (float*)(base + 2 * tb);
-    const int64_t nt = 4 * pl.Np * pl.Kp;
-    const unsigned tg = (unsigned)((nt + 255) / 256);
-    hipLaunchKernelGGL(k_lp_thin<TL>, dim3(tg), dim3(256), 0, st, (const float*)d.B, d.ldb, d.bps, d.K, d.N, Bhi, pl.Np,
-                       pl.Kp);
-    hipLaunchKernelGGL(k_lp_thin_res<TL>, dim3(tg), dim3(256), 0, st, (const float*)d.B, d.ldb, d.bps, d.K, d.N, Blo,
-                       pl.Np, pl.Kp);
+    TL* Blo = SPL ? (TL*)(base + tb) : nullptr;
+    float* part = (float*)(base + (SPL ? 2 : 1) * tb);
+    const int64_t NT = pl.Np / 16, S = pl.Kp / LBK;
+    const unsigned tg = (unsigned)((S * 4 * NT * 128 + 255) / 256);
+    hipLaunchKernelGGL((k_lp_thin<TL, false>), dim3(tg), dim3(256), 0, st, (const float*)d.B, d.ldb, d.bps, d.K, d.N,
+                       Bhi, NT, S);
+    if (SPL)
+        hipLaunchKernelGGL((k_lp_thin<TL, true>), dim3(tg), dim3(256), 0, st, (const float*)d.B, d.ldb, d.bps, d.K,
+                           d.N, Blo, NT, S);
     LpParams P{};
-    P.A = d.A; P.A2 = d.A_lo; P.akt = (d.K + LBK - 1) / LBK; P.art = (d.M + 15) / 16;
-    P.Bt = Bhi; P.Bt2 = Blo; P.bkp = pl.Kp;
+    P.A = d.A; P.A2 = SPL ? d.A_lo : nullptr; P.akt = (d.K + LBK - 1) / LBK; P.art = (d.M + 15) / 16;
+    P.Bt = Bhi; P.Bt2 = Blo; P.bnt = NT;
     P.C = (float*)d.C; P.ldc = d.ldc; P.cps = d.cps;
     P.M = d.M; P.N = d.N; P.K = d.K;
     P.kchunk = pl.kchunk; P.splits = (int)pl.splits;
@@ -1179,13 +1157,7 @@ hipError_t launch_lp3(const QgemmDesc& d, const LpPlan& pl, void* scratch, hipSt
     P.skip = d.skip_flag;
     P.cscale = d.cscale;
     dim3 grid((unsigned)pl.gx, (unsigned)pl.gy, (unsigned)pl.splits);
-#define QL_LP3(CN_) \
-    if (pl.CN == CN_) \
-        hipLaunchKernelGGL((k_qgemm_lp<TL, ADJ, CN_, 1, CN_, LBK, true>), grid, dim3(256), 0, st, P); \
-    else
-    QL_LP3(1) QL_LP3(2) QL_LP3(3) QL_LP3(4) QL_LP3(5)
-    return hipErrorInvalidValue;
-#undef QL_LP3
+    if (!lp_product<TL, ADJ, SPL>(pl.CN, grid, P, st)) return hipErrorInvalidValue;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || pl.splits == 1) return e;
     return reduce_f32(part, (int)pl.splits, pl.Mp, pl.Np, (float*)d.C, d.ldc, d.cps, d.M, d.N, (int)ST_SET,
@@ -1199,11 +1171,8 @@ bool vec_ok(const void* p, int64_t ld, int64_t ps, size_t el) {
 }  // namespace
 
 size_t qgemm_partial_bytes(const QgemmDesc& d) {
-    if (d.math == MATH_BF16X3 || d.math == MATH_F16X3) return lp3_scratch_bytes(make_lp_plan(d));
-    if (d.math == MATH_BF16 || d.math == MATH_F16) {
-        const LpPlan lp = make_lp_plan(d);
-        return ((lp_thin_bytes(lp) + 255) & ~size_t(255)) + lp_part_bytes(lp);
-    }
+    if (d.math == MATH_BF16X3 || d.math == MATH_F16X3) return lp_scratch_bytes(make_lp_plan(d), true);
+    if (d.math == MATH_BF16 || d.math == MATH_F16) return lp_scratch_bytes(make_lp_plan(d), false);
     if (d.math == MATH_F32) {
         const VPlan vp = make_vplan(d);
         return vplan_thin_bytes(vp) + vplan_part_bytes(vp);
@@ -1224,15 +1193,19 @@ hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t s
         if (d.b_f64 || d.c_f64 || d.store != ST_SET || !s.partial || !d.A_lo) return hipErrorInvalidValue;
         const LpPlan lp = make_lp_plan(d);
         if (d.math == MATH_BF16X3)
-            return d.op == OP_HN ? launch_lp3<__bf16, true>(d, lp, s.partial, st) : launch_lp3<__bf16, false>(d, lp, s.partial, st);
-        return d.op == OP_HN ? launch_lp3<_Float16, true>(d, lp, s.partial, st) : launch_lp3<_Float16, false>(d, lp, s.partial, st);
+            return d.op == OP_HN ? launch_lp<__bf16, true, true>(d, lp, s.partial, st)
+                                 : launch_lp<__bf16, false, true>(d, lp, s.partial, st);
+        return d.op == OP_HN ? launch_lp<_Float16, true, true>(d, lp, s.partial, st)
+                             : launch_lp<_Float16, false, true>(d, lp, s.partial, st);
     }
     if (d.math == MATH_BF16 || d.math == MATH_F16) {
         if (d.b_f64 || d.c_f64 || d.store != ST_SET || !s.partial) return hipErrorInvalidValue;
         const LpPlan lp = make_lp_plan(d);
         if (d.math == MATH_BF16)
-            return d.op == OP_HN ? launch_lp<__bf16, true>(d, lp, s.partial, st) : launch_lp<__bf16, false>(d, lp, s.partial, st);
-        return d.op == OP_HN ? launch_lp<_Float16, true>(d, lp, s.partial, st) : launch_lp<_Float16, false>(d, lp, s.partial, st);
+            return d.op == OP_HN ? launch_lp<__bf16, true, false>(d, lp, s.partial, st)
+                                 : launch_lp<__bf16, false, false>(d, lp, s.partial, st);
+        return d.op == OP_HN ? launch_lp<_Float16, true, false>(d, lp, s.partial, st)
+                             : launch_lp<_Float16, false, false>(d, lp, s.partial, st);
     }
     if (d.math == MATH_F32) {
         if (d.a_f64 || d.b_f64 || d.c_f64) return hipErrorInvalidValue;
