@@ -100,7 +100,7 @@ struct BigRec {
     double* lam;    // W, ascending
     double* refl;   // 4 W (W + 1) / 2, reflector j's entry i > j at refl_at(W, i, j): columns contiguous
     double* P;      // 2 x 4 W: p = tau G v of a reflector (the two buffers alternate by step parity)
-    double* KP;     // 2 x step_blocks(W) shares of v^H p
+    double* KP;     // 2 x SRB step_blocks(W) shares of v^H p (one per row wave)
     double* CB;     // 2 x 4 W: copy of the column of the next reflector, taken before its update
     double* X;      // W x nvec eigenvectors of T (entry i of vector t at X[i nvec + t])
     double* DM;     // W x nvec backward pivots (the same layout)
@@ -120,37 +120,35 @@ __host__ __device__ inline BigRec big_rec(double* base, int64_t W, int64_t nvec)
     r.lam = p; p += W;
     r.refl = p; p += 4 * (W * (W + 1) / 2);
     r.P = p; p += 8 * W;
-    r.KP = p; p += 2 * step_blocks(W);
+    r.KP = p; p += 2 * SRB * step_blocks(W);
     r.CB = p; p += 8 * W;
     r.X = p; p += W * nvec;
     r.DM = p; p += W * nvec;
     return r;
 }
 __host__ __device__ inline int64_t big_rec_doubles(int64_t W, int64_t nvec) {
-    return 4 * W * W + 9 * W + 8 + 4 * (W * (W + 1) / 2) + 16 * W + 2 * step_blocks(W) + 2 * W * nvec;
+    return 4 * W * W + 9 * W + 8 + 4 * (W * (W + 1) / 2) + 16 * W + 2 * SRB * step_blocks(W) + 2 * W * nvec;
 }
 
 // The reflector of a column x (entries r > j0 below the diagonal held in vn[r], zero elsewhere):
 // alpha = |x|, phi = x_{j0+1} / |x_{j0+1}|, v = x + alpha phi e_{j0+1} (H x = -alpha phi e_{j0+1}),
-// tau = 1 / (alpha (alpha + |x_{j0+1}|)).  Every thread returns tau; block 0 stores v (rows > j0)
-// in the record's column j0, tau and s = -alpha phi.  part: this thread's share of |x|^2.
-__device__ double make_reflector(double* vn, int W, int j0, double part, double* red, const BigRec& R, bool store) {
+// tau = 1 / (alpha (alpha + |x_{j0+1}|)).  vn is left as x: v differs from it only in entry j0 + 1,
+// which every thread gets in v1 (so no thread rewrites LDS that others read).  Every thread
+// returns tau; block 0 stores v (rows > j0) in the record's column j0, tau and s = -alpha phi.
+// part: this thread's share of |x|^2.
+__device__ double make_reflector(const double* vn, int W, int j0, double part, double* red, const BigRec& R, bool store,
+                                 Q4& v1) {
     const double alpha = sqrt(block_total(part, red));
     const Q4 x1 = j0 + 1 < W ? Q4{vn[j0 + 1], vn[W + j0 + 1], vn[2 * W + j0 + 1], vn[3 * W + j0 + 1]}
                              : Q4{0, 0, 0, 0};
     const double ax1 = sqrt(qn2(x1));
     const Q4 phi = ax1 > 0.0 ? qscale(x1, 1.0 / ax1) : Q4{1, 0, 0, 0};
     const double tau = alpha > 0.0 ? 1.0 / (alpha * (alpha + ax1)) : 0.0;
-    __syncthreads();                                     // every thread has read x1
-    if (threadIdx.x == 0 && j0 + 1 < W) {
-        const Q4 v1 = qadd(x1, qscale(phi, alpha));
-        vn[j0 + 1] = v1.w; vn[W + j0 + 1] = v1.x; vn[2 * W + j0 + 1] = v1.y; vn[3 * W + j0 + 1] = v1.z;
-    }
-    __syncthreads();
+    v1 = qadd(x1, qscale(phi, alpha));
     if (store) {
         const int64_t pps = (int64_t)W * (W + 1) / 2;
         for (int r = j0 + 1 + (int)threadIdx.x; r < W; r += BT)
-            st(R.refl, pps, refl_at(W, r, j0), Q4{vn[r], vn[W + r], vn[2 * W + r], vn[3 * W + r]});
+            st(R.refl, pps, refl_at(W, r, j0), r == j0 + 1 ? v1 : Q4{vn[r], vn[W + r], vn[2 * W + r], vn[3 * W + r]});
         if (threadIdx.x == 0) {
             R.tau[j0] = tau;
             const Q4 sj = qscale(phi, -alpha);
@@ -158,6 +156,11 @@ __device__ double make_reflector(double* vn, int W, int j0, double part, double*
         }
     }
     return tau;
+}
+
+// entry c of the reflector held as x in vn with its entry j0 + 1 in v1
+__device__ __forceinline__ Q4 refl_entry(const double* vn, int W, int c, int j0, Q4 v1) {
+    return c == j0 + 1 ? v1 : Q4{vn[c], vn[W + c], vn[2 * W + c], vn[3 * W + c]};
 }
 
 // Start of the tridiagonalisation of problem blockIdx.y: copy its rows of G into the record,
@@ -174,6 +177,7 @@ __global__ __launch_bounds__(BT) void k_big_start(const double* __restrict__ G0,
     const int nbs = (int)step_blocks(W);
     const bool refl = W >= 3;
     double tau = 0.0;
+    Q4 v1{0, 0, 0, 0};
     if (refl) {
         double part = 0.0;
         for (int r = tid; r < W; r += BT) {
@@ -181,7 +185,7 @@ __global__ __launch_bounds__(BT) void k_big_start(const double* __restrict__ G0,
             vn[r] = x.w; vn[W + r] = x.x; vn[2 * W + r] = x.y; vn[3 * W + r] = x.z;
             part += qn2(x);
         }
-        tau = make_reflector(vn, W, 0, part, red, R, blockIdx.x == 0);
+        tau = make_reflector(vn, W, 0, part, red, R, blockIdx.x == 0, v1);
     }
     const int wave = tid >> 6, lane = tid & 63;
     const int r = blockIdx.x * SRB + wave;
@@ -192,7 +196,7 @@ __global__ __launch_bounds__(BT) void k_big_start(const double* __restrict__ G0,
             const int64_t e = (int64_t)r * W + c;
             const Q4 g = ld(G, ps, e);
             st(R.Gw, ps, e, g);
-            if (refl && c > 0) acc = qadd(acc, qmul(g, Q4{vn[c], vn[W + c], vn[2 * W + c], vn[3 * W + c]}));
+            if (refl && c > 0) acc = qadd(acc, qmul(g, refl_entry(vn, W, c, 0, v1)));
             if (c == 1 && r > 1) st(R.CB, W, r, g);
         }
         if (refl) {
@@ -200,12 +204,11 @@ __global__ __launch_bounds__(BT) void k_big_start(const double* __restrict__ G0,
             const Q4 p = qscale(acc, tau);
             if (lane == 0 && r > 0) {
                 st(R.P, W, r, p);
-                kp = qdot(Q4{vn[r], vn[W + r], vn[2 * W + r], vn[3 * W + r]}, p);
+                kp = qdot(refl_entry(vn, W, r, 0, v1), p);
             }
         }
     }
-    const double kt = block_total(kp, red);
-    if (tid == 0) R.KP[blockIdx.x] = kt;
+    if (lane == 0) R.KP[blockIdx.x * SRB + wave] = kp;   // this wave's share of v^H p
     (void)nbs;
 }
 
@@ -229,8 +232,11 @@ __global__ __launch_bounds__(BT) void k_big_step(double* base0, int64_t rstride,
     double* Pn = R.P + (int64_t)nxt * 4 * W;
     const double* CBc = R.CB + (int64_t)cur * 4 * W;
     double* CBn = R.CB + (int64_t)nxt * 4 * W;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int r = blockIdx.x * SRB + wave;
+    const int nks = SRB * nbs;
     double part = 0.0;
-    for (int i = tid; i < nbs; i += BT) part += R.KP[cur * nbs + i];
+    for (int i = tid; i < nks; i += BT) part += R.KP[cur * nks + i];
     const double tau = R.tau[j];
     const double K = 0.5 * tau * block_total(part, red);
     for (int c = tid; c < W; c += BT) {
@@ -246,6 +252,7 @@ __global__ __launch_bounds__(BT) void k_big_step(double* base0, int64_t rstride,
     const int j1 = j + 1;
     const bool more = j1 <= W - 3;
     double tau1 = 0.0;
+    Q4 v1n{0, 0, 0, 0};
     if (more) {
         // column j1 after this step's update, rows below the diagonal (the same arithmetic as the
         // row update below, so v' is exactly the updated column)
@@ -263,10 +270,8 @@ __global__ __launch_bounds__(BT) void k_big_step(double* base0, int64_t rstride,
             }
             vn[r] = x.w; vn[W + r] = x.x; vn[2 * W + r] = x.y; vn[3 * W + r] = x.z;
         }
-        tau1 = make_reflector(vn, W, j1, p2, red, R, blockIdx.x == 0);
+        tau1 = make_reflector(vn, W, j1, p2, red, R, blockIdx.x == 0, v1n);
     }
-    const int wave = tid >> 6, lane = tid & 63;
-    const int r = blockIdx.x * SRB + wave;
     double kp = 0.0;
     if (r > j && r < W) {
         const Q4 vr{vs[r], vs[W + r], vs[2 * W + r], vs[3 * W + r]};
@@ -279,7 +284,7 @@ __global__ __launch_bounds__(BT) void k_big_step(double* base0, int64_t rstride,
             Q4 t = qsub(qsub(ld(R.Gw, ps, e), qmul(vr, qconj(qc))), qmul(qr, qconj(vc)));
             if (r == c) t.x = t.y = t.z = 0.0;
             st(R.Gw, ps, e, t);
-            if (more) acc = qadd(acc, qmul(t, Q4{vn[c], vn[W + c], vn[2 * W + c], vn[3 * W + c]}));
+            if (more) acc = qadd(acc, qmul(t, refl_entry(vn, W, c, j1, v1n)));
             if (c == j + 2 && r > j + 2) st(CBn, W, r, t);
         }
         if (more) {
@@ -287,12 +292,11 @@ __global__ __launch_bounds__(BT) void k_big_step(double* base0, int64_t rstride,
             const Q4 p = qscale(acc, tau1);
             if (lane == 0 && r > j1) {
                 st(Pn, W, r, p);
-                kp = qdot(Q4{vn[r], vn[W + r], vn[2 * W + r], vn[3 * W + r]}, p);
+                kp = qdot(refl_entry(vn, W, r, j1, v1n), p);
             }
         }
     }
-    const double kt = block_total(kp, red);
-    if (tid == 0) R.KP[nxt * nbs + blockIdx.x] = kt;
+    if (lane == 0) R.KP[nxt * nks + blockIdx.x * SRB + wave] = kp;   // this wave's share of v'^H p'
 }
 
 // diagonal, real subdiagonal b_j = |s_j|, phases ph_{j+1} = s_j ph_j / |s_j|, bounds (problem

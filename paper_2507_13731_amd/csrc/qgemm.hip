@@ -635,6 +635,245 @@ __global__ __launch_bounds__(256, CN <= 3 ? 2 : 1) void k_qview(VParams P) {
 }
 
 // ------------------------------------------------------------------------------------------
+// FP64 A^H B of FP32 operands (Grams, Krylov projections): operands straight from global memory.
+//
+// The same tiles, K splits and partial layout as k_qgemm (32 x 32 output tiles, four waves of
+// 16 x 16, steps of 16 reduction rows), but no LDS and no barrier: each wave loads its own
+// fragments in the order v_mfma_f64_16x16x4f64 consumes them.  Lane (r, g) = (l % 16, l / 16)
+// supplies, for the j-th of the four MFMAs of a step, reduction row k0 + 4 g + j: A_q(k, i0 + r)
+// for the A^H operand and B_q(k, j0 + r) for B, each a 4-byte load (the 16 lanes of a group
+// read 64 contiguous bytes of a row), converted to FP64 (exact).  The loads of step s + 1 are in
+// flight during the MFMAs of step s.  The signs of eq. (1) go on a negated copy of the A^H
+// fragment.  Rows past the K range and columns past M or N load zeros.
+template <bool SYM>
+__global__ __launch_bounds__(256) void k_qgemm_hn(KParams P) {
+    if (P.skip && *P.skip == 0) return;
+    if (SYM && blockIdx.x > blockIdx.y) return;     // below the diagonal: the mirror of (y, x)
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int64_t row0 = (int64_t)blockIdx.x * 32 + wm * 16, col0 = (int64_t)blockIdx.y * 32 + wn * 16;
+    const int split = blockIdx.z;
+    const int64_t kb = (int64_t)split * P.kchunk;
+    int64_t ke = P.K < kb + P.kchunk ? P.K : kb + P.kchunk;
+    if (P.b_upper && ke > (int64_t)blockIdx.y * 32 + 32) ke = (int64_t)blockIdx.y * 32 + 32;   // B(k, c) = 0 for k > c
+    const float* __restrict__ A = (const float*)P.A;
+    const float* __restrict__ B = (const float*)P.B;
+    const int r = lane & 15, g = lane >> 4;
+    const bool aok = row0 + r < P.M, bok = col0 + r < P.N;
+    // per-lane byte offsets (32-bit: the launcher checks the range) from uniform row bases
+    const unsigned aofs = (unsigned)((4 * g * P.lda + (aok ? row0 + r : 0)) * sizeof(float));
+    const unsigned bofs = (unsigned)((4 * g * P.ldb + (bok ? col0 + r : 0)) * sizeof(float));
+
+    f64x4 acc[4];
+#pragma unroll
+    for (int p = 0; p < 4; p++) acc[p] = f64x4{0, 0, 0, 0};
+
+    // one step's operands: fa[q][j] = A_q(k0 + 4 g + j, i0 + r), fb[q][j] likewise for B
+    // a full step (rows k0 .. k0 + 15 all below ke) loads unconditionally: a lane past M or N reads
+    // column 0, which only reaches output rows or columns that are never stored
+    auto fetch = [&](int64_t k0, float (&fa)[4][4], float (&fb)[4][4]) {
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const char* arow = (const char*)(A + q * P.aps + (k0 + j) * P.lda);   // uniform over the wave
+                const char* brow = (const char*)(B + q * P.bps + (k0 + j) * P.ldb);
+                fa[q][j] = *(const float*)(arow + aofs);
+                fb[q][j] = *(const float*)(brow + bofs);
+            }
+    };
+    // a ragged last step masks its rows (they may lie past K)
+    auto fetch_tail = [&](int64_t k0, float (&fa)[4][4], float (&fb)[4][4]) {
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const bool kin = k0 + 4 * g + j < ke;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const char* arow = (const char*)(A + q * P.aps + (k0 + j) * P.lda);
+                const char* brow = (const char*)(B + q * P.bps + (k0 + j) * P.ldb);
+                fa[q][j] = kin ? *(const float*)(arow + aofs) : 0.0f;
+                fb[q][j] = kin ? *(const float*)(brow + bofs) : 0.0f;
+            }
+        }
+    };
+    auto step = [&](const float (&fa)[4][4], const float (&fb)[4][4]) {
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            double a[4], na[4], b[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                a[q] = (double)fa[q][j];
+                na[q] = -a[q];
+                b[q] = (double)fb[q][j];
+            }
+            // q outermost: consecutive MFMAs update different accumulators
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+#pragma unroll
+                for (int p = 0; p < 4; p++)
+                    acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(term_sign<true>(p, q) > 0 ? a[q] : na[q], b[p ^ q],
+                                                                  acc[p], 0, 0, 0);
+        }
+    };
+
+    // nf full steps, then a ragged one if K's range does not end on a step; the operands of the
+    // next step are in flight during the MFMAs of the current one (ping-pong x / y; a fetch
+    // past the last full step reloads it, so that every fetch in the loop is unconditional)
+    const int64_t nf = kb < ke ? (ke - kb) / 16 : 0;
+    float xa[4][4], xb[4][4], ya[4][4], yb[4][4];
+    if (nf > 0) fetch(kb, xa, xb);
+    int64_t t = 0;
+    for (; t + 1 < nf; t += 2) {
+        fetch(kb + 16 * (t + 1), ya, yb);
+        step(xa, xb);
+        fetch(kb + 16 * (t + 2 < nf ? t + 2 : nf - 1), xa, xb);
+        step(ya, yb);
+    }
+    if (t < nf) step(xa, xb);
+    if (kb + 16 * nf < ke) {
+        fetch_tail(kb + 16 * nf, ya, yb);
+        step(ya, yb);
+    }
+
+    // D element (lane, i) of v_mfma_f64_16x16x4f64 sits at row lane / 16 + 4 i, column lane % 16
+    if (P.splits == 1) {
+        double* __restrict__ C = (double*)P.C;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int64_t rr = row0 + g + 4 * i, c = col0 + r;
+            if (rr < P.M && c < P.N) {
+#pragma unroll
+                for (int p = 0; p < 4; p++) {
+                    const double v = acc[p][i];
+                    double* dst = C + p * P.cps + rr * P.ldc + c;
+                    *dst = P.store == ST_SUB ? *dst - v : v;
+                    // an off-diagonal tile of a Hermitian Gram also gives (c, rr) = conj(rr, c)
+                    if (SYM && blockIdx.x < blockIdx.y) C[p * P.cps + c * P.ldc + rr] = p ? -v : v;
+                }
+            }
+        }
+        return;
+    }
+    double* __restrict__ part = (double*)P.part;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const int64_t rr = row0 + g + 4 * i, c = col0 + r;
+#pragma unroll
+        for (int p = 0; p < 4; p++) part[(((int64_t)split * 4 + p) * P.Mp + rr) * P.Np + c] = acc[p][i];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// FP64 A B of an FP32 tall operand and an FP64 small one (CholeskyQR applies, Krylov
+// projections, the back-multiplication): operands straight from global memory, the tiles, K
+// splits and partial layout of the 2 x 2 plan.  Lane (r, g) supplies, for the j-th of the four
+// MFMAs of a step, reduction index k0 + 4 g + j: A_q(i0 + r, k0 + 4 g .. + 3) is one 16-byte load
+// per plane (element j feeds MFMA j) and B_q(k0 + 4 g + j, j0 + r) an 8-byte load.  The loads of
+// step s + 1 are in flight during the MFMAs of step s.  Rows past M and columns past N read row
+// or column 0 and are never stored; a ragged last step masks its elements.
+__global__ __launch_bounds__(256) void k_qgemm_nn(KParams P) {
+    if (P.skip && *P.skip == 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    const int64_t row0 = (int64_t)blockIdx.x * 32 + wm * 16, col0 = (int64_t)blockIdx.y * 32 + wn * 16;
+    const int split = blockIdx.z;
+    const int64_t kb = (int64_t)split * P.kchunk;
+    int64_t ke = P.K < kb + P.kchunk ? P.K : kb + P.kchunk;
+    if (P.b_upper && ke > (int64_t)blockIdx.y * 32 + 32) ke = (int64_t)blockIdx.y * 32 + 32;   // B(k, c) = 0 for k > c
+    const float* __restrict__ A = (const float*)P.A;
+    const double* __restrict__ B = (const double*)P.B;
+    const int r = lane & 15, g = lane >> 4;
+    // per-lane byte offsets (32-bit: the launcher checks the range) from uniform bases
+    const unsigned aofs = (unsigned)(((row0 + r < P.M ? row0 + r : 0) * P.lda + 4 * g) * sizeof(float));
+    const unsigned bofs = (unsigned)(((col0 + r < P.N ? col0 + r : 0) + 4 * g * P.ldb) * sizeof(double));
+    auto at_a = [&](int64_t e) -> const float* { return (const float*)((const char*)(A + e) + aofs); };
+    auto at_b = [&](int64_t e) -> const double* { return (const double*)((const char*)(B + e) + bofs); };
+
+    f64x4 acc[4];
+#pragma unroll
+    for (int p = 0; p < 4; p++) acc[p] = f64x4{0, 0, 0, 0};
+
+    auto fetch = [&](int64_t k0, f32x4 (&fa)[4], double (&fb)[4][4]) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) fa[q] = *reinterpret_cast<const f32x4*>(at_a(q * P.aps + k0));
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) fb[q][j] = *at_b(q * P.bps + (k0 + j) * P.ldb);
+    };
+    auto fetch_tail = [&](int64_t k0, f32x4 (&fa)[4], double (&fb)[4][4]) {
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const bool kin = k0 + 4 * g + j < ke;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                fa[q][j] = kin ? *at_a(q * P.aps + k0 + j) : 0.0f;
+                fb[q][j] = kin ? *at_b(q * P.bps + (k0 + j) * P.ldb) : 0.0;
+            }
+        }
+    };
+    auto step = [&](const f32x4 (&fa)[4], const double (&fb)[4][4]) {
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            double a[4], na[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                a[q] = (double)fa[q][j];
+                na[q] = -a[q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; q++)
+#pragma unroll
+                for (int p = 0; p < 4; p++)
+                    acc[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(term_sign<false>(p, q) > 0 ? a[q] : na[q],
+                                                                  fb[p ^ q][j], acc[p], 0, 0, 0);
+        }
+    };
+
+    const int64_t nf = kb < ke ? (ke - kb) / 16 : 0;
+    f32x4 xa[4], ya[4];
+    double xb[4][4], yb[4][4];
+    if (nf > 0) fetch(kb, xa, xb);
+    int64_t t = 0;
+    for (; t + 1 < nf; t += 2) {
+        fetch(kb + 16 * (t + 1), ya, yb);
+        step(xa, xb);
+        fetch(kb + 16 * (t + 2 < nf ? t + 2 : nf - 1), xa, xb);
+        step(ya, yb);
+    }
+    if (t < nf) step(xa, xb);
+    if (kb + 16 * nf < ke) {
+        fetch_tail(kb + 16 * nf, ya, yb);
+        step(ya, yb);
+    }
+
+    // D element (lane, i) of v_mfma_f64_16x16x4f64 sits at row lane / 16 + 4 i, column lane % 16
+    if (P.splits == 1) {
+        float* __restrict__ C = (float*)P.C;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int64_t rr = row0 + g + 4 * i, c = col0 + r;
+            if (rr < P.M && c < P.N) {
+#pragma unroll
+                for (int p = 0; p < 4; p++) {
+                    float* dst = C + p * P.cps + rr * P.ldc + c;
+                    const double v = acc[p][i];
+                    *dst = P.store == ST_SUB ? (float)((double)*dst - v) : (float)v;
+                }
+            }
+        }
+        return;
+    }
+    double* __restrict__ part = (double*)P.part;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const int64_t rr = row0 + g + 4 * i, c = col0 + r;
+#pragma unroll
+        for (int p = 0; p < 4; p++) part[(((int64_t)split * 4 + p) * P.Mp + rr) * P.Np + c] = acc[p][i];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // configuration choice
 
 struct Plan {
@@ -651,16 +890,24 @@ bool is_sym_gram(const QgemmDesc& d) {
            d.a_f64 == d.b_f64 && d.M == d.N && d.store == ST_SET;
 }
 
+// FP32 A times FP64 B into FP32, with 16-byte aligned rows of A: the direct kernel k_qgemm_nn
+bool nn_direct(const QgemmDesc& d) {
+    return d.math == MATH_F64 && d.op == OP_NN && !d.a_f64 && d.b_f64 && !d.c_f64 && ((uintptr_t)d.A % 16) == 0 &&
+           d.lda % 4 == 0 && d.aps % 4 == 0;
+}
+
 Plan make_plan(const QgemmDesc& d) {
     Plan p{};
-    if (d.op == OP_HN || d.b_upper) {
+    if (d.op == OP_HN || d.b_upper || nn_direct(d)) {
         // Gram-like products: small M x N output, long K; 32 x 32 tiles so that K splits
         // spread the FP64 MFMA work over many CUs.  Products with an upper triangular right
         // operand (Y R^{-1}) take them too: a column tile's reduction then stops 32 columns
         // apart, and w = 160 needs no padded columns.
+        // FP32 times FP64 products (applies, projections, back-multiplication) take them in the
+        // direct kernel: 160 columns are five tiles, no padding.
         p.BK = 16; p.WM = 2; p.WN = 2; p.RM = 1; p.CN = 1;
     } else {
-        // tall times small (applies, projections, back-multiplication)
+        // tall times small with FP64 operands
         p.BK = 16; p.WM = 1; p.WN = 4; p.RM = 1; p.CN = 1;
     }
     const int64_t BM = p.WM * p.RM * 16, BN = p.WN * p.CN * 16;
@@ -690,16 +937,10 @@ Plan make_plan(const QgemmDesc& d) {
     return p;
 }
 
-template <class T, int WM, int WN, int RM, int CN, int BK, bool ADJ, class TA, class TB, class TC>
-hipError_t launch_t(const Plan& pl, const KParams& kp, hipStream_t st) {
-    dim3 grid((unsigned)pl.gx, (unsigned)pl.gy, (unsigned)pl.splits);
-    hipLaunchKernelGGL((k_qgemm<T, WM, WN, RM, CN, BK, ADJ, TA, TB, TC>), grid, dim3(256), 0, st, kp);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || pl.splits == 1) return e;
-    if constexpr (std::is_same<T, float>::value && std::is_same<TC, float>::value)
-        return reduce_f32((const float*)kp.part, (int)pl.splits, pl.Mp, pl.Np, (float*)kp.C, kp.ldc, kp.cps, kp.M,
-                          kp.N, kp.store, kp.skip, st);
-    const int sym_bm = kp.sym ? WM * RM * 16 : 0;
+// the ordered sum of the split-K partial tiles into C (sym_bm > 0: Hermitian Gram with square
+// tiles of sym_bm, the tiles below the diagonal mirrored)
+template <class T, class TC>
+hipError_t reduce_parts(const Plan& pl, const KParams& kp, int sym_bm, hipStream_t st) {
     if (pl.splits <= 8) {
         const int64_t total = 4 * kp.M * kp.N;
         hipLaunchKernelGGL((k_splitk_reduce_few<T, TC>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
@@ -712,6 +953,45 @@ hipError_t launch_t(const Plan& pl, const KParams& kp, hipStream_t st) {
                        (const T*)kp.part, (int)pl.splits, pl.Mp, pl.Np, (TC*)kp.C, kp.ldc, kp.cps, kp.M, kp.N,
                        kp.store, kp.skip, sym_bm);
     return hipGetLastError();
+}
+
+template <class T, int WM, int WN, int RM, int CN, int BK, bool ADJ, class TA, class TB, class TC>
+hipError_t launch_t(const Plan& pl, const KParams& kp, hipStream_t st) {
+    dim3 grid((unsigned)pl.gx, (unsigned)pl.gy, (unsigned)pl.splits);
+    hipLaunchKernelGGL((k_qgemm<T, WM, WN, RM, CN, BK, ADJ, TA, TB, TC>), grid, dim3(256), 0, st, kp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || pl.splits == 1) return e;
+    if constexpr (std::is_same<T, float>::value && std::is_same<TC, float>::value)
+        return reduce_f32((const float*)kp.part, (int)pl.splits, pl.Mp, pl.Np, (float*)kp.C, kp.ldc, kp.cps, kp.M,
+                          kp.N, kp.store, kp.skip, st);
+    return reduce_parts<T, TC>(pl, kp, kp.sym ? WM * RM * 16 : 0, st);
+}
+
+// k_qgemm_nn for the FP32 x FP64 products (the 2 x 2 plan; partials in FP64)
+hipError_t launch_nn(const Plan& pl, const KParams& kp, hipStream_t st) {
+    // the kernel's per-lane offsets are 32-bit
+    const int64_t lim = (int64_t)1 << 30;
+    if (kp.M * kp.lda + 16 >= lim || 2 * (kp.N + 12 * kp.ldb) >= lim)
+        return launch_t<double, 2, 2, 1, 1, 16, false, float, double, float>(pl, kp, st);
+    dim3 grid((unsigned)pl.gx, (unsigned)pl.gy, (unsigned)pl.splits);
+    hipLaunchKernelGGL(k_qgemm_nn, grid, dim3(256), 0, st, kp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || pl.splits == 1) return e;
+    return reduce_parts<double, float>(pl, kp, 0, st);
+}
+
+// k_qgemm_hn for the FP32 A^H B products (the tiles and partial layout of the 2 x 2 plan)
+hipError_t launch_hn(const Plan& pl, const KParams& kp, hipStream_t st) {
+    // the kernel's per-lane offsets are 32-bit
+    const int64_t lim = (int64_t)1 << 30;
+    if (12 * kp.lda + kp.M >= lim || 12 * kp.ldb + kp.N >= lim)
+        return launch_t<double, 2, 2, 1, 1, 16, true, float, float, double>(pl, kp, st);
+    dim3 grid((unsigned)pl.gx, (unsigned)pl.gy, (unsigned)pl.splits);
+    if (kp.sym) hipLaunchKernelGGL(k_qgemm_hn<true>, grid, dim3(256), 0, st, kp);
+    else hipLaunchKernelGGL(k_qgemm_hn<false>, grid, dim3(256), 0, st, kp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || pl.splits == 1) return e;
+    return reduce_parts<double, double>(pl, kp, kp.sym ? 32 : 0, st);
 }
 
 struct VPlan {
@@ -1228,13 +1508,13 @@ hipError_t qgemm_launch(const QgemmDesc& d, const QgemmScratch& s, hipStream_t s
     if (pl.splits > 1 && !s.partial) return hipErrorInvalidValue;
     // FP64 arithmetic
     if (d.op == OP_HN) {
-        if (!d.a_f64 && !d.b_f64 && d.c_f64)
-            return launch_t<double, 2, 2, 1, 1, 16, true, float, float, double>(pl, kp, st);
+        if (!d.a_f64 && !d.b_f64 && d.c_f64) return launch_hn(pl, kp, st);
         if (d.a_f64 && d.b_f64 && d.c_f64)
             return launch_t<double, 2, 2, 1, 1, 16, true, double, double, double>(pl, kp, st);
         return hipErrorInvalidValue;
     }
     const bool square = pl.WN == 2;
+    if (nn_direct(d)) return launch_nn(pl, kp, st);
     if (!d.a_f64 && d.b_f64 && !d.c_f64)
         return square ? launch_t<double, 2, 2, 1, 1, 16, false, float, double, float>(pl, kp, st)
                       : launch_t<double, 1, 4, 1, 1, 16, false, float, double, float>(pl, kp, st);
