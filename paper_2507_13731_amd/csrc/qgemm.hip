@@ -8,17 +8,20 @@
 // planes and each B_r fragment feeds four, so one pass over A computes the whole quaternion
 // product with A read once.
 //
-// Three kernel families:
+// Kernel families:
 //  - k_qview (math = MATH_F32): the views.  FP32 operands loaded straight from global memory
 //    in MFMA operand order (the thin block transposed first by k_thin_t), v_mfma_f32_16x16x4f32,
 //    FP32 accumulation; see the section below.
-//  - k_qgemm (math = MATH_F64): Gram matrices, CholeskyQR applies, Krylov projections and the
-//    back-multiplication.  A workgroup of 4 waves owns a BM x BN tile of all four output planes;
-//    per K step the four planes of an A tile and of a B tile are staged through LDS (converted
-//    to FP64 there: exact for FP32 data) and multiplied with v_mfma_f64_16x16x4f64; the global
-//    loads of step t+1 are in flight during the MFMAs of step t.  The MFMA A operand always
-//    comes from the A tile, stored row-major for A B and k-major for A^H B, so one kernel serves
-//    both orientations.  Signs go on a negated register copy of the thin operand.
+//  - k_qgemm_hn / k_qgemm_nn (math = MATH_F64, FP32 operands, and FP64 for the small right
+//    operand of A B): Gram matrices, Krylov projections, CholeskyQR applies and the
+//    back-multiplication.  Four waves of 16 x 16 per 32 x 32 output tile of all four planes, the
+//    operands loaded straight from global memory in v_mfma_f64_16x16x4f64 operand order and
+//    converted to FP64 (exact for FP32 data), no LDS and no barrier in the K loop.
+//  - k_qgemm (math = MATH_F64): the products of FP64 operands (the blocked Cholesky's off-diagonal
+//    blocks) and the fallback for layouts the direct kernels do not take.  A workgroup of 4 waves
+//    owns a BM x BN tile of all four output planes; per K step the four planes of an A tile and of
+//    a B tile are staged through LDS in FP64; the MFMA A operand always comes from the A tile,
+//    stored row-major for A B and k-major for A^H B, so one kernel serves both orientations.
 //  - k_qgemm_lp (MATH_BF16 / MATH_F16): the reduced-precision views, and (with the residual
 //    copies staged beside the values) the split forms (MATH_BF16X3 / MATH_F16X3).
 // When the output tiles cannot fill the chip, K is split across workgroups; partial tiles go to
@@ -724,10 +727,16 @@ __global__ __launch_bounds__(256) void k_qgemm_hn(KParams P) {
     if (nf > 0) fetch(kb, xa, xb);
     int64_t t = 0;
     for (; t + 1 < nf; t += 2) {
+        // the order is pinned (sched_barrier): a step's conversions and MFMAs stay after the next
+        // step's loads are issued and never wait for them
         fetch(kb + 16 * (t + 1), ya, yb);
+        __builtin_amdgcn_sched_barrier(0);
         step(xa, xb);
+        __builtin_amdgcn_sched_barrier(0);
         fetch(kb + 16 * (t + 2 < nf ? t + 2 : nf - 1), xa, xb);
+        __builtin_amdgcn_sched_barrier(0);
         step(ya, yb);
+        __builtin_amdgcn_sched_barrier(0);
     }
     if (t < nf) step(xa, xb);
     if (kb + 16 * nf < ke) {
@@ -836,10 +845,16 @@ __global__ __launch_bounds__(256) void k_qgemm_nn(KParams P) {
     if (nf > 0) fetch(kb, xa, xb);
     int64_t t = 0;
     for (; t + 1 < nf; t += 2) {
+        // the order is pinned (sched_barrier): a step's conversions and MFMAs stay after the next
+        // step's loads are issued and never wait for them
         fetch(kb + 16 * (t + 1), ya, yb);
+        __builtin_amdgcn_sched_barrier(0);
         step(xa, xb);
+        __builtin_amdgcn_sched_barrier(0);
         fetch(kb + 16 * (t + 2 < nf ? t + 2 : nf - 1), xa, xb);
+        __builtin_amdgcn_sched_barrier(0);
         step(ya, yb);
+        __builtin_amdgcn_sched_barrier(0);
     }
     if (t < nf) step(xa, xb);
     if (kb + 16 * nf < ke) {
@@ -918,8 +933,7 @@ Plan make_plan(const QgemmDesc& d) {
     // a Hermitian Gram computes the tiles on and above the diagonal only
     const int64_t tiles = is_sym_gram(d) ? p.gx * (p.gx + 1) / 2 : p.gx * p.gy;
     // split K so that several workgroups per CU run (Gram-like products: about four, which hide
-    // the latency of one another's strided loads; the others about one), each over at least 2 K
-    // steps
+    // the latency of one another's loads; the others about one), each over at least 2 K steps
     const int64_t min_steps = 2;
     const int64_t target = d.op == OP_HN ? kGramWgPerCU * kCUs : kCUs;
     int64_t splits = 1;
