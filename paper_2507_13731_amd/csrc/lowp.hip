@@ -34,11 +34,19 @@ __device__ __forceinline__ int64_t tiled_index(int64_t row, int64_t k, int p, in
 // Ar / Ar_t in the same pass; 2: the residual copies alone (into Ar / Ar_t).  fro (optional): the
 // tile's sum of squares of A (FP64, the values before scaling) into fro[blockIdx.y * gridDim.x +
 // blockIdx.x], so that the pass also yields ||A||_F^2.
+template <class TL>
+struct Vec8;
+template <>
+struct Vec8<__bf16> { typedef __bf16 type __attribute__((ext_vector_type(8))); };
+template <>
+struct Vec8<_Float16> { typedef _Float16 type __attribute__((ext_vector_type(8))); };
+
 template <class TL, int MODE>
 __global__ __launch_bounds__(256) void k_lowp_copy(const float* __restrict__ A, int64_t m, int64_t n, int64_t lda,
                                                    int64_t aps, TL* __restrict__ Alo, TL* __restrict__ Alo_t,
                                                    TL* __restrict__ Ar, TL* __restrict__ Ar_t,
                                                    const float* __restrict__ scale, double* __restrict__ fro) {
+    using V8 = typename Vec8<TL>::type;
     __shared__ float tile[kT][kT + 1];
     __shared__ double red[4];
     const int64_t r0 = (int64_t)blockIdx.y * kT, c0 = (int64_t)blockIdx.x * kT;
@@ -62,28 +70,39 @@ __global__ __launch_bounds__(256) void k_lowp_copy(const float* __restrict__ A, 
         for (int u = 0; u < kT / 4; u++) tile[ty + 4 * u][tx] = v[u];
         __syncthreads();
         // Alo: row tiles r0/16 .. +3, reduction tile c0/64; each (row tile, plane) block of 1024
-        // elements is contiguous: thread tid writes offsets tid, tid + 256, ...
-        for (int rq = 0; rq < rtiles_m; rq++)
-            for (int o = tid; o < 1024; o += 256) {
-                const int h = o >> 9, kq = (o >> 7) & 3, r = (o >> 3) & 15, t = o & 7;
-                const int il = rq * 16 + r, kl = h * 32 + kq * 8 + t;
-                const float x = tile[il][kl];
-                const TL hi = (TL)x;
-                const int64_t at = tiled_index(r0 + il, c0 + kl, p, KTn);
-                if constexpr (MODE != 2) Alo[at] = hi;
-                if constexpr (MODE != 0) Ar[at] = (TL)(x - (float)hi);
+        // elements is contiguous, and a lane's 8 elements (t = 0..7) are 16 contiguous bytes:
+        // one thread per 8 elements, one 16-byte store each
+        for (int q8 = tid; q8 < rtiles_m * 128; q8 += 256) {
+            const int rq = q8 >> 7, o8 = q8 & 127;
+            const int h = o8 >> 6, kq = (o8 >> 4) & 3, r = o8 & 15;
+            const int il = rq * 16 + r, kl = h * 32 + kq * 8;
+            V8 hi, lo;
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                const float x = tile[il][kl + t];
+                hi[t] = (TL)x;
+                lo[t] = (TL)(x - (float)hi[t]);
             }
+            const int64_t at = tiled_index(r0 + il, c0 + kl, p, KTn);
+            if constexpr (MODE != 2) *reinterpret_cast<V8*>(Alo + at) = hi;
+            if constexpr (MODE != 0) *reinterpret_cast<V8*>(Ar + at) = lo;
+        }
         // Alo_t: rows = columns of A (c0 ..), reduction = rows of A (r0 ..)
-        for (int rq = 0; rq < rtiles_n; rq++)
-            for (int o = tid; o < 1024; o += 256) {
-                const int h = o >> 9, kq = (o >> 7) & 3, r = (o >> 3) & 15, t = o & 7;
-                const int il = rq * 16 + r, kl = h * 32 + kq * 8 + t;   // il: column of A, kl: row of A
-                const float x = tile[kl][il];
-                const TL hi = (TL)x;
-                const int64_t at = tiled_index(c0 + il, r0 + kl, p, KTm);
-                if constexpr (MODE != 2) Alo_t[at] = hi;
-                if constexpr (MODE != 0) Ar_t[at] = (TL)(x - (float)hi);
+        for (int q8 = tid; q8 < rtiles_n * 128; q8 += 256) {
+            const int rq = q8 >> 7, o8 = q8 & 127;
+            const int h = o8 >> 6, kq = (o8 >> 4) & 3, r = o8 & 15;
+            const int il = rq * 16 + r, kl = h * 32 + kq * 8;   // il: column of A, kl: row of A
+            V8 hi, lo;
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                const float x = tile[kl + t][il];
+                hi[t] = (TL)x;
+                lo[t] = (TL)(x - (float)hi[t]);
             }
+            const int64_t at = tiled_index(c0 + il, r0 + kl, p, KTm);
+            if constexpr (MODE != 2) *reinterpret_cast<V8*>(Alo_t + at) = hi;
+            if constexpr (MODE != 0) *reinterpret_cast<V8*>(Ar_t + at) = lo;
+        }
     }
     if (fro) {
 #pragma unroll
