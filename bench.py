@@ -48,6 +48,7 @@ LL = LK + LP
 LW = (LV // 2) * LL            # width of the Krylov stack and of the last view (even v)
 GOLDEN = os.path.join(ROOT, "tests", "golden", "config4_krylov_k128_p32_v8_seed11.json")
 PMC_FILE = os.path.join(ROOT, "profiles", "qgemm_f32_view_16384x16384x160_pmc.json")
+PMC_FILE_LOWP = os.path.join(ROOT, "profiles", "qgemm_bf16_view_16384x16384x160_pmc.json")
 TRACE_FILE = os.path.join(ROOT, "profiles", "solve_16384x16384_krylov_k128_p32_v8_trace.md")
 
 # secondary: 2048 x 2048, sigma_i = exp(-i/20) + noise, subspace k = 50, p = 10, budgets 2, 3, 4, 6
@@ -81,6 +82,10 @@ def parse():
     ap.add_argument("--trace-summary", nargs="+", metavar="FILE",
                     help="kernel trace CSV of a rocprofv3 --kernel-trace run of the default bench (then, optionally, "
                          "that run's output): writes the per-kernel summary of the headline solves under profiles/")
+    ap.add_argument("--counters-lowp", action="store_true",
+                    help="the same launch sequence with the BF16 view products (from the solve's copies of A)")
+    ap.add_argument("--pmc-summary-lowp", nargs="+", metavar="CSV",
+                    help="as --pmc-summary, for three --counters-lowp runs: writes the BF16 view's record")
     ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
                     help="FETCH_SIZE and WRITE_SIZE CSVs of two --counters runs (then optional MFMA counter "
                          "CSVs): writes the traffic record under profiles/")
@@ -132,18 +137,27 @@ COUNTER_REPS = 3
 COUNTER_OPS = ((0, LL, "forward"), (1, LL, "adjoint"))
 
 
-def counters_run(Q, torch, A):
+def counters_run(Q, torch, A, lowp=False):
     """The launch sequence the hardware counters are read on: COUNTER_REPS forward and adjoint
-    FP32 view products (16384 x 16384 by 160), then COUNTER_REPS elementwise passes over 256 MiB
-    (read once, written once) whose counter readings calibrate the scale of FETCH_SIZE and
-    WRITE_SIZE."""
+    view products (16384 x 16384 by 160; FP32, or BF16 from the solve's copies of A with lowp),
+    then COUNTER_REPS elementwise passes over 256 MiB (read once, written once) whose counter
+    readings calibrate the scale of FETCH_SIZE and WRITE_SIZE."""
     g = torch.Generator(device="cuda").manual_seed(0)
+    copies = Q.qlra_lowp_copy(A, Q.QLRA_BF16) if lowp else None
+    torch.cuda.synchronize()
     for op, w, _ in COUNTER_OPS:
         X = torch.randn((4, LN, w), device="cuda", generator=g)
-        ws = Q.qlra_qgemm_workspace(op, LN, LN, w)
+        if lowp:
+            ws = Q.qlra_qgemm_lp_workspace(op, Q.QLRA_BF16, LN, LN, w)
+        else:
+            ws = Q.qlra_qgemm_workspace(op, LN, LN, w)
         C = torch.empty((4, LN, w), device="cuda")
         for _ in range(COUNTER_REPS):
-            Q.qlra_qgemm(op, A, X, C, stream=torch.cuda.current_stream(), workspace=ws)
+            if lowp:
+                Q.qlra_qgemm_lp(op, Q.QLRA_BF16, copies[op], LN, LN, X, C, stream=torch.cuda.current_stream(),
+                                workspace=ws)
+            else:
+                Q.qlra_qgemm(op, A, X, C, stream=torch.cuda.current_stream(), workspace=ws)
             torch.cuda.synchronize()
     src = torch.ones(COPY_BYTES // 4, device="cuda")
     dst = torch.empty_like(src)
@@ -177,12 +191,14 @@ def _read_counter_csv(path):
     return out
 
 
-def pmc_summary(paths):
+def pmc_summary(paths, lowp=False):
     """Per-dispatch counters from rocprofv3 --pmc runs of --counters (CSV output): FETCH_SIZE
     and WRITE_SIZE (KiB; the elementwise pass's readings give the factor that turns each into
-    bytes), and any further counters (MFMA activity) per view kernel."""
+    bytes), and any further counters (MFMA activity) per view kernel.  lowp: the runs of
+    --counters-lowp (BF16 views), written to their own record."""
     import statistics
-    view_kernels = ("k_thin_t", "k_qview", "k_splitk_reduce")
+    view_kernels = ("k_lp_thin", "k_qgemm_lp", "k_splitk_reduce") if lowp else ("k_thin_t", "k_qview", "k_splitk_reduce")
+    product = "k_qgemm_lp" if lowp else "k_qview"
     out = {}
     extra = {}
     for path in paths:
@@ -203,7 +219,7 @@ def pmc_summary(paths):
             else:
                 per_op, dur_op = {}, {}
                 for i, (_, w, name) in enumerate(COUNTER_OPS):
-                    part = [(n, v, t) for n, v, t in view[i * nper:(i + 1) * nper] if "k_qview" in n]
+                    part = [(n, v, t) for n, v, t in view[i * nper:(i + 1) * nper] if product in n]
                     per_op[name] = round(sum(v for _, v, _ in part) / max(1, len(part)), 1)
                     dur_op[name] = round(sum(t for _, _, t in part) / max(1, len(part)))
                 extra[counter] = {"per_product_kernel_launch": per_op, "duration_ns": dur_op}
@@ -220,27 +236,34 @@ def pmc_summary(paths):
             dur = extra["GRBM_GUI_ACTIVE"]["duration_ns"][name]
             rec_op = {"mfma_busy_frac": round(busy / (act * SIMDS), 4), "active_cycles_per_xcd": round(act),
                       "dispatch_ns": dur, "implied_clock_ghz": round(act / dur, 3) if dur else None}
-            if "SQ_INSTS_VALU_MFMA_MOPS_F32" in extra:
-                fl = 512.0 * extra["SQ_INSTS_VALU_MFMA_MOPS_F32"]["per_product_kernel_launch"][name]
-                rec_op["mfma_f32_flops"] = fl
+            mops = "SQ_INSTS_VALU_MFMA_MOPS_BF16" if lowp else "SQ_INSTS_VALU_MFMA_MOPS_F32"
+            if mops in extra:
+                fl = 512.0 * extra[mops]["per_product_kernel_launch"][name]
+                rec_op["mfma_flops"] = fl
                 rec_op["mfma_flops_over_algorithmic"] = round(fl / (32.0 * LN * LN * w), 4)
+            if dur:
+                rec_op["tflops_at_dispatch_duration"] = round(32.0 * LN * LN * w / dur / 1e3, 1)
             mfma[name] = rec_op
-    rec = {"kernel": f"FP32 view product {LN}x{LN} by {LL} (the product kernel and any split-K reduction), "
+    mode, tag, mops = ("--counters-lowp", "lp", "SQ_INSTS_VALU_MFMA_MOPS_BF16") if lowp else \
+        ("--counters", "", "SQ_INSTS_VALU_MFMA_MOPS_F32")
+    what = "BF16 view product (k_lp_thin + k_qgemm_lp)" if lowp else "FP32 view product"
+    rec = {"kernel": f"{what} {LN}x{LN} by {LL} (the product kernel and any split-K reduction), "
                      "mean of A X and A^H X",
-           "commands": ["cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/"
-                        "pmc_fetch -o f -- python3 <repo>/bench.py --counters",
-                        "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/"
-                        "pmc_write -o w -- python3 <repo>/bench.py --counters",
-                        "cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES "
-                        "SQ_INSTS_VALU_MFMA_MOPS_F32 GRBM_GUI_ACTIVE --output-format csv -d <out>/pmc_mfma -o m -- "
-                        "python3 <repo>/bench.py --counters",
-                        "python bench.py --pmc-summary <out>/pmc_fetch/f_counter_collection.csv "
-                        "<out>/pmc_write/w_counter_collection.csv <out>/pmc_mfma/m_counter_collection.csv"],
+           "commands": [f"cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d <out>/"
+                        f"pmc{tag}_fetch -o f -- python3 <repo>/bench.py {mode}",
+                        f"cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d <out>/"
+                        f"pmc{tag}_write -o w -- python3 <repo>/bench.py {mode}",
+                        f"cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES "
+                        f"{mops} GRBM_GUI_ACTIVE --output-format csv -d <out>/pmc{tag}_mfma -o m -- "
+                        f"python3 <repo>/bench.py {mode}",
+                        f"python bench.py --pmc-summary{'-lowp' if lowp else ''} <out>/pmc{tag}_fetch/f_counter_collection.csv "
+                        f"<out>/pmc{tag}_write/w_counter_collection.csv <out>/pmc{tag}_mfma/m_counter_collection.csv"],
            "kernel_source_hash": kernel_source_hash(), "hbm_bytes_per_launch": round(hbm),
-           "algorithmic_bytes_per_launch": 16 * LN * LN + 2 * 16 * LN * LL, **out, "mfma": mfma,
+           "algorithmic_bytes_per_launch": (8 if lowp else 16) * LN * LN + 2 * 16 * LN * LL, **out, "mfma": mfma,
            "other_counters": extra}
-    os.makedirs(os.path.dirname(PMC_FILE), exist_ok=True)
-    json.dump(rec, open(PMC_FILE, "w"), indent=1)
+    path = PMC_FILE_LOWP if lowp else PMC_FILE
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    json.dump(rec, open(path, "w"), indent=1)
     print(json.dumps(rec))
 
 
@@ -749,6 +772,9 @@ def main():
     if args.pmc_summary:
         pmc_summary(args.pmc_summary)
         return
+    if args.pmc_summary_lowp:
+        pmc_summary(args.pmc_summary_lowp, lowp=True)
+        return
     if args.trace_summary:
         trace_summary(*args.trace_summary[:2])
         return
@@ -763,9 +789,9 @@ def main():
     if args.only_completion:
         print(json.dumps({"completion": completion(Q, torch, W)}))
         return
-    if args.counters:
+    if args.counters or args.counters_lowp:
         A, _, _, _ = headline_matrix(torch)
-        counters_run(Q, torch, A)
+        counters_run(Q, torch, A, lowp=args.counters_lowp)
         return
     res, views, kt, opt, golden, A32 = headline(Q, torch, args)
     fp = res["fp32"]

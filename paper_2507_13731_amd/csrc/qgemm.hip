@@ -937,9 +937,9 @@ Plan make_plan(const QgemmDesc& d) {
     const int64_t min_steps = 2;
     const int64_t target = d.op == OP_HN ? kGramWgPerCU * kCUs : kCUs;
     int64_t splits = 1;
-    // a tiny product (the blocked Cholesky's off-diagonal blocks) runs unsplit: its few K steps cost
-    // less than the extra launch that would sum the partial tiles
-    const bool tiny = (double)d.M * (double)d.N * (double)d.K <= 1048576.0;
+    // a tiny product with a short reduction (the blocked Cholesky's off-diagonal blocks) runs
+    // unsplit: its few K steps cost less than the extra launch that would sum the partial tiles
+    const bool tiny = d.K <= 128 && (double)d.M * (double)d.N * (double)d.K <= 1048576.0;
     if (tiles < target && !tiny) {
         splits = std::min<int64_t>((target + tiles - 1) / tiles, (d.K + min_steps * p.BK - 1) / (min_steps * p.BK));
         splits = std::max<int64_t>(splits, 1);
