@@ -13,8 +13,10 @@
 //    v'^H p and the column copies are double-buffered between launches.  Several problems of one
 //    order go in one launch (grid y), so the estimates of all views cost one launch sequence.
 //  - eigenvalues: 16 lanes per eigenvalue, the tridiagonal in LDS.
-//  - eigenvectors: only the wanted ones (the largest), one wave each, the reflectors read from
-//    the record.
+//  - eigenvectors: only the wanted ones (the largest), by twisted factorisations of the
+//    tridiagonal, then the back-transformation with the reflectors in blocks of four (compact
+//    WY form: one cross-lane sum per block instead of one per reflector), one workgroup per
+//    vector with its rows split over its four waves.
 #include <algorithm>
 
 #include "common.h"
@@ -104,6 +106,7 @@ struct BigRec {
     double* CB;     // 2 x 4 W: copy of the column of the next reflector, taken before its update
     double* X;      // W x nvec eigenvectors of T (entry i of vector t at X[i nvec + t])
     double* DM;     // W x nvec backward pivots (the same layout)
+    double* wyT;    // 16 (W + 4) doubles: the T factors of the WY blocks of the reflectors
 };
 
 __host__ __device__ inline BigRec big_rec(double* base, int64_t W, int64_t nvec) {
@@ -124,10 +127,12 @@ __host__ __device__ inline BigRec big_rec(double* base, int64_t W, int64_t nvec)
     r.CB = p; p += 8 * W;
     r.X = p; p += W * nvec;
     r.DM = p; p += W * nvec;
+    r.wyT = p; p += 16 * (W + 4);
     return r;
 }
 __host__ __device__ inline int64_t big_rec_doubles(int64_t W, int64_t nvec) {
-    return 4 * W * W + 9 * W + 8 + 4 * (W * (W + 1) / 2) + 16 * W + 2 * SRB * step_blocks(W) + 2 * W * nvec;
+    return 4 * W * W + 9 * W + 8 + 4 * (W * (W + 1) / 2) + 16 * W + 2 * SRB * step_blocks(W) + 2 * W * nvec +
+           16 * (W + 4);
 }
 
 // The reflector of a column x (entries r > j0 below the diagonal held in vn[r], zero elsewhere):
@@ -506,58 +511,172 @@ __global__ void k_big_mgs(double* __restrict__ base, int W, int nvec, int kfirst
     }
 }
 
-// back-transformation y = H_0 ... H_{W-3} D x for the nout largest eigenvalues, one wave each,
-// lane holding rows lane + 64 u (u < NR, W <= 64 NR); E (W x nout, ld nout) gets them in
-// descending order.  The reflector of the next step is loaded (into the other of two register
-// sets) while the current one is applied; rows at or above a reflector's pivot hold zeros.
-template <int NR>
-__global__ __launch_bounds__(BT) void k_big_back(double* __restrict__ base, int W, int nvec, int kfirst, int nout,
-                                                 double* __restrict__ E) {
+// Compact WY form of the back-transformation.  Block m holds reflectors 4 m .. 4 m + 3 (zero past
+// W - 3): H_{4m} H_{4m+1} H_{4m+2} H_{4m+3} = I - V T V^H with T upper triangular (quaternion
+// entries; the tau are real), built column by column: T_kk = tau_k and, above it,
+// -tau_k T (V^H v_k) from the Gram entries v_a^H v_k.  One workgroup per block.
+constexpr int WYB = 4;                         // reflectors per block
+
+__host__ __device__ inline int64_t wy_blocks(int64_t W) { return W >= 3 ? (W - 2 + WYB - 1) / WYB : 0; }
+
+__global__ __launch_bounds__(BT) void k_big_wy(double* __restrict__ base, int W, int nvec) {
+    __shared__ double red[4];
     BigRec R = big_rec(base, W, nvec);
-    const int lane = threadIdx.x & 63;
-    const int o = blockIdx.x * (BT / 64) + (threadIdx.x >> 6);   // output column
-    if (o >= nout) return;
+    const int m = blockIdx.x, j0 = WYB * m, tid = threadIdx.x;
+    const int64_t pps = (int64_t)W * (W + 1) / 2;
+    // g[a][b] = v_a^H v_b for a < b (six pairs), each thread's share over the rows
+    Q4 g[6];
+#pragma unroll
+    for (int e = 0; e < 6; e++) g[e] = Q4{0, 0, 0, 0};
+    for (int i = tid; i < W; i += BT) {
+        Q4 v[WYB];
+#pragma unroll
+        for (int a = 0; a < WYB; a++) {
+            const int j = j0 + a;
+            v[a] = (j <= W - 3 && i > j) ? ld(R.refl, pps, refl_at(W, i, j)) : Q4{0, 0, 0, 0};
+        }
+        int e = 0;
+#pragma unroll
+        for (int a = 0; a < WYB; a++)
+#pragma unroll
+            for (int b = a + 1; b < WYB; b++) g[e] = qadd(g[e], qmul(qconj(v[a]), v[b])), e++;
+    }
+#pragma unroll
+    for (int e = 0; e < 6; e++) {
+        g[e].w = block_total(g[e].w, red); g[e].x = block_total(g[e].x, red);
+        g[e].y = block_total(g[e].y, red); g[e].z = block_total(g[e].z, red);
+    }
+    if (tid != 0) return;
+    double tau[WYB];
+#pragma unroll
+    for (int a = 0; a < WYB; a++) tau[a] = j0 + a <= W - 3 ? R.tau[j0 + a] : 0.0;
+    Q4 T[WYB][WYB];
+#pragma unroll
+    for (int r = 0; r < WYB; r++)
+#pragma unroll
+        for (int c = 0; c < WYB; c++) T[r][c] = Q4{0, 0, 0, 0};
+    auto gram = [&](int a, int b) {   // v_a^H v_b, a < b
+        const int e = a == 0 ? b - 1 : (a == 1 ? b + 1 : 5);
+        return g[e];
+    };
+    T[0][0] = Q4{tau[0], 0, 0, 0};
+#pragma unroll
+    for (int k = 1; k < WYB; k++) {
+#pragma unroll
+        for (int r = 0; r < k; r++) {
+            Q4 z{0, 0, 0, 0};
+#pragma unroll
+            for (int c = r; c < k; c++) z = qadd(z, qmul(T[r][c], gram(c, k)));
+            T[r][k] = qscale(z, -tau[k]);
+        }
+        T[k][k] = Q4{tau[k], 0, 0, 0};
+    }
+    double* out = R.wyT + (int64_t)m * 4 * WYB * WYB;
+#pragma unroll
+    for (int r = 0; r < WYB; r++)
+#pragma unroll
+        for (int c = 0; c < WYB; c++) {
+            const int e = 4 * (r * WYB + c);
+            out[e] = T[r][c].w; out[e + 1] = T[r][c].x; out[e + 2] = T[r][c].y; out[e + 3] = T[r][c].z;
+        }
+}
+
+// back-transformation y = H_0 ... H_{W-3} D x for the nout largest eigenvalues by WY blocks, last
+// block first: y <- y - V (T (V^H y)).  One workgroup of BWV waves per vector, the waves holding
+// row slices of SL = 64 NRS rows (lane l of wave s: rows s SL + l + 64 u); the slices' shares of
+// V^H y and the block's T meet in LDS (double-buffered by block parity; the shares summed in
+// slice order).  The reflectors of the next block are loaded into the other register set while
+// the current block is applied.  E (W x nout, ld nout) gets the vectors in descending order.
+constexpr int BWV = 4;                          // waves per vector
+template <int NRS>
+__global__ __launch_bounds__(64 * BWV) void k_big_back_wy(double* __restrict__ base, int W, int nvec, int kfirst,
+                                                          int nout, double* __restrict__ E) {
+    constexpr int SL = 64 * NRS;
+    __shared__ double part[2][BWV][4 * WYB];
+    __shared__ double tb[2][4 * WYB * WYB];
+    BigRec R = big_rec(base, W, nvec);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int o = blockIdx.x;                                   // output column
     const int slot = W - 1 - o - kfirst;                        // ascending index W - 1 - o
     const int64_t pps = (int64_t)W * (W + 1) / 2;
-    Q4 y[NR];
+    const int nb = (int)wy_blocks(W);
+    Q4 y[NRS];
 #pragma unroll
-    for (int u = 0; u < NR; u++) {
-        const int i = lane + 64 * u;
+    for (int u = 0; u < NRS; u++) {
+        const int i = wave * SL + lane + 64 * u;
         y[u] = i < W ? qscale(Q4{R.ph[i], R.ph[W + i], R.ph[2 * W + i], R.ph[3 * W + i]},
                               R.X[(int64_t)i * nvec + slot])
                      : Q4{0, 0, 0, 0};
     }
-    auto load_v = [&](int j, Q4 (&v)[NR]) {
+    auto load_v = [&](int m, Q4 (&v)[WYB][NRS]) {
 #pragma unroll
-        for (int u = 0; u < NR; u++) {
-            const int i = lane + 64 * u;
-            v[u] = (i > j && i < W) ? ld(R.refl, pps, refl_at(W, i, j)) : Q4{0, 0, 0, 0};
+        for (int a = 0; a < WYB; a++) {
+            const int j = WYB * m + a;
+#pragma unroll
+            for (int u = 0; u < NRS; u++) {
+                const int i = wave * SL + lane + 64 * u;
+                v[a][u] = (j <= W - 3 && i > j && i < W) ? ld(R.refl, pps, refl_at(W, i, j)) : Q4{0, 0, 0, 0};
+            }
         }
     };
-    auto apply = [&](int j, const Q4 (&v)[NR]) {
-        const double tj = R.tau[j];
-        Q4 s{0, 0, 0, 0};
+    auto apply = [&](int m, const Q4 (&v)[WYB][NRS]) {
+        const int pb = m & 1;
+        if (tid < 4 * WYB * WYB) tb[pb][tid] = R.wyT[(int64_t)m * 4 * WYB * WYB + tid];
+        Q4 s[WYB];
 #pragma unroll
-        for (int u = 0; u < NR; u++) s = qadd(s, qmul(qconj(v[u]), y[u]));
-        s.w = wave_total(s.w); s.x = wave_total(s.x); s.y = wave_total(s.y); s.z = wave_total(s.z);
-        s = qscale(s, tj);
+        for (int a = 0; a < WYB; a++) {
+            s[a] = Q4{0, 0, 0, 0};
 #pragma unroll
-        for (int u = 0; u < NR; u++) y[u] = qsub(y[u], qmul(v[u], s));
+            for (int u = 0; u < NRS; u++) s[a] = qadd(s[a], qmul(qconj(v[a][u]), y[u]));
+            s[a].w = wave_total(s[a].w); s[a].x = wave_total(s[a].x);
+            s[a].y = wave_total(s[a].y); s[a].z = wave_total(s[a].z);
+        }
+        if (lane == 0)
+#pragma unroll
+            for (int a = 0; a < WYB; a++) {
+                double* q = part[pb][wave] + 4 * a;
+                q[0] = s[a].w; q[1] = s[a].x; q[2] = s[a].y; q[3] = s[a].z;
+            }
+        __syncthreads();
+        Q4 S[WYB];
+#pragma unroll
+        for (int a = 0; a < WYB; a++) {
+            S[a] = Q4{0, 0, 0, 0};
+#pragma unroll
+            for (int w = 0; w < BWV; w++) {
+                const double* q = part[pb][w] + 4 * a;
+                S[a] = qadd(S[a], Q4{q[0], q[1], q[2], q[3]});
+            }
+        }
+        Q4 U[WYB];
+#pragma unroll
+        for (int r = 0; r < WYB; r++) {
+            U[r] = Q4{0, 0, 0, 0};
+#pragma unroll
+            for (int c = r; c < WYB; c++) {
+                const double* t = tb[pb] + 4 * (r * WYB + c);
+                U[r] = qadd(U[r], qmul(Q4{t[0], t[1], t[2], t[3]}, S[c]));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < NRS; u++)
+#pragma unroll
+            for (int a = 0; a < WYB; a++) y[u] = qsub(y[u], qmul(v[a][u], U[a]));
     };
-    Q4 va[NR], vb[NR];
-    int j = W - 3;
-    if (j >= 0) load_v(j, va);
-    for (; j >= 1; j -= 2) {
-        load_v(j - 1, vb);
-        apply(j, va);
-        if (j >= 2) load_v(j - 2, va);
-        apply(j - 1, vb);
+    Q4 va[WYB][NRS], vb[WYB][NRS];
+    int m = nb - 1;
+    if (m >= 0) load_v(m, va);
+    for (; m >= 1; m -= 2) {
+        load_v(m - 1, vb);
+        apply(m, va);
+        if (m >= 2) load_v(m - 2, va);
+        apply(m - 1, vb);
     }
-    if (j == 0) apply(0, va);
+    if (m == 0) apply(0, va);
     const int64_t eps = (int64_t)W * nout;
 #pragma unroll
-    for (int u = 0; u < NR; u++) {
-        const int i = lane + 64 * u;
+    for (int u = 0; u < NRS; u++) {
+        const int i = wave * SL + lane + 64 * u;
         if (i < W) st(E, eps, (int64_t)i * nout + o, y[u]);
     }
 }
@@ -618,17 +737,17 @@ hipError_t heig_big_launch(const double* G, int64_t W, double* lam, double* E, i
     hipLaunchKernelGGL(k_big_twisted, dim3((unsigned)((nvec + BT - 1) / BT)), dim3(BT), 0, st, work, (int)W,
                        (int)nvec, kfirst);
     hipLaunchKernelGGL(k_big_mgs, dim3(1), dim3(64), 0, st, work, (int)W, (int)nvec, kfirst, (int)nvec);
-    const dim3 gb((unsigned)((nout + 3) / 4));
-    if (W <= 256)
-        hipLaunchKernelGGL(k_big_back<4>, gb, dim3(BT), 0, st, work, (int)W, (int)nvec, kfirst, (int)nout, E);
-    else if (W <= 512)
-        hipLaunchKernelGGL(k_big_back<8>, gb, dim3(BT), 0, st, work, (int)W, (int)nvec, kfirst, (int)nout, E);
-    else if (W <= 640)
-        hipLaunchKernelGGL(k_big_back<10>, gb, dim3(BT), 0, st, work, (int)W, (int)nvec, kfirst, (int)nout, E);
-    else if (W <= 768)
-        hipLaunchKernelGGL(k_big_back<12>, gb, dim3(BT), 0, st, work, (int)W, (int)nvec, kfirst, (int)nout, E);
+    const int64_t nb = wy_blocks(W);
+    if (nb > 0) hipLaunchKernelGGL(k_big_wy, dim3((unsigned)nb), dim3(BT), 0, st, work, (int)W, (int)nvec);
+    const dim3 gb((unsigned)nout);
+    if (W <= 64 * BWV)
+        hipLaunchKernelGGL(k_big_back_wy<1>, gb, dim3(64 * BWV), 0, st, work, (int)W, (int)nvec, kfirst, (int)nout, E);
+    else if (W <= 128 * BWV)
+        hipLaunchKernelGGL(k_big_back_wy<2>, gb, dim3(64 * BWV), 0, st, work, (int)W, (int)nvec, kfirst, (int)nout, E);
+    else if (W <= 192 * BWV)
+        hipLaunchKernelGGL(k_big_back_wy<3>, gb, dim3(64 * BWV), 0, st, work, (int)W, (int)nvec, kfirst, (int)nout, E);
     else
-        hipLaunchKernelGGL(k_big_back<16>, gb, dim3(BT), 0, st, work, (int)W, (int)nvec, kfirst, (int)nout, E);
+        hipLaunchKernelGGL(k_big_back_wy<4>, gb, dim3(64 * BWV), 0, st, work, (int)W, (int)nvec, kfirst, (int)nout, E);
     return hipGetLastError();
 }
 
