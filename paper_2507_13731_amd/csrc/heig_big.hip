@@ -451,36 +451,66 @@ __global__ __launch_bounds__(BT) void k_big_twisted(double* __restrict__ base, i
         fp = f;
         bp = g;
     }
+    // the twist index r: the smallest |gamma_i| (the last one in descending i on ties); the loads
+    // of a chunk of TWC entries are issued together
+    constexpr int TWC = 8;
     int r = W - 1;
     double best = fabs(x[(int64_t)(W - 1) * sv]);
-    for (int i = W - 2; i >= 0; i--) {
-        const double gam = fabs(x[(int64_t)i * sv] + dm[(int64_t)i * sv] - (sd[i] - mu));
-        if (gam < best) { best = gam; r = i; }
+    for (int i0 = W - 2; i0 >= 0; i0 -= TWC) {
+        double xv[TWC], dv[TWC];
+#pragma unroll
+        for (int u = 0; u < TWC; u++) {
+            const int i = i0 - u;
+            xv[u] = i >= 0 ? x[(int64_t)i * sv] : 0.0;
+            dv[u] = i >= 0 ? dm[(int64_t)i * sv] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < TWC; u++) {
+            const int i = i0 - u;
+            if (i < 0) break;
+            const double gam = fabs(xv[u] + dv[u] - (sd[i] - mu));
+            if (gam < best) { best = gam; r = i; }
+        }
     }
-    // x_{r +- s} from x_{r +- (s - 1)}; the pivots of the next step are loaded one step ahead
+    // x_{r +- s} from x_{r +- (s - 1)}; the pivots of a chunk of TWC steps are loaded together,
+    // before the chunk overwrites the entries it read
     double xd = 1.0, xu = 1.0, nrm = 1.0;
     const int steps = max(W - 1 - r, r);
-    double dn = r + 1 < W ? dm[(int64_t)(r + 1) * sv] : 1.0;
-    double up = r - 1 >= 0 ? x[(int64_t)(r - 1) * sv] : 1.0;
-    for (int s = 1; s <= steps; s++) {
-        const int id = r + s, iu = r - s;
-        const double dcur = dn, ucur = up;
-        dn = id + 1 < W ? dm[(int64_t)(id + 1) * sv] : 1.0;
-        up = iu - 1 >= 0 ? x[(int64_t)(iu - 1) * sv] : 1.0;
-        if (id < W) {
-            xd = -fdiv(sb[id - 1] * xd, dcur);
-            x[(int64_t)id * sv] = xd;
-            nrm += xd * xd;
+    for (int s0 = 1; s0 <= steps; s0 += TWC) {
+        double dcur[TWC], ucur[TWC];
+#pragma unroll
+        for (int u = 0; u < TWC; u++) {
+            const int id = r + s0 + u, iu = r - s0 - u;
+            dcur[u] = id < W ? dm[(int64_t)id * sv] : 1.0;
+            ucur[u] = iu >= 0 ? x[(int64_t)iu * sv] : 1.0;
         }
-        if (iu >= 0) {
-            xu = -fdiv(sb[iu] * xu, ucur);
-            x[(int64_t)iu * sv] = xu;
-            nrm += xu * xu;
+#pragma unroll
+        for (int u = 0; u < TWC; u++) {
+            const int s = s0 + u;
+            if (s > steps) break;
+            const int id = r + s, iu = r - s;
+            if (id < W) {
+                xd = -fdiv(sb[id - 1] * xd, dcur[u]);
+                x[(int64_t)id * sv] = xd;
+                nrm += xd * xd;
+            }
+            if (iu >= 0) {
+                xu = -fdiv(sb[iu] * xu, ucur[u]);
+                x[(int64_t)iu * sv] = xu;
+                nrm += xu * xu;
+            }
         }
     }
     x[(int64_t)r * sv] = 1.0;
     nrm = 1.0 / sqrt(nrm);
-    for (int i = 0; i < W; i++) x[(int64_t)i * sv] *= nrm;
+    for (int i0 = 0; i0 < W; i0 += TWC) {
+        double v[TWC];
+#pragma unroll
+        for (int u = 0; u < TWC; u++) v[u] = i0 + u < W ? x[(int64_t)(i0 + u) * sv] : 0.0;
+#pragma unroll
+        for (int u = 0; u < TWC; u++)
+            if (i0 + u < W) x[(int64_t)(i0 + u) * sv] = v[u] * nrm;
+    }
 }
 
 // modified Gram-Schmidt inside clusters of close eigenvalues among the computed vectors (one wave)
