@@ -282,60 +282,35 @@ __global__ __launch_bounds__(256) void k_qgemm(KParams P) {
             }
 }
 
-// C (M x N, 4 planes) = sum over splits of the partial tiles.  Eight lanes per output entry
-// each add every eighth split in order, then the eight sums are combined in a fixed tree:
-// deterministic, and enough independent loads in flight to stream the partials.
-// sym_bm > 0 (a Hermitian Gram with square tiles of sym_bm): an entry whose tile lies below the
-// diagonal is the conjugate of its mirror entry, whose partials were computed.
+// C (M x N, 4 planes) = sum over splits of the partial tiles: one thread per output entry, the
+// splits added in order (deterministic), eight loads in flight; the threads of a wave read 64
+// consecutive entries of one partial tile.  sym_bm > 0 (a Hermitian Gram with square tiles of
+// sym_bm): only the tiles on and above the diagonal have partials; the thread of an entry in a
+// tile above the diagonal also writes its mirror, the conjugate.
 template <class T, class TC>
 __global__ __launch_bounds__(256) void k_splitk_reduce(const T* __restrict__ part, int splits, int64_t Mp, int64_t Np,
                                                        TC* __restrict__ C, int64_t ldc, int64_t cps, int64_t M,
                                                        int64_t N, int store, const int* skip, int sym_bm) {
     if (skip && *skip == 0) return;
-    const int64_t total = 4 * M * N;
-    const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
-    const int sub = threadIdx.x & 7;
-    const bool act = e < total;
-    T s = 0;
-    int64_t p = 0, r = 0, c = 0;
-    bool mirror = false;
-    if (act) {
-        p = e / (M * N);
-        const int64_t rem = e - p * M * N;
-        r = rem / N;
-        c = rem - r * N;
-        mirror = sym_bm > 0 && r / sym_bm > c / sym_bm;
-        const int64_t stride = 4 * Mp * Np;
-        const T* src = part + (p * Mp + (mirror ? c : r)) * Np + (mirror ? r : c);
-        for (int sp = sub; sp < splits; sp += 8) s += src[sp * stride];
-    }
-#pragma unroll
-    for (int o = 1; o < 8; o <<= 1) s += __shfl_xor(s, o, 64);
-    if (mirror && p != 0) s = -s;
-    if (act && sub == 0) {
-        TC* dst = C + p * cps + r * ldc + c;
-        *dst = store == ST_SUB ? (TC)((T)*dst - s) : (TC)s;
-    }
-}
-
-// Few splits (<= 8): one thread per output, the splits added in order.
-template <class T, class TC>
-__global__ __launch_bounds__(256) void k_splitk_reduce_few(const T* __restrict__ part, int splits, int64_t Mp,
-                                                           int64_t Np, TC* __restrict__ C, int64_t ldc, int64_t cps,
-                                                           int64_t M, int64_t N, int store, const int* skip,
-                                                           int sym_bm) {
-    if (skip && *skip == 0) return;
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= 4 * M * N) return;
     const int64_t p = e / (M * N), rem = e - p * M * N, r = rem / N, c = rem - r * N;
-    const bool mirror = sym_bm > 0 && r / sym_bm > c / sym_bm;
+    if (sym_bm > 0 && r / sym_bm > c / sym_bm) return;        // written by the thread of its mirror
     const int64_t stride = 4 * Mp * Np;
-    const T* src = part + (p * Mp + (mirror ? c : r)) * Np + (mirror ? r : c);
-    T s = src[0];
-    for (int sp = 1; sp < splits; sp++) s += src[sp * stride];
-    if (mirror && p != 0) s = -s;
+    const T* src = part + (p * Mp + r) * Np + c;
+    T s = 0;
+    int sp = 0;
+    for (; sp + 8 <= splits; sp += 8) {
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) v[u] = src[(int64_t)(sp + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; u++) s += v[u];
+    }
+    for (; sp < splits; sp++) s += src[(int64_t)sp * stride];
     TC* dst = C + p * cps + r * ldc + c;
     *dst = store == ST_SUB ? (TC)((T)*dst - s) : (TC)s;
+    if (sym_bm > 0 && r / sym_bm < c / sym_bm) C[p * cps + c * ldc + r] = (TC)(p ? -s : s);
 }
 
 // The same sum for FP32 partials and outputs whose rows are 16-byte aligned: one thread per
@@ -364,7 +339,7 @@ hipError_t reduce_f32(const float* part, int splits, int64_t Mp, int64_t Np, flo
         hipLaunchKernelGGL(k_splitk_reduce4, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, part, splits,
                            Mp, Np, C, ldc, cps, M, N, store, skip);
     } else {
-        const int64_t total = 8 * 4 * M * N;
+        const int64_t total = 4 * M * N;
         hipLaunchKernelGGL((k_splitk_reduce<float, float>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
                            part, splits, Mp, Np, C, ldc, cps, M, N, store, skip, 0);
     }
@@ -958,14 +933,7 @@ Plan make_plan(const QgemmDesc& d) {
 // tiles of sym_bm, the tiles below the diagonal mirrored)
 template <class T, class TC>
 hipError_t reduce_parts(const Plan& pl, const KParams& kp, int sym_bm, hipStream_t st) {
-    if (pl.splits <= 8) {
-        const int64_t total = 4 * kp.M * kp.N;
-        hipLaunchKernelGGL((k_splitk_reduce_few<T, TC>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
-                           (const T*)kp.part, (int)pl.splits, pl.Mp, pl.Np, (TC*)kp.C, kp.ldc, kp.cps, kp.M, kp.N,
-                           kp.store, kp.skip, sym_bm);
-        return hipGetLastError();
-    }
-    const int64_t total = 8 * 4 * kp.M * kp.N;
+    const int64_t total = 4 * kp.M * kp.N;
     hipLaunchKernelGGL((k_splitk_reduce<T, TC>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
                        (const T*)kp.part, (int)pl.splits, pl.Mp, pl.Np, (TC*)kp.C, kp.ldc, kp.cps, kp.M, kp.N,
                        kp.store, kp.skip, sym_bm);
