@@ -20,7 +20,6 @@ __device__ __forceinline__ Q4 qmul(Q4 a, Q4 b) {   // eq. (1)
               a.w * b.z + a.x * b.y - a.y * b.x + a.z * b.w};
 }
 __device__ __forceinline__ Q4 qconj(Q4 a) { return Q4{a.w, -a.x, -a.y, -a.z}; }
-__device__ __forceinline__ Q4 qsub(Q4 a, Q4 b) { return Q4{a.w - b.w, a.x - b.x, a.y - b.y, a.z - b.z}; }
 __device__ __forceinline__ Q4 qscale(Q4 a, double s) { return Q4{a.w * s, a.x * s, a.y * s, a.z * s}; }
 __device__ __forceinline__ double qn2(Q4 a) { return a.w * a.w + a.x * a.x + a.y * a.y + a.z * a.z; }
 __device__ __forceinline__ Q4 ld4(const double* P, int64_t ps, int64_t i) {
@@ -155,8 +154,10 @@ __device__ void chol_factor(Q4 (&g)[NB][NB], const double* __restrict__ G, int64
                 g[ri][ci] = v;
             }
         bool fail = false;
-        __syncthreads();
-        for (int j = 0; j < w; j++) {
+        // the pivot row j (the half wave that owns row j, into rowb[j & 1]) is formed during step
+        // j - 1, as soon as that half wave has updated its own row block: the other rows' updates
+        // of step j - 1 overlap it, and the wave runs at raised priority until it is done
+        auto pivot = [&](int j) {
             const int jr = j & 31, jh = j >> 5;
             double* rb = rowb[j & 1];
             if (ty == jr) {
@@ -174,7 +175,14 @@ __device__ void chol_factor(Q4 (&g)[NB][NB], const double* __restrict__ G, int64
                     chol_row_at<NB>(g, jh, j, w, tx, rb, rjj, inv);
                 }
             }
+        };
+        pivot(0);
+        for (int j = 0; j < w; j++) {
             __syncthreads();
+            double* rb = rowb[j & 1];
+            const int jn = j + 1, hn = jn >> 5;
+            const bool next_owner = (ty >> 1) == ((jn & 31) >> 1);   // uniform over the wave
+            if (next_owner) __builtin_amdgcn_s_setprio(2);
             // the pivot row's entries of this thread's rows and columns and the flag in one round
             // of LDS reads (indices stay below kRegMax; entries of rows and columns that are not
             // live are read and not used); at NB = 3 the row entries are read per row block, which
@@ -186,24 +194,32 @@ __device__ void chol_factor(Q4 (&g)[NB][NB], const double* __restrict__ G, int64
                 if constexpr (NB <= 2) rja_all[i] = qconj(ldi(rb, ty + 32 * i));
             }
             if (rb[kFlag] != 0.0) { fail = true; break; }    // uniform
+            // row blocks in ascending order: rows a <= j do nothing, so the block of row j + 1 is
+            // the first one updated; the next pivot follows it at once
 #pragma unroll
             for (int ri = 0; ri < NB; ri++) {
                 const int a = ty + 32 * ri;
-                if (a <= j || a >= w) continue;
-                Q4 rja;
-                if constexpr (NB <= 2) rja = rja_all[ri];
-                else rja = qconj(ldi(rb, a));
+                if (a > j && a < w) {
+                    Q4 rja;
+                    if constexpr (NB <= 2) rja = rja_all[ri];
+                    else rja = qconj(ldi(rb, a));
 #pragma unroll
-                for (int ci = 0; ci < NB; ci++) {
-                    if (ci < ri) continue;
-                    const int b = tx + 32 * ci;
-                    if (b < a || b >= w) continue;
-                    Q4 v = qfms(g[ri][ci], rja, rjb[ci]);
-                    if (ri == ci && a == b) v.x = v.y = v.z = 0.0;
-                    g[ri][ci] = v;
+                    for (int ci = 0; ci < NB; ci++) {
+                        if (ci < ri) continue;
+                        const int b = tx + 32 * ci;
+                        if (b < a || b >= w) continue;
+                        Q4 v = qfms(g[ri][ci], rja, rjb[ci]);
+                        if (ri == ci && a == b) v.x = v.y = v.z = 0.0;
+                        g[ri][ci] = v;
+                    }
+                }
+                if (ri == hn && jn < w) {
+                    pivot(jn);
+                    if (next_owner) __builtin_amdgcn_s_setprio(0);
                 }
             }
         }
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         if (!fail) break;
         if (!allow_shift || attempt == 1) { failed = 1; break; }
@@ -276,34 +292,21 @@ __global__ __launch_bounds__(kThreads) void k_chol_reg(const double* __restrict_
         }
 }
 
-// Cholesky and triangular inverse of order w <= 32 NB, in place inside larger matrices:
-//   G (row stride ldg, plane stride gps):  G + shift I = R^H R
-//   R into Rout and R^{-1} into Rinv (row strides ldr / ldx, plane strides rps / xps), zeros
-//   below the diagonal; with band_w > 0 the block sits at column band_off of a row band of
-//   width band_w, whose other columns (rows 0 .. w-1 of the block) are set to zero in both.
-// The factor comes from chol_factor; R's upper triangle then goes to LDS (packed by columns,
-// components side by side) and the inverse is formed by columns, each by back substitution
-// R x = e_c in one 16-lane group (column c and column w - 1 - c per group, so that every group
-// takes w + 1 steps): step t finishes x_t = acc_t / r_tt on its owner lane, broadcasts it over the
-// group, and every lane takes r_it x_t off its later rows i < t (slots i = s + 16 u).  No barrier
-// after the staging; R^{-1} is accurate to about u64 cond(R) relative, as a substitution.
-// cond_gate (if non-null) := 1 when ||R||_F ||R^{-1}||_F > cond_limit, the shift was taken or the
-// factorization failed, else 0.
+// Cholesky of order w <= 32 NB in place inside larger matrices: G (row stride ldg, plane stride
+// gps), G + shift I = R^H R, R into Rout (row stride ldr, plane stride rps) with zeros below the
+// diagonal; with band_w > 0 the block sits at column band_off of a row band of width band_w,
+// whose other columns (rows 0 .. w-1 of the block) are set to zero in Rout and in Rinv (ldx, xps),
+// the band of the inverse that k_tri_inv fills at the block's columns.  The factor comes from
+// chol_factor.
 template <int NB>
-__global__ __launch_bounds__(kThreads) void k_chol_inv(const double* __restrict__ G, int64_t ldg, int64_t gps, int w,
+__global__ __launch_bounds__(kThreads) void k_chol_fac(const double* __restrict__ G, int64_t ldg, int64_t gps, int w,
                                                         double* __restrict__ Rout, int64_t ldr, int64_t rps,
                                                         double* __restrict__ Rinv, int64_t ldx, int64_t xps,
                                                         int64_t band_off, int64_t band_w, int* status, int* shift_out,
-                                                        const int* gate, int allow_shift, double shift_scale,
-                                                        int* cond_gate, double cond_limit) {
-    constexpr int NP = 32 * NB * (32 * NB + 1) / 2;
-    constexpr int NU = 2 * NB;                       // slots per lane of a 16-lane group
+                                                        const int* gate, int allow_shift, double shift_scale) {
     __shared__ __attribute__((aligned(16))) RowBuf rowb[2];
-    __shared__ __attribute__((aligned(16))) double sR[4 * NP];
-    __shared__ double sdi[32 * NB];
-    __shared__ double s_red[kThreads / 64][2];
     if (gate && *gate == 0) return;
-    const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31, lane = tid & 63;
+    const int tid = threadIdx.x, ty = tid >> 5, tx = tid & 31;
     Q4 g[NB][NB];
     int shifted, failed;
     chol_factor<NB>(g, G, ldg, gps, w, allow_shift, shift_scale, rowb, shifted, failed);
@@ -311,7 +314,6 @@ __global__ __launch_bounds__(kThreads) void k_chol_inv(const double* __restrict_
         if (shift_out) *shift_out = shifted;
         if (failed) atomicOr(status, 2);
     }
-    double nr = 0.0;
 #pragma unroll
     for (int ri = 0; ri < NB; ri++)
 #pragma unroll
@@ -319,13 +321,7 @@ __global__ __launch_bounds__(kThreads) void k_chol_inv(const double* __restrict_
             const int a = ty + 32 * ri, b = tx + 32 * ci;
             if (a >= w || b >= w) continue;
             const bool up = ci >= ri && b >= a;
-            const Q4 v = up ? g[ri][ci] : Q4{0, 0, 0, 0};
-            st4(Rout, rps, (int64_t)a * ldr + b, v);
-            if (up) {
-                sti(sR, b * (b + 1) / 2 + a, v);          // packed by columns
-                nr += qn2(v);
-                if (a == b) sdi[a] = v.w > 0.0 ? 1.0 / v.w : 0.0;
-            }
+            st4(Rout, rps, (int64_t)a * ldr + b, up ? g[ri][ci] : Q4{0, 0, 0, 0});
         }
     // the rest of the row band
     if (band_w > 0) {
@@ -337,58 +333,73 @@ __global__ __launch_bounds__(kThreads) void k_chol_inv(const double* __restrict_
             st4(Rinv, xps, a * ldx + cb, Q4{0, 0, 0, 0});
         }
     }
+}
+
+// R^{-1} of an upper triangular R of order w <= kRegMax (row stride ldr, plane stride rps) into
+// Rinv (ldx, xps), zeros below the diagonal.  Column c = 4 blockIdx.x + (wave) is the back
+// substitution R x = e_c in one wave, whose lanes hold rows i = lane and lane + 64: step t (c down
+// to 0, the same for every lane) finishes x_t = acc_t / r_tt on lane t and reads it on every lane,
+// and the rows i < t take r_it x_t off.  No lane of a wave idles on another's column, and the
+// columns run on ceil(w / 4) workgroups.  A workgroup first stages columns 0 .. (its last column)
+// of R in LDS, packed by columns with the four components of an entry side by side.  A zero or
+// negative diagonal entry (a failed factorization) takes 0 for its reciprocal.
+__global__ __launch_bounds__(256) void k_tri_inv(const double* __restrict__ R, int64_t ldr, int64_t rps, int w,
+                                                 double* __restrict__ Rinv, int64_t ldx, int64_t xps, const int* gate) {
+    constexpr int NP = kRegMax * (kRegMax + 1) / 2;
+    __shared__ __attribute__((aligned(16))) double sR[4 * NP];
+    __shared__ double sdi[kRegMax];
+    if (gate && *gate == 0) return;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int c0 = 4 * (int)blockIdx.x;
+    const int n = (c0 + 4 < w ? c0 + 4 : w);                 // columns 0 .. n-1 of R are read
+    // consecutive threads read along a row of R; four entries per thread are in flight at once
+    for (int e0 = 0; e0 < n * n; e0 += 4 * 256) {
+        Q4 v[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int e = e0 + q * 256 + tid;
+            const int a = e / n, t = e - a * n;
+            const int64_t o = (e < n * n && t >= a) ? (int64_t)a * ldr + t : 0;
+            v[q] = Q4{R[o], R[rps + o], R[2 * rps + o], R[3 * rps + o]};
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int e = e0 + q * 256 + tid;
+            const int a = e / n, t = e - a * n;
+            if (e < n * n && t >= a) {
+                sti(sR, t * (t + 1) / 2 + a, v[q]);
+                if (t == a) sdi[a] = v[q].w > 0.0 ? 1.0 / v[q].w : 0.0;
+            }
+        }
+    }
     __syncthreads();
-    const int grp = tid >> 4, s = tid & 15;
-    double ni = 0.0;
-    if (grp < (w + 1) / 2) {
-        for (int pass = 0; pass < 2; pass++) {
-            const int c = pass == 0 ? grp : w - 1 - grp;
-            if (pass == 1 && c == grp) break;        // the middle column of an odd order
-            Q4 acc[NU];
-#pragma unroll
-            for (int u = 0; u < NU; u++) acc[u] = (s + 16 * u == c) ? Q4{1, 0, 0, 0} : Q4{0, 0, 0, 0};
-            for (int t = c; t >= 0; t--) {
-                const int ut = t >> 4, src = (lane & ~15) | (t & 15);
-                const int cb = t * (t + 1) / 2;         // column t of R: rows 0 .. t contiguous
-                Q4 v{0, 0, 0, 0};
-#pragma unroll
-                for (int u = 0; u < NU; u++)
-                    if (u == ut) v = acc[u];
-                v = qscale(v, sdi[t]);
-                const Q4 x{__shfl(v.w, src, 64), __shfl(v.x, src, 64), __shfl(v.y, src, 64), __shfl(v.z, src, 64)};
-                // only the rows above t read R (consecutive lanes, consecutive entries)
-#pragma unroll
-                for (int u = 0; u < NU; u++) {
-                    const int i = s + 16 * u;
-                    if (i < t) acc[u] = qfms(acc[u], ldi(sR, cb + i), x);
-                    else if (i == t) acc[u] = x;
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < NU; u++) {
-                const int i = s + 16 * u;
-                if (i < w) {
-                    const Q4 v = i <= c ? acc[u] : Q4{0, 0, 0, 0};
-                    st4(Rinv, xps, (int64_t)i * ldx + c, v);
-                    ni += qn2(v);
-                }
-            }
+    const int c = c0 + wave;
+    if (c >= w) return;                                      // uniform over the wave
+    Q4 acc0 = lane == c ? Q4{1, 0, 0, 0} : Q4{0, 0, 0, 0};
+    Q4 acc1 = lane + 64 == c ? Q4{1, 0, 0, 0} : Q4{0, 0, 0, 0};
+    // the LDS operands of step t - 1 are read during step t
+    const Q4 zero{0, 0, 0, 0};
+    auto col = [&](int t, int i) { return ldi(sR, t * (t + 1) / 2 + (i < t ? i : t)); };
+    double dn = sdi[c];
+    Q4 r0n = col(c, lane), r1n = c >= 64 ? col(c, lane + 64) : zero;
+    for (int t = c; t >= 0; t--) {
+        const double d = dn;
+        const Q4 r0 = r0n, r1 = r1n;
+        if (t > 0) {
+            dn = sdi[t - 1];
+            r0n = col(t - 1, lane);
+            if (t - 1 >= 64) r1n = col(t - 1, lane + 64);
         }
+        const Q4 v = qsel(t < 64, acc0, acc1);
+        const int src = t & 63;
+        const Q4 x{bcast(v.w, src) * d, bcast(v.x, src) * d, bcast(v.y, src) * d, bcast(v.z, src) * d};
+        acc0 = qsel(lane < t, qfms(acc0, r0, x), qsel(lane == t, x, acc0));
+        if (t >= 64) acc1 = qsel(lane + 64 < t, qfms(acc1, r1, x), qsel(lane + 64 == t, x, acc1));
     }
-    if (cond_gate) {
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            nr += __shfl_xor(nr, o, 64);
-            ni += __shfl_xor(ni, o, 64);
-        }
-        if (lane == 0) { s_red[tid >> 6][0] = nr; s_red[tid >> 6][1] = ni; }
-        __syncthreads();
-        if (tid == 0) {
-            double a = 0, b = 0;
-            for (int i = 0; i < kThreads / 64; i++) { a += s_red[i][0]; b += s_red[i][1]; }
-            *cond_gate = (failed || shifted || !(a * b <= cond_limit * cond_limit)) ? 1 : 0;
-        }
-    }
+    // rows past c hold zeros
+    if (lane < w) st4(Rinv, xps, (int64_t)lane * ldx + c, acc0);
+    if (lane + 64 < w) st4(Rinv, xps, (int64_t)(lane + 64) * ldx + c, acc1);
 }
 
 template <int CTRL>
@@ -572,7 +583,7 @@ __global__ __launch_bounds__(256) void k_rcopy(const double* __restrict__ src, d
 
 // ------------------------------------------------------------------------------------------
 // Pieces of the blocked factorization of orders above kRegMax (the block steps are driven from
-// the host side of the library: diagonal blocks by k_chol_inv, the rest as FP64 products).
+// the host side of the library: diagonal blocks by k_chol_fac and k_tri_inv, the rest as FP64 products).
 
 // W = G with a real diagonal, plus shift I where shift = shift_scale * trace(G) (at least 1e-300)
 // when `shifted`; nothing when gate && *gate == 0.
@@ -725,30 +736,31 @@ hipError_t flag_nonzero_launch(int* dst, const int* src, hipStream_t st) {
 
 hipError_t chol_inv_launch(const double* G, int64_t ldg, int64_t gps, int64_t w, double* R, int64_t ldr, int64_t rps,
                            double* Rinv, int64_t ldi, int64_t ips, int64_t band_off, int64_t band_w, int* status,
-                           int* shift_out, const int* gate, int allow_shift, double shift_scale, int* cond_gate,
-                           double cond_limit, hipStream_t st) {
+                           int* shift_out, const int* gate, int allow_shift, double shift_scale, hipStream_t st) {
     if (w < 1 || w > kRegMax || !R || !Rinv || (band_w > 0 && (band_off < 0 || band_off + w > band_w)))
         return hipErrorInvalidValue;
     if (w <= 64)
-        hipLaunchKernelGGL(k_chol_inv<2>, dim3(1), dim3(kThreads), 0, st, G, ldg, gps, (int)w, R, ldr, rps, Rinv, ldi,
-                           ips, band_off, band_w, status, shift_out, gate, allow_shift, shift_scale, cond_gate,
-                           cond_limit);
+        hipLaunchKernelGGL(k_chol_fac<2>, dim3(1), dim3(kThreads), 0, st, G, ldg, gps, (int)w, R, ldr, rps, Rinv, ldi,
+                           ips, band_off, band_w, status, shift_out, gate, allow_shift, shift_scale);
     else
-        hipLaunchKernelGGL(k_chol_inv<3>, dim3(1), dim3(kThreads), 0, st, G, ldg, gps, (int)w, R, ldr, rps, Rinv, ldi,
-                           ips, band_off, band_w, status, shift_out, gate, allow_shift, shift_scale, cond_gate,
-                           cond_limit);
+        hipLaunchKernelGGL(k_chol_fac<3>, dim3(1), dim3(kThreads), 0, st, G, ldg, gps, (int)w, R, ldr, rps, Rinv, ldi,
+                           ips, band_off, band_w, status, shift_out, gate, allow_shift, shift_scale);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tri_inv, dim3((unsigned)((w + 3) / 4)), dim3(256), 0, st, (const double*)R, ldr, rps, (int)w,
+                       Rinv, ldi, ips, gate);
     return hipGetLastError();
 }
 
 hipError_t chol_launch(const double* G, int64_t w, double* R, double* Rinv, const double* Rprev, double* work,
                        int* status, int* shift_out, const int* gate, int allow_shift, double shift_scale,
-                       int* cond_gate, double cond_limit, hipStream_t st) {
+                       hipStream_t st) {
     if (w < 1 || w > kRegMax) return hipErrorInvalidValue;   // larger orders: the blocked factorization
     // with an earlier factor: the new factor goes to `work`, then R = work * Rprev
     double* Rnew = Rprev ? work : R;
     const int64_t ps = w * w;
     hipError_t e = chol_inv_launch(G, w, ps, w, Rnew, w, ps, Rinv ? Rinv : work + 4 * ps, w, ps, 0, 0, status,
-                                   shift_out, gate, allow_shift, shift_scale, cond_gate, cond_limit, st);
+                                   shift_out, gate, allow_shift, shift_scale, st);
     if (e != hipSuccess || !Rprev) return e;
     const int64_t n = w * w;
     hipLaunchKernelGGL(k_rmul, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, (const double*)Rnew, Rprev, R,

@@ -104,21 +104,18 @@ hipError_t omega_srht_launch(uint64_t seed, int64_t n, int64_t l, float* Om, int
 // Rout = R * Rprev (Rprev null: Rout = R) and Rinv = R^{-1} (if non-null).  If the unshifted
 // factorization breaks down and allow_shift is set, it is redone with
 // shift = shift_scale * trace(G) and *shift_out (if non-null) is set to 1 (else 0).  A failure
-// that remains ORs 2 into *status.  cond_gate (if non-null) is set to 1 when
-// ||R||_F ||R^{-1}||_F > cond_limit or the shift was needed, else 0.  If gate is non-null and
-// *gate == 0 nothing is done.  work: 8*w*w doubles (the new factor when Rprev is given, R^{-1}
-// when Rinv is null).
+// that remains ORs 2 into *status.  If gate is non-null and *gate == 0 nothing is done.  work:
+// 8*w*w doubles (the new factor when Rprev is given, R^{-1} when Rinv is null).
 hipError_t chol_launch(const double* G, int64_t w, double* Rout, double* Rinv, const double* Rprev,
                        double* work, int* status, int* shift_out, const int* gate, int allow_shift,
-                       double shift_scale, int* cond_gate, double cond_limit, hipStream_t st);
+                       double shift_scale, hipStream_t st);
 int chol_lds_max();   // chol_launch handles w <= chol_lds_max(); larger orders are factored by blocks
 // The same factorization and inverse in place inside larger matrices: G, R and Rinv with their own
 // row strides and plane strides; with band_w > 0 the w x w block sits at column band_off of a row
 // band of width band_w whose other columns are set to zero in R and Rinv (w <= chol_lds_max()).
 hipError_t chol_inv_launch(const double* G, int64_t ldg, int64_t gps, int64_t w, double* R, int64_t ldr, int64_t rps,
                            double* Rinv, int64_t ldi, int64_t ips, int64_t band_off, int64_t band_w, int* status,
-                           int* shift_out, const int* gate, int allow_shift, double shift_scale, int* cond_gate,
-                           double cond_limit, hipStream_t st);
+                           int* shift_out, const int* gate, int allow_shift, double shift_scale, hipStream_t st);
 // Pieces of the blocked factorization (each does nothing when gate && *gate == 0):
 // W = G with a real diagonal (+ shift_scale * trace(G) on it when `shifted`);
 hipError_t chol_prep_launch(const double* G, int64_t w, double* W, const int* gate, int shifted, double shift_scale,

@@ -130,7 +130,7 @@ void chol_blocked(Ctx& c, const double* G, int64_t w, double* Rout, double* Rinv
             double* Ik = Rinv + k0 * w + k0;
             if (c.live())
                 note(c, chol_inv_launch(W + k0 * w + k0, w, ps, kb, Rw + k0 * w + k0, w, ps, Ik, w, ps, k0, w, st,
-                                        nullptr, gate, 0, 0.0, nullptr, 0.0, c.st));
+                                        nullptr, gate, 0, 0.0, c.st));
             if (rest > 0) {
                 qg(c, desc(OP_HN, MATH_F64, Ik, w, ps, 1, W + k0 * w + k1, w, ps, 1, Rw + k0 * w + k1, w, ps, 1,
                            kb, rest, kb, ST_SET, gate));
@@ -243,7 +243,7 @@ void cholqr(Ctx& c, const float* Y, int64_t rows, int64_t w, int64_t ldy, int64_
                 if (c.live())
                     note(c, chol_launch(G, w, Rout, c.Rinv, rp, c.chol_work, c.status,
                                         round == 0 ? shifted : nullptr, g, round == 0 ? 1 : 0,
-                                        shift_scale(rows, w), nullptr, 0.0, c.st));
+                                        shift_scale(rows, w), c.st));
             } else {
                 chol_blocked(c, G, w, Rout, c.Rinv, rp, round == 0 ? shifted : nullptr, round == 0 ? 1 : 0,
                              shift_scale(rows, w), g);
