@@ -85,6 +85,9 @@ struct KParams {
     int sym;             // Hermitian Gram A^H A (B = A, square tiles): only tiles on or above the
                          // diagonal are computed, the others are their conjugate transposes
     int b_upper;         // B upper triangular: a column tile's reduction stops at its last column
+    int xcd;             // k_qgemm_hn on a 1-D grid of xtiles x (splits rounded up to a multiple of 8)
+    int xtiles, xgx;     // workgroups: split s on XCD s mod 8 (tiles in row-major order over xgx
+                         // columns of tiles, or the upper triangle when sym)
 };
 
 // Four consecutive elements (along the contiguous dimension) of a plane, zero outside
@@ -624,16 +627,35 @@ __global__ __launch_bounds__(256, CN <= 3 ? 2 : 1) void k_qview(VParams P) {
 // flight during the MFMAs of step s.  The signs of eq. (1) go on a negated copy of the A^H
 // fragment.  Rows past the K range and columns past M or N load zeros.
 template <bool SYM>
-__global__ __launch_bounds__(256) void k_qgemm_hn(KParams P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_qgemm_hn(KParams P) {
     if (P.skip && *P.skip == 0) return;
-    if (SYM && blockIdx.x > blockIdx.y) return;     // below the diagonal: the mirror of (y, x)
+    int bx = blockIdx.x, by = blockIdx.y, split = blockIdx.z;
+    if (P.xcd) {
+        // workgroup L is dispatched to XCD L mod 8: split 8 q + (L mod 8) takes tile (L / 8) mod
+        // xtiles, so that all the tiles of a split (one range of K rows) share one XCD's L2; the
+        // grid is rounded up to whole rounds of 8 splits, and the workgroups past the last split
+        // do nothing
+        const int L = blockIdx.x, u = L >> 3, t = u % P.xtiles;
+        split = 8 * (u / P.xtiles) + (L & 7);
+        if (split >= P.splits) return;
+        if (SYM) {
+            // t = by (by + 1) / 2 + bx, 0 <= bx <= by
+            by = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+            while (by * (by + 1) / 2 > t) by--;
+            while ((by + 1) * (by + 2) / 2 <= t) by++;
+            bx = t - by * (by + 1) / 2;
+        } else {
+            bx = t % P.xgx;
+            by = t / P.xgx;
+        }
+    }
+    if (SYM && bx > by) return;     // below the diagonal: the mirror of (by, bx)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
-    const int64_t row0 = (int64_t)blockIdx.x * 32 + wm * 16, col0 = (int64_t)blockIdx.y * 32 + wn * 16;
-    const int split = blockIdx.z;
+    const int64_t row0 = (int64_t)bx * 32 + wm * 16, col0 = (int64_t)by * 32 + wn * 16;
     const int64_t kb = (int64_t)split * P.kchunk;
     int64_t ke = P.K < kb + P.kchunk ? P.K : kb + P.kchunk;
-    if (P.b_upper && ke > (int64_t)blockIdx.y * 32 + 32) ke = (int64_t)blockIdx.y * 32 + 32;   // B(k, c) = 0 for k > c
+    if (P.b_upper && ke > (int64_t)by * 32 + 32) ke = (int64_t)by * 32 + 32;   // B(k, c) = 0 for k > c
     const float* __restrict__ A = (const float*)P.A;
     const float* __restrict__ B = (const float*)P.B;
     const int r = lane & 15, g = lane >> 4;
@@ -732,7 +754,7 @@ __global__ __launch_bounds__(256) void k_qgemm_hn(KParams P) {
                     double* dst = C + p * P.cps + rr * P.ldc + c;
                     *dst = P.store == ST_SUB ? *dst - v : v;
                     // an off-diagonal tile of a Hermitian Gram also gives (c, rr) = conj(rr, c)
-                    if (SYM && blockIdx.x < blockIdx.y) C[p * P.cps + c * P.ldc + rr] = p ? -v : v;
+                    if (SYM && bx < by) C[p * P.cps + c * P.ldc + rr] = p ? -v : v;
                 }
             }
         }
@@ -755,15 +777,18 @@ __global__ __launch_bounds__(256) void k_qgemm_hn(KParams P) {
 // per plane (element j feeds MFMA j) and B_q(k0 + 4 g + j, j0 + r) an 8-byte load.  The loads of
 // step s + 1 are in flight during the MFMAs of step s.  Rows past M and columns past N read row
 // or column 0 and are never stored; a ragged last step masks its elements.
-__global__ __launch_bounds__(256) void k_qgemm_nn(KParams P) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_qgemm_nn(KParams P) {
     if (P.skip && *P.skip == 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
-    const int64_t row0 = (int64_t)blockIdx.x * 32 + wm * 16, col0 = (int64_t)blockIdx.y * 32 + wn * 16;
+    // with a triangular right operand the column tiles further right reduce over more rows: they
+    // are dispatched first, so that the short ones fill in behind them
+    const int64_t ty = P.b_upper ? (int64_t)gridDim.y - 1 - blockIdx.y : (int64_t)blockIdx.y;
+    const int64_t row0 = (int64_t)blockIdx.x * 32 + wm * 16, col0 = ty * 32 + wn * 16;
     const int split = blockIdx.z;
     const int64_t kb = (int64_t)split * P.kchunk;
     int64_t ke = P.K < kb + P.kchunk ? P.K : kb + P.kchunk;
-    if (P.b_upper && ke > (int64_t)blockIdx.y * 32 + 32) ke = (int64_t)blockIdx.y * 32 + 32;   // B(k, c) = 0 for k > c
+    if (P.b_upper && ke > ty * 32 + 32) ke = ty * 32 + 32;   // B(k, c) = 0 for k > c
     const float* __restrict__ A = (const float*)P.A;
     const double* __restrict__ B = (const double*)P.B;
     const int r = lane & 15, g = lane >> 4;
@@ -869,6 +894,7 @@ __global__ __launch_bounds__(256) void k_qgemm_nn(KParams P) {
 struct Plan {
     int WM, WN, RM, CN, BK;
     int64_t gx, gy, splits, kchunk, Mp, Np;
+    bool xcd;   // A^H B of FP32 operands in 8 splits, each on one XCD
 };
 
 constexpr int kCUs = 256;
@@ -907,18 +933,28 @@ Plan make_plan(const QgemmDesc& d) {
     p.Np = p.gy * BN;
     // a Hermitian Gram computes the tiles on and above the diagonal only
     const int64_t tiles = is_sym_gram(d) ? p.gx * (p.gx + 1) / 2 : p.gx * p.gy;
-    // split K so that several workgroups per CU run (Gram-like products: about four, which hide
-    // the latency of one another's loads; the others about one), each over at least 2 K steps
+    // split K so that several workgroups per CU run (Gram-like products: four, which hide the
+    // latency of one another's loads, and no more, so that all of them run in the one round that
+    // the direct kernel's occupancy holds; the others about one), each over at least 2 K steps
     const int64_t min_steps = 2;
-    const int64_t target = d.op == OP_HN ? kGramWgPerCU * kCUs : kCUs;
+    const bool gram_like = d.op == OP_HN;
+    const int64_t target = gram_like ? kGramWgPerCU * kCUs : kCUs;
     int64_t splits = 1;
     // a tiny product with a short reduction (the blocked Cholesky's off-diagonal blocks) runs
     // unsplit: its few K steps cost less than the extra launch that would sum the partial tiles
     const bool tiny = d.K <= 128 && (double)d.M * (double)d.N * (double)d.K <= 1048576.0;
     if (tiles < target && !tiny) {
-        splits = std::min<int64_t>((target + tiles - 1) / tiles, (d.K + min_steps * p.BK - 1) / (min_steps * p.BK));
+        splits = std::min<int64_t>(gram_like ? target / tiles : (target + tiles - 1) / tiles,
+                                   (d.K + min_steps * p.BK - 1) / (min_steps * p.BK));
         splits = std::max<int64_t>(splits, 1);
     }
+    // the direct A^H B kernel with many output tiles and a long reduction (fewer than 8 splits by
+    // the rule above, e.g. the Gram of 640 columns): 8 splits, one per XCD, whose tiles then
+    // read the same K rows through that XCD's L2 instead of every XCD streaming all of K
+    const bool direct_hn = gram_like && !d.a_f64 && !d.b_f64 && d.c_f64;
+    const int64_t max_splits = (d.K + min_steps * p.BK - 1) / (min_steps * p.BK);
+    const bool xcd8 = direct_hn && !tiny && tiles < target && splits < 8 && max_splits >= 8;
+    if (xcd8) splits = 8;
     int64_t kchunk = (d.K + splits - 1) / splits;
     kchunk = ((kchunk + p.BK - 1) / p.BK) * p.BK;
     if (kchunk < p.BK) kchunk = p.BK;
@@ -926,6 +962,7 @@ Plan make_plan(const QgemmDesc& d) {
     if (splits < 1) splits = 1;
     p.splits = splits;
     p.kchunk = kchunk;
+    p.xcd = xcd8 && splits == 8;
     return p;
 }
 
@@ -972,8 +1009,15 @@ hipError_t launch_hn(const Plan& pl, const KParams& kp, hipStream_t st) {
     if (12 * kp.lda + kp.M >= lim || 12 * kp.ldb + kp.N >= lim)
         return launch_t<double, 2, 2, 1, 1, 16, true, float, float, double>(pl, kp, st);
     dim3 grid((unsigned)pl.gx, (unsigned)pl.gy, (unsigned)pl.splits);
-    if (kp.sym) hipLaunchKernelGGL(k_qgemm_hn<true>, grid, dim3(256), 0, st, kp);
-    else hipLaunchKernelGGL(k_qgemm_hn<false>, grid, dim3(256), 0, st, kp);
+    KParams kx = kp;
+    if (pl.xcd) {
+        kx.xcd = 1;
+        kx.xgx = (int)pl.gx;
+        kx.xtiles = (int)(kp.sym ? pl.gx * (pl.gx + 1) / 2 : pl.gx * pl.gy);
+        grid = dim3((unsigned)(kx.xtiles * ((pl.splits + 7) / 8 * 8)), 1, 1);   // past the last split: none
+    }
+    if (kp.sym) hipLaunchKernelGGL(k_qgemm_hn<true>, grid, dim3(256), 0, st, kx);
+    else hipLaunchKernelGGL(k_qgemm_hn<false>, grid, dim3(256), 0, st, kx);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || pl.splits == 1) return e;
     return reduce_parts<double, double>(pl, kp, kp.sym ? 32 : 0, st);
