@@ -589,17 +589,27 @@ double* gram_slot(const Bufs& b, const Problem& pr, int64_t l, int i) {
 // large-order solver (values only) one Gram after another.
 // The stream the estimates go to: the side stream, forked from the solve's stream, or without
 // one (a call that may create no streams) the solve's stream itself.
-hipStream_t est_stream(Ctx& c) {
+// marked: the fork point was recorded earlier by mark_fork.
+hipStream_t est_stream(Ctx& c, bool marked = false) {
     if (!c.side) return c.st;
     c.forked = true;
-    note(c, hipEventRecord(c.ev_fork, c.st));
+    if (!marked) note(c, hipEventRecord(c.ev_fork, c.st));
     note(c, hipStreamWaitEvent(c.side, c.ev_fork, 0));
     return c.side;
 }
 
-void fork_estimates(Ctx& c, const Bufs& b, const Problem& pr, int64_t l) {
+// The fork point of the batched estimates, recorded on the solve's stream where their Grams are
+// complete; the side stream's launches are enqueued after the next long main-stream kernel (the
+// last view, fork_estimates with marked set), so that the host's launches of the large-order
+// estimate solver (one per reflector) never leave the main stream's queue empty: between the
+// views the host only just keeps ahead of the GPU.
+void mark_fork(Ctx& c, const Bufs& b, const Problem& pr) {
+    if (c.live() && pr.estimate && b.Gs && c.side) note(c, hipEventRecord(c.ev_fork, c.st));
+}
+
+void fork_estimates(Ctx& c, const Bufs& b, const Problem& pr, int64_t l, bool marked = false) {
     if (!c.live() || !pr.estimate || !b.Gs) return;
-    const hipStream_t es = est_stream(c);
+    const hipStream_t es = est_stream(c, marked);
     if (l <= heig_max()) {
         note(c, estimate_batch_launch(b.Gs, 4 * l * l, l, pr.v - 2, pr.k, b.nA2, pr.pass_err + 1, b.est_work, es));
         return;
@@ -740,9 +750,10 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
         for (int i = 1; i <= pr.v; i++) {
             if (i == pr.v && gram_final) {
                 const bool merge = merged_estimates(pr, d) && b.Gs;
-                if (!merge) fork_estimates(c, b, pr, l);
+                if (!merge) mark_fork(c, b, pr);
                 const bool odd = i % 2 == 1;
                 view_product(c, pr, b, !odd, odd ? Q2cur : b.Q1, l, l, b.T, view_mode(pr, i));
+                if (!merge) fork_estimates(c, b, pr, l, true);
                 finish_gram(c, b, pr, b.T, odd ? pr.m : pr.n, odd ? Q2cur : b.Q1, l, odd ? pr.n : pr.m, l, odd, merge);
                 return;
             }
@@ -787,23 +798,27 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
         i++;
         if (i >= 2) fork_estimate(c, b, pr, R, l, i);
         stack_in(b.Q1, d.s);
-        fork_estimates(c, b, pr, l);
+        mark_fork(c, b, pr);
         orth_stack(c, b.stack, pr.m, Wk, l, b.Cbuf);
         if (Wk <= heig_big_max()) {
             view_product(c, pr, b, true, b.stack, Wk, Wk, b.T, view_mode(pr, pr.v));
+            fork_estimates(c, b, pr, l, true);
             finish_gram(c, b, pr, b.T, pr.n, b.stack, Wk, pr.m, Wk, false);
         } else {
             view(c, pr, b, true, b.stack, Wk, Wk, b.T, b.Q2, Wk, b.Rfin, 2, nullptr, view_mode(pr, pr.v));
+            fork_estimates(c, b, pr, l, true);
             finish(c, b, pr, b.Rfin, Wk, b.stack, Wk, b.Q2, Wk, true);
         }
     } else {
-        fork_estimates(c, b, pr, l);
+        mark_fork(c, b, pr);
         orth_stack(c, b.stack, pr.n, Wk, l, b.Cbuf);
         if (Wk <= heig_big_max()) {
             view_product(c, pr, b, false, b.stack, Wk, Wk, b.T, view_mode(pr, pr.v));
+            fork_estimates(c, b, pr, l, true);
             finish_gram(c, b, pr, b.T, pr.m, b.stack, Wk, pr.n, Wk, true);
         } else {
             view(c, pr, b, false, b.stack, Wk, Wk, b.T, b.Q1, Wk, b.Rfin, 2, nullptr, view_mode(pr, pr.v));
+            fork_estimates(c, b, pr, l, true);
             finish(c, b, pr, b.Rfin, Wk, b.Q1, Wk, b.stack, Wk, false);
         }
     }
