@@ -70,17 +70,22 @@ __device__ __forceinline__ double wave_total(double v) {
     v = row16_sum(v);
     return bcast(v, 0) + bcast(v, 16) + bcast(v, 32) + bcast(v, 48);
 }
-// sum over the workgroup (256 threads); every thread receives it
+// sum over a workgroup of NW waves (red: NW doubles of LDS); every thread receives it
+template <int NW = 4>
 __device__ double block_total(double v, double* red) {
     v = wave_total(v);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) red[wave] = v;
     __syncthreads();
-    return red[0] + red[1] + red[2] + red[3];
+    double t = red[0];
+#pragma unroll
+    for (int i = 1; i < NW; i++) t += red[i];
+    return t;
 }
 
 constexpr int SRB = 4;        // rows per workgroup in the tridiagonalisation (one wave each)
+constexpr int SBT = 64 * SRB; // threads of the tridiagonalisation's workgroups
 constexpr int BT = 256;
 
 __host__ __device__ inline int64_t step_blocks(int64_t W) { return (W + SRB - 1) / SRB; }
@@ -143,7 +148,7 @@ __host__ __device__ inline int64_t big_rec_doubles(int64_t W, int64_t nvec) {
 // part: this thread's share of |x|^2.
 __device__ double make_reflector(const double* vn, int W, int j0, double part, double* red, const BigRec& R, bool store,
                                  Q4& v1) {
-    const double alpha = sqrt(block_total(part, red));
+    const double alpha = sqrt(block_total<SRB>(part, red));
     const Q4 x1 = j0 + 1 < W ? Q4{vn[j0 + 1], vn[W + j0 + 1], vn[2 * W + j0 + 1], vn[3 * W + j0 + 1]}
                              : Q4{0, 0, 0, 0};
     const double ax1 = sqrt(qn2(x1));
@@ -152,7 +157,7 @@ __device__ double make_reflector(const double* vn, int W, int j0, double part, d
     v1 = qadd(x1, qscale(phi, alpha));
     if (store) {
         const int64_t pps = (int64_t)W * (W + 1) / 2;
-        for (int r = j0 + 1 + (int)threadIdx.x; r < W; r += BT)
+        for (int r = j0 + 1 + (int)threadIdx.x; r < W; r += SBT)
             st(R.refl, pps, refl_at(W, r, j0), r == j0 + 1 ? v1 : Q4{vn[r], vn[W + r], vn[2 * W + r], vn[3 * W + r]});
         if (threadIdx.x == 0) {
             R.tau[j0] = tau;
@@ -171,10 +176,10 @@ __device__ __forceinline__ Q4 refl_entry(const double* vn, int W, int c, int j0,
 // Start of the tridiagonalisation of problem blockIdx.y: copy its rows of G into the record,
 // reflector 0 from column 0 (every block), p = tau G v for its rows, its share of v^H p, and the
 // copy of column 1.  Grid (step_blocks(W), problems).
-__global__ __launch_bounds__(BT) void k_big_start(const double* __restrict__ G0, int64_t gstride, double* base0,
+__global__ __launch_bounds__(SBT) void k_big_start(const double* __restrict__ G0, int64_t gstride, double* base0,
                                                   int64_t rstride, int W, int nvec) {
     __shared__ double vn[4 * 1024];                       // W <= 1024
-    __shared__ double red[4];
+    __shared__ double red[SRB];
     const double* G = G0 + blockIdx.y * gstride;
     BigRec R = big_rec(base0 + blockIdx.y * rstride, W, nvec);
     const int64_t ps = (int64_t)W * W;
@@ -185,7 +190,7 @@ __global__ __launch_bounds__(BT) void k_big_start(const double* __restrict__ G0,
     Q4 v1{0, 0, 0, 0};
     if (refl) {
         double part = 0.0;
-        for (int r = tid; r < W; r += BT) {
+        for (int r = tid; r < W; r += SBT) {
             const Q4 x = r > 0 ? ld(G, ps, (int64_t)r * W) : Q4{0, 0, 0, 0};
             vn[r] = x.w; vn[W + r] = x.x; vn[2 * W + r] = x.y; vn[3 * W + r] = x.z;
             part += qn2(x);
@@ -222,12 +227,12 @@ __global__ __launch_bounds__(BT) void k_big_start(const double* __restrict__ G0,
 // (the copy taken before it, updated here), formed by every block; then this block's rows:
 // G <- G - v q^H - q v^H, p' = tau' G v' of the next reflector, the copy of column j + 2.
 // Grid (step_blocks(W), problems).
-__global__ __launch_bounds__(BT) void k_big_step(double* base0, int64_t rstride, int W, int nvec, int j) {
+__global__ __launch_bounds__(SBT) void k_big_step(double* base0, int64_t rstride, int W, int nvec, int j) {
     __shared__ double sh[12 * 1024];                      // W <= 1024
     double* vs = sh;            // v of reflector j
     double* qs = sh + 4 * W;    // q of reflector j
     double* vn = sh + 8 * W;    // v of reflector j + 1
-    __shared__ double red[4];
+    __shared__ double red[SRB];
     BigRec R = big_rec(base0 + blockIdx.y * rstride, W, nvec);
     const int64_t ps = (int64_t)W * W, pps = (int64_t)W * (W + 1) / 2;
     const int tid = threadIdx.x;
@@ -241,10 +246,10 @@ __global__ __launch_bounds__(BT) void k_big_step(double* base0, int64_t rstride,
     const int r = blockIdx.x * SRB + wave;
     const int nks = SRB * nbs;
     double part = 0.0;
-    for (int i = tid; i < nks; i += BT) part += R.KP[cur * nks + i];
+    for (int i = tid; i < nks; i += SBT) part += R.KP[cur * nks + i];
     const double tau = R.tau[j];
-    const double K = 0.5 * tau * block_total(part, red);
-    for (int c = tid; c < W; c += BT) {
+    const double K = 0.5 * tau * block_total<SRB>(part, red);
+    for (int c = tid; c < W; c += SBT) {
         Q4 v{0, 0, 0, 0}, q{0, 0, 0, 0};
         if (c > j) {
             v = ld(R.refl, pps, refl_at(W, c, j));
@@ -265,7 +270,7 @@ __global__ __launch_bounds__(BT) void k_big_step(double* base0, int64_t rstride,
         const Q4 qj{qs[j1], qs[W + j1], qs[2 * W + j1], qs[3 * W + j1]};
         const Q4 cvj = qconj(vj), cqj = qconj(qj);
         double p2 = 0.0;
-        for (int r = tid; r < W; r += BT) {
+        for (int r = tid; r < W; r += SBT) {
             Q4 x{0, 0, 0, 0};
             if (r > j1) {
                 const Q4 vr{vs[r], vs[W + r], vs[2 * W + r], vs[3 * W + r]};
@@ -728,9 +733,9 @@ __global__ void k_big_estimates(const double* __restrict__ base0, int64_t rstrid
 void tridiagonalise(const double* G, int64_t gstride, int64_t W, int nprob, double* work, int64_t rstride,
                     int64_t nvec, hipStream_t st) {
     const dim3 grid((unsigned)step_blocks(W), (unsigned)nprob);
-    hipLaunchKernelGGL(k_big_start, grid, dim3(BT), 0, st, G, gstride, work, rstride, (int)W, (int)nvec);
+    hipLaunchKernelGGL(k_big_start, grid, dim3(SBT), 0, st, G, gstride, work, rstride, (int)W, (int)nvec);
     for (int j = 0; j + 2 < W; j++)
-        hipLaunchKernelGGL(k_big_step, grid, dim3(BT), 0, st, work, rstride, (int)W, (int)nvec, j);
+        hipLaunchKernelGGL(k_big_step, grid, dim3(SBT), 0, st, work, rstride, (int)W, (int)nvec, j);
     hipLaunchKernelGGL(k_big_fin, dim3((unsigned)nprob), dim3(64), 0, st, work, rstride, (int)W, (int)nvec);
 }
 
