@@ -624,9 +624,9 @@ __global__ __launch_bounds__(256) void k_zero_f64(double* __restrict__ p, int64_
 // *gate_out = 1 when max |G - I| over the four planes of a w x w Gram exceeds tol (or is not
 // finite), else 0; always 0 when gate_in is given and *gate_in == 0.  *gate_not (if given) is
 // the opposite.  One workgroup.
-__global__ __launch_bounds__(256) void k_orth_gate(const double* __restrict__ G, int w, double tol, int* gate_out,
+__global__ __launch_bounds__(1024) void k_orth_gate(const double* __restrict__ G, int w, double tol, int* gate_out,
                                                    const int* gate_in, int* gate_not) {
-    __shared__ double red[4];
+    __shared__ double red[16];
     const int tid = threadIdx.x;
     if (gate_in && *gate_in == 0) {
         if (tid == 0) {
@@ -637,11 +637,19 @@ __global__ __launch_bounds__(256) void k_orth_gate(const double* __restrict__ G,
     }
     const int64_t ps = (int64_t)w * w;
     double mx = 0.0;
-    for (int64_t e = tid; e < ps; e += 256) {
-        const Q4 v = ld4(G, ps, e);
-        const double d = (e / w == e % w) ? v.w - 1.0 : v.w;
+    auto visit = [&](const Q4& v, bool diag) {
+        const double d = diag ? v.w - 1.0 : v.w;
         const double a = fmax(fmax(fabs(d), fabs(v.x)), fmax(fabs(v.y), fabs(v.z)));
         mx = (a > mx || a != a) ? a : mx;     // a NaN sticks
+    };
+    if (ps < ((int64_t)1 << 31)) {
+        // 32-bit indices (a 64-bit division per entry cost more than the loads)
+        for (int e = tid; e < (int)ps; e += 1024) {
+            const int r = e / w;
+            visit(ld4(G, ps, e), e == r * w + r);
+        }
+    } else {
+        for (int64_t e = tid; e < ps; e += 1024) visit(ld4(G, ps, e), e / w == e % w);
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -652,7 +660,7 @@ __global__ __launch_bounds__(256) void k_orth_gate(const double* __restrict__ G,
     __syncthreads();
     if (tid == 0) {
         double m = red[0];
-        for (int i = 1; i < 4; i++) m = (red[i] > m || red[i] != red[i]) ? red[i] : m;
+        for (int i = 1; i < 16; i++) m = (red[i] > m || red[i] != red[i]) ? red[i] : m;
         *gate_out = (m <= tol) ? 0 : 1;
         if (gate_not) *gate_not = (m <= tol) ? 1 : 0;
     }
@@ -725,7 +733,7 @@ hipError_t zero_f64_launch(double* p, int64_t count, const int* gate, hipStream_
 hipError_t orth_gate_launch(const double* G, int64_t w, double tol, int* gate_out, const int* gate_in,
                             hipStream_t st, int* gate_not) {
     if (w < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_orth_gate, dim3(1), dim3(256), 0, st, G, (int)w, tol, gate_out, gate_in, gate_not);
+    hipLaunchKernelGGL(k_orth_gate, dim3(1), dim3(1024), 0, st, G, (int)w, tol, gate_out, gate_in, gate_not);
     return hipGetLastError();
 }
 

@@ -589,7 +589,7 @@ double* gram_slot(const Bufs& b, const Problem& pr, int64_t l, int i) {
 // large-order solver (values only) one Gram after another.
 // The stream the estimates go to: the side stream, forked from the solve's stream, or without
 // one (a call that may create no streams) the solve's stream itself.
-// marked: the fork point was recorded earlier by mark_fork.
+// marked: the fork point was recorded earlier (fork_point).
 hipStream_t est_stream(Ctx& c, bool marked = false) {
     if (!c.side) return c.st;
     c.forked = true;
@@ -598,14 +598,6 @@ hipStream_t est_stream(Ctx& c, bool marked = false) {
     return c.side;
 }
 
-// The fork point of the batched estimates, recorded on the solve's stream where their Grams are
-// complete; the side stream's launches are enqueued after the next long main-stream kernel (the
-// last view, fork_estimates with marked set), so that the host's launches of the large-order
-// estimate solver (one per reflector) never leave the main stream's queue empty: between the
-// views the host only just keeps ahead of the GPU.
-void mark_fork(Ctx& c, const Bufs& b, const Problem& pr) {
-    if (c.live() && pr.estimate && b.Gs && c.side) note(c, hipEventRecord(c.ev_fork, c.st));
-}
 
 void fork_estimates(Ctx& c, const Bufs& b, const Problem& pr, int64_t l, bool marked = false) {
     if (!c.live() || !pr.estimate || !b.Gs) return;
@@ -615,6 +607,27 @@ void fork_estimates(Ctx& c, const Bufs& b, const Problem& pr, int64_t l, bool ma
         return;
     }
     note(c, heig_big_estimates_launch(b.Gs, 4 * l * l, l, pr.v - 2, pr.k, b.nA2, pr.pass_err + 1, b.est_work, es));
+}
+
+// The fork point of the batched estimates, where their Grams are complete.  When one call
+// enqueues the whole solve, only the event is recorded there, and the side stream's launches are
+// enqueued after the next long main-stream kernel (the last view: fork_deferred), so that the
+// host's launches of the large-order estimate solver (one per reflector) never leave the main
+// stream's queue empty (between the views the host only just keeps ahead of the GPU).  A solve
+// enqueued one step at a time (the server) forks here, inside the step: a step is captured as a
+// graph of its own, and the side stream must wait on an event recorded in the same step.
+bool defer_fork(const Ctx& c) { return c.step_only < 0; }
+
+void fork_point(Ctx& c, const Bufs& b, const Problem& pr, int64_t l) {
+    if (!defer_fork(c)) {
+        fork_estimates(c, b, pr, l);
+        return;
+    }
+    if (c.live() && pr.estimate && b.Gs && c.side) note(c, hipEventRecord(c.ev_fork, c.st));
+}
+
+void fork_deferred(Ctx& c, const Bufs& b, const Problem& pr, int64_t l) {
+    if (defer_fork(c)) fork_estimates(c, b, pr, l, true);
 }
 
 // Side-stream estimate of view `i` (1-based) from its R (l x l), for widths above the batched
@@ -750,10 +763,10 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
         for (int i = 1; i <= pr.v; i++) {
             if (i == pr.v && gram_final) {
                 const bool merge = merged_estimates(pr, d) && b.Gs;
-                if (!merge) mark_fork(c, b, pr);
+                if (!merge) fork_point(c, b, pr, l);
                 const bool odd = i % 2 == 1;
                 view_product(c, pr, b, !odd, odd ? Q2cur : b.Q1, l, l, b.T, view_mode(pr, i));
-                if (!merge) fork_estimates(c, b, pr, l, true);
+                if (!merge) fork_deferred(c, b, pr, l);
                 finish_gram(c, b, pr, b.T, odd ? pr.m : pr.n, odd ? Q2cur : b.Q1, l, odd ? pr.n : pr.m, l, odd, merge);
                 return;
             }
@@ -798,27 +811,27 @@ void run_solve(Ctx& c, const Problem& pr, const Dims& d, const Bufs& b) {
         i++;
         if (i >= 2) fork_estimate(c, b, pr, R, l, i);
         stack_in(b.Q1, d.s);
-        mark_fork(c, b, pr);
+        fork_point(c, b, pr, l);
         orth_stack(c, b.stack, pr.m, Wk, l, b.Cbuf);
         if (Wk <= heig_big_max()) {
             view_product(c, pr, b, true, b.stack, Wk, Wk, b.T, view_mode(pr, pr.v));
-            fork_estimates(c, b, pr, l, true);
+            fork_deferred(c, b, pr, l);
             finish_gram(c, b, pr, b.T, pr.n, b.stack, Wk, pr.m, Wk, false);
         } else {
             view(c, pr, b, true, b.stack, Wk, Wk, b.T, b.Q2, Wk, b.Rfin, 2, nullptr, view_mode(pr, pr.v));
-            fork_estimates(c, b, pr, l, true);
+            fork_deferred(c, b, pr, l);
             finish(c, b, pr, b.Rfin, Wk, b.stack, Wk, b.Q2, Wk, true);
         }
     } else {
-        mark_fork(c, b, pr);
+        fork_point(c, b, pr, l);
         orth_stack(c, b.stack, pr.n, Wk, l, b.Cbuf);
         if (Wk <= heig_big_max()) {
             view_product(c, pr, b, false, b.stack, Wk, Wk, b.T, view_mode(pr, pr.v));
-            fork_estimates(c, b, pr, l, true);
+            fork_deferred(c, b, pr, l);
             finish_gram(c, b, pr, b.T, pr.m, b.stack, Wk, pr.n, Wk, true);
         } else {
             view(c, pr, b, false, b.stack, Wk, Wk, b.T, b.Q1, Wk, b.Rfin, 2, nullptr, view_mode(pr, pr.v));
-            fork_estimates(c, b, pr, l, true);
+            fork_deferred(c, b, pr, l);
             finish(c, b, pr, b.Rfin, Wk, b.Q1, Wk, b.stack, Wk, false);
         }
     }
