@@ -85,9 +85,8 @@ struct KParams {
     int sym;             // Hermitian Gram A^H A (B = A, square tiles): only tiles on or above the
                          // diagonal are computed, the others are their conjugate transposes
     int b_upper;         // B upper triangular: a column tile's reduction stops at its last column
-    int xcd;             // k_qgemm_hn on a 1-D grid of xtiles x (splits rounded up to a multiple of 8)
-    int xtiles, xgx;     // workgroups: split s on XCD s mod 8 (tiles in row-major order over xgx
-                         // columns of tiles, or the upper triangle when sym)
+    int xcd;             // Hermitian Gram in k_qgemm_hn on a 1-D grid of xtiles upper tiles x (splits
+    int xtiles;          // rounded up to a multiple of 8) workgroups: split s on XCD s mod 8
 };
 
 // Four consecutive elements (along the contiguous dimension) of a plane, zero outside
@@ -630,24 +629,19 @@ template <bool SYM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_qgemm_hn(KParams P) {
     if (P.skip && *P.skip == 0) return;
     int bx = blockIdx.x, by = blockIdx.y, split = blockIdx.z;
-    if (P.xcd) {
-        // workgroup L is dispatched to XCD L mod 8: split 8 q + (L mod 8) takes tile (L / 8) mod
-        // xtiles, so that all the tiles of a split (one range of K rows) share one XCD's L2; the
-        // grid is rounded up to whole rounds of 8 splits, and the workgroups past the last split
-        // do nothing
+    if (SYM && P.xcd) {
+        // workgroup L is dispatched to XCD L mod 8: split 8 q + (L mod 8) takes upper tile
+        // t = (L / 8) mod xtiles, so that all the tiles of a split (one range of K rows) share one
+        // XCD's L2; the grid is rounded up to whole rounds of 8 splits, and the workgroups past
+        // the last split do nothing
         const int L = blockIdx.x, u = L >> 3, t = u % P.xtiles;
         split = 8 * (u / P.xtiles) + (L & 7);
         if (split >= P.splits) return;
-        if (SYM) {
-            // t = by (by + 1) / 2 + bx, 0 <= bx <= by
-            by = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
-            while (by * (by + 1) / 2 > t) by--;
-            while ((by + 1) * (by + 2) / 2 <= t) by++;
-            bx = t - by * (by + 1) / 2;
-        } else {
-            bx = t % P.xgx;
-            by = t / P.xgx;
-        }
+        // t = by (by + 1) / 2 + bx, 0 <= bx <= by
+        by = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+        while (by * (by + 1) / 2 > t) by--;
+        while ((by + 1) * (by + 2) / 2 <= t) by++;
+        bx = t - by * (by + 1) / 2;
     }
     if (SYM && bx > by) return;     // below the diagonal: the mirror of (by, bx)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -894,7 +888,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) voi
 struct Plan {
     int WM, WN, RM, CN, BK;
     int64_t gx, gy, splits, kchunk, Mp, Np;
-    bool xcd;   // A^H B of FP32 operands in 8 splits, each on one XCD
+    bool xcd;   // Hermitian Gram of FP32 data in 8 splits, each on one XCD
 };
 
 constexpr int kCUs = 256;
@@ -948,12 +942,12 @@ Plan make_plan(const QgemmDesc& d) {
                                    (d.K + min_steps * p.BK - 1) / (min_steps * p.BK));
         splits = std::max<int64_t>(splits, 1);
     }
-    // the direct A^H B kernel with many output tiles and a long reduction (fewer than 8 splits by
-    // the rule above, e.g. the Gram of 640 columns): 8 splits, one per XCD, whose tiles then
-    // read the same K rows through that XCD's L2 instead of every XCD streaming all of K
-    const bool direct_hn = gram_like && !d.a_f64 && !d.b_f64 && d.c_f64;
+    // a Hermitian Gram of many tiles and a long reduction (fewer than 8 splits by the rule above,
+    // e.g. 640 columns) in the direct kernel: 8 splits, one per XCD, whose tiles then read the
+    // same K rows through that XCD's L2 instead of every XCD streaming all of K
+    const bool direct_gram = is_sym_gram(d) && !d.a_f64 && !d.b_f64 && d.c_f64;
     const int64_t max_splits = (d.K + min_steps * p.BK - 1) / (min_steps * p.BK);
-    const bool xcd8 = direct_hn && !tiny && tiles < target && splits < 8 && max_splits >= 8;
+    const bool xcd8 = direct_gram && !tiny && tiles < target && splits < 8 && max_splits >= 8;
     if (xcd8) splits = 8;
     int64_t kchunk = (d.K + splits - 1) / splits;
     kchunk = ((kchunk + p.BK - 1) / p.BK) * p.BK;
@@ -1010,10 +1004,9 @@ hipError_t launch_hn(const Plan& pl, const KParams& kp, hipStream_t st) {
         return launch_t<double, 2, 2, 1, 1, 16, true, float, float, double>(pl, kp, st);
     dim3 grid((unsigned)pl.gx, (unsigned)pl.gy, (unsigned)pl.splits);
     KParams kx = kp;
-    if (pl.xcd) {
+    if (pl.xcd && kp.sym) {
         kx.xcd = 1;
-        kx.xgx = (int)pl.gx;
-        kx.xtiles = (int)(kp.sym ? pl.gx * (pl.gx + 1) / 2 : pl.gx * pl.gy);
+        kx.xtiles = (int)(pl.gx * (pl.gx + 1) / 2);
         grid = dim3((unsigned)(kx.xtiles * ((pl.splits + 7) / 8 * 8)), 1, 1);   // past the last split: none
     }
     if (kp.sym) hipLaunchKernelGGL(k_qgemm_hn<true>, grid, dim3(256), 0, st, kx);

@@ -118,6 +118,27 @@ def test_cholqr_matches_householder(gq, oracle, m, w):
     np.testing.assert_allclose(qref.mul(Qg.astype(np.float64), Rg), Y, atol=1e-4 * np.abs(Y).max())
 
 
+def test_cholqr_many_tiles(gq):
+    """A Gram of 544 columns (153 upper tiles of 32: K split eight ways, one split per XCD) and its
+    blocked factorization (six diagonal blocks of 91: the inverse's last workgroup holds three
+    columns).  The QR with positive real diagonal is unique, so an orthonormal Q (FP32 level), an
+    upper triangular R with positive real diagonal and Q R = Y pin it (the oracle's QR of this
+    size takes a minute on the host)."""
+    m, w = 2048, 544
+    print(f"cholqr m={m} w={w}", flush=True)
+    rng = np.random.default_rng(m + w)
+    Y = rng.standard_normal((4, m, w)).astype(np.float32)
+    Qg, Rg = gq.qlra_cholqr(dev(Y))
+    Qg, Rg = host(Qg).astype(np.float64), host(Rg)
+    gram = qref.mul(qref.adj(Qg), Qg)
+    eye = np.zeros_like(gram); eye[0] = np.eye(w)
+    assert np.abs(gram - eye).max() < 50 * U32 * np.sqrt(m)
+    low = np.tril(np.ones((w, w), dtype=bool), -1)
+    assert np.all(Rg[:, low] == 0)
+    assert np.all(np.diag(Rg[0]) > 0) and np.all(np.diagonal(Rg[1:], axis1=1, axis2=2) == 0)
+    np.testing.assert_allclose(qref.mul(Qg, Rg), Y, atol=1e-4 * np.abs(Y).max())
+
+
 @pytest.mark.parametrize("m,w", [(600, 20), (900, 130)])
 def test_cholqr_rank_deficient_uses_shift(gq, oracle, m, w):
     """Exactly rank-deficient input: plain CholeskyQR breaks down; the shifted round and the
