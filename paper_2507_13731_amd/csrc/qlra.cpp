@@ -154,15 +154,18 @@ void chol_blocked(Ctx& c, const double* G, int64_t w, double* Rout, double* Rinv
 }
 
 // One CholeskyQR round on X (rows x w, in place), every launch gated on *gate (0: nothing done):
-// G = X^H X, G = Rx^H Rx, X = X Rx^{-1} and, when R is given, R = Rx R.  Scratch: G, R1, R2,
-// chol_work, Rinv, blk and T2.
+// G = X^H X, G = Rx^H Rx, X = X Rx^{-1} and, when R is given, R = Rx R.  allow_shift: a breakdown
+// of the factorization is retried with a shift (for orders above chol_reg_max() the retry is a
+// second set of launches, each costing a few microseconds even when its gate is closed).
+// Scratch: G, R1, R2, chol_work, Rinv, blk and T2.
 void cholqr_round_gated(Ctx& c, float* X, int64_t rows, int64_t w, int64_t ldx, int64_t xps, double* R,
-                        const int* gate) {
+                        const int* gate, int allow_shift = 1) {
     const int64_t ps = w * w;
     qg(c, desc(OP_HN, MATH_F64, X, ldx, xps, 0, X, ldx, xps, 0, c.G, w, ps, 1, w, w, rows, ST_SET, gate));
     if (w <= chol_reg_max()) {
         if (c.live()) {
-            note(c, chol_reg_launch(c.G, w, c.R1, c.chol_work, c.status, nullptr, gate, 1, shift_scale(rows, w), c.st));
+            note(c, chol_reg_launch(c.G, w, c.R1, c.chol_work, c.status, nullptr, gate, allow_shift, shift_scale(rows, w),
+                                    c.st));
             note(c, trsm_launch(X, ldx, xps, X, ldx, xps, c.chol_work, w, rows, gate, c.st));
             if (R) {
                 note(c, rmul_launch(c.R1, R, c.R2, w, gate, c.st));
@@ -171,7 +174,7 @@ void cholqr_round_gated(Ctx& c, float* X, int64_t rows, int64_t w, int64_t ldx, 
         }
         return;
     }
-    chol_blocked(c, c.G, w, c.R1, c.Rinv, R, nullptr, 1, shift_scale(rows, w), gate);
+    chol_blocked(c, c.G, w, c.R1, c.Rinv, R, nullptr, allow_shift, shift_scale(rows, w), gate);
     QgemmDesc ap = desc(OP_NN, MATH_F64, X, ldx, xps, 0, c.Rinv, w, ps, 1, c.T2, w, rows * w, 0, rows, w, w, ST_SET, gate);
     ap.b_upper = 1;                            // R^{-1} is upper triangular
     qg(c, ap);
@@ -262,7 +265,9 @@ void cholqr(Ctx& c, const float* Y, int64_t rows, int64_t w, int64_t ldy, int64_
     // and gated on the device by the shift flag (its launches do nothing when it is 0), brings
     // the loss of orthogonality to about u64 cond^2 (shifted CholeskyQR followed by CholeskyQR,
     // three rounds in all for the two-round calls as in Fukaya et al. 2020).
-    if (shifted || c.dry) cholqr_round_gated(c, Q, rows, w, ldq, qps, R, shifted);
+    // That round's Gram has a condition number of at most about 1e10, far from a breakdown in
+    // FP64, so it takes no shifted retry (a failure still sets the status flag).
+    if (shifted || c.dry) cholqr_round_gated(c, Q, rows, w, ldq, qps, R, shifted, 0);
 }
 
 // A returned factor of the final QSVD from the Gram (rows x k, in place): the Y side Y E_k S^{-1}
