@@ -288,7 +288,9 @@ void cholqr(Ctx& c, const float* Y, int64_t rows, int64_t w, int64_t ldy, int64_
 void reorthonormalize(Ctx& c, float* X, int64_t rows, int64_t k, int64_t ldx, int64_t xps, const double* S) {
     int* gate = c.status ? c.status + 5 : nullptr;
     if (c.live()) note(c, fill_degenerate_launch(X, rows, (int)k, ldx, xps, S, gate, c.st));
-    for (int r = 0; r < 2; r++) cholqr_round_gated(c, X, rows, k, ldx, xps, nullptr, gate);
+    // no shifted retry: the factor's kept columns are orthonormal to about u32 S_0 / S_{k-1} and
+    // the filled ones are independent of them, so neither round's Gram is near a breakdown
+    for (int r = 0; r < 2; r++) cholqr_round_gated(c, X, rows, k, ldx, xps, nullptr, gate, 0);
 }
 
 // Orthonormalise the columns of a stack of blocks (rows x W, ld W) of width l: CholeskyQR2 of
