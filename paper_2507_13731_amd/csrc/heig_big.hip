@@ -110,7 +110,6 @@ struct BigRec {
     double* KP;     // 2 x SRB step_blocks(W) shares of v^H p (one per row wave)
     double* CB;     // 2 x 4 W: copy of the column of the next reflector, taken before its update
     double* X;      // W x nvec eigenvectors of T (entry i of vector t at X[i nvec + t])
-    double* DM;     // W x nvec backward pivots (the same layout)
     double* wyT;    // 16 (W + 4) doubles: the T factors of the WY blocks of the reflectors
 };
 
@@ -131,12 +130,11 @@ __host__ __device__ inline BigRec big_rec(double* base, int64_t W, int64_t nvec)
     r.KP = p; p += 2 * SRB * step_blocks(W);
     r.CB = p; p += 8 * W;
     r.X = p; p += W * nvec;
-    r.DM = p; p += W * nvec;
     r.wyT = p; p += 16 * (W + 4);
     return r;
 }
 __host__ __device__ inline int64_t big_rec_doubles(int64_t W, int64_t nvec) {
-    return 4 * W * W + 9 * W + 8 + 4 * (W * (W + 1) / 2) + 16 * W + 2 * SRB * step_blocks(W) + 2 * W * nvec +
+    return 4 * W * W + 9 * W + 8 + 4 * (W * (W + 1) / 2) + 16 * W + 2 * SRB * step_blocks(W) + W * nvec +
            16 * (W + 4);
 }
 
@@ -419,13 +417,21 @@ __device__ __forceinline__ double fdiv(double x, double y) {
 
 // eigenvectors of T for the ascending indices [c0, W) (c0 = W - nvec extended down to the start
 // of its cluster, computed on the host side of the launch by every block alike): twisted
-// factorisations, one thread each.  The tridiagonal is staged in LDS; vector t's entry i sits at
-// X[i nvec + t] (and its backward pivots at DM[i nvec + t]), so that the threads' accesses of a
-// step are one coalesced run.
-__global__ __launch_bounds__(BT) void k_big_twisted(double* __restrict__ base, int W, int nvec, int kfirst) {
-    __shared__ double sd[1024], sb[1024], sb2[1024];    // W <= 1024
+// factorisations, one workgroup of one wave per vector, with the tridiagonal, the forward and
+// backward pivots and the vector in LDS.  The two recurrences (the pivots, then the vector
+// outward from the twist index) run on lane 0 in their serial order; the twist search and the
+// normalisation are spread over the wave.  Vector t's entry i goes to X[i nvec + t].
+__global__ __launch_bounds__(64) void k_big_twisted(double* __restrict__ base, int W, int nvec, int kfirst) {
+    extern __shared__ double tw[];
+    double* sd = tw;                 // W each: d, b, b^2, forward pivots / the vector, backward pivots
+    double* sb = tw + W;
+    double* sb2 = tw + 2 * W;
+    double* xs = tw + 3 * W;
+    double* ds = tw + 4 * W;
     BigRec R = big_rec(base, W, nvec);
-    for (int i = threadIdx.x; i < W; i += BT) {
+    const int t = blockIdx.x, k = kfirst + t, lane = threadIdx.x;
+    if (t >= nvec || k >= W) return;                   // uniform over the workgroup
+    for (int i = lane; i < W; i += 64) {
         sd[i] = R.d[i];
         sb[i] = R.b[i];
         sb2[i] = R.b2[i];
@@ -433,89 +439,68 @@ __global__ __launch_bounds__(BT) void k_big_twisted(double* __restrict__ base, i
     __syncthreads();
     const double tnorm = fmax(fabs(R.bnd[0]), fabs(R.bnd[1])) + 1e-300;
     const double tiny = 1e-300 + 2.220446049250313e-16 * tnorm * 1e-3;
-    const int t = blockIdx.x * BT + threadIdx.x;     // vector slot
-    const int k = kfirst + t;
-    if (t >= nvec || k >= W) return;
     const double mu = R.lam[k];
-    double* x = R.X + t;
-    double* dm = R.DM + t;
-    const int64_t sv = nvec;                         // stride between entries of one vector
-    double fp = sd[0] - mu, bp = sd[W - 1] - mu;
-    if (fabs(fp) < tiny) fp = -tiny;
-    if (fabs(bp) < tiny) bp = -tiny;
-    x[0] = fp;
-    dm[(int64_t)(W - 1) * sv] = bp;
-    for (int i = 1; i < W; i++) {
-        const int ib = W - 1 - i;
-        double f = (sd[i] - mu) - fdiv(sb2[i - 1], fp);
-        double g = (sd[ib] - mu) - fdiv(sb2[ib], bp);
-        if (fabs(f) < tiny) f = -tiny;
-        if (fabs(g) < tiny) g = -tiny;
-        x[(int64_t)i * sv] = f;
-        dm[(int64_t)ib * sv] = g;
-        fp = f;
-        bp = g;
-    }
-    // the twist index r: the smallest |gamma_i| (the last one in descending i on ties); the loads
-    // of a chunk of TWC entries are issued together
-    constexpr int TWC = 8;
-    int r = W - 1;
-    double best = fabs(x[(int64_t)(W - 1) * sv]);
-    for (int i0 = W - 2; i0 >= 0; i0 -= TWC) {
-        double xv[TWC], dv[TWC];
-#pragma unroll
-        for (int u = 0; u < TWC; u++) {
-            const int i = i0 - u;
-            xv[u] = i >= 0 ? x[(int64_t)i * sv] : 0.0;
-            dv[u] = i >= 0 ? dm[(int64_t)i * sv] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < TWC; u++) {
-            const int i = i0 - u;
-            if (i < 0) break;
-            const double gam = fabs(xv[u] + dv[u] - (sd[i] - mu));
-            if (gam < best) { best = gam; r = i; }
+    if (lane == 0) {
+        double fp = sd[0] - mu, bp = sd[W - 1] - mu;
+        if (fabs(fp) < tiny) fp = -tiny;
+        if (fabs(bp) < tiny) bp = -tiny;
+        xs[0] = fp;
+        ds[W - 1] = bp;
+        for (int i = 1; i < W; i++) {
+            const int ib = W - 1 - i;
+            double f = (sd[i] - mu) - fdiv(sb2[i - 1], fp);
+            double g = (sd[ib] - mu) - fdiv(sb2[ib], bp);
+            if (fabs(f) < tiny) f = -tiny;
+            if (fabs(g) < tiny) g = -tiny;
+            xs[i] = f;
+            ds[ib] = g;
+            fp = f;
+            bp = g;
         }
     }
-    // x_{r +- s} from x_{r +- (s - 1)}; the pivots of a chunk of TWC steps are loaded together,
-    // before the chunk overwrites the entries it read
-    double xd = 1.0, xu = 1.0, nrm = 1.0;
-    const int steps = max(W - 1 - r, r);
-    for (int s0 = 1; s0 <= steps; s0 += TWC) {
-        double dcur[TWC], ucur[TWC];
+    __syncthreads();
+    // the twist index r: the smallest |gamma_i| = |x_i + dm_i - (d_i - mu)| (|x_{W-1}| for the
+    // last), the largest i on ties; a non-finite gamma_{W-1} keeps r = W - 1 (the serial scan
+    // downwards from W - 1 with a strict comparison)
+    double best = __builtin_inf();
+    int r = -1;
+    for (int i = W - 1 - lane; i >= 0; i -= 64) {
+        const double gam = i == W - 1 ? fabs(xs[i]) : fabs(xs[i] + ds[i] - (sd[i] - mu));
+        if (gam < best) { best = gam; r = i; }          // descending i: ties keep the larger i
+    }
 #pragma unroll
-        for (int u = 0; u < TWC; u++) {
-            const int id = r + s0 + u, iu = r - s0 - u;
-            dcur[u] = id < W ? dm[(int64_t)id * sv] : 1.0;
-            ucur[u] = iu >= 0 ? x[(int64_t)iu * sv] : 1.0;
-        }
-#pragma unroll
-        for (int u = 0; u < TWC; u++) {
-            const int s = s0 + u;
-            if (s > steps) break;
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int orr = __shfl_xor(r, o, 64);
+        if (ob < best || (ob == best && orr > r)) { best = ob; r = orr; }
+    }
+    const double g_last = fabs(xs[W - 1]);
+    if (!(g_last == g_last) || r < 0) r = W - 1;
+    // x_{r +- s} from x_{r +- (s - 1)}, overwriting the forward pivots as they are used
+    __shared__ double nrm_sh;
+    if (lane == 0) {
+        double xd = 1.0, xu = 1.0, nrm = 1.0;
+        const int steps = max(W - 1 - r, r);
+        for (int s = 1; s <= steps; s++) {
             const int id = r + s, iu = r - s;
             if (id < W) {
-                xd = -fdiv(sb[id - 1] * xd, dcur[u]);
-                x[(int64_t)id * sv] = xd;
+                xd = -fdiv(sb[id - 1] * xd, ds[id]);
+                xs[id] = xd;
                 nrm += xd * xd;
             }
             if (iu >= 0) {
-                xu = -fdiv(sb[iu] * xu, ucur[u]);
-                x[(int64_t)iu * sv] = xu;
+                xu = -fdiv(sb[iu] * xu, xs[iu]);
+                xs[iu] = xu;
                 nrm += xu * xu;
             }
         }
+        xs[r] = 1.0;
+        nrm_sh = 1.0 / sqrt(nrm);
     }
-    x[(int64_t)r * sv] = 1.0;
-    nrm = 1.0 / sqrt(nrm);
-    for (int i0 = 0; i0 < W; i0 += TWC) {
-        double v[TWC];
-#pragma unroll
-        for (int u = 0; u < TWC; u++) v[u] = i0 + u < W ? x[(int64_t)(i0 + u) * sv] : 0.0;
-#pragma unroll
-        for (int u = 0; u < TWC; u++)
-            if (i0 + u < W) x[(int64_t)(i0 + u) * sv] = v[u] * nrm;
-    }
+    __syncthreads();
+    const double nrm = nrm_sh;
+    double* x = R.X + t;
+    for (int i = lane; i < W; i += 64) x[(int64_t)i * nvec] = xs[i] * nrm;
 }
 
 // modified Gram-Schmidt inside clusters of close eigenvalues among the computed vectors (one wave)
@@ -769,8 +754,8 @@ hipError_t heig_big_launch(const double* G, int64_t W, double* lam, double* E, i
     if (!E || nout == 0) return hipGetLastError();
     // vectors of ascending indices [W - nvec, W): the top nout plus room below for a cluster
     const int kfirst = (int)(W - nvec);
-    hipLaunchKernelGGL(k_big_twisted, dim3((unsigned)((nvec + BT - 1) / BT)), dim3(BT), 0, st, work, (int)W,
-                       (int)nvec, kfirst);
+    hipLaunchKernelGGL(k_big_twisted, dim3((unsigned)nvec), dim3(64), (size_t)(5 * W * sizeof(double)), st, work,
+                       (int)W, (int)nvec, kfirst);
     hipLaunchKernelGGL(k_big_mgs, dim3(1), dim3(64), 0, st, work, (int)W, (int)nvec, kfirst, (int)nvec);
     const int64_t nb = wy_blocks(W);
     if (nb > 0) hipLaunchKernelGGL(k_big_wy, dim3((unsigned)nb), dim3(BT), 0, st, work, (int)W, (int)nvec);
