@@ -371,7 +371,8 @@ __device__ int sturm_lds(const double* d, const double* b2, int W, double x) {
     return cnt;
 }
 
-// eigenvalues: grid (ceil(W / 16), problems), 16 lanes per eigenvalue, 17-section rounds;
+// eigenvalues: grid (ceil(W / 4), problems), one wave per eigenvalue, 65-section rounds (six bits
+// of the interval a round, ten rounds: a width of 65^-10 of the Gershgorin bounds, about 7e-19);
 // lam_out (problem 0 only) descending
 __global__ __launch_bounds__(BT) void k_big_eigvals(double* __restrict__ base0, int64_t rstride, int W, int nvec,
                                                     double* __restrict__ lam_out) {
@@ -380,7 +381,7 @@ __global__ __launch_bounds__(BT) void k_big_eigvals(double* __restrict__ base0, 
     double* b2 = sh + W;
     BigRec R = big_rec(base0 + blockIdx.y * rstride, W, nvec);
     if (blockIdx.y != 0) lam_out = nullptr;
-    const int tid = threadIdx.x, lane = tid & 63, s16 = tid & 15;
+    const int tid = threadIdx.x, lane = tid & 63;
     int ex;
     frexp(fmax(fabs(R.bnd[0]), fabs(R.bnd[1])), &ex);
     for (int i = tid; i < W; i += BT) {
@@ -388,20 +389,19 @@ __global__ __launch_bounds__(BT) void k_big_eigvals(double* __restrict__ base0, 
         b2[i] = ldexp(R.b2[i], -2 * ex);
     }
     __syncthreads();
-    const int k = blockIdx.x * 16 + (tid >> 4);
+    const int k = blockIdx.x * (BT / 64) + (tid >> 6);
     double a = ldexp(R.bnd[0], -ex), bb = ldexp(R.bnd[1], -ex);
-    for (int round = 0; round < 14; round++) {
-        const double x = a + (bb - a) * (double)(s16 + 1) / 17.0;
+    for (int round = 0; round < 10; round++) {
+        const double x = a + (bb - a) * (double)(lane + 1) / 65.0;
         const int c = sturm_lds(d, b2, W, x);
         const unsigned long long m = __ballot(c > k);
-        const unsigned grp = (unsigned)((m >> (lane & ~15)) & 0xFFFFull);
-        const int first = grp ? __builtin_ctz(grp) : 16;
-        const double xa = first == 0 ? a : a + (bb - a) * (double)first / 17.0;
-        const double xb = first == 16 ? bb : a + (bb - a) * (double)(first + 1) / 17.0;
+        const int first = m ? __builtin_ctzll(m) : 64;
+        const double xa = first == 0 ? a : a + (bb - a) * (double)first / 65.0;
+        const double xb = first == 64 ? bb : a + (bb - a) * (double)(first + 1) / 65.0;
         a = xa;
         bb = xb;
     }
-    if (k < W && s16 == 0) {
+    if (k < W && lane == 0) {
         const double lam = ldexp(0.5 * (a + bb), ex);
         R.lam[k] = lam;
         if (lam_out) lam_out[W - 1 - k] = lam;
@@ -733,7 +733,7 @@ hipError_t heig_big_estimates_launch(const double* G, int64_t gstride, int64_t W
     if (W < 1 || W > heig_big_max() || nprob < 1) return hipErrorInvalidValue;
     const int64_t rstride = big_rec_doubles(W, 0);
     tridiagonalise(G, gstride, W, nprob, work, rstride, 0, st);
-    hipLaunchKernelGGL(k_big_eigvals, dim3((unsigned)((W + 15) / 16), (unsigned)nprob), dim3(BT),
+    hipLaunchKernelGGL(k_big_eigvals, dim3((unsigned)((W + 3) / 4), (unsigned)nprob), dim3(BT),
                        (size_t)(2 * W * sizeof(double)), st, work, rstride, (int)W, 0, (double*)nullptr);
     hipLaunchKernelGGL(k_big_estimates, dim3((unsigned)((nprob + 63) / 64)), dim3(64), 0, st, (const double*)work,
                        rstride, (int)W, nprob, k, nA2, e);
@@ -749,7 +749,7 @@ hipError_t heig_big_launch(const double* G, int64_t W, double* lam, double* E, i
                            int64_t nvec, hipStream_t st) {
     if (W < 1 || W > heig_big_max() || nout < 0 || nout > W || (E && nvec < nout)) return hipErrorInvalidValue;
     tridiagonalise(G, 0, W, 1, work, 0, nvec, st);
-    hipLaunchKernelGGL(k_big_eigvals, dim3((unsigned)((W + 15) / 16), 1), dim3(BT), (size_t)(2 * W * sizeof(double)),
+    hipLaunchKernelGGL(k_big_eigvals, dim3((unsigned)((W + 3) / 4), 1), dim3(BT), (size_t)(2 * W * sizeof(double)),
                        st, work, (int64_t)0, (int)W, (int)nvec, lam);
     if (!E || nout == 0) return hipGetLastError();
     // vectors of ascending indices [W - nvec, W): the top nout plus room below for a cluster
