@@ -308,44 +308,60 @@ __global__ __launch_bounds__(SBT) void k_big_step(double* base0, int64_t rstride
 }
 
 // diagonal, real subdiagonal b_j = |s_j|, phases ph_{j+1} = s_j ph_j / |s_j|, bounds (problem
-// blockIdx.x): the diagonal of the working matrix and the s_j are first staged in LDS by the
-// whole wave (independent loads), then one lane runs the chain of phases from LDS.
+// blockIdx.x): the diagonal of the working matrix and the s_j are staged in LDS by the whole wave
+// (independent loads), which also forms b_j, 1 / b_j and the Gershgorin bounds and writes d, b
+// and b^2; one lane runs only the chain of phases, into LDS, and the wave writes them out.
 __global__ __launch_bounds__(64) void k_big_fin(double* __restrict__ base0, int64_t rstride, int W, int nvec) {
-    __shared__ double sd[1024], ss[4 * 1024];          // W <= 1024
+    __shared__ double sd[1024], ss[4 * 1024], sbr[1024], sinv[1024], sph[4 * 1024];   // W <= 1024
     BigRec R = big_rec(base0 + blockIdx.x * rstride, W, nvec);
     const int64_t ps = (int64_t)W * W;
-    for (int i = threadIdx.x; i < W; i += 64) {
+    const int lane = threadIdx.x;
+    for (int i = lane; i < W; i += 64) {
         sd[i] = R.Gw[(int64_t)i * W + i];
         Q4 sj{0, 0, 0, 0};
         if (i + 2 < W) sj = Q4{R.ph[i], R.ph[W + i], R.ph[2 * W + i], R.ph[3 * W + i]};
         else if (i + 2 == W) sj = ld(R.Gw, ps, (int64_t)(W - 1) * W + (W - 2));   // the last subdiagonal entry
         ss[i] = sj.w; ss[W + i] = sj.x; ss[2 * W + i] = sj.y; ss[3 * W + i] = sj.z;
+        const double br = i + 1 < W ? sqrt(qn2(sj)) : 0.0;
+        sbr[i] = br;
+        sinv[i] = br > 0.0 ? 1.0 / br : 0.0;
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    if (W >= 2) R.tau[W - 2] = 0.0;
-    R.tau[W - 1] = 0.0;
-    Q4 pj{1, 0, 0, 0};
-    double lo = 1e300, hi = -1e300, bl = 0.0;
-    for (int i = 0; i < W; i++) {
-        const double dd = sd[i];
+    double lo = 1e300, hi = -1e300;
+    for (int i = lane; i < W; i += 64) {
+        const double dd = sd[i], br = sbr[i], bl = i > 0 ? sbr[i - 1] : 0.0;
         R.d[i] = dd;
-        double br = 0.0;
-        R.ph[i] = pj.w; R.ph[W + i] = pj.x; R.ph[2 * W + i] = pj.y; R.ph[3 * W + i] = pj.z;
-        if (i + 1 < W) {
-            const Q4 sj{ss[i], ss[W + i], ss[2 * W + i], ss[3 * W + i]};
-            br = sqrt(qn2(sj));
-            pj = br > 0.0 ? qscale(qmul(sj, pj), 1.0 / br) : Q4{1, 0, 0, 0};
-        }
         R.b[i] = br;
         R.b2[i] = br * br;
         lo = fmin(lo, dd - bl - br);
         hi = fmax(hi, dd + bl + br);
-        bl = br;
     }
-    const double pad = 1e-14 * fmax(fabs(lo), fabs(hi)) + 1e-300;
-    R.bnd[0] = lo - pad;
-    R.bnd[1] = hi + pad;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, o, 64));
+        hi = fmax(hi, __shfl_xor(hi, o, 64));
+    }
+    if (lane == 0) {
+        if (W >= 2) R.tau[W - 2] = 0.0;
+        R.tau[W - 1] = 0.0;
+        Q4 pj{1, 0, 0, 0};
+        // unrolled: the LDS reads of several steps go out together (they do not depend on pj)
+#pragma unroll 8
+        for (int i = 0; i < W; i++) {
+            sph[i] = pj.w; sph[W + i] = pj.x; sph[2 * W + i] = pj.y; sph[3 * W + i] = pj.z;
+            if (i + 1 < W) {
+                const Q4 sj{ss[i], ss[W + i], ss[2 * W + i], ss[3 * W + i]};
+                pj = sbr[i] > 0.0 ? qscale(qmul(sj, pj), sinv[i]) : Q4{1, 0, 0, 0};
+            }
+        }
+        const double pad = 1e-14 * fmax(fabs(lo), fabs(hi)) + 1e-300;
+        R.bnd[0] = lo - pad;
+        R.bnd[1] = hi + pad;
+    }
+    __syncthreads();
+    for (int i = lane; i < W; i += 64) {
+        R.ph[i] = sph[i]; R.ph[W + i] = sph[W + i]; R.ph[2 * W + i] = sph[2 * W + i]; R.ph[3 * W + i] = sph[3 * W + i];
+    }
 }
 
 // Sturm count with the (scaled) tridiagonal in LDS
