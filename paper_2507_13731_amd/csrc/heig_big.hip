@@ -344,19 +344,49 @@ __global__ __launch_bounds__(64) void k_big_fin(double* __restrict__ base0, int6
     if (lane == 0) {
         if (W >= 2) R.tau[W - 2] = 0.0;
         R.tau[W - 1] = 0.0;
-        Q4 pj{1, 0, 0, 0};
-        // unrolled: the LDS reads of several steps go out together (they do not depend on pj)
-#pragma unroll 8
-        for (int i = 0; i < W; i++) {
-            sph[i] = pj.w; sph[W + i] = pj.x; sph[2 * W + i] = pj.y; sph[3 * W + i] = pj.z;
-            if (i + 1 < W) {
-                const Q4 sj{ss[i], ss[W + i], ss[2 * W + i], ss[3 * W + i]};
-                pj = sbr[i] > 0.0 ? qscale(qmul(sj, pj), sinv[i]) : Q4{1, 0, 0, 0};
-            }
-        }
         const double pad = 1e-14 * fmax(fabs(lo), fabs(hi)) + 1e-300;
         R.bnd[0] = lo - pad;
         R.bnd[1] = hi + pad;
+    }
+    // The phases: step i maps ph_i to ph_{i+1} = (s_i / b_i) ph_i, or to 1 where b_i = 0, and
+    // ph_0 = 1.  Such maps (left multiplication by a quaternion, or a constant) compose
+    // associatively: every lane composes the steps of its run of C = ceil(W / 64) entries, a scan
+    // over the wave gives each lane the phase at the start of its run, and the lane replays its
+    // run from there (about 2 C + 6 dependent products instead of W).
+    const int C = (W + 63) / 64;
+    const int i0 = lane * C, i1 = min(i0 + C, W);                 // this lane's entries
+    auto step = [&](int i, Q4 p) -> Q4 {                          // ph_{i+1} from ph_i
+        const Q4 sj{ss[i], ss[W + i], ss[2 * W + i], ss[3 * W + i]};
+        return sbr[i] > 0.0 ? qscale(qmul(sj, p), sinv[i]) : Q4{1, 0, 0, 0};
+    };
+    // the composite of steps i0 .. i1 - 1 (those below W - 1): p -> M p, or the constant M
+    Q4 M{1, 0, 0, 0};
+    bool cst = false;
+    for (int i = i0; i < i1 && i + 1 < W; i++) {
+        if (sbr[i] > 0.0) {
+            const Q4 sj{ss[i], ss[W + i], ss[2 * W + i], ss[3 * W + i]};
+            M = qmul(qscale(sj, sinv[i]), M);
+        } else {
+            M = Q4{1, 0, 0, 0};
+            cst = true;
+        }
+    }
+    // inclusive scan: lane l composes the runs of lanes <= l (the later map applied after)
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const Q4 Mo{__shfl_up(M.w, o, 64), __shfl_up(M.x, o, 64), __shfl_up(M.y, o, 64), __shfl_up(M.z, o, 64)};
+        const bool co = __shfl_up((int)cst, o, 64) != 0;
+        if (lane >= o && !cst) {
+            M = qmul(M, Mo);
+            cst = co;
+        }
+    }
+    // the phase at the start of this lane's run: the runs of the lanes before it applied to 1
+    Q4 p{__shfl_up(M.w, 1, 64), __shfl_up(M.x, 1, 64), __shfl_up(M.y, 1, 64), __shfl_up(M.z, 1, 64)};
+    if (lane == 0) p = Q4{1, 0, 0, 0};
+    for (int i = i0; i < i1; i++) {
+        sph[i] = p.w; sph[W + i] = p.x; sph[2 * W + i] = p.y; sph[3 * W + i] = p.z;
+        if (i + 1 < W) p = step(i, p);
     }
     __syncthreads();
     for (int i = lane; i < W; i += 64) {
