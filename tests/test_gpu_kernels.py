@@ -173,6 +173,30 @@ def test_qsvd_against_oracle(gq, oracle, w):
     np.testing.assert_allclose(qref.mul(qref.adj(Vh), Vh), eye, atol=1e-11)
 
 
+def test_qsvd_block_diagonal(gq, oracle):
+    """A block-diagonal R of order 130 (blocks of 70 and 60) through the large-order eigensolver:
+    the Householder tridiagonalisation of its block-diagonal Gram keeps the blocks apart exactly,
+    so the tridiagonal has an exact zero at the block boundary (a reflector of tau = 0, the
+    phase chain restarting at 1, Sturm counts and twisted factorisations with b_j = 0)."""
+    w, w1 = 130, 70
+    print(f"qsvd block-diagonal w={w}", flush=True)
+    R = np.zeros((4, w, w))
+    R[:, :w1, :w1] = W.random_quat(7201, w1, w1)
+    R[:, w1:, w1:] = W.random_quat(7202, w - w1, w - w1)
+    Uh, S, Vh = gq.qlra_qsvd(dev(R))
+    Uh, S, Vh = host(Uh), host(S), host(Vh)
+    _, So, _ = oracle.qsvd(R)
+    np.testing.assert_allclose(S, So, rtol=1e-12, atol=1e-13 * So[0])
+    np.testing.assert_allclose(qref.reconstruct(Uh, S, Vh), R, atol=1e-11 * So[0])
+    # eigenvectors of the Gram are orthogonal to about u64 lambda_max / (smallest gap of its
+    # eigenvalues); here that is 4e-12
+    lam = So ** 2
+    tol = max(1e-11, 50 * 2.0 ** -52 * lam[0] / np.min(np.abs(np.diff(lam))))
+    eye = np.zeros((4, w, w)); eye[0] = np.eye(w)
+    np.testing.assert_allclose(qref.mul(qref.adj(Uh), Uh), eye, atol=tol)
+    np.testing.assert_allclose(qref.mul(qref.adj(Vh), Vh), eye, atol=tol)
+
+
 def test_qsvd_upper_triangular_graded(gq, oracle):
     """The solve feeds the QSVD upper triangular R factors with graded diagonals.  For
     w <= 96 the GPU takes the QSVD from the eigendecomposition of R^H R, whose eigenvalues
